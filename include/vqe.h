@@ -1,0 +1,272 @@
+/*
+ * vqe.h -- C ABI of the MI355X (gfx950) VQE hot-path library, libvqe.so.
+ *
+ * The calls follow the statement of the problem in arXiv 2601.09951:
+ *   prepare the reference state        (Section 3.3, Eq. 4: |HF>)
+ *   apply the ansatz U(theta)          (Section 3.3, Eqs. 4-5; Section 4.3)
+ *   expect <psi|H|psi> of a Pauli sum  (Section 3.1, Eq. 2; Section 3.2)
+ *   gradient dE/dtheta                 (Algorithm 1; Sections 4.3, 5.2.5)
+ *   optimiser step                     (Section 3.4, Adam, lr 0.01)
+ *   the per-bond-length loop           (Algorithm 1, Section 4.2; Eq. 7)
+ *
+ * Conventions (shared by every call)
+ * ----------------------------------
+ * - A state on n qubits is complex128 [batch][2^n], re/im interleaved,
+ *   row-major, in device memory.  Wire w is bit (n-1-w) of the amplitude
+ *   index: a printed ket |w0 w1 ... w_{n-1}> reads as the binary expansion
+ *   of its index (|1100> is index 12 at n = 4).
+ * - A Pauli string is (xmask, zmask) over amplitude-index bits: bit b of
+ *   xmask is set for X or Y on the wire owning bit b, bit b of zmask for Z
+ *   or Y; the string acts as P|b> = i^{popcount(x&z)} (-1)^{popcount(z&b)}
+ *   |b xor x>.
+ * - Parameters are float64 [batch][n_params]; energies float64 [batch];
+ *   gradients float64 [batch][n_params]; all in device memory.
+ * - `stream` is a hipStream_t (NULL = the null stream).  Every call that
+ *   takes a stream only enqueues work on it and returns; results are valid
+ *   once the stream has reached that point.
+ * - Memory passed in is borrowed: the library never frees caller memory and
+ *   never keeps a pointer to it after the call returns.  Handles own the
+ *   device tables they allocate, until destroyed.
+ * - Every call returns VQE_OK (0) or a negative error code; no C++
+ *   exception crosses this boundary.  On error nothing is enqueued, and
+ *   vqe_last_error(ctx) describes the cause.
+ * - A context is bound to one device.  Calls on one context must not run
+ *   concurrently from several host threads.
+ */
+#ifndef VQE_H
+#define VQE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------- */
+#define VQE_OK 0
+#define VQE_EINVAL (-1)       /* bad argument: null pointer, size, wire, NaN/Inf */
+#define VQE_ENOMEM (-2)       /* device memory or the context's budget exhausted */
+#define VQE_EUNSUPPORTED (-3) /* n outside [1, VQE_MAX_QUBITS], unknown gate kind */
+#define VQE_EHIP (-4)         /* a HIP runtime call failed; message in the context */
+
+#define VQE_MAX_QUBITS 34
+
+/* ---- gate kinds (Section 3.3 and the hardware-efficient ansatz) --------
+ * Rotations are U(a) = exp(-i a G / 2) with generator G:
+ *   RX: G = X; RY: G = Y; RZ: G = Z;
+ *   SINGLE_EXC (wires a, b): |01> -> c|01> + s|10>, |10> -> c|10> - s|01>,
+ *       c = cos(a/2), s = sin(a/2), G = (Y(x)X - X(x)Y) / 2;
+ *   DOUBLE_EXC (wires a, b, c, d): |0011> -> c|0011> + s|1100>,
+ *       |1100> -> c|1100> - s|0011>, identity elsewhere: the Givens-rotation
+ *       reading of Eq. (5) (whose printed exponent is not anti-Hermitian).
+ * Fixed gates: H, X, CNOT (control = first wire), CZ. */
+enum {
+    VQE_GATE_RX = 0,
+    VQE_GATE_RY = 1,
+    VQE_GATE_RZ = 2,
+    VQE_GATE_H = 3,
+    VQE_GATE_X = 4,
+    VQE_GATE_CNOT = 5,
+    VQE_GATE_CZ = 6,
+    VQE_GATE_SINGLE_EXC = 7,
+    VQE_GATE_DOUBLE_EXC = 8
+};
+
+/* optimisers for vqe_run */
+enum { VQE_OPT_ADAM = 0, VQE_OPT_GD = 1 };
+
+typedef struct vqe_ctx *vqe_ctx_t;
+typedef struct vqe_ham *vqe_ham_t;
+typedef struct vqe_circ *vqe_circ_t;
+
+/* ---- context ----------------------------------------------------------- */
+
+/* Create a context on HIP device `device` (made current for every later
+ * call on this context).  *out receives the handle.  device = -1 creates a
+ * host-only planning context: Hamiltonians, circuits, workspace sizes and
+ * schedule exports work without a GPU; calls that enqueue device work fail
+ * with VQE_EUNSUPPORTED.  Errors: EINVAL (out NULL, bad device), EHIP. */
+int vqe_ctx_create(int device, vqe_ctx_t *out);
+
+/* Destroy a context and everything it caches.  Handles created from it must
+ * be destroyed first.  Waits for nothing: the caller synchronises. */
+int vqe_ctx_destroy(vqe_ctx_t ctx);
+
+/* Cap on the device memory the context may allocate for its own tables and
+ * caches (0 = no cap).  Allocations that would exceed it fail with ENOMEM. */
+int vqe_ctx_set_mem_budget(vqe_ctx_t ctx, size_t bytes);
+
+/* Tile geometry of the state passes: k_fwd / k_rev = log2 of the number of
+ * amplitudes a workgroup holds in LDS in forward / reverse (adjoint) passes
+ * (forward 6..13, reverse 6..12), c_low = number of lowest index bits every
+ * tile contains (contiguous runs of 2^c_low amplitudes); c_low >= 2 and
+ * k - c_low >= 4 for both k, so a four-wire gate always fits a tile.  Pass 0
+ * to keep a value.  Changes apply to plans built afterwards.  A Pauli string
+ * whose X/Y bits outside the lowest c_low bits number more than
+ * k_fwd - c_low (or k_rev - c_low for gradients) is not supported
+ * (VQE_EUNSUPPORTED from the calls that evaluate it). */
+int vqe_ctx_set_tile(vqe_ctx_t ctx, int k_fwd, int k_rev, int c_low);
+
+/* Reserve `bytes` of context scratch now (used by vqe_expect and
+ * vqe_apply_ansatz for per-launch tables), so later calls do not allocate. */
+int vqe_ctx_reserve(vqe_ctx_t ctx, size_t bytes);
+
+/* Text of the last error on this context (never NULL). */
+const char *vqe_last_error(vqe_ctx_t ctx);
+
+/* Name of an error code (never NULL). */
+const char *vqe_strerror(int code);
+
+/* ---- Hamiltonians (Section 3.2, Eq. 3 and its Jordan-Wigner image) ----- */
+
+/* A Pauli sum H = sum_t coeff[t] P(xmask[t], zmask[t]) on n_qubits qubits.
+ * Host arrays of length n_terms are copied; equal strings are merged; the
+ * identity string (x = z = 0) is allowed.  Errors: EINVAL (NaN/Inf
+ * coefficient, mask bits at or above n_qubits, n_terms < 1),
+ * EUNSUPPORTED (n_qubits outside [1, VQE_MAX_QUBITS]), ENOMEM, EHIP. */
+int vqe_ham_create(vqe_ctx_t ctx, int n_qubits, int64_t n_terms, const uint64_t *xmask,
+                   const uint64_t *zmask, const double *coeff, vqe_ham_t *out);
+
+/* The qubit Hamiltonian of Eq. (3) from spatial-orbital integrals, mapped by
+ * Jordan-Wigner on n_qubits = 2 * n_orb interleaved spin orbitals (wire 2p =
+ * orbital p spin alpha, 2p+1 = spin beta; |1> = occupied):
+ *   H = e_core + sum_{PQ} h_PQ a+_P a_Q + 1/2 sum_{PQRS} (ps|qr) a+_P a+_Q a_R a_S
+ * with spin conserved on each one-body and two-body vertex.  h1 is the host
+ * array [n_orb][n_orb], h2 the host array [n_orb]^4 of chemist-notation
+ * integrals (pq|rs); both are read, not kept.  Coefficients with magnitude
+ * <= 1e-14 are dropped.  Errors: EINVAL (NaN/Inf, a complex coefficient
+ * from non-symmetric input), EUNSUPPORTED (n_orb < 1 or 2*n_orb > 34). */
+int vqe_ham_from_integrals(vqe_ctx_t ctx, int n_orb, const double *h1, const double *h2,
+                           double e_core, vqe_ham_t *out);
+
+/* Sizes of a Hamiltonian: qubits, merged terms, distinct flip masks. */
+int vqe_ham_info(vqe_ham_t ham, int *n_qubits, int64_t *n_terms, int64_t *n_groups);
+
+/* Copy the merged terms (sorted by (xmask, zmask)) into host arrays of
+ * length n_terms as reported by vqe_ham_info. */
+int vqe_ham_terms(vqe_ham_t ham, uint64_t *xmask, uint64_t *zmask, double *coeff);
+
+int vqe_ham_destroy(vqe_ham_t ham);
+
+/* ---- circuits (the ansatz U(theta) of Eq. 4) --------------------------- */
+
+/* A gate list applied in order.  kind[g] is a VQE_GATE_* code; wires is the
+ * host array [n_gates][4] listing gate g's wires in the order its
+ * definition uses (unused slots -1); param_idx[g] indexes the parameter
+ * vector (-1 = fixed gate with angle fixed_angle[g]; fixed_angle may be NULL
+ * when no gate is fixed-angle); n_params is the parameter-vector length.
+ * Host arrays are copied.  Errors: EINVAL (wire out of range or repeated,
+ * param_idx >= n_params, parameter on a non-rotation gate), EUNSUPPORTED
+ * (unknown kind, n_qubits out of range). */
+int vqe_circ_create(vqe_ctx_t ctx, int n_qubits, int64_t n_gates, const int32_t *kind,
+                    const int32_t *wires, const int32_t *param_idx, const double *fixed_angle,
+                    int32_t n_params, vqe_circ_t *out);
+
+int vqe_circ_destroy(vqe_circ_t circ);
+
+/* ---- workspace --------------------------------------------------------- */
+
+/* Bytes of device workspace that vqe_energy (want_grad = 0),
+ * vqe_energy_grad (want_grad = 1) or vqe_run (want_grad = 2) needs for `batch` instances: the state, the
+ * adjoint state lambda = H psi, and small per-launch tables.  A state is
+ * batch * 2^n * 16 bytes. */
+int vqe_workspace_bytes(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams,
+                        int64_t batch, int want_grad, size_t *bytes);
+
+/* ---- the hot path ------------------------------------------------------ */
+
+/* psi[b] <- e_ref for every instance b (Eq. 4's |HF>, or |0...0>).
+ * psi: device complex128 [batch][2^n_qubits]. */
+int vqe_prepare_reference(vqe_ctx_t ctx, int n_qubits, int64_t batch, uint64_t ref_index,
+                          void *psi, void *stream);
+
+/* psi[b] <- U(theta[b]) psi[b] in place, gates in list order.  theta: device
+ * float64 [batch][n_params]. */
+int vqe_apply_ansatz(vqe_ctx_t ctx, vqe_circ_t circ, int64_t batch, const double *theta,
+                     void *psi, void *stream);
+
+/* energy[b] = <psi[b]|H_b|psi[b]> (real part; Eq. 2).  hams has n_hams = 1
+ * (shared) or n_hams = batch entries, all on the state's qubit count.  Terms
+ * are evaluated grouped by flip mask, one tile sweep serving every group
+ * whose flip bits the tile holds.  energy: device float64 [batch]. */
+int vqe_expect(vqe_ctx_t ctx, int n_hams, const vqe_ham_t *hams, int64_t batch, const void *psi,
+               double *energy, void *stream);
+
+/* energy[b] = <psi_b|H_b|psi_b> with psi_b = U(theta[b]) e_ref: prepare, apply
+ * and expect in one call, using caller workspace (at least
+ * vqe_workspace_bytes(..., want_grad = 0)) instead of context scratch.
+ * energy: device float64 [batch]. */
+int vqe_energy(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams, int64_t batch,
+               uint64_t ref_index, const double *theta, double *energy, void *workspace,
+               size_t ws_bytes, void *stream);
+
+/* out[b] = H_b psi[b] (the adjoint seed lambda).  out must not alias psi. */
+int vqe_apply_hamiltonian(vqe_ctx_t ctx, int n_hams, const vqe_ham_t *hams, int64_t batch,
+                          const void *psi, void *out, void *stream);
+
+/* Energy and adjoint gradient for every instance: prepare e_ref, apply
+ * U(theta[b]), lambda = H psi with E fused, then the reverse sweep
+ *   g_l = Im <lambda_l|G_l|psi_l>,  psi <- U_l^dag psi,  lambda <- U_l^dag lambda
+ * accumulated per parameter (dE/dtheta_p = sum of g_l over gates using p).
+ * energy: device [batch]; grad: device [batch][n_params]; workspace: device
+ * memory of at least vqe_workspace_bytes(..., want_grad = 1). */
+int vqe_energy_grad(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams,
+                    int64_t batch, uint64_t ref_index, const double *theta, double *energy,
+                    double *grad, void *workspace, size_t ws_bytes, void *stream);
+
+/* One Adam step in place (Section 3.4; Kingma-Ba with epsilon outside the
+ * square root): m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * theta -= lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps).  t >= 1.
+ * All arrays device float64 [batch][n_params]. */
+int vqe_adam_step(vqe_ctx_t ctx, int64_t batch, int32_t n_params, double *theta, double *m,
+                  double *v, const double *grad, int32_t t, double lr, double b1, double b2,
+                  double eps, void *stream);
+
+/* The per-bond-length loop of Algorithm 1 for a batch of independent
+ * instances (Eq. 7): theta[b] (device, in: theta_0, out: final) takes
+ * `iters` optimiser steps (VQE_OPT_ADAM with lr, b1, b2, eps; or VQE_OPT_GD
+ * with step lr), each on the adjoint gradient at the current theta.
+ * energies: device float64 [batch][iters + 1]: the energy before each step,
+ * then the energy at the final theta.  Small states run the whole loop in
+ * one persistent launch; larger ones loop over vqe_energy_grad-style
+ * launches on the stream.  workspace: at least
+ * vqe_workspace_bytes(..., want_grad = 2). */
+int vqe_run(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams, int64_t batch,
+            uint64_t ref_index, double *theta, int32_t iters, int32_t optimizer, double lr,
+            double b1, double b2, double eps, double *energies, void *workspace, size_t ws_bytes,
+            void *stream);
+
+/* ---- schedule inspection (tooling and tests) ---------------------------
+ * Copy a compiled schedule into host memory.  If buf is NULL or buf_bytes is
+ * smaller than needed, only *needed is written.  Layouts (little endian,
+ * natural alignment):
+ *
+ * vqe_circ_plan_export: int32 {n_passes, n_ops, geom_bytes (72), op_bytes
+ *   (48)}, then per pass {geom, int32 op_begin, op_count, n_param_ops, 0},
+ *   then n_ops op records.  geom = int32 {n, k, c, n - k}, uint8 tpos[16]
+ *   (index bit of tile bit i), uint8 opos[40] (index bit of tile-number bit
+ *   i).  op = uint32 m, uint32 fixed_bits, uint64 cmask_out, uint64
+ *   cval_out, int32 gate, int32 pgate, int16 cls (0 general, 1 diagonal,
+ *   2 swap), int16 gen (0 none, 1 X, 2 Y, 3 Z), int8 nfix, uint8
+ *   fixpos[7]: the op updates the pairs p0 = (j with zero bits inserted at
+ *   fixpos[0..nfix)) | fixed_bits, p1 = p0 ^ m, j < 2^(k - nfix), of the
+ *   tiles whose base satisfies (base & cmask_out) == cval_out.
+ *   reverse = 1 exports the adjoint sweep's schedule (gates in reverse).
+ *
+ * vqe_ham_plan_export (for_gradient = 0: the expectation schedule, 1: the
+ *   H psi schedule): int32 {n_sweeps, n_groups, n_union_groups, n_inst,
+ *   n_terms, geom_bytes, group_bytes (16), term_bytes (24)}, per sweep
+ *   {geom, int32 group_begin, group_count, 0, 0}, groups {uint32 floc,
+ *   uint32 pivot, int32 union_group, 0}, int32 toff[n_inst][n_union][3]
+ *   (begin of real-phase terms, begin of imaginary-phase terms, end), terms
+ *   {uint64 z, uint32 zloc, 0, double w}. */
+int vqe_circ_plan_export(vqe_ctx_t ctx, vqe_circ_t circ, int reverse, void *buf, size_t buf_bytes,
+                         size_t *needed);
+int vqe_ham_plan_export(vqe_ctx_t ctx, int n_hams, const vqe_ham_t *hams, int64_t batch,
+                        int for_gradient, void *buf, size_t buf_bytes, size_t *needed);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VQE_H */

@@ -1,0 +1,860 @@
+// api.cpp -- the extern "C" boundary of libvqe (declared in include/vqe.h).
+//
+// Argument checking, handle ownership, workspace layout and the launch
+// sequences of the hot path of arXiv 2601.09951:
+//   energy:      prepare (Eq. 4) -> forward passes (Eqs. 4-5) -> sweeps (Eq. 2)
+//   energy_grad: prepare -> forward -> lambda = H psi with E fused ->
+//                reverse passes (adjoint) -> fixed-order reductions
+//   run:         Algorithm 1's loop: energy_grad + Adam/GD per step.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <sstream>
+
+#include "internal.h"
+
+namespace vqe {
+
+int set_err(Context *ctx, int code, const std::string &msg)
+{
+    if (ctx) ctx->err = msg;
+    return code;
+}
+
+int hip_check(Context *ctx, hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return VQE_OK;
+    std::ostringstream os;
+    os << what << ": " << hipGetErrorName(e) << " (" << hipGetErrorString(e) << ")";
+    return set_err(ctx, VQE_EHIP, os.str());
+}
+
+int dev_alloc(Context *ctx, DevMem &m, size_t bytes)
+{
+    m.p = nullptr;
+    m.bytes = 0;
+    if (bytes == 0) return VQE_OK;
+    if (ctx->budget && ctx->used + bytes > ctx->budget)
+        return set_err(ctx, VQE_ENOMEM, "context memory budget exhausted");
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return set_err(ctx, VQE_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    }
+    m.p = p;
+    m.bytes = bytes;
+    ctx->used += bytes;
+    return VQE_OK;
+}
+
+void dev_free(Context *ctx, DevMem &m)
+{
+    if (m.p) {
+        (void)hipFree(m.p);
+        if (ctx) ctx->used -= std::min(ctx->used, m.bytes);
+    }
+    m.p = nullptr;
+    m.bytes = 0;
+}
+
+int upload(Context *ctx, DevMem &m, const void *src, size_t bytes)
+{
+    if (ctx->device < 0) {  // host-only planning context: plans keep host copies only
+        m.p = nullptr;
+        m.bytes = 0;
+        return VQE_OK;
+    }
+    int r = dev_alloc(ctx, m, bytes);
+    if (r) return r;
+    if (!bytes) return VQE_OK;
+    return hip_check(ctx, hipMemcpy(m.p, src, bytes, hipMemcpyHostToDevice), "hipMemcpy (upload)");
+}
+
+int scratch_get(Context *ctx, size_t bytes, void **p)
+{
+    if (ctx->scratch.bytes < bytes) {
+        if (ctx->scratch.p) {
+            // the old buffer may still be read by queued work
+            int r = hip_check(ctx, hipDeviceSynchronize(), "hipDeviceSynchronize");
+            if (r) return r;
+            dev_free(ctx, ctx->scratch);
+        }
+        size_t want = std::max<size_t>(bytes, 1 << 20);
+        int r = dev_alloc(ctx, ctx->scratch, want);
+        if (r) return r;
+    }
+    *p = ctx->scratch.p;
+    return VQE_OK;
+}
+
+namespace {
+
+inline size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct Layout {
+    size_t psi = 0, lam = 0, mats = 0, pe = 0, pg = 0, grad = 0, m = 0, v = 0, etmp = 0;
+    size_t total = 0;
+    int W_fwd_sweep = 1, W_hpsi = 1, W_rev = 1;
+    int n_sweeps_e = 1;
+};
+
+int check_ctx(Context *ctx)
+{
+    if (!ctx) return VQE_EINVAL;
+    if (ctx->device < 0) return VQE_OK;
+    hipError_t e = hipSetDevice(ctx->device);
+    return hip_check(ctx, e, "hipSetDevice");
+}
+
+// entry points that enqueue device work
+int check_dev(Context *ctx)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (ctx->device < 0)
+        return set_err(ctx, VQE_EUNSUPPORTED, "host-only planning context cannot launch device work");
+    return VQE_OK;
+}
+
+constexpr int64_t kMaxBatch = 65535;  // instances map to gridDim.y
+
+int check_hams(Context *ctx, int n_hams, const vqe_ham_t *hams, int64_t batch, int n,
+               std::vector<Ham *> &out)
+{
+    if (batch > kMaxBatch) return set_err(ctx, VQE_EUNSUPPORTED, "batch > 65535");
+    if (!hams || n_hams < 1) return set_err(ctx, VQE_EINVAL, "hams is NULL or n_hams < 1");
+    if (n_hams != 1 && n_hams != batch)
+        return set_err(ctx, VQE_EINVAL, "n_hams must be 1 or batch");
+    out.resize(n_hams);
+    for (int i = 0; i < n_hams; ++i) {
+        Ham *h = hams[i];
+        if (!h) return set_err(ctx, VQE_EINVAL, "NULL Hamiltonian handle");
+        if (h->ctx != ctx) return set_err(ctx, VQE_EINVAL, "Hamiltonian from another context");
+        if (h->n != n) return set_err(ctx, VQE_EINVAL, "Hamiltonian qubit count differs from the state's");
+        out[i] = h;
+    }
+    return VQE_OK;
+}
+
+int wg_for(Context *ctx, int n, int k)
+{
+    const int keff = std::min(n, k);
+    const int64_t tiles = 1ll << (n - keff);
+    return (int)std::min<int64_t>(tiles, ctx->wg_max);
+}
+
+// workspace layout; want: 0 energy, 1 energy+grad, 2 run (adds optimiser state)
+int layout_for(Context *ctx, Circ *C, int n_hams, Ham *const *H, int64_t B, int want, Layout &L)
+{
+    int rc;
+    const int n = C->n;
+    const uint64_t dim = 1ull << n;
+    const size_t state = (size_t)B * dim * 16;
+    const int G = (int)C->gates.size();
+    const int n_inst = n_hams == 1 ? 1 : (int)B;
+    size_t off = 0;
+    L.psi = off;
+    off = align_up(off + state);
+    if (want >= 1) {
+        L.lam = off;
+        off = align_up(off + state);
+    }
+    L.mats = off;
+    off = align_up(off + (size_t)B * std::max(G, 1) * 64);
+    if (want == 0) {
+        PauliPlan *pp = get_pauli_plan(ctx, n_hams, H, n_inst, ctx->k_fwd, ctx->c_low, &rc);
+        if (!pp) return rc;
+        L.n_sweeps_e = (int)pp->sweeps.size();
+        L.W_fwd_sweep = wg_for(ctx, n, ctx->k_fwd);
+        L.pe = off;
+        off = align_up(off + (size_t)B * L.n_sweeps_e * L.W_fwd_sweep * 8);
+    } else {
+        L.W_hpsi = wg_for(ctx, n, ctx->k_rev);
+        L.W_rev = wg_for(ctx, n, ctx->k_rev);
+        L.pe = off;
+        off = align_up(off + (size_t)B * L.W_hpsi * 8);
+        L.pg = off;
+        off = align_up(off + (size_t)B * std::max(C->n_pgates, 1) * L.W_rev * 8);
+    }
+    if (want == 2) {
+        L.grad = off;
+        off = align_up(off + (size_t)B * std::max(C->n_params, 1) * 8);
+        L.m = off;
+        off = align_up(off + (size_t)B * std::max(C->n_params, 1) * 8);
+        L.v = off;
+        off = align_up(off + (size_t)B * std::max(C->n_params, 1) * 8);
+        // expectation partials for the final energy evaluation
+        PauliPlan *pp = get_pauli_plan(ctx, n_hams, H, n_inst, ctx->k_fwd, ctx->c_low, &rc);
+        if (!pp) return rc;
+        L.n_sweeps_e = (int)pp->sweeps.size();
+        L.W_fwd_sweep = wg_for(ctx, n, ctx->k_fwd);
+        L.etmp = off;
+        off = align_up(off + (size_t)B * L.n_sweeps_e * L.W_fwd_sweep * 8);
+    }
+    L.total = off;
+    return VQE_OK;
+}
+
+int forward(Context *ctx, Circ *C, int64_t B, const double *theta, double2 *psi, double2 *mats,
+            hipStream_t s)
+{
+    int rc;
+    CircPlan *fp = get_circ_plan(C, false, ctx->k_fwd, ctx->c_low, &rc);
+    if (!fp) return rc;
+    const int G = (int)C->gates.size();
+    if (G == 0) return VQE_OK;
+    rc = hip_check(ctx, launch_gate_mats(reinterpret_cast<const GateDev *>(C->gates_dev.p), G, theta,
+                                         C->n_params, B, mats, s),
+                   "gate matrices");
+    if (rc) return rc;
+    for (const PassPlan &pp : fp->passes) {
+        rc = hip_check(ctx, launch_forward_pass(pp, reinterpret_cast<const OpDesc *>(fp->ops.p), mats, G,
+                                                psi, B, ctx->wg_max, s),
+                       "forward pass");
+        if (rc) return rc;
+    }
+    return VQE_OK;
+}
+
+// energy by paired expectation sweeps (no lambda)
+int expect_into(Context *ctx, int n_hams, Ham *const *H, int64_t B, const double2 *psi,
+                double *energy, int64_t e_stride, double *partials, hipStream_t s)
+{
+    int rc;
+    const int n = H[0]->n;
+    const int n_inst = n_hams == 1 ? 1 : (int)B;
+    PauliPlan *pp = get_pauli_plan(ctx, n_hams, H, n_inst, ctx->k_fwd, ctx->c_low, &rc);
+    if (!pp) return rc;
+    const int W = wg_for(ctx, n, ctx->k_fwd);
+    const int S = (int)pp->sweeps.size();
+    for (int i = 0; i < S; ++i) {
+        rc = hip_check(ctx, launch_pauli_sweep(pp->sweeps[i], *pp, i, psi, nullptr, B, n_hams == 1, W,
+                                               partials, S, false, i == 0, i == S - 1, s),
+                       "expectation sweep");
+        if (rc) return rc;
+    }
+    return hip_check(ctx, launch_reduce_slots(partials, S, W, B, energy, e_stride, 1.0, s), "energy reduce");
+}
+
+int energy_grad_into(Context *ctx, Circ *C, int n_hams, Ham *const *H, int64_t B, uint64_t ref,
+                     const double *theta, double *energy, int64_t e_stride, double *grad,
+                     unsigned char *ws, const Layout &L, hipStream_t s)
+{
+    int rc;
+    const int n = C->n;
+    double2 *psi = reinterpret_cast<double2 *>(ws + L.psi);
+    double2 *lam = reinterpret_cast<double2 *>(ws + L.lam);
+    double2 *mats = reinterpret_cast<double2 *>(ws + L.mats);
+    double *pe = reinterpret_cast<double *>(ws + L.pe);
+    double *pg = reinterpret_cast<double *>(ws + L.pg);
+    const int n_inst = n_hams == 1 ? 1 : (int)B;
+    PauliPlan *pp = get_pauli_plan(ctx, n_hams, H, n_inst, ctx->k_rev, ctx->c_low, &rc);
+    if (!pp) return rc;
+    CircPlan *rp = get_circ_plan(C, true, ctx->k_rev, ctx->c_low, &rc);
+    if (!rp) return rc;
+
+    rc = hip_check(ctx, launch_prepare(psi, n, B, ref, s), "prepare");
+    if (rc) return rc;
+    rc = forward(ctx, C, B, theta, psi, mats, s);
+    if (rc) return rc;
+    const int S = (int)pp->sweeps.size();
+    for (int i = 0; i < S; ++i) {
+        rc = hip_check(ctx, launch_pauli_sweep(pp->sweeps[i], *pp, i, psi, lam, B, n_hams == 1, L.W_hpsi,
+                                               pe, 1, true, i == 0, i == S - 1, s),
+                       "H psi sweep");
+        if (rc) return rc;
+    }
+    rc = hip_check(ctx, launch_reduce_slots(pe, 1, L.W_hpsi, B, energy, e_stride, 1.0, s), "energy reduce");
+    if (rc) return rc;
+    const int G = (int)C->gates.size();
+    for (const PassPlan &p : rp->passes) {
+        rc = hip_check(ctx, launch_reverse_pass(p, reinterpret_cast<const OpDesc *>(rp->ops.p), mats, G, psi,
+                                                lam, B, L.W_rev, pg, C->n_pgates, s),
+                       "reverse pass");
+        if (rc) return rc;
+    }
+    return hip_check(ctx, launch_grad_reduce(pg, C->n_pgates, L.W_rev,
+                                             reinterpret_cast<const int32_t *>(C->pmap_off.p),
+                                             reinterpret_cast<const int32_t *>(C->pmap_idx.p),
+                                             C->n_params, B, grad, s),
+                     "gradient reduce");
+}
+
+}  // namespace
+}  // namespace vqe
+
+using namespace vqe;
+
+// ===========================================================================
+extern "C" {
+
+const char *vqe_strerror(int code)
+{
+    switch (code) {
+    case VQE_OK: return "VQE_OK";
+    case VQE_EINVAL: return "VQE_EINVAL: invalid argument";
+    case VQE_ENOMEM: return "VQE_ENOMEM: out of device memory or budget";
+    case VQE_EUNSUPPORTED: return "VQE_EUNSUPPORTED: unsupported size or gate";
+    case VQE_EHIP: return "VQE_EHIP: HIP runtime error";
+    default: return "unknown vqe error code";
+    }
+}
+
+const char *vqe_last_error(vqe_ctx_t ctx)
+{
+    return ctx ? ctx->err.c_str() : "NULL context";
+}
+
+int vqe_ctx_create(int device, vqe_ctx_t *out)
+{
+    if (!out) return VQE_EINVAL;
+    *out = nullptr;
+    if (device == -1) {  // host-only planning context (schedule inspection, no device work)
+        vqe_ctx *c = new (std::nothrow) vqe_ctx();
+        if (!c) return VQE_ENOMEM;
+        c->device = -1;
+        *out = c;
+        return VQE_OK;
+    }
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) {
+        (void)hipGetLastError();
+        return VQE_EINVAL;
+    }
+    if (hipSetDevice(device) != hipSuccess) return VQE_EHIP;
+    vqe_ctx *c = new (std::nothrow) vqe_ctx();
+    if (!c) return VQE_ENOMEM;
+    c->device = device;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+        c->cu_count = cus;
+    *out = c;
+    return VQE_OK;
+}
+
+int vqe_ctx_destroy(vqe_ctx_t ctx)
+{
+    if (!ctx) return VQE_EINVAL;
+    if (ctx->device >= 0) (void)hipSetDevice(ctx->device);
+    for (auto &kv : ctx->pauli_cache) {
+        dev_free(ctx, kv.second->groups);
+        dev_free(ctx, kv.second->toff);
+        dev_free(ctx, kv.second->terms);
+    }
+    ctx->pauli_cache.clear();
+    dev_free(ctx, ctx->scratch);
+    delete ctx;
+    return VQE_OK;
+}
+
+int vqe_ctx_set_mem_budget(vqe_ctx_t ctx, size_t bytes)
+{
+    if (!ctx) return VQE_EINVAL;
+    ctx->budget = bytes;
+    return VQE_OK;
+}
+
+int vqe_ctx_set_tile(vqe_ctx_t ctx, int k_fwd, int k_rev, int c_low)
+{
+    if (!ctx) return VQE_EINVAL;
+    int kf = k_fwd ? k_fwd : ctx->k_fwd, kr = k_rev ? k_rev : ctx->k_rev, c = c_low ? c_low : ctx->c_low;
+    if (kf < 6 || kf > kMaxTileBits || kr < 6 || kr > 12 || c < 2 || std::min(kf, kr) - c < 4)
+        return set_err(ctx, VQE_EINVAL, "tile geometry out of range (need 6 <= k, 2 <= c, k - c >= 4)");
+    if (kf != ctx->k_fwd || kr != ctx->k_rev || c != ctx->c_low) {
+        if (ctx->device >= 0) {
+            (void)hipSetDevice(ctx->device);
+            (void)hipDeviceSynchronize();
+        }
+        for (auto &kv : ctx->pauli_cache) {
+            dev_free(ctx, kv.second->groups);
+            dev_free(ctx, kv.second->toff);
+            dev_free(ctx, kv.second->terms);
+        }
+        ctx->pauli_cache.clear();
+    }
+    ctx->k_fwd = kf;
+    ctx->k_rev = kr;
+    ctx->c_low = c;
+    return VQE_OK;
+}
+
+int vqe_ctx_reserve(vqe_ctx_t ctx, size_t bytes)
+{
+    int rc = check_dev(ctx);
+    if (rc) return rc;
+    void *p;
+    return scratch_get(ctx, bytes, &p);
+}
+
+// ---------------------------------------------------------------------------
+static int ham_finish(vqe_ctx_t ctx, vqe_ham *h, vqe_ham_t *out)
+{
+    std::vector<uint64_t> xs(h->x);
+    std::sort(xs.begin(), xs.end());
+    h->n_groups = (int64_t)(std::unique(xs.begin(), xs.end()) - xs.begin());
+    h->id = ctx->next_id++;
+    h->ctx = ctx;
+    *out = h;
+    return VQE_OK;
+}
+
+int vqe_ham_create(vqe_ctx_t ctx, int n_qubits, int64_t n_terms, const uint64_t *xmask,
+                   const uint64_t *zmask, const double *coeff, vqe_ham_t *out)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!out) return set_err(ctx, VQE_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n_qubits < 1 || n_qubits > VQE_MAX_QUBITS)
+        return set_err(ctx, VQE_EUNSUPPORTED, "n_qubits outside [1, 34]");
+    if (n_terms < 1 || !xmask || !zmask || !coeff)
+        return set_err(ctx, VQE_EINVAL, "empty or NULL term arrays");
+    const uint64_t lim = n_qubits == 64 ? ~0ull : ((1ull << n_qubits) - 1);
+    vqe_ham *h = new (std::nothrow) vqe_ham();
+    if (!h) return set_err(ctx, VQE_ENOMEM, "host allocation");
+    h->n = n_qubits;
+    h->x.assign(xmask, xmask + n_terms);
+    h->z.assign(zmask, zmask + n_terms);
+    h->c.assign(coeff, coeff + n_terms);
+    for (int64_t t = 0; t < n_terms; ++t) {
+        if (!std::isfinite(coeff[t])) {
+            delete h;
+            return set_err(ctx, VQE_EINVAL, "non-finite coefficient");
+        }
+        if ((xmask[t] | zmask[t]) & ~lim) {
+            delete h;
+            return set_err(ctx, VQE_EINVAL, "Pauli mask has bits at or above n_qubits");
+        }
+    }
+    merge_terms(h->x, h->z, h->c, 0.0);
+    if (h->c.empty()) {  // every term cancelled: keep a zero identity
+        h->x.push_back(0);
+        h->z.push_back(0);
+        h->c.push_back(0.0);
+    }
+    return ham_finish(ctx, h, out);
+}
+
+int vqe_ham_from_integrals(vqe_ctx_t ctx, int n_orb, const double *h1, const double *h2,
+                           double e_core, vqe_ham_t *out)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!out || !h1 || !h2) return set_err(ctx, VQE_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (n_orb < 1 || 2 * n_orb > VQE_MAX_QUBITS)
+        return set_err(ctx, VQE_EUNSUPPORTED, "2 * n_orb outside [2, 34]");
+    vqe_ham *h = new (std::nothrow) vqe_ham();
+    if (!h) return set_err(ctx, VQE_ENOMEM, "host allocation");
+    h->n = 2 * n_orb;
+    std::string err;
+    rc = jordan_wigner(n_orb, h1, h2, e_core, h->x, h->z, h->c, err);
+    if (rc) {
+        delete h;
+        return set_err(ctx, rc, err);
+    }
+    if (h->c.empty()) {
+        h->x.push_back(0);
+        h->z.push_back(0);
+        h->c.push_back(0.0);
+    }
+    return ham_finish(ctx, h, out);
+}
+
+int vqe_ham_info(vqe_ham_t ham, int *n_qubits, int64_t *n_terms, int64_t *n_groups)
+{
+    if (!ham) return VQE_EINVAL;
+    if (n_qubits) *n_qubits = ham->n;
+    if (n_terms) *n_terms = (int64_t)ham->c.size();
+    if (n_groups) *n_groups = ham->n_groups;
+    return VQE_OK;
+}
+
+int vqe_ham_terms(vqe_ham_t ham, uint64_t *xmask, uint64_t *zmask, double *coeff)
+{
+    if (!ham || !xmask || !zmask || !coeff) return VQE_EINVAL;
+    std::memcpy(xmask, ham->x.data(), ham->x.size() * 8);
+    std::memcpy(zmask, ham->z.data(), ham->z.size() * 8);
+    std::memcpy(coeff, ham->c.data(), ham->c.size() * 8);
+    return VQE_OK;
+}
+
+int vqe_ham_destroy(vqe_ham_t ham)
+{
+    if (!ham) return VQE_EINVAL;
+    Context *ctx = ham->ctx;
+    if (ctx) {
+        // drop cached plans that reference this Hamiltonian
+        std::ostringstream tag;
+        tag << ':' << ham->id;
+        const std::string t = tag.str();
+        bool synced = false;
+        for (auto it = ctx->pauli_cache.begin(); it != ctx->pauli_cache.end();) {
+            const std::string &k = it->first;
+            bool hit = false;
+            for (size_t pos = k.find(t); pos != std::string::npos; pos = k.find(t, pos + 1)) {
+                size_t end = pos + t.size();
+                if (end == k.size() || k[end] == ':') {
+                    hit = true;
+                    break;
+                }
+            }
+            if (hit) {
+                if (!synced && ctx->device >= 0) {
+                    (void)hipSetDevice(ctx->device);
+                    (void)hipDeviceSynchronize();
+                    synced = true;
+                }
+                dev_free(ctx, it->second->groups);
+                dev_free(ctx, it->second->toff);
+                dev_free(ctx, it->second->terms);
+                it = ctx->pauli_cache.erase(it);
+            } else {
+                ++it;
+            }
+        }
+    }
+    delete ham;
+    return VQE_OK;
+}
+
+// ---------------------------------------------------------------------------
+int vqe_circ_create(vqe_ctx_t ctx, int n_qubits, int64_t n_gates, const int32_t *kind,
+                    const int32_t *wires, const int32_t *param_idx, const double *fixed_angle,
+                    int32_t n_params, vqe_circ_t *out)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!out) return set_err(ctx, VQE_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n_qubits < 1 || n_qubits > VQE_MAX_QUBITS)
+        return set_err(ctx, VQE_EUNSUPPORTED, "n_qubits outside [1, 34]");
+    if (n_gates < 0 || n_params < 0 || (n_gates > 0 && (!kind || !wires)))
+        return set_err(ctx, VQE_EINVAL, "bad gate arrays");
+    vqe_circ *C = new (std::nothrow) vqe_circ();
+    if (!C) return set_err(ctx, VQE_ENOMEM, "host allocation");
+    C->ctx = ctx;
+    C->n = n_qubits;
+    C->n_params = n_params;
+    std::string err;
+    rc = build_circuit_gates(C, n_gates, kind, wires, param_idx, fixed_angle, err);
+    if (rc) {
+        delete C;
+        return set_err(ctx, rc, err);
+    }
+    std::vector<GateDev> gd(C->gates.size());
+    for (size_t g = 0; g < C->gates.size(); ++g) {
+        gd[g].kind = C->gates[g].kind;
+        gd[g].pidx = C->gates[g].pidx;
+        gd[g].fixed = C->gates[g].fixed;
+    }
+    // CSR map parameter -> parametric gates (ascending gate order)
+    std::vector<int32_t> off(n_params + 1, 0), idx;
+    for (size_t g = 0; g < C->gates.size(); ++g)
+        if (C->gates[g].pidx >= 0) off[C->gates[g].pidx + 1]++;
+    for (int p = 0; p < n_params; ++p) off[p + 1] += off[p];
+    idx.assign(off[n_params], 0);
+    std::vector<int32_t> fill(off.begin(), off.end() - 1);
+    for (size_t g = 0; g < C->gates.size(); ++g)
+        if (C->gates[g].pidx >= 0) idx[fill[C->gates[g].pidx]++] = C->pgate_of_gate[g];
+    rc = upload(ctx, C->gates_dev, gd.data(), gd.size() * sizeof(GateDev));
+    if (!rc) rc = upload(ctx, C->pmap_off, off.data(), off.size() * sizeof(int32_t));
+    if (!rc && !idx.empty()) rc = upload(ctx, C->pmap_idx, idx.data(), idx.size() * sizeof(int32_t));
+    if (rc) {
+        dev_free(ctx, C->gates_dev);
+        dev_free(ctx, C->pmap_off);
+        dev_free(ctx, C->pmap_idx);
+        delete C;
+        return rc;
+    }
+    C->id = ctx->next_id++;
+    *out = C;
+    return VQE_OK;
+}
+
+int vqe_circ_destroy(vqe_circ_t C)
+{
+    if (!C) return VQE_EINVAL;
+    Context *ctx = C->ctx;
+    if (ctx->device >= 0) {
+        (void)hipSetDevice(ctx->device);
+        (void)hipDeviceSynchronize();
+    }
+    for (auto *cache : {&C->fwd, &C->rev})
+        for (auto &kv : *cache) dev_free(ctx, kv.second->ops);
+    dev_free(ctx, C->gates_dev);
+    dev_free(ctx, C->pmap_off);
+    dev_free(ctx, C->pmap_idx);
+    delete C;
+    return VQE_OK;
+}
+
+int vqe_workspace_bytes(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams,
+                        int64_t batch, int want_grad, size_t *bytes)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!circ || !bytes || batch < 1 || want_grad < 0 || want_grad > 2)
+        return set_err(ctx, VQE_EINVAL, "bad argument");
+    std::vector<Ham *> H;
+    rc = check_hams(ctx, n_hams, hams, batch, circ->n, H);
+    if (rc) return rc;
+    Layout L;
+    rc = layout_for(ctx, circ, n_hams, H.data(), batch, want_grad, L);
+    if (rc) return rc;
+    *bytes = L.total;
+    return VQE_OK;
+}
+
+// ---------------------------------------------------------------------------
+int vqe_prepare_reference(vqe_ctx_t ctx, int n_qubits, int64_t batch, uint64_t ref_index, void *psi,
+                          void *stream)
+{
+    int rc = check_dev(ctx);
+    if (rc) return rc;
+    if (n_qubits < 1 || n_qubits > VQE_MAX_QUBITS) return set_err(ctx, VQE_EUNSUPPORTED, "n_qubits");
+    if (!psi || batch < 1) return set_err(ctx, VQE_EINVAL, "psi NULL or batch < 1");
+    if (batch > kMaxBatch) return set_err(ctx, VQE_EUNSUPPORTED, "batch > 65535");
+    if (ref_index >> n_qubits) return set_err(ctx, VQE_EINVAL, "ref_index >= 2^n");
+    return hip_check(ctx, launch_prepare((double2 *)psi, n_qubits, batch, ref_index, (hipStream_t)stream),
+                     "prepare");
+}
+
+int vqe_apply_ansatz(vqe_ctx_t ctx, vqe_circ_t circ, int64_t batch, const double *theta, void *psi,
+                     void *stream)
+{
+    int rc = check_dev(ctx);
+    if (rc) return rc;
+    if (!circ || !psi || batch < 1 || (circ->n_params > 0 && !theta))
+        return set_err(ctx, VQE_EINVAL, "bad argument");
+    if (batch > kMaxBatch) return set_err(ctx, VQE_EUNSUPPORTED, "batch > 65535");
+    void *mats;
+    rc = scratch_get(ctx, (size_t)batch * std::max<size_t>(circ->gates.size(), 1) * 64, &mats);
+    if (rc) return rc;
+    return forward(ctx, circ, batch, theta, (double2 *)psi, (double2 *)mats, (hipStream_t)stream);
+}
+
+int vqe_expect(vqe_ctx_t ctx, int n_hams, const vqe_ham_t *hams, int64_t batch, const void *psi,
+               double *energy, void *stream)
+{
+    int rc = check_dev(ctx);
+    if (rc) return rc;
+    if (!psi || !energy || batch < 1) return set_err(ctx, VQE_EINVAL, "bad argument");
+    if (!hams || n_hams < 1 || !hams[0]) return set_err(ctx, VQE_EINVAL, "no Hamiltonian");
+    std::vector<Ham *> H;
+    rc = check_hams(ctx, n_hams, hams, batch, hams[0]->n, H);
+    if (rc) return rc;
+    const int n = H[0]->n;
+    const int n_inst = n_hams == 1 ? 1 : (int)batch;
+    PauliPlan *pp = get_pauli_plan(ctx, n_hams, H.data(), n_inst, ctx->k_fwd, ctx->c_low, &rc);
+    if (!pp) return rc;
+    void *part;
+    rc = scratch_get(ctx, (size_t)batch * pp->sweeps.size() * wg_for(ctx, n, ctx->k_fwd) * 8, &part);
+    if (rc) return rc;
+    return expect_into(ctx, n_hams, H.data(), batch, (const double2 *)psi, energy, 1, (double *)part,
+                       (hipStream_t)stream);
+}
+
+int vqe_apply_hamiltonian(vqe_ctx_t ctx, int n_hams, const vqe_ham_t *hams, int64_t batch,
+                          const void *psi, void *out, void *stream)
+{
+    int rc = check_dev(ctx);
+    if (rc) return rc;
+    if (!psi || !out || batch < 1 || psi == out) return set_err(ctx, VQE_EINVAL, "bad argument");
+    if (!hams || n_hams < 1 || !hams[0]) return set_err(ctx, VQE_EINVAL, "no Hamiltonian");
+    std::vector<Ham *> H;
+    rc = check_hams(ctx, n_hams, hams, batch, hams[0]->n, H);
+    if (rc) return rc;
+    const int n = H[0]->n;
+    const int n_inst = n_hams == 1 ? 1 : (int)batch;
+    PauliPlan *pp = get_pauli_plan(ctx, n_hams, H.data(), n_inst, ctx->k_rev, ctx->c_low, &rc);
+    if (!pp) return rc;
+    const int W = wg_for(ctx, n, ctx->k_rev);
+    void *part;
+    rc = scratch_get(ctx, (size_t)batch * W * 8, &part);
+    if (rc) return rc;
+    const int S = (int)pp->sweeps.size();
+    for (int i = 0; i < S; ++i) {
+        rc = hip_check(ctx, launch_pauli_sweep(pp->sweeps[i], *pp, i, (const double2 *)psi, (double2 *)out,
+                                               batch, n_hams == 1, W, (double *)part, 1, true, i == 0,
+                                               i == S - 1, (hipStream_t)stream),
+                       "H psi sweep");
+        if (rc) return rc;
+    }
+    return VQE_OK;
+}
+
+int vqe_energy(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams, int64_t batch,
+               uint64_t ref_index, const double *theta, double *energy, void *workspace,
+               size_t ws_bytes, void *stream)
+{
+    int rc = check_dev(ctx);
+    if (rc) return rc;
+    if (!circ || !energy || !workspace || batch < 1 || (circ->n_params > 0 && !theta))
+        return set_err(ctx, VQE_EINVAL, "bad argument");
+    if (ref_index >> circ->n) return set_err(ctx, VQE_EINVAL, "ref_index >= 2^n");
+    std::vector<Ham *> H;
+    rc = check_hams(ctx, n_hams, hams, batch, circ->n, H);
+    if (rc) return rc;
+    Layout L;
+    rc = layout_for(ctx, circ, n_hams, H.data(), batch, 0, L);
+    if (rc) return rc;
+    if (ws_bytes < L.total) return set_err(ctx, VQE_EINVAL, "workspace too small");
+    unsigned char *ws = (unsigned char *)workspace;
+    hipStream_t s = (hipStream_t)stream;
+    double2 *psi = (double2 *)(ws + L.psi);
+    rc = hip_check(ctx, launch_prepare(psi, circ->n, batch, ref_index, s), "prepare");
+    if (rc) return rc;
+    rc = forward(ctx, circ, batch, theta, psi, (double2 *)(ws + L.mats), s);
+    if (rc) return rc;
+    return expect_into(ctx, n_hams, H.data(), batch, psi, energy, 1, (double *)(ws + L.pe), s);
+}
+
+int vqe_energy_grad(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams, int64_t batch,
+                    uint64_t ref_index, const double *theta, double *energy, double *grad,
+                    void *workspace, size_t ws_bytes, void *stream)
+{
+    int rc = check_dev(ctx);
+    if (rc) return rc;
+    if (!circ || !energy || !grad || !workspace || batch < 1 || (circ->n_params > 0 && !theta))
+        return set_err(ctx, VQE_EINVAL, "bad argument");
+    if (ref_index >> circ->n) return set_err(ctx, VQE_EINVAL, "ref_index >= 2^n");
+    std::vector<Ham *> H;
+    rc = check_hams(ctx, n_hams, hams, batch, circ->n, H);
+    if (rc) return rc;
+    Layout L;
+    rc = layout_for(ctx, circ, n_hams, H.data(), batch, 1, L);
+    if (rc) return rc;
+    if (ws_bytes < L.total) return set_err(ctx, VQE_EINVAL, "workspace too small");
+    return energy_grad_into(ctx, circ, n_hams, H.data(), batch, ref_index, theta, energy, 1, grad,
+                            (unsigned char *)workspace, L, (hipStream_t)stream);
+}
+
+int vqe_adam_step(vqe_ctx_t ctx, int64_t batch, int32_t n_params, double *theta, double *m, double *v,
+                  const double *grad, int32_t t, double lr, double b1, double b2, double eps,
+                  void *stream)
+{
+    int rc = check_dev(ctx);
+    if (rc) return rc;
+    if (batch < 1 || n_params < 0 || t < 1 || !theta || !m || !v || !grad)
+        return set_err(ctx, VQE_EINVAL, "bad argument");
+    return hip_check(ctx, launch_adam(batch * n_params, theta, m, v, grad, t, lr, b1, b2, eps,
+                                      (hipStream_t)stream),
+                     "adam");
+}
+
+int vqe_run(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams, int64_t batch,
+            uint64_t ref_index, double *theta, int32_t iters, int32_t optimizer, double lr, double b1,
+            double b2, double eps, double *energies, void *workspace, size_t ws_bytes, void *stream)
+{
+    int rc = check_dev(ctx);
+    if (rc) return rc;
+    if (!circ || !energies || !workspace || batch < 1 || iters < 0 || (circ->n_params > 0 && !theta))
+        return set_err(ctx, VQE_EINVAL, "bad argument");
+    if (optimizer != VQE_OPT_ADAM && optimizer != VQE_OPT_GD) return set_err(ctx, VQE_EINVAL, "optimizer");
+    if (ref_index >> circ->n) return set_err(ctx, VQE_EINVAL, "ref_index >= 2^n");
+    std::vector<Ham *> H;
+    rc = check_hams(ctx, n_hams, hams, batch, circ->n, H);
+    if (rc) return rc;
+    Layout L;
+    rc = layout_for(ctx, circ, n_hams, H.data(), batch, 2, L);
+    if (rc) return rc;
+    if (ws_bytes < L.total) return set_err(ctx, VQE_EINVAL, "workspace too small");
+    unsigned char *ws = (unsigned char *)workspace;
+    hipStream_t s = (hipStream_t)stream;
+    const int P = circ->n_params;
+    double *g = (double *)(ws + L.grad), *m = (double *)(ws + L.m), *v = (double *)(ws + L.v);
+    const int64_t e_stride = (int64_t)iters + 1;
+    const int64_t np = batch * (int64_t)P;
+    if (np > 0) {
+        rc = hip_check(ctx, launch_fill(m, np, 0.0, s), "zero moments");
+        if (!rc) rc = hip_check(ctx, launch_fill(v, np, 0.0, s), "zero moments");
+        if (rc) return rc;
+    }
+    for (int it = 0; it < iters; ++it) {
+        rc = energy_grad_into(ctx, circ, n_hams, H.data(), batch, ref_index, theta, energies + it, e_stride, g,
+                              ws, L, s);
+        if (rc) return rc;
+        if (optimizer == VQE_OPT_ADAM)
+            rc = hip_check(ctx, launch_adam(np, theta, m, v, g, it + 1, lr, b1, b2, eps, s), "adam");
+        else
+            rc = hip_check(ctx, launch_gd(np, theta, g, lr, s), "gd");
+        if (rc) return rc;
+    }
+    // energy at the final parameters
+    double2 *psi = (double2 *)(ws + L.psi);
+    rc = hip_check(ctx, launch_prepare(psi, circ->n, batch, ref_index, s), "prepare");
+    if (rc) return rc;
+    rc = forward(ctx, circ, batch, theta, psi, (double2 *)(ws + L.mats), s);
+    if (rc) return rc;
+    return expect_into(ctx, n_hams, H.data(), batch, psi, energies + iters, e_stride, (double *)(ws + L.etmp), s);
+}
+
+int vqe_circ_plan_export(vqe_ctx_t ctx, vqe_circ_t circ, int reverse, void *buf, size_t buf_bytes,
+                         size_t *needed)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!circ || !needed) return set_err(ctx, VQE_EINVAL, "bad argument");
+    CircPlan *p = get_circ_plan(circ, reverse != 0, reverse ? ctx->k_rev : ctx->k_fwd, ctx->c_low, &rc);
+    if (!p) return rc;
+    const size_t pass_bytes = sizeof(TileGeom) + 16;
+    const size_t need = 16 + p->passes.size() * pass_bytes + p->host_ops.size() * sizeof(OpDesc);
+    *needed = need;
+    if (!buf || buf_bytes < need) return VQE_OK;
+    unsigned char *o = (unsigned char *)buf;
+    int32_t hdr[4] = {(int32_t)p->passes.size(), (int32_t)p->host_ops.size(), (int32_t)sizeof(TileGeom),
+                      (int32_t)sizeof(OpDesc)};
+    std::memcpy(o, hdr, 16);
+    o += 16;
+    for (const PassPlan &pp : p->passes) {
+        std::memcpy(o, &pp.geom, sizeof(TileGeom));
+        int32_t meta[4] = {pp.op_begin, pp.op_count, pp.n_param_ops, 0};
+        std::memcpy(o + sizeof(TileGeom), meta, 16);
+        o += pass_bytes;
+    }
+    std::memcpy(o, p->host_ops.data(), p->host_ops.size() * sizeof(OpDesc));
+    return VQE_OK;
+}
+
+int vqe_ham_plan_export(vqe_ctx_t ctx, int n_hams, const vqe_ham_t *hams, int64_t batch,
+                        int for_gradient, void *buf, size_t buf_bytes, size_t *needed)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!needed || batch < 1 || !hams || n_hams < 1 || !hams[0]) return set_err(ctx, VQE_EINVAL, "bad argument");
+    std::vector<Ham *> H;
+    rc = check_hams(ctx, n_hams, hams, batch, hams[0]->n, H);
+    if (rc) return rc;
+    const int n_inst = n_hams == 1 ? 1 : (int)batch;
+    PauliPlan *p = get_pauli_plan(ctx, n_hams, H.data(), n_inst, for_gradient ? ctx->k_rev : ctx->k_fwd,
+                                  ctx->c_low, &rc);
+    if (!p) return rc;
+    const size_t sweep_bytes = sizeof(TileGeom) + 16;
+    const size_t need = 32 + p->sweeps.size() * sweep_bytes + p->host_groups.size() * sizeof(GroupDev) +
+                        p->host_toff.size() * 4 + p->host_terms.size() * sizeof(TermDev);
+    *needed = need;
+    if (!buf || buf_bytes < need) return VQE_OK;
+    unsigned char *o = (unsigned char *)buf;
+    int32_t hdr[8] = {(int32_t)p->sweeps.size(), (int32_t)p->host_groups.size(), p->n_ugroups, p->n_inst,
+                      (int32_t)p->host_terms.size(), (int32_t)sizeof(TileGeom), (int32_t)sizeof(GroupDev),
+                      (int32_t)sizeof(TermDev)};
+    std::memcpy(o, hdr, 32);
+    o += 32;
+    for (const SweepPlan &sp : p->sweeps) {
+        std::memcpy(o, &sp.geom, sizeof(TileGeom));
+        int32_t meta[4] = {sp.grp_begin, sp.grp_count, 0, 0};
+        std::memcpy(o + sizeof(TileGeom), meta, 16);
+        o += sweep_bytes;
+    }
+    std::memcpy(o, p->host_groups.data(), p->host_groups.size() * sizeof(GroupDev));
+    o += p->host_groups.size() * sizeof(GroupDev);
+    std::memcpy(o, p->host_toff.data(), p->host_toff.size() * 4);
+    o += p->host_toff.size() * 4;
+    std::memcpy(o, p->host_terms.data(), p->host_terms.size() * sizeof(TermDev));
+    return VQE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,255 @@
+// internal.h -- shared host/device declarations of libvqe (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/vqe.h"
+
+namespace vqe {
+
+// ---------------------------------------------------------------------------
+// Device-side descriptors (plain structs, copied to device memory or passed
+// by value as kernel arguments).
+// ---------------------------------------------------------------------------
+
+constexpr int kMaxTileBits = 13;   // 2^13 complex128 = 128 KiB of LDS
+constexpr int kMaxOutBits = 40;
+constexpr int kThreads = 256;      // workgroup size of the state passes
+
+// Geometry of one tile pass: the tile holds the amplitudes whose index bits
+// outside `tpos` equal the tile's base.  tpos[0..k) are ascending; the first
+// c of them are 0..c-1 (contiguous runs of 2^c amplitudes).
+struct TileGeom {
+    int32_t n;           // qubits
+    int32_t k;           // tile bits
+    int32_t c;           // low contiguous bits (c <= k)
+    int32_t nout;        // n - k
+    uint8_t tpos[16];    // bit position of local bit i
+    uint8_t opos[kMaxOutBits];  // bit position of tile-index bit i
+};
+
+// Gate classes on an amplitude pair (first, second).
+enum : int16_t { CLS_GENERAL = 0, CLS_DIAG = 1, CLS_SWAP = 2 };
+// Generator classes for the adjoint gradient.
+enum : int16_t { GEN_NONE = 0, GEN_X = 1, GEN_Y = 2, GEN_Z = 3 };
+
+// One gate in tile-local coordinates.  The active pairs are
+// p0 = insert_zeros(j, fixpos) | fixed_bits, p1 = p0 ^ m, j in [0, 2^(k-nfix)),
+// restricted to tiles with (base & cmask_out) == cval_out.
+struct OpDesc {
+    uint32_t m;          // local flip mask
+    uint32_t fixed_bits; // local pattern of the first element and local controls
+    uint64_t cmask_out;  // controls on index bits outside the tile
+    uint64_t cval_out;
+    int32_t gate;        // index in the circuit's gate list (matrix slot)
+    int32_t pgate;       // index among parametric gates, -1 if none
+    int16_t cls;         // CLS_*
+    int16_t gen;         // GEN_*
+    int8_t nfix;         // number of fixed local bits
+    uint8_t fixpos[7];   // ascending local positions of the fixed bits
+};
+static_assert(sizeof(OpDesc) == 48, "OpDesc layout");
+static_assert(sizeof(TileGeom) == 72, "TileGeom layout");
+
+// Per-gate data for the matrix preparation kernel.
+struct GateDev {
+    int32_t kind;
+    int32_t pidx;
+    double fixed;
+};
+
+// A Pauli term inside a sweep: sign over the tile's outside bits comes from
+// zfull, the in-tile sign from zloc; w is the real weight described in
+// pauli.cpp (kappa = w for "real" terms, kappa = i*w for "imaginary" ones).
+struct TermDev {
+    uint64_t zfull;
+    uint32_t zloc;
+    uint32_t pad;
+    double w;
+};
+
+// A flip group inside a sweep.
+struct GroupDev {
+    uint32_t floc;       // local flip mask (0 for the diagonal group)
+    uint32_t pivot;      // local bit cleared to enumerate pairs (0 if floc == 0)
+    int32_t ugroup;      // group index in the union ordering
+    int32_t pad;
+};
+
+// ---------------------------------------------------------------------------
+// Host objects behind the opaque handles.
+// ---------------------------------------------------------------------------
+struct DevMem {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct Context;
+
+struct Ham {
+    Context *ctx = nullptr;
+    int n = 0;
+    uint64_t id = 0;
+    std::vector<uint64_t> x, z;  // merged, sorted by (x, z)
+    std::vector<double> c;
+    int64_t n_groups = 0;
+};
+
+struct GateHost {
+    int kind;
+    int wires[4];
+    int nw;
+    int pidx;
+    double fixed;
+    // index-bit view
+    uint32_t mbits_pos[4];   // positions of flip bits
+    int nm;
+    uint64_t m;              // flip mask (global)
+    uint64_t first;          // pattern of m-bits for the first element
+    uint64_t cmask, cval;    // controls (global)
+    int16_t cls, gen;
+};
+
+struct PassPlan {
+    TileGeom geom;
+    int op_begin = 0, op_count = 0;
+    int n_param_ops = 0;     // parametric ops in this pass (reverse plans)
+};
+
+struct CircPlan {
+    int k = 0, c = 0;
+    bool reverse = false;
+    std::vector<PassPlan> passes;
+    DevMem ops;              // OpDesc[]
+    std::vector<OpDesc> host_ops;
+    int max_param_ops = 0;
+};
+
+struct Circ {
+    Context *ctx = nullptr;
+    int n = 0;
+    int n_params = 0;
+    int n_pgates = 0;
+    std::vector<GateHost> gates;
+    std::vector<int> pgate_of_gate;  // -1 or index among parametric gates
+    DevMem gates_dev;                // GateDev[]
+    DevMem pmap_off, pmap_idx;       // CSR param -> pgates
+    std::map<std::pair<int, int>, std::unique_ptr<CircPlan>> fwd, rev;
+    uint64_t id = 0;
+};
+
+// Union Pauli plan for a list of Hamiltonians on one tile geometry.
+struct SweepPlan {
+    TileGeom geom;
+    int grp_begin = 0, grp_count = 0;
+};
+
+struct PauliPlan {
+    int n = 0, n_inst = 0, k = 0, c = 0;
+    int n_ugroups = 0;
+    std::vector<SweepPlan> sweeps;
+    DevMem groups;   // GroupDev[total groups over sweeps]
+    DevMem toff;     // int32 [n_inst][n_ugroups][3] (begin_re, begin_im, end)
+    DevMem terms;    // TermDev[] (per instance, grouped)
+    std::vector<GroupDev> host_groups;
+    std::vector<int32_t> host_toff;
+    std::vector<TermDev> host_terms;
+    int max_terms_group = 0;
+};
+
+struct Context {
+    int device = 0;
+    size_t budget = 0;
+    size_t used = 0;
+    int k_fwd = 12, k_rev = 11, c_low = 4;
+    int wg_max = 1024;          // workgroups per instance in tile passes
+    std::string err;
+    DevMem scratch;
+    std::map<std::string, std::unique_ptr<PauliPlan>> pauli_cache;
+    uint64_t next_id = 1;
+    int cu_count = 256;
+};
+
+// ---------------------------------------------------------------------------
+// helpers implemented in api.cpp
+// ---------------------------------------------------------------------------
+int set_err(Context *ctx, int code, const std::string &msg);
+int dev_alloc(Context *ctx, DevMem &m, size_t bytes);
+void dev_free(Context *ctx, DevMem &m);
+int upload(Context *ctx, DevMem &m, const void *src, size_t bytes);
+int hip_check(Context *ctx, hipError_t e, const char *what);
+int scratch_get(Context *ctx, size_t bytes, void **p);
+
+// jw.cpp
+int jordan_wigner(int n_orb, const double *h1, const double *h2, double e_core,
+                  std::vector<uint64_t> &x, std::vector<uint64_t> &z, std::vector<double> &c,
+                  std::string &err);
+void merge_terms(std::vector<uint64_t> &x, std::vector<uint64_t> &z, std::vector<double> &c,
+                 double drop);
+
+// plan.cpp
+int build_circuit_gates(Circ *C, int64_t n_gates, const int32_t *kind, const int32_t *wires,
+                        const int32_t *pidx, const double *fixed, std::string &err);
+CircPlan *get_circ_plan(Circ *C, bool reverse, int k, int c, int *rc);
+PauliPlan *get_pauli_plan(Context *ctx, int n_hams, Ham *const *hams, int n_inst, int k, int c,
+                          int *rc);
+TileGeom make_geom(int n, int k, int c, const std::vector<int> &tile_bits);
+
+// kernels.hip -- launchers (return hipError_t of the launch)
+hipError_t launch_prepare(double2 *psi, int n, int64_t batch, uint64_t ref, hipStream_t s);
+hipError_t launch_gate_mats(const GateDev *gates, int n_gates, const double *theta,
+                            int n_params, int64_t batch, double2 *mats, hipStream_t s);
+hipError_t launch_forward_pass(const PassPlan &pp, const OpDesc *ops, const double2 *mats,
+                               int n_gates, double2 *psi, int64_t batch, int wg_max,
+                               hipStream_t s);
+hipError_t launch_reverse_pass(const PassPlan &pp, const OpDesc *ops, const double2 *mats,
+                               int n_gates, double2 *psi, double2 *lam, int64_t batch,
+                               int wg_per_inst, double *partials, int n_pgates,
+                               hipStream_t s);
+hipError_t launch_pauli_sweep(const SweepPlan &sp, const PauliPlan &pp, int sweep_idx,
+                              const double2 *psi, double2 *lam, int64_t batch,
+                              int shared_ham, int wg_per_inst, double *partials,
+                              int n_slots, bool write_lambda, bool first, bool last,
+                              hipStream_t s);
+hipError_t launch_reduce_slots(const double *partials, int n_slots, int wg_per_inst,
+                               int64_t batch, double *out, int64_t out_stride, double scale,
+                               hipStream_t s);
+hipError_t launch_grad_reduce(const double *partials, int n_pgates, int wg_per_inst,
+                              const int32_t *pmap_off, const int32_t *pmap_idx, int n_params,
+                              int64_t batch, double *grad, hipStream_t s);
+hipError_t launch_adam(int64_t count, double *theta, double *m, double *v, const double *g,
+                       int t, double lr, double b1, double b2, double eps, hipStream_t s);
+hipError_t launch_gd(int64_t count, double *theta, const double *g, double lr, hipStream_t s);
+hipError_t launch_fill(double *p, int64_t count, double value, hipStream_t s);
+
+// small-state persistent loop (kernels_small.hip)
+struct SmallRunArgs {
+    int n, n_gates, n_params, iters, opt, n_inst;
+    uint64_t ref;
+    double lr, b1, b2, eps;
+    const GateDev *gates;          // [n_gates]
+    const OpDesc *ops;             // [n_gates] (single-tile forward plan, gate order)
+    const GroupDev *groups;        // union groups (single sweep)
+    int n_groups;
+    const int32_t *toff;           // [n_inst or 1][n_groups][3]
+    const TermDev *terms;
+    int shared_ham;
+    double *theta;                 // [B][P]
+    double *energies;              // [B][iters+1]
+    double *work;                  // [B][2P] Adam moments
+};
+hipError_t launch_small_run(const SmallRunArgs &a, int64_t batch, hipStream_t s);
+int small_run_supported(int n, int n_gates, int n_params, int n_groups, int max_terms);
+
+}  // namespace vqe
+
+struct vqe_ctx : vqe::Context {};
+struct vqe_ham : vqe::Ham {};
+struct vqe_circ : vqe::Circ {};

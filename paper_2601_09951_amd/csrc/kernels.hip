@@ -1,0 +1,590 @@
+// kernels.hip -- gfx950 kernels of the VQE hot path (arXiv 2601.09951):
+// reference-state preparation (Eq. 4), tile passes that apply many gates per
+// HBM round trip (Eqs. 4-5), flip-group Pauli sweeps for <psi|H|psi> and
+// H psi (Eq. 2), the adjoint reverse sweep, fixed-order reductions and the
+// Adam update (Section 3.4).
+//
+// All state arithmetic is complex128 (double2, re/im interleaved).  A tile
+// pass stages 2^k amplitudes in LDS: the low c index bits are contiguous in
+// HBM (runs of 2^c * 16 bytes per wavefront access), the remaining k - c
+// tile bits are gathered through a per-pass offset table.  Each workgroup
+// walks tiles t = blockIdx.x, blockIdx.x + gridDim.x, ... of one instance
+// (blockIdx.y), so the per-instance reduction tree does not depend on the
+// batch size.
+#include "internal.h"
+
+namespace vqe {
+
+namespace {
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b)
+{
+    return make_double2(a.x + b.x, a.y + b.y);
+}
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+
+__device__ __forceinline__ uint32_t insert_zeros(uint32_t j, int nfix, const uint8_t *pos)
+{
+    for (int i = 0; i < nfix; ++i) {
+        const uint32_t p = pos[i];
+        j = ((j >> p) << (p + 1)) | (j & ((1u << p) - 1u));
+    }
+    return j;
+}
+
+__device__ __forceinline__ uint64_t tile_base(const TileGeom &g, int64_t t)
+{
+    uint64_t base = 0;
+    for (int i = 0; i < g.nout; ++i)
+        if ((t >> i) & 1) base |= 1ull << g.opos[i];
+    return base;
+}
+
+// offsets of the gathered (non-contiguous) part of a tile
+__device__ __forceinline__ void fill_hoff(const TileGeom &g, uint64_t *hoff)
+{
+    const int nh = 1 << (g.k - g.c);
+    for (int h = threadIdx.x; h < nh; h += blockDim.x) {
+        uint64_t o = 0;
+        for (int i = 0; i < g.k - g.c; ++i)
+            if ((h >> i) & 1) o |= 1ull << g.tpos[g.c + i];
+        hoff[h] = o;
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// sum of v over the workgroup (kThreads threads), fixed order; result in
+// thread 0.  red must hold kThreads/64 doubles.
+__device__ __forceinline__ double block_sum(double v, double *red)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+    __syncthreads();
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+__global__ void k_prepare(double2 *__restrict__ psi, uint64_t dim_mask, uint64_t total,
+                          uint64_t ref)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride)
+        psi[i] = make_double2((i & dim_mask) == ref ? 1.0 : 0.0, 0.0);
+}
+
+// 2x2 matrix of gate g of instance b on its pair (first, second)
+__global__ void k_gate_mats(const GateDev *__restrict__ gates, int n_gates,
+                            const double *__restrict__ theta, int n_params, int64_t batch,
+                            double2 *__restrict__ mats)
+{
+    const int64_t total = batch * n_gates;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = i / n_gates;
+    const int g = (int)(i - b * n_gates);
+    const GateDev gd = gates[g];
+    const double a = gd.pidx >= 0 ? theta[b * n_params + gd.pidx] : gd.fixed;
+    double s, c;
+    sincos(0.5 * a, &s, &c);
+    double2 u00 = {0, 0}, u01 = {0, 0}, u10 = {0, 0}, u11 = {0, 0};
+    switch (gd.kind) {
+    case VQE_GATE_RX: u00 = {c, 0}; u01 = {0, -s}; u10 = {0, -s}; u11 = {c, 0}; break;
+    case VQE_GATE_RY:
+    case VQE_GATE_SINGLE_EXC:
+    case VQE_GATE_DOUBLE_EXC: u00 = {c, 0}; u01 = {-s, 0}; u10 = {s, 0}; u11 = {c, 0}; break;
+    case VQE_GATE_RZ: u00 = {c, -s}; u11 = {c, s}; break;
+    case VQE_GATE_H: {
+        const double r = 0.70710678118654752440;
+        u00 = {r, 0}; u01 = {r, 0}; u10 = {r, 0}; u11 = {-r, 0};
+        break;
+    }
+    case VQE_GATE_X:
+    case VQE_GATE_CNOT: u01 = {1, 0}; u10 = {1, 0}; break;
+    case VQE_GATE_CZ: u00 = {1, 0}; u11 = {-1, 0}; break;
+    }
+    double2 *m = mats + i * 4;
+    m[0] = u00;
+    m[1] = u01;
+    m[2] = u10;
+    m[3] = u11;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// forward pass: apply the pass's ops in order to every tile
+__global__ __launch_bounds__(kThreads) void k_forward_pass(
+    TileGeom g, const OpDesc *__restrict__ ops, int nops, const double2 *__restrict__ mats,
+    int n_gates, double2 *__restrict__ psi, int64_t tiles)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    double2 *tile = reinterpret_cast<double2 *>(smem);
+    uint64_t *hoff = reinterpret_cast<uint64_t *>(smem + (16u << g.k));
+    const int tid = threadIdx.x;
+    const uint64_t dim = 1ull << g.n;
+    double2 *st = psi + (uint64_t)blockIdx.y * dim;
+    const double2 *M = mats + (size_t)blockIdx.y * n_gates * 4;
+    const int T = 1 << g.k;
+    const uint32_t lowm = (1u << g.c) - 1u;
+    fill_hoff(g, hoff);
+    __syncthreads();
+    for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+        const uint64_t base = tile_base(g, t);
+        for (int j = tid; j < T; j += kThreads) tile[j] = st[base + hoff[j >> g.c] + (j & lowm)];
+        __syncthreads();
+        for (int q = 0; q < nops; ++q) {
+            const OpDesc o = ops[q];
+            if ((base & o.cmask_out) != o.cval_out) continue;
+            const double2 u00 = M[o.gate * 4 + 0], u01 = M[o.gate * 4 + 1];
+            const double2 u10 = M[o.gate * 4 + 2], u11 = M[o.gate * 4 + 3];
+            const int np = 1 << (g.k - o.nfix);
+            for (int j = tid; j < np; j += kThreads) {
+                const uint32_t p0 = insert_zeros((uint32_t)j, o.nfix, o.fixpos) | o.fixed_bits;
+                const uint32_t p1 = p0 ^ o.m;
+                const double2 a = tile[p0], b = tile[p1];
+                if (o.cls == CLS_SWAP) {
+                    tile[p0] = b;
+                    tile[p1] = a;
+                } else if (o.cls == CLS_DIAG) {
+                    tile[p0] = cmul(u00, a);
+                    tile[p1] = cmul(u11, b);
+                } else {
+                    tile[p0] = cadd(cmul(u00, a), cmul(u01, b));
+                    tile[p1] = cadd(cmul(u10, a), cmul(u11, b));
+                }
+            }
+            __syncthreads();
+        }
+        for (int j = tid; j < T; j += kThreads) st[base + hoff[j >> g.c] + (j & lowm)] = tile[j];
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// reverse (adjoint) pass: for each op, in the plan's (reversed) order,
+//   g_l += Im <lam|G_l|psi> over the tile's active pairs, then
+//   psi <- U_l^dag psi, lam <- U_l^dag lam.
+// Per-op sums are reduced per wave into LDS slots red[slot][wave] (summed
+// across this workgroup's tiles), then written as one partial per
+// (instance, parametric gate, workgroup).
+__global__ __launch_bounds__(kThreads) void k_reverse_pass(
+    TileGeom g, const OpDesc *__restrict__ ops, int nops, int n_param_ops,
+    const double2 *__restrict__ mats, int n_gates, double2 *__restrict__ psi,
+    double2 *__restrict__ lam, int64_t tiles, double *__restrict__ partials, int n_pgates)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    double2 *tp = reinterpret_cast<double2 *>(smem);
+    double2 *tl = tp + (1u << g.k);
+    uint64_t *hoff = reinterpret_cast<uint64_t *>(smem + (32u << g.k));
+    double *red = reinterpret_cast<double *>(hoff + (1u << (g.k - g.c)));
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint64_t dim = 1ull << g.n;
+    double2 *sp = psi + (uint64_t)blockIdx.y * dim;
+    double2 *sl = lam + (uint64_t)blockIdx.y * dim;
+    const double2 *M = mats + (size_t)blockIdx.y * n_gates * 4;
+    const int T = 1 << g.k;
+    const uint32_t lowm = (1u << g.c) - 1u;
+    fill_hoff(g, hoff);
+    for (int i = tid; i < n_param_ops * 4; i += kThreads) red[i] = 0.0;
+    __syncthreads();
+    for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+        const uint64_t base = tile_base(g, t);
+        for (int j = tid; j < T; j += kThreads) {
+            const uint64_t gi = base + hoff[j >> g.c] + (j & lowm);
+            tp[j] = sp[gi];
+            tl[j] = sl[gi];
+        }
+        __syncthreads();
+        int slot = 0;
+        for (int q = 0; q < nops; ++q) {
+            const OpDesc o = ops[q];
+            const bool param = o.pgate >= 0;
+            const int my_slot = slot;
+            if (param) ++slot;
+            if ((base & o.cmask_out) != o.cval_out) continue;
+            // U^dagger
+            const double2 v00 = cconj(M[o.gate * 4 + 0]), v01 = cconj(M[o.gate * 4 + 2]);
+            const double2 v10 = cconj(M[o.gate * 4 + 1]), v11 = cconj(M[o.gate * 4 + 3]);
+            const int np = 1 << (g.k - o.nfix);
+            double acc = 0.0;
+            for (int j = tid; j < np; j += kThreads) {
+                const uint32_t p0 = insert_zeros((uint32_t)j, o.nfix, o.fixpos) | o.fixed_bits;
+                const uint32_t p1 = p0 ^ o.m;
+                const double2 a = tp[p0], b = tp[p1];
+                const double2 la = tl[p0], lb = tl[p1];
+                if (param) {
+                    if (o.gen == GEN_Y)  // Im(<la|-i b> + <lb|i a>)
+                        acc += -(la.x * b.x + la.y * b.y) + (lb.x * a.x + lb.y * a.y);
+                    else if (o.gen == GEN_X)  // Im(<la|b> + <lb|a>)
+                        acc += (la.x * b.y - la.y * b.x) + (lb.x * a.y - lb.y * a.x);
+                    else  // GEN_Z: Im(<la|a> - <lb|b>)
+                        acc += (la.x * a.y - la.y * a.x) - (lb.x * b.y - lb.y * b.x);
+                }
+                if (o.cls == CLS_SWAP) {
+                    tp[p0] = b;
+                    tp[p1] = a;
+                    tl[p0] = lb;
+                    tl[p1] = la;
+                } else if (o.cls == CLS_DIAG) {
+                    tp[p0] = cmul(v00, a);
+                    tp[p1] = cmul(v11, b);
+                    tl[p0] = cmul(v00, la);
+                    tl[p1] = cmul(v11, lb);
+                } else {
+                    tp[p0] = cadd(cmul(v00, a), cmul(v01, b));
+                    tp[p1] = cadd(cmul(v10, a), cmul(v11, b));
+                    tl[p0] = cadd(cmul(v00, la), cmul(v01, lb));
+                    tl[p1] = cadd(cmul(v10, la), cmul(v11, lb));
+                }
+            }
+            if (param) {
+                acc = wave_sum(acc);
+                if (lane == 0) red[my_slot * 4 + wave] += acc;
+            }
+            __syncthreads();
+        }
+        for (int j = tid; j < T; j += kThreads) {
+            const uint64_t gi = base + hoff[j >> g.c] + (j & lowm);
+            sp[gi] = tp[j];
+            sl[gi] = tl[j];
+        }
+        __syncthreads();
+    }
+    // one partial per parametric op of this pass
+    if (tid == 0) {
+        int slot = 0;
+        const int W = gridDim.x;
+        for (int q = 0; q < nops; ++q) {
+            const int pg = ops[q].pgate;
+            if (pg < 0) continue;
+            const double v = red[slot * 4 + 0] + red[slot * 4 + 1] + red[slot * 4 + 2] + red[slot * 4 + 3];
+            partials[((size_t)blockIdx.y * n_pgates + pg) * W + blockIdx.x] = v;
+            ++slot;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pauli sweep over the groups of one sweep.
+//
+// Expectation (lam == nullptr), paired over (b, b ^ f) with b's pivot bit 0,
+// w = conj(psi[b ^ f]) psi[b], sigma_t(b) = (-1)^{z_t . b}:
+//   f != 0:  2 * (Re w * sum_{real t} w_t sigma_t(b) - Im w * sum_{imag t} w_t sigma_t(b))
+//   f == 0:  |psi_b|^2 * sum_t w_t sigma_t(b)
+// H psi (lam != nullptr): with A = sum_real w sigma(b), B = sum_imag w sigma(b),
+//   lam[b ^ f] += (A + iB) psi[b],   lam[b] += (A - iB) psi[b ^ f]
+// (kappa_t = w_t or i w_t, sigma_t(b ^ f) = sigma_t(b) (-1)^{ny_t}).
+// The sign from index bits outside the tile, (-1)^{z_t . base}, is folded
+// into w_t per tile.
+__device__ __forceinline__ void term_sums(const TermDev *__restrict__ terms, int tb, int tm,
+                                          int te, uint64_t base, uint32_t b, double &A,
+                                          double &B)
+{
+    A = 0.0;
+    B = 0.0;
+    for (int t = tb; t < tm; ++t) {
+        const TermDev d = terms[t];
+        const int s = (__popcll(d.zfull & base) + __popc(d.zloc & b)) & 1;
+        A += s ? -d.w : d.w;
+    }
+    for (int t = tm; t < te; ++t) {
+        const TermDev d = terms[t];
+        const int s = (__popcll(d.zfull & base) + __popc(d.zloc & b)) & 1;
+        B += s ? -d.w : d.w;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_pauli_sweep(
+    TileGeom g, const GroupDev *__restrict__ groups, int ngroups,
+    const int32_t *__restrict__ toff, int n_ugroups, const TermDev *__restrict__ terms,
+    int shared_ham, const double2 *__restrict__ psi, double2 *__restrict__ lam, int64_t tiles,
+    int first, int last, double *__restrict__ partials, int n_slots, int slot)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const bool hpsi = lam != nullptr;
+    double2 *tp = reinterpret_cast<double2 *>(smem);
+    double2 *tl = tp + (1u << g.k);
+    uint64_t *hoff = reinterpret_cast<uint64_t *>(smem + ((hpsi ? 32u : 16u) << g.k));
+    double *red = reinterpret_cast<double *>(hoff + (1u << (g.k - g.c)));
+    const int tid = threadIdx.x;
+    const uint64_t dim = 1ull << g.n;
+    const int inst = blockIdx.y;
+    const double2 *sp = psi + (uint64_t)inst * dim;
+    double2 *sl = hpsi ? lam + (uint64_t)inst * dim : nullptr;
+    const int32_t *to = toff + (size_t)(shared_ham ? 0 : inst) * n_ugroups * 3;
+    const int T = 1 << g.k;
+    const uint32_t lowm = (1u << g.c) - 1u;
+    fill_hoff(g, hoff);
+    __syncthreads();
+    double acc = 0.0;
+    for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+        const uint64_t base = tile_base(g, t);
+        for (int j = tid; j < T; j += kThreads) {
+            tp[j] = sp[base + hoff[j >> g.c] + (j & lowm)];
+            if (hpsi) tl[j] = make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        for (int q = 0; q < ngroups; ++q) {
+            const GroupDev gd = groups[q];
+            const int tb = to[gd.ugroup * 3 + 0], tm = to[gd.ugroup * 3 + 1], te = to[gd.ugroup * 3 + 2];
+            if (te == tb) continue;
+            if (gd.floc == 0) {
+                for (int j = tid; j < T; j += kThreads) {
+                    double A, B;
+                    term_sums(terms, tb, tm, te, base, (uint32_t)j, A, B);
+                    const double2 a = tp[j];
+                    if (hpsi)
+                        tl[j] = cadd(tl[j], make_double2(A * a.x, A * a.y));
+                    else
+                        acc += (a.x * a.x + a.y * a.y) * A;
+                }
+            } else {
+                const uint32_t pv = gd.pivot;
+                for (int j = tid; j < (T >> 1); j += kThreads) {
+                    const uint32_t b = (((uint32_t)j >> pv) << (pv + 1)) | ((uint32_t)j & ((1u << pv) - 1u));
+                    const uint32_t bf = b ^ gd.floc;
+                    double A, B;
+                    term_sums(terms, tb, tm, te, base, b, A, B);
+                    const double2 x0 = tp[b], x1 = tp[bf];
+                    if (hpsi) {
+                        // lam[bf] += (A + iB) x0 ; lam[b] += (A - iB) x1
+                        tl[bf] = cadd(tl[bf], make_double2(A * x0.x - B * x0.y, A * x0.y + B * x0.x));
+                        tl[b] = cadd(tl[b], make_double2(A * x1.x + B * x1.y, A * x1.y - B * x1.x));
+                    } else {
+                        // w = conj(x1) x0
+                        const double wr = x1.x * x0.x + x1.y * x0.y;
+                        const double wi = x1.x * x0.y - x1.y * x0.x;
+                        acc += 2.0 * (wr * A - wi * B);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        if (hpsi) {
+            for (int j = tid; j < T; j += kThreads) {
+                const uint64_t gi = base + hoff[j >> g.c] + (j & lowm);
+                double2 v = tl[j];
+                if (!first) v = cadd(v, sl[gi]);
+                sl[gi] = v;
+                if (last) {
+                    const double2 a = tp[j];
+                    acc += a.x * v.x + a.y * v.y;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (!hpsi || last) {
+        const double s = block_sum(acc, red);
+        if (tid == 0) partials[((size_t)inst * n_slots + slot) * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+// out[inst * stride] = scale * sum_{slot, wg} partials[inst][slot][wg], fixed order
+__global__ __launch_bounds__(kThreads) void k_reduce_slots(const double *__restrict__ partials,
+                                                           int n, double *__restrict__ out,
+                                                           int64_t stride, double scale)
+{
+    __shared__ double red[kThreads / 64];
+    const double *p = partials + (size_t)blockIdx.x * n;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += kThreads) s += p[i];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) out[(int64_t)blockIdx.x * stride] = scale * s;
+}
+
+// grad[inst][p] = sum over the parametric gates using p (ascending) of
+// sum_wg partials[inst][pgate][wg]
+__global__ __launch_bounds__(kThreads) void k_grad_reduce(const double *__restrict__ partials,
+                                                          int n_pgates, int W,
+                                                          const int32_t *__restrict__ off,
+                                                          const int32_t *__restrict__ idx,
+                                                          int n_params, double *__restrict__ grad)
+{
+    __shared__ double red[kThreads / 64];
+    const int p = blockIdx.x, inst = blockIdx.y;
+    double s = 0.0;
+    for (int e = off[p]; e < off[p + 1]; ++e) {
+        const double *q = partials + ((size_t)inst * n_pgates + idx[e]) * W;
+        for (int i = threadIdx.x; i < W; i += kThreads) s += q[i];
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) grad[(size_t)inst * n_params + p] = s;
+}
+
+__global__ void k_adam(int64_t count, double *__restrict__ theta, double *__restrict__ m,
+                       double *__restrict__ v, const double *__restrict__ g, double lr, double b1,
+                       double b2, double eps, double c1, double c2)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double gi = g[i];
+        const double mi = b1 * m[i] + (1.0 - b1) * gi;
+        const double vi = b2 * v[i] + (1.0 - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        theta[i] -= lr * (mi / c1) / (sqrt(vi / c2) + eps);
+    }
+}
+
+__global__ void k_gd(int64_t count, double *__restrict__ theta, const double *__restrict__ g,
+                     double lr)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        theta[i] -= lr * g[i];
+}
+
+__global__ void k_fill(double *__restrict__ p, int64_t count, double value)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+inline int grid_for(int64_t n, int block) { return (int)std::min<int64_t>((n + block - 1) / block, 1 << 20); }
+
+template <typename K>
+hipError_t ensure_lds(K kernel, size_t bytes)
+{
+    if (bytes <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_prepare(double2 *psi, int n, int64_t batch, uint64_t ref, hipStream_t s)
+{
+    const uint64_t dim = 1ull << n;
+    const uint64_t total = dim * (uint64_t)batch;
+    const int blocks = (int)std::min<uint64_t>((total + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_prepare, dim3(blocks), dim3(256), 0, s, psi, dim - 1, total, ref);
+    return hipGetLastError();
+}
+
+hipError_t launch_gate_mats(const GateDev *gates, int n_gates, const double *theta, int n_params,
+                            int64_t batch, double2 *mats, hipStream_t s)
+{
+    const int64_t total = batch * n_gates;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gate_mats, dim3(grid_for(total, 128)), dim3(128), 0, s, gates, n_gates,
+                       theta, n_params, batch, mats);
+    return hipGetLastError();
+}
+
+static size_t fwd_lds(const TileGeom &g) { return (16u << g.k) + (8u << (g.k - g.c)); }
+static size_t rev_lds(const TileGeom &g, int nparam)
+{
+    return (32u << g.k) + (8u << (g.k - g.c)) + 32u * (size_t)std::max(nparam, 1);
+}
+
+hipError_t launch_forward_pass(const PassPlan &pp, const OpDesc *ops, const double2 *mats,
+                               int n_gates, double2 *psi, int64_t batch, int wg_max,
+                               hipStream_t s)
+{
+    const TileGeom &g = pp.geom;
+    const int64_t tiles = 1ll << g.nout;
+    const int W = (int)std::min<int64_t>(tiles, wg_max);
+    const size_t lds = fwd_lds(g);
+    hipError_t e = ensure_lds(k_forward_pass, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_forward_pass, dim3(W, (unsigned)batch), dim3(kThreads), lds, s, g,
+                       ops + pp.op_begin, pp.op_count, mats, n_gates, psi, tiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_reverse_pass(const PassPlan &pp, const OpDesc *ops, const double2 *mats,
+                               int n_gates, double2 *psi, double2 *lam, int64_t batch,
+                               int wg_per_inst, double *partials, int n_pgates, hipStream_t s)
+{
+    const TileGeom &g = pp.geom;
+    const int64_t tiles = 1ll << g.nout;
+    const size_t lds = rev_lds(g, pp.n_param_ops);
+    hipError_t e = ensure_lds(k_reverse_pass, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reverse_pass, dim3(wg_per_inst, (unsigned)batch), dim3(kThreads), lds, s,
+                       g, ops + pp.op_begin, pp.op_count, pp.n_param_ops, mats, n_gates, psi, lam,
+                       tiles, partials, n_pgates);
+    return hipGetLastError();
+}
+
+hipError_t launch_pauli_sweep(const SweepPlan &sp, const PauliPlan &pp, int sweep_idx,
+                              const double2 *psi, double2 *lam, int64_t batch, int shared_ham,
+                              int wg_per_inst, double *partials, int n_slots, bool write_lambda,
+                              bool first, bool last, hipStream_t s)
+{
+    const TileGeom &g = sp.geom;
+    const int64_t tiles = 1ll << g.nout;
+    const size_t lds = ((write_lambda ? 32u : 16u) << g.k) + (8u << (g.k - g.c)) + 64;
+    hipError_t e = ensure_lds(k_pauli_sweep, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_pauli_sweep, dim3(wg_per_inst, (unsigned)batch), dim3(kThreads), lds, s, g,
+                       reinterpret_cast<const GroupDev *>(pp.groups.p) + sp.grp_begin, sp.grp_count,
+                       reinterpret_cast<const int32_t *>(pp.toff.p), pp.n_ugroups,
+                       reinterpret_cast<const TermDev *>(pp.terms.p), shared_ham, psi,
+                       write_lambda ? lam : nullptr, tiles, (int)first, (int)last, partials,
+                       n_slots, write_lambda ? 0 : sweep_idx);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_slots(const double *partials, int n_slots, int wg_per_inst, int64_t batch,
+                               double *out, int64_t out_stride, double scale, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reduce_slots, dim3((unsigned)batch), dim3(kThreads), 0, s, partials,
+                       n_slots * wg_per_inst, out, out_stride, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_reduce(const double *partials, int n_pgates, int wg_per_inst,
+                              const int32_t *pmap_off, const int32_t *pmap_idx, int n_params,
+                              int64_t batch, double *grad, hipStream_t s)
+{
+    if (n_params == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_grad_reduce, dim3(n_params, (unsigned)batch), dim3(kThreads), 0, s,
+                       partials, n_pgates, wg_per_inst, pmap_off, pmap_idx, n_params, grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(int64_t count, double *theta, double *m, double *v, const double *g, int t,
+                       double lr, double b1, double b2, double eps, hipStream_t s)
+{
+    if (count == 0) return hipSuccess;
+    const double c1 = 1.0 - std::pow(b1, (double)t), c2 = 1.0 - std::pow(b2, (double)t);
+    hipLaunchKernelGGL(k_adam, dim3(grid_for(count, 256)), dim3(256), 0, s, count, theta, m, v, g,
+                       lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_gd(int64_t count, double *theta, const double *g, double lr, hipStream_t s)
+{
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gd, dim3(grid_for(count, 256)), dim3(256), 0, s, count, theta, g, lr);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(double *p, int64_t count, double value, hipStream_t s)
+{
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(count, 256)), dim3(256), 0, s, p, count, value);
+    return hipGetLastError();
+}
+
+}  // namespace vqe

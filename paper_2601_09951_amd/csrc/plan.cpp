@@ -1,0 +1,439 @@
+// plan.cpp -- host-side compilers of libvqe.
+//
+// * Circuits: every gate of the ansatz (Eqs. 4-5 of arXiv 2601.09951 and the
+//   hardware-efficient ansatz of the scaling study, Section 5.2.5) is a 2x2
+//   update of amplitude pairs (b, b ^ m) selected by a bit pattern.  The
+//   circuit compiler packs gates into passes: a pass holds a tile of 2^k
+//   amplitudes (all index bits of the tile set S) in LDS and applies every
+//   gate whose flip bits lie in S, so one HBM round trip serves many gates.
+//   Gates on disjoint qubits commute, so a gate may join a pass ahead of an
+//   earlier gate that is blocked, provided it touches none of the blocked
+//   gates' qubits.
+// * Pauli sums (Eq. 2, Section 3.2): terms are grouped by flip mask
+//   f = xmask.  A sweep walks tiles over a bit set S and serves every group
+//   whose flip bits lie in S; sweeps are chosen greedily to cover all groups.
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <set>
+#include <sstream>
+
+#include "internal.h"
+
+namespace vqe {
+
+namespace {
+
+constexpr int kMaxParamOpsPerPass = 256;
+
+inline int popc(uint64_t v) { return __builtin_popcountll(v); }
+inline int bit_of_wire(int n, int w) { return n - 1 - w; }
+
+// compress the bits of v at positions S (ascending) into local bits 0..|S|-1
+uint32_t compress(uint64_t v, const std::vector<int> &S)
+{
+    uint32_t out = 0;
+    for (size_t i = 0; i < S.size(); ++i)
+        if ((v >> S[i]) & 1) out |= 1u << i;
+    return out;
+}
+
+uint64_t mask_of(const std::vector<int> &S)
+{
+    uint64_t m = 0;
+    for (int b : S) m |= 1ull << b;
+    return m;
+}
+
+std::vector<int> bits_of(uint64_t m)
+{
+    std::vector<int> v;
+    for (int b = 0; b < 64; ++b)
+        if ((m >> b) & 1) v.push_back(b);
+    return v;
+}
+
+// Fill a tile set up to exactly k bits: keep `must`, then add the lowest
+// unused bits.
+std::vector<int> complete_tile(uint64_t must, int n, int k)
+{
+    uint64_t S = must;
+    for (int b = 0; b < n && popc(S) < k; ++b) S |= 1ull << b;
+    return bits_of(S);
+}
+
+}  // namespace
+
+TileGeom make_geom(int n, int k, int c, const std::vector<int> &tile_bits)
+{
+    TileGeom g;
+    std::memset(&g, 0, sizeof(g));
+    g.n = n;
+    g.k = k;
+    g.c = c;
+    g.nout = n - k;
+    for (int i = 0; i < k; ++i) g.tpos[i] = (uint8_t)tile_bits[i];
+    uint64_t tm = mask_of(tile_bits);
+    int j = 0;
+    for (int b = 0; b < n; ++b)
+        if (!((tm >> b) & 1)) g.opos[j++] = (uint8_t)b;
+    return g;
+}
+
+// ---------------------------------------------------------------------------
+// circuits
+// ---------------------------------------------------------------------------
+int build_circuit_gates(Circ *C, int64_t n_gates, const int32_t *kind, const int32_t *wires,
+                        const int32_t *pidx, const double *fixed, std::string &err)
+{
+    const int n = C->n;
+    C->gates.clear();
+    C->pgate_of_gate.clear();
+    int npg = 0;
+    for (int64_t g = 0; g < n_gates; ++g) {
+        GateHost h;
+        std::memset(&h, 0, sizeof(h));
+        h.kind = kind[g];
+        int arity;
+        bool parametric;
+        switch (h.kind) {
+        case VQE_GATE_RX: case VQE_GATE_RY: case VQE_GATE_RZ: arity = 1; parametric = true; break;
+        case VQE_GATE_H: case VQE_GATE_X: arity = 1; parametric = false; break;
+        case VQE_GATE_CNOT: case VQE_GATE_CZ: arity = 2; parametric = false; break;
+        case VQE_GATE_SINGLE_EXC: arity = 2; parametric = true; break;
+        case VQE_GATE_DOUBLE_EXC: arity = 4; parametric = true; break;
+        default: {
+            std::ostringstream os;
+            os << "gate " << g << ": unknown kind " << h.kind;
+            err = os.str();
+            return VQE_EUNSUPPORTED;
+        }
+        }
+        h.nw = arity;
+        for (int j = 0; j < 4; ++j) {
+            int w = wires[4 * g + j];
+            if (j < arity) {
+                if (w < 0 || w >= n) {
+                    std::ostringstream os;
+                    os << "gate " << g << ": wire " << w << " out of range [0, " << n << ")";
+                    err = os.str();
+                    return VQE_EINVAL;
+                }
+                for (int i = 0; i < j; ++i)
+                    if (h.wires[i] == w) {
+                        std::ostringstream os;
+                        os << "gate " << g << ": repeated wire " << w;
+                        err = os.str();
+                        return VQE_EINVAL;
+                    }
+            }
+            h.wires[j] = j < arity ? w : -1;
+        }
+        h.pidx = pidx ? pidx[g] : -1;
+        h.fixed = fixed ? fixed[g] : 0.0;
+        if (h.pidx >= C->n_params || h.pidx < -1) {
+            std::ostringstream os;
+            os << "gate " << g << ": parameter index " << h.pidx << " outside [-1, " << C->n_params << ")";
+            err = os.str();
+            return VQE_EINVAL;
+        }
+        if (h.pidx >= 0 && !parametric) {
+            std::ostringstream os;
+            os << "gate " << g << ": a fixed gate kind cannot take a parameter";
+            err = os.str();
+            return VQE_EINVAL;
+        }
+        if (h.pidx < 0 && !std::isfinite(h.fixed)) {
+            err = "non-finite fixed angle";
+            return VQE_EINVAL;
+        }
+        auto B = [&](int j) { return 1ull << bit_of_wire(n, h.wires[j]); };
+        h.cls = CLS_GENERAL;
+        h.gen = GEN_NONE;
+        switch (h.kind) {
+        case VQE_GATE_RX: h.m = B(0); h.gen = GEN_X; break;
+        case VQE_GATE_RY: h.m = B(0); h.gen = GEN_Y; break;
+        case VQE_GATE_RZ: h.m = B(0); h.gen = GEN_Z; h.cls = CLS_DIAG; break;
+        case VQE_GATE_H: h.m = B(0); break;
+        case VQE_GATE_X: h.m = B(0); h.cls = CLS_SWAP; break;
+        case VQE_GATE_CNOT: h.m = B(1); h.cmask = h.cval = B(0); h.cls = CLS_SWAP; break;
+        case VQE_GATE_CZ: h.m = B(1); h.cmask = h.cval = B(0); h.cls = CLS_DIAG; break;
+        case VQE_GATE_SINGLE_EXC:  // first element |01> on (a, b)
+            h.m = B(0) | B(1); h.first = B(1); h.gen = GEN_Y; break;
+        case VQE_GATE_DOUBLE_EXC:  // first element |0011> on (a, b, c, d)
+            h.m = B(0) | B(1) | B(2) | B(3); h.first = B(2) | B(3); h.gen = GEN_Y; break;
+        }
+        if (h.pidx < 0) h.gen = GEN_NONE;
+        C->gates.push_back(h);
+        C->pgate_of_gate.push_back(h.pidx >= 0 ? npg++ : -1);
+    }
+    C->n_pgates = npg;
+    return VQE_OK;
+}
+
+static void free_plan(Context *ctx, CircPlan *p)
+{
+    if (p) dev_free(ctx, p->ops);
+}
+
+CircPlan *get_circ_plan(Circ *C, bool reverse, int k, int c, int *rc)
+{
+    const int n = C->n;
+    int keff = n <= k ? n : k;
+    int ceff = n <= k ? n : std::min(c, k);
+    auto &cache = reverse ? C->rev : C->fwd;
+    auto key = std::make_pair(keff, ceff);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+        *rc = VQE_OK;
+        return it->second.get();
+    }
+    std::unique_ptr<CircPlan> plan(new CircPlan);
+    plan->k = keff;
+    plan->c = ceff;
+    plan->reverse = reverse;
+
+    const int G = (int)C->gates.size();
+    std::vector<int> order(G);
+    for (int g = 0; g < G; ++g) order[g] = reverse ? G - 1 - g : g;
+    std::vector<char> done(G, 0);
+    int remaining = G;
+    std::vector<OpDesc> ops;
+    const uint64_t low = ceff >= 64 ? ~0ull : ((1ull << ceff) - 1);
+
+    while (remaining > 0) {
+        uint64_t S = low;
+        uint64_t blocked = 0;
+        std::vector<int> take;
+        int nparam = 0;
+        for (int oi = 0; oi < G; ++oi) {
+            int g = order[oi];
+            if (done[g]) continue;
+            const GateHost &h = C->gates[g];
+            uint64_t touched = h.m | h.cmask;
+            if (touched & blocked) {
+                blocked |= touched;
+                continue;
+            }
+            uint64_t need = h.m & ~S;
+            bool room = popc(S) + popc(need) <= keff;
+            bool param_room = h.pidx < 0 || nparam < kMaxParamOpsPerPass;
+            if (room && param_room) {
+                S |= need;
+                take.push_back(g);
+                if (h.pidx >= 0) ++nparam;
+            } else {
+                blocked |= touched;
+            }
+        }
+        if (take.empty()) {  // cannot happen: a gate touches at most 4 bits
+            *rc = VQE_EUNSUPPORTED;
+            return nullptr;
+        }
+        std::vector<int> tile = complete_tile(S, n, keff);
+        PassPlan pp;
+        pp.geom = make_geom(n, keff, ceff, tile);
+        pp.op_begin = (int)ops.size();
+        pp.op_count = (int)take.size();
+        pp.n_param_ops = nparam;
+        plan->max_param_ops = std::max(plan->max_param_ops, nparam);
+        const uint64_t tmask = mask_of(tile);
+        for (int g : take) {
+            const GateHost &h = C->gates[g];
+            OpDesc o;
+            std::memset(&o, 0, sizeof(o));
+            o.m = compress(h.m, tile);
+            uint64_t cin = h.cmask & tmask;
+            uint32_t cin_loc = compress(cin, tile);
+            o.fixed_bits = compress(h.first, tile) | compress(h.cval & tmask, tile);
+            o.cmask_out = h.cmask & ~tmask;
+            o.cval_out = h.cval & ~tmask;
+            o.gate = g;
+            o.pgate = C->pgate_of_gate[g];
+            o.cls = h.cls;
+            o.gen = h.gen;
+            uint32_t fixm = o.m | cin_loc;
+            o.nfix = (int8_t)popc(fixm);
+            int j = 0;
+            for (int b = 0; b < 32; ++b)
+                if ((fixm >> b) & 1) o.fixpos[j++] = (uint8_t)b;
+            ops.push_back(o);
+            done[g] = 1;
+            --remaining;
+        }
+        plan->passes.push_back(pp);
+    }
+    if (!ops.empty()) {
+        int r = upload(C->ctx, plan->ops, ops.data(), ops.size() * sizeof(OpDesc));
+        if (r) {
+            free_plan(C->ctx, plan.get());
+            *rc = r;
+            return nullptr;
+        }
+    }
+    plan->host_ops = std::move(ops);
+    CircPlan *out = plan.get();
+    cache[key] = std::move(plan);
+    *rc = VQE_OK;
+    return out;
+}
+
+// ---------------------------------------------------------------------------
+// Pauli sums
+// ---------------------------------------------------------------------------
+PauliPlan *get_pauli_plan(Context *ctx, int n_hams, Ham *const *hams, int n_inst, int k, int c,
+                          int *rc)
+{
+    const int n = hams[0]->n;
+    const int keff = n <= k ? n : k;
+    const int ceff = n <= k ? n : std::min(c, k);
+    std::ostringstream key;
+    key << n << ':' << keff << ':' << ceff << ':' << n_inst;
+    for (int i = 0; i < n_hams; ++i) key << ':' << hams[i]->id;
+    auto it = ctx->pauli_cache.find(key.str());
+    if (it != ctx->pauli_cache.end()) {
+        *rc = VQE_OK;
+        return it->second.get();
+    }
+    // bound the cache: plans are small, but a serving loop creates many
+    if (ctx->pauli_cache.size() >= 256) {
+        if (ctx->device >= 0) (void)hipDeviceSynchronize();
+        for (auto &kv : ctx->pauli_cache) {
+            dev_free(ctx, kv.second->groups);
+            dev_free(ctx, kv.second->toff);
+            dev_free(ctx, kv.second->terms);
+        }
+        ctx->pauli_cache.clear();
+    }
+
+    std::unique_ptr<PauliPlan> plan(new PauliPlan);
+    plan->n = n;
+    plan->n_inst = n_inst;
+    plan->k = keff;
+    plan->c = ceff;
+
+    // union of flip masks
+    std::set<uint64_t> fset;
+    for (int i = 0; i < n_hams; ++i)
+        for (uint64_t x : hams[i]->x) fset.insert(x);
+    std::vector<uint64_t> flips(fset.begin(), fset.end());  // ascending: 0 first if present
+    std::map<uint64_t, int> ug;
+    for (size_t g = 0; g < flips.size(); ++g) ug[flips[g]] = (int)g;
+    plan->n_ugroups = (int)flips.size();
+
+    // greedy sweep cover
+    const uint64_t low = ((1ull << ceff) - 1);
+    std::vector<int> sweep_of(flips.size(), -1);
+    std::vector<std::vector<int>> sweep_tiles;
+    std::vector<std::vector<int>> sweep_groups;
+    size_t assigned = 0;
+    while (assigned < flips.size()) {
+        uint64_t S = low;
+        for (;;) {
+            int best = -1, best_new = 1 << 30;
+            for (size_t g = 0; g < flips.size(); ++g) {
+                if (sweep_of[g] >= 0) continue;
+                uint64_t f = flips[g];
+                int nw = popc(f & ~S);
+                if (nw == 0) continue;
+                if (popc(S) + nw <= keff && nw < best_new) {
+                    best = (int)g;
+                    best_new = nw;
+                }
+            }
+            if (best < 0) break;
+            S |= flips[best];
+        }
+        std::vector<int> tile = complete_tile(S, n, keff);
+        uint64_t tmask = mask_of(tile);
+        int s = (int)sweep_tiles.size();
+        sweep_tiles.push_back(tile);
+        sweep_groups.emplace_back();
+        for (size_t g = 0; g < flips.size(); ++g) {
+            if (sweep_of[g] >= 0) continue;
+            if ((flips[g] & ~tmask) == 0) {
+                sweep_of[g] = s;
+                sweep_groups[s].push_back((int)g);
+                ++assigned;
+            }
+        }
+        if (sweep_groups[s].empty()) {  // a group wider than a tile: impossible for k >= 4
+            *rc = VQE_EUNSUPPORTED;
+            return nullptr;
+        }
+    }
+
+    std::vector<GroupDev> gdev;
+    for (size_t s = 0; s < sweep_tiles.size(); ++s) {
+        SweepPlan sp;
+        sp.geom = make_geom(n, keff, ceff, sweep_tiles[s]);
+        sp.grp_begin = (int)gdev.size();
+        sp.grp_count = (int)sweep_groups[s].size();
+        for (int g : sweep_groups[s]) {
+            GroupDev d;
+            std::memset(&d, 0, sizeof(d));
+            d.floc = compress(flips[g], sweep_tiles[s]);
+            d.pivot = d.floc ? (uint32_t)__builtin_ctz(d.floc) : 0u;
+            d.ugroup = g;
+            gdev.push_back(d);
+        }
+        plan->sweeps.push_back(sp);
+    }
+
+    // per-instance term tables, grouped by union group, real terms first
+    std::vector<int32_t> toff((size_t)n_inst * flips.size() * 3, 0);
+    std::vector<TermDev> terms;
+    for (int i = 0; i < n_inst; ++i) {
+        const Ham *H = hams[n_hams == 1 ? 0 : i];
+        // terms of this Hamiltonian by flip mask
+        std::map<uint64_t, std::vector<size_t>> by_f;
+        for (size_t t = 0; t < H->x.size(); ++t) by_f[H->x[t]].push_back(t);
+        for (size_t g = 0; g < flips.size(); ++g) {
+            int32_t *o = &toff[((size_t)i * flips.size() + g) * 3];
+            const std::vector<int> &tile = sweep_tiles[sweep_of[g]];
+            o[0] = (int32_t)terms.size();
+            auto itf = by_f.find(flips[g]);
+            int cnt = 0;
+            for (int pass = 0; pass < 2; ++pass) {
+                if (pass == 1) o[1] = (int32_t)terms.size();
+                if (itf == by_f.end()) continue;
+                for (size_t t : itf->second) {
+                    int ny = popc(H->x[t] & H->z[t]);
+                    if ((ny & 1) != pass) continue;
+                    TermDev d;
+                    std::memset(&d, 0, sizeof(d));
+                    d.zfull = H->z[t];
+                    d.zloc = compress(H->z[t], tile);
+                    // kappa = c i^ny: real part c (-1)^{ny/2} (ny even);
+                    // kappa = i w with w = c (-1)^{(ny-1)/2} (ny odd)
+                    int e = pass == 0 ? ny / 2 : (ny - 1) / 2;
+                    d.w = (e & 1) ? -H->c[t] : H->c[t];
+                    terms.push_back(d);
+                    ++cnt;
+                }
+            }
+            o[2] = (int32_t)terms.size();
+            plan->max_terms_group = std::max(plan->max_terms_group, cnt);
+        }
+        if (n_hams == 1) break;
+    }
+    int r = upload(ctx, plan->groups, gdev.data(), gdev.size() * sizeof(GroupDev));
+    if (!r) r = upload(ctx, plan->toff, toff.data(), toff.size() * sizeof(int32_t));
+    if (!r && !terms.empty()) r = upload(ctx, plan->terms, terms.data(), terms.size() * sizeof(TermDev));
+    if (r) {
+        dev_free(ctx, plan->groups);
+        dev_free(ctx, plan->toff);
+        dev_free(ctx, plan->terms);
+        *rc = r;
+        return nullptr;
+    }
+    plan->host_groups = std::move(gdev);
+    plan->host_toff = std::move(toff);
+    plan->host_terms = std::move(terms);
+    PauliPlan *out = plan.get();
+    ctx->pauli_cache[key.str()] = std::move(plan);
+    *rc = VQE_OK;
+    return out;
+}
+
+}  // namespace vqe

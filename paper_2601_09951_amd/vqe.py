@@ -1,0 +1,392 @@
+"""Python binding of libvqe: handles plus thin calls that marshal torch tensors.
+
+Every computation runs in the HIP library; this module only converts
+arguments (device pointers, the current HIP stream, host arrays) and raises
+on error codes.  PyTorch provides device memory and streams.
+
+Names follow the problem statement of arXiv 2601.09951: prepare the
+reference state, apply the ansatz U(theta), expect <psi|H|psi>, gradient,
+optimiser step, and the per-bond-length loop of Algorithm 1.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Sequence, Union
+
+import numpy as np
+import torch
+
+from . import capi
+from .capi import VQEError, check, lib
+
+_P = ctypes.c_void_p
+
+
+def _stream(device=None):
+    return _P(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t: torch.Tensor):
+    return _P(t.data_ptr())
+
+
+def _host(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _hp(a: np.ndarray):
+    return a.ctypes.data_as(_P)
+
+
+class Context:
+    """A libvqe context bound to one device (device=-1: host-only planning)."""
+
+    def __init__(self, device: int = 0):
+        h = _P()
+        rc = lib().vqe_ctx_create(int(device), ctypes.byref(h))
+        if rc:
+            raise VQEError(rc, f"vqe_ctx_create({device}) failed: {lib().vqe_strerror(rc).decode()}")
+        self._h = h
+        self.device = device
+
+    @property
+    def handle(self):
+        return self._h
+
+    def check(self, rc):
+        check(rc, self._h)
+
+    def set_tile(self, k_fwd: int = 0, k_rev: int = 0, c_low: int = 0):
+        self.check(lib().vqe_ctx_set_tile(self._h, k_fwd, k_rev, c_low))
+
+    def set_mem_budget(self, nbytes: int):
+        self.check(lib().vqe_ctx_set_mem_budget(self._h, int(nbytes)))
+
+    def reserve(self, nbytes: int):
+        self.check(lib().vqe_ctx_reserve(self._h, int(nbytes)))
+
+    def close(self):
+        if self._h:
+            lib().vqe_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Hamiltonian:
+    """A Pauli sum resident on the device (vqe_ham_t)."""
+
+    def __init__(self, ctx: Context, handle):
+        self.ctx = ctx
+        self._h = handle
+        n = ctypes.c_int()
+        t = ctypes.c_int64()
+        g = ctypes.c_int64()
+        ctx.check(lib().vqe_ham_info(handle, ctypes.byref(n), ctypes.byref(t), ctypes.byref(g)))
+        self.n_qubits, self.n_terms, self.n_groups = n.value, t.value, g.value
+
+    @classmethod
+    def from_pauli(cls, ctx: Context, n_qubits: int, xmask, zmask, coeff) -> "Hamiltonian":
+        x, z, c = _host(xmask, np.uint64), _host(zmask, np.uint64), _host(coeff, np.float64)
+        h = _P()
+        ctx.check(lib().vqe_ham_create(ctx.handle, int(n_qubits), int(c.shape[0]), _hp(x), _hp(z), _hp(c),
+                                       ctypes.byref(h)))
+        return cls(ctx, h)
+
+    @classmethod
+    def from_sum(cls, ctx: Context, pauli_sum) -> "Hamiltonian":
+        """From any object with n, xmask, zmask, coeff."""
+        return cls.from_pauli(ctx, pauli_sum.n, pauli_sum.xmask, pauli_sum.zmask, pauli_sum.coeff)
+
+    @classmethod
+    def from_integrals(cls, ctx: Context, h1, h2, e_core: float = 0.0) -> "Hamiltonian":
+        h1 = _host(h1, np.float64)
+        h2 = _host(h2, np.float64)
+        n_orb = h1.shape[0]
+        if h1.shape != (n_orb, n_orb) or h2.shape != (n_orb,) * 4:
+            raise ValueError("h1 must be [n_orb, n_orb] and h2 [n_orb]^4")
+        h = _P()
+        ctx.check(lib().vqe_ham_from_integrals(ctx.handle, n_orb, _hp(h1), _hp(h2), float(e_core),
+                                               ctypes.byref(h)))
+        return cls(ctx, h)
+
+    def terms(self):
+        x = np.zeros(self.n_terms, dtype=np.uint64)
+        z = np.zeros(self.n_terms, dtype=np.uint64)
+        c = np.zeros(self.n_terms, dtype=np.float64)
+        self.ctx.check(lib().vqe_ham_terms(self._h, _hp(x), _hp(z), _hp(c)))
+        return x, z, c
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            lib().vqe_ham_destroy(self._h)
+            self._h = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Circuit:
+    """An ansatz gate list compiled by the library (vqe_circ_t)."""
+
+    def __init__(self, ctx: Context, n_qubits: int, kinds: Sequence[Union[str, int]], wires, param_idx,
+                 fixed_angle=None, n_params: int = None, ref_index: int = 0):
+        k = _host([capi.GATE_CODES[x] if isinstance(x, str) else int(x) for x in kinds], np.int32)
+        w = _host(wires, np.int32).reshape(-1, 4)
+        p = _host(param_idx, np.int32)
+        f = _host(fixed_angle if fixed_angle is not None else np.zeros(len(k)), np.float64)
+        if n_params is None:
+            n_params = int(p.max()) + 1 if p.size and p.max() >= 0 else 0
+        h = _P()
+        ctx.check(lib().vqe_circ_create(ctx.handle, int(n_qubits), int(k.shape[0]), _hp(k), _hp(w), _hp(p),
+                                        _hp(f), int(n_params), ctypes.byref(h)))
+        self.ctx = ctx
+        self._h = h
+        self.n_qubits = int(n_qubits)
+        self.n_params = int(n_params)
+        self.n_gates = int(k.shape[0])
+        self.ref_index = int(ref_index)
+
+    @classmethod
+    def from_spec(cls, ctx: Context, spec) -> "Circuit":
+        """From any object with n, kinds, wires, param_idx, fixed_angle, n_params, ref_index."""
+        return cls(ctx, spec.n, spec.kinds, spec.wires, spec.param_idx, spec.fixed_angle, spec.n_params,
+                   spec.ref_index)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            lib().vqe_circ_destroy(self._h)
+            self._h = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _hams_array(hams):
+    if isinstance(hams, Hamiltonian):
+        hams = [hams]
+    arr = (_P * len(hams))(*[h.handle for h in hams])
+    return arr, len(hams)
+
+
+def _check_tensor(t: torch.Tensor, dtype, shape=None, name="tensor"):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+# ---------------------------------------------------------------------------
+# the hot path
+# ---------------------------------------------------------------------------
+def workspace_bytes(ctx: Context, circ: Circuit, hams, batch: int, want_grad: int) -> int:
+    arr, nh = _hams_array(hams)
+    out = ctypes.c_size_t()
+    ctx.check(lib().vqe_workspace_bytes(ctx.handle, circ.handle, nh, arr, int(batch), int(want_grad),
+                                        ctypes.byref(out)))
+    return out.value
+
+
+def workspace(ctx: Context, circ: Circuit, hams, batch: int, want_grad: int, device=None) -> torch.Tensor:
+    nbytes = workspace_bytes(ctx, circ, hams, batch, want_grad)
+    return torch.empty(nbytes, dtype=torch.uint8, device=device or f"cuda:{ctx.device}")
+
+
+def prepare_reference(ctx: Context, n_qubits: int, batch: int, ref_index: int, psi: torch.Tensor):
+    _check_tensor(psi, torch.complex128, (batch, 1 << n_qubits), "psi")
+    ctx.check(lib().vqe_prepare_reference(ctx.handle, n_qubits, batch, ref_index, _ptr(psi), _stream(psi.device)))
+
+
+def apply_ansatz(ctx: Context, circ: Circuit, theta: torch.Tensor, psi: torch.Tensor):
+    B = psi.shape[0]
+    _check_tensor(psi, torch.complex128, (B, 1 << circ.n_qubits), "psi")
+    _check_tensor(theta, torch.float64, (B, circ.n_params), "theta")
+    ctx.check(lib().vqe_apply_ansatz(ctx.handle, circ.handle, B, _ptr(theta), _ptr(psi), _stream(psi.device)))
+
+
+def expect(ctx: Context, hams, psi: torch.Tensor, out: torch.Tensor = None) -> torch.Tensor:
+    arr, nh = _hams_array(hams)
+    B = psi.shape[0]
+    _check_tensor(psi, torch.complex128, None, "psi")
+    if out is None:
+        out = torch.empty(B, dtype=torch.float64, device=psi.device)
+    _check_tensor(out, torch.float64, (B,), "energy")
+    ctx.check(lib().vqe_expect(ctx.handle, nh, arr, B, _ptr(psi), _ptr(out), _stream(psi.device)))
+    return out
+
+
+def apply_hamiltonian(ctx: Context, hams, psi: torch.Tensor, out: torch.Tensor = None) -> torch.Tensor:
+    arr, nh = _hams_array(hams)
+    _check_tensor(psi, torch.complex128, None, "psi")
+    if out is None:
+        out = torch.empty_like(psi)
+    _check_tensor(out, torch.complex128, tuple(psi.shape), "out")
+    ctx.check(lib().vqe_apply_hamiltonian(ctx.handle, nh, arr, psi.shape[0], _ptr(psi), _ptr(out),
+                                          _stream(psi.device)))
+    return out
+
+
+def energy(ctx: Context, circ: Circuit, hams, theta: torch.Tensor, ref_index: int = None,
+           ws: torch.Tensor = None, out: torch.Tensor = None) -> torch.Tensor:
+    B = theta.shape[0]
+    _check_tensor(theta, torch.float64, (B, circ.n_params), "theta")
+    arr, nh = _hams_array(hams)
+    ref = circ.ref_index if ref_index is None else ref_index
+    if ws is None:
+        ws = workspace(ctx, circ, hams, B, 0, theta.device)
+    if out is None:
+        out = torch.empty(B, dtype=torch.float64, device=theta.device)
+    ctx.check(lib().vqe_energy(ctx.handle, circ.handle, nh, arr, B, ref, _ptr(theta), _ptr(out), _ptr(ws),
+                               ws.numel(), _stream(theta.device)))
+    return out
+
+
+def energy_grad(ctx: Context, circ: Circuit, hams, theta: torch.Tensor, ref_index: int = None,
+                ws: torch.Tensor = None, out_e: torch.Tensor = None, out_g: torch.Tensor = None):
+    B = theta.shape[0]
+    _check_tensor(theta, torch.float64, (B, circ.n_params), "theta")
+    arr, nh = _hams_array(hams)
+    ref = circ.ref_index if ref_index is None else ref_index
+    if ws is None:
+        ws = workspace(ctx, circ, hams, B, 1, theta.device)
+    if out_e is None:
+        out_e = torch.empty(B, dtype=torch.float64, device=theta.device)
+    if out_g is None:
+        out_g = torch.empty(B, circ.n_params, dtype=torch.float64, device=theta.device)
+    ctx.check(lib().vqe_energy_grad(ctx.handle, circ.handle, nh, arr, B, ref, _ptr(theta), _ptr(out_e),
+                                    _ptr(out_g), _ptr(ws), ws.numel(), _stream(theta.device)))
+    return out_e, out_g
+
+
+def adam_step(ctx: Context, theta: torch.Tensor, m: torch.Tensor, v: torch.Tensor, grad: torch.Tensor, t: int,
+              lr: float = 0.01, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8):
+    B, P = theta.shape
+    for name, a in (("theta", theta), ("m", m), ("v", v), ("grad", grad)):
+        _check_tensor(a, torch.float64, (B, P), name)
+    ctx.check(lib().vqe_adam_step(ctx.handle, B, P, _ptr(theta), _ptr(m), _ptr(v), _ptr(grad), int(t), lr, b1,
+                                  b2, eps, _stream(theta.device)))
+
+
+def run(ctx: Context, circ: Circuit, hams, theta: torch.Tensor, iters: int, optimizer: str = "adam",
+        lr: float = 0.01, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8, ref_index: int = None,
+        ws: torch.Tensor = None, energies: torch.Tensor = None) -> torch.Tensor:
+    """Algorithm 1's loop for a batch: theta is updated in place.
+
+    Returns energies [B, iters + 1] (before each step, then at the final theta).
+    """
+    B = theta.shape[0]
+    _check_tensor(theta, torch.float64, (B, circ.n_params), "theta")
+    arr, nh = _hams_array(hams)
+    ref = circ.ref_index if ref_index is None else ref_index
+    if ws is None:
+        ws = workspace(ctx, circ, hams, B, 2, theta.device)
+    if energies is None:
+        energies = torch.empty(B, iters + 1, dtype=torch.float64, device=theta.device)
+    opt = {"adam": capi.OPT_ADAM, "gd": capi.OPT_GD}[optimizer]
+    ctx.check(lib().vqe_run(ctx.handle, circ.handle, nh, arr, B, ref, _ptr(theta), int(iters), opt, lr, b1, b2,
+                            eps, _ptr(energies), _ptr(ws), ws.numel(), _stream(theta.device)))
+    return energies
+
+
+# ---------------------------------------------------------------------------
+# autograd
+# ---------------------------------------------------------------------------
+class VQEEnergy(torch.autograd.Function):
+    """E(theta) with the adjoint gradient computed by the library.
+
+    ``VQEEnergy.apply(theta[B, P], ctx, circ, hams)`` returns E[B]; when theta
+    requires grad the forward pass runs the adjoint sweep and keeps dE/dtheta
+    for backward, which returns grad_E[:, None] * dE/dtheta.
+    """
+
+    @staticmethod
+    def forward(fctx, theta, ctx, circ, hams):
+        th = theta.detach().contiguous()
+        if theta.requires_grad:
+            e, g = energy_grad(ctx, circ, hams, th)
+            fctx.save_for_backward(g)
+        else:
+            e = energy(ctx, circ, hams, th)
+        return e
+
+    @staticmethod
+    def backward(fctx, grad_e):
+        (g,) = fctx.saved_tensors
+        return grad_e[:, None] * g, None, None, None
+
+
+# ---------------------------------------------------------------------------
+# schedule inspection
+# ---------------------------------------------------------------------------
+_GEOM = np.dtype([("n", "<i4"), ("k", "<i4"), ("c", "<i4"), ("nout", "<i4"), ("tpos", "u1", 16),
+                  ("opos", "u1", 40)])
+_PASS = np.dtype([("geom", _GEOM), ("op_begin", "<i4"), ("op_count", "<i4"), ("n_param_ops", "<i4"),
+                  ("pad", "<i4")])
+_OP = np.dtype([("m", "<u4"), ("fixed_bits", "<u4"), ("cmask_out", "<u8"), ("cval_out", "<u8"),
+                ("gate", "<i4"), ("pgate", "<i4"), ("cls", "<i2"), ("gen", "<i2"), ("nfix", "i1"),
+                ("fixpos", "u1", 7), ("pad", "<u4")])
+_SWEEP = np.dtype([("geom", _GEOM), ("grp_begin", "<i4"), ("grp_count", "<i4"), ("pad", "<i4", 2)])
+_GROUP = np.dtype([("floc", "<u4"), ("pivot", "<u4"), ("ugroup", "<i4"), ("pad", "<i4")])
+_TERM = np.dtype([("z", "<u8"), ("zloc", "<u4"), ("pad", "<u4"), ("w", "<f8")])
+
+
+def circuit_plan(ctx: Context, circ: Circuit, reverse: bool = False):
+    """(passes, ops) structured arrays of the compiled pass schedule."""
+    need = ctypes.c_size_t()
+    ctx.check(lib().vqe_circ_plan_export(ctx.handle, circ.handle, int(reverse), None, 0, ctypes.byref(need)))
+    buf = np.zeros(need.value, dtype=np.uint8)
+    ctx.check(lib().vqe_circ_plan_export(ctx.handle, circ.handle, int(reverse), _hp(buf), buf.size,
+                                         ctypes.byref(need)))
+    hdr = buf[:16].view("<i4")
+    npass, nops = int(hdr[0]), int(hdr[1])
+    assert hdr[2] == _GEOM.itemsize and hdr[3] == _OP.itemsize
+    off = 16
+    passes = buf[off:off + npass * _PASS.itemsize].view(_PASS)
+    off += npass * _PASS.itemsize
+    ops = buf[off:off + nops * _OP.itemsize].view(_OP)
+    return passes, ops
+
+
+def hamiltonian_plan(ctx: Context, hams, batch: int = 1, for_gradient: bool = False):
+    """dict of structured arrays describing the flip-group sweep schedule."""
+    arr, nh = _hams_array(hams)
+    need = ctypes.c_size_t()
+    ctx.check(lib().vqe_ham_plan_export(ctx.handle, nh, arr, int(batch), int(for_gradient), None, 0,
+                                        ctypes.byref(need)))
+    buf = np.zeros(need.value, dtype=np.uint8)
+    ctx.check(lib().vqe_ham_plan_export(ctx.handle, nh, arr, int(batch), int(for_gradient), _hp(buf), buf.size,
+                                        ctypes.byref(need)))
+    hdr = buf[:32].view("<i4")
+    ns, ng, nu, ni, nt = (int(v) for v in hdr[:5])
+    assert hdr[5] == _GEOM.itemsize and hdr[6] == _GROUP.itemsize and hdr[7] == _TERM.itemsize
+    off = 32
+    sweeps = buf[off:off + ns * _SWEEP.itemsize].view(_SWEEP)
+    off += ns * _SWEEP.itemsize
+    groups = buf[off:off + ng * _GROUP.itemsize].view(_GROUP)
+    off += ng * _GROUP.itemsize
+    toff = buf[off:off + ni * nu * 3 * 4].view("<i4").reshape(ni, nu, 3)
+    off += ni * nu * 3 * 4
+    terms = buf[off:off + nt * _TERM.itemsize].view(_TERM)
+    return {"sweeps": sweeps, "groups": groups, "toff": toff, "terms": terms, "n_union": nu, "n_inst": ni}

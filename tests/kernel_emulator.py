@@ -1,0 +1,222 @@
+"""CPU emulation of the library's device schedules (test utility).
+
+Executes the pass and sweep schedules exported by libvqe with the same index
+arithmetic the HIP kernels use (tile bases, gathered offsets, zero-bit
+insertion, pair selection, folded signs), in numpy, and asserts that every
+index stays inside its tile and that each tile set partitions the state.
+It lets the CPU test-suite check the schedules and the kernels' indexing
+before any of it runs on a GPU; it is compared against the oracle, never
+used by the library.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+CLS_GENERAL, CLS_DIAG, CLS_SWAP = 0, 1, 2
+GEN_NONE, GEN_X, GEN_Y, GEN_Z = 0, 1, 2, 3
+KIND = {"RX": 0, "RY": 1, "RZ": 2, "H": 3, "X": 4, "CNOT": 5, "CZ": 6, "SingleExcitation": 7,
+        "DoubleExcitation": 8}
+
+
+def gate_matrices(circ, theta):
+    """2x2 matrices on each gate's (first, second) pair, as the gate-matrix kernel builds them."""
+    out = np.zeros((circ.n_gates, 2, 2), dtype=complex)
+    for g in range(circ.n_gates):
+        kind = KIND[circ.kinds[g]]
+        p = circ.param_idx[g]
+        a = theta[p] if p >= 0 else circ.fixed_angle[g]
+        c, s = math.cos(0.5 * a), math.sin(0.5 * a)
+        if kind == 0:
+            U = [[c, -1j * s], [-1j * s, c]]
+        elif kind in (1, 7, 8):
+            U = [[c, -s], [s, c]]
+        elif kind == 2:
+            U = [[c - 1j * s, 0], [0, c + 1j * s]]
+        elif kind == 3:
+            r = 1 / math.sqrt(2)
+            U = [[r, r], [r, -r]]
+        elif kind in (4, 5):
+            U = [[0, 1], [1, 0]]
+        else:
+            U = [[1, 0], [0, -1]]
+        out[g] = U
+    return out
+
+
+def _tile_index(geom):
+    n, k, c, nout = int(geom["n"]), int(geom["k"]), int(geom["c"]), int(geom["nout"])
+    tpos = [int(v) for v in geom["tpos"][:k]]
+    opos = [int(v) for v in geom["opos"][:nout]]
+    assert tpos[:c] == list(range(c)), "low tile bits must be 0..c-1"
+    assert sorted(tpos) == tpos and len(set(tpos + opos)) == n
+    j = np.arange(1 << k, dtype=np.uint64)
+    hoff = np.zeros(1 << (k - c), dtype=np.uint64)
+    for h in range(1 << (k - c)):
+        o = 0
+        for i in range(k - c):
+            if (h >> i) & 1:
+                o |= 1 << tpos[c + i]
+        hoff[h] = o
+    local = hoff[(j >> np.uint64(c)).astype(np.int64)] + (j & np.uint64((1 << c) - 1))
+    t = np.arange(1 << nout, dtype=np.uint64)
+    base = np.zeros(1 << nout, dtype=np.uint64)
+    for i, b in enumerate(opos):
+        base |= ((t >> np.uint64(i)) & np.uint64(1)) << np.uint64(b)
+    idx = base[:, None] + local[None, :]
+    assert idx.max() < (1 << n)
+    assert np.unique(idx).size == idx.size == (1 << n), "tiles must partition the state"
+    return idx.astype(np.int64), base
+
+
+def _insert_zeros(j, nfix, pos):
+    j = j.astype(np.uint64)
+    for i in range(nfix):
+        p = np.uint64(int(pos[i]))
+        j = ((j >> p) << (p + np.uint64(1))) | (j & ((np.uint64(1) << p) - np.uint64(1)))
+    return j
+
+
+def _pairs(op, k):
+    nfix = int(op["nfix"])
+    j = np.arange(1 << (k - nfix), dtype=np.uint64)
+    p0 = _insert_zeros(j, nfix, op["fixpos"]) | np.uint64(int(op["fixed_bits"]))
+    p1 = p0 ^ np.uint64(int(op["m"]))
+    assert p0.max() < (1 << k) and p1.max() < (1 << k), "pair index outside the tile"
+    both = np.concatenate([p0, p1])
+    assert np.unique(both).size == both.size, "pairs must be disjoint"
+    return p0.astype(np.int64), p1.astype(np.int64)
+
+
+def forward(passes, ops, psi, mats):
+    psi = psi.copy()
+    for ps in passes:
+        g = ps["geom"]
+        k = int(g["k"])
+        idx, base = _tile_index(g)
+        T = psi[idx]
+        for op in ops[int(ps["op_begin"]):int(ps["op_begin"]) + int(ps["op_count"])]:
+            act = (base & np.uint64(int(op["cmask_out"]))) == np.uint64(int(op["cval_out"]))
+            p0, p1 = _pairs(op, k)
+            U = mats[int(op["gate"])]
+            a = T[act][:, p0]
+            b = T[act][:, p1]
+            cls = int(op["cls"])
+            if cls == CLS_SWAP:
+                na, nb = b, a
+            elif cls == CLS_DIAG:
+                na, nb = U[0, 0] * a, U[1, 1] * b
+            else:
+                na, nb = U[0, 0] * a + U[0, 1] * b, U[1, 0] * a + U[1, 1] * b
+            Ta = T[act]
+            Ta[:, p0] = na
+            Ta[:, p1] = nb
+            T[act] = Ta
+        psi[idx] = T
+    return psi
+
+
+def reverse(passes, ops, psi, lam, mats, n_pgates):
+    psi, lam = psi.copy(), lam.copy()
+    gpart = np.zeros(n_pgates)
+    for ps in passes:
+        g = ps["geom"]
+        k = int(g["k"])
+        idx, base = _tile_index(g)
+        TP, TL = psi[idx], lam[idx]
+        for op in ops[int(ps["op_begin"]):int(ps["op_begin"]) + int(ps["op_count"])]:
+            act = (base & np.uint64(int(op["cmask_out"]))) == np.uint64(int(op["cval_out"]))
+            p0, p1 = _pairs(op, k)
+            U = mats[int(op["gate"])]
+            V = U.conj().T
+            a, b = TP[act][:, p0], TP[act][:, p1]
+            la, lb = TL[act][:, p0], TL[act][:, p1]
+            if int(op["pgate"]) >= 0:
+                gen = int(op["gen"])
+                if gen == GEN_Y:
+                    v = -(la.conj() * b).real + (lb.conj() * a).real
+                elif gen == GEN_X:
+                    v = (la.conj() * b).imag + (lb.conj() * a).imag
+                else:
+                    v = (la.conj() * a).imag - (lb.conj() * b).imag
+                gpart[int(op["pgate"])] += v.sum()
+            cls = int(op["cls"])
+            if cls == CLS_SWAP:
+                res = (b, a, lb, la)
+            elif cls == CLS_DIAG:
+                res = (V[0, 0] * a, V[1, 1] * b, V[0, 0] * la, V[1, 1] * lb)
+            else:
+                res = (V[0, 0] * a + V[0, 1] * b, V[1, 0] * a + V[1, 1] * b,
+                       V[0, 0] * la + V[0, 1] * lb, V[1, 0] * la + V[1, 1] * lb)
+            TPa, TLa = TP[act], TL[act]
+            TPa[:, p0], TPa[:, p1], TLa[:, p0], TLa[:, p1] = res
+            TP[act], TL[act] = TPa, TLa
+        psi[idx], lam[idx] = TP, TL
+    return psi, lam, gpart
+
+
+def _parity(v):
+    v = v.astype(np.uint64)
+    out = np.zeros(v.shape, dtype=np.int64)
+    for s in range(64):
+        out ^= ((v >> np.uint64(s)) & np.uint64(1)).astype(np.int64)
+    return out
+
+
+def sweeps(plan, psi, inst=0, hpsi=False):
+    """Emulate the sweep kernel: energy (paired form), or (lambda, energy)."""
+    toff = plan["toff"][0 if plan["n_inst"] == 1 else inst]
+    terms = plan["terms"]
+    E = 0.0
+    lam = np.zeros_like(psi) if hpsi else None
+    for sw in plan["sweeps"]:
+        g = sw["geom"]
+        k = int(g["k"])
+        idx, base = _tile_index(g)
+        TP = psi[idx]
+        TL = np.zeros_like(TP)
+        j = np.arange(1 << k, dtype=np.uint64)
+        for grp in plan["groups"][int(sw["grp_begin"]):int(sw["grp_begin"]) + int(sw["grp_count"])]:
+            tb, tm, te = (int(v) for v in toff[int(grp["ugroup"])])
+            if te == tb:
+                continue
+            floc = np.uint64(int(grp["floc"]))
+            if floc == 0:
+                b = j
+            else:
+                pv = np.uint64(int(grp["pivot"]))
+                jj = np.arange(1 << (k - 1), dtype=np.uint64)
+                b = ((jj >> pv) << (pv + np.uint64(1))) | (jj & ((np.uint64(1) << pv) - np.uint64(1)))
+            assert b.max() < (1 << k)
+            A = np.zeros((base.size, b.size))
+            Bv = np.zeros((base.size, b.size))
+            for t in range(tb, te):
+                d = terms[t]
+                s = (_parity(np.uint64(int(d["z"])) & base)[:, None] + _parity(np.uint64(int(d["zloc"])) & b)[None, :]) & 1
+                val = np.where(s == 1, -d["w"], d["w"])
+                if t < tm:
+                    A += val
+                else:
+                    Bv += val
+            if floc == 0:
+                x = TP[:, b]
+                if hpsi:
+                    TL[:, b] += A * x
+                else:
+                    E += float(np.sum(np.abs(x) ** 2 * A))
+            else:
+                bf = (b ^ floc).astype(np.int64)
+                bi = b.astype(np.int64)
+                x0, x1 = TP[:, bi], TP[:, bf]
+                if hpsi:
+                    TL[:, bf] += (A + 1j * Bv) * x0
+                    TL[:, bi] += (A - 1j * Bv) * x1
+                else:
+                    w = x1.conj() * x0
+                    E += float(np.sum(2.0 * (w.real * A - w.imag * Bv)))
+        if hpsi:
+            lam[idx] += TL
+    if hpsi:
+        return lam, float(np.vdot(psi, lam).real)
+    return E

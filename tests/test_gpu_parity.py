@@ -1,0 +1,257 @@
+"""GPU parity: the HIP path through the C ABI against the oracle, element by element.
+
+Tolerances (from the energy and gradient targets of the hot path): energies
+1e-10 Ha absolute, gradients 1e-9, states 1e-12 per amplitude.  Every case
+prints its name before touching the device.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import fermion
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+E_TOL = 1e-10
+G_TOL = 1e-9
+S_TOL = 1e-12
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def vqe():
+    from paper_2601_09951_amd import vqe as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(vqe):
+    c = vqe.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+@pytest.fixture(autouse=True)
+def _default_tile(ctx):
+    ctx.set_tile(12, 11, 4)
+    yield
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda:0").contiguous()
+
+
+def test_library_is_the_hip_build(vqe):
+    from paper_2601_09951_amd import capi
+    import os
+    L = capi.lib()
+    assert os.path.basename(L._name) == "libvqe.so"
+    for name in capi.EXPORTED:
+        assert hasattr(L, name)
+
+
+@pytest.mark.parametrize("n,B", [(1, 1), (4, 3), (13, 2), (20, 1)])
+def test_prepare_reference(vqe, ctx, n, B):
+    _say("prepare", n, B)
+    psi = torch.full((B, 1 << n), 7 + 7j, dtype=torch.complex128, device="cuda:0")
+    ref = (1 << n) - 1 if n > 1 else 1
+    vqe.prepare_reference(ctx, n, B, ref, psi)
+    torch.cuda.synchronize()
+    host = psi.cpu().numpy()
+    want = np.zeros((B, 1 << n), dtype=complex)
+    want[:, ref] = 1
+    assert np.array_equal(host, want)
+
+
+GEOMS = [(12, 11, 4), (6, 6, 2), (8, 7, 3)]
+
+
+@pytest.mark.parametrize("geom", GEOMS)
+@pytest.mark.parametrize("n,seed", [(1, 0), (2, 1), (5, 2), (9, 3), (12, 4)])
+def test_apply_ansatz_random_circuits(vqe, ctx, geom, n, seed):
+    _say("apply", geom, n, seed)
+    ctx.set_tile(*geom)
+    spec = synth.random_circuit(n, 50, seed=seed)
+    th = synth.uniform_thetas(spec.n_params, 2, seed=seed)
+    C = vqe.Circuit.from_spec(ctx, spec)
+    psi = torch.empty(2, 1 << n, dtype=torch.complex128, device="cuda:0")
+    vqe.prepare_reference(ctx, n, 2, spec.ref_index, psi)
+    vqe.apply_ansatz(ctx, C, dev(th), psi)
+    torch.cuda.synchronize()
+    got = psi.cpu().numpy()
+    for b in range(2):
+        np.testing.assert_allclose(got[b], oracle.state(spec, th[b]), atol=S_TOL)
+
+
+@pytest.mark.parametrize("geom", GEOMS)
+@pytest.mark.parametrize("n,T,seed", [(1, 3, 0), (3, 10, 1), (7, 40, 2), (10, 80, 3), (14, 200, 4)])
+def test_expect_and_h_psi(vqe, ctx, geom, n, T, seed):
+    _say("expect", geom, n, T, seed)
+    ctx.set_tile(*geom)
+    ham = synth.random_pauli_sum(n, min(T, 4 ** n - 1), seed=seed)
+    H = vqe.Hamiltonian.from_sum(ctx, ham)
+    states = np.stack([synth.random_state(n, seed=seed * 7 + b) for b in range(3)])
+    psi = dev(states, torch.complex128)
+    e = vqe.expect(ctx, H, psi)
+    lam = vqe.apply_hamiltonian(ctx, H, psi)
+    torch.cuda.synchronize()
+    e = e.cpu().numpy()
+    lam = lam.cpu().numpy()
+    for b in range(3):
+        assert abs(e[b] - oracle.expect(states[b], ham).real) < E_TOL
+        np.testing.assert_allclose(lam[b], oracle.apply_hamiltonian(states[b], ham), atol=S_TOL)
+
+
+@pytest.mark.parametrize("geom", GEOMS)
+@pytest.mark.parametrize("n,seed", [(2, 1), (6, 2), (10, 3), (13, 4)])
+def test_energy_grad_random_circuits(vqe, ctx, geom, n, seed):
+    _say("energy_grad", geom, n, seed)
+    ctx.set_tile(*geom)
+    spec = synth.random_circuit(n, 40, seed=seed)
+    ham = synth.random_pauli_sum(n, min(30, 4 ** n - 1), seed=seed)
+    B = 3
+    th = synth.uniform_thetas(spec.n_params, B, seed=seed)
+    C = vqe.Circuit.from_spec(ctx, spec)
+    H = vqe.Hamiltonian.from_sum(ctx, ham)
+    e, g = vqe.energy_grad(ctx, C, H, dev(th))
+    e0 = vqe.energy(ctx, C, H, dev(th))
+    torch.cuda.synchronize()
+    e, g, e0 = e.cpu().numpy(), g.cpu().numpy(), e0.cpu().numpy()
+    for b in range(B):
+        eo, go = oracle.energy_grad(spec, ham, th[b], "adjoint")
+        assert abs(e[b] - eo) < E_TOL
+        assert abs(e0[b] - eo) < E_TOL
+        np.testing.assert_allclose(g[b], go, atol=G_TOL)
+
+
+@pytest.mark.parametrize("n,k,c", [(14, 8, 3), (16, 12, 4), (17, 11, 4)])
+def test_hea_energy_grad_multi_tile(vqe, ctx, n, k, c):
+    _say("hea", n, k, c)
+    ctx.set_tile(k, min(k, 12), c)
+    spec = synth.hea_circuit(n, 2)
+    ham = synth.random_pauli_sum(n, 100, seed=n)
+    th = synth.uniform_thetas(spec.n_params, 1, seed=n)
+    C = vqe.Circuit.from_spec(ctx, spec)
+    H = vqe.Hamiltonian.from_sum(ctx, ham)
+    e, g = vqe.energy_grad(ctx, C, H, dev(th))
+    torch.cuda.synchronize()
+    eo, go = oracle.energy_grad(spec, ham, th[0], "adjoint")
+    assert abs(e.item() - eo) < E_TOL
+    np.testing.assert_allclose(g.cpu().numpy()[0], go, atol=G_TOL)
+
+
+def test_batched_per_instance_hamiltonians(vqe, ctx):
+    _say("batched hams")
+    n, B = 8, 5
+    spec = synth.ucc_circuit(8, 2)
+    model = synth.smooth_integral_model(4, seed=synth.MASTER_SEED)
+    ds = synth.bond_grid(B)
+    ints = [model.at(d) for d in ds]
+    hams = [vqe.Hamiltonian.from_integrals(ctx, i.h1, i.h2, i.e_core) for i in ints]
+    th = synth.uniform_thetas(spec.n_params, B, seed=3) * 0.3
+    C = vqe.Circuit.from_spec(ctx, spec)
+    e, g = vqe.energy_grad(ctx, C, hams, dev(th))
+    torch.cuda.synchronize()
+    e, g = e.cpu().numpy(), g.cpu().numpy()
+    for b in range(B):
+        ho = fermion.qubit_hamiltonian(ints[b])
+        eo, go = oracle.energy_grad(spec, ho, th[b], "adjoint")
+        assert abs(e[b] - eo) < E_TOL
+        np.testing.assert_allclose(g[b], go, atol=G_TOL)
+        # alone == in the batch
+        e1, g1 = vqe.energy_grad(ctx, C, hams[b], dev(th[b:b + 1]))
+        torch.cuda.synchronize()
+        assert abs(e1.item() - e[b]) < E_TOL
+        np.testing.assert_allclose(g1.cpu().numpy()[0], g[b], atol=G_TOL)
+
+
+def test_c1_energy_curve_and_gradient_descent(vqe, ctx):
+    _say("c1")
+    ints = synth.random_integrals(2, seed=synth.MASTER_SEED)
+    ham = fermion.qubit_hamiltonian(ints)
+    spec = synth.h2_circuit()
+    C = vqe.Circuit.from_spec(ctx, spec)
+    H = vqe.Hamiltonian.from_integrals(ctx, ints.h1, ints.h2)
+    thetas = synth.theta_grid(100)[:, None]
+    e = vqe.energy(ctx, C, H, dev(thetas)).cpu().numpy()
+    for j, t in enumerate(thetas[:, 0]):
+        assert abs(e[j] - oracle.energy(spec, ham, [t])) < E_TOL
+    th = dev(np.zeros((1, 1)))
+    traj = vqe.run(ctx, C, H, th, 50, optimizer="gd", lr=0.2).cpu().numpy()[0]
+    want, th_o = oracle.vqe_run(spec, ham, [0.0], 50, optimizer="gd", lr=0.2)
+    np.testing.assert_allclose(traj, want, atol=E_TOL)
+    assert abs(th.item() - th_o[0]) < 1e-9
+
+
+@pytest.mark.parametrize("n_orb", [2, 4])
+def test_batched_pes_adam_trajectories(vqe, ctx, n_orb):
+    _say("pes", n_orb)
+    B, iters = 100, 200 if n_orb == 2 else 60
+    model = synth.smooth_integral_model(n_orb, seed=synth.MASTER_SEED)
+    ds = synth.bond_grid(B)
+    ints = [model.at(d) for d in ds]
+    spec = synth.h2_circuit() if n_orb == 2 else synth.ucc_circuit(8, 2)
+    C = vqe.Circuit.from_spec(ctx, spec)
+    hams = [vqe.Hamiltonian.from_integrals(ctx, i.h1, i.h2, i.e_core) for i in ints]
+    th = dev(np.zeros((B, spec.n_params)))
+    traj = vqe.run(ctx, C, hams, th, iters).cpu().numpy()
+    th_final = th.cpu().numpy()
+    for b in range(0, B, 9 if n_orb == 2 else 33):
+        ho = fermion.qubit_hamiltonian(ints[b])
+        want, tho = oracle.vqe_run(spec, ho, np.zeros(spec.n_params), iters)
+        np.testing.assert_allclose(traj[b], want, atol=E_TOL)
+        np.testing.assert_allclose(th_final[b], tho, atol=1e-7)
+
+
+def test_adam_step_kernel(vqe, ctx):
+    _say("adam")
+    rng = np.random.default_rng(0)
+    B, P = 4, 7
+    th, m, v = rng.normal(size=(B, P)), np.zeros((B, P)), np.zeros((B, P))
+    T = [dev(a) for a in (th, m, v)]
+    for t in range(1, 6):
+        g = rng.normal(size=(B, P))
+        vqe.adam_step(ctx, T[0], T[1], T[2], dev(g), t)
+        for b in range(B):
+            oracle.adam_step(th[b], m[b], v[b], g[b], t)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(T[0].cpu().numpy(), th, atol=1e-14)
+
+
+def test_autograd_function(vqe, ctx):
+    _say("autograd")
+    spec = synth.hea_circuit(6, 2)
+    ham = synth.random_pauli_sum(6, 30, seed=5)
+    C = vqe.Circuit.from_spec(ctx, spec)
+    H = vqe.Hamiltonian.from_sum(ctx, ham)
+    th0 = synth.uniform_thetas(spec.n_params, 2, seed=5)
+    th = dev(th0).requires_grad_(True)
+    e = vqe.VQEEnergy.apply(th, ctx, C, H)
+    (e * torch.tensor([1.0, -2.0], dtype=torch.float64, device="cuda:0")).sum().backward()
+    g = th.grad.cpu().numpy()
+    for b, w in enumerate([1.0, -2.0]):
+        _, go = oracle.energy_grad(spec, ham, th0[b])
+        np.testing.assert_allclose(g[b], w * go, atol=G_TOL)
+
+
+def test_errors_do_not_launch(vqe, ctx):
+    _say("errors")
+    spec = synth.h2_circuit()
+    C = vqe.Circuit.from_spec(ctx, spec)
+    H8 = vqe.Hamiltonian.from_sum(ctx, synth.random_pauli_sum(8, 5, seed=1))
+    with pytest.raises(vqe.VQEError):
+        vqe.energy_grad(ctx, C, H8, dev(np.zeros((1, 1))))  # qubit count mismatch
+    H4 = vqe.Hamiltonian.from_sum(ctx, synth.random_pauli_sum(4, 5, seed=1))
+    ws = torch.empty(16, dtype=torch.uint8, device="cuda:0")
+    with pytest.raises(vqe.VQEError):
+        vqe.energy_grad(ctx, C, H4, dev(np.zeros((1, 1))), ws=ws)  # workspace too small
+    with pytest.raises(vqe.VQEError):
+        vqe.energy(ctx, C, [H4, H4], dev(np.zeros((3, 1))))  # n_hams neither 1 nor B

@@ -1,0 +1,168 @@
+"""The library's compiled schedules, executed by the CPU emulator, against the oracle.
+
+Runs without a GPU: a host-only planning context (device -1) compiles the
+circuits and Pauli sums exactly as the device path does, and
+``kernel_emulator`` executes them with the kernels' index arithmetic.  This
+pins the pass/sweep compilers and the kernels' pair and sign logic before
+anything runs on the device.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import fermion
+
+from . import kernel_emulator as emu
+
+vqe = pytest.importorskip("paper_2601_09951_amd.vqe")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = vqe.Context(-1)
+    yield c
+    c.close()
+
+
+GEOMS = [(12, 11, 4), (6, 6, 2), (7, 6, 2), (8, 7, 3)]
+
+
+def _grad_from_parts(circ, gpart):
+    g = np.zeros(circ.n_params)
+    pg = 0
+    for gate in range(circ.n_gates):
+        p = circ.param_idx[gate]
+        if p >= 0:
+            g[p] += gpart[pg]
+            pg += 1
+    return g
+
+
+@pytest.mark.parametrize("geom", GEOMS)
+@pytest.mark.parametrize("n,seed", [(3, 1), (6, 2), (9, 3), (10, 4)])
+def test_forward_and_adjoint_schedules(ctx, geom, n, seed):
+    ctx.set_tile(*geom)
+    spec = synth.random_circuit(n, 40, seed=seed)
+    ham = synth.random_pauli_sum(n, 25, seed=seed)
+    th = synth.uniform_thetas(spec.n_params, 1, seed=seed)[0]
+    C = vqe.Circuit.from_spec(ctx, spec)
+    mats = emu.gate_matrices(spec, th)
+    passes, ops = vqe.circuit_plan(ctx, C)
+    ref = np.zeros(1 << n, dtype=complex)
+    ref[spec.ref_index] = 1
+    psi = emu.forward(passes, ops, ref, mats)
+    want = oracle.state(spec, th)
+    np.testing.assert_allclose(psi, want, atol=1e-13)
+
+    H = vqe.Hamiltonian.from_sum(ctx, ham)
+    for for_grad in (False, True):
+        plan = vqe.hamiltonian_plan(ctx, H, 1, for_grad)
+        e = emu.sweeps(plan, psi)
+        assert abs(e - oracle.expect(psi, ham).real) < 1e-12
+        lam, e2 = emu.sweeps(plan, psi, hpsi=True)
+        np.testing.assert_allclose(lam, oracle.apply_hamiltonian(psi, ham), atol=1e-12)
+        assert abs(e2 - e) < 1e-12
+
+    rpasses, rops = vqe.circuit_plan(ctx, C, reverse=True)
+    n_pg = int((spec.param_idx >= 0).sum())
+    back, _, gpart = emu.reverse(rpasses, rops, psi, oracle.apply_hamiltonian(psi, ham), mats, n_pg)
+    np.testing.assert_allclose(back, ref, atol=1e-12)
+    _, g_or = oracle.energy_grad(spec, ham, th, "adjoint")
+    np.testing.assert_allclose(_grad_from_parts(spec, gpart), g_or, atol=1e-11)
+
+
+@pytest.mark.parametrize("n,k,c", [(12, 8, 3), (14, 9, 4), (11, 6, 2)])
+def test_hea_schedules_multi_tile(ctx, n, k, c):
+    ctx.set_tile(k, k, c)
+    spec = synth.hea_circuit(n, 2)
+    ham = synth.random_pauli_sum(n, 60, seed=n)
+    th = synth.uniform_thetas(spec.n_params, 1, seed=n)[0]
+    C = vqe.Circuit.from_spec(ctx, spec)
+    mats = emu.gate_matrices(spec, th)
+    passes, ops = vqe.circuit_plan(ctx, C)
+    assert len(passes) > 1
+    ref = np.zeros(1 << n, dtype=complex)
+    ref[0] = 1
+    psi = emu.forward(passes, ops, ref, mats)
+    np.testing.assert_allclose(psi, oracle.state(spec, th), atol=1e-12)
+    H = vqe.Hamiltonian.from_sum(ctx, ham)
+    plan = vqe.hamiltonian_plan(ctx, H, 1, False)
+    assert len(plan["sweeps"]) > 1
+    assert abs(emu.sweeps(plan, psi) - oracle.expect(psi, ham).real) < 1e-12
+    plan = vqe.hamiltonian_plan(ctx, H, 1, True)
+    lam, _ = emu.sweeps(plan, psi, hpsi=True)
+    np.testing.assert_allclose(lam, oracle.apply_hamiltonian(psi, ham), atol=1e-12)
+    rpasses, rops = vqe.circuit_plan(ctx, C, reverse=True)
+    _, _, gpart = emu.reverse(rpasses, rops, psi, lam, mats, spec.n_params)
+    _, g_or = oracle.energy_grad(spec, ham, th, "adjoint")
+    np.testing.assert_allclose(_grad_from_parts(spec, gpart), g_or, atol=1e-11)
+
+
+def test_batched_union_plan_per_instance_tables(ctx):
+    ctx.set_tile(6, 6, 2)
+    n = 8
+    hams = [synth.random_pauli_sum(n, 20 + 5 * i, seed=40 + i) for i in range(3)]
+    H = [vqe.Hamiltonian.from_sum(ctx, h) for h in hams]
+    plan = vqe.hamiltonian_plan(ctx, H, 3, False)
+    assert plan["n_inst"] == 3
+    for i, h in enumerate(hams):
+        psi = synth.random_state(n, seed=i)
+        assert abs(emu.sweeps(plan, psi, inst=i) - oracle.expect(psi, h).real) < 1e-12
+
+
+def test_library_jordan_wigner_matches_oracle(ctx):
+    for n_orb, seed, zero in [(2, synth.MASTER_SEED, True), (2, 3, False), (3, 4, False), (4, 5, False)]:
+        ints = synth.random_integrals(n_orb, seed=seed, zero_odd_parity=zero)
+        ints.e_core = 0.123
+        H = vqe.Hamiltonian.from_integrals(ctx, ints.h1, ints.h2, ints.e_core)
+        x, z, c = H.terms()
+        ref = fermion.qubit_hamiltonian(ints)
+        assert np.array_equal(x, ref.xmask) and np.array_equal(z, ref.zmask)
+        np.testing.assert_allclose(c, ref.coeff, atol=1e-13)
+    # the H2-like model: 15 terms in 2 flip groups
+    ints = synth.random_integrals(2, seed=synth.MASTER_SEED)
+    H = vqe.Hamiltonian.from_integrals(ctx, ints.h1, ints.h2)
+    assert H.n_terms == 15 and H.n_groups == 2
+
+
+def test_library_rejects_bad_input(ctx):
+    with pytest.raises(vqe.VQEError):
+        vqe.Hamiltonian.from_pauli(ctx, 4, [1 << 5], [0], [1.0])
+    with pytest.raises(vqe.VQEError):
+        vqe.Hamiltonian.from_pauli(ctx, 4, [1], [0], [float("nan")])
+    with pytest.raises(vqe.VQEError):
+        vqe.Hamiltonian.from_pauli(ctx, 40, [1], [0], [1.0])
+    with pytest.raises(vqe.VQEError):
+        vqe.Circuit(ctx, 3, ["RY"], [[5, -1, -1, -1]], [0], n_params=1)
+    with pytest.raises(vqe.VQEError):
+        vqe.Circuit(ctx, 3, ["CNOT"], [[1, 1, -1, -1]], [-1], n_params=0)
+    with pytest.raises(vqe.VQEError):
+        vqe.Circuit(ctx, 3, ["CNOT"], [[0, 1, -1, -1]], [0], n_params=1)
+    with pytest.raises(vqe.VQEError):
+        vqe.Circuit(ctx, 3, [99], [[0, -1, -1, -1]], [-1], n_params=0)
+    with pytest.raises(vqe.VQEError):
+        vqe.Circuit(ctx, 3, ["RY"], [[0, -1, -1, -1]], [3], n_params=2)
+    # device work is refused on a planning context
+    spec = synth.h2_circuit()
+    C = vqe.Circuit.from_spec(ctx, spec)
+    from paper_2601_09951_amd import capi
+    rc = capi.lib().vqe_prepare_reference(ctx.handle, 4, 1, 0, None, None)
+    assert rc == capi.VQE_EUNSUPPORTED
+    del C
+
+
+def test_workspace_accounts_for_states(ctx):
+    ctx.set_tile(12, 11, 4)
+    n = 16
+    spec = synth.hea_circuit(n, 1)
+    C = vqe.Circuit.from_spec(ctx, spec)
+    H = vqe.Hamiltonian.from_sum(ctx, synth.random_pauli_sum(n, 10, seed=1))
+    state = (1 << n) * 16
+    for B in (1, 4):
+        w0 = vqe.workspace_bytes(ctx, C, H, B, 0)
+        w1 = vqe.workspace_bytes(ctx, C, H, B, 1)
+        w2 = vqe.workspace_bytes(ctx, C, H, B, 2)
+        assert B * state <= w0 < B * state * 1.2
+        assert 2 * B * state <= w1 < 2 * B * state * 1.2
+        assert w2 > w1
