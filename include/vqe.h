@@ -108,6 +108,13 @@ int vqe_ctx_set_mem_budget(vqe_ctx_t ctx, size_t bytes);
  * (VQE_EUNSUPPORTED from the calls that evaluate it). */
 int vqe_ctx_set_tile(vqe_ctx_t ctx, int k_fwd, int k_rev, int c_low);
 
+/* How vqe_run executes: mode 0 (default) runs the whole loop in one
+ * persistent launch per batch when a state fits one workgroup's LDS (n up to
+ * 10 with the default tiles), else per-step launches; mode 1 always uses
+ * per-step launches (one energy_grad sequence and one optimiser launch per
+ * step). */
+int vqe_ctx_set_loop_mode(vqe_ctx_t ctx, int mode);
+
 /* Reserve `bytes` of context scratch now (used by vqe_expect and
  * vqe_apply_ansatz for per-launch tables), so later calls do not allocate. */
 int vqe_ctx_reserve(vqe_ctx_t ctx, size_t bytes);

@@ -380,6 +380,14 @@ int vqe_ctx_set_tile(vqe_ctx_t ctx, int k_fwd, int k_rev, int c_low)
     return VQE_OK;
 }
 
+int vqe_ctx_set_loop_mode(vqe_ctx_t ctx, int mode)
+{
+    if (!ctx) return VQE_EINVAL;
+    if (mode != 0 && mode != 1) return set_err(ctx, VQE_EINVAL, "loop mode must be 0 or 1");
+    ctx->force_generic = mode;
+    return VQE_OK;
+}
+
 int vqe_ctx_reserve(vqe_ctx_t ctx, size_t bytes)
 {
     int rc = check_dev(ctx);
@@ -765,6 +773,52 @@ int vqe_run(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams, i
     unsigned char *ws = (unsigned char *)workspace;
     hipStream_t s = (hipStream_t)stream;
     const int P = circ->n_params;
+
+    // small states: the whole loop in one persistent launch, state on chip
+    const int n = circ->n;
+    if (n <= std::min(ctx->k_fwd, ctx->k_rev) && circ->gates.size() > 0 && !ctx->force_generic) {
+        const int n_inst = n_hams == 1 ? 1 : (int)batch;
+        CircPlan *fp = get_circ_plan(circ, false, ctx->k_fwd, ctx->c_low, &rc);
+        if (!fp) return rc;
+        CircPlan *rp = get_circ_plan(circ, true, ctx->k_rev, ctx->c_low, &rc);
+        if (!rp) return rc;
+        PauliPlan *pp = get_pauli_plan(ctx, n_hams, H.data(), n_inst, ctx->k_rev, ctx->c_low, &rc);
+        if (!pp) return rc;
+        const int G = (int)circ->gates.size();
+        if (fp->passes.size() == 1 && rp->passes.size() == 1 && pp->sweeps.size() == 1 &&
+            fp->passes[0].op_count == G && rp->passes[0].op_count == G &&
+            pp->sweeps[0].grp_count == pp->n_ugroups &&
+            small_run_supported(n, G, P, circ->n_pgates, pp->max_terms_group)) {
+            SmallRunArgs a;
+            a.n = n;
+            a.n_gates = G;
+            a.n_params = P;
+            a.iters = iters;
+            a.opt = optimizer;
+            a.n_inst = n_inst;
+            a.ref = ref_index;
+            a.lr = lr;
+            a.b1 = b1;
+            a.b2 = b2;
+            a.eps = eps;
+            a.gates = reinterpret_cast<const GateDev *>(circ->gates_dev.p);
+            a.ops = reinterpret_cast<const OpDesc *>(fp->ops.p);
+            a.groups = reinterpret_cast<const GroupDev *>(pp->groups.p);
+            a.n_groups = pp->n_ugroups;
+            a.toff = reinterpret_cast<const int32_t *>(pp->toff.p);
+            a.terms = reinterpret_cast<const TermDev *>(pp->terms.p);
+            a.shared_ham = n_hams == 1;
+            a.theta = theta;
+            a.energies = energies;
+            a.work = nullptr;
+            return hip_check(ctx, launch_small_run(a, reinterpret_cast<const OpDesc *>(rp->ops.p),
+                                                   reinterpret_cast<const int32_t *>(circ->pmap_off.p),
+                                                   reinterpret_cast<const int32_t *>(circ->pmap_idx.p),
+                                                   circ->n_pgates, batch, s),
+                             "persistent VQE loop");
+        }
+    }
+
     double *g = (double *)(ws + L.grad), *m = (double *)(ws + L.m), *v = (double *)(ws + L.v);
     const int64_t e_stride = (int64_t)iters + 1;
     const int64_t np = batch * (int64_t)P;

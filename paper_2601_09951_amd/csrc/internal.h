@@ -170,6 +170,7 @@ struct Context {
     size_t used = 0;
     int k_fwd = 12, k_rev = 11, c_low = 4;
     int wg_max = 1024;          // workgroups per instance in tile passes
+    int force_generic = 0;      // route vqe_run through the per-step launches
     std::string err;
     DevMem scratch;
     std::map<std::string, std::unique_ptr<PauliPlan>> pauli_cache;
@@ -245,9 +246,9 @@ struct SmallRunArgs {
     double *energies;              // [B][iters+1]
     double *work;                  // [B][2P] Adam moments
 };
-hipError_t launch_small_run(const SmallRunArgs &a, int64_t batch, hipStream_t s);
-int small_run_supported(int n, int n_gates, int n_params, int n_groups, int max_terms);
-
+hipError_t launch_small_run(const SmallRunArgs &a, const OpDesc *rops, const int32_t *pmap_off,
+                            const int32_t *pmap_idx, int n_pgates, int64_t batch, hipStream_t s);
+int small_run_supported(int n, int n_gates, int n_params, int n_pgates, int max_terms);
 }  // namespace vqe
 
 struct vqe_ctx : vqe::Context {};

@@ -62,6 +62,10 @@ class Context:
     def set_mem_budget(self, nbytes: int):
         self.check(lib().vqe_ctx_set_mem_budget(self._h, int(nbytes)))
 
+    def set_loop_mode(self, mode: int):
+        """0: persistent single-launch loop when the state fits on chip; 1: per-step launches."""
+        self.check(lib().vqe_ctx_set_loop_mode(self._h, int(mode)))
+
     def reserve(self, nbytes: int):
         self.check(lib().vqe_ctx_reserve(self._h, int(nbytes)))
 

@@ -184,16 +184,21 @@ def test_c1_energy_curve_and_gradient_descent(vqe, ctx):
     e = vqe.energy(ctx, C, H, dev(thetas)).cpu().numpy()
     for j, t in enumerate(thetas[:, 0]):
         assert abs(e[j] - oracle.energy(spec, ham, [t])) < E_TOL
-    th = dev(np.zeros((1, 1)))
-    traj = vqe.run(ctx, C, H, th, 50, optimizer="gd", lr=0.2).cpu().numpy()[0]
     want, th_o = oracle.vqe_run(spec, ham, [0.0], 50, optimizer="gd", lr=0.2)
-    np.testing.assert_allclose(traj, want, atol=E_TOL)
-    assert abs(th.item() - th_o[0]) < 1e-9
+    for mode in (0, 1):
+        ctx.set_loop_mode(mode)
+        th = dev(np.zeros((1, 1)))
+        traj = vqe.run(ctx, C, H, th, 50, optimizer="gd", lr=0.2).cpu().numpy()[0]
+        np.testing.assert_allclose(traj, want, atol=E_TOL)
+        assert abs(th.item() - th_o[0]) < 1e-9
+    ctx.set_loop_mode(0)
 
 
+@pytest.mark.parametrize("mode", [0, 1])
 @pytest.mark.parametrize("n_orb", [2, 4])
-def test_batched_pes_adam_trajectories(vqe, ctx, n_orb):
-    _say("pes", n_orb)
+def test_batched_pes_adam_trajectories(vqe, ctx, n_orb, mode):
+    _say("pes", n_orb, "loop mode", mode)
+    ctx.set_loop_mode(mode)
     B, iters = 100, 200 if n_orb == 2 else 60
     model = synth.smooth_integral_model(n_orb, seed=synth.MASTER_SEED)
     ds = synth.bond_grid(B)
@@ -204,6 +209,7 @@ def test_batched_pes_adam_trajectories(vqe, ctx, n_orb):
     th = dev(np.zeros((B, spec.n_params)))
     traj = vqe.run(ctx, C, hams, th, iters).cpu().numpy()
     th_final = th.cpu().numpy()
+    ctx.set_loop_mode(0)
     for b in range(0, B, 9 if n_orb == 2 else 33):
         ho = fermion.qubit_hamiltonian(ints[b])
         want, tho = oracle.vqe_run(spec, ho, np.zeros(spec.n_params), iters)
