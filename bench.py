@@ -1,0 +1,280 @@
+"""Benchmark of the VQE hot path on one MI355X.
+
+Workload (the batched potential-energy-surface scan): 100 bond lengths d in
+[0.3, 3.0], integrals that are seeded smooth functions of d, the 4-qubit
+model (2 spatial orbitals, HF |1100> + one DoubleExcitation) and the 8-qubit
+model (4 spatial orbitals, all spin-conserving single and double
+excitations from the HF state), each bond length optimised with Adam
+(lr 0.01, 200 iterations, theta_0 = 0) on adjoint gradients, complex128.
+One step = one full scan of both qubit counts: 2 x 100 x 200 = 40,000
+energy + gradient evaluations, the Hamiltonians resident on the device.
+
+Prints one JSON line.  Extra objects: `roofline` for the dominant kernel
+(the persistent loop of the 8-qubit scan), `cpu_baseline` (the oracle on a
+bounded sample of the same workload, rank 0 only), `setup` (host-side
+Hamiltonian build and upload per scan, outside the timed region) and
+`hea` (a large-state energy + gradient evaluation of the hardware-efficient
+ansatz with per-pass HBM bandwidth, measured separately).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+ITERS = 200
+BATCH = 100
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-hea", action="store_true")
+    ap.add_argument("--hea-n", type=int, default=24)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+# ---------------------------------------------------------------------------
+# algorithmic work per evaluation (counted from the problem, not the kernel)
+# ---------------------------------------------------------------------------
+GATE_FLOPS_PER_PAIR = {"RX": 12, "RY": 12, "RZ": 12, "H": 8, "X": 0, "CNOT": 0, "CZ": 0,
+                       "SingleExcitation": 12, "DoubleExcitation": 12}
+# active pairs of a gate on n qubits: 2^(n - number of pattern-fixed wires)
+FIXED_WIRES = {"RX": 1, "RY": 1, "RZ": 1, "H": 1, "X": 1, "CNOT": 2, "CZ": 2, "SingleExcitation": 2,
+               "DoubleExcitation": 4}
+
+
+def eval_flops(spec, n_terms, n_groups, n_diag_terms):
+    """Algorithmic FP64 flops of one energy + adjoint-gradient evaluation.
+
+    gates: 12 flops per active amplitude pair for rotations, 8 for H, 0 for
+    permutations; H psi: 1 flop per term per pair (signed accumulate) plus 16
+    per pair per flip group (two complex multiply-adds), diagonal group 4 per
+    amplitude plus 1 per term per amplitude; E = Re<psi|lambda>: 4 per
+    amplitude; reverse sweep: the gates twice (psi and lambda) plus 7 flops
+    per active pair of every parametric gate.
+    """
+    n = spec.n
+    D = 1 << n
+    fwd = 0
+    grad = 0
+    for k, p in zip(spec.kinds, spec.param_idx):
+        pairs = D >> FIXED_WIRES[k]
+        fwd += GATE_FLOPS_PER_PAIR[k] * pairs
+        if p >= 0:
+            grad += 7 * pairs
+    off_terms = n_terms - n_diag_terms
+    off_groups = n_groups - (1 if n_diag_terms else 0)
+    hpsi = (D // 2) * (off_terms + 16 * off_groups) + D * (n_diag_terms + 4 * (1 if n_diag_terms else 0))
+    energy = 4 * D
+    return fwd + hpsi + energy + 2 * fwd + grad
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "gpus_requested": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    from paper_2601_09951_amd import vqe
+
+    dev = torch.device("cuda:0")
+    ctx = vqe.Context(0)
+    stream = torch.cuda.current_stream(dev)
+
+    # ---------------------------------------------------------------- setup
+    ds = synth.bond_grid(BATCH)
+    problems = []
+    t0 = time.perf_counter()
+    for n_orb, spec in ((2, synth.h2_circuit()), (4, synth.ucc_circuit(8, 2))):
+        model = synth.smooth_integral_model(n_orb, seed=synth.MASTER_SEED)
+        ints = [model.at(float(d)) for d in ds]
+        hams = [vqe.Hamiltonian.from_integrals(ctx, i.h1, i.h2, i.e_core) for i in ints]
+        C = vqe.Circuit.from_spec(ctx, spec)
+        theta = torch.zeros(BATCH, spec.n_params, dtype=torch.float64, device=dev)
+        ws = vqe.workspace(ctx, C, hams, BATCH, 2)
+        energies = torch.empty(BATCH, ITERS + 1, dtype=torch.float64, device=dev)
+        problems.append(dict(n=spec.n, spec=spec, ints=ints, hams=hams, C=C, theta=theta, ws=ws,
+                             energies=energies))
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+
+    def one_scan(events=None):
+        for i, p in enumerate(problems):
+            p["theta"].zero_()
+            if events is not None:
+                events[i][0].record(stream)
+            vqe.run(ctx, p["C"], p["hams"], p["theta"], ITERS, ws=p["ws"], energies=p["energies"])
+            if events is not None:
+                events[i][1].record(stream)
+
+    for _ in range(args.warmup):
+        one_scan()
+    torch.cuda.synchronize()
+
+    K = args.steps
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in problems]
+          for _ in range(K)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(K):
+        one_scan([ev[s][i] for i in range(len(problems))])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    evals = K * len(problems) * BATCH * ITERS
+    value = evals / elapsed
+    kernel_ms = {p["n"]: float(np.mean([ev[s][i][0].elapsed_time(ev[s][i][1]) for s in range(K)]))
+                 for i, p in enumerate(problems)}
+
+    # roofline of the dominant kernel: the persistent loop of the 8-qubit scan
+    p8 = problems[1]
+    x, z, c = p8["hams"][0].terms()
+    n_diag = int(np.sum(x == 0))
+    n_groups = len(set(int(v) for v in x))
+    flops_eval = eval_flops(p8["spec"], len(c), n_groups, n_diag)
+    flops_launch = flops_eval * BATCH * ITERS
+    achieved = flops_launch / (kernel_ms[8] * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": "k_small_run (8 qubits, 100 instances x 200 steps)",
+                "achieved": round(achieved, 4), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP64_PEAK_TFLOPS, 5), "traffic": None,
+                "flops_per_eval": flops_eval, "kernel_ms": round(kernel_ms[8], 4)}
+
+    final_e = {p["n"]: p["energies"][:, -1].cpu().numpy() for p in problems}
+    out = {
+        "metric": "VQE energy+grad evals/s (batched PES scan, 4q + 8q)",
+        "value": round(value, 1),
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / K * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "batched PES scan: 100 bond lengths x 200 Adam steps, 4-qubit H2-like "
+                               "(15 terms) and 8-qubit all-excitations (UCC) models, complex128",
+                   "global_batch": BATCH, "iterations": ITERS, "qubits": [4, 8],
+                   "evals_per_step": len(problems) * BATCH * ITERS},
+        "kernel_ms": {f"{k}q": round(v, 4) for k, v in kernel_ms.items()},
+        "setup": {"seconds": round(setup_s, 3),
+                  "what": "host Jordan-Wigner of 200 Hamiltonians + device upload + plans (outside timing)"},
+        "roofline": roofline,
+        "pes_min_energy": {f"{k}q": round(float(np.min(v)), 10) for k, v in final_e.items()},
+    }
+
+    # -------------------------------------------------- large-state HEA
+    if not args.no_hea:
+        out["hea"] = hea_measure(ctx, vqe, synth, torch, args.hea_n)
+
+    # -------------------------------------------------- CPU baseline
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(problems, args.cpu_seconds)
+
+    print(json.dumps(out), flush=True)
+
+
+def hea_measure(ctx, vqe, synth, torch, n):
+    """One energy + gradient of the hardware-efficient ansatz (L = n layers,
+    500 random Pauli strings) and the HBM bandwidth of its forward passes."""
+    dev = torch.device("cuda:0")
+    spec = synth.hea_circuit(n, n)
+    ham = synth.random_pauli_sum(n, 500, seed=synth.MASTER_SEED + n)
+    C = vqe.Circuit.from_spec(ctx, spec)
+    H = vqe.Hamiltonian.from_sum(ctx, ham)
+    th = torch.tensor(synth.uniform_thetas(spec.n_params, 1, seed=synth.MASTER_SEED + n), device=dev)
+    ws = vqe.workspace(ctx, C, H, 1, 1)
+    e = torch.empty(1, dtype=torch.float64, device=dev)
+    g = torch.empty(1, spec.n_params, dtype=torch.float64, device=dev)
+    vqe.energy_grad(ctx, C, H, th, ws=ws, out_e=e, out_g=g)
+    torch.cuda.synchronize()
+    reps = 3
+    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s0.record()
+    for _ in range(reps):
+        vqe.energy_grad(ctx, C, H, th, ws=ws, out_e=e, out_g=g)
+    s1.record()
+    torch.cuda.synchronize()
+    ms_eval = s0.elapsed_time(s1) / reps
+    # forward passes alone
+    passes, _ = vqe.circuit_plan(ctx, C)
+    psi = torch.empty(1, 1 << n, dtype=torch.complex128, device=dev)
+    vqe.prepare_reference(ctx, n, 1, 0, psi)
+    vqe.apply_ansatz(ctx, C, th, psi)
+    torch.cuda.synchronize()
+    s0.record()
+    for _ in range(reps):
+        vqe.apply_ansatz(ctx, C, th, psi)
+    s1.record()
+    torch.cuda.synchronize()
+    ms_fwd = s0.elapsed_time(s1) / reps
+    pass_ms = ms_fwd / len(passes)
+    gbps = 32.0 * (1 << n) / (pass_ms * 1e-3) / 1e9
+    # expectation sweeps alone
+    pl = vqe.hamiltonian_plan(ctx, H, 1, False)
+    s0.record()
+    for _ in range(reps):
+        vqe.expect(ctx, H, psi)
+    s1.record()
+    torch.cuda.synchronize()
+    ms_exp = s0.elapsed_time(s1) / reps
+    sweep_gbps = 16.0 * (1 << n) * len(pl["sweeps"]) / (ms_exp * 1e-3) / 1e9
+    return {"n": n, "layers": n, "gates": spec.n_gates, "params": spec.n_params, "terms": 500,
+            "flip_groups": int(H.n_groups), "ms_per_energy_grad": round(ms_eval, 3),
+            "forward_passes": int(len(passes)), "ms_forward": round(ms_fwd, 3),
+            "forward_pass_GBps": round(gbps, 1), "forward_pass_frac_of_hbm": round(gbps / HBM_PEAK_GBPS, 4),
+            "expect_sweeps": int(len(pl["sweeps"])), "ms_expect": round(ms_exp, 3),
+            "expect_sweep_GBps": round(sweep_gbps, 1),
+            "expect_sweep_frac_of_hbm": round(sweep_gbps / HBM_PEAK_GBPS, 4)}
+
+
+def cpu_baseline(problems, budget_s):
+    """The oracle (plain FP64 C, one thread) on a bounded sample of the same
+    scan: the first bond lengths of each qubit count, 200 Adam steps each on
+    adjoint gradients.  Each qubit count gets about budget_s / 2 seconds of
+    wall time (the oracle's dense Jordan-Wigner build included, but only the
+    optimisation loop is timed); the rate is scaled to the full scan."""
+    import oracle
+    from oracle import fermion
+    oracle.set_threads(1)
+    done, spent = {}, {}
+    for p in problems:
+        n = p["n"]
+        done[n], spent[n] = 0, 0.0
+        wall0 = time.perf_counter()
+        while done[n] < BATCH and (done[n] == 0 or time.perf_counter() - wall0 < budget_s / 2):
+            ho = fermion.qubit_hamiltonian(p["ints"][done[n]])
+            t0 = time.perf_counter()
+            oracle.vqe_run(p["spec"], ho, np.zeros(p["spec"].n_params), ITERS)
+            spent[n] += time.perf_counter() - t0
+            done[n] += 1
+    scan_s = sum(spent[n] / done[n] * BATCH for n in spent)
+    evals = len(spent) * BATCH * ITERS
+    return {"value": round(evals / scan_s, 1), "unit": "evals/s", "cores": 1, "kind": "oracle",
+            "sample": " and ".join(f"{done[n]} x {n}q bond lengths" for n in sorted(done))
+                      + f", {ITERS} Adam steps each (adjoint gradients), "
+                      f"{sum(spent.values()):.1f} s of timed CPU; rate scaled to the full 2 x {BATCH}-bond scan",
+            "per_qubit_evals_per_s": {f"{n}q": round(done[n] * ITERS / spent[n], 1) for n in sorted(spent)}}
+
+
+if __name__ == "__main__":
+    main()
