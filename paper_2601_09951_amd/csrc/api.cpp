@@ -209,9 +209,11 @@ int forward(Context *ctx, Circ *C, int64_t B, const double *theta, double2 *psi,
                                          C->n_params, B, mats, s),
                    "gate matrices");
     if (rc) return rc;
-    for (const PassPlan &pp : fp->passes) {
-        rc = hip_check(ctx, launch_forward_pass(pp, reinterpret_cast<const OpDesc *>(fp->ops.p), mats, G,
-                                                psi, B, ctx->wg_max, s),
+    for (size_t i = 0; i < fp->passes.size(); ++i) {
+        const PassPlan &pp = fp->passes[i];
+        rc = hip_check(ctx, launch_forward_pass(pp, reinterpret_cast<const TileGeom *>(fp->geoms.p) + i,
+                                                reinterpret_cast<const OpDesc *>(fp->ops.p), mats, G, psi, B,
+                                                ctx->wg_max, s),
                        "forward pass");
         if (rc) return rc;
     }
@@ -269,8 +271,10 @@ int energy_grad_into(Context *ctx, Circ *C, int n_hams, Ham *const *H, int64_t B
     rc = hip_check(ctx, launch_reduce_slots(pe, 1, L.W_hpsi, B, energy, e_stride, 1.0, s), "energy reduce");
     if (rc) return rc;
     const int G = (int)C->gates.size();
-    for (const PassPlan &p : rp->passes) {
-        rc = hip_check(ctx, launch_reverse_pass(p, reinterpret_cast<const OpDesc *>(rp->ops.p), mats, G, psi,
+    for (size_t i = 0; i < rp->passes.size(); ++i) {
+        const PassPlan &p = rp->passes[i];
+        rc = hip_check(ctx, launch_reverse_pass(p, reinterpret_cast<const TileGeom *>(rp->geoms.p) + i,
+                                                reinterpret_cast<const OpDesc *>(rp->ops.p), mats, G, psi,
                                                 lam, B, L.W_rev, pg, C->n_pgates, s),
                        "reverse pass");
         if (rc) return rc;
@@ -340,6 +344,7 @@ int vqe_ctx_destroy(vqe_ctx_t ctx)
     if (ctx->device >= 0) (void)hipSetDevice(ctx->device);
     for (auto &kv : ctx->pauli_cache) {
         dev_free(ctx, kv.second->groups);
+            dev_free(ctx, kv.second->geoms);
         dev_free(ctx, kv.second->toff);
         dev_free(ctx, kv.second->terms);
     }
@@ -369,6 +374,7 @@ int vqe_ctx_set_tile(vqe_ctx_t ctx, int k_fwd, int k_rev, int c_low)
         }
         for (auto &kv : ctx->pauli_cache) {
             dev_free(ctx, kv.second->groups);
+            dev_free(ctx, kv.second->geoms);
             dev_free(ctx, kv.second->toff);
             dev_free(ctx, kv.second->terms);
         }
@@ -516,6 +522,7 @@ int vqe_ham_destroy(vqe_ham_t ham)
                     synced = true;
                 }
                 dev_free(ctx, it->second->groups);
+                dev_free(ctx, it->second->geoms);
                 dev_free(ctx, it->second->toff);
                 dev_free(ctx, it->second->terms);
                 it = ctx->pauli_cache.erase(it);
@@ -591,7 +598,10 @@ int vqe_circ_destroy(vqe_circ_t C)
         (void)hipDeviceSynchronize();
     }
     for (auto *cache : {&C->fwd, &C->rev})
-        for (auto &kv : *cache) dev_free(ctx, kv.second->ops);
+        for (auto &kv : *cache) {
+            dev_free(ctx, kv.second->ops);
+            dev_free(ctx, kv.second->geoms);
+        }
     dev_free(ctx, C->gates_dev);
     dev_free(ctx, C->pmap_off);
     dev_free(ctx, C->pmap_idx);
@@ -785,10 +795,21 @@ int vqe_run(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams, i
         PauliPlan *pp = get_pauli_plan(ctx, n_hams, H.data(), n_inst, ctx->k_rev, ctx->c_low, &rc);
         if (!pp) return rc;
         const int G = (int)circ->gates.size();
+        // per-instance term counts and whether any phase is imaginary
+        int max_inst_terms = 0, has_imag = 0;
+        const int NU = pp->n_ugroups;
+        for (int i = 0; i < pp->n_inst; ++i) {
+            const int32_t *o = &pp->host_toff[(size_t)i * NU * 3];
+            max_inst_terms = std::max(max_inst_terms, o[(NU - 1) * 3 + 2] - o[0]);
+            for (int g = 0; g < NU; ++g)
+                if (o[3 * g + 2] > o[3 * g + 1]) has_imag = 1;
+        }
+        int mode = 0;
+        size_t lds = 0;
         if (fp->passes.size() == 1 && rp->passes.size() == 1 && pp->sweeps.size() == 1 &&
             fp->passes[0].op_count == G && rp->passes[0].op_count == G &&
-            pp->sweeps[0].grp_count == pp->n_ugroups &&
-            small_run_supported(n, G, P, circ->n_pgates, pp->max_terms_group)) {
+            pp->sweeps[0].grp_count == NU &&
+            small_run_plan(n, G, P, circ->n_pgates, NU, max_inst_terms, has_imag, &mode, &lds)) {
             SmallRunArgs a;
             a.n = n;
             a.n_gates = G;
@@ -814,7 +835,7 @@ int vqe_run(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams, i
             return hip_check(ctx, launch_small_run(a, reinterpret_cast<const OpDesc *>(rp->ops.p),
                                                    reinterpret_cast<const int32_t *>(circ->pmap_off.p),
                                                    reinterpret_cast<const int32_t *>(circ->pmap_idx.p),
-                                                   circ->n_pgates, batch, s),
+                                                   circ->n_pgates, mode, max_inst_terms, batch, s),
                              "persistent VQE loop");
         }
     }

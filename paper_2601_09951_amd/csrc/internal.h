@@ -128,6 +128,7 @@ struct CircPlan {
     bool reverse = false;
     std::vector<PassPlan> passes;
     DevMem ops;              // OpDesc[]
+    DevMem geoms;            // TileGeom[passes] (read through a pointer by the kernels)
     std::vector<OpDesc> host_ops;
     int max_param_ops = 0;
 };
@@ -156,6 +157,7 @@ struct PauliPlan {
     int n_ugroups = 0;
     std::vector<SweepPlan> sweeps;
     DevMem groups;   // GroupDev[total groups over sweeps]
+    DevMem geoms;    // TileGeom[sweeps]
     DevMem toff;     // int32 [n_inst][n_ugroups][3] (begin_re, begin_im, end)
     DevMem terms;    // TermDev[] (per instance, grouped)
     std::vector<GroupDev> host_groups;
@@ -207,10 +209,11 @@ TileGeom make_geom(int n, int k, int c, const std::vector<int> &tile_bits);
 hipError_t launch_prepare(double2 *psi, int n, int64_t batch, uint64_t ref, hipStream_t s);
 hipError_t launch_gate_mats(const GateDev *gates, int n_gates, const double *theta,
                             int n_params, int64_t batch, double2 *mats, hipStream_t s);
-hipError_t launch_forward_pass(const PassPlan &pp, const OpDesc *ops, const double2 *mats,
-                               int n_gates, double2 *psi, int64_t batch, int wg_max,
-                               hipStream_t s);
-hipError_t launch_reverse_pass(const PassPlan &pp, const OpDesc *ops, const double2 *mats,
+hipError_t launch_forward_pass(const PassPlan &pp, const TileGeom *geom_dev, const OpDesc *ops,
+                               const double2 *mats, int n_gates, double2 *psi, int64_t batch,
+                               int wg_max, hipStream_t s);
+hipError_t launch_reverse_pass(const PassPlan &pp, const TileGeom *geom_dev, const OpDesc *ops,
+                               const double2 *mats,
                                int n_gates, double2 *psi, double2 *lam, int64_t batch,
                                int wg_per_inst, double *partials, int n_pgates,
                                hipStream_t s);
@@ -247,8 +250,10 @@ struct SmallRunArgs {
     double *work;                  // [B][2P] Adam moments
 };
 hipError_t launch_small_run(const SmallRunArgs &a, const OpDesc *rops, const int32_t *pmap_off,
-                            const int32_t *pmap_idx, int n_pgates, int64_t batch, hipStream_t s);
-int small_run_supported(int n, int n_gates, int n_params, int n_pgates, int max_terms);
+                            const int32_t *pmap_idx, int n_pgates, int mode, int max_inst_terms,
+                            int64_t batch, hipStream_t s);
+int small_run_plan(int n, int n_gates, int n_params, int n_pgates, int n_groups, int max_inst_terms,
+                   int has_imag, int *mode_out, size_t *lds_out);
 }  // namespace vqe
 
 struct vqe_ctx : vqe::Context {};

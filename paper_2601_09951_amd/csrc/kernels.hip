@@ -27,31 +27,42 @@ __device__ __forceinline__ double2 cadd(double2 a, double2 b)
 }
 __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
 
-__device__ __forceinline__ uint32_t insert_zeros(uint32_t j, int nfix, const uint8_t *pos)
+// zero bits inserted at the ascending positions packed 6 bits apiece in `pack`
+__device__ __forceinline__ uint32_t insert_zeros(uint32_t j, uint64_t pack, int nfix)
 {
     for (int i = 0; i < nfix; ++i) {
-        const uint32_t p = pos[i];
+        const uint32_t p = (uint32_t)(pack >> (6 * i)) & 63u;
         j = ((j >> p) << (p + 1)) | (j & ((1u << p) - 1u));
     }
     return j;
 }
 
-__device__ __forceinline__ uint64_t tile_base(const TileGeom &g, int64_t t)
+// the fixed positions of an op as one register word (compile-time indices only)
+__device__ __forceinline__ uint64_t fix_pack(const OpDesc &o)
+{
+    uint64_t pk = 0;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) pk |= (uint64_t)o.fixpos[i] << (6 * i);
+    return pk;
+}
+
+// geometry is read through a device pointer (uniform scalar loads)
+__device__ __forceinline__ uint64_t tile_base(const TileGeom *__restrict__ gp, int nout, int64_t t)
 {
     uint64_t base = 0;
-    for (int i = 0; i < g.nout; ++i)
-        if ((t >> i) & 1) base |= 1ull << g.opos[i];
+    for (int i = 0; i < nout; ++i)
+        if ((t >> i) & 1) base |= 1ull << gp->opos[i];
     return base;
 }
 
 // offsets of the gathered (non-contiguous) part of a tile
-__device__ __forceinline__ void fill_hoff(const TileGeom &g, uint64_t *hoff)
+__device__ __forceinline__ void fill_hoff(const TileGeom *__restrict__ gp, int k, int c, uint64_t *hoff)
 {
-    const int nh = 1 << (g.k - g.c);
+    const int nh = 1 << (k - c);
     for (int h = threadIdx.x; h < nh; h += blockDim.x) {
         uint64_t o = 0;
-        for (int i = 0; i < g.k - g.c; ++i)
-            if ((h >> i) & 1) o |= 1ull << g.tpos[g.c + i];
+        for (int i = 0; i < k - c; ++i)
+            if ((h >> i) & 1) o |= 1ull << gp->tpos[c + i];
         hoff[h] = o;
     }
 }
@@ -128,32 +139,33 @@ __global__ void k_gate_mats(const GateDev *__restrict__ gates, int n_gates,
 // ---------------------------------------------------------------------------
 // forward pass: apply the pass's ops in order to every tile
 __global__ __launch_bounds__(kThreads) void k_forward_pass(
-    TileGeom g, const OpDesc *__restrict__ ops, int nops, const double2 *__restrict__ mats,
-    int n_gates, double2 *__restrict__ psi, int64_t tiles)
+    const TileGeom *__restrict__ gp, int n, int k, int c, int nout, const OpDesc *__restrict__ ops,
+    int nops, const double2 *__restrict__ mats, int n_gates, double2 *__restrict__ psi, int64_t tiles)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     double2 *tile = reinterpret_cast<double2 *>(smem);
-    uint64_t *hoff = reinterpret_cast<uint64_t *>(smem + (16u << g.k));
+    uint64_t *hoff = reinterpret_cast<uint64_t *>(smem + (16u << k));
     const int tid = threadIdx.x;
-    const uint64_t dim = 1ull << g.n;
+    const uint64_t dim = 1ull << n;
     double2 *st = psi + (uint64_t)blockIdx.y * dim;
     const double2 *M = mats + (size_t)blockIdx.y * n_gates * 4;
-    const int T = 1 << g.k;
-    const uint32_t lowm = (1u << g.c) - 1u;
-    fill_hoff(g, hoff);
+    const int T = 1 << k;
+    const uint32_t lowm = (1u << c) - 1u;
+    fill_hoff(gp, k, c, hoff);
     __syncthreads();
     for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
-        const uint64_t base = tile_base(g, t);
-        for (int j = tid; j < T; j += kThreads) tile[j] = st[base + hoff[j >> g.c] + (j & lowm)];
+        const uint64_t base = tile_base(gp, nout, t);
+        for (int j = tid; j < T; j += kThreads) tile[j] = st[base + hoff[j >> c] + (j & lowm)];
         __syncthreads();
         for (int q = 0; q < nops; ++q) {
             const OpDesc o = ops[q];
             if ((base & o.cmask_out) != o.cval_out) continue;
+            const uint64_t pk = fix_pack(o);
             const double2 u00 = M[o.gate * 4 + 0], u01 = M[o.gate * 4 + 1];
             const double2 u10 = M[o.gate * 4 + 2], u11 = M[o.gate * 4 + 3];
-            const int np = 1 << (g.k - o.nfix);
+            const int np = 1 << (k - o.nfix);
             for (int j = tid; j < np; j += kThreads) {
-                const uint32_t p0 = insert_zeros((uint32_t)j, o.nfix, o.fixpos) | o.fixed_bits;
+                const uint32_t p0 = insert_zeros((uint32_t)j, pk, o.nfix) | o.fixed_bits;
                 const uint32_t p1 = p0 ^ o.m;
                 const double2 a = tile[p0], b = tile[p1];
                 if (o.cls == CLS_SWAP) {
@@ -169,7 +181,7 @@ __global__ __launch_bounds__(kThreads) void k_forward_pass(
             }
             __syncthreads();
         }
-        for (int j = tid; j < T; j += kThreads) st[base + hoff[j >> g.c] + (j & lowm)] = tile[j];
+        for (int j = tid; j < T; j += kThreads) st[base + hoff[j >> c] + (j & lowm)] = tile[j];
         __syncthreads();
     }
 }
@@ -182,29 +194,30 @@ __global__ __launch_bounds__(kThreads) void k_forward_pass(
 // across this workgroup's tiles), then written as one partial per
 // (instance, parametric gate, workgroup).
 __global__ __launch_bounds__(kThreads) void k_reverse_pass(
-    TileGeom g, const OpDesc *__restrict__ ops, int nops, int n_param_ops,
-    const double2 *__restrict__ mats, int n_gates, double2 *__restrict__ psi,
-    double2 *__restrict__ lam, int64_t tiles, double *__restrict__ partials, int n_pgates)
+    const TileGeom *__restrict__ gp, int n, int k, int c, int nout, const OpDesc *__restrict__ ops,
+    int nops, int n_param_ops, const double2 *__restrict__ mats, int n_gates,
+    double2 *__restrict__ psi, double2 *__restrict__ lam, int64_t tiles,
+    double *__restrict__ partials, int n_pgates)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     double2 *tp = reinterpret_cast<double2 *>(smem);
-    double2 *tl = tp + (1u << g.k);
-    uint64_t *hoff = reinterpret_cast<uint64_t *>(smem + (32u << g.k));
-    double *red = reinterpret_cast<double *>(hoff + (1u << (g.k - g.c)));
+    double2 *tl = tp + (1u << k);
+    uint64_t *hoff = reinterpret_cast<uint64_t *>(smem + (32u << k));
+    double *red = reinterpret_cast<double *>(hoff + (1u << (k - c)));
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint64_t dim = 1ull << g.n;
+    const uint64_t dim = 1ull << n;
     double2 *sp = psi + (uint64_t)blockIdx.y * dim;
     double2 *sl = lam + (uint64_t)blockIdx.y * dim;
     const double2 *M = mats + (size_t)blockIdx.y * n_gates * 4;
-    const int T = 1 << g.k;
-    const uint32_t lowm = (1u << g.c) - 1u;
-    fill_hoff(g, hoff);
+    const int T = 1 << k;
+    const uint32_t lowm = (1u << c) - 1u;
+    fill_hoff(gp, k, c, hoff);
     for (int i = tid; i < n_param_ops * 4; i += kThreads) red[i] = 0.0;
     __syncthreads();
     for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
-        const uint64_t base = tile_base(g, t);
+        const uint64_t base = tile_base(gp, nout, t);
         for (int j = tid; j < T; j += kThreads) {
-            const uint64_t gi = base + hoff[j >> g.c] + (j & lowm);
+            const uint64_t gi = base + hoff[j >> c] + (j & lowm);
             tp[j] = sp[gi];
             tl[j] = sl[gi];
         }
@@ -219,10 +232,11 @@ __global__ __launch_bounds__(kThreads) void k_reverse_pass(
             // U^dagger
             const double2 v00 = cconj(M[o.gate * 4 + 0]), v01 = cconj(M[o.gate * 4 + 2]);
             const double2 v10 = cconj(M[o.gate * 4 + 1]), v11 = cconj(M[o.gate * 4 + 3]);
-            const int np = 1 << (g.k - o.nfix);
+            const int np = 1 << (k - o.nfix);
+            const uint64_t pk = fix_pack(o);
             double acc = 0.0;
             for (int j = tid; j < np; j += kThreads) {
-                const uint32_t p0 = insert_zeros((uint32_t)j, o.nfix, o.fixpos) | o.fixed_bits;
+                const uint32_t p0 = insert_zeros((uint32_t)j, pk, o.nfix) | o.fixed_bits;
                 const uint32_t p1 = p0 ^ o.m;
                 const double2 a = tp[p0], b = tp[p1];
                 const double2 la = tl[p0], lb = tl[p1];
@@ -258,7 +272,7 @@ __global__ __launch_bounds__(kThreads) void k_reverse_pass(
             __syncthreads();
         }
         for (int j = tid; j < T; j += kThreads) {
-            const uint64_t gi = base + hoff[j >> g.c] + (j & lowm);
+            const uint64_t gi = base + hoff[j >> c] + (j & lowm);
             sp[gi] = tp[j];
             sl[gi] = tl[j];
         }
@@ -309,7 +323,8 @@ __device__ __forceinline__ void term_sums(const TermDev *__restrict__ terms, int
 }
 
 __global__ __launch_bounds__(kThreads) void k_pauli_sweep(
-    TileGeom g, const GroupDev *__restrict__ groups, int ngroups,
+    const TileGeom *__restrict__ gp, int n, int k, int c, int nout,
+    const GroupDev *__restrict__ groups, int ngroups,
     const int32_t *__restrict__ toff, int n_ugroups, const TermDev *__restrict__ terms,
     int shared_ham, const double2 *__restrict__ psi, double2 *__restrict__ lam, int64_t tiles,
     int first, int last, double *__restrict__ partials, int n_slots, int slot)
@@ -317,24 +332,24 @@ __global__ __launch_bounds__(kThreads) void k_pauli_sweep(
     extern __shared__ __align__(16) unsigned char smem[];
     const bool hpsi = lam != nullptr;
     double2 *tp = reinterpret_cast<double2 *>(smem);
-    double2 *tl = tp + (1u << g.k);
-    uint64_t *hoff = reinterpret_cast<uint64_t *>(smem + ((hpsi ? 32u : 16u) << g.k));
-    double *red = reinterpret_cast<double *>(hoff + (1u << (g.k - g.c)));
+    double2 *tl = tp + (1u << k);
+    uint64_t *hoff = reinterpret_cast<uint64_t *>(smem + ((hpsi ? 32u : 16u) << k));
+    double *red = reinterpret_cast<double *>(hoff + (1u << (k - c)));
     const int tid = threadIdx.x;
-    const uint64_t dim = 1ull << g.n;
+    const uint64_t dim = 1ull << n;
     const int inst = blockIdx.y;
     const double2 *sp = psi + (uint64_t)inst * dim;
     double2 *sl = hpsi ? lam + (uint64_t)inst * dim : nullptr;
     const int32_t *to = toff + (size_t)(shared_ham ? 0 : inst) * n_ugroups * 3;
-    const int T = 1 << g.k;
-    const uint32_t lowm = (1u << g.c) - 1u;
-    fill_hoff(g, hoff);
+    const int T = 1 << k;
+    const uint32_t lowm = (1u << c) - 1u;
+    fill_hoff(gp, k, c, hoff);
     __syncthreads();
     double acc = 0.0;
     for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
-        const uint64_t base = tile_base(g, t);
+        const uint64_t base = tile_base(gp, nout, t);
         for (int j = tid; j < T; j += kThreads) {
-            tp[j] = sp[base + hoff[j >> g.c] + (j & lowm)];
+            tp[j] = sp[base + hoff[j >> c] + (j & lowm)];
             if (hpsi) tl[j] = make_double2(0.0, 0.0);
         }
         __syncthreads();
@@ -376,7 +391,7 @@ __global__ __launch_bounds__(kThreads) void k_pauli_sweep(
         }
         if (hpsi) {
             for (int j = tid; j < T; j += kThreads) {
-                const uint64_t gi = base + hoff[j >> g.c] + (j & lowm);
+                const uint64_t gi = base + hoff[j >> c] + (j & lowm);
                 double2 v = tl[j];
                 if (!first) v = cadd(v, sl[gi]);
                 sl[gi] = v;
@@ -496,9 +511,9 @@ static size_t rev_lds(const TileGeom &g, int nparam)
     return (32u << g.k) + (8u << (g.k - g.c)) + 32u * (size_t)std::max(nparam, 1);
 }
 
-hipError_t launch_forward_pass(const PassPlan &pp, const OpDesc *ops, const double2 *mats,
-                               int n_gates, double2 *psi, int64_t batch, int wg_max,
-                               hipStream_t s)
+hipError_t launch_forward_pass(const PassPlan &pp, const TileGeom *geom_dev, const OpDesc *ops,
+                               const double2 *mats, int n_gates, double2 *psi, int64_t batch,
+                               int wg_max, hipStream_t s)
 {
     const TileGeom &g = pp.geom;
     const int64_t tiles = 1ll << g.nout;
@@ -506,23 +521,24 @@ hipError_t launch_forward_pass(const PassPlan &pp, const OpDesc *ops, const doub
     const size_t lds = fwd_lds(g);
     hipError_t e = ensure_lds(k_forward_pass, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_forward_pass, dim3(W, (unsigned)batch), dim3(kThreads), lds, s, g,
-                       ops + pp.op_begin, pp.op_count, mats, n_gates, psi, tiles);
+    hipLaunchKernelGGL(k_forward_pass, dim3(W, (unsigned)batch), dim3(kThreads), lds, s, geom_dev, g.n, g.k,
+                       g.c, g.nout, ops + pp.op_begin, pp.op_count, mats, n_gates, psi, tiles);
     return hipGetLastError();
 }
 
-hipError_t launch_reverse_pass(const PassPlan &pp, const OpDesc *ops, const double2 *mats,
-                               int n_gates, double2 *psi, double2 *lam, int64_t batch,
-                               int wg_per_inst, double *partials, int n_pgates, hipStream_t s)
+hipError_t launch_reverse_pass(const PassPlan &pp, const TileGeom *geom_dev, const OpDesc *ops,
+                               const double2 *mats, int n_gates, double2 *psi, double2 *lam,
+                               int64_t batch, int wg_per_inst, double *partials, int n_pgates,
+                               hipStream_t s)
 {
     const TileGeom &g = pp.geom;
     const int64_t tiles = 1ll << g.nout;
     const size_t lds = rev_lds(g, pp.n_param_ops);
     hipError_t e = ensure_lds(k_reverse_pass, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reverse_pass, dim3(wg_per_inst, (unsigned)batch), dim3(kThreads), lds, s,
-                       g, ops + pp.op_begin, pp.op_count, pp.n_param_ops, mats, n_gates, psi, lam,
-                       tiles, partials, n_pgates);
+    hipLaunchKernelGGL(k_reverse_pass, dim3(wg_per_inst, (unsigned)batch), dim3(kThreads), lds, s, geom_dev,
+                       g.n, g.k, g.c, g.nout, ops + pp.op_begin, pp.op_count, pp.n_param_ops, mats, n_gates,
+                       psi, lam, tiles, partials, n_pgates);
     return hipGetLastError();
 }
 
@@ -536,7 +552,8 @@ hipError_t launch_pauli_sweep(const SweepPlan &sp, const PauliPlan &pp, int swee
     const size_t lds = ((write_lambda ? 32u : 16u) << g.k) + (8u << (g.k - g.c)) + 64;
     hipError_t e = ensure_lds(k_pauli_sweep, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_pauli_sweep, dim3(wg_per_inst, (unsigned)batch), dim3(kThreads), lds, s, g,
+    hipLaunchKernelGGL(k_pauli_sweep, dim3(wg_per_inst, (unsigned)batch), dim3(kThreads), lds, s,
+                       reinterpret_cast<const TileGeom *>(pp.geoms.p) + sweep_idx, g.n, g.k, g.c, g.nout,
                        reinterpret_cast<const GroupDev *>(pp.groups.p) + sp.grp_begin, sp.grp_count,
                        reinterpret_cast<const int32_t *>(pp.toff.p), pp.n_ugroups,
                        reinterpret_cast<const TermDev *>(pp.terms.p), shared_ham, psi,

@@ -3,13 +3,20 @@
 //
 // One workgroup owns one instance (one bond length or parameter point, Eq. 7)
 // and keeps everything on chip for all iterations: psi and lambda in LDS,
-// gate matrices, parameters and Adam moments in LDS.  Each iteration runs
+// gate matrices, parameters and Adam moments in LDS, and the instance's
+// Hamiltonian.  Each iteration runs
 //   prepare e_ref -> gates (Eqs. 4-5) -> lambda = H psi, E = <psi|lambda>
 //   -> reverse sweep g_l = Im<lambda|G_l|psi> with U_l^dag on both
 //   -> dE/dtheta -> Adam (Section 3.4) or gradient descent,
-// and after the last step the energy at the final parameters.  There is no
-// host round trip and no HBM traffic inside the loop apart from the tiny
-// term tables (cache resident) and the per-step energy store.
+// and after the last step the energy at the final parameters.
+//
+// The Hamiltonian is held in one of two forms:
+//  * table form: for every flip group f the diagonal D_f[b] = s_f(b ^ f)
+//    with s_f(b) = sum_{t in f} kappa_t (-1)^{z_t . b}, so that
+//    lambda[b] = sum_f D_f[b] psi[b ^ f] is a barrier-free gather (H in
+//    XOR-offset diagonal storage, built once per launch);
+//  * term form (when the table does not fit LDS): terms staged in LDS and
+//    summed per pair of each flip group.
 #include "internal.h"
 
 namespace vqe {
@@ -26,10 +33,10 @@ __device__ __forceinline__ double2 cadd(double2 a, double2 b)
 }
 __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
 
-__device__ __forceinline__ uint32_t insert_zeros(uint32_t j, int nfix, const uint8_t *pos)
+__device__ __forceinline__ uint32_t insert_zeros(uint32_t j, uint64_t pack, int nfix)
 {
     for (int i = 0; i < nfix; ++i) {
-        const uint32_t p = pos[i];
+        const uint32_t p = (uint32_t)(pack >> (6 * i)) & 63u;
         j = ((j >> p) << (p + 1)) | (j & ((1u << p) - 1u));
     }
     return j;
@@ -81,46 +88,83 @@ __device__ __forceinline__ void gate_matrix(int kind, double a, double2 *m)
     m[3] = u11;
 }
 
-__device__ __forceinline__ void term_sums(const TermDev *__restrict__ terms, int tb, int tm, int te,
-                                          uint32_t b, double &A, double &B)
-{
-    A = 0.0;
-    B = 0.0;
-    for (int t = tb; t < tm; ++t) {
-        const TermDev d = terms[t];
-        A += (__popc(d.zloc & b) & 1) ? -d.w : d.w;
-    }
-    for (int t = tm; t < te; ++t) {
-        const TermDev d = terms[t];
-        B += (__popc(d.zloc & b) & 1) ? -d.w : d.w;
-    }
-}
-
-struct SmallLayout {
-    int D, G, P, NPG, nw;
-    size_t psi, lam, mats, th, mom, vel, grd, red, bred, total;
+// compact per-op record kept in LDS
+struct SmallOp {
+    uint32_t m, fixed_bits;
+    uint64_t fixpack;   // 6-bit fields: ascending fixed positions
+    int32_t gate, pgate;
+    int16_t cls, gen;
+    int32_t nfix;
 };
 
-__host__ __device__ inline SmallLayout small_layout(int n, int G, int P, int NPG, int nthreads)
+struct SmallLayout {
+    int D, G, P, NPG, NG, nw, nterms, mode;
+    size_t psi, lam, mats, th, mom, vel, grd, red, bred, ops, rops, gf, tab, toff, tz, tw, total;
+};
+
+// mode 1: real table, 2: complex table, 0: term form
+__host__ __device__ inline SmallLayout small_layout(int n, int G, int P, int NPG, int NG, int nterms,
+                                                    int nthreads, int mode)
 {
     SmallLayout L;
     L.D = 1 << n;
     L.G = G;
     L.P = P;
     L.NPG = NPG;
+    L.NG = NG;
+    L.nterms = nterms;
+    L.mode = mode;
     L.nw = nthreads / 64;
     size_t o = 0;
-    L.psi = o; o += (size_t)16 * L.D;
-    L.lam = o; o += (size_t)16 * L.D;
-    L.mats = o; o += (size_t)64 * G;
-    L.th = o; o += (size_t)8 * P;
-    L.mom = o; o += (size_t)8 * P;
-    L.vel = o; o += (size_t)8 * P;
-    L.grd = o; o += (size_t)8 * P;
-    L.red = o; o += (size_t)8 * NPG * L.nw;
-    L.bred = o; o += (size_t)8 * L.nw;
+    auto take = [&](size_t bytes, size_t align) {
+        o = (o + align - 1) / align * align;
+        size_t r = o;
+        o += bytes;
+        return r;
+    };
+    L.psi = take((size_t)16 * L.D, 16);
+    L.lam = take((size_t)16 * L.D, 16);
+    L.mats = take((size_t)64 * G, 16);
+    L.th = take((size_t)8 * P, 8);
+    L.mom = take((size_t)8 * P, 8);
+    L.vel = take((size_t)8 * P, 8);
+    L.grd = take((size_t)8 * P, 8);
+    L.red = take((size_t)8 * NPG * L.nw, 8);
+    L.bred = take((size_t)8 * L.nw, 8);
+    L.ops = take(sizeof(SmallOp) * G, 16);
+    L.rops = take(sizeof(SmallOp) * G, 16);
+    L.gf = take((size_t)8 * NG, 8);  // uint32 flip, uint32 pivot
+    if (mode == 1) {
+        L.tab = take((size_t)8 * NG * L.D, 16);
+        L.toff = L.tz = L.tw = o;
+    } else if (mode == 2) {
+        L.tab = take((size_t)16 * NG * L.D, 16);
+        L.toff = L.tz = L.tw = o;
+    } else {
+        L.tab = o;
+        L.toff = take((size_t)12 * NG, 4);
+        L.tz = take((size_t)4 * nterms, 4);
+        L.tw = take((size_t)8 * nterms, 8);
+    }
     L.total = o;
     return L;
+}
+
+__device__ __forceinline__ SmallOp pack_op(const OpDesc &o)
+{
+    SmallOp s;
+    s.m = o.m;
+    s.fixed_bits = o.fixed_bits;
+    uint64_t pk = 0;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) pk |= (uint64_t)o.fixpos[i] << (6 * i);
+    s.fixpack = pk;
+    s.gate = o.gate;
+    s.pgate = o.pgate;
+    s.cls = o.cls;
+    s.gen = o.gen;
+    s.nfix = o.nfix;
+    return s;
 }
 
 struct SmallKernelArgs {
@@ -129,34 +173,90 @@ struct SmallKernelArgs {
     const int32_t *pmap_off; // [P+1]
     const int32_t *pmap_idx;
     int n_pgates;
-    int nthreads;
+    int mode;
+    int max_inst_terms;
 };
 
 __global__ __launch_bounds__(256) void k_small_run(SmallKernelArgs ka)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const SmallRunArgs &a = ka.a;
-    const SmallLayout L = small_layout(a.n, a.n_gates, a.n_params, ka.n_pgates, blockDim.x);
+    const SmallLayout L = small_layout(a.n, a.n_gates, a.n_params, ka.n_pgates, a.n_groups, ka.max_inst_terms,
+                                       blockDim.x, ka.mode);
     double2 *psi = reinterpret_cast<double2 *>(smem + L.psi);
     double2 *lam = reinterpret_cast<double2 *>(smem + L.lam);
     double2 *mats = reinterpret_cast<double2 *>(smem + L.mats);
     double *th = reinterpret_cast<double *>(smem + L.th);
     double *mom = reinterpret_cast<double *>(smem + L.mom);
     double *vel = reinterpret_cast<double *>(smem + L.vel);
-    double *grd = reinterpret_cast<double *>(smem + L.grd);
     double *red = reinterpret_cast<double *>(smem + L.red);
     double *bred = reinterpret_cast<double *>(smem + L.bred);
+    SmallOp *fops = reinterpret_cast<SmallOp *>(smem + L.ops);
+    SmallOp *rops = reinterpret_cast<SmallOp *>(smem + L.rops);
+    uint32_t *gf = reinterpret_cast<uint32_t *>(smem + L.gf);
+    double *tabr = reinterpret_cast<double *>(smem + L.tab);
+    double2 *tabc = reinterpret_cast<double2 *>(smem + L.tab);
+    int32_t *stoff = reinterpret_cast<int32_t *>(smem + L.toff);
+    uint32_t *tz = reinterpret_cast<uint32_t *>(smem + L.tz);
+    double *tw = reinterpret_cast<double *>(smem + L.tw);
 
     const int tid = threadIdx.x, bs = blockDim.x, lane = tid & 63, wave = tid >> 6;
     const int inst = blockIdx.x;
-    const int D = L.D, G = L.G, P = L.P;
-    const int32_t *to = a.toff + (size_t)(a.shared_ham ? 0 : inst) * a.n_groups * 3;
+    const int D = L.D, G = L.G, P = L.P, NG = L.NG;
+    const int32_t *to = a.toff + (size_t)(a.shared_ham ? 0 : inst) * NG * 3;
     double *energies = a.energies + (size_t)inst * (a.iters + 1);
 
+    // ---- one-time staging: parameters, ops, groups, the Hamiltonian
     for (int p = tid; p < P; p += bs) {
         th[p] = a.theta[(size_t)inst * P + p];
         mom[p] = 0.0;
         vel[p] = 0.0;
+    }
+    for (int q = tid; q < G; q += bs) {
+        fops[q] = pack_op(a.ops[q]);
+        rops[q] = pack_op(ka.rops[q]);
+    }
+    for (int g = tid; g < NG; g += bs) {
+        gf[2 * g] = a.groups[g].floc;
+        gf[2 * g + 1] = a.groups[g].pivot;
+    }
+    __syncthreads();
+    if (ka.mode != 0) {
+        // D_g[b] = sum_t kappa_t (-1)^{z_t . (b ^ f_g)}
+        for (int i = tid; i < NG * D; i += bs) {
+            const int g = i / D;
+            const uint32_t b = (uint32_t)(i - g * D);
+            const int ug = a.groups[g].ugroup;
+            const int tb = to[ug * 3], tm = to[ug * 3 + 1], te = to[ug * 3 + 2];
+            const uint32_t bb = b ^ gf[2 * g];
+            double re = 0.0, im = 0.0;
+            for (int t = tb; t < tm; ++t) {
+                const TermDev d = a.terms[t];
+                re += (__popc(d.zloc & bb) & 1) ? -d.w : d.w;
+            }
+            for (int t = tm; t < te; ++t) {
+                const TermDev d = a.terms[t];
+                im += (__popc(d.zloc & bb) & 1) ? -d.w : d.w;
+            }
+            if (ka.mode == 1)
+                tabr[i] = re;
+            else
+                tabc[i] = make_double2(re, im);
+        }
+    } else {
+        // stage this instance's terms (contiguous in the term table)
+        const int t0 = to[0];
+        for (int g = tid; g < NG; g += bs) {
+            const int ug = a.groups[g].ugroup;
+            stoff[3 * g] = to[ug * 3] - t0;
+            stoff[3 * g + 1] = to[ug * 3 + 1] - t0;
+            stoff[3 * g + 2] = to[ug * 3 + 2] - t0;
+        }
+        const int t1 = to[(NG - 1) * 3 + 2];
+        for (int t = tid; t < t1 - t0; t += bs) {
+            tz[t] = a.terms[t0 + t].zloc;
+            tw[t] = a.terms[t0 + t].w;
+        }
     }
     __syncthreads();
 
@@ -166,19 +266,16 @@ __global__ __launch_bounds__(256) void k_small_run(SmallKernelArgs ka)
             const GateDev gd = a.gates[g];
             gate_matrix(gd.kind, gd.pidx >= 0 ? th[gd.pidx] : gd.fixed, mats + 4 * g);
         }
-        for (int j = tid; j < D; j += bs) {
-            psi[j] = make_double2(j == (int)a.ref ? 1.0 : 0.0, 0.0);
-            lam[j] = make_double2(0.0, 0.0);
-        }
+        for (int j = tid; j < D; j += bs) psi[j] = make_double2(j == (int)a.ref ? 1.0 : 0.0, 0.0);
         __syncthreads();
         // U(theta) e_ref
         for (int q = 0; q < G; ++q) {
-            const OpDesc o = a.ops[q];
+            const SmallOp o = fops[q];
             const double2 u00 = mats[4 * o.gate], u01 = mats[4 * o.gate + 1];
             const double2 u10 = mats[4 * o.gate + 2], u11 = mats[4 * o.gate + 3];
             const int np = D >> o.nfix;
             for (int j = tid; j < np; j += bs) {
-                const uint32_t p0 = insert_zeros((uint32_t)j, o.nfix, o.fixpos) | o.fixed_bits;
+                const uint32_t p0 = insert_zeros((uint32_t)j, o.fixpack, o.nfix) | o.fixed_bits;
                 const uint32_t p1 = p0 ^ o.m;
                 const double2 x = psi[p0], y = psi[p1];
                 if (o.cls == CLS_SWAP) {
@@ -194,50 +291,69 @@ __global__ __launch_bounds__(256) void k_small_run(SmallKernelArgs ka)
             }
             __syncthreads();
         }
-        // lambda = H psi (paired over (b, b ^ f)); E = Re <psi|lambda>
-        for (int q = 0; q < a.n_groups; ++q) {
-            const GroupDev gd = a.groups[q];
-            const int tb = to[gd.ugroup * 3], tm = to[gd.ugroup * 3 + 1], te = to[gd.ugroup * 3 + 2];
-            if (te == tb) continue;
-            if (gd.floc == 0) {
-                for (int j = tid; j < D; j += bs) {
-                    double A, B;
-                    term_sums(a.terms, tb, tm, te, (uint32_t)j, A, B);
-                    const double2 x = psi[j];
-                    lam[j] = cadd(lam[j], make_double2(A * x.x, A * x.y));
-                }
-            } else {
-                const uint32_t pv = gd.pivot;
-                for (int j = tid; j < (D >> 1); j += bs) {
-                    const uint32_t b = (((uint32_t)j >> pv) << (pv + 1)) | ((uint32_t)j & ((1u << pv) - 1u));
-                    const uint32_t bf = b ^ gd.floc;
-                    double A, B;
-                    term_sums(a.terms, tb, tm, te, b, A, B);
-                    const double2 x0 = psi[b], x1 = psi[bf];
-                    lam[bf] = cadd(lam[bf], make_double2(A * x0.x - B * x0.y, A * x0.y + B * x0.x));
-                    lam[b] = cadd(lam[b], make_double2(A * x1.x + B * x1.y, A * x1.y - B * x1.x));
-                }
-            }
-            __syncthreads();
-        }
+        // lambda = H psi; E = Re <psi|lambda>
         double e = 0.0;
-        for (int j = tid; j < D; j += bs) e += psi[j].x * lam[j].x + psi[j].y * lam[j].y;
-        e = block_sum_all(e, bred);
+        if (ka.mode != 0) {
+            for (int b = tid; b < D; b += bs) {
+                double2 acc = make_double2(0.0, 0.0);
+                if (ka.mode == 1) {
+                    for (int g = 0; g < NG; ++g) {
+                        const double d = tabr[g * D + b];
+                        const double2 x = psi[b ^ gf[2 * g]];
+                        acc.x += d * x.x;
+                        acc.y += d * x.y;
+                    }
+                } else {
+                    for (int g = 0; g < NG; ++g) acc = cadd(acc, cmul(tabc[g * D + b], psi[b ^ gf[2 * g]]));
+                }
+                lam[b] = acc;
+                const double2 x = psi[b];
+                e += x.x * acc.x + x.y * acc.y;
+            }
+        } else {
+            for (int j = tid; j < D; j += bs) lam[j] = make_double2(0.0, 0.0);
+            __syncthreads();
+            for (int g = 0; g < NG; ++g) {
+                const uint32_t f = gf[2 * g], pv = gf[2 * g + 1];
+                const int tb = stoff[3 * g], tm = stoff[3 * g + 1], te = stoff[3 * g + 2];
+                if (te == tb) continue;
+                if (f == 0) {
+                    for (int j = tid; j < D; j += bs) {
+                        double A = 0.0;
+                        for (int t = tb; t < tm; ++t) A += (__popc(tz[t] & (uint32_t)j) & 1) ? -tw[t] : tw[t];
+                        const double2 x = psi[j];
+                        lam[j] = cadd(lam[j], make_double2(A * x.x, A * x.y));
+                    }
+                } else {
+                    for (int j = tid; j < (D >> 1); j += bs) {
+                        const uint32_t b = (((uint32_t)j >> pv) << (pv + 1)) | ((uint32_t)j & ((1u << pv) - 1u));
+                        const uint32_t bf = b ^ f;
+                        double A = 0.0, B = 0.0;
+                        for (int t = tb; t < tm; ++t) A += (__popc(tz[t] & b) & 1) ? -tw[t] : tw[t];
+                        for (int t = tm; t < te; ++t) B += (__popc(tz[t] & b) & 1) ? -tw[t] : tw[t];
+                        const double2 x0 = psi[b], x1 = psi[bf];
+                        lam[bf] = cadd(lam[bf], make_double2(A * x0.x - B * x0.y, A * x0.y + B * x0.x));
+                        lam[b] = cadd(lam[b], make_double2(A * x1.x + B * x1.y, A * x1.y - B * x1.x));
+                    }
+                }
+                __syncthreads();
+            }
+            for (int j = tid; j < D; j += bs) e += psi[j].x * lam[j].x + psi[j].y * lam[j].y;
+        }
+        e = block_sum_all(e, bred);  // also orders the lambda writes before the reverse sweep
         if (tid == 0) energies[it] = e;
         if (it == a.iters) break;
 
         // reverse sweep
-        for (int i = tid; i < L.NPG * L.nw; i += bs) red[i] = 0.0;
-        __syncthreads();
         for (int q = 0; q < G; ++q) {
-            const OpDesc o = ka.rops[q];
+            const SmallOp o = rops[q];
             const double2 v00 = cconj(mats[4 * o.gate]), v01 = cconj(mats[4 * o.gate + 2]);
             const double2 v10 = cconj(mats[4 * o.gate + 1]), v11 = cconj(mats[4 * o.gate + 3]);
             const int np = D >> o.nfix;
             const bool param = o.pgate >= 0;
             double acc = 0.0;
             for (int j = tid; j < np; j += bs) {
-                const uint32_t p0 = insert_zeros((uint32_t)j, o.nfix, o.fixpos) | o.fixed_bits;
+                const uint32_t p0 = insert_zeros((uint32_t)j, o.fixpack, o.nfix) | o.fixed_bits;
                 const uint32_t p1 = p0 ^ o.m;
                 const double2 x = psi[p0], y = psi[p1];
                 const double2 lx = lam[p0], ly = lam[p1];
@@ -281,7 +397,6 @@ __global__ __launch_bounds__(256) void k_small_run(SmallKernelArgs ka)
                 for (int w = 0; w < L.nw; ++w) s += red[pg * L.nw + w];
                 gp += s;
             }
-            grd[p] = gp;
             if (a.opt == VQE_OPT_ADAM) {
                 const double mi = a.b1 * mom[p] + (1.0 - a.b1) * gp;
                 const double vi = a.b2 * vel[p] + (1.0 - a.b2) * gp * gp;
@@ -299,29 +414,50 @@ __global__ __launch_bounds__(256) void k_small_run(SmallKernelArgs ka)
     for (int p = tid; p < P; p += bs) a.theta[(size_t)inst * P + p] = th[p];
 }
 
+constexpr size_t kSmallLdsMax = 160 * 1024 - 1024;
+
+int choose_block(int n)
+{
+    if (n <= 6) return 64;
+    if (n <= 8) return 128;
+    return 256;
+}
+
 }  // namespace
 
-int small_run_supported(int n, int n_gates, int n_params, int n_pgates, int max_terms)
+// 1 if the persistent loop can run this problem; *mode_out gets the Hamiltonian form
+int small_run_plan(int n, int n_gates, int n_params, int n_pgates, int n_groups, int max_inst_terms,
+                   int has_imag, int *mode_out, size_t *lds_out)
 {
-    (void)max_terms;
-    if (n > 10 || n_gates > 1024 || n_params > 1024) return 0;
-    const int nthreads = n <= 7 ? 64 : (n == 8 ? 128 : 256);
-    const SmallLayout L = small_layout(n, n_gates, n_params, n_pgates, nthreads);
-    return L.total <= 150 * 1024;
+    if (n > 10 || n_gates > 2048 || n_params > 2048) return 0;
+    const int nt = choose_block(n);
+    int mode = has_imag ? 2 : 1;
+    SmallLayout L = small_layout(n, n_gates, n_params, n_pgates, n_groups, max_inst_terms, nt, mode);
+    if (L.total > kSmallLdsMax) {
+        mode = 0;
+        L = small_layout(n, n_gates, n_params, n_pgates, n_groups, max_inst_terms, nt, mode);
+        if (L.total > kSmallLdsMax) return 0;
+    }
+    *mode_out = mode;
+    *lds_out = L.total;
+    return 1;
 }
 
 hipError_t launch_small_run(const SmallRunArgs &a, const OpDesc *rops, const int32_t *pmap_off,
-                            const int32_t *pmap_idx, int n_pgates, int64_t batch, hipStream_t s)
+                            const int32_t *pmap_idx, int n_pgates, int mode, int max_inst_terms,
+                            int64_t batch, hipStream_t s)
 {
-    const int nthreads = a.n <= 7 ? 64 : (a.n == 8 ? 128 : 256);
+    const int nthreads = choose_block(a.n);
     SmallKernelArgs ka;
     ka.a = a;
     ka.rops = rops;
     ka.pmap_off = pmap_off;
     ka.pmap_idx = pmap_idx;
     ka.n_pgates = n_pgates;
-    ka.nthreads = nthreads;
-    const SmallLayout L = small_layout(a.n, a.n_gates, a.n_params, n_pgates, nthreads);
+    ka.mode = mode;
+    ka.max_inst_terms = max_inst_terms;
+    const SmallLayout L = small_layout(a.n, a.n_gates, a.n_params, n_pgates, a.n_groups, max_inst_terms,
+                                       nthreads, mode);
     if (L.total > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_small_run),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total);

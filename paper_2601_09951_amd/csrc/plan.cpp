@@ -173,7 +173,10 @@ int build_circuit_gates(Circ *C, int64_t n_gates, const int32_t *kind, const int
 
 static void free_plan(Context *ctx, CircPlan *p)
 {
-    if (p) dev_free(ctx, p->ops);
+    if (p) {
+        dev_free(ctx, p->ops);
+        dev_free(ctx, p->geoms);
+    }
 }
 
 CircPlan *get_circ_plan(Circ *C, bool reverse, int k, int c, int *rc)
@@ -265,6 +268,9 @@ CircPlan *get_circ_plan(Circ *C, bool reverse, int k, int c, int *rc)
     }
     if (!ops.empty()) {
         int r = upload(C->ctx, plan->ops, ops.data(), ops.size() * sizeof(OpDesc));
+        std::vector<TileGeom> geoms;
+        for (const PassPlan &pp : plan->passes) geoms.push_back(pp.geom);
+        if (!r) r = upload(C->ctx, plan->geoms, geoms.data(), geoms.size() * sizeof(TileGeom));
         if (r) {
             free_plan(C->ctx, plan.get());
             *rc = r;
@@ -299,6 +305,7 @@ PauliPlan *get_pauli_plan(Context *ctx, int n_hams, Ham *const *hams, int n_inst
     if (ctx->pauli_cache.size() >= 256) {
         if (ctx->device >= 0) (void)hipDeviceSynchronize();
         for (auto &kv : ctx->pauli_cache) {
+            dev_free(ctx, kv.second->geoms);
             dev_free(ctx, kv.second->groups);
             dev_free(ctx, kv.second->toff);
             dev_free(ctx, kv.second->terms);
@@ -417,11 +424,15 @@ PauliPlan *get_pauli_plan(Context *ctx, int n_hams, Ham *const *hams, int n_inst
         }
         if (n_hams == 1) break;
     }
+    std::vector<TileGeom> sgeoms;
+    for (const SweepPlan &sp : plan->sweeps) sgeoms.push_back(sp.geom);
     int r = upload(ctx, plan->groups, gdev.data(), gdev.size() * sizeof(GroupDev));
+    if (!r) r = upload(ctx, plan->geoms, sgeoms.data(), sgeoms.size() * sizeof(TileGeom));
     if (!r) r = upload(ctx, plan->toff, toff.data(), toff.size() * sizeof(int32_t));
     if (!r && !terms.empty()) r = upload(ctx, plan->terms, terms.data(), terms.size() * sizeof(TermDev));
     if (r) {
         dev_free(ctx, plan->groups);
+        dev_free(ctx, plan->geoms);
         dev_free(ctx, plan->toff);
         dev_free(ctx, plan->terms);
         *rc = r;

@@ -261,3 +261,26 @@ def test_errors_do_not_launch(vqe, ctx):
         vqe.energy_grad(ctx, C, H4, dev(np.zeros((1, 1))), ws=ws)  # workspace too small
     with pytest.raises(vqe.VQEError):
         vqe.energy(ctx, C, [H4, H4], dev(np.zeros((3, 1))))  # n_hams neither 1 nor B
+
+
+@pytest.mark.parametrize("n,T,L,iters", [(6, 40, 2, 25), (10, 300, 1, 6), (3, 20, 2, 30)])
+def test_persistent_loop_hamiltonian_forms(vqe, ctx, n, T, L, iters):
+    # random strings carry imaginary phases (odd Y count): complex table at n = 3, 6;
+    # at n = 10 the diagonal table does not fit LDS and the term form runs
+    _say("persistent forms", n, T, L, iters)
+    spec = synth.hea_circuit(n, L)
+    ham = synth.random_pauli_sum(n, min(T, 4 ** n - 1), seed=n)
+    C = vqe.Circuit.from_spec(ctx, spec)
+    H = vqe.Hamiltonian.from_sum(ctx, ham)
+    th0 = synth.uniform_thetas(spec.n_params, 3, seed=n)
+    out = {}
+    for mode in (0, 1):
+        ctx.set_loop_mode(mode)
+        th = dev(th0)
+        out[mode] = (vqe.run(ctx, C, H, th, iters).cpu().numpy(), th.cpu().numpy())
+    ctx.set_loop_mode(0)
+    for b in range(3):
+        want, tho = oracle.vqe_run(spec, ham, th0[b], iters)
+        for mode in (0, 1):
+            np.testing.assert_allclose(out[mode][0][b], want, atol=E_TOL)
+            np.testing.assert_allclose(out[mode][1][b], tho, atol=1e-7)
