@@ -115,6 +115,12 @@ int vqe_ctx_set_tile(vqe_ctx_t ctx, int k_fwd, int k_rev, int c_low);
  * step). */
 int vqe_ctx_set_loop_mode(vqe_ctx_t ctx, int mode);
 
+/* Kernel variant of the state passes: staged = 1 (default) applies the gates
+ * of a pass in register stages of four tile bits (tiles of 8 or more bits);
+ * staged = 0 applies one gate per LDS round trip.  Both compute the same
+ * result; the switch exists for measurement. */
+int vqe_ctx_set_staged(vqe_ctx_t ctx, int staged);
+
 /* Reserve `bytes` of context scratch now (used by vqe_expect and
  * vqe_apply_ansatz for per-launch tables), so later calls do not allocate. */
 int vqe_ctx_reserve(vqe_ctx_t ctx, size_t bytes);
@@ -250,15 +256,27 @@ int vqe_run(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams, i
  * natural alignment):
  *
  * vqe_circ_plan_export: int32 {n_passes, n_ops, geom_bytes (72), op_bytes
- *   (48)}, then per pass {geom, int32 op_begin, op_count, n_param_ops, 0},
- *   then n_ops op records.  geom = int32 {n, k, c, n - k}, uint8 tpos[16]
+ *   (48), n_stages, n_stage_ops, stage_bytes (32), stage_op_bytes (40)},
+ *   then per pass {geom, int32 op_begin, op_count, n_param_ops,
+ *   stage_begin, stage_count, 0, 0, 0}, then n_ops op records, n_stages
+ *   stage records and n_stage_ops stage-op records.  geom = int32 {n, k, c,
+ *   n - k}, uint8 tpos[16]
  *   (index bit of tile bit i), uint8 opos[40] (index bit of tile-number bit
  *   i).  op = uint32 m, uint32 fixed_bits, uint64 cmask_out, uint64
  *   cval_out, int32 gate, int32 pgate, int16 cls (0 general, 1 diagonal,
  *   2 swap), int16 gen (0 none, 1 X, 2 Y, 3 Z), int8 nfix, uint8
  *   fixpos[7]: the op updates the pairs p0 = (j with zero bits inserted at
  *   fixpos[0..nfix)) | fixed_bits, p1 = p0 ^ m, j < 2^(k - nfix), of the
- *   tiles whose base satisfies (base & cmask_out) == cval_out.
+ *   tiles whose base satisfies (base & cmask_out) == cval_out.  For tiles
+ *   of 8 or more bits the same ops are also grouped into register stages:
+ *   stage = uint8 rpos[4] (tile bits held in registers), uint8 cpos[12]
+ *   (the other tile bits, ascending), int32 op_begin, op_count,
+ *   n_param_ops, 0; stage op = uint64 cmo, cvo (controls outside the tile),
+ *   uint32 cmt, cvt (tile controls outside the registers), int32 gate,
+ *   pgate, uint8 M, lo, cmr, cvr (register flip mask, lower-element
+ *   pattern, register controls), uint8 swap, cls, gen, 0: register index i
+ *   pairs with i ^ M when (i & M) == lo and the controls hold; swap = 1
+ *   means the lower index holds the op's second element.
  *   reverse = 1 exports the adjoint sweep's schedule (gates in reverse).
  *
  * vqe_ham_plan_export (for_gradient = 0: the expectation schedule, 1: the

@@ -27,7 +27,7 @@ OPT_GD = 1
 
 EXPORTED = [
     "vqe_ctx_create", "vqe_ctx_destroy", "vqe_ctx_set_mem_budget", "vqe_ctx_set_tile",
-    "vqe_ctx_reserve", "vqe_ctx_set_loop_mode", "vqe_last_error", "vqe_strerror",
+    "vqe_ctx_reserve", "vqe_ctx_set_loop_mode", "vqe_ctx_set_staged", "vqe_last_error", "vqe_strerror",
     "vqe_ham_create", "vqe_ham_from_integrals", "vqe_ham_info", "vqe_ham_terms", "vqe_ham_destroy",
     "vqe_circ_create", "vqe_circ_destroy", "vqe_workspace_bytes",
     "vqe_prepare_reference", "vqe_apply_ansatz", "vqe_expect", "vqe_energy",
@@ -61,6 +61,7 @@ def _declare(L):
         "vqe_ctx_set_tile": [P, i32, i32, i32],
         "vqe_ctx_reserve": [P, sz],
         "vqe_ctx_set_loop_mode": [P, i32],
+        "vqe_ctx_set_staged": [P, i32],
         "vqe_ham_create": [P, i32, i64, P, P, P, PP],
         "vqe_ham_from_integrals": [P, i32, P, P, f64, PP],
         "vqe_ham_info": [P, P, P, P],

@@ -211,10 +211,16 @@ int forward(Context *ctx, Circ *C, int64_t B, const double *theta, double2 *psi,
     if (rc) return rc;
     for (size_t i = 0; i < fp->passes.size(); ++i) {
         const PassPlan &pp = fp->passes[i];
-        rc = hip_check(ctx, launch_forward_pass(pp, reinterpret_cast<const TileGeom *>(fp->geoms.p) + i,
-                                                reinterpret_cast<const OpDesc *>(fp->ops.p), mats, G, psi, B,
-                                                ctx->wg_max, s),
-                       "forward pass");
+        const TileGeom *gd = reinterpret_cast<const TileGeom *>(fp->geoms.p) + i;
+        if (pp.stage_count > 0 && !ctx->no_stages)
+            rc = hip_check(ctx, launch_forward_staged(pp, gd, reinterpret_cast<const StageDesc *>(fp->stages.p),
+                                                      reinterpret_cast<const StageOp *>(fp->sops.p), mats, G, psi,
+                                                      B, ctx->wg_max, s),
+                           "forward pass (staged)");
+        else
+            rc = hip_check(ctx, launch_forward_pass(pp, gd, reinterpret_cast<const OpDesc *>(fp->ops.p), mats, G,
+                                                    psi, B, ctx->wg_max, s),
+                           "forward pass");
         if (rc) return rc;
     }
     return VQE_OK;
@@ -273,7 +279,14 @@ int energy_grad_into(Context *ctx, Circ *C, int n_hams, Ham *const *H, int64_t B
     const int G = (int)C->gates.size();
     for (size_t i = 0; i < rp->passes.size(); ++i) {
         const PassPlan &p = rp->passes[i];
-        rc = hip_check(ctx, launch_reverse_pass(p, reinterpret_cast<const TileGeom *>(rp->geoms.p) + i,
+        const TileGeom *gd = reinterpret_cast<const TileGeom *>(rp->geoms.p) + i;
+        if (p.stage_count > 0 && !ctx->no_stages)
+            rc = hip_check(ctx, launch_reverse_staged(p, gd, reinterpret_cast<const StageDesc *>(rp->stages.p),
+                                                      reinterpret_cast<const StageOp *>(rp->sops.p), mats, G, psi,
+                                                      lam, B, L.W_rev, pg, C->n_pgates, s),
+                           "reverse pass (staged)");
+        else
+        rc = hip_check(ctx, launch_reverse_pass(p, gd,
                                                 reinterpret_cast<const OpDesc *>(rp->ops.p), mats, G, psi,
                                                 lam, B, L.W_rev, pg, C->n_pgates, s),
                        "reverse pass");
@@ -391,6 +404,14 @@ int vqe_ctx_set_loop_mode(vqe_ctx_t ctx, int mode)
     if (!ctx) return VQE_EINVAL;
     if (mode != 0 && mode != 1) return set_err(ctx, VQE_EINVAL, "loop mode must be 0 or 1");
     ctx->force_generic = mode;
+    return VQE_OK;
+}
+
+int vqe_ctx_set_staged(vqe_ctx_t ctx, int staged)
+{
+    if (!ctx) return VQE_EINVAL;
+    if (staged != 0 && staged != 1) return set_err(ctx, VQE_EINVAL, "staged must be 0 or 1");
+    ctx->no_stages = !staged;
     return VQE_OK;
 }
 
@@ -601,6 +622,8 @@ int vqe_circ_destroy(vqe_circ_t C)
         for (auto &kv : *cache) {
             dev_free(ctx, kv.second->ops);
             dev_free(ctx, kv.second->geoms);
+            dev_free(ctx, kv.second->stages);
+            dev_free(ctx, kv.second->sops);
         }
     dev_free(ctx, C->gates_dev);
     dev_free(ctx, C->pmap_off);
@@ -875,22 +898,28 @@ int vqe_circ_plan_export(vqe_ctx_t ctx, vqe_circ_t circ, int reverse, void *buf,
     if (!circ || !needed) return set_err(ctx, VQE_EINVAL, "bad argument");
     CircPlan *p = get_circ_plan(circ, reverse != 0, reverse ? ctx->k_rev : ctx->k_fwd, ctx->c_low, &rc);
     if (!p) return rc;
-    const size_t pass_bytes = sizeof(TileGeom) + 16;
-    const size_t need = 16 + p->passes.size() * pass_bytes + p->host_ops.size() * sizeof(OpDesc);
+    const size_t pass_bytes = sizeof(TileGeom) + 32;
+    const size_t need = 32 + p->passes.size() * pass_bytes + p->host_ops.size() * sizeof(OpDesc) +
+                        p->host_stages.size() * sizeof(StageDesc) + p->host_sops.size() * sizeof(StageOp);
     *needed = need;
     if (!buf || buf_bytes < need) return VQE_OK;
     unsigned char *o = (unsigned char *)buf;
-    int32_t hdr[4] = {(int32_t)p->passes.size(), (int32_t)p->host_ops.size(), (int32_t)sizeof(TileGeom),
-                      (int32_t)sizeof(OpDesc)};
-    std::memcpy(o, hdr, 16);
-    o += 16;
+    int32_t hdr[8] = {(int32_t)p->passes.size(), (int32_t)p->host_ops.size(), (int32_t)sizeof(TileGeom),
+                      (int32_t)sizeof(OpDesc), (int32_t)p->host_stages.size(), (int32_t)p->host_sops.size(),
+                      (int32_t)sizeof(StageDesc), (int32_t)sizeof(StageOp)};
+    std::memcpy(o, hdr, 32);
+    o += 32;
     for (const PassPlan &pp : p->passes) {
         std::memcpy(o, &pp.geom, sizeof(TileGeom));
-        int32_t meta[4] = {pp.op_begin, pp.op_count, pp.n_param_ops, 0};
-        std::memcpy(o + sizeof(TileGeom), meta, 16);
+        int32_t meta[8] = {pp.op_begin, pp.op_count, pp.n_param_ops, pp.stage_begin, pp.stage_count, 0, 0, 0};
+        std::memcpy(o + sizeof(TileGeom), meta, 32);
         o += pass_bytes;
     }
     std::memcpy(o, p->host_ops.data(), p->host_ops.size() * sizeof(OpDesc));
+    o += p->host_ops.size() * sizeof(OpDesc);
+    std::memcpy(o, p->host_stages.data(), p->host_stages.size() * sizeof(StageDesc));
+    o += p->host_stages.size() * sizeof(StageDesc);
+    std::memcpy(o, p->host_sops.data(), p->host_sops.size() * sizeof(StageOp));
     return VQE_OK;
 }
 

@@ -58,6 +58,35 @@ struct OpDesc {
 static_assert(sizeof(OpDesc) == 48, "OpDesc layout");
 static_assert(sizeof(TileGeom) == 72, "TileGeom layout");
 
+// Register stages of a pass (tiles with k >= kStageMinK).  A stage holds
+// four tile bits (rpos) in registers: each thread owns 2^4 amplitudes that
+// differ only in those bits and applies the stage's ops to them in
+// registers; the other k - 4 tile bits (cpos) number the sub-cubes.
+constexpr int kStageBits = 4;
+constexpr int kStageMinK = 8;
+
+struct StageDesc {
+    uint8_t rpos[4];     // tile-local positions of the register bits (ascending)
+    uint8_t cpos[12];    // tile-local positions of the sub-cube bits (ascending)
+    int32_t op_begin, op_count;
+    int32_t n_param_ops;
+    int32_t pad;
+};
+static_assert(sizeof(StageDesc) == 32, "StageDesc layout");
+
+// One op inside a stage.  Register index i (4 bits) pairs with i ^ M; the
+// pair is active when (i & M) == lo, (i & cmr) == cvr, the sub-cube base
+// satisfies (base_loc & cmt) == cvt and the tile base (base & cmo) == cvo.
+// swap = 1: the lower register index holds the op's second element.
+struct StageOp {
+    uint64_t cmo, cvo;
+    uint32_t cmt, cvt;
+    int32_t gate, pgate;
+    uint8_t M, lo, cmr, cvr;
+    uint8_t swap, cls, gen, pad;
+};
+static_assert(sizeof(StageOp) == 40, "StageOp layout");
+
 // Per-gate data for the matrix preparation kernel.
 struct GateDev {
     int32_t kind;
@@ -121,6 +150,7 @@ struct PassPlan {
     TileGeom geom;
     int op_begin = 0, op_count = 0;
     int n_param_ops = 0;     // parametric ops in this pass (reverse plans)
+    int stage_begin = 0, stage_count = 0;  // register stages (k >= kStageMinK)
 };
 
 struct CircPlan {
@@ -129,7 +159,10 @@ struct CircPlan {
     std::vector<PassPlan> passes;
     DevMem ops;              // OpDesc[]
     DevMem geoms;            // TileGeom[passes] (read through a pointer by the kernels)
+    DevMem stages, sops;     // StageDesc[], StageOp[]
     std::vector<OpDesc> host_ops;
+    std::vector<StageDesc> host_stages;
+    std::vector<StageOp> host_sops;
     int max_param_ops = 0;
 };
 
@@ -173,6 +206,7 @@ struct Context {
     int k_fwd = 12, k_rev = 11, c_low = 4;
     int wg_max = 1024;          // workgroups per instance in tile passes
     int force_generic = 0;      // route vqe_run through the per-step launches
+    int no_stages = 0;          // use the one-op-per-LDS-round-trip pass kernels only
     std::string err;
     DevMem scratch;
     std::map<std::string, std::unique_ptr<PauliPlan>> pauli_cache;
@@ -212,6 +246,13 @@ hipError_t launch_gate_mats(const GateDev *gates, int n_gates, const double *the
 hipError_t launch_forward_pass(const PassPlan &pp, const TileGeom *geom_dev, const OpDesc *ops,
                                const double2 *mats, int n_gates, double2 *psi, int64_t batch,
                                int wg_max, hipStream_t s);
+hipError_t launch_forward_staged(const PassPlan &pp, const TileGeom *geom_dev,
+                                 const StageDesc *stages, const StageOp *sops, const double2 *mats,
+                                 int n_gates, double2 *psi, int64_t batch, int wg_max, hipStream_t s);
+hipError_t launch_reverse_staged(const PassPlan &pp, const TileGeom *geom_dev,
+                                 const StageDesc *stages, const StageOp *sops, const double2 *mats,
+                                 int n_gates, double2 *psi, double2 *lam, int64_t batch,
+                                 int wg_per_inst, double *partials, int n_pgates, hipStream_t s);
 hipError_t launch_reverse_pass(const PassPlan &pp, const TileGeom *geom_dev, const OpDesc *ops,
                                const double2 *mats,
                                int n_gates, double2 *psi, double2 *lam, int64_t batch,

@@ -293,6 +293,303 @@ __global__ __launch_bounds__(kThreads) void k_reverse_pass(
 }
 
 // ---------------------------------------------------------------------------
+// Register-staged passes (tiles with k >= 8).  The tile sits in LDS under an
+// XOR swizzle (bits 4..7 folded into bits 0..3) so that sub-cubes strided in
+// any four bits spread over all banks.  Per stage each thread loads its
+// 16-amplitude sub-cube into registers, applies the stage's ops there (the
+// pair partner i ^ M is resolved at compile time for every mask M), and
+// stores the sub-cube back: one LDS round trip per stage instead of per op.
+__device__ __forceinline__ uint32_t swz(uint32_t i) { return i ^ ((i >> 4) & 15u); }
+
+struct Mat2 {
+    double2 a, b, c, d;  // [[a, b], [c, d]] acting on (lower, upper) register index
+};
+
+__device__ __forceinline__ Mat2 stage_matrix(const double2 *__restrict__ M, int gate, int swap)
+{
+    const double2 u00 = M[gate * 4 + 0], u01 = M[gate * 4 + 1], u10 = M[gate * 4 + 2], u11 = M[gate * 4 + 3];
+    Mat2 v;
+    if (swap) {
+        v.a = u11; v.b = u10; v.c = u01; v.d = u00;
+    } else {
+        v.a = u00; v.b = u01; v.c = u10; v.d = u11;
+    }
+    return v;
+}
+
+__device__ __forceinline__ Mat2 dagger(const Mat2 &v)
+{
+    Mat2 w;
+    w.a = cconj(v.a);
+    w.b = cconj(v.c);
+    w.c = cconj(v.b);
+    w.d = cconj(v.d);
+    return w;
+}
+
+template <int M>
+__device__ __forceinline__ void stage_fwd(double2 (&x)[16], const Mat2 &v, int cls, int lo, int cmr, int cvr,
+                                          bool tpred)
+{
+    constexpr int HB = M >= 8 ? 8 : (M >= 4 ? 4 : (M >= 2 ? 2 : 1));
+    if (cls == CLS_SWAP) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            if (i & HB) continue;
+            if (((i & M) == lo) && ((i & cmr) == cvr) && tpred) {
+                const double2 t = x[i];
+                x[i] = x[i ^ M];
+                x[i ^ M] = t;
+            }
+        }
+    } else if (cls == CLS_DIAG) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            if (i & HB) continue;
+            if (((i & M) == lo) && ((i & cmr) == cvr) && tpred) {
+                x[i] = cmul(v.a, x[i]);
+                x[i ^ M] = cmul(v.d, x[i ^ M]);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            if (i & HB) continue;
+            if (((i & M) == lo) && ((i & cmr) == cvr) && tpred) {
+                const double2 p = x[i], q = x[i ^ M];
+                x[i] = cadd(cmul(v.a, p), cmul(v.b, q));
+                x[i ^ M] = cadd(cmul(v.c, p), cmul(v.d, q));
+            }
+        }
+    }
+}
+
+// reverse: gradient term over the pair (in (lower, upper) orientation; sgn
+// restores the op's (first, second) orientation for the antisymmetric
+// generators), then U^dagger on both states
+template <int M>
+__device__ __forceinline__ double stage_rev(double2 (&x)[16], double2 (&l)[16], const Mat2 &w, int cls, int gen,
+                                            int lo, int cmr, int cvr, bool tpred, double sgn)
+{
+    constexpr int HB = M >= 8 ? 8 : (M >= 4 ? 4 : (M >= 2 ? 2 : 1));
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        if (i & HB) continue;
+        if (((i & M) == lo) && ((i & cmr) == cvr) && tpred) {
+            const double2 a = x[i], b = x[i ^ M], la = l[i], lb = l[i ^ M];
+            if (gen == GEN_Y)
+                acc += sgn * (-(la.x * b.x + la.y * b.y) + (lb.x * a.x + lb.y * a.y));
+            else if (gen == GEN_X)
+                acc += (la.x * b.y - la.y * b.x) + (lb.x * a.y - lb.y * a.x);
+            else if (gen == GEN_Z)
+                acc += sgn * ((la.x * a.y - la.y * a.x) - (lb.x * b.y - lb.y * b.x));
+            if (cls == CLS_SWAP) {
+                x[i] = b;
+                x[i ^ M] = a;
+                l[i] = lb;
+                l[i ^ M] = la;
+            } else if (cls == CLS_DIAG) {
+                x[i] = cmul(w.a, a);
+                x[i ^ M] = cmul(w.d, b);
+                l[i] = cmul(w.a, la);
+                l[i ^ M] = cmul(w.d, lb);
+            } else {
+                x[i] = cadd(cmul(w.a, a), cmul(w.b, b));
+                x[i ^ M] = cadd(cmul(w.c, a), cmul(w.d, b));
+                l[i] = cadd(cmul(w.a, la), cmul(w.b, lb));
+                l[i ^ M] = cadd(cmul(w.c, la), cmul(w.d, lb));
+            }
+        }
+    }
+    return acc;
+}
+
+#define VQE_MASK_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15)
+
+__device__ __forceinline__ void dispatch_fwd(int M, double2 (&x)[16], const Mat2 &v, int cls, int lo, int cmr,
+                                             int cvr, bool tpred)
+{
+    switch (M) {
+#define VQE_CASE(m) case m: stage_fwd<m>(x, v, cls, lo, cmr, cvr, tpred); break;
+        VQE_MASK_CASES(VQE_CASE)
+#undef VQE_CASE
+    default: break;
+    }
+}
+
+__device__ __forceinline__ double dispatch_rev(int M, double2 (&x)[16], double2 (&l)[16], const Mat2 &w, int cls,
+                                               int gen, int lo, int cmr, int cvr, bool tpred, double sgn)
+{
+    switch (M) {
+#define VQE_CASE(m) case m: return stage_rev<m>(x, l, w, cls, gen, lo, cmr, cvr, tpred, sgn);
+        VQE_MASK_CASES(VQE_CASE)
+#undef VQE_CASE
+    default: return 0.0;
+    }
+}
+
+__device__ __forceinline__ void stage_offsets(const StageDesc *__restrict__ sd, uint32_t (&roff)[16])
+{
+    const uint32_t r0 = 1u << sd->rpos[0], r1 = 1u << sd->rpos[1], r2 = 1u << sd->rpos[2], r3 = 1u << sd->rpos[3];
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+        roff[i] = ((i & 1) ? r0 : 0u) | ((i & 2) ? r1 : 0u) | ((i & 4) ? r2 : 0u) | ((i & 8) ? r3 : 0u);
+}
+
+__device__ __forceinline__ uint32_t subcube_base(const StageDesc *__restrict__ sd, int nc, uint32_t u)
+{
+    uint32_t b = 0;
+    for (int i = 0; i < nc; ++i)
+        if ((u >> i) & 1u) b |= 1u << sd->cpos[i];
+    return b;
+}
+
+__global__ __launch_bounds__(kThreads) void k_forward_staged(
+    const TileGeom *__restrict__ gp, int n, int k, int c, int nout, const StageDesc *__restrict__ stages,
+    int nstages, const StageOp *__restrict__ sops, const double2 *__restrict__ mats, int n_gates,
+    double2 *__restrict__ psi, int64_t tiles)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    double2 *tile = reinterpret_cast<double2 *>(smem);
+    uint64_t *hoff = reinterpret_cast<uint64_t *>(smem + (16u << k));
+    const int tid = threadIdx.x;
+    const uint64_t dim = 1ull << n;
+    double2 *st = psi + (uint64_t)blockIdx.y * dim;
+    const double2 *Mx = mats + (size_t)blockIdx.y * n_gates * 4;
+    const int T = 1 << k;
+    const int nsub = 1 << (k - kStageBits);
+    const uint32_t lowm = (1u << c) - 1u;
+    fill_hoff(gp, k, c, hoff);
+    __syncthreads();
+    for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+        const uint64_t base = tile_base(gp, nout, t);
+        for (int j = tid; j < T; j += kThreads) tile[swz(j)] = st[base + hoff[j >> c] + (j & lowm)];
+        __syncthreads();
+        for (int s = 0; s < nstages; ++s) {
+            const StageDesc *sd = stages + s;
+            uint32_t roff[16];
+            stage_offsets(sd, roff);
+            const int ob = sd->op_begin, oc = sd->op_count;
+            for (int u = tid; u < nsub; u += kThreads) {
+                const uint32_t bl = subcube_base(sd, k - kStageBits, (uint32_t)u);
+                double2 x[16];
+#pragma unroll
+                for (int i = 0; i < 16; ++i) x[i] = tile[swz(bl | roff[i])];
+                for (int q = ob; q < ob + oc; ++q) {
+                    const StageOp o = sops[q];
+                    if ((base & o.cmo) != o.cvo) continue;
+                    const Mat2 v = stage_matrix(Mx, o.gate, o.swap);
+                    dispatch_fwd(o.M, x, v, o.cls, o.lo, o.cmr, o.cvr, (bl & o.cmt) == o.cvt);
+                }
+#pragma unroll
+                for (int i = 0; i < 16; ++i) tile[swz(bl | roff[i])] = x[i];
+            }
+            __syncthreads();
+        }
+        for (int j = tid; j < T; j += kThreads) st[base + hoff[j >> c] + (j & lowm)] = tile[swz(j)];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_reverse_staged(
+    const TileGeom *__restrict__ gp, int n, int k, int c, int nout, const StageDesc *__restrict__ stages,
+    int nstages, const StageOp *__restrict__ sops, int n_param_ops, const double2 *__restrict__ mats,
+    int n_gates, double2 *__restrict__ psi, double2 *__restrict__ lam, int64_t tiles,
+    double *__restrict__ partials, int n_pgates)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    double2 *tp = reinterpret_cast<double2 *>(smem);
+    double2 *tl = tp + (1u << k);
+    uint64_t *hoff = reinterpret_cast<uint64_t *>(smem + (32u << k));
+    double *red = reinterpret_cast<double *>(hoff + (1u << (k - c)));
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint64_t dim = 1ull << n;
+    double2 *sp = psi + (uint64_t)blockIdx.y * dim;
+    double2 *sl = lam + (uint64_t)blockIdx.y * dim;
+    const double2 *Mx = mats + (size_t)blockIdx.y * n_gates * 4;
+    const int T = 1 << k;
+    const int nsub = 1 << (k - kStageBits);
+    const uint32_t lowm = (1u << c) - 1u;
+    fill_hoff(gp, k, c, hoff);
+    for (int i = tid; i < n_param_ops * 4; i += kThreads) red[i] = 0.0;
+    __syncthreads();
+    for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+        const uint64_t base = tile_base(gp, nout, t);
+        for (int j = tid; j < T; j += kThreads) {
+            const uint64_t gi = base + hoff[j >> c] + (j & lowm);
+            tp[swz(j)] = sp[gi];
+            tl[swz(j)] = sl[gi];
+        }
+        __syncthreads();
+        int slot0 = 0;
+        for (int s = 0; s < nstages; ++s) {
+            const StageDesc *sd = stages + s;
+            uint32_t roff[16];
+            stage_offsets(sd, roff);
+            const int ob = sd->op_begin, oc = sd->op_count;
+            // every thread walks the ops (a thread with no sub-cube contributes 0)
+            for (int u0 = 0; u0 < nsub; u0 += kThreads) {
+                const int u = u0 + tid;
+                const bool have = u < nsub;
+                const uint32_t bl = have ? subcube_base(sd, k - kStageBits, (uint32_t)u) : 0u;
+                double2 x[16], l[16];
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    x[i] = have ? tp[swz(bl | roff[i])] : make_double2(0.0, 0.0);
+                    l[i] = have ? tl[swz(bl | roff[i])] : make_double2(0.0, 0.0);
+                }
+                int slot = slot0;
+                for (int q = ob; q < ob + oc; ++q) {
+                    const StageOp o = sops[q];
+                    const int my_slot = slot;
+                    if (o.pgate >= 0) ++slot;
+                    if ((base & o.cmo) != o.cvo) continue;
+                    const Mat2 w = dagger(stage_matrix(Mx, o.gate, o.swap));
+                    const double sgn = o.swap ? -1.0 : 1.0;
+                    const int gen = o.pgate >= 0 ? o.gen : GEN_NONE;
+                    double acc = dispatch_rev(o.M, x, l, w, o.cls, gen, o.lo, o.cmr, o.cvr,
+                                              have && ((bl & o.cmt) == o.cvt), sgn);
+                    if (o.pgate >= 0) {
+                        acc = wave_sum(acc);
+                        if (lane == 0) red[my_slot * 4 + wave] += acc;
+                    }
+                }
+                if (have) {
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) {
+                        tp[swz(bl | roff[i])] = x[i];
+                        tl[swz(bl | roff[i])] = l[i];
+                    }
+                }
+            }
+            slot0 += sd->n_param_ops;
+            __syncthreads();
+        }
+        for (int j = tid; j < T; j += kThreads) {
+            const uint64_t gi = base + hoff[j >> c] + (j & lowm);
+            sp[gi] = tp[swz(j)];
+            sl[gi] = tl[swz(j)];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const int W = gridDim.x;
+        int slot = 0;
+        for (int s = 0; s < nstages; ++s) {
+            const StageDesc *sd = stages + s;
+            for (int q = sd->op_begin; q < sd->op_begin + sd->op_count; ++q) {
+                const int pg = sops[q].pgate;
+                if (pg < 0) continue;
+                const double v = red[slot * 4 + 0] + red[slot * 4 + 1] + red[slot * 4 + 2] + red[slot * 4 + 3];
+                partials[((size_t)blockIdx.y * n_pgates + pg) * W + blockIdx.x] = v;
+                ++slot;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Pauli sweep over the groups of one sweep.
 //
 // Expectation (lam == nullptr), paired over (b, b ^ f) with b's pivot bit 0,
@@ -539,6 +836,37 @@ hipError_t launch_reverse_pass(const PassPlan &pp, const TileGeom *geom_dev, con
     hipLaunchKernelGGL(k_reverse_pass, dim3(wg_per_inst, (unsigned)batch), dim3(kThreads), lds, s, geom_dev,
                        g.n, g.k, g.c, g.nout, ops + pp.op_begin, pp.op_count, pp.n_param_ops, mats, n_gates,
                        psi, lam, tiles, partials, n_pgates);
+    return hipGetLastError();
+}
+
+hipError_t launch_forward_staged(const PassPlan &pp, const TileGeom *geom_dev,
+                                 const StageDesc *stages, const StageOp *sops, const double2 *mats,
+                                 int n_gates, double2 *psi, int64_t batch, int wg_max, hipStream_t s)
+{
+    const TileGeom &g = pp.geom;
+    const int64_t tiles = 1ll << g.nout;
+    const int W = (int)std::min<int64_t>(tiles, wg_max);
+    const size_t lds = fwd_lds(g);
+    hipError_t e = ensure_lds(k_forward_staged, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_forward_staged, dim3(W, (unsigned)batch), dim3(kThreads), lds, s, geom_dev, g.n, g.k,
+                       g.c, g.nout, stages + pp.stage_begin, pp.stage_count, sops, mats, n_gates, psi, tiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_reverse_staged(const PassPlan &pp, const TileGeom *geom_dev,
+                                 const StageDesc *stages, const StageOp *sops, const double2 *mats,
+                                 int n_gates, double2 *psi, double2 *lam, int64_t batch,
+                                 int wg_per_inst, double *partials, int n_pgates, hipStream_t s)
+{
+    const TileGeom &g = pp.geom;
+    const int64_t tiles = 1ll << g.nout;
+    const size_t lds = rev_lds(g, pp.n_param_ops);
+    hipError_t e = ensure_lds(k_reverse_staged, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reverse_staged, dim3(wg_per_inst, (unsigned)batch), dim3(kThreads), lds, s, geom_dev,
+                       g.n, g.k, g.c, g.nout, stages + pp.stage_begin, pp.stage_count, sops, pp.n_param_ops,
+                       mats, n_gates, psi, lam, tiles, partials, n_pgates);
     return hipGetLastError();
 }
 

@@ -176,7 +176,96 @@ static void free_plan(Context *ctx, CircPlan *p)
     if (p) {
         dev_free(ctx, p->ops);
         dev_free(ctx, p->geoms);
+        dev_free(ctx, p->stages);
+        dev_free(ctx, p->sops);
     }
+}
+
+// Split a pass's ops (tile-local, in order) into register stages of
+// kStageBits bits.  An op needs its flip bits in registers; its controls may
+// be anywhere (register, other tile bits or outside the tile).  An op may
+// move ahead of skipped ops only if it shares no tile bit with them.
+static void build_stages(const Circ *C, const std::vector<int> &take, const std::vector<int> &tile,
+                         int keff, CircPlan *plan, PassPlan &pp)
+{
+    const uint64_t tmask = mask_of(tile);
+    struct Loc {
+        uint32_t m, first, cin, cvin;
+    };
+    std::vector<Loc> loc(take.size());
+    for (size_t q = 0; q < take.size(); ++q) {
+        const GateHost &h = C->gates[take[q]];
+        loc[q].m = compress(h.m, tile);
+        loc[q].first = compress(h.first, tile);
+        loc[q].cin = compress(h.cmask & tmask, tile);
+        loc[q].cvin = compress(h.cval & tmask, tile);
+    }
+    std::vector<char> done(take.size(), 0);
+    size_t remaining = take.size();
+    pp.stage_begin = (int)plan->host_stages.size();
+    while (remaining > 0) {
+        uint32_t R = 0, blocked = 0;
+        std::vector<size_t> st;
+        for (size_t q = 0; q < take.size(); ++q) {
+            if (done[q]) continue;
+            const uint32_t touched = loc[q].m | loc[q].cin;
+            if (touched & blocked) {
+                blocked |= touched;
+                continue;
+            }
+            const uint32_t need = loc[q].m & ~R;
+            if (popc(R) + popc(need) <= kStageBits) {
+                R |= need;
+                st.push_back(q);
+            } else {
+                blocked |= touched;
+            }
+        }
+        // pad the register set to exactly kStageBits bits
+        for (int b = 0; b < keff && popc(R) < kStageBits; ++b) R |= 1u << b;
+        std::vector<int> rbits, cbits;
+        for (int b = 0; b < keff; ++b) ((R >> b) & 1 ? rbits : cbits).push_back(b);
+        StageDesc sd;
+        std::memset(&sd, 0, sizeof(sd));
+        for (int i = 0; i < kStageBits; ++i) sd.rpos[i] = (uint8_t)rbits[i];
+        for (size_t i = 0; i < cbits.size(); ++i) sd.cpos[i] = (uint8_t)cbits[i];
+        sd.op_begin = (int)plan->host_sops.size();
+        sd.op_count = (int)st.size();
+        int nparam = 0;
+        for (size_t q : st) {
+            const GateHost &h = C->gates[take[q]];
+            StageOp so;
+            std::memset(&so, 0, sizeof(so));
+            so.M = (uint8_t)compress(loc[q].m, rbits);
+            const uint32_t q0 = compress(loc[q].first, rbits);
+            const uint32_t hb = 1u << (31 - __builtin_clz((uint32_t)so.M));
+            if (q0 & hb) {
+                so.lo = (uint8_t)(q0 ^ so.M);
+                so.swap = 1;
+            } else {
+                so.lo = (uint8_t)q0;
+                so.swap = 0;
+            }
+            const uint32_t cin_r = loc[q].cin & R, cin_t = loc[q].cin & ~R;
+            so.cmr = (uint8_t)compress(cin_r, rbits);
+            so.cvr = (uint8_t)compress(loc[q].cvin & R, rbits);
+            so.cmt = cin_t;
+            so.cvt = loc[q].cvin & ~R;
+            so.cmo = h.cmask & ~tmask;
+            so.cvo = h.cval & ~tmask;
+            so.gate = take[q];
+            so.pgate = C->pgate_of_gate[take[q]];
+            so.cls = (uint8_t)h.cls;
+            so.gen = (uint8_t)h.gen;
+            if (so.pgate >= 0) ++nparam;
+            plan->host_sops.push_back(so);
+            done[q] = 1;
+            --remaining;
+        }
+        sd.n_param_ops = nparam;
+        plan->host_stages.push_back(sd);
+    }
+    pp.stage_count = (int)plan->host_stages.size() - pp.stage_begin;
 }
 
 CircPlan *get_circ_plan(Circ *C, bool reverse, int k, int c, int *rc)
@@ -264,6 +353,7 @@ CircPlan *get_circ_plan(Circ *C, bool reverse, int k, int c, int *rc)
             done[g] = 1;
             --remaining;
         }
+        if (keff >= kStageMinK) build_stages(C, take, tile, keff, plan.get(), pp);
         plan->passes.push_back(pp);
     }
     if (!ops.empty()) {
@@ -271,6 +361,10 @@ CircPlan *get_circ_plan(Circ *C, bool reverse, int k, int c, int *rc)
         std::vector<TileGeom> geoms;
         for (const PassPlan &pp : plan->passes) geoms.push_back(pp.geom);
         if (!r) r = upload(C->ctx, plan->geoms, geoms.data(), geoms.size() * sizeof(TileGeom));
+        if (!r && !plan->host_stages.empty())
+            r = upload(C->ctx, plan->stages, plan->host_stages.data(), plan->host_stages.size() * sizeof(StageDesc));
+        if (!r && !plan->host_sops.empty())
+            r = upload(C->ctx, plan->sops, plan->host_sops.data(), plan->host_sops.size() * sizeof(StageOp));
         if (r) {
             free_plan(C->ctx, plan.get());
             *rc = r;

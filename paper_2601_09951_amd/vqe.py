@@ -66,6 +66,10 @@ class Context:
         """0: persistent single-launch loop when the state fits on chip; 1: per-step launches."""
         self.check(lib().vqe_ctx_set_loop_mode(self._h, int(mode)))
 
+    def set_staged(self, staged: bool):
+        """Register-staged state passes (default) or one LDS round trip per gate."""
+        self.check(lib().vqe_ctx_set_staged(self._h, int(bool(staged))))
+
     def reserve(self, nbytes: int):
         self.check(lib().vqe_ctx_reserve(self._h, int(nbytes)))
 
@@ -347,7 +351,12 @@ class VQEEnergy(torch.autograd.Function):
 _GEOM = np.dtype([("n", "<i4"), ("k", "<i4"), ("c", "<i4"), ("nout", "<i4"), ("tpos", "u1", 16),
                   ("opos", "u1", 40)])
 _PASS = np.dtype([("geom", _GEOM), ("op_begin", "<i4"), ("op_count", "<i4"), ("n_param_ops", "<i4"),
-                  ("pad", "<i4")])
+                  ("stage_begin", "<i4"), ("stage_count", "<i4"), ("pad", "<i4", 3)])
+_STAGE = np.dtype([("rpos", "u1", 4), ("cpos", "u1", 12), ("op_begin", "<i4"), ("op_count", "<i4"),
+                   ("n_param_ops", "<i4"), ("pad", "<i4")])
+_SOP = np.dtype([("cmo", "<u8"), ("cvo", "<u8"), ("cmt", "<u4"), ("cvt", "<u4"), ("gate", "<i4"),
+                 ("pgate", "<i4"), ("M", "u1"), ("lo", "u1"), ("cmr", "u1"), ("cvr", "u1"), ("swap", "u1"),
+                 ("cls", "u1"), ("gen", "u1"), ("pad", "u1")])
 _OP = np.dtype([("m", "<u4"), ("fixed_bits", "<u4"), ("cmask_out", "<u8"), ("cval_out", "<u8"),
                 ("gate", "<i4"), ("pgate", "<i4"), ("cls", "<i2"), ("gen", "<i2"), ("nfix", "i1"),
                 ("fixpos", "u1", 7), ("pad", "<u4")])
@@ -356,20 +365,28 @@ _GROUP = np.dtype([("floc", "<u4"), ("pivot", "<u4"), ("ugroup", "<i4"), ("pad",
 _TERM = np.dtype([("z", "<u8"), ("zloc", "<u4"), ("pad", "<u4"), ("w", "<f8")])
 
 
-def circuit_plan(ctx: Context, circ: Circuit, reverse: bool = False):
-    """(passes, ops) structured arrays of the compiled pass schedule."""
+def circuit_plan(ctx: Context, circ: Circuit, reverse: bool = False, stages: bool = False):
+    """(passes, ops) structured arrays of the compiled pass schedule
+    (plus (stages, stage_ops) when stages=True)."""
     need = ctypes.c_size_t()
     ctx.check(lib().vqe_circ_plan_export(ctx.handle, circ.handle, int(reverse), None, 0, ctypes.byref(need)))
     buf = np.zeros(need.value, dtype=np.uint8)
     ctx.check(lib().vqe_circ_plan_export(ctx.handle, circ.handle, int(reverse), _hp(buf), buf.size,
                                          ctypes.byref(need)))
-    hdr = buf[:16].view("<i4")
-    npass, nops = int(hdr[0]), int(hdr[1])
+    hdr = buf[:32].view("<i4")
+    npass, nops, nst, nsop = int(hdr[0]), int(hdr[1]), int(hdr[4]), int(hdr[5])
     assert hdr[2] == _GEOM.itemsize and hdr[3] == _OP.itemsize
-    off = 16
+    assert hdr[6] == _STAGE.itemsize and hdr[7] == _SOP.itemsize
+    off = 32
     passes = buf[off:off + npass * _PASS.itemsize].view(_PASS)
     off += npass * _PASS.itemsize
     ops = buf[off:off + nops * _OP.itemsize].view(_OP)
+    off += nops * _OP.itemsize
+    st = buf[off:off + nst * _STAGE.itemsize].view(_STAGE)
+    off += nst * _STAGE.itemsize
+    sops = buf[off:off + nsop * _SOP.itemsize].view(_SOP)
+    if stages:
+        return passes, ops, st, sops
     return passes, ops
 
 

@@ -220,3 +220,110 @@ def sweeps(plan, psi, inst=0, hpsi=False):
     if hpsi:
         return lam, float(np.vdot(psi, lam).real)
     return E
+
+
+# ---------------------------------------------------------------------------
+# register stages
+# ---------------------------------------------------------------------------
+def _stage_index(st, k):
+    rpos = [int(v) for v in st["rpos"]]
+    cpos = [int(v) for v in st["cpos"][:k - 4]]
+    assert len(set(rpos + cpos)) == k and max(rpos + cpos) < k
+    roff = np.array([sum(((i >> b) & 1) << rpos[b] for b in range(4)) for i in range(16)], dtype=np.int64)
+    u = np.arange(1 << (k - 4), dtype=np.int64)
+    bl = np.zeros_like(u)
+    for i, p in enumerate(cpos):
+        bl |= ((u >> i) & 1) << p
+    idx = bl[:, None] | roff[None, :]
+    assert idx.max() < (1 << k) and np.unique(idx).size == idx.size == (1 << k), "sub-cubes must partition the tile"
+    return bl, idx
+
+
+def _stage_pairs(op):
+    M, lo, cmr, cvr = int(op["M"]), int(op["lo"]), int(op["cmr"]), int(op["cvr"])
+    assert 1 <= M <= 15
+    hb = 1 << (M.bit_length() - 1)
+    return [(i, i ^ M) for i in range(16) if not (i & hb) and (i & M) == lo and (i & cmr) == cvr]
+
+
+def _stage_matrix(U, swap):
+    return np.array([[U[1, 1], U[1, 0]], [U[0, 1], U[0, 0]]]) if swap else U
+
+
+def forward_staged(passes, stages, sops, psi, mats):
+    psi = psi.copy()
+    for ps in passes:
+        g = ps["geom"]
+        k = int(g["k"])
+        assert int(ps["stage_count"]) > 0
+        idx, base = _tile_index(g)
+        T = psi[idx]
+        for st in stages[int(ps["stage_begin"]):int(ps["stage_begin"]) + int(ps["stage_count"])]:
+            bl, sidx = _stage_index(st, k)
+            for op in sops[int(st["op_begin"]):int(st["op_begin"]) + int(st["op_count"])]:
+                act = (base & np.uint64(int(op["cmo"]))) == np.uint64(int(op["cvo"]))
+                tpred = (bl & int(op["cmt"])) == int(op["cvt"])
+                V = _stage_matrix(mats[int(op["gate"])], int(op["swap"]))
+                sel = np.ix_(act, tpred)
+                for i, j in _stage_pairs(op):
+                    a = T[:, sidx[:, i]][sel]
+                    b = T[:, sidx[:, j]][sel]
+                    cls = int(op["cls"])
+                    if cls == CLS_SWAP:
+                        na, nb = b, a
+                    elif cls == CLS_DIAG:
+                        na, nb = V[0, 0] * a, V[1, 1] * b
+                    else:
+                        na, nb = V[0, 0] * a + V[0, 1] * b, V[1, 0] * a + V[1, 1] * b
+                    Ti = T[:, sidx[:, i]]
+                    Tj = T[:, sidx[:, j]]
+                    Ti[sel] = na
+                    Tj[sel] = nb
+                    T[:, sidx[:, i]] = Ti
+                    T[:, sidx[:, j]] = Tj
+        psi[idx] = T
+    return psi
+
+
+def reverse_staged(passes, stages, sops, psi, lam, mats, n_pgates):
+    psi, lam = psi.copy(), lam.copy()
+    gpart = np.zeros(n_pgates)
+    for ps in passes:
+        g = ps["geom"]
+        k = int(g["k"])
+        idx, base = _tile_index(g)
+        TP, TL = psi[idx], lam[idx]
+        for st in stages[int(ps["stage_begin"]):int(ps["stage_begin"]) + int(ps["stage_count"])]:
+            bl, sidx = _stage_index(st, k)
+            for op in sops[int(st["op_begin"]):int(st["op_begin"]) + int(st["op_count"])]:
+                act = (base & np.uint64(int(op["cmo"]))) == np.uint64(int(op["cvo"]))
+                tpred = (bl & int(op["cmt"])) == int(op["cvt"])
+                W = _stage_matrix(mats[int(op["gate"])], int(op["swap"])).conj().T
+                sgn = -1.0 if int(op["swap"]) else 1.0
+                sel = np.ix_(act, tpred)
+                for i, j in _stage_pairs(op):
+                    a, b = TP[:, sidx[:, i]][sel], TP[:, sidx[:, j]][sel]
+                    la, lb = TL[:, sidx[:, i]][sel], TL[:, sidx[:, j]][sel]
+                    if int(op["pgate"]) >= 0:
+                        gen = int(op["gen"])
+                        if gen == GEN_Y:
+                            v = sgn * (-(la.conj() * b).real + (lb.conj() * a).real)
+                        elif gen == GEN_X:
+                            v = (la.conj() * b).imag + (lb.conj() * a).imag
+                        else:
+                            v = sgn * ((la.conj() * a).imag - (lb.conj() * b).imag)
+                        gpart[int(op["pgate"])] += v.sum()
+                    cls = int(op["cls"])
+                    if cls == CLS_SWAP:
+                        res = (b, a, lb, la)
+                    elif cls == CLS_DIAG:
+                        res = (W[0, 0] * a, W[1, 1] * b, W[0, 0] * la, W[1, 1] * lb)
+                    else:
+                        res = (W[0, 0] * a + W[0, 1] * b, W[1, 0] * a + W[1, 1] * b,
+                               W[0, 0] * la + W[0, 1] * lb, W[1, 0] * la + W[1, 1] * lb)
+                    for arr, col, val in ((TP, i, res[0]), (TP, j, res[1]), (TL, i, res[2]), (TL, j, res[3])):
+                        cur = arr[:, sidx[:, col]]
+                        cur[sel] = val
+                        arr[:, sidx[:, col]] = cur
+        psi[idx], lam[idx] = TP, TL
+    return psi, lam, gpart

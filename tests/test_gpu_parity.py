@@ -132,10 +132,12 @@ def test_energy_grad_random_circuits(vqe, ctx, geom, n, seed):
         np.testing.assert_allclose(g[b], go, atol=G_TOL)
 
 
-@pytest.mark.parametrize("n,k,c", [(14, 8, 3), (16, 12, 4), (17, 11, 4)])
-def test_hea_energy_grad_multi_tile(vqe, ctx, n, k, c):
-    _say("hea", n, k, c)
+@pytest.mark.parametrize("staged", [1, 0])
+@pytest.mark.parametrize("n,k,c", [(14, 8, 3), (16, 12, 4), (17, 11, 4), (15, 13, 5)])
+def test_hea_energy_grad_multi_tile(vqe, ctx, n, k, c, staged):
+    _say("hea", n, k, c, "staged", staged)
     ctx.set_tile(k, min(k, 12), c)
+    ctx.set_staged(staged)
     spec = synth.hea_circuit(n, 2)
     ham = synth.random_pauli_sum(n, 100, seed=n)
     th = synth.uniform_thetas(spec.n_params, 1, seed=n)
@@ -143,6 +145,7 @@ def test_hea_energy_grad_multi_tile(vqe, ctx, n, k, c):
     H = vqe.Hamiltonian.from_sum(ctx, ham)
     e, g = vqe.energy_grad(ctx, C, H, dev(th))
     torch.cuda.synchronize()
+    ctx.set_staged(1)
     eo, go = oracle.energy_grad(spec, ham, th[0], "adjoint")
     assert abs(e.item() - eo) < E_TOL
     np.testing.assert_allclose(g.cpu().numpy()[0], go, atol=G_TOL)

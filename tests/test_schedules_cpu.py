@@ -166,3 +166,29 @@ def test_workspace_accounts_for_states(ctx):
         assert B * state <= w0 < B * state * 1.2
         assert 2 * B * state <= w1 < 2 * B * state * 1.2
         assert w2 > w1
+
+
+@pytest.mark.parametrize("kind,n,k,c", [("random", 9, 8, 3), ("random", 10, 9, 4), ("hea", 12, 8, 3),
+                                         ("hea", 13, 12, 4), ("ucc", 8, 8, 3), ("random", 12, 12, 4)])
+def test_register_stage_schedules(ctx, kind, n, k, c):
+    ctx.set_tile(k, min(k, 12), c)
+    spec = {"random": lambda: synth.random_circuit(n, 60, seed=n),
+            "hea": lambda: synth.hea_circuit(n, 2),
+            "ucc": lambda: synth.ucc_circuit(8, 2)}[kind]()
+    ham = synth.random_pauli_sum(n, 30, seed=n)
+    th = synth.uniform_thetas(spec.n_params, 1, seed=n)[0]
+    C = vqe.Circuit.from_spec(ctx, spec)
+    mats = emu.gate_matrices(spec, th)
+    passes, ops, stages, sops = vqe.circuit_plan(ctx, C, stages=True)
+    assert len(stages) > 0 and int(passes["stage_count"].sum()) == len(stages)
+    assert len(sops) == len(ops)
+    ref = np.zeros(1 << n, dtype=complex)
+    ref[spec.ref_index] = 1
+    psi = emu.forward_staged(passes, stages, sops, ref, mats)
+    np.testing.assert_allclose(psi, oracle.state(spec, th), atol=1e-12)
+    rp, rops, rst, rsops = vqe.circuit_plan(ctx, C, reverse=True, stages=True)
+    n_pg = int((spec.param_idx >= 0).sum())
+    back, _, gpart = emu.reverse_staged(rp, rst, rsops, psi, oracle.apply_hamiltonian(psi, ham), mats, n_pg)
+    np.testing.assert_allclose(back, ref, atol=1e-12)
+    _, g_or = oracle.energy_grad(spec, ham, th, "adjoint")
+    np.testing.assert_allclose(_grad_from_parts(spec, gpart), g_or, atol=1e-11)
