@@ -229,6 +229,15 @@ def hea_measure(ctx, vqe, synth, torch, n):
     ms_fwd = s0.elapsed_time(s1) / reps
     pass_ms = ms_fwd / len(passes)
     gbps = 32.0 * (1 << n) / (pass_ms * 1e-3) / 1e9
+    # the same passes with one LDS round trip per gate (A/B of the register stages)
+    ctx.set_staged(False)
+    vqe.apply_ansatz(ctx, C, th, psi)
+    s0.record()
+    vqe.apply_ansatz(ctx, C, th, psi)
+    s1.record()
+    torch.cuda.synchronize()
+    ctx.set_staged(True)
+    ms_fwd_unstaged = s0.elapsed_time(s1)
     # expectation sweeps alone
     pl = vqe.hamiltonian_plan(ctx, H, 1, False)
     s0.record()
@@ -242,6 +251,7 @@ def hea_measure(ctx, vqe, synth, torch, n):
             "flip_groups": int(H.n_groups), "ms_per_energy_grad": round(ms_eval, 3),
             "forward_passes": int(len(passes)), "ms_forward": round(ms_fwd, 3),
             "forward_pass_GBps": round(gbps, 1), "forward_pass_frac_of_hbm": round(gbps / HBM_PEAK_GBPS, 4),
+            "ms_forward_one_gate_per_lds_trip": round(ms_fwd_unstaged, 3),
             "expect_sweeps": int(len(pl["sweeps"])), "ms_expect": round(ms_exp, 3),
             "expect_sweep_GBps": round(sweep_gbps, 1),
             "expect_sweep_frac_of_hbm": round(sweep_gbps / HBM_PEAK_GBPS, 4)}

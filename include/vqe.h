@@ -256,7 +256,7 @@ int vqe_run(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams, i
  * natural alignment):
  *
  * vqe_circ_plan_export: int32 {n_passes, n_ops, geom_bytes (72), op_bytes
- *   (48), n_stages, n_stage_ops, stage_bytes (32), stage_op_bytes (40)},
+ *   (48), n_stages, n_stage_ops, stage_bytes (48), stage_op_bytes (40)},
  *   then per pass {geom, int32 op_begin, op_count, n_param_ops,
  *   stage_begin, stage_count, 0, 0, 0}, then n_ops op records, n_stages
  *   stage records and n_stage_ops stage-op records.  geom = int32 {n, k, c,
@@ -271,7 +271,8 @@ int vqe_run(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams, i
  *   of 8 or more bits the same ops are also grouped into register stages:
  *   stage = uint8 rpos[4] (tile bits held in registers), uint8 cpos[12]
  *   (the other tile bits, ascending), int32 op_begin, op_count,
- *   n_param_ops, 0; stage op = uint64 cmo, cvo (controls outside the tile),
+ *   n_param_ops, 0, uint64 cpos packed 4 bits apiece, uint32 rpos packed
+ *   4 bits apiece, 0; stage op = uint64 cmo, cvo (controls outside the tile),
  *   uint32 cmt, cvt (tile controls outside the registers), int32 gate,
  *   pgate, uint8 M, lo, cmr, cvr (register flip mask, lower-element
  *   pattern, register controls), uint8 swap, cls, gen, 0: register index i

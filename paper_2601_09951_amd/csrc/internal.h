@@ -71,8 +71,11 @@ struct StageDesc {
     int32_t op_begin, op_count;
     int32_t n_param_ops;
     int32_t pad;
+    uint64_t cpack;      // cpos packed 4 bits apiece (register-resident copy)
+    uint32_t rpack;      // rpos packed 4 bits apiece
+    uint32_t pad2;
 };
-static_assert(sizeof(StageDesc) == 32, "StageDesc layout");
+static_assert(sizeof(StageDesc) == 48, "StageDesc layout");
 
 // One op inside a stage.  Register index i (4 bits) pairs with i ^ M; the
 // pair is active when (i & M) == lo, (i & cmr) == cvr, the sub-cube base

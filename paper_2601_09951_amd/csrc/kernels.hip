@@ -429,30 +429,69 @@ __device__ __forceinline__ double dispatch_rev(int M, double2 (&x)[16], double2 
     }
 }
 
-__device__ __forceinline__ void stage_offsets(const StageDesc *__restrict__ sd, uint32_t (&roff)[16])
+__device__ __forceinline__ void stage_offsets(uint32_t rpack, uint32_t (&roff)[16])
 {
-    const uint32_t r0 = 1u << sd->rpos[0], r1 = 1u << sd->rpos[1], r2 = 1u << sd->rpos[2], r3 = 1u << sd->rpos[3];
+    const uint32_t r0 = 1u << (rpack & 15u), r1 = 1u << ((rpack >> 4) & 15u);
+    const uint32_t r2 = 1u << ((rpack >> 8) & 15u), r3 = 1u << ((rpack >> 12) & 15u);
 #pragma unroll
     for (int i = 0; i < 16; ++i)
         roff[i] = ((i & 1) ? r0 : 0u) | ((i & 2) ? r1 : 0u) | ((i & 4) ? r2 : 0u) | ((i & 8) ? r3 : 0u);
 }
 
-__device__ __forceinline__ uint32_t subcube_base(const StageDesc *__restrict__ sd, int nc, uint32_t u)
+__device__ __forceinline__ uint32_t subcube_base(uint64_t cpack, int nc, uint32_t u)
 {
     uint32_t b = 0;
     for (int i = 0; i < nc; ++i)
-        if ((u >> i) & 1u) b |= 1u << sd->cpos[i];
+        if ((u >> i) & 1u) b |= 1u << ((uint32_t)(cpack >> (4 * i)) & 15u);
     return b;
+}
+
+// Per-workgroup copy of a pass's control data: stage descriptors, stage ops
+// and each op's matrix for this instance, so the inner loops read LDS
+// (broadcast) instead of chains of dependent global loads.
+struct StageCtl {
+    uint64_t cpack;
+    uint32_t rpack;
+    int32_t op_begin, op_count, n_param_ops;
+};
+
+__device__ __forceinline__ void load_stage_ctl(const StageDesc *__restrict__ stages, int nstages,
+                                               const StageOp *__restrict__ sops, const double2 *__restrict__ Mx,
+                                               StageCtl *sctl, StageOp *sop_l, Mat2 *mat_l, int reverse)
+{
+    const int ob0 = nstages ? stages[0].op_begin : 0;
+    for (int s = threadIdx.x; s < nstages; s += blockDim.x) {
+        sctl[s].cpack = stages[s].cpack;
+        sctl[s].rpack = stages[s].rpack;
+        sctl[s].op_begin = stages[s].op_begin - ob0;
+        sctl[s].op_count = stages[s].op_count;
+        sctl[s].n_param_ops = stages[s].n_param_ops;
+    }
+    const int nops = nstages ? stages[nstages - 1].op_begin + stages[nstages - 1].op_count - ob0 : 0;
+    for (int q = threadIdx.x; q < nops; q += blockDim.x) {
+        const StageOp o = sops[ob0 + q];
+        sop_l[q] = o;
+        const Mat2 v = stage_matrix(Mx, o.gate, o.swap);
+        mat_l[q] = reverse ? dagger(v) : v;
+    }
+}
+
+__host__ __device__ inline size_t stage_ctl_bytes(int nstages, int nops)
+{
+    return (size_t)nstages * sizeof(StageCtl) + (size_t)nops * (sizeof(StageOp) + sizeof(Mat2));
 }
 
 __global__ __launch_bounds__(kThreads) void k_forward_staged(
     const TileGeom *__restrict__ gp, int n, int k, int c, int nout, const StageDesc *__restrict__ stages,
-    int nstages, const StageOp *__restrict__ sops, const double2 *__restrict__ mats, int n_gates,
+    int nstages, int nops, const StageOp *__restrict__ sops, const double2 *__restrict__ mats, int n_gates,
     double2 *__restrict__ psi, int64_t tiles)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     double2 *tile = reinterpret_cast<double2 *>(smem);
     uint64_t *hoff = reinterpret_cast<uint64_t *>(smem + (16u << k));
+    Mat2 *mat_l = reinterpret_cast<Mat2 *>(hoff + (1u << (k - c)));
+    StageOp *sop_l = reinterpret_cast<StageOp *>(mat_l + nops);
+    StageCtl *sctl = reinterpret_cast<StageCtl *>(sop_l + nops);
     const int tid = threadIdx.x;
     const uint64_t dim = 1ull << n;
     double2 *st = psi + (uint64_t)blockIdx.y * dim;
@@ -461,26 +500,25 @@ __global__ __launch_bounds__(kThreads) void k_forward_staged(
     const int nsub = 1 << (k - kStageBits);
     const uint32_t lowm = (1u << c) - 1u;
     fill_hoff(gp, k, c, hoff);
+    load_stage_ctl(stages, nstages, sops, Mx, sctl, sop_l, mat_l, 0);
     __syncthreads();
     for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
         const uint64_t base = tile_base(gp, nout, t);
         for (int j = tid; j < T; j += kThreads) tile[swz(j)] = st[base + hoff[j >> c] + (j & lowm)];
         __syncthreads();
         for (int s = 0; s < nstages; ++s) {
-            const StageDesc *sd = stages + s;
+            const StageCtl sc = sctl[s];
             uint32_t roff[16];
-            stage_offsets(sd, roff);
-            const int ob = sd->op_begin, oc = sd->op_count;
+            stage_offsets(sc.rpack, roff);
             for (int u = tid; u < nsub; u += kThreads) {
-                const uint32_t bl = subcube_base(sd, k - kStageBits, (uint32_t)u);
+                const uint32_t bl = subcube_base(sc.cpack, k - kStageBits, (uint32_t)u);
                 double2 x[16];
 #pragma unroll
                 for (int i = 0; i < 16; ++i) x[i] = tile[swz(bl | roff[i])];
-                for (int q = ob; q < ob + oc; ++q) {
-                    const StageOp o = sops[q];
+                for (int q = sc.op_begin; q < sc.op_begin + sc.op_count; ++q) {
+                    const StageOp o = sop_l[q];
                     if ((base & o.cmo) != o.cvo) continue;
-                    const Mat2 v = stage_matrix(Mx, o.gate, o.swap);
-                    dispatch_fwd(o.M, x, v, o.cls, o.lo, o.cmr, o.cvr, (bl & o.cmt) == o.cvt);
+                    dispatch_fwd(o.M, x, mat_l[q], o.cls, o.lo, o.cmr, o.cvr, (bl & o.cmt) == o.cvt);
                 }
 #pragma unroll
                 for (int i = 0; i < 16; ++i) tile[swz(bl | roff[i])] = x[i];
@@ -494,7 +532,7 @@ __global__ __launch_bounds__(kThreads) void k_forward_staged(
 
 __global__ __launch_bounds__(kThreads) void k_reverse_staged(
     const TileGeom *__restrict__ gp, int n, int k, int c, int nout, const StageDesc *__restrict__ stages,
-    int nstages, const StageOp *__restrict__ sops, int n_param_ops, const double2 *__restrict__ mats,
+    int nstages, int nops, const StageOp *__restrict__ sops, int n_param_ops, const double2 *__restrict__ mats,
     int n_gates, double2 *__restrict__ psi, double2 *__restrict__ lam, int64_t tiles,
     double *__restrict__ partials, int n_pgates)
 {
@@ -503,6 +541,9 @@ __global__ __launch_bounds__(kThreads) void k_reverse_staged(
     double2 *tl = tp + (1u << k);
     uint64_t *hoff = reinterpret_cast<uint64_t *>(smem + (32u << k));
     double *red = reinterpret_cast<double *>(hoff + (1u << (k - c)));
+    Mat2 *mat_l = reinterpret_cast<Mat2 *>(red + 4 * (size_t)(n_param_ops > 0 ? n_param_ops : 1));
+    StageOp *sop_l = reinterpret_cast<StageOp *>(mat_l + nops);
+    StageCtl *sctl = reinterpret_cast<StageCtl *>(sop_l + nops);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint64_t dim = 1ull << n;
     double2 *sp = psi + (uint64_t)blockIdx.y * dim;
@@ -512,6 +553,7 @@ __global__ __launch_bounds__(kThreads) void k_reverse_staged(
     const int nsub = 1 << (k - kStageBits);
     const uint32_t lowm = (1u << c) - 1u;
     fill_hoff(gp, k, c, hoff);
+    load_stage_ctl(stages, nstages, sops, Mx, sctl, sop_l, mat_l, 1);
     for (int i = tid; i < n_param_ops * 4; i += kThreads) red[i] = 0.0;
     __syncthreads();
     for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
@@ -524,15 +566,14 @@ __global__ __launch_bounds__(kThreads) void k_reverse_staged(
         __syncthreads();
         int slot0 = 0;
         for (int s = 0; s < nstages; ++s) {
-            const StageDesc *sd = stages + s;
+            const StageCtl sc = sctl[s];
             uint32_t roff[16];
-            stage_offsets(sd, roff);
-            const int ob = sd->op_begin, oc = sd->op_count;
+            stage_offsets(sc.rpack, roff);
             // every thread walks the ops (a thread with no sub-cube contributes 0)
             for (int u0 = 0; u0 < nsub; u0 += kThreads) {
                 const int u = u0 + tid;
                 const bool have = u < nsub;
-                const uint32_t bl = have ? subcube_base(sd, k - kStageBits, (uint32_t)u) : 0u;
+                const uint32_t bl = have ? subcube_base(sc.cpack, k - kStageBits, (uint32_t)u) : 0u;
                 double2 x[16], l[16];
 #pragma unroll
                 for (int i = 0; i < 16; ++i) {
@@ -540,15 +581,14 @@ __global__ __launch_bounds__(kThreads) void k_reverse_staged(
                     l[i] = have ? tl[swz(bl | roff[i])] : make_double2(0.0, 0.0);
                 }
                 int slot = slot0;
-                for (int q = ob; q < ob + oc; ++q) {
-                    const StageOp o = sops[q];
+                for (int q = sc.op_begin; q < sc.op_begin + sc.op_count; ++q) {
+                    const StageOp o = sop_l[q];
                     const int my_slot = slot;
                     if (o.pgate >= 0) ++slot;
                     if ((base & o.cmo) != o.cvo) continue;
-                    const Mat2 w = dagger(stage_matrix(Mx, o.gate, o.swap));
                     const double sgn = o.swap ? -1.0 : 1.0;
                     const int gen = o.pgate >= 0 ? o.gen : GEN_NONE;
-                    double acc = dispatch_rev(o.M, x, l, w, o.cls, gen, o.lo, o.cmr, o.cvr,
+                    double acc = dispatch_rev(o.M, x, l, mat_l[q], o.cls, gen, o.lo, o.cmr, o.cvr,
                                               have && ((bl & o.cmt) == o.cvt), sgn);
                     if (o.pgate >= 0) {
                         acc = wave_sum(acc);
@@ -563,7 +603,7 @@ __global__ __launch_bounds__(kThreads) void k_reverse_staged(
                     }
                 }
             }
-            slot0 += sd->n_param_ops;
+            slot0 += sc.n_param_ops;
             __syncthreads();
         }
         for (int j = tid; j < T; j += kThreads) {
@@ -576,15 +616,12 @@ __global__ __launch_bounds__(kThreads) void k_reverse_staged(
     if (tid == 0) {
         const int W = gridDim.x;
         int slot = 0;
-        for (int s = 0; s < nstages; ++s) {
-            const StageDesc *sd = stages + s;
-            for (int q = sd->op_begin; q < sd->op_begin + sd->op_count; ++q) {
-                const int pg = sops[q].pgate;
-                if (pg < 0) continue;
-                const double v = red[slot * 4 + 0] + red[slot * 4 + 1] + red[slot * 4 + 2] + red[slot * 4 + 3];
-                partials[((size_t)blockIdx.y * n_pgates + pg) * W + blockIdx.x] = v;
-                ++slot;
-            }
+        for (int q = 0; q < nops; ++q) {
+            const int pg = sop_l[q].pgate;
+            if (pg < 0) continue;
+            const double v = red[slot * 4 + 0] + red[slot * 4 + 1] + red[slot * 4 + 2] + red[slot * 4 + 3];
+            partials[((size_t)blockIdx.y * n_pgates + pg) * W + blockIdx.x] = v;
+            ++slot;
         }
     }
 }
@@ -846,11 +883,12 @@ hipError_t launch_forward_staged(const PassPlan &pp, const TileGeom *geom_dev,
     const TileGeom &g = pp.geom;
     const int64_t tiles = 1ll << g.nout;
     const int W = (int)std::min<int64_t>(tiles, wg_max);
-    const size_t lds = fwd_lds(g);
+    const size_t lds = fwd_lds(g) + stage_ctl_bytes(pp.stage_count, pp.op_count);
     hipError_t e = ensure_lds(k_forward_staged, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_forward_staged, dim3(W, (unsigned)batch), dim3(kThreads), lds, s, geom_dev, g.n, g.k,
-                       g.c, g.nout, stages + pp.stage_begin, pp.stage_count, sops, mats, n_gates, psi, tiles);
+                       g.c, g.nout, stages + pp.stage_begin, pp.stage_count, pp.op_count, sops, mats, n_gates,
+                       psi, tiles);
     return hipGetLastError();
 }
 
@@ -861,12 +899,12 @@ hipError_t launch_reverse_staged(const PassPlan &pp, const TileGeom *geom_dev,
 {
     const TileGeom &g = pp.geom;
     const int64_t tiles = 1ll << g.nout;
-    const size_t lds = rev_lds(g, pp.n_param_ops);
+    const size_t lds = rev_lds(g, pp.n_param_ops) + stage_ctl_bytes(pp.stage_count, pp.op_count);
     hipError_t e = ensure_lds(k_reverse_staged, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_reverse_staged, dim3(wg_per_inst, (unsigned)batch), dim3(kThreads), lds, s, geom_dev,
-                       g.n, g.k, g.c, g.nout, stages + pp.stage_begin, pp.stage_count, sops, pp.n_param_ops,
-                       mats, n_gates, psi, lam, tiles, partials, n_pgates);
+                       g.n, g.k, g.c, g.nout, stages + pp.stage_begin, pp.stage_count, pp.op_count, sops,
+                       pp.n_param_ops, mats, n_gates, psi, lam, tiles, partials, n_pgates);
     return hipGetLastError();
 }
 

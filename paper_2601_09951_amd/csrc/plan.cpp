@@ -24,7 +24,9 @@ namespace vqe {
 
 namespace {
 
-constexpr int kMaxParamOpsPerPass = 256;
+// bounds that keep a pass's control data plus a two-state 2^12 tile inside 160 KiB of LDS
+constexpr int kMaxParamOpsPerPass = 128;
+constexpr int kMaxOpsPerPass = 128;
 
 inline int popc(uint64_t v) { return __builtin_popcountll(v); }
 inline int bit_of_wire(int n, int w) { return n - 1 - w; }
@@ -227,8 +229,14 @@ static void build_stages(const Circ *C, const std::vector<int> &take, const std:
         for (int b = 0; b < keff; ++b) ((R >> b) & 1 ? rbits : cbits).push_back(b);
         StageDesc sd;
         std::memset(&sd, 0, sizeof(sd));
-        for (int i = 0; i < kStageBits; ++i) sd.rpos[i] = (uint8_t)rbits[i];
-        for (size_t i = 0; i < cbits.size(); ++i) sd.cpos[i] = (uint8_t)cbits[i];
+        for (int i = 0; i < kStageBits; ++i) {
+            sd.rpos[i] = (uint8_t)rbits[i];
+            sd.rpack |= (uint32_t)rbits[i] << (4 * i);
+        }
+        for (size_t i = 0; i < cbits.size(); ++i) {
+            sd.cpos[i] = (uint8_t)cbits[i];
+            sd.cpack |= (uint64_t)cbits[i] << (4 * i);
+        }
         sd.op_begin = (int)plan->host_sops.size();
         sd.op_count = (int)st.size();
         int nparam = 0;
@@ -309,7 +317,7 @@ CircPlan *get_circ_plan(Circ *C, bool reverse, int k, int c, int *rc)
             }
             uint64_t need = h.m & ~S;
             bool room = popc(S) + popc(need) <= keff;
-            bool param_room = h.pidx < 0 || nparam < kMaxParamOpsPerPass;
+            bool param_room = (h.pidx < 0 || nparam < kMaxParamOpsPerPass) && (int)take.size() < kMaxOpsPerPass;
             if (room && param_room) {
                 S |= need;
                 take.push_back(g);
