@@ -271,12 +271,13 @@ int vqe_run(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams, i
  *   of 8 or more bits the same ops are also grouped into register stages:
  *   stage = uint8 rpos[4] (tile bits held in registers), uint8 cpos[12]
  *   (the other tile bits, ascending), int32 op_begin, op_count,
- *   n_param_ops, 0, uint64 cpos packed 4 bits apiece, uint32 rpos packed
- *   4 bits apiece, 0; stage op = uint64 cmo, cvo (controls outside the tile),
+ *   n_param_ops, nbits (register bits: 4 forward, 3 adjoint), uint64 cpos
+ *   packed 4 bits apiece, uint32 rpos packed 4 bits apiece, 0; stage op =
+ *   uint64 cmo, cvo (controls outside the tile),
  *   uint32 cmt, cvt (tile controls outside the registers), int32 gate,
  *   pgate, uint8 M, lo, cmr, cvr (register flip mask, lower-element
  *   pattern, register controls), uint8 swap, cls, gen, 0: register index i
- *   pairs with i ^ M when (i & M) == lo and the controls hold; swap = 1
+ *   pairs with i ^ M (i < 2^nbits) when (i & M) == lo and the controls hold; swap = 1
  *   means the lower index holds the op's second element.
  *   reverse = 1 exports the adjoint sweep's schedule (gates in reverse).
  *

@@ -62,7 +62,8 @@ static_assert(sizeof(TileGeom) == 72, "TileGeom layout");
 // four tile bits (rpos) in registers: each thread owns 2^4 amplitudes that
 // differ only in those bits and applies the stage's ops to them in
 // registers; the other k - 4 tile bits (cpos) number the sub-cubes.
-constexpr int kStageBits = 4;
+constexpr int kStageBitsFwd = 4;   // forward passes: 16 amplitudes per thread
+constexpr int kStageBitsRev = 3;   // adjoint passes: 8 amplitudes of psi and of lambda per thread
 constexpr int kStageMinK = 8;
 
 struct StageDesc {
@@ -70,7 +71,7 @@ struct StageDesc {
     uint8_t cpos[12];    // tile-local positions of the sub-cube bits (ascending)
     int32_t op_begin, op_count;
     int32_t n_param_ops;
-    int32_t pad;
+    int32_t nbits;       // register bits of this stage (rpos[0..nbits))
     uint64_t cpack;      // cpos packed 4 bits apiece (register-resident copy)
     uint32_t rpack;      // rpos packed 4 bits apiece
     uint32_t pad2;
@@ -158,6 +159,7 @@ struct PassPlan {
 
 struct CircPlan {
     int k = 0, c = 0;
+    int stage_bits = 0;
     bool reverse = false;
     std::vector<PassPlan> passes;
     DevMem ops;              // OpDesc[]
@@ -249,10 +251,10 @@ hipError_t launch_gate_mats(const GateDev *gates, int n_gates, const double *the
 hipError_t launch_forward_pass(const PassPlan &pp, const TileGeom *geom_dev, const OpDesc *ops,
                                const double2 *mats, int n_gates, double2 *psi, int64_t batch,
                                int wg_max, hipStream_t s);
-hipError_t launch_forward_staged(const PassPlan &pp, const TileGeom *geom_dev,
+hipError_t launch_forward_staged(const PassPlan &pp, int stage_bits, const TileGeom *geom_dev,
                                  const StageDesc *stages, const StageOp *sops, const double2 *mats,
                                  int n_gates, double2 *psi, int64_t batch, int wg_max, hipStream_t s);
-hipError_t launch_reverse_staged(const PassPlan &pp, const TileGeom *geom_dev,
+hipError_t launch_reverse_staged(const PassPlan &pp, int stage_bits, const TileGeom *geom_dev,
                                  const StageDesc *stages, const StageOp *sops, const double2 *mats,
                                  int n_gates, double2 *psi, double2 *lam, int64_t batch,
                                  int wg_per_inst, double *partials, int n_pgates, hipStream_t s);

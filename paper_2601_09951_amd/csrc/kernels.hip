@@ -327,14 +327,14 @@ __device__ __forceinline__ Mat2 dagger(const Mat2 &v)
     return w;
 }
 
-template <int M>
-__device__ __forceinline__ void stage_fwd(double2 (&x)[16], const Mat2 &v, int cls, int lo, int cmr, int cvr,
+template <int RB, int M>
+__device__ __forceinline__ void stage_fwd(double2 (&x)[1 << RB], const Mat2 &v, int cls, int lo, int cmr, int cvr,
                                           bool tpred)
 {
     constexpr int HB = M >= 8 ? 8 : (M >= 4 ? 4 : (M >= 2 ? 2 : 1));
     if (cls == CLS_SWAP) {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
+        for (int i = 0; i < (1 << RB); ++i) {
             if (i & HB) continue;
             if (((i & M) == lo) && ((i & cmr) == cvr) && tpred) {
                 const double2 t = x[i];
@@ -344,7 +344,7 @@ __device__ __forceinline__ void stage_fwd(double2 (&x)[16], const Mat2 &v, int c
         }
     } else if (cls == CLS_DIAG) {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
+        for (int i = 0; i < (1 << RB); ++i) {
             if (i & HB) continue;
             if (((i & M) == lo) && ((i & cmr) == cvr) && tpred) {
                 x[i] = cmul(v.a, x[i]);
@@ -353,7 +353,7 @@ __device__ __forceinline__ void stage_fwd(double2 (&x)[16], const Mat2 &v, int c
         }
     } else {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
+        for (int i = 0; i < (1 << RB); ++i) {
             if (i & HB) continue;
             if (((i & M) == lo) && ((i & cmr) == cvr) && tpred) {
                 const double2 p = x[i], q = x[i ^ M];
@@ -367,14 +367,14 @@ __device__ __forceinline__ void stage_fwd(double2 (&x)[16], const Mat2 &v, int c
 // reverse: gradient term over the pair (in (lower, upper) orientation; sgn
 // restores the op's (first, second) orientation for the antisymmetric
 // generators), then U^dagger on both states
-template <int M>
-__device__ __forceinline__ double stage_rev(double2 (&x)[16], double2 (&l)[16], const Mat2 &w, int cls, int gen,
-                                            int lo, int cmr, int cvr, bool tpred, double sgn)
+template <int RB, int M>
+__device__ __forceinline__ double stage_rev(double2 (&x)[1 << RB], double2 (&l)[1 << RB], const Mat2 &w, int cls,
+                                            int gen, int lo, int cmr, int cvr, bool tpred, double sgn)
 {
     constexpr int HB = M >= 8 ? 8 : (M >= 4 ? 4 : (M >= 2 ? 2 : 1));
     double acc = 0.0;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
+    for (int i = 0; i < (1 << RB); ++i) {
         if (i & HB) continue;
         if (((i & M) == lo) && ((i & cmr) == cvr) && tpred) {
             const double2 a = x[i], b = x[i ^ M], la = l[i], lb = l[i ^ M];
@@ -407,35 +407,50 @@ __device__ __forceinline__ double stage_rev(double2 (&x)[16], double2 (&l)[16], 
 
 #define VQE_MASK_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15)
 
-__device__ __forceinline__ void dispatch_fwd(int M, double2 (&x)[16], const Mat2 &v, int cls, int lo, int cmr,
+template <int RB>
+__device__ __forceinline__ void dispatch_fwd(int M, double2 (&x)[1 << RB], const Mat2 &v, int cls, int lo, int cmr,
                                              int cvr, bool tpred)
 {
     switch (M) {
-#define VQE_CASE(m) case m: stage_fwd<m>(x, v, cls, lo, cmr, cvr, tpred); break;
+#define VQE_CASE(m)                                                                                    \
+    case m:                                                                                            \
+        if constexpr (m < (1 << RB)) stage_fwd<RB, m>(x, v, cls, lo, cmr, cvr, tpred);                \
+        break;
         VQE_MASK_CASES(VQE_CASE)
 #undef VQE_CASE
     default: break;
     }
 }
 
-__device__ __forceinline__ double dispatch_rev(int M, double2 (&x)[16], double2 (&l)[16], const Mat2 &w, int cls,
-                                               int gen, int lo, int cmr, int cvr, bool tpred, double sgn)
+template <int RB>
+__device__ __forceinline__ double dispatch_rev(int M, double2 (&x)[1 << RB], double2 (&l)[1 << RB], const Mat2 &w,
+                                               int cls, int gen, int lo, int cmr, int cvr, bool tpred, double sgn)
 {
     switch (M) {
-#define VQE_CASE(m) case m: return stage_rev<m>(x, l, w, cls, gen, lo, cmr, cvr, tpred, sgn);
+#define VQE_CASE(m)                                                                                    \
+    case m:                                                                                            \
+        if constexpr (m < (1 << RB)) return stage_rev<RB, m>(x, l, w, cls, gen, lo, cmr, cvr, tpred, sgn); \
+        break;
         VQE_MASK_CASES(VQE_CASE)
 #undef VQE_CASE
-    default: return 0.0;
+    default: break;
     }
+    return 0.0;
 }
 
-__device__ __forceinline__ void stage_offsets(uint32_t rpack, uint32_t (&roff)[16])
+template <int RB>
+__device__ __forceinline__ void stage_offsets(uint32_t rpack, uint32_t (&roff)[1 << RB])
 {
-    const uint32_t r0 = 1u << (rpack & 15u), r1 = 1u << ((rpack >> 4) & 15u);
-    const uint32_t r2 = 1u << ((rpack >> 8) & 15u), r3 = 1u << ((rpack >> 12) & 15u);
+    uint32_t r[RB];
 #pragma unroll
-    for (int i = 0; i < 16; ++i)
-        roff[i] = ((i & 1) ? r0 : 0u) | ((i & 2) ? r1 : 0u) | ((i & 4) ? r2 : 0u) | ((i & 8) ? r3 : 0u);
+    for (int b = 0; b < RB; ++b) r[b] = 1u << ((rpack >> (4 * b)) & 15u);
+#pragma unroll
+    for (int i = 0; i < (1 << RB); ++i) {
+        uint32_t o = 0;
+#pragma unroll
+        for (int b = 0; b < RB; ++b) o |= ((i >> b) & 1) ? r[b] : 0u;
+        roff[i] = o;
+    }
 }
 
 __device__ __forceinline__ uint32_t subcube_base(uint64_t cpack, int nc, uint32_t u)
@@ -481,6 +496,7 @@ __host__ __device__ inline size_t stage_ctl_bytes(int nstages, int nops)
     return (size_t)nstages * sizeof(StageCtl) + (size_t)nops * (sizeof(StageOp) + sizeof(Mat2));
 }
 
+template <int RB>
 __global__ __launch_bounds__(kThreads) void k_forward_staged(
     const TileGeom *__restrict__ gp, int n, int k, int c, int nout, const StageDesc *__restrict__ stages,
     int nstages, int nops, const StageOp *__restrict__ sops, const double2 *__restrict__ mats, int n_gates,
@@ -497,7 +513,7 @@ __global__ __launch_bounds__(kThreads) void k_forward_staged(
     double2 *st = psi + (uint64_t)blockIdx.y * dim;
     const double2 *Mx = mats + (size_t)blockIdx.y * n_gates * 4;
     const int T = 1 << k;
-    const int nsub = 1 << (k - kStageBits);
+    const int nsub = 1 << (k - RB);
     const uint32_t lowm = (1u << c) - 1u;
     fill_hoff(gp, k, c, hoff);
     load_stage_ctl(stages, nstages, sops, Mx, sctl, sop_l, mat_l, 0);
@@ -508,20 +524,20 @@ __global__ __launch_bounds__(kThreads) void k_forward_staged(
         __syncthreads();
         for (int s = 0; s < nstages; ++s) {
             const StageCtl sc = sctl[s];
-            uint32_t roff[16];
-            stage_offsets(sc.rpack, roff);
+            uint32_t roff[1 << RB];
+            stage_offsets<RB>(sc.rpack, roff);
             for (int u = tid; u < nsub; u += kThreads) {
-                const uint32_t bl = subcube_base(sc.cpack, k - kStageBits, (uint32_t)u);
-                double2 x[16];
+                const uint32_t bl = subcube_base(sc.cpack, k - RB, (uint32_t)u);
+                double2 x[1 << RB];
 #pragma unroll
-                for (int i = 0; i < 16; ++i) x[i] = tile[swz(bl | roff[i])];
+                for (int i = 0; i < (1 << RB); ++i) x[i] = tile[swz(bl | roff[i])];
                 for (int q = sc.op_begin; q < sc.op_begin + sc.op_count; ++q) {
                     const StageOp o = sop_l[q];
                     if ((base & o.cmo) != o.cvo) continue;
-                    dispatch_fwd(o.M, x, mat_l[q], o.cls, o.lo, o.cmr, o.cvr, (bl & o.cmt) == o.cvt);
+                    dispatch_fwd<RB>(o.M, x, mat_l[q], o.cls, o.lo, o.cmr, o.cvr, (bl & o.cmt) == o.cvt);
                 }
 #pragma unroll
-                for (int i = 0; i < 16; ++i) tile[swz(bl | roff[i])] = x[i];
+                for (int i = 0; i < (1 << RB); ++i) tile[swz(bl | roff[i])] = x[i];
             }
             __syncthreads();
         }
@@ -530,6 +546,7 @@ __global__ __launch_bounds__(kThreads) void k_forward_staged(
     }
 }
 
+template <int RB>
 __global__ __launch_bounds__(kThreads) void k_reverse_staged(
     const TileGeom *__restrict__ gp, int n, int k, int c, int nout, const StageDesc *__restrict__ stages,
     int nstages, int nops, const StageOp *__restrict__ sops, int n_param_ops, const double2 *__restrict__ mats,
@@ -550,7 +567,7 @@ __global__ __launch_bounds__(kThreads) void k_reverse_staged(
     double2 *sl = lam + (uint64_t)blockIdx.y * dim;
     const double2 *Mx = mats + (size_t)blockIdx.y * n_gates * 4;
     const int T = 1 << k;
-    const int nsub = 1 << (k - kStageBits);
+    const int nsub = 1 << (k - RB);
     const uint32_t lowm = (1u << c) - 1u;
     fill_hoff(gp, k, c, hoff);
     load_stage_ctl(stages, nstages, sops, Mx, sctl, sop_l, mat_l, 1);
@@ -567,16 +584,16 @@ __global__ __launch_bounds__(kThreads) void k_reverse_staged(
         int slot0 = 0;
         for (int s = 0; s < nstages; ++s) {
             const StageCtl sc = sctl[s];
-            uint32_t roff[16];
-            stage_offsets(sc.rpack, roff);
+            uint32_t roff[1 << RB];
+            stage_offsets<RB>(sc.rpack, roff);
             // every thread walks the ops (a thread with no sub-cube contributes 0)
             for (int u0 = 0; u0 < nsub; u0 += kThreads) {
                 const int u = u0 + tid;
                 const bool have = u < nsub;
-                const uint32_t bl = have ? subcube_base(sc.cpack, k - kStageBits, (uint32_t)u) : 0u;
-                double2 x[16], l[16];
+                const uint32_t bl = have ? subcube_base(sc.cpack, k - RB, (uint32_t)u) : 0u;
+                double2 x[1 << RB], l[1 << RB];
 #pragma unroll
-                for (int i = 0; i < 16; ++i) {
+                for (int i = 0; i < (1 << RB); ++i) {
                     x[i] = have ? tp[swz(bl | roff[i])] : make_double2(0.0, 0.0);
                     l[i] = have ? tl[swz(bl | roff[i])] : make_double2(0.0, 0.0);
                 }
@@ -588,7 +605,7 @@ __global__ __launch_bounds__(kThreads) void k_reverse_staged(
                     if ((base & o.cmo) != o.cvo) continue;
                     const double sgn = o.swap ? -1.0 : 1.0;
                     const int gen = o.pgate >= 0 ? o.gen : GEN_NONE;
-                    double acc = dispatch_rev(o.M, x, l, mat_l[q], o.cls, gen, o.lo, o.cmr, o.cvr,
+                    double acc = dispatch_rev<RB>(o.M, x, l, mat_l[q], o.cls, gen, o.lo, o.cmr, o.cvr,
                                               have && ((bl & o.cmt) == o.cvt), sgn);
                     if (o.pgate >= 0) {
                         acc = wave_sum(acc);
@@ -597,7 +614,7 @@ __global__ __launch_bounds__(kThreads) void k_reverse_staged(
                 }
                 if (have) {
 #pragma unroll
-                    for (int i = 0; i < 16; ++i) {
+                    for (int i = 0; i < (1 << RB); ++i) {
                         tp[swz(bl | roff[i])] = x[i];
                         tl[swz(bl | roff[i])] = l[i];
                     }
@@ -876,7 +893,7 @@ hipError_t launch_reverse_pass(const PassPlan &pp, const TileGeom *geom_dev, con
     return hipGetLastError();
 }
 
-hipError_t launch_forward_staged(const PassPlan &pp, const TileGeom *geom_dev,
+hipError_t launch_forward_staged(const PassPlan &pp, int stage_bits, const TileGeom *geom_dev,
                                  const StageDesc *stages, const StageOp *sops, const double2 *mats,
                                  int n_gates, double2 *psi, int64_t batch, int wg_max, hipStream_t s)
 {
@@ -884,15 +901,15 @@ hipError_t launch_forward_staged(const PassPlan &pp, const TileGeom *geom_dev,
     const int64_t tiles = 1ll << g.nout;
     const int W = (int)std::min<int64_t>(tiles, wg_max);
     const size_t lds = fwd_lds(g) + stage_ctl_bytes(pp.stage_count, pp.op_count);
-    hipError_t e = ensure_lds(k_forward_staged, lds);
+    auto kern = stage_bits == 4 ? k_forward_staged<4> : k_forward_staged<3>;
+    hipError_t e = ensure_lds(kern, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_forward_staged, dim3(W, (unsigned)batch), dim3(kThreads), lds, s, geom_dev, g.n, g.k,
-                       g.c, g.nout, stages + pp.stage_begin, pp.stage_count, pp.op_count, sops, mats, n_gates,
-                       psi, tiles);
+    hipLaunchKernelGGL(kern, dim3(W, (unsigned)batch), dim3(kThreads), lds, s, geom_dev, g.n, g.k, g.c, g.nout,
+                       stages + pp.stage_begin, pp.stage_count, pp.op_count, sops, mats, n_gates, psi, tiles);
     return hipGetLastError();
 }
 
-hipError_t launch_reverse_staged(const PassPlan &pp, const TileGeom *geom_dev,
+hipError_t launch_reverse_staged(const PassPlan &pp, int stage_bits, const TileGeom *geom_dev,
                                  const StageDesc *stages, const StageOp *sops, const double2 *mats,
                                  int n_gates, double2 *psi, double2 *lam, int64_t batch,
                                  int wg_per_inst, double *partials, int n_pgates, hipStream_t s)
@@ -900,11 +917,12 @@ hipError_t launch_reverse_staged(const PassPlan &pp, const TileGeom *geom_dev,
     const TileGeom &g = pp.geom;
     const int64_t tiles = 1ll << g.nout;
     const size_t lds = rev_lds(g, pp.n_param_ops) + stage_ctl_bytes(pp.stage_count, pp.op_count);
-    hipError_t e = ensure_lds(k_reverse_staged, lds);
+    auto kern = stage_bits == 4 ? k_reverse_staged<4> : k_reverse_staged<3>;
+    hipError_t e = ensure_lds(kern, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reverse_staged, dim3(wg_per_inst, (unsigned)batch), dim3(kThreads), lds, s, geom_dev,
-                       g.n, g.k, g.c, g.nout, stages + pp.stage_begin, pp.stage_count, pp.op_count, sops,
-                       pp.n_param_ops, mats, n_gates, psi, lam, tiles, partials, n_pgates);
+    hipLaunchKernelGGL(kern, dim3(wg_per_inst, (unsigned)batch), dim3(kThreads), lds, s, geom_dev, g.n, g.k, g.c,
+                       g.nout, stages + pp.stage_begin, pp.stage_count, pp.op_count, sops, pp.n_param_ops, mats,
+                       n_gates, psi, lam, tiles, partials, n_pgates);
     return hipGetLastError();
 }
 

@@ -184,11 +184,11 @@ static void free_plan(Context *ctx, CircPlan *p)
 }
 
 // Split a pass's ops (tile-local, in order) into register stages of
-// kStageBits bits.  An op needs its flip bits in registers; its controls may
+// `nbits` bits.  An op needs its flip bits in registers; its controls may
 // be anywhere (register, other tile bits or outside the tile).  An op may
 // move ahead of skipped ops only if it shares no tile bit with them.
 static void build_stages(const Circ *C, const std::vector<int> &take, const std::vector<int> &tile,
-                         int keff, CircPlan *plan, PassPlan &pp)
+                         int keff, int nbits, CircPlan *plan, PassPlan &pp)
 {
     const uint64_t tmask = mask_of(tile);
     struct Loc {
@@ -216,20 +216,21 @@ static void build_stages(const Circ *C, const std::vector<int> &take, const std:
                 continue;
             }
             const uint32_t need = loc[q].m & ~R;
-            if (popc(R) + popc(need) <= kStageBits) {
+            if (popc(R) + popc(need) <= nbits) {
                 R |= need;
                 st.push_back(q);
             } else {
                 blocked |= touched;
             }
         }
-        // pad the register set to exactly kStageBits bits
-        for (int b = 0; b < keff && popc(R) < kStageBits; ++b) R |= 1u << b;
+        // pad the register set to exactly nbits bits
+        for (int b = 0; b < keff && popc(R) < nbits; ++b) R |= 1u << b;
         std::vector<int> rbits, cbits;
         for (int b = 0; b < keff; ++b) ((R >> b) & 1 ? rbits : cbits).push_back(b);
         StageDesc sd;
         std::memset(&sd, 0, sizeof(sd));
-        for (int i = 0; i < kStageBits; ++i) {
+        sd.nbits = nbits;
+        for (int i = 0; i < nbits; ++i) {
             sd.rpos[i] = (uint8_t)rbits[i];
             sd.rpack |= (uint32_t)rbits[i] << (4 * i);
         }
@@ -292,6 +293,7 @@ CircPlan *get_circ_plan(Circ *C, bool reverse, int k, int c, int *rc)
     plan->k = keff;
     plan->c = ceff;
     plan->reverse = reverse;
+    plan->stage_bits = reverse ? kStageBitsRev : kStageBitsFwd;
 
     const int G = (int)C->gates.size();
     std::vector<int> order(G);
@@ -361,7 +363,7 @@ CircPlan *get_circ_plan(Circ *C, bool reverse, int k, int c, int *rc)
             done[g] = 1;
             --remaining;
         }
-        if (keff >= kStageMinK) build_stages(C, take, tile, keff, plan.get(), pp);
+        if (keff >= kStageMinK) build_stages(C, take, tile, keff, plan->stage_bits, plan.get(), pp);
         plan->passes.push_back(pp);
     }
     if (!ops.empty()) {

@@ -353,7 +353,7 @@ _GEOM = np.dtype([("n", "<i4"), ("k", "<i4"), ("c", "<i4"), ("nout", "<i4"), ("t
 _PASS = np.dtype([("geom", _GEOM), ("op_begin", "<i4"), ("op_count", "<i4"), ("n_param_ops", "<i4"),
                   ("stage_begin", "<i4"), ("stage_count", "<i4"), ("pad", "<i4", 3)])
 _STAGE = np.dtype([("rpos", "u1", 4), ("cpos", "u1", 12), ("op_begin", "<i4"), ("op_count", "<i4"),
-                   ("n_param_ops", "<i4"), ("pad", "<i4"), ("cpack", "<u8"), ("rpack", "<u4"), ("pad2", "<u4")])
+                   ("n_param_ops", "<i4"), ("nbits", "<i4"), ("cpack", "<u8"), ("rpack", "<u4"), ("pad2", "<u4")])
 _SOP = np.dtype([("cmo", "<u8"), ("cvo", "<u8"), ("cmt", "<u4"), ("cvt", "<u4"), ("gate", "<i4"),
                  ("pgate", "<i4"), ("M", "u1"), ("lo", "u1"), ("cmr", "u1"), ("cvr", "u1"), ("swap", "u1"),
                  ("cls", "u1"), ("gen", "u1"), ("pad", "u1")])

@@ -226,11 +226,15 @@ def sweeps(plan, psi, inst=0, hpsi=False):
 # register stages
 # ---------------------------------------------------------------------------
 def _stage_index(st, k):
-    rpos = [int(v) for v in st["rpos"]]
-    cpos = [int(v) for v in st["cpos"][:k - 4]]
+    nb = int(st["nbits"])
+    assert nb in (3, 4)
+    rpos = [int(v) for v in st["rpos"][:nb]]
+    cpos = [int(v) for v in st["cpos"][:k - nb]]
     assert len(set(rpos + cpos)) == k and max(rpos + cpos) < k
-    roff = np.array([sum(((i >> b) & 1) << rpos[b] for b in range(4)) for i in range(16)], dtype=np.int64)
-    u = np.arange(1 << (k - 4), dtype=np.int64)
+    assert [int(st["rpack"]) >> (4 * i) & 15 for i in range(nb)] == rpos
+    assert [int(st["cpack"]) >> (4 * i) & 15 for i in range(k - nb)] == cpos
+    roff = np.array([sum(((i >> b) & 1) << rpos[b] for b in range(nb)) for i in range(1 << nb)], dtype=np.int64)
+    u = np.arange(1 << (k - nb), dtype=np.int64)
     bl = np.zeros_like(u)
     for i, p in enumerate(cpos):
         bl |= ((u >> i) & 1) << p
@@ -239,11 +243,11 @@ def _stage_index(st, k):
     return bl, idx
 
 
-def _stage_pairs(op):
+def _stage_pairs(op, nb):
     M, lo, cmr, cvr = int(op["M"]), int(op["lo"]), int(op["cmr"]), int(op["cvr"])
-    assert 1 <= M <= 15
+    assert 1 <= M < (1 << nb) and cmr < (1 << nb)
     hb = 1 << (M.bit_length() - 1)
-    return [(i, i ^ M) for i in range(16) if not (i & hb) and (i & M) == lo and (i & cmr) == cvr]
+    return [(i, i ^ M) for i in range(1 << nb) if not (i & hb) and (i & M) == lo and (i & cmr) == cvr]
 
 
 def _stage_matrix(U, swap):
@@ -265,7 +269,7 @@ def forward_staged(passes, stages, sops, psi, mats):
                 tpred = (bl & int(op["cmt"])) == int(op["cvt"])
                 V = _stage_matrix(mats[int(op["gate"])], int(op["swap"]))
                 sel = np.ix_(act, tpred)
-                for i, j in _stage_pairs(op):
+                for i, j in _stage_pairs(op, int(st["nbits"])):
                     a = T[:, sidx[:, i]][sel]
                     b = T[:, sidx[:, j]][sel]
                     cls = int(op["cls"])
@@ -301,7 +305,7 @@ def reverse_staged(passes, stages, sops, psi, lam, mats, n_pgates):
                 W = _stage_matrix(mats[int(op["gate"])], int(op["swap"])).conj().T
                 sgn = -1.0 if int(op["swap"]) else 1.0
                 sel = np.ix_(act, tpred)
-                for i, j in _stage_pairs(op):
+                for i, j in _stage_pairs(op, int(st["nbits"])):
                     a, b = TP[:, sidx[:, i]][sel], TP[:, sidx[:, j]][sel]
                     la, lb = TL[:, sidx[:, i]][sel], TL[:, sidx[:, j]][sel]
                     if int(op["pgate"]) >= 0:
