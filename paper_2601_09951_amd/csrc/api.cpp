@@ -213,7 +213,7 @@ int forward(Context *ctx, Circ *C, int64_t B, const double *theta, double2 *psi,
         const PassPlan &pp = fp->passes[i];
         const TileGeom *gd = reinterpret_cast<const TileGeom *>(fp->geoms.p) + i;
         if (pp.stage_count > 0 && !ctx->no_stages)
-            rc = hip_check(ctx, launch_forward_staged(pp, fp->stage_bits, gd, reinterpret_cast<const StageDesc *>(fp->stages.p),
+            rc = hip_check(ctx, launch_forward_staged(pp, pp.stage_bits, gd, reinterpret_cast<const StageDesc *>(fp->stages.p),
                                                       reinterpret_cast<const StageOp *>(fp->sops.p), mats, G, psi,
                                                       B, ctx->wg_max, s),
                            "forward pass (staged)");
@@ -281,7 +281,7 @@ int energy_grad_into(Context *ctx, Circ *C, int n_hams, Ham *const *H, int64_t B
         const PassPlan &p = rp->passes[i];
         const TileGeom *gd = reinterpret_cast<const TileGeom *>(rp->geoms.p) + i;
         if (p.stage_count > 0 && !ctx->no_stages)
-            rc = hip_check(ctx, launch_reverse_staged(p, rp->stage_bits, gd, reinterpret_cast<const StageDesc *>(rp->stages.p),
+            rc = hip_check(ctx, launch_reverse_staged(p, p.stage_bits, gd, reinterpret_cast<const StageDesc *>(rp->stages.p),
                                                       reinterpret_cast<const StageOp *>(rp->sops.p), mats, G, psi,
                                                       lam, B, L.W_rev, pg, C->n_pgates, s),
                            "reverse pass (staged)");

@@ -155,11 +155,12 @@ struct PassPlan {
     int op_begin = 0, op_count = 0;
     int n_param_ops = 0;     // parametric ops in this pass (reverse plans)
     int stage_begin = 0, stage_count = 0;  // register stages (k >= kStageMinK)
+    int stage_bits = 0;                     // register bits of this pass's stages
 };
 
 struct CircPlan {
     int k = 0, c = 0;
-    int stage_bits = 0;
+    int stage_bits = 0;      // preferred register bits (a pass widens to its widest gate)
     bool reverse = false;
     std::vector<PassPlan> passes;
     DevMem ops;              // OpDesc[]

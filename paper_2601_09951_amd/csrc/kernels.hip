@@ -901,6 +901,7 @@ hipError_t launch_forward_staged(const PassPlan &pp, int stage_bits, const TileG
     const int64_t tiles = 1ll << g.nout;
     const int W = (int)std::min<int64_t>(tiles, wg_max);
     const size_t lds = fwd_lds(g) + stage_ctl_bytes(pp.stage_count, pp.op_count);
+    if (stage_bits != 3 && stage_bits != 4) return hipErrorInvalidValue;
     auto kern = stage_bits == 4 ? k_forward_staged<4> : k_forward_staged<3>;
     hipError_t e = ensure_lds(kern, lds);
     if (e != hipSuccess) return e;
@@ -917,6 +918,7 @@ hipError_t launch_reverse_staged(const PassPlan &pp, int stage_bits, const TileG
     const TileGeom &g = pp.geom;
     const int64_t tiles = 1ll << g.nout;
     const size_t lds = rev_lds(g, pp.n_param_ops) + stage_ctl_bytes(pp.stage_count, pp.op_count);
+    if (stage_bits != 3 && stage_bits != 4) return hipErrorInvalidValue;
     auto kern = stage_bits == 4 ? k_reverse_staged<4> : k_reverse_staged<3>;
     hipError_t e = ensure_lds(kern, lds);
     if (e != hipSuccess) return e;

@@ -187,9 +187,13 @@ static void free_plan(Context *ctx, CircPlan *p)
 // `nbits` bits.  An op needs its flip bits in registers; its controls may
 // be anywhere (register, other tile bits or outside the tile).  An op may
 // move ahead of skipped ops only if it shares no tile bit with them.
-static void build_stages(const Circ *C, const std::vector<int> &take, const std::vector<int> &tile,
+static bool build_stages(const Circ *C, const std::vector<int> &take, const std::vector<int> &tile,
                          int keff, int nbits, CircPlan *plan, PassPlan &pp)
 {
+    // the stage width must hold the widest gate of the pass
+    for (int g : take) nbits = std::max(nbits, popc(C->gates[g].m));
+    if (nbits > 4 || nbits > keff) return false;
+    pp.stage_bits = nbits;
     const uint64_t tmask = mask_of(tile);
     struct Loc {
         uint32_t m, first, cin, cvin;
@@ -223,6 +227,7 @@ static void build_stages(const Circ *C, const std::vector<int> &take, const std:
                 blocked |= touched;
             }
         }
+        if (st.empty()) return false;  // cannot happen once nbits >= every gate's width
         // pad the register set to exactly nbits bits
         for (int b = 0; b < keff && popc(R) < nbits; ++b) R |= 1u << b;
         std::vector<int> rbits, cbits;
@@ -275,6 +280,7 @@ static void build_stages(const Circ *C, const std::vector<int> &take, const std:
         plan->host_stages.push_back(sd);
     }
     pp.stage_count = (int)plan->host_stages.size() - pp.stage_begin;
+    return true;
 }
 
 CircPlan *get_circ_plan(Circ *C, bool reverse, int k, int c, int *rc)
@@ -363,7 +369,17 @@ CircPlan *get_circ_plan(Circ *C, bool reverse, int k, int c, int *rc)
             done[g] = 1;
             --remaining;
         }
-        if (keff >= kStageMinK) build_stages(C, take, tile, keff, plan->stage_bits, plan.get(), pp);
+        if (keff >= kStageMinK) {
+            const size_t st0 = plan->host_stages.size(), so0 = plan->host_sops.size();
+            if (!build_stages(C, take, tile, keff, plan->stage_bits, plan.get(), pp)) {
+                // no register stages for this pass: the one-op-per-round-trip kernel runs it
+                plan->host_stages.resize(st0);
+                plan->host_sops.resize(so0);
+                pp.stage_begin = (int)st0;
+                pp.stage_count = 0;
+                pp.stage_bits = 0;
+            }
+        }
         plan->passes.push_back(pp);
     }
     if (!ops.empty()) {
