@@ -45,6 +45,10 @@ def parse():
     ap.add_argument("--no-hea", action="store_true")
     ap.add_argument("--hea-n", type=int, default=24)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--served-requests", type=int, default=400)
+    ap.add_argument("--served-rates", type=str, default="1.0",
+                    help="comma-separated multiples of the measured plain-path capacity")
     return ap.parse_args()
 
 
@@ -186,6 +190,11 @@ def main():
     if not args.no_hea:
         out["hea"] = hea_measure(ctx, vqe, synth, torch, args.hea_n)
 
+    # -------------------------------------------------- served stream
+    if not args.no_served:
+        out["served"] = served_measure(ctx, args.served_requests,
+                                       tuple(float(x) for x in args.served_rates.split(",")))
+
     # -------------------------------------------------- CPU baseline
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(problems, args.cpu_seconds)
@@ -255,6 +264,37 @@ def hea_measure(ctx, vqe, synth, torch, n):
             "expect_sweeps": int(len(pl["sweeps"])), "ms_expect": round(ms_exp, 3),
             "expect_sweep_GBps": round(sweep_gbps, 1),
             "expect_sweep_frac_of_hbm": round(sweep_gbps / HBM_PEAK_GBPS, 4)}
+
+
+def served_measure(ctx, count, rates=(1.0,)):
+    """The served mix (n in 4..24 with weights 40/25/15/10/6/4 %, energy-only or
+    energy + gradient 50/50): the plain path (arrival order, one request per
+    launch sequence, host sync each) sets the capacity; the continuous-batching
+    server then serves Poisson arrivals at multiples of that capacity."""
+    import synth
+    from paper_2601_09951_amd import serve
+    reqs = synth.served_requests(count, 1000.0, seed=synth.MASTER_SEED + 5)
+    serve.run_plain(ctx, reqs[:20], realtime=False)  # warm plans and code objects
+    t0 = time.perf_counter()
+    plain = serve.run_plain(ctx, reqs, realtime=False)
+    plain_wall = time.perf_counter() - t0
+    capacity = count / plain_wall
+    out = {"requests": count, "plain_capacity_evals_per_s": round(capacity, 1), "rates": []}
+    ex = serve.LibvqeExecutor(ctx)
+    srv = serve.Server(ex, mem_budget=32 << 30, max_batch=128)
+    srv.run(synth.served_requests(40, 1000.0, seed=synth.MASTER_SEED + 6), realtime=False)  # warm
+    for mult in rates:
+        rate = mult * capacity
+        rq = synth.served_requests(count, rate, seed=synth.MASTER_SEED + 5)
+        res = srv.run(rq)
+        s = serve.latency_summary(res)
+        # the same arrival trace through the plain path
+        pres = serve.run_plain(ctx, rq)
+        ps = serve.latency_summary(pres)
+        out["rates"].append({"rate_x_plain_capacity": mult, "offered_per_s": round(rate, 1),
+                             "served": s, "plain": {k: ps[k] for k in ("p50_ms", "p99_ms", "evals_per_s")}})
+    ex.close()
+    return out
 
 
 def cpu_baseline(problems, budget_s):

@@ -401,3 +401,66 @@ def random_state(n: int, seed: int) -> np.ndarray:
     rng = np.random.Generator(np.random.PCG64(seed))
     v = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
     return v / np.linalg.norm(v)
+
+
+# ---------------------------------------------------------------------------
+# served request stream
+# ---------------------------------------------------------------------------
+@dataclasses.dataclass
+class Request:
+    """One served evaluation: a state size, an ansatz, a Hamiltonian, parameters.
+
+    Exactly one of ``integrals`` (chemistry models, mapped by the consumer) and
+    ``pauli`` (random strings) is set.  ``arrival`` is seconds after the start.
+    """
+
+    rid: int
+    n: int
+    want_grad: bool
+    circuit: Circuit
+    theta: np.ndarray
+    arrival: float
+    integrals: Integrals = None
+    pauli: PauliSum = None
+
+
+SERVED_MIX = ((4, 0.40), (8, 0.25), (12, 0.15), (16, 0.10), (20, 0.06), (24, 0.04))
+
+
+def served_requests(count: int, rate: float, seed: int = MASTER_SEED, mix=SERVED_MIX,
+                    hea_layers: int = 4):
+    """A Poisson stream of ``count`` requests at ``rate`` per second.
+
+    n drawn from ``mix``; n = 4 and 8 use the smooth integral models at a
+    random bond length (HF + DoubleExcitation, HF + all excitations), larger n
+    use a hardware-efficient ansatz with ``hea_layers`` layers and T ~ U{15..500}
+    random Pauli strings; parameters U(-pi, pi) (zero-centred small angles for
+    the chemistry models); energy-only or energy + gradient with probability 1/2.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ns = np.array([m[0] for m in mix])
+    ps = np.array([m[1] for m in mix], dtype=float)
+    ps = ps / ps.sum()
+    models = {4: smooth_integral_model(2, seed=seed), 8: smooth_integral_model(4, seed=seed)}
+    circuits = {4: h2_circuit(), 8: ucc_circuit(8, 2)}
+    t = 0.0
+    out = []
+    for rid in range(count):
+        t += float(rng.exponential(1.0 / rate))
+        n = int(rng.choice(ns, p=ps))
+        want_grad = bool(rng.random() < 0.5)
+        sub = int(rng.integers(0, 2 ** 31))
+        if n in models:
+            d = float(rng.uniform(0.3, 3.0))
+            circ = circuits[n]
+            theta = np.random.Generator(np.random.PCG64(sub)).uniform(-0.5, 0.5, size=circ.n_params)
+            out.append(Request(rid, n, want_grad, circ, theta, t, integrals=models[n].at(d)))
+        else:
+            if n not in circuits:
+                circuits[n] = hea_circuit(n, hea_layers)
+            circ = circuits[n]
+            T = int(rng.integers(15, 501))
+            ham = random_pauli_sum(n, T, seed=sub)
+            theta = uniform_thetas(circ.n_params, 1, seed=sub + 1)[0]
+            out.append(Request(rid, n, want_grad, circ, theta, t, pauli=ham))
+    return out
