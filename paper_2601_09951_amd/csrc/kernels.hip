@@ -655,92 +655,139 @@ __global__ __launch_bounds__(kThreads) void k_reverse_staged(
 // (kappa_t = w_t or i w_t, sigma_t(b ^ f) = sigma_t(b) (-1)^{ny_t}).
 // The sign from index bits outside the tile, (-1)^{z_t . base}, is folded
 // into w_t per tile.
-__device__ __forceinline__ void term_sums(const TermDev *__restrict__ terms, int tb, int tm,
-                                          int te, uint64_t base, uint32_t b, double &A,
-                                          double &B)
+// sign flip of a double by the parity of popcount(z & b): the parity bit is
+// moved to the sign position of the high word (integer ops only)
+__device__ __forceinline__ double signed_by_parity(double w, uint32_t zb)
 {
-    A = 0.0;
-    B = 0.0;
-    for (int t = tb; t < tm; ++t) {
-        const TermDev d = terms[t];
-        const int s = (__popcll(d.zfull & base) + __popc(d.zloc & b)) & 1;
-        A += s ? -d.w : d.w;
-    }
-    for (int t = tm; t < te; ++t) {
-        const TermDev d = terms[t];
-        const int s = (__popcll(d.zfull & base) + __popc(d.zloc & b)) & 1;
-        B += s ? -d.w : d.w;
-    }
+    const uint32_t flip = (uint32_t)__popc(zb) << 31;
+    return __hiloint2double(__double2hiint(w) ^ (int)flip, __double2loint(w));
 }
 
+// RP pairs per thread at a time share each term read
+template <bool HPSI, int RP>
 __global__ __launch_bounds__(kThreads) void k_pauli_sweep(
     const TileGeom *__restrict__ gp, int n, int k, int c, int nout,
     const GroupDev *__restrict__ groups, int ngroups,
     const int32_t *__restrict__ toff, int n_ugroups, const TermDev *__restrict__ terms,
     int shared_ham, const double2 *__restrict__ psi, double2 *__restrict__ lam, int64_t tiles,
-    int first, int last, double *__restrict__ partials, int n_slots, int slot)
+    int first, int last, double *__restrict__ partials, int n_slots, int slot, int tcap)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const bool hpsi = lam != nullptr;
     double2 *tp = reinterpret_cast<double2 *>(smem);
     double2 *tl = tp + (1u << k);
-    uint64_t *hoff = reinterpret_cast<uint64_t *>(smem + ((hpsi ? 32u : 16u) << k));
+    uint64_t *hoff = reinterpret_cast<uint64_t *>(smem + ((HPSI ? 32u : 16u) << k));
     double *red = reinterpret_cast<double *>(hoff + (1u << (k - c)));
+    uint64_t *zf = reinterpret_cast<uint64_t *>(red + 4);
+    double *w0 = reinterpret_cast<double *>(zf + tcap);
+    double *wl = w0 + tcap;
+    uint32_t *zl = reinterpret_cast<uint32_t *>(wl + tcap);
     const int tid = threadIdx.x;
     const uint64_t dim = 1ull << n;
     const int inst = blockIdx.y;
     const double2 *sp = psi + (uint64_t)inst * dim;
-    double2 *sl = hpsi ? lam + (uint64_t)inst * dim : nullptr;
+    double2 *sl = HPSI ? lam + (uint64_t)inst * dim : nullptr;
     const int32_t *to = toff + (size_t)(shared_ham ? 0 : inst) * n_ugroups * 3;
     const int T = 1 << k;
     const uint32_t lowm = (1u << c) - 1u;
+    // this sweep's terms for this instance are one contiguous range
+    const int tstart = to[groups[0].ugroup * 3];
+    const int nt = to[groups[ngroups - 1].ugroup * 3 + 2] - tstart;
+    const bool staged = nt <= tcap;
     fill_hoff(gp, k, c, hoff);
+    if (staged)
+        for (int i = tid; i < nt; i += kThreads) {
+            const TermDev d = terms[tstart + i];
+            zf[i] = d.zfull;
+            zl[i] = d.zloc;
+            w0[i] = d.w;
+        }
     __syncthreads();
     double acc = 0.0;
     for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
         const uint64_t base = tile_base(gp, nout, t);
         for (int j = tid; j < T; j += kThreads) {
             tp[j] = sp[base + hoff[j >> c] + (j & lowm)];
-            if (hpsi) tl[j] = make_double2(0.0, 0.0);
+            if (HPSI) tl[j] = make_double2(0.0, 0.0);
         }
+        if (staged)  // fold the sign of the bits outside the tile into the weights
+            for (int i = tid; i < nt; i += kThreads)
+                wl[i] = signed_by_parity(w0[i], (uint32_t)(__popcll(zf[i] & base) & 1));
         __syncthreads();
         for (int q = 0; q < ngroups; ++q) {
             const GroupDev gd = groups[q];
             const int tb = to[gd.ugroup * 3 + 0], tm = to[gd.ugroup * 3 + 1], te = to[gd.ugroup * 3 + 2];
             if (te == tb) continue;
-            if (gd.floc == 0) {
-                for (int j = tid; j < T; j += kThreads) {
-                    double A, B;
-                    term_sums(terms, tb, tm, te, base, (uint32_t)j, A, B);
-                    const double2 a = tp[j];
-                    if (hpsi)
-                        tl[j] = cadd(tl[j], make_double2(A * a.x, A * a.y));
-                    else
-                        acc += (a.x * a.x + a.y * a.y) * A;
+            const bool diag = gd.floc == 0;
+            const int npos = diag ? T : (T >> 1);
+            const uint32_t pv = gd.pivot;
+            for (int j0 = 0; j0 < npos; j0 += RP * kThreads) {
+                uint32_t b[RP];
+                double A[RP], B[RP];
+                bool ok[RP];
+#pragma unroll
+                for (int r = 0; r < RP; ++r) {
+                    const int j = j0 + r * kThreads + tid;
+                    ok[r] = j < npos;
+                    const uint32_t jj = ok[r] ? (uint32_t)j : 0u;
+                    b[r] = diag ? jj : (((jj >> pv) << (pv + 1)) | (jj & ((1u << pv) - 1u)));
+                    A[r] = 0.0;
+                    B[r] = 0.0;
                 }
-            } else {
-                const uint32_t pv = gd.pivot;
-                for (int j = tid; j < (T >> 1); j += kThreads) {
-                    const uint32_t b = (((uint32_t)j >> pv) << (pv + 1)) | ((uint32_t)j & ((1u << pv) - 1u));
-                    const uint32_t bf = b ^ gd.floc;
-                    double A, B;
-                    term_sums(terms, tb, tm, te, base, b, A, B);
-                    const double2 x0 = tp[b], x1 = tp[bf];
-                    if (hpsi) {
-                        // lam[bf] += (A + iB) x0 ; lam[b] += (A - iB) x1
-                        tl[bf] = cadd(tl[bf], make_double2(A * x0.x - B * x0.y, A * x0.y + B * x0.x));
-                        tl[b] = cadd(tl[b], make_double2(A * x1.x + B * x1.y, A * x1.y - B * x1.x));
+                if (staged) {
+                    for (int i = tb - tstart; i < tm - tstart; ++i) {
+                        const uint32_t z = zl[i];
+                        const double w = wl[i];
+#pragma unroll
+                        for (int r = 0; r < RP; ++r) A[r] += signed_by_parity(w, z & b[r]);
+                    }
+                    for (int i = tm - tstart; i < te - tstart; ++i) {
+                        const uint32_t z = zl[i];
+                        const double w = wl[i];
+#pragma unroll
+                        for (int r = 0; r < RP; ++r) B[r] += signed_by_parity(w, z & b[r]);
+                    }
+                } else {
+                    for (int i = tb; i < te; ++i) {
+                        const TermDev d = terms[i];
+                        const double w = signed_by_parity(d.w, (uint32_t)(__popcll(d.zfull & base) & 1));
+#pragma unroll
+                        for (int r = 0; r < RP; ++r) {
+                            const double v = signed_by_parity(w, d.zloc & b[r]);
+                            if (i < tm)
+                                A[r] += v;
+                            else
+                                B[r] += v;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < RP; ++r) {
+                    if (!ok[r]) continue;
+                    if (diag) {
+                        const double2 a = tp[b[r]];
+                        if (HPSI)
+                            tl[b[r]] = cadd(tl[b[r]], make_double2(A[r] * a.x, A[r] * a.y));
+                        else
+                            acc += (a.x * a.x + a.y * a.y) * A[r];
                     } else {
-                        // w = conj(x1) x0
-                        const double wr = x1.x * x0.x + x1.y * x0.y;
-                        const double wi = x1.x * x0.y - x1.y * x0.x;
-                        acc += 2.0 * (wr * A - wi * B);
+                        const uint32_t bf = b[r] ^ gd.floc;
+                        const double2 x0 = tp[b[r]], x1 = tp[bf];
+                        if (HPSI) {
+                            // lam[bf] += (A + iB) x0 ; lam[b] += (A - iB) x1
+                            tl[bf] = cadd(tl[bf], make_double2(A[r] * x0.x - B[r] * x0.y, A[r] * x0.y + B[r] * x0.x));
+                            tl[b[r]] = cadd(tl[b[r]], make_double2(A[r] * x1.x + B[r] * x1.y, A[r] * x1.y - B[r] * x1.x));
+                        } else {
+                            // w = conj(x1) x0
+                            const double wr = x1.x * x0.x + x1.y * x0.y;
+                            const double wi = x1.x * x0.y - x1.y * x0.x;
+                            acc += 2.0 * (wr * A[r] - wi * B[r]);
+                        }
                     }
                 }
             }
             __syncthreads();
         }
-        if (hpsi) {
+        if (HPSI) {
             for (int j = tid; j < T; j += kThreads) {
                 const uint64_t gi = base + hoff[j >> c] + (j & lowm);
                 double2 v = tl[j];
@@ -754,7 +801,7 @@ __global__ __launch_bounds__(kThreads) void k_pauli_sweep(
             __syncthreads();
         }
     }
-    if (!hpsi || last) {
+    if (!HPSI || last) {
         const double s = block_sum(acc, red);
         if (tid == 0) partials[((size_t)inst * n_slots + slot) * gridDim.x + blockIdx.x] = s;
     }
@@ -928,6 +975,9 @@ hipError_t launch_reverse_staged(const PassPlan &pp, int stage_bits, const TileG
     return hipGetLastError();
 }
 
+static constexpr size_t kLdsLimit = 160 * 1024;
+static constexpr size_t kTermBytes = 28;  // zfull + w + folded w + zloc
+
 hipError_t launch_pauli_sweep(const SweepPlan &sp, const PauliPlan &pp, int sweep_idx,
                               const double2 *psi, double2 *lam, int64_t batch, int shared_ham,
                               int wg_per_inst, double *partials, int n_slots, bool write_lambda,
@@ -935,16 +985,28 @@ hipError_t launch_pauli_sweep(const SweepPlan &sp, const PauliPlan &pp, int swee
 {
     const TileGeom &g = sp.geom;
     const int64_t tiles = 1ll << g.nout;
-    const size_t lds = ((write_lambda ? 32u : 16u) << g.k) + (8u << (g.k - g.c)) + 64;
-    hipError_t e = ensure_lds(k_pauli_sweep, lds);
+    const size_t base = ((write_lambda ? 32u : 16u) << g.k) + (8u << (g.k - g.c)) + 64;
+    // stage up to tcap terms; keep two workgroups per CU when the tile allows it
+    size_t budget = base + 64 * kTermBytes + 16 <= kLdsLimit / 2 ? kLdsLimit / 2 : kLdsLimit;
+    int tcap = (int)std::min<size_t>(2048, (budget - std::min(budget, base)) / kTermBytes);
+    if (tcap < 64) tcap = (int)std::min<size_t>(2048, (kLdsLimit - std::min(kLdsLimit, base)) / kTermBytes);
+    const size_t lds = base + (size_t)tcap * kTermBytes + 16;
+    const bool big = g.k >= 11;
+    void (*kern)(const TileGeom *, int, int, int, int, const GroupDev *, int, const int32_t *, int,
+                 const TermDev *, int, const double2 *, double2 *, int64_t, int, int, double *, int, int, int);
+    if (write_lambda)
+        kern = big ? k_pauli_sweep<true, 4> : k_pauli_sweep<true, 1>;
+    else
+        kern = big ? k_pauli_sweep<false, 4> : k_pauli_sweep<false, 1>;
+    hipError_t e = ensure_lds(kern, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_pauli_sweep, dim3(wg_per_inst, (unsigned)batch), dim3(kThreads), lds, s,
+    hipLaunchKernelGGL(kern, dim3(wg_per_inst, (unsigned)batch), dim3(kThreads), lds, s,
                        reinterpret_cast<const TileGeom *>(pp.geoms.p) + sweep_idx, g.n, g.k, g.c, g.nout,
                        reinterpret_cast<const GroupDev *>(pp.groups.p) + sp.grp_begin, sp.grp_count,
                        reinterpret_cast<const int32_t *>(pp.toff.p), pp.n_ugroups,
                        reinterpret_cast<const TermDev *>(pp.terms.p), shared_ham, psi,
                        write_lambda ? lam : nullptr, tiles, (int)first, (int)last, partials,
-                       n_slots, write_lambda ? 0 : sweep_idx);
+                       n_slots, write_lambda ? 0 : sweep_idx, tcap);
     return hipGetLastError();
 }
 

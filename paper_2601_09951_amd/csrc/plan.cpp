@@ -490,6 +490,21 @@ PauliPlan *get_pauli_plan(Context *ctx, int n_hams, Ham *const *hams, int n_inst
         }
     }
 
+    // renumber the union groups in sweep order, so that every sweep's terms
+    // form one contiguous range per instance
+    {
+        std::vector<uint64_t> nf;
+        std::vector<int> nsweep;
+        for (size_t s = 0; s < sweep_tiles.size(); ++s)
+            for (int &g : sweep_groups[s]) {
+                nf.push_back(flips[g]);
+                nsweep.push_back((int)s);
+                g = (int)nf.size() - 1;
+            }
+        flips.swap(nf);
+        sweep_of.assign(nsweep.begin(), nsweep.end());
+    }
+
     std::vector<GroupDev> gdev;
     for (size_t s = 0; s < sweep_tiles.size(); ++s) {
         SweepPlan sp;
