@@ -46,6 +46,11 @@ def parse():
     ap.add_argument("--hea-n", type=int, default=24)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-c1", action="store_true")
+    ap.add_argument("--scaling", type=str, default="",
+                    help="comma-separated qubit counts for the hardware-efficient scaling leg (L = n, 500 strings)")
+    ap.add_argument("--large", action="store_true",
+                    help="30-qubit energy + gradient and 32-qubit energy (L = 4, 2000 strings)")
     ap.add_argument("--served-requests", type=int, default=400)
     ap.add_argument("--served-rates", type=str, default="1.0",
                     help="comma-separated multiples of the measured plain-path capacity")
@@ -190,6 +195,14 @@ def main():
     if not args.no_hea:
         out["hea"] = hea_measure(ctx, vqe, synth, torch, args.hea_n)
 
+    # -------------------------------------------------- C1: plain vs batched
+    if not args.no_c1:
+        out["c1"] = c1_measure(ctx, vqe, synth, torch)
+    if args.scaling:
+        out["scaling"] = [scaling_measure(ctx, vqe, synth, torch, int(v)) for v in args.scaling.split(",")]
+    if args.large:
+        out["large"] = large_measure(ctx, vqe, synth, torch)
+
     # -------------------------------------------------- served stream
     if not args.no_served:
         out["served"] = served_measure(ctx, args.served_requests,
@@ -264,6 +277,98 @@ def hea_measure(ctx, vqe, synth, torch, n):
             "expect_sweeps": int(len(pl["sweeps"])), "ms_expect": round(ms_exp, 3),
             "expect_sweep_GBps": round(sweep_gbps, 1),
             "expect_sweep_frac_of_hbm": round(sweep_gbps / HBM_PEAK_GBPS, 4)}
+
+
+def c1_measure(ctx, vqe, synth, torch):
+    """The 4-qubit H2-like model: 100 energy-only theta points and 50
+    gradient-descent steps (lr 0.2), once one instance per launch sequence with
+    a host synchronisation per evaluation (the plain path), once batched /
+    persistent."""
+    dev = torch.device("cuda:0")
+    ints = synth.random_integrals(2, seed=synth.MASTER_SEED)
+    C = vqe.Circuit.from_spec(ctx, synth.h2_circuit())
+    H = vqe.Hamiltonian.from_integrals(ctx, ints.h1, ints.h2)
+    thetas = synth.theta_grid(100)
+    ws = vqe.workspace(ctx, C, H, 1, 0)
+    wsg = vqe.workspace(ctx, C, H, 1, 1)
+    for _ in range(3):
+        vqe.energy(ctx, C, H, torch.zeros(1, 1, dtype=torch.float64, device=dev), ws=ws).item()
+    t0 = time.perf_counter()
+    for t in thetas:
+        vqe.energy(ctx, C, H, torch.full((1, 1), float(t), dtype=torch.float64, device=dev), ws=ws).item()
+    plain_points = time.perf_counter() - t0
+    th_all = torch.tensor(thetas[:, None], dtype=torch.float64, device=dev)
+    vqe.energy(ctx, C, H, th_all)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    vqe.energy(ctx, C, H, th_all).cpu()
+    batched_points = time.perf_counter() - t0
+    # 50 GD steps: plain = energy_grad + host update per step
+    th = 0.0
+    t0 = time.perf_counter()
+    for _ in range(50):
+        e, g = vqe.energy_grad(ctx, C, H, torch.full((1, 1), th, dtype=torch.float64, device=dev), ws=wsg)
+        th -= 0.2 * g.item()
+    plain_gd = time.perf_counter() - t0
+    tt = torch.zeros(1, 1, dtype=torch.float64, device=dev)
+    vqe.run(ctx, C, H, tt, 50, optimizer="gd", lr=0.2)
+    torch.cuda.synchronize()
+    tt.zero_()
+    t0 = time.perf_counter()
+    traj = vqe.run(ctx, C, H, tt, 50, optimizer="gd", lr=0.2).cpu()
+    persistent_gd = time.perf_counter() - t0
+    return {"theta_points": 100, "plain_evals_per_s": round(100 / plain_points, 1),
+            "batched_evals_per_s": round(100 / batched_points, 1),
+            "gd_steps": 50, "plain_gd_ms_per_step": round(plain_gd / 50 * 1e3, 4),
+            "persistent_gd_ms_per_step": round(persistent_gd / 50 * 1e3, 4),
+            "gd_final_energy": round(float(traj[0, -1]), 12)}
+
+
+def _hea_eval(ctx, vqe, synth, torch, n, layers, terms, batch, want_grad, reps=3):
+    dev = torch.device("cuda:0")
+    spec = synth.hea_circuit(n, layers)
+    ham = synth.random_pauli_sum(n, terms, seed=synth.MASTER_SEED + n)
+    C = vqe.Circuit.from_spec(ctx, spec)
+    H = vqe.Hamiltonian.from_sum(ctx, ham)
+    th = torch.tensor(synth.uniform_thetas(spec.n_params, batch, seed=synth.MASTER_SEED + n), device=dev)
+    ws = vqe.workspace(ctx, C, H, batch, 1 if want_grad else 0)
+    call = (lambda: vqe.energy_grad(ctx, C, H, th, ws=ws)) if want_grad else (lambda: vqe.energy(ctx, C, H, th, ws=ws))
+    call()
+    torch.cuda.synchronize()
+    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s0.record()
+    for _ in range(reps):
+        call()
+    s1.record()
+    torch.cuda.synchronize()
+    ms = s0.elapsed_time(s1) / reps
+    del ws
+    torch.cuda.empty_cache()
+    return ms, spec, H
+
+
+def scaling_measure(ctx, vqe, synth, torch, n):
+    """Energy + adjoint gradient of the hardware-efficient ansatz, L = n layers,
+    500 random strings; batches of 8 and 32 where the states are small."""
+    ms, spec, H = _hea_eval(ctx, vqe, synth, torch, n, n, 500, 1, True, reps=2 if n >= 24 else 3)
+    out = {"n": n, "gates": spec.n_gates, "params": spec.n_params, "flip_groups": int(H.n_groups),
+           "ms_per_energy_grad": round(ms, 3)}
+    if n <= 20:
+        for B in (8, 32):
+            msb, _, _ = _hea_eval(ctx, vqe, synth, torch, n, n, 500, B, True)
+            out[f"batch{B}_evals_per_s"] = round(B / (msb * 1e-3), 2)
+    return out
+
+
+def large_measure(ctx, vqe, synth, torch):
+    """30 qubits energy + gradient (two resident 16 GiB states) and 32 qubits
+    energy only (one 64 GiB state); hardware-efficient ansatz with 4 layers,
+    2000 random strings."""
+    ms30, spec30, H30 = _hea_eval(ctx, vqe, synth, torch, 30, 4, 2000, 1, True, reps=1)
+    ms32, spec32, H32 = _hea_eval(ctx, vqe, synth, torch, 32, 4, 2000, 1, False, reps=1)
+    return {"n30_energy_grad_s": round(ms30 * 1e-3, 3), "n30_flip_groups": int(H30.n_groups),
+            "n32_energy_s": round(ms32 * 1e-3, 3), "n32_flip_groups": int(H32.n_groups),
+            "n32_state_GiB": 64}
 
 
 def served_measure(ctx, count, rates=(1.0,)):
