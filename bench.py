@@ -116,21 +116,26 @@ def main():
     for n_orb, spec in ((2, synth.h2_circuit()), (4, synth.ucc_circuit(8, 2))):
         model = synth.smooth_integral_model(n_orb, seed=synth.MASTER_SEED)
         ints = [model.at(float(d)) for d in ds]
-        hams = [vqe.Hamiltonian.from_integrals(ctx, i.h1, i.h2, i.e_core) for i in ints]
+        # S0 on the device: the Jordan-Wigner map of Eq. (3) is built once per
+        # orbital count; each scan evaluates H(d_i) for all bond lengths on the GPU
+        fam = vqe.HamFamily(ctx, n_orb, BATCH)
+        ints_dev = torch.tensor(vqe.HamFamily.pack(ints), dtype=torch.float64, device=dev)  # resident input
+        hams = fam.members(BATCH)
         C = vqe.Circuit.from_spec(ctx, spec)
         theta = torch.zeros(BATCH, spec.n_params, dtype=torch.float64, device=dev)
         ws = vqe.workspace(ctx, C, hams, BATCH, 2)
         energies = torch.empty(BATCH, ITERS + 1, dtype=torch.float64, device=dev)
-        problems.append(dict(n=spec.n, spec=spec, ints=ints, hams=hams, C=C, theta=theta, ws=ws,
-                             energies=energies))
+        problems.append(dict(n=spec.n, spec=spec, ints=ints, ints_dev=ints_dev, fam=fam, hams=hams, C=C,
+                             theta=theta, ws=ws, energies=energies))
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
 
     def one_scan(events=None):
         for i, p in enumerate(problems):
-            p["theta"].zero_()
             if events is not None:
                 events[i][0].record(stream)
+            p["fam"].set_integrals(p["ints_dev"])      # S0: H(d_i) for every bond length
+            p["theta"].zero_()                          # theta_0 = 0
             vqe.run(ctx, p["C"], p["hams"], p["theta"], ITERS, ws=p["ws"], energies=p["energies"])
             if events is not None:
                 events[i][1].record(stream)
@@ -161,7 +166,8 @@ def main():
     flops_eval = eval_flops(p8["spec"], len(c), n_groups, n_diag)
     flops_launch = flops_eval * BATCH * ITERS
     achieved = flops_launch / (kernel_ms[8] * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": "k_small_run (8 qubits, 100 instances x 200 steps)",
+    roofline = {"bound": "alu", "kernel": "k_small_run (8 qubits, 100 instances x 200 steps; the event "
+                                          "interval also holds the H(d) build and theta reset, < 1 %)",
                 "achieved": round(achieved, 4), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP64_PEAK_TFLOPS, 5), "traffic": None,
                 "flops_per_eval": flops_eval, "kernel_ms": round(kernel_ms[8], 4)}
@@ -181,12 +187,14 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "batched PES scan: 100 bond lengths x 200 Adam steps, 4-qubit H2-like "
-                               "(15 terms) and 8-qubit all-excitations (UCC) models, complex128",
+                               "(15 terms) and 8-qubit all-excitations (UCC) models, complex128; each step "
+                               "builds H(d_i) on the device (Jordan-Wigner map) and runs the full loop",
                    "global_batch": BATCH, "iterations": ITERS, "qubits": [4, 8],
                    "evals_per_step": len(problems) * BATCH * ITERS},
         "kernel_ms": {f"{k}q": round(v, 4) for k, v in kernel_ms.items()},
         "setup": {"seconds": round(setup_s, 3),
-                  "what": "host Jordan-Wigner of 200 Hamiltonians + device upload + plans (outside timing)"},
+                  "what": "once per orbital count (outside timing): symbolic Jordan-Wigner map, circuit and "
+                          "Hamiltonian plans, workspace; each timed step builds all 200 H(d_i) on the device"},
         "roofline": roofline,
         "pes_min_energy": {f"{k}q": round(float(np.min(v)), 10) for k, v in final_e.items()},
     }

@@ -162,6 +162,38 @@ int vqe_ham_terms(vqe_ham_t ham, uint64_t *xmask, uint64_t *zmask, double *coeff
 
 int vqe_ham_destroy(vqe_ham_t ham);
 
+/* ---- Hamiltonian families (Eq. 3 for many integral sets, on the device) --
+ * The Jordan-Wigner coefficients of Eq. (3) are linear in the integrals.  A
+ * family holds that linear map for n_orb spatial orbitals (built once on the
+ * host) and device storage for the coefficients of `capacity` members; the
+ * coefficients of any set of members are then computed on the device from
+ * integrals already in device memory (one sparse product per member, no
+ * host round trip), which is how a potential-energy scan builds H(d_i) for
+ * every bond length.  Integrals must be symmetric (h1 symmetric, h2 with the
+ * 8-fold permutational symmetry); the map reads one entry per symmetry
+ * class. */
+typedef struct vqe_hfam *vqe_hfam_t;
+
+int vqe_hfam_create(vqe_ctx_t ctx, int n_orb, int64_t capacity, vqe_hfam_t *out);
+
+/* qubits (2 n_orb), Pauli strings of the map, integral inputs per member
+ * (1 + n_orb^2 + n_orb^4, laid out {e_core, h1[n_orb][n_orb], h2[n_orb]^4}). */
+int vqe_hfam_info(vqe_hfam_t fam, int *n_qubits, int64_t *n_terms, int64_t *n_inputs);
+
+/* A Hamiltonian handle for member `index` (0 <= index < capacity): its strings
+ * are the family's, its coefficients the member's device row.  Usable
+ * wherever a vqe_ham_t is taken; all Hamiltonians of one call must come from
+ * one family or from none.  Destroy members before their family. */
+int vqe_hfam_member(vqe_hfam_t fam, int64_t index, vqe_ham_t *out);
+
+/* Coefficients of members [first, first + count) from device integrals
+ * float64 [count][n_inputs]; enqueued on `stream`.  Calls on the same stream
+ * that evaluate these members see the new coefficients. */
+int vqe_hfam_set_integrals(vqe_ctx_t ctx, vqe_hfam_t fam, int64_t first, int64_t count,
+                           const double *integrals, void *stream);
+
+int vqe_hfam_destroy(vqe_hfam_t fam);
+
 /* ---- circuits (the ansatz U(theta) of Eq. 4) --------------------------- */
 
 /* A gate list applied in order.  kind[g] is a VQE_GATE_* code; wires is the

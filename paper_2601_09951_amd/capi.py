@@ -33,6 +33,7 @@ EXPORTED = [
     "vqe_prepare_reference", "vqe_apply_ansatz", "vqe_expect", "vqe_energy",
     "vqe_apply_hamiltonian", "vqe_energy_grad", "vqe_adam_step", "vqe_run",
     "vqe_circ_plan_export", "vqe_ham_plan_export",
+    "vqe_hfam_create", "vqe_hfam_info", "vqe_hfam_member", "vqe_hfam_set_integrals", "vqe_hfam_destroy",
 ]
 
 
@@ -80,6 +81,11 @@ def _declare(L):
         "vqe_run": [P, P, i32, P, i64, u64, P, i32, i32, f64, f64, f64, f64, P, P, sz, P],
         "vqe_circ_plan_export": [P, P, i32, P, sz, ctypes.POINTER(sz)],
         "vqe_ham_plan_export": [P, i32, P, i64, i32, P, sz, ctypes.POINTER(sz)],
+        "vqe_hfam_create": [P, i32, i64, PP],
+        "vqe_hfam_info": [P, P, P, P],
+        "vqe_hfam_member": [P, i64, PP],
+        "vqe_hfam_set_integrals": [P, P, i64, i64, P, P],
+        "vqe_hfam_destroy": [P],
     }
     for name, args in sig.items():
         f = getattr(L, name)

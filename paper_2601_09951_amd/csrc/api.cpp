@@ -197,6 +197,17 @@ int layout_for(Context *ctx, Circ *C, int n_hams, Ham *const *H, int64_t B, int 
     return VQE_OK;
 }
 
+// plans over family members take their weights from the family's device coefficients
+int refresh_weights(Context *ctx, PauliPlan *pp, hipStream_t s)
+{
+    if (!pp->fam) return VQE_OK;
+    return hip_check(ctx, launch_refresh_weights(reinterpret_cast<const WeightSrc *>(pp->wsrc.p),
+                                                 reinterpret_cast<const double *>(pp->fam->d_coef.p),
+                                                 reinterpret_cast<TermDev *>(pp->terms.p),
+                                                 (int64_t)pp->host_terms.size(), s),
+                     "refresh weights");
+}
+
 int forward(Context *ctx, Circ *C, int64_t B, const double *theta, double2 *psi, double2 *mats,
             hipStream_t s)
 {
@@ -235,6 +246,8 @@ int expect_into(Context *ctx, int n_hams, Ham *const *H, int64_t B, const double
     const int n_inst = n_hams == 1 ? 1 : (int)B;
     PauliPlan *pp = get_pauli_plan(ctx, n_hams, H, n_inst, ctx->k_fwd, ctx->c_low, &rc);
     if (!pp) return rc;
+    rc = refresh_weights(ctx, pp, s);
+    if (rc) return rc;
     const int W = wg_for(ctx, n, ctx->k_fwd);
     const int S = (int)pp->sweeps.size();
     for (int i = 0; i < S; ++i) {
@@ -262,6 +275,8 @@ int energy_grad_into(Context *ctx, Circ *C, int n_hams, Ham *const *H, int64_t B
     if (!pp) return rc;
     CircPlan *rp = get_circ_plan(C, true, ctx->k_rev, ctx->c_low, &rc);
     if (!rp) return rc;
+    rc = refresh_weights(ctx, pp, s);
+    if (rc) return rc;
 
     rc = hip_check(ctx, launch_prepare(psi, n, B, ref, s), "prepare");
     if (rc) return rc;
@@ -358,6 +373,7 @@ int vqe_ctx_destroy(vqe_ctx_t ctx)
     for (auto &kv : ctx->pauli_cache) {
         dev_free(ctx, kv.second->groups);
             dev_free(ctx, kv.second->geoms);
+            dev_free(ctx, kv.second->wsrc);
         dev_free(ctx, kv.second->toff);
         dev_free(ctx, kv.second->terms);
     }
@@ -388,6 +404,7 @@ int vqe_ctx_set_tile(vqe_ctx_t ctx, int k_fwd, int k_rev, int c_low)
         for (auto &kv : ctx->pauli_cache) {
             dev_free(ctx, kv.second->groups);
             dev_free(ctx, kv.second->geoms);
+            dev_free(ctx, kv.second->wsrc);
             dev_free(ctx, kv.second->toff);
             dev_free(ctx, kv.second->terms);
         }
@@ -512,7 +529,115 @@ int vqe_ham_terms(vqe_ham_t ham, uint64_t *xmask, uint64_t *zmask, double *coeff
     if (!ham || !xmask || !zmask || !coeff) return VQE_EINVAL;
     std::memcpy(xmask, ham->x.data(), ham->x.size() * 8);
     std::memcpy(zmask, ham->z.data(), ham->z.size() * 8);
+    if (ham->fam && ham->fam->d_coef.p) {  // device-resident coefficients of a family member
+        Context *ctx = ham->ctx;
+        int rc = check_ctx(ctx);
+        if (rc) return rc;
+        const double *src = reinterpret_cast<const double *>(ham->fam->d_coef.p) + ham->member * (int64_t)ham->x.size();
+        return hip_check(ctx, hipMemcpy(coeff, src, ham->x.size() * 8, hipMemcpyDeviceToHost), "copy coefficients");
+    }
     std::memcpy(coeff, ham->c.data(), ham->c.size() * 8);
+    return VQE_OK;
+}
+
+// ---------------------------------------------------------------------------
+int vqe_hfam_create(vqe_ctx_t ctx, int n_orb, int64_t capacity, vqe_hfam_t *out)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!out || capacity < 1) return set_err(ctx, VQE_EINVAL, "out is NULL or capacity < 1");
+    *out = nullptr;
+    if (n_orb < 1 || 2 * n_orb > VQE_MAX_QUBITS) return set_err(ctx, VQE_EUNSUPPORTED, "2 * n_orb outside [2, 34]");
+    vqe_hfam *f = new (std::nothrow) vqe_hfam();
+    if (!f) return set_err(ctx, VQE_ENOMEM, "host allocation");
+    f->ctx = ctx;
+    f->n_orb = n_orb;
+    f->n = 2 * n_orb;
+    f->n_inputs = 1 + (int64_t)n_orb * n_orb + (int64_t)n_orb * n_orb * n_orb * n_orb;
+    f->capacity = capacity;
+    std::string err;
+    rc = jordan_wigner_linear(n_orb, f->x, f->z, f->row_off, f->col, f->val, err);
+    if (rc) {
+        delete f;
+        return set_err(ctx, rc, err);
+    }
+    const size_t T = f->x.size();
+    rc = upload(ctx, f->d_row, f->row_off.data(), f->row_off.size() * 8);
+    if (!rc) rc = upload(ctx, f->d_col, f->col.data(), f->col.size() * 4);
+    if (!rc) rc = upload(ctx, f->d_val, f->val.data(), f->val.size() * 8);
+    if (!rc && ctx->device >= 0) {
+        rc = dev_alloc(ctx, f->d_coef, (size_t)capacity * T * 8);
+        if (!rc) rc = hip_check(ctx, launch_fill((double *)f->d_coef.p, capacity * (int64_t)T, 0.0, nullptr), "zero");
+        if (!rc) rc = hip_check(ctx, hipDeviceSynchronize(), "zero coefficients");
+    }
+    if (rc) {
+        dev_free(ctx, f->d_row);
+        dev_free(ctx, f->d_col);
+        dev_free(ctx, f->d_val);
+        dev_free(ctx, f->d_coef);
+        delete f;
+        return rc;
+    }
+    *out = f;
+    return VQE_OK;
+}
+
+int vqe_hfam_info(vqe_hfam_t fam, int *n_qubits, int64_t *n_terms, int64_t *n_inputs)
+{
+    if (!fam) return VQE_EINVAL;
+    if (n_qubits) *n_qubits = fam->n;
+    if (n_terms) *n_terms = (int64_t)fam->x.size();
+    if (n_inputs) *n_inputs = fam->n_inputs;
+    return VQE_OK;
+}
+
+int vqe_hfam_member(vqe_hfam_t fam, int64_t index, vqe_ham_t *out)
+{
+    if (!fam || !out) return VQE_EINVAL;
+    Context *ctx = fam->ctx;
+    *out = nullptr;
+    if (index < 0 || index >= fam->capacity) return set_err(ctx, VQE_EINVAL, "member index outside the family");
+    vqe_ham *h = new (std::nothrow) vqe_ham();
+    if (!h) return set_err(ctx, VQE_ENOMEM, "host allocation");
+    h->n = fam->n;
+    h->x = fam->x;
+    h->z = fam->z;
+    h->c.assign(fam->x.size(), 0.0);
+    h->fam = fam;
+    h->member = index;
+    return ham_finish(static_cast<vqe_ctx_t>(ctx), h, out);
+}
+
+int vqe_hfam_set_integrals(vqe_ctx_t ctx, vqe_hfam_t fam, int64_t first, int64_t count, const double *integrals,
+                           void *stream)
+{
+    int rc = check_dev(ctx);
+    if (rc) return rc;
+    if (!fam || fam->ctx != ctx || !integrals || first < 0 || count < 1 || first + count > fam->capacity)
+        return set_err(ctx, VQE_EINVAL, "bad family range or pointer");
+    const int64_t T = (int64_t)fam->x.size();
+    return hip_check(ctx, launch_family_coeffs(reinterpret_cast<const int64_t *>(fam->d_row.p),
+                                               reinterpret_cast<const int32_t *>(fam->d_col.p),
+                                               reinterpret_cast<const double *>(fam->d_val.p), T, integrals,
+                                               fam->n_inputs, count,
+                                               reinterpret_cast<double *>(fam->d_coef.p) + first * T,
+                                               (hipStream_t)stream),
+                     "family coefficients");
+}
+
+int vqe_hfam_destroy(vqe_hfam_t fam)
+{
+    if (!fam) return VQE_EINVAL;
+    Context *ctx = fam->ctx;
+    if (ctx->device >= 0) {
+        (void)hipSetDevice(ctx->device);
+        (void)hipDeviceSynchronize();
+    }
+    dev_free(ctx, fam->d_row);
+    dev_free(ctx, fam->d_col);
+    dev_free(ctx, fam->d_val);
+    dev_free(ctx, fam->d_coef);
+    delete fam;
     return VQE_OK;
 }
 
@@ -544,6 +669,7 @@ int vqe_ham_destroy(vqe_ham_t ham)
                 }
                 dev_free(ctx, it->second->groups);
                 dev_free(ctx, it->second->geoms);
+                dev_free(ctx, it->second->wsrc);
                 dev_free(ctx, it->second->toff);
                 dev_free(ctx, it->second->terms);
                 it = ctx->pauli_cache.erase(it);
@@ -712,6 +838,8 @@ int vqe_apply_hamiltonian(vqe_ctx_t ctx, int n_hams, const vqe_ham_t *hams, int6
     const int n_inst = n_hams == 1 ? 1 : (int)batch;
     PauliPlan *pp = get_pauli_plan(ctx, n_hams, H.data(), n_inst, ctx->k_rev, ctx->c_low, &rc);
     if (!pp) return rc;
+    rc = refresh_weights(ctx, pp, (hipStream_t)stream);
+    if (rc) return rc;
     const int W = wg_for(ctx, n, ctx->k_rev);
     void *part;
     rc = scratch_get(ctx, (size_t)batch * W * 8, &part);
@@ -855,6 +983,8 @@ int vqe_run(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams, i
             a.theta = theta;
             a.energies = energies;
             a.work = nullptr;
+            rc = refresh_weights(ctx, pp, s);
+            if (rc) return rc;
             return hip_check(ctx, launch_small_run(a, reinterpret_cast<const OpDesc *>(rp->ops.p),
                                                    reinterpret_cast<const int32_t *>(circ->pmap_off.p),
                                                    reinterpret_cast<const int32_t *>(circ->pmap_idx.p),

@@ -126,13 +126,36 @@ struct DevMem {
 
 struct Context;
 
+struct HamFamily;
+
 struct Ham {
     Context *ctx = nullptr;
     int n = 0;
     uint64_t id = 0;
     std::vector<uint64_t> x, z;  // merged, sorted by (x, z)
-    std::vector<double> c;
+    std::vector<double> c;       // host coefficients (zeros for family members)
     int64_t n_groups = 0;
+    HamFamily *fam = nullptr;    // set for members whose coefficients live on the device
+    int64_t member = -1;
+};
+
+// Jordan-Wigner image of Eq. (3) as a linear map integrals -> coefficients,
+// with device storage for the coefficients of `capacity` members.
+struct HamFamily {
+    Context *ctx = nullptr;
+    int n_orb = 0, n = 0;
+    int64_t n_inputs = 0, capacity = 0;
+    std::vector<uint64_t> x, z;
+    std::vector<int64_t> row_off;
+    std::vector<int32_t> col;
+    std::vector<double> val;
+    DevMem d_row, d_col, d_val, d_coef;  // coefficients: double [capacity][T]
+};
+
+// Source of a plan term's weight for family members: w = sgn * coef[idx].
+struct WeightSrc {
+    int64_t idx;
+    double sgn;
 };
 
 struct GateHost {
@@ -203,6 +226,8 @@ struct PauliPlan {
     std::vector<int32_t> host_toff;
     std::vector<TermDev> host_terms;
     int max_terms_group = 0;
+    const HamFamily *fam = nullptr;  // weights refreshed from the family's device coefficients
+    DevMem wsrc;                     // WeightSrc[terms] when fam is set
 };
 
 struct Context {
@@ -236,6 +261,9 @@ int jordan_wigner(int n_orb, const double *h1, const double *h2, double e_core,
                   std::string &err);
 void merge_terms(std::vector<uint64_t> &x, std::vector<uint64_t> &z, std::vector<double> &c,
                  double drop);
+int jordan_wigner_linear(int n_orb, std::vector<uint64_t> &xo, std::vector<uint64_t> &zo,
+                         std::vector<int64_t> &row_off, std::vector<int32_t> &col,
+                         std::vector<double> &val, std::string &err);
 
 // plan.cpp
 int build_circuit_gates(Circ *C, int64_t n_gates, const int32_t *kind, const int32_t *wires,
@@ -279,6 +307,11 @@ hipError_t launch_adam(int64_t count, double *theta, double *m, double *v, const
                        int t, double lr, double b1, double b2, double eps, hipStream_t s);
 hipError_t launch_gd(int64_t count, double *theta, const double *g, double lr, hipStream_t s);
 hipError_t launch_fill(double *p, int64_t count, double value, hipStream_t s);
+hipError_t launch_family_coeffs(const int64_t *row_off, const int32_t *col, const double *val, int64_t n_terms,
+                                const double *ints, int64_t n_inputs, int64_t count, double *coef,
+                                hipStream_t s);
+hipError_t launch_refresh_weights(const WeightSrc *src, const double *coef, TermDev *terms, int64_t n,
+                                  hipStream_t s);
 
 // small-state persistent loop (kernels_small.hip)
 struct SmallRunArgs {
@@ -306,3 +339,4 @@ int small_run_plan(int n, int n_gates, int n_params, int n_pgates, int n_groups,
 struct vqe_ctx : vqe::Context {};
 struct vqe_ham : vqe::Ham {};
 struct vqe_circ : vqe::Circ {};
+struct vqe_hfam : vqe::HamFamily {};

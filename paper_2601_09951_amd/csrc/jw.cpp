@@ -181,4 +181,102 @@ int jordan_wigner(int n_orb, const double *h1, const double *h2, double e_core,
     return VQE_OK;
 }
 
+// The same expansion with the integrals kept symbolic: every Pauli string's
+// coefficient is a linear form in the integral entries.  Entries are
+// numbered in the input layout {e_core, h1[n][n], h2[n][n][n][n]}, and every
+// entry is mapped to the first entry of its symmetry class (h1 symmetric,
+// h2 with the 8-fold permutational symmetry), so the imaginary parts of the
+// weights cancel and the map is real for symmetric integrals.
+int jordan_wigner_linear(int n_orb, std::vector<uint64_t> &xo, std::vector<uint64_t> &zo,
+                         std::vector<int64_t> &row_off, std::vector<int32_t> &col,
+                         std::vector<double> &val, std::string &err)
+{
+    const int M = 2 * n_orb;
+    const int n = M;
+    const int64_t n1 = (int64_t)n_orb * n_orb;
+    auto h1_index = [&](int p, int q) {
+        if (q < p) std::swap(p, q);
+        return (int32_t)(1 + (int64_t)p * n_orb + q);
+    };
+    auto h2_index = [&](int p, int q, int r, int s) {
+        int cand[8][4] = {{p, q, r, s}, {q, p, r, s}, {p, q, s, r}, {q, p, s, r},
+                          {r, s, p, q}, {s, r, p, q}, {r, s, q, p}, {s, r, q, p}};
+        int64_t best = -1;
+        for (auto &c : cand) {
+            int64_t v = (((int64_t)c[0] * n_orb + c[1]) * n_orb + c[2]) * n_orb + c[3];
+            if (best < 0 || v < best) best = v;
+        }
+        return (int32_t)(1 + n1 + best);
+    };
+    std::unordered_map<std::pair<uint64_t, uint64_t>, std::unordered_map<int32_t, cd>, KeyHash> acc;
+    auto add = [&](const PStr &s, int32_t e, double scale) { acc[{s.x, s.z}][e] += s.c * scale; };
+    add({0, 0, cd(1, 0)}, 0, 1.0);
+
+    PStr lp[2], lq[2], lr[2], ls[2];
+    for (int P = 0; P < M; ++P) {
+        ladder(n, P, true, lp);
+        for (int Q = 0; Q < M; ++Q) {
+            if ((P & 1) != (Q & 1)) continue;
+            ladder(n, Q, false, lq);
+            const int32_t e = h1_index(P / 2, Q / 2);
+            for (auto &a : lp)
+                for (auto &b : lq) add(mul(a, b), e, 1.0);
+        }
+    }
+    for (int P = 0; P < M; ++P) {
+        ladder(n, P, true, lp);
+        for (int Q = 0; Q < M; ++Q) {
+            if (Q == P) continue;
+            ladder(n, Q, true, lq);
+            PStr pq[4];
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) pq[2 * a + b] = mul(lp[a], lq[b]);
+            for (int R = 0; R < M; ++R) {
+                if ((R & 1) != (Q & 1)) continue;
+                ladder(n, R, false, lr);
+                for (int S = 0; S < M; ++S) {
+                    if (S == R || (S & 1) != (P & 1)) continue;
+                    ladder(n, S, false, ls);
+                    const int32_t e = h2_index(P / 2, S / 2, Q / 2, R / 2);
+                    for (auto &ab : pq)
+                        for (auto &c3 : lr) {
+                            PStr t = mul(ab, c3);
+                            for (auto &d : ls) add(mul(t, d), e, 0.5);
+                        }
+                }
+            }
+        }
+    }
+    // deterministic order: strings by (x, z), entries ascending
+    std::vector<std::pair<uint64_t, uint64_t>> keys;
+    for (auto &kv : acc) keys.push_back(kv.first);
+    std::sort(keys.begin(), keys.end());
+    xo.clear();
+    zo.clear();
+    row_off.assign(1, 0);
+    col.clear();
+    val.clear();
+    for (auto &k : keys) {
+        std::vector<std::pair<int32_t, double>> row;
+        for (auto &ev : acc[k]) {
+            const cd w = ev.second;
+            if (std::fabs(w.imag()) > 1e-12) {
+                err = "internal error: non-real symbolic Jordan-Wigner weight";
+                return VQE_EINVAL;
+            }
+            if (std::fabs(w.real()) > 1e-14) row.push_back({ev.first, w.real()});
+        }
+        if (row.empty()) continue;
+        std::sort(row.begin(), row.end());
+        xo.push_back(k.first);
+        zo.push_back(k.second);
+        for (auto &r : row) {
+            col.push_back(r.first);
+            val.push_back(r.second);
+        }
+        row_off.push_back((int64_t)col.size());
+    }
+    return VQE_OK;
+}
+
 }  // namespace vqe

@@ -869,6 +869,29 @@ __global__ void k_fill(double *__restrict__ p, int64_t count, double value)
         p[i] = value;
 }
 
+// Eq. (3) through the Jordan-Wigner map, on the device: for each member i and
+// string t, coef[i][t] = sum_k val[k] * ints[i][col[k]] over row t.
+__global__ void k_family_coeffs(const int64_t *__restrict__ row_off, const int32_t *__restrict__ col,
+                                const double *__restrict__ val, int64_t n_terms, const double *__restrict__ ints,
+                                int64_t n_inputs, int64_t count, double *__restrict__ coef)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count * n_terms;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t m = i / n_terms, t = i - m * n_terms;
+        const double *v = ints + m * n_inputs;
+        double s = 0.0;
+        for (int64_t k = row_off[t]; k < row_off[t + 1]; ++k) s += val[k] * v[col[k]];
+        coef[i] = s;
+    }
+}
+
+__global__ void k_refresh_weights(const WeightSrc *__restrict__ src, const double *__restrict__ coef,
+                                  TermDev *__restrict__ terms, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        terms[i].w = src[i].sgn * coef[src[i].idx];
+}
+
 inline int grid_for(int64_t n, int block) { return (int)std::min<int64_t>((n + block - 1) / block, 1 << 20); }
 
 template <typename K>
@@ -1042,6 +1065,23 @@ hipError_t launch_gd(int64_t count, double *theta, const double *g, double lr, h
 {
     if (count == 0) return hipSuccess;
     hipLaunchKernelGGL(k_gd, dim3(grid_for(count, 256)), dim3(256), 0, s, count, theta, g, lr);
+    return hipGetLastError();
+}
+
+hipError_t launch_family_coeffs(const int64_t *row_off, const int32_t *col, const double *val, int64_t n_terms,
+                                const double *ints, int64_t n_inputs, int64_t count, double *coef, hipStream_t s)
+{
+    if (count * n_terms == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_family_coeffs, dim3(grid_for(count * n_terms, 256)), dim3(256), 0, s, row_off, col, val,
+                       n_terms, ints, n_inputs, count, coef);
+    return hipGetLastError();
+}
+
+hipError_t launch_refresh_weights(const WeightSrc *src, const double *coef, TermDev *terms, int64_t n,
+                                  hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_refresh_weights, dim3(grid_for(n, 256)), dim3(256), 0, s, src, coef, terms, n);
     return hipGetLastError();
 }
 

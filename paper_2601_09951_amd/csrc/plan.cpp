@@ -426,6 +426,7 @@ PauliPlan *get_pauli_plan(Context *ctx, int n_hams, Ham *const *hams, int n_inst
         if (ctx->device >= 0) (void)hipDeviceSynchronize();
         for (auto &kv : ctx->pauli_cache) {
             dev_free(ctx, kv.second->geoms);
+            dev_free(ctx, kv.second->wsrc);
             dev_free(ctx, kv.second->groups);
             dev_free(ctx, kv.second->toff);
             dev_free(ctx, kv.second->terms);
@@ -523,6 +524,13 @@ PauliPlan *get_pauli_plan(Context *ctx, int n_hams, Ham *const *hams, int n_inst
     }
 
     // per-instance term tables, grouped by union group, real terms first
+    const HamFamily *fam = hams[0]->fam;
+    for (int i = 0; i < n_hams; ++i)
+        if (hams[i]->fam != fam) {  // a plan draws device weights from one family at most
+            *rc = VQE_EUNSUPPORTED;
+            return nullptr;
+        }
+    std::vector<WeightSrc> wsrc;
     std::vector<int32_t> toff((size_t)n_inst * flips.size() * 3, 0);
     std::vector<TermDev> terms;
     for (int i = 0; i < n_inst; ++i) {
@@ -550,6 +558,7 @@ PauliPlan *get_pauli_plan(Context *ctx, int n_hams, Ham *const *hams, int n_inst
                     // kappa = i w with w = c (-1)^{(ny-1)/2} (ny odd)
                     int e = pass == 0 ? ny / 2 : (ny - 1) / 2;
                     d.w = (e & 1) ? -H->c[t] : H->c[t];
+                    if (fam) wsrc.push_back({H->member * (int64_t)fam->x.size() + (int64_t)t, (e & 1) ? -1.0 : 1.0});
                     terms.push_back(d);
                     ++cnt;
                 }
@@ -565,9 +574,14 @@ PauliPlan *get_pauli_plan(Context *ctx, int n_hams, Ham *const *hams, int n_inst
     if (!r) r = upload(ctx, plan->geoms, sgeoms.data(), sgeoms.size() * sizeof(TileGeom));
     if (!r) r = upload(ctx, plan->toff, toff.data(), toff.size() * sizeof(int32_t));
     if (!r && !terms.empty()) r = upload(ctx, plan->terms, terms.data(), terms.size() * sizeof(TermDev));
+    if (!r && fam) {
+        plan->fam = fam;
+        r = upload(ctx, plan->wsrc, wsrc.data(), wsrc.size() * sizeof(WeightSrc));
+    }
     if (r) {
         dev_free(ctx, plan->groups);
         dev_free(ctx, plan->geoms);
+        dev_free(ctx, plan->wsrc);
         dev_free(ctx, plan->toff);
         dev_free(ctx, plan->terms);
         *rc = r;

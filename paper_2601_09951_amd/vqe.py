@@ -145,6 +145,59 @@ class Hamiltonian:
             pass
 
 
+class HamFamily:
+    """Eq. (3) for many integral sets: the Jordan-Wigner map integrals ->
+    coefficients, with member Hamiltonians whose coefficients live on the device."""
+
+    def __init__(self, ctx: Context, n_orb: int, capacity: int):
+        h = _P()
+        ctx.check(lib().vqe_hfam_create(ctx.handle, int(n_orb), int(capacity), ctypes.byref(h)))
+        self.ctx = ctx
+        self._h = h
+        self.n_orb = int(n_orb)
+        self.capacity = int(capacity)
+        nq, nt, ni = ctypes.c_int(), ctypes.c_int64(), ctypes.c_int64()
+        ctx.check(lib().vqe_hfam_info(h, ctypes.byref(nq), ctypes.byref(nt), ctypes.byref(ni)))
+        self.n_qubits, self.n_terms, self.n_inputs = nq.value, nt.value, ni.value
+        self._members = []
+
+    def member(self, index: int) -> "Hamiltonian":
+        h = _P()
+        self.ctx.check(lib().vqe_hfam_member(self._h, int(index), ctypes.byref(h)))
+        m = Hamiltonian(self.ctx, h)
+        self._members.append(m)
+        return m
+
+    def members(self, count: int, first: int = 0):
+        return [self.member(first + i) for i in range(count)]
+
+    @staticmethod
+    def pack(integrals) -> np.ndarray:
+        """[count, 1 + n^2 + n^4] float64 rows {e_core, h1, h2} from objects with h1, h2, e_core."""
+        return np.stack([np.concatenate([[float(i.e_core)], np.asarray(i.h1, dtype=np.float64).ravel(),
+                                         np.asarray(i.h2, dtype=np.float64).ravel()]) for i in integrals])
+
+    def set_integrals(self, ints: torch.Tensor, first: int = 0):
+        """Coefficients of members [first, first + len(ints)) from device integrals."""
+        _check_tensor(ints, torch.float64, (ints.shape[0], self.n_inputs), "integrals")
+        self.ctx.check(lib().vqe_hfam_set_integrals(self.ctx.handle, self._h, int(first), int(ints.shape[0]),
+                                                    _ptr(ints), _stream(ints.device)))
+
+    def close(self):
+        for m in self._members:
+            m.close()
+        self._members = []
+        if self._h:
+            lib().vqe_hfam_destroy(self._h)
+            self._h = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Circuit:
     """An ansatz gate list compiled by the library (vqe_circ_t)."""
 

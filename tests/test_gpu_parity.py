@@ -287,3 +287,50 @@ def test_persistent_loop_hamiltonian_forms(vqe, ctx, n, T, L, iters):
         for mode in (0, 1):
             np.testing.assert_allclose(out[mode][0][b], want, atol=E_TOL)
             np.testing.assert_allclose(out[mode][1][b], tho, atol=1e-7)
+
+
+@pytest.mark.parametrize("n_orb,zero", [(2, True), (3, False), (4, False)])
+def test_family_coefficients_on_device_match_oracle(vqe, ctx, n_orb, zero):
+    # Eq. (3) -> Jordan-Wigner as a device sparse product vs the oracle's dense build
+    _say("family", n_orb)
+    ints = [synth.random_integrals(n_orb, seed=70 + i, zero_odd_parity=zero) for i in range(3)]
+    for i, it in enumerate(ints):
+        it.e_core = 0.1 * i
+    fam = vqe.HamFamily(ctx, n_orb, 3)
+    fam.set_integrals(dev(vqe.HamFamily.pack(ints)))
+    torch.cuda.synchronize()
+    for i, it in enumerate(ints):
+        x, z, c = fam.member(i).terms()
+        got = {(int(a), int(b)): v for a, b, v in zip(x, z, c) if abs(v) > 1e-14}
+        ref = fermion.qubit_hamiltonian(it)
+        want = {(int(a), int(b)): v for a, b, v in zip(ref.xmask, ref.zmask, ref.coeff)}
+        assert got.keys() == want.keys()
+        for k in want:
+            assert abs(got[k] - want[k]) < 1e-13
+    fam.close()
+
+
+def test_family_pes_run_matches_oracle(vqe, ctx):
+    _say("family pes")
+    B, iters = 100, 200
+    model = synth.smooth_integral_model(4, seed=synth.MASTER_SEED)
+    ints = [model.at(float(d)) for d in synth.bond_grid(B)]
+    spec = synth.ucc_circuit(8, 2)
+    C = vqe.Circuit.from_spec(ctx, spec)
+    fam = vqe.HamFamily(ctx, 4, B)
+    fam.set_integrals(dev(vqe.HamFamily.pack(ints)))
+    hams = fam.members(B)
+    th = dev(np.zeros((B, spec.n_params)))
+    traj = vqe.run(ctx, C, hams, th, iters).cpu().numpy()
+    # new integrals into the same members: the next call sees them
+    ints2 = [model.at(float(d) + 0.05) for d in synth.bond_grid(B)]
+    fam.set_integrals(dev(vqe.HamFamily.pack(ints2)))
+    th2 = dev(np.zeros((B, spec.n_params)))
+    traj2 = vqe.run(ctx, C, hams, th2, 20).cpu().numpy()
+    for b in (0, 37, 99):
+        want, _ = oracle.vqe_run(spec, fermion.qubit_hamiltonian(ints[b]), np.zeros(spec.n_params), iters)
+        np.testing.assert_allclose(traj[b], want, atol=E_TOL)
+        want2, _ = oracle.vqe_run(spec, fermion.qubit_hamiltonian(ints2[b]), np.zeros(spec.n_params), 20)
+        np.testing.assert_allclose(traj2[b], want2, atol=E_TOL)
+    del hams
+    fam.close()
