@@ -260,6 +260,7 @@ __global__ __launch_bounds__(256) void k_small_run(SmallKernelArgs ka)
     }
     __syncthreads();
 
+    double b1t = 1.0, b2t = 1.0;  // beta1^t, beta2^t for Adam's bias corrections
     for (int it = 0; it <= a.iters; ++it) {
         // gate matrices at the current parameters; reference state
         for (int g = tid; g < G; g += bs) {
@@ -389,6 +390,8 @@ __global__ __launch_bounds__(256) void k_small_run(SmallKernelArgs ka)
             __syncthreads();
         }
         // dE/dtheta_p and the optimiser step
+        b1t *= a.b1;
+        b2t *= a.b2;
         for (int p = tid; p < P; p += bs) {
             double gp = 0.0;
             for (int e2 = ka.pmap_off[p]; e2 < ka.pmap_off[p + 1]; ++e2) {
@@ -402,8 +405,8 @@ __global__ __launch_bounds__(256) void k_small_run(SmallKernelArgs ka)
                 const double vi = a.b2 * vel[p] + (1.0 - a.b2) * gp * gp;
                 mom[p] = mi;
                 vel[p] = vi;
-                const double c1 = 1.0 - pow(a.b1, (double)(it + 1));
-                const double c2 = 1.0 - pow(a.b2, (double)(it + 1));
+                const double c1 = 1.0 - b1t;
+                const double c2 = 1.0 - b2t;
                 th[p] -= a.lr * (mi / c1) / (sqrt(vi / c2) + a.eps);
             } else {
                 th[p] -= a.lr * gp;
