@@ -213,7 +213,8 @@ int vqe_circ_destroy(vqe_circ_t circ);
 /* ---- workspace --------------------------------------------------------- */
 
 /* Bytes of device workspace that vqe_energy (want_grad = 0),
- * vqe_energy_grad (want_grad = 1) or vqe_run (want_grad = 2) needs for `batch` instances: the state, the
+ * vqe_energy_grad (want_grad = 1), vqe_run (want_grad = 2) or
+ * vqe_grad_shift (want_grad = 3) needs for `batch` instances: the state, the
  * adjoint state lambda = H psi, and small per-launch tables.  A state is
  * batch * 2^n * 16 bytes. */
 int vqe_workspace_bytes(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams,
@@ -259,6 +260,22 @@ int vqe_apply_hamiltonian(vqe_ctx_t ctx, int n_hams, const vqe_ham_t *hams, int6
 int vqe_energy_grad(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams,
                     int64_t batch, uint64_t ref_index, const double *theta, double *energy,
                     double *grad, void *workspace, size_t ws_bytes, void *stream);
+
+/* Energy and the parameter-shift gradient of Algorithm 1 (Section 4.3: two
+ * evaluations per parameter): every instance is expanded into shifted rows,
+ * gate by gate, evaluated as one batch of states (prepare, apply, expect),
+ * and combined per parameter (the chain rule sums shared parameters):
+ *   RX, RY, RZ (generator eigenvalues +-1):  [E(a + pi/2) - E(a - pi/2)] / 2
+ *   SINGLE_EXC, DOUBLE_EXC (eigenvalues -1, 0, 1):
+ *     d+ [E(a + pi/2) - E(a - pi/2)] - d- [E(a + 3pi/2) - E(a - 3pi/2)],
+ *     d+- = (sqrt2 +- 1) / (4 sqrt2).
+ * Exact for these gates, so it equals the adjoint gradient up to rounding.
+ * energy: device [batch]; grad: device [batch][n_params]; workspace: at
+ * least vqe_workspace_bytes(..., want_grad = 3).  batch times the rows per
+ * instance (1 + 2 per rotation + 4 per excitation) must not exceed 65535. */
+int vqe_grad_shift(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams, int64_t batch,
+                   uint64_t ref_index, const double *theta, double *energy, double *grad,
+                   void *workspace, size_t ws_bytes, void *stream);
 
 /* One Adam step in place (Section 3.4; Kingma-Ba with epsilon outside the
  * square root): m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,

@@ -31,7 +31,7 @@ EXPORTED = [
     "vqe_ham_create", "vqe_ham_from_integrals", "vqe_ham_info", "vqe_ham_terms", "vqe_ham_destroy",
     "vqe_circ_create", "vqe_circ_destroy", "vqe_workspace_bytes",
     "vqe_prepare_reference", "vqe_apply_ansatz", "vqe_expect", "vqe_energy",
-    "vqe_apply_hamiltonian", "vqe_energy_grad", "vqe_adam_step", "vqe_run",
+    "vqe_apply_hamiltonian", "vqe_energy_grad", "vqe_grad_shift", "vqe_adam_step", "vqe_run",
     "vqe_circ_plan_export", "vqe_ham_plan_export",
     "vqe_hfam_create", "vqe_hfam_info", "vqe_hfam_member", "vqe_hfam_set_integrals", "vqe_hfam_destroy",
 ]
@@ -77,6 +77,7 @@ def _declare(L):
         "vqe_apply_hamiltonian": [P, i32, P, i64, P, P, P],
         "vqe_energy": [P, P, i32, P, i64, u64, P, P, P, sz, P],
         "vqe_energy_grad": [P, P, i32, P, i64, u64, P, P, P, P, sz, P],
+        "vqe_grad_shift": [P, P, i32, P, i64, u64, P, P, P, P, sz, P],
         "vqe_adam_step": [P, i64, i32, P, P, P, P, i32, f64, f64, f64, f64, P],
         "vqe_run": [P, P, i32, P, i64, u64, P, i32, i32, f64, f64, f64, f64, P, P, sz, P],
         "vqe_circ_plan_export": [P, P, i32, P, sz, ctypes.POINTER(sz)],

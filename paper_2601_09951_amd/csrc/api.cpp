@@ -146,14 +146,28 @@ int wg_for(Context *ctx, int n, int k)
 }
 
 // workspace layout; want: 0 energy, 1 energy+grad, 2 run (adds optimiser state)
+int build_shift(Context *ctx, Circ *C);
+
 int layout_for(Context *ctx, Circ *C, int n_hams, Ham *const *H, int64_t B, int want, Layout &L)
 {
     int rc;
+    if (want == 3) {  // parameter shift: B * rows states, matrices, expectation partials, row energies
+        rc = build_shift(ctx, C);
+        if (rc) return rc;
+        const int64_t R = B * C->shift_rows;
+        Layout S;
+        rc = layout_for(ctx, C, n_hams, H, R, 0, S);  // rows share the instance's tables (n_hams 1 or B)
+        if (rc) return rc;
+        L = S;
+        L.etmp = L.total;
+        L.total = align_up(L.total + (size_t)R * 8);
+        return VQE_OK;
+    }
     const int n = C->n;
     const uint64_t dim = 1ull << n;
     const size_t state = (size_t)B * dim * 16;
     const int G = (int)C->gates.size();
-    const int n_inst = n_hams == 1 ? 1 : (int)B;
+    const int n_inst = n_hams;  // 1 (shared) or one table per instance
     size_t off = 0;
     L.psi = off;
     off = align_up(off + state);
@@ -251,7 +265,7 @@ int expect_into(Context *ctx, int n_hams, Ham *const *H, int64_t B, const double
     const int W = wg_for(ctx, n, ctx->k_fwd);
     const int S = (int)pp->sweeps.size();
     for (int i = 0; i < S; ++i) {
-        rc = hip_check(ctx, launch_pauli_sweep(pp->sweeps[i], *pp, i, psi, nullptr, B, n_hams == 1, W,
+        rc = hip_check(ctx, launch_pauli_sweep(pp->sweeps[i], *pp, i, psi, nullptr, B, n_hams == 1 ? 0 : 1, W,
                                                partials, S, false, i == 0, i == S - 1, s),
                        "expectation sweep");
         if (rc) return rc;
@@ -284,7 +298,7 @@ int energy_grad_into(Context *ctx, Circ *C, int n_hams, Ham *const *H, int64_t B
     if (rc) return rc;
     const int S = (int)pp->sweeps.size();
     for (int i = 0; i < S; ++i) {
-        rc = hip_check(ctx, launch_pauli_sweep(pp->sweeps[i], *pp, i, psi, lam, B, n_hams == 1, L.W_hpsi,
+        rc = hip_check(ctx, launch_pauli_sweep(pp->sweeps[i], *pp, i, psi, lam, B, n_hams == 1 ? 0 : 1, L.W_hpsi,
                                                pe, 1, true, i == 0, i == S - 1, s),
                        "H psi sweep");
         if (rc) return rc;
@@ -312,6 +326,56 @@ int energy_grad_into(Context *ctx, Circ *C, int n_hams, Ham *const *H, int64_t B
                                              reinterpret_cast<const int32_t *>(C->pmap_idx.p),
                                              C->n_params, B, grad, s),
                      "gradient reduce");
+}
+
+int build_shift(Context *ctx, Circ *C)
+{
+    if (C->shift_rows > 0) return VQE_OK;
+    const double dp = (std::sqrt(2.0) + 1.0) / (4.0 * std::sqrt(2.0));
+    const double dm = (std::sqrt(2.0) - 1.0) / (4.0 * std::sqrt(2.0));
+    const double h = 0.5 * M_PI;
+    std::vector<ShiftRow> rows(1, ShiftRow{-1, 0, 0.0});
+    std::vector<std::vector<std::pair<int32_t, double>>> per(C->n_params);
+    for (size_t g = 0; g < C->gates.size(); ++g) {
+        const GateHost &gh = C->gates[g];
+        if (gh.pidx < 0) continue;
+        auto add = [&](double shift, double coef) {
+            rows.push_back(ShiftRow{(int32_t)g, 0, shift});
+            per[gh.pidx].push_back({(int32_t)rows.size() - 1, coef});
+        };
+        if (gh.kind == VQE_GATE_SINGLE_EXC || gh.kind == VQE_GATE_DOUBLE_EXC) {
+            // generator eigenvalues {-1, 0, 1}: four-term rule
+            add(h, dp);
+            add(-h, -dp);
+            add(3 * h, -dm);
+            add(-3 * h, dm);
+        } else {
+            add(h, 0.5);
+            add(-h, -0.5);
+        }
+    }
+    std::vector<int32_t> off(C->n_params + 1, 0), row;
+    std::vector<double> coef;
+    for (int p = 0; p < C->n_params; ++p) {
+        for (auto &e : per[p]) {
+            row.push_back(e.first);
+            coef.push_back(e.second);
+        }
+        off[p + 1] = (int32_t)row.size();
+    }
+    int rc = upload(ctx, C->shift_tab, rows.data(), rows.size() * sizeof(ShiftRow));
+    if (!rc) rc = upload(ctx, C->shift_off, off.data(), off.size() * 4);
+    if (!rc && !row.empty()) rc = upload(ctx, C->shift_row, row.data(), row.size() * 4);
+    if (!rc && !coef.empty()) rc = upload(ctx, C->shift_coef, coef.data(), coef.size() * 8);
+    if (rc) {
+        dev_free(ctx, C->shift_tab);
+        dev_free(ctx, C->shift_off);
+        dev_free(ctx, C->shift_row);
+        dev_free(ctx, C->shift_coef);
+        return rc;
+    }
+    C->shift_rows = (int)rows.size();
+    return VQE_OK;
 }
 
 }  // namespace
@@ -754,6 +818,10 @@ int vqe_circ_destroy(vqe_circ_t C)
     dev_free(ctx, C->gates_dev);
     dev_free(ctx, C->pmap_off);
     dev_free(ctx, C->pmap_idx);
+    dev_free(ctx, C->shift_tab);
+    dev_free(ctx, C->shift_off);
+    dev_free(ctx, C->shift_row);
+    dev_free(ctx, C->shift_coef);
     delete C;
     return VQE_OK;
 }
@@ -763,7 +831,7 @@ int vqe_workspace_bytes(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ha
 {
     int rc = check_ctx(ctx);
     if (rc) return rc;
-    if (!circ || !bytes || batch < 1 || want_grad < 0 || want_grad > 2)
+    if (!circ || !bytes || batch < 1 || want_grad < 0 || want_grad > 3)
         return set_err(ctx, VQE_EINVAL, "bad argument");
     std::vector<Ham *> H;
     rc = check_hams(ctx, n_hams, hams, batch, circ->n, H);
@@ -847,7 +915,7 @@ int vqe_apply_hamiltonian(vqe_ctx_t ctx, int n_hams, const vqe_ham_t *hams, int6
     const int S = (int)pp->sweeps.size();
     for (int i = 0; i < S; ++i) {
         rc = hip_check(ctx, launch_pauli_sweep(pp->sweeps[i], *pp, i, (const double2 *)psi, (double2 *)out,
-                                               batch, n_hams == 1, W, (double *)part, 1, true, i == 0,
+                                               batch, n_hams == 1 ? 0 : 1, W, (double *)part, 1, true, i == 0,
                                                i == S - 1, (hipStream_t)stream),
                        "H psi sweep");
         if (rc) return rc;
@@ -899,6 +967,77 @@ int vqe_energy_grad(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t 
     if (ws_bytes < L.total) return set_err(ctx, VQE_EINVAL, "workspace too small");
     return energy_grad_into(ctx, circ, n_hams, H.data(), batch, ref_index, theta, energy, 1, grad,
                             (unsigned char *)workspace, L, (hipStream_t)stream);
+}
+
+int vqe_grad_shift(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams, int64_t batch,
+                   uint64_t ref_index, const double *theta, double *energy, double *grad, void *workspace,
+                   size_t ws_bytes, void *stream)
+{
+    int rc = check_dev(ctx);
+    if (rc) return rc;
+    if (!circ || !energy || !grad || !workspace || batch < 1 || (circ->n_params > 0 && !theta))
+        return set_err(ctx, VQE_EINVAL, "bad argument");
+    if (ref_index >> circ->n) return set_err(ctx, VQE_EINVAL, "ref_index >= 2^n");
+    std::vector<Ham *> H;
+    rc = check_hams(ctx, n_hams, hams, batch, circ->n, H);
+    if (rc) return rc;
+    rc = build_shift(ctx, circ);
+    if (rc) return rc;
+    const int R0 = circ->shift_rows;
+    const int64_t R = batch * R0;
+    if (R > kMaxBatch) return set_err(ctx, VQE_EUNSUPPORTED, "batch x shifted rows > 65535");
+    Layout L;
+    rc = layout_for(ctx, circ, n_hams, H.data(), batch, 3, L);
+    if (rc) return rc;
+    if (ws_bytes < L.total) return set_err(ctx, VQE_EINVAL, "workspace too small");
+    unsigned char *ws = (unsigned char *)workspace;
+    hipStream_t s = (hipStream_t)stream;
+    double2 *psi = (double2 *)(ws + L.psi);
+    double2 *mats = (double2 *)(ws + L.mats);
+    double *part = (double *)(ws + L.pe);
+    double *erows = (double *)(ws + L.etmp);
+    const int n = circ->n;
+    const int G = (int)circ->gates.size();
+    CircPlan *fp = get_circ_plan(circ, false, ctx->k_fwd, ctx->c_low, &rc);
+    if (!fp) return rc;
+    PauliPlan *pp = get_pauli_plan(ctx, n_hams, H.data(), n_hams, ctx->k_fwd, ctx->c_low, &rc);
+    if (!pp) return rc;
+    rc = refresh_weights(ctx, pp, s);
+    if (!rc) rc = hip_check(ctx, launch_prepare(psi, n, R, ref_index, s), "prepare");
+    if (!rc && G > 0)
+        rc = hip_check(ctx, launch_shift_mats(reinterpret_cast<const GateDev *>(circ->gates_dev.p), G, theta,
+                                              circ->n_params, batch, reinterpret_cast<const ShiftRow *>(circ->shift_tab.p),
+                                              R0, mats, s),
+                       "shifted gate matrices");
+    for (size_t i = 0; !rc && G > 0 && i < fp->passes.size(); ++i) {
+        const PassPlan &p = fp->passes[i];
+        const TileGeom *gd = reinterpret_cast<const TileGeom *>(fp->geoms.p) + i;
+        if (p.stage_count > 0 && !ctx->no_stages)
+            rc = hip_check(ctx, launch_forward_staged(p, p.stage_bits, gd, reinterpret_cast<const StageDesc *>(fp->stages.p),
+                                                      reinterpret_cast<const StageOp *>(fp->sops.p), mats, G, psi, R,
+                                                      ctx->wg_max, s),
+                           "forward pass (staged)");
+        else
+            rc = hip_check(ctx, launch_forward_pass(p, gd, reinterpret_cast<const OpDesc *>(fp->ops.p), mats, G, psi, R,
+                                                    ctx->wg_max, s),
+                           "forward pass");
+    }
+    if (rc) return rc;
+    const int W = wg_for(ctx, n, ctx->k_fwd);
+    const int S = (int)pp->sweeps.size();
+    for (int i = 0; i < S; ++i) {
+        rc = hip_check(ctx, launch_pauli_sweep(pp->sweeps[i], *pp, i, psi, nullptr, R, n_hams == 1 ? 0 : R0, W, part,
+                                               S, false, i == 0, i == S - 1, s),
+                       "expectation sweep");
+        if (rc) return rc;
+    }
+    rc = hip_check(ctx, launch_reduce_slots(part, S, W, R, erows, 1, 1.0, s), "energy reduce");
+    if (rc) return rc;
+    return hip_check(ctx, launch_shift_combine(erows, R0, reinterpret_cast<const int32_t *>(circ->shift_off.p),
+                                               reinterpret_cast<const int32_t *>(circ->shift_row.p),
+                                               reinterpret_cast<const double *>(circ->shift_coef.p), circ->n_params,
+                                               batch, energy, grad, s),
+                     "shift combine");
 }
 
 int vqe_adam_step(vqe_ctx_t ctx, int64_t batch, int32_t n_params, double *theta, double *m, double *v,

@@ -195,6 +195,15 @@ struct CircPlan {
     int max_param_ops = 0;
 };
 
+// Parameter-shift schedule of a circuit: row r of an instance evaluates the
+// circuit with gate `gate` shifted by `shift` (row 0: unshifted); parameter p's
+// derivative is sum_k coef[k] * E[row[k]] over its CSR entries.
+struct ShiftRow {
+    int32_t gate;
+    int32_t pad;
+    double shift;
+};
+
 struct Circ {
     Context *ctx = nullptr;
     int n = 0;
@@ -206,6 +215,9 @@ struct Circ {
     DevMem pmap_off, pmap_idx;       // CSR param -> pgates
     std::map<std::pair<int, int>, std::unique_ptr<CircPlan>> fwd, rev;
     uint64_t id = 0;
+    int shift_rows = 0;              // rows per instance of the parameter-shift schedule
+    DevMem shift_tab;                // ShiftRow[shift_rows]
+    DevMem shift_off, shift_row, shift_coef;  // CSR param -> (row, coefficient)
 };
 
 // Union Pauli plan for a list of Hamiltonians on one tile geometry.
@@ -294,7 +306,7 @@ hipError_t launch_reverse_pass(const PassPlan &pp, const TileGeom *geom_dev, con
                                hipStream_t s);
 hipError_t launch_pauli_sweep(const SweepPlan &sp, const PauliPlan &pp, int sweep_idx,
                               const double2 *psi, double2 *lam, int64_t batch,
-                              int shared_ham, int wg_per_inst, double *partials,
+                              int ham_div, int wg_per_inst, double *partials,
                               int n_slots, bool write_lambda, bool first, bool last,
                               hipStream_t s);
 hipError_t launch_reduce_slots(const double *partials, int n_slots, int wg_per_inst,
@@ -307,6 +319,12 @@ hipError_t launch_adam(int64_t count, double *theta, double *m, double *v, const
                        int t, double lr, double b1, double b2, double eps, hipStream_t s);
 hipError_t launch_gd(int64_t count, double *theta, const double *g, double lr, hipStream_t s);
 hipError_t launch_fill(double *p, int64_t count, double value, hipStream_t s);
+hipError_t launch_shift_mats(const GateDev *gates, int n_gates, const double *theta, int n_params,
+                             int64_t batch, const ShiftRow *rows, int rows_per_inst, double2 *mats,
+                             hipStream_t s);
+hipError_t launch_shift_combine(const double *erows, int rows_per_inst, const int32_t *off,
+                                const int32_t *row, const double *coef, int n_params, int64_t batch,
+                                double *energy, double *grad, hipStream_t s);
 hipError_t launch_family_coeffs(const int64_t *row_off, const int32_t *col, const double *val, int64_t n_terms,
                                 const double *ints, int64_t n_inputs, int64_t count, double *coef,
                                 hipStream_t s);

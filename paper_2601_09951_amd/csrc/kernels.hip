@@ -98,22 +98,13 @@ __global__ void k_prepare(double2 *__restrict__ psi, uint64_t dim_mask, uint64_t
         psi[i] = make_double2((i & dim_mask) == ref ? 1.0 : 0.0, 0.0);
 }
 
-// 2x2 matrix of gate g of instance b on its pair (first, second)
-__global__ void k_gate_mats(const GateDev *__restrict__ gates, int n_gates,
-                            const double *__restrict__ theta, int n_params, int64_t batch,
-                            double2 *__restrict__ mats)
+// 2x2 matrix of a gate on its pair (first, second) at angle a
+__device__ __forceinline__ void gate_matrix(int kind, double a, double2 *m)
 {
-    const int64_t total = batch * n_gates;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t b = i / n_gates;
-    const int g = (int)(i - b * n_gates);
-    const GateDev gd = gates[g];
-    const double a = gd.pidx >= 0 ? theta[b * n_params + gd.pidx] : gd.fixed;
     double s, c;
     sincos(0.5 * a, &s, &c);
     double2 u00 = {0, 0}, u01 = {0, 0}, u10 = {0, 0}, u11 = {0, 0};
-    switch (gd.kind) {
+    switch (kind) {
     case VQE_GATE_RX: u00 = {c, 0}; u01 = {0, -s}; u10 = {0, -s}; u11 = {c, 0}; break;
     case VQE_GATE_RY:
     case VQE_GATE_SINGLE_EXC:
@@ -128,11 +119,64 @@ __global__ void k_gate_mats(const GateDev *__restrict__ gates, int n_gates,
     case VQE_GATE_CNOT: u01 = {1, 0}; u10 = {1, 0}; break;
     case VQE_GATE_CZ: u00 = {1, 0}; u11 = {-1, 0}; break;
     }
-    double2 *m = mats + i * 4;
     m[0] = u00;
     m[1] = u01;
     m[2] = u10;
     m[3] = u11;
+}
+
+// matrices of gate g of instance b
+__global__ void k_gate_mats(const GateDev *__restrict__ gates, int n_gates,
+                            const double *__restrict__ theta, int n_params, int64_t batch,
+                            double2 *__restrict__ mats)
+{
+    const int64_t total = batch * n_gates;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = i / n_gates;
+        const int g = (int)(i - b * n_gates);
+        const GateDev gd = gates[g];
+        gate_matrix(gd.kind, gd.pidx >= 0 ? theta[b * n_params + gd.pidx] : gd.fixed, mats + i * 4);
+    }
+}
+
+// parameter-shift rows: row (b, r) evaluates instance b with gate rows[r].gate shifted
+__global__ void k_shift_mats(const GateDev *__restrict__ gates, int n_gates, const double *__restrict__ theta,
+                             int n_params, int64_t batch, const ShiftRow *__restrict__ rows, int rows_per_inst,
+                             double2 *__restrict__ mats)
+{
+    const int64_t total = batch * rows_per_inst * n_gates;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t row = i / n_gates;
+        const int g = (int)(i - row * n_gates);
+        const int64_t b = row / rows_per_inst;
+        const int r = (int)(row - b * rows_per_inst);
+        const GateDev gd = gates[g];
+        double a = gd.pidx >= 0 ? theta[b * n_params + gd.pidx] : gd.fixed;
+        if (rows[r].gate == g) a += rows[r].shift;
+        gate_matrix(gd.kind, a, mats + i * 4);
+    }
+}
+
+// energy[b] = E[b][0]; grad[b][p] = sum_k coef[k] E[b][row[k]] over p's entries
+__global__ void k_shift_combine(const double *__restrict__ erows, int rows_per_inst, const int32_t *__restrict__ off,
+                                const int32_t *__restrict__ row, const double *__restrict__ coef, int n_params,
+                                int64_t batch, double *__restrict__ energy, double *__restrict__ grad)
+{
+    const int64_t total = batch * (int64_t)(n_params + 1);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = i / (n_params + 1);
+        const int p = (int)(i - b * (n_params + 1));
+        const double *e = erows + b * rows_per_inst;
+        if (p == n_params) {
+            energy[b] = e[0];
+        } else {
+            double s = 0.0;
+            for (int k = off[p]; k < off[p + 1]; ++k) s += coef[k] * e[row[k]];
+            grad[b * n_params + p] = s;
+        }
     }
 }
 
@@ -669,7 +713,7 @@ __global__ __launch_bounds__(kThreads) void k_pauli_sweep(
     const TileGeom *__restrict__ gp, int n, int k, int c, int nout,
     const GroupDev *__restrict__ groups, int ngroups,
     const int32_t *__restrict__ toff, int n_ugroups, const TermDev *__restrict__ terms,
-    int shared_ham, const double2 *__restrict__ psi, double2 *__restrict__ lam, int64_t tiles,
+    int ham_div, const double2 *__restrict__ psi, double2 *__restrict__ lam, int64_t tiles,
     int first, int last, double *__restrict__ partials, int n_slots, int slot, int tcap)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -686,7 +730,8 @@ __global__ __launch_bounds__(kThreads) void k_pauli_sweep(
     const int inst = blockIdx.y;
     const double2 *sp = psi + (uint64_t)inst * dim;
     double2 *sl = HPSI ? lam + (uint64_t)inst * dim : nullptr;
-    const int32_t *to = toff + (size_t)(shared_ham ? 0 : inst) * n_ugroups * 3;
+    // ham_div 0: one Hamiltonian for every row; else rows [i*ham_div, (i+1)*ham_div) use table i
+    const int32_t *to = toff + (size_t)(ham_div == 0 ? 0 : inst / ham_div) * n_ugroups * 3;
     const int T = 1 << k;
     const uint32_t lowm = (1u << c) - 1u;
     // this sweep's terms for this instance are one contiguous range
@@ -1002,7 +1047,7 @@ static constexpr size_t kLdsLimit = 160 * 1024;
 static constexpr size_t kTermBytes = 28;  // zfull + w + folded w + zloc
 
 hipError_t launch_pauli_sweep(const SweepPlan &sp, const PauliPlan &pp, int sweep_idx,
-                              const double2 *psi, double2 *lam, int64_t batch, int shared_ham,
+                              const double2 *psi, double2 *lam, int64_t batch, int ham_div,
                               int wg_per_inst, double *partials, int n_slots, bool write_lambda,
                               bool first, bool last, hipStream_t s)
 {
@@ -1027,7 +1072,7 @@ hipError_t launch_pauli_sweep(const SweepPlan &sp, const PauliPlan &pp, int swee
                        reinterpret_cast<const TileGeom *>(pp.geoms.p) + sweep_idx, g.n, g.k, g.c, g.nout,
                        reinterpret_cast<const GroupDev *>(pp.groups.p) + sp.grp_begin, sp.grp_count,
                        reinterpret_cast<const int32_t *>(pp.toff.p), pp.n_ugroups,
-                       reinterpret_cast<const TermDev *>(pp.terms.p), shared_ham, psi,
+                       reinterpret_cast<const TermDev *>(pp.terms.p), ham_div, psi,
                        write_lambda ? lam : nullptr, tiles, (int)first, (int)last, partials,
                        n_slots, write_lambda ? 0 : sweep_idx, tcap);
     return hipGetLastError();
@@ -1082,6 +1127,27 @@ hipError_t launch_refresh_weights(const WeightSrc *src, const double *coef, Term
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_refresh_weights, dim3(grid_for(n, 256)), dim3(256), 0, s, src, coef, terms, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_shift_mats(const GateDev *gates, int n_gates, const double *theta, int n_params,
+                             int64_t batch, const ShiftRow *rows, int rows_per_inst, double2 *mats,
+                             hipStream_t s)
+{
+    const int64_t total = batch * rows_per_inst * n_gates;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_shift_mats, dim3(grid_for(total, 128)), dim3(128), 0, s, gates, n_gates, theta, n_params,
+                       batch, rows, rows_per_inst, mats);
+    return hipGetLastError();
+}
+
+hipError_t launch_shift_combine(const double *erows, int rows_per_inst, const int32_t *off, const int32_t *row,
+                                const double *coef, int n_params, int64_t batch, double *energy, double *grad,
+                                hipStream_t s)
+{
+    const int64_t total = batch * (int64_t)(n_params + 1);
+    hipLaunchKernelGGL(k_shift_combine, dim3(grid_for(total, 256)), dim3(256), 0, s, erows, rows_per_inst, off, row,
+                       coef, n_params, batch, energy, grad);
     return hipGetLastError();
 }
 

@@ -341,6 +341,22 @@ def energy_grad(ctx: Context, circ: Circuit, hams, theta: torch.Tensor, ref_inde
     return out_e, out_g
 
 
+def grad_shift(ctx: Context, circ: Circuit, hams, theta: torch.Tensor, ref_index: int = None,
+               ws: torch.Tensor = None):
+    """(E, dE/dtheta) by the parameter-shift rules (Algorithm 1), all shifted rows in one batch."""
+    B = theta.shape[0]
+    _check_tensor(theta, torch.float64, (B, circ.n_params), "theta")
+    arr, nh = _hams_array(hams)
+    ref = circ.ref_index if ref_index is None else ref_index
+    if ws is None:
+        ws = workspace(ctx, circ, hams, B, 3, theta.device)
+    e = torch.empty(B, dtype=torch.float64, device=theta.device)
+    g = torch.empty(B, circ.n_params, dtype=torch.float64, device=theta.device)
+    ctx.check(lib().vqe_grad_shift(ctx.handle, circ.handle, nh, arr, B, ref, _ptr(theta), _ptr(e), _ptr(g),
+                                   _ptr(ws), ws.numel(), _stream(theta.device)))
+    return e, g
+
+
 def adam_step(ctx: Context, theta: torch.Tensor, m: torch.Tensor, v: torch.Tensor, grad: torch.Tensor, t: int,
               lr: float = 0.01, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8):
     B, P = theta.shape

@@ -334,3 +334,37 @@ def test_family_pes_run_matches_oracle(vqe, ctx):
         np.testing.assert_allclose(traj2[b], want2, atol=E_TOL)
     del hams
     fam.close()
+
+
+@pytest.mark.parametrize("case", ["h2", "ucc", "random6", "hea12"])
+def test_parameter_shift_gradient_on_device(vqe, ctx, case):
+    # Algorithm 1's gradient on the device equals the oracle's parameter shift and the adjoint
+    _say("shift", case)
+    if case == "h2":
+        ints = synth.random_integrals(2, seed=synth.MASTER_SEED)
+        spec, ham = synth.h2_circuit(), fermion.qubit_hamiltonian(ints)
+        H = vqe.Hamiltonian.from_integrals(ctx, ints.h1, ints.h2)
+        th = synth.theta_grid(8)[:, None]
+    elif case == "ucc":
+        ints = synth.smooth_integral_model(4).at(0.9)
+        spec, ham = synth.ucc_circuit(8, 2), fermion.qubit_hamiltonian(ints)
+        H = vqe.Hamiltonian.from_integrals(ctx, ints.h1, ints.h2, ints.e_core)
+        th = synth.uniform_thetas(spec.n_params, 3, seed=4) * 0.4
+    elif case == "random6":
+        spec, ham = synth.random_circuit(6, 30, seed=8), synth.random_pauli_sum(6, 40, seed=8)
+        H = vqe.Hamiltonian.from_sum(ctx, ham)
+        th = synth.uniform_thetas(spec.n_params, 2, seed=8)
+    else:
+        spec, ham = synth.hea_circuit(12, 2), synth.random_pauli_sum(12, 80, seed=12)
+        H = vqe.Hamiltonian.from_sum(ctx, ham)
+        th = synth.uniform_thetas(spec.n_params, 1, seed=12)
+    C = vqe.Circuit.from_spec(ctx, spec)
+    e, g = vqe.grad_shift(ctx, C, H, dev(th))
+    ea, ga = vqe.energy_grad(ctx, C, H, dev(th))
+    torch.cuda.synchronize()
+    e, g, ea, ga = e.cpu().numpy(), g.cpu().numpy(), ea.cpu().numpy(), ga.cpu().numpy()
+    for b in range(th.shape[0]):
+        eo, go = oracle.energy_grad(spec, ham, th[b], "shift")
+        assert abs(e[b] - eo) < E_TOL
+        np.testing.assert_allclose(g[b], go, atol=G_TOL)
+        np.testing.assert_allclose(g[b], ga[b], atol=G_TOL)
