@@ -67,6 +67,120 @@ __device__ __forceinline__ void fill_hoff(const TileGeom *__restrict__ gp, int k
     }
 }
 
+// XOR swizzle of an LDS tile index: bits 4..7 folded into bits 0..3, so that
+// 16-amplitude sub-cubes strided in any four bits spread over all banks
+__device__ __forceinline__ uint32_t swz(uint32_t i) { return i ^ ((i >> 4) & 15u); }
+
+// Streaming a tile between HBM and LDS.  Tile element j lives at
+// base + hoff[j >> c] + (j & lowm) in HBM (the low c bits are contiguous) and
+// at j (or swz(j)) in LDS.  NB elements per thread are read from HBM before
+// the first LDS write, so that every CU keeps tens of kilobytes of reads in
+// flight; one outstanding 16-byte load per thread leaves the passes far below
+// HBM bandwidth.  Lanes past the tile's end re-read their first element (in
+// bounds) so that every load is unconditional and the batch stays in
+// registers; only the writes are predicated.
+template <int NB, bool SWZ>
+__device__ __forceinline__ void tile_in(double2 *tile, const double2 *__restrict__ src, uint64_t base,
+                                        const uint64_t *hoff, int T, int c)
+{
+    const uint32_t lowm = (1u << c) - 1u;
+    for (int j0 = threadIdx.x; j0 < T; j0 += NB * kThreads) {
+        double rx[NB], ry[NB];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int j = j0 + u * kThreads < T ? j0 + u * kThreads : j0;
+            const double2 v = src[base + hoff[j >> c] + (j & lowm)];
+            rx[u] = v.x;
+            ry[u] = v.y;
+        }
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int j = j0 + u * kThreads;
+            if (j < T) tile[SWZ ? swz(j) : j] = make_double2(rx[u], ry[u]);
+        }
+    }
+}
+
+// both states of the adjoint pass (same element offsets)
+template <int NB, bool SWZ>
+__device__ __forceinline__ void tile_in2(double2 *ta, double2 *tb, const double2 *__restrict__ a,
+                                         const double2 *__restrict__ b, uint64_t base, const uint64_t *hoff, int T,
+                                         int c)
+{
+    const uint32_t lowm = (1u << c) - 1u;
+    for (int j0 = threadIdx.x; j0 < T; j0 += NB * kThreads) {
+        double ax[NB], ay[NB], bx[NB], by[NB];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int j = j0 + u * kThreads < T ? j0 + u * kThreads : j0;
+            const uint64_t gi = base + hoff[j >> c] + (j & lowm);
+            const double2 va = a[gi], vb = b[gi];
+            ax[u] = va.x;
+            ay[u] = va.y;
+            bx[u] = vb.x;
+            by[u] = vb.y;
+        }
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int j = j0 + u * kThreads;
+            if (j < T) {
+                ta[SWZ ? swz(j) : j] = make_double2(ax[u], ay[u]);
+                tb[SWZ ? swz(j) : j] = make_double2(bx[u], by[u]);
+            }
+        }
+    }
+}
+
+template <int NB, bool SWZ>
+__device__ __forceinline__ void tile_out(const double2 *tile, double2 *__restrict__ dst, uint64_t base,
+                                         const uint64_t *hoff, int T, int c)
+{
+    const uint32_t lowm = (1u << c) - 1u;
+    for (int j0 = threadIdx.x; j0 < T; j0 += NB * kThreads) {
+        double rx[NB], ry[NB];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int j = j0 + u * kThreads < T ? j0 + u * kThreads : j0;
+            const double2 v = tile[SWZ ? swz(j) : j];
+            rx[u] = v.x;
+            ry[u] = v.y;
+        }
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int j = j0 + u * kThreads;
+            if (j < T) dst[base + hoff[j >> c] + (j & lowm)] = make_double2(rx[u], ry[u]);
+        }
+    }
+}
+
+template <int NB, bool SWZ>
+__device__ __forceinline__ void tile_out2(const double2 *ta, const double2 *tb, double2 *__restrict__ a,
+                                          double2 *__restrict__ b, uint64_t base, const uint64_t *hoff, int T, int c)
+{
+    const uint32_t lowm = (1u << c) - 1u;
+    for (int j0 = threadIdx.x; j0 < T; j0 += NB * kThreads) {
+        double ax[NB], ay[NB], bx[NB], by[NB];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int j = j0 + u * kThreads < T ? j0 + u * kThreads : j0;
+            const double2 va = ta[SWZ ? swz(j) : j], vb = tb[SWZ ? swz(j) : j];
+            ax[u] = va.x;
+            ay[u] = va.y;
+            bx[u] = vb.x;
+            by[u] = vb.y;
+        }
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int j = j0 + u * kThreads;
+            if (j < T) {
+                const uint64_t gi = base + hoff[j >> c] + (j & lowm);
+                a[gi] = make_double2(ax[u], ay[u]);
+                b[gi] = make_double2(bx[u], by[u]);
+            }
+        }
+    }
+}
+
 __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
@@ -199,7 +313,7 @@ __global__ __launch_bounds__(kThreads) void k_forward_pass(
     __syncthreads();
     for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
         const uint64_t base = tile_base(gp, nout, t);
-        for (int j = tid; j < T; j += kThreads) tile[j] = st[base + hoff[j >> c] + (j & lowm)];
+        tile_in<8, false>(tile, st, base, hoff, T, c);
         __syncthreads();
         for (int q = 0; q < nops; ++q) {
             const OpDesc o = ops[q];
@@ -225,7 +339,7 @@ __global__ __launch_bounds__(kThreads) void k_forward_pass(
             }
             __syncthreads();
         }
-        for (int j = tid; j < T; j += kThreads) st[base + hoff[j >> c] + (j & lowm)] = tile[j];
+        tile_out<8, false>(tile, st, base, hoff, T, c);
         __syncthreads();
     }
 }
@@ -260,11 +374,7 @@ __global__ __launch_bounds__(kThreads) void k_reverse_pass(
     __syncthreads();
     for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
         const uint64_t base = tile_base(gp, nout, t);
-        for (int j = tid; j < T; j += kThreads) {
-            const uint64_t gi = base + hoff[j >> c] + (j & lowm);
-            tp[j] = sp[gi];
-            tl[j] = sl[gi];
-        }
+        tile_in2<8, false>(tp, tl, sp, sl, base, hoff, T, c);
         __syncthreads();
         int slot = 0;
         for (int q = 0; q < nops; ++q) {
@@ -315,11 +425,7 @@ __global__ __launch_bounds__(kThreads) void k_reverse_pass(
             }
             __syncthreads();
         }
-        for (int j = tid; j < T; j += kThreads) {
-            const uint64_t gi = base + hoff[j >> c] + (j & lowm);
-            sp[gi] = tp[j];
-            sl[gi] = tl[j];
-        }
+        tile_out2<8, false>(tp, tl, sp, sl, base, hoff, T, c);
         __syncthreads();
     }
     // one partial per parametric op of this pass
@@ -343,7 +449,6 @@ __global__ __launch_bounds__(kThreads) void k_reverse_pass(
 // 16-amplitude sub-cube into registers, applies the stage's ops there (the
 // pair partner i ^ M is resolved at compile time for every mask M), and
 // stores the sub-cube back: one LDS round trip per stage instead of per op.
-__device__ __forceinline__ uint32_t swz(uint32_t i) { return i ^ ((i >> 4) & 15u); }
 
 struct Mat2 {
     double2 a, b, c, d;  // [[a, b], [c, d]] acting on (lower, upper) register index
@@ -564,7 +669,7 @@ __global__ __launch_bounds__(kThreads) void k_forward_staged(
     __syncthreads();
     for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
         const uint64_t base = tile_base(gp, nout, t);
-        for (int j = tid; j < T; j += kThreads) tile[swz(j)] = st[base + hoff[j >> c] + (j & lowm)];
+        tile_in<16, true>(tile, st, base, hoff, T, c);
         __syncthreads();
         for (int s = 0; s < nstages; ++s) {
             const StageCtl sc = sctl[s];
@@ -585,7 +690,7 @@ __global__ __launch_bounds__(kThreads) void k_forward_staged(
             }
             __syncthreads();
         }
-        for (int j = tid; j < T; j += kThreads) st[base + hoff[j >> c] + (j & lowm)] = tile[swz(j)];
+        tile_out<16, true>(tile, st, base, hoff, T, c);
         __syncthreads();
     }
 }
@@ -619,11 +724,7 @@ __global__ __launch_bounds__(kThreads) void k_reverse_staged(
     __syncthreads();
     for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
         const uint64_t base = tile_base(gp, nout, t);
-        for (int j = tid; j < T; j += kThreads) {
-            const uint64_t gi = base + hoff[j >> c] + (j & lowm);
-            tp[swz(j)] = sp[gi];
-            tl[swz(j)] = sl[gi];
-        }
+        tile_in2<8, true>(tp, tl, sp, sl, base, hoff, T, c);
         __syncthreads();
         int slot0 = 0;
         for (int s = 0; s < nstages; ++s) {
@@ -667,11 +768,7 @@ __global__ __launch_bounds__(kThreads) void k_reverse_staged(
             slot0 += sc.n_param_ops;
             __syncthreads();
         }
-        for (int j = tid; j < T; j += kThreads) {
-            const uint64_t gi = base + hoff[j >> c] + (j & lowm);
-            sp[gi] = tp[swz(j)];
-            sl[gi] = tl[swz(j)];
-        }
+        tile_out2<8, true>(tp, tl, sp, sl, base, hoff, T, c);
         __syncthreads();
     }
     if (tid == 0) {
@@ -750,10 +847,9 @@ __global__ __launch_bounds__(kThreads) void k_pauli_sweep(
     double acc = 0.0;
     for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
         const uint64_t base = tile_base(gp, nout, t);
-        for (int j = tid; j < T; j += kThreads) {
-            tp[j] = sp[base + hoff[j >> c] + (j & lowm)];
-            if (HPSI) tl[j] = make_double2(0.0, 0.0);
-        }
+        tile_in<8, false>(tp, sp, base, hoff, T, c);
+        if (HPSI)
+            for (int j = tid; j < T; j += kThreads) tl[j] = make_double2(0.0, 0.0);
         if (staged)  // fold the sign of the bits outside the tile into the weights
             for (int i = tid; i < nt; i += kThreads)
                 wl[i] = signed_by_parity(w0[i], (uint32_t)(__popcll(zf[i] & base) & 1));
@@ -833,14 +929,31 @@ __global__ __launch_bounds__(kThreads) void k_pauli_sweep(
             __syncthreads();
         }
         if (HPSI) {
-            for (int j = tid; j < T; j += kThreads) {
-                const uint64_t gi = base + hoff[j >> c] + (j & lowm);
-                double2 v = tl[j];
-                if (!first) v = cadd(v, sl[gi]);
-                sl[gi] = v;
-                if (last) {
-                    const double2 a = tp[j];
-                    acc += a.x * v.x + a.y * v.y;
+            // lam += the tile's H psi, all reads of a batch in flight together
+            constexpr int NB = 8;
+            for (int j0 = tid; j0 < T; j0 += NB * kThreads) {
+                double px[NB], py[NB];
+#pragma unroll
+                for (int u = 0; u < NB; ++u) {
+                    const int j = j0 + u * kThreads < T ? j0 + u * kThreads : j0;
+                    px[u] = 0.0;
+                    py[u] = 0.0;
+                    if (!first) {
+                        const double2 v = sl[base + hoff[j >> c] + (j & lowm)];
+                        px[u] = v.x;
+                        py[u] = v.y;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < NB; ++u) {
+                    const int j = j0 + u * kThreads;
+                    if (j >= T) continue;
+                    const double2 v = first ? tl[j] : cadd(tl[j], make_double2(px[u], py[u]));
+                    sl[base + hoff[j >> c] + (j & lowm)] = v;
+                    if (last) {
+                        const double2 a = tp[j];
+                        acc += a.x * v.x + a.y * v.y;
+                    }
                 }
             }
             __syncthreads();
