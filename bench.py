@@ -51,6 +51,9 @@ def parse():
                     help="comma-separated qubit counts for the hardware-efficient scaling leg (L = n, 500 strings)")
     ap.add_argument("--large", action="store_true",
                     help="30-qubit energy + gradient and 32-qubit energy (L = 4, 2000 strings)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB three times (calibrates the HBM byte "
+                         "counters FETCH_SIZE / WRITE_SIZE of a profiler run) and exit")
     ap.add_argument("--served-requests", type=int, default=400)
     ap.add_argument("--served-rates", type=str, default="1.0",
                     help="comma-separated multiples of the measured plain-path capacity")
@@ -101,6 +104,16 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nbytes, "copies": 3}), flush=True)
+        return
 
     import synth
     from paper_2601_09951_amd import vqe

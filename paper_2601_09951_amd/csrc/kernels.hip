@@ -1166,12 +1166,13 @@ hipError_t launch_pauli_sweep(const SweepPlan &sp, const PauliPlan &pp, int swee
 {
     const TileGeom &g = sp.geom;
     const int64_t tiles = 1ll << g.nout;
-    const size_t base = ((write_lambda ? 32u : 16u) << g.k) + (8u << (g.k - g.c)) + 64;
+    // tiles, hoff, the reduction slots and alignment slack; then kTermBytes per staged term
+    const size_t base = ((write_lambda ? 32u : 16u) << g.k) + (8u << (g.k - g.c)) + 64 + 16;
     // stage up to tcap terms; keep two workgroups per CU when the tile allows it
-    size_t budget = base + 64 * kTermBytes + 16 <= kLdsLimit / 2 ? kLdsLimit / 2 : kLdsLimit;
-    int tcap = (int)std::min<size_t>(2048, (budget - std::min(budget, base)) / kTermBytes);
-    if (tcap < 64) tcap = (int)std::min<size_t>(2048, (kLdsLimit - std::min(kLdsLimit, base)) / kTermBytes);
-    const size_t lds = base + (size_t)tcap * kTermBytes + 16;
+    const size_t budget = base + 64 * kTermBytes <= kLdsLimit / 2 ? kLdsLimit / 2 : kLdsLimit;
+    const int tcap = (int)std::min<size_t>(2048, (budget - std::min(budget, base)) / kTermBytes);
+    const size_t lds = base + (size_t)tcap * kTermBytes;
+    if (lds > kLdsLimit) return hipErrorInvalidValue;
     const bool big = g.k >= 11;
     void (*kern)(const TileGeom *, int, int, int, int, const GroupDev *, int, const int32_t *, int,
                  const TermDev *, int, const double2 *, double2 *, int64_t, int, int, double *, int, int, int);
