@@ -40,7 +40,7 @@ def _alone(vqe, ctx, r):
     return e.item(), g.cpu().numpy()[0]
 
 
-@pytest.mark.parametrize("budget", [32 << 30, 3 << 20])
+@pytest.mark.parametrize("budget", [32 << 30, 6 << 20])
 def test_served_equals_alone(mods, ctx, budget):
     serve, vqe = mods
     print("[case] served mix, budget", budget, flush=True)
