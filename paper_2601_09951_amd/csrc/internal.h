@@ -36,7 +36,9 @@ struct TileGeom {
 };
 
 // Gate classes on an amplitude pair (first, second).
-enum : int16_t { CLS_GENERAL = 0, CLS_DIAG = 1, CLS_SWAP = 2 };
+// CLS_REAL: a general 2x2 whose entries are real for every angle (RY, H, the
+// excitations); kernels may apply it with real arithmetic or as CLS_GENERAL.
+enum : int16_t { CLS_GENERAL = 0, CLS_DIAG = 1, CLS_SWAP = 2, CLS_REAL = 3 };
 // Generator classes for the adjoint gradient.
 enum : int16_t { GEN_NONE = 0, GEN_X = 1, GEN_Y = 2, GEN_Z = 3 };
 

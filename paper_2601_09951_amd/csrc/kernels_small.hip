@@ -62,10 +62,9 @@ __device__ __forceinline__ double block_sum_all(double v, double *red)
     return s;
 }
 
-__device__ __forceinline__ void gate_matrix(int kind, double a, double2 *m)
+// the 2x2 of a gate kind from c = cos(a/2), s = sin(a/2)
+__device__ __forceinline__ void gate_matrix_cs(int kind, double c, double s, double2 *m)
 {
-    double s, c;
-    sincos(0.5 * a, &s, &c);
     double2 u00 = {0, 0}, u01 = {0, 0}, u10 = {0, 0}, u11 = {0, 0};
     switch (kind) {
     case VQE_GATE_RX: u00 = {c, 0}; u01 = {0, -s}; u10 = {0, -s}; u11 = {c, 0}; break;
@@ -88,6 +87,13 @@ __device__ __forceinline__ void gate_matrix(int kind, double a, double2 *m)
     m[3] = u11;
 }
 
+__device__ __forceinline__ void gate_matrix(int kind, double a, double2 *m)
+{
+    double s, c;
+    sincos(0.5 * a, &s, &c);
+    gate_matrix_cs(kind, c, s, m);
+}
+
 // compact per-op record kept in LDS
 struct SmallOp {
     uint32_t m, fixed_bits;
@@ -98,13 +104,15 @@ struct SmallOp {
 };
 
 struct SmallLayout {
-    int D, G, P, NPG, NG, nw, nterms, mode;
-    size_t psi, lam, mats, th, mom, vel, grd, red, bred, ops, rops, gf, tab, toff, tz, tw, total;
+    int D, G, P, NPG, NG, nw, nterms, mode, defer;
+    size_t psi, lam, mats, th, mom, vel, grd, red, bred, ops, rops, gf, gdev, poff, pidx, tab, toff, tz, tw, total;
 };
 
-// mode 1: real table, 2: complex table, 0: term form
+// mode 1: real table, 2: complex table, 0: term form.  defer: per-thread
+// gradient partials [NPG][nthreads] kept in LDS and summed once after the
+// reverse sweep (else one workgroup reduction per parametric gate)
 __host__ __device__ inline SmallLayout small_layout(int n, int G, int P, int NPG, int NG, int nterms,
-                                                    int nthreads, int mode)
+                                                    int nthreads, int mode, int defer)
 {
     SmallLayout L;
     L.D = 1 << n;
@@ -114,6 +122,7 @@ __host__ __device__ inline SmallLayout small_layout(int n, int G, int P, int NPG
     L.NG = NG;
     L.nterms = nterms;
     L.mode = mode;
+    L.defer = defer;
     L.nw = nthreads / 64;
     size_t o = 0;
     auto take = [&](size_t bytes, size_t align) {
@@ -129,11 +138,14 @@ __host__ __device__ inline SmallLayout small_layout(int n, int G, int P, int NPG
     L.mom = take((size_t)8 * P, 8);
     L.vel = take((size_t)8 * P, 8);
     L.grd = take((size_t)8 * P, 8);
-    L.red = take((size_t)8 * NPG * L.nw, 8);
+    L.red = take((size_t)8 * NPG * (defer ? nthreads : L.nw), 8);
     L.bred = take((size_t)8 * L.nw, 8);
     L.ops = take(sizeof(SmallOp) * G, 16);
     L.rops = take(sizeof(SmallOp) * G, 16);
     L.gf = take((size_t)8 * NG, 8);  // uint32 flip, uint32 pivot
+    L.gdev = take(sizeof(GateDev) * G, 16);
+    L.poff = take((size_t)4 * (P + 1), 4);
+    L.pidx = take((size_t)4 * (NPG > 0 ? NPG : 1), 4);
     if (mode == 1) {
         L.tab = take((size_t)8 * NG * L.D, 16);
         L.toff = L.tz = L.tw = o;
@@ -175,6 +187,7 @@ struct SmallKernelArgs {
     int n_pgates;
     int mode;
     int max_inst_terms;
+    int defer;
 };
 
 __global__ __launch_bounds__(256) void k_small_run(SmallKernelArgs ka)
@@ -182,7 +195,7 @@ __global__ __launch_bounds__(256) void k_small_run(SmallKernelArgs ka)
     extern __shared__ __align__(16) unsigned char smem[];
     const SmallRunArgs &a = ka.a;
     const SmallLayout L = small_layout(a.n, a.n_gates, a.n_params, ka.n_pgates, a.n_groups, ka.max_inst_terms,
-                                       blockDim.x, ka.mode);
+                                       blockDim.x, ka.mode, ka.defer);
     double2 *psi = reinterpret_cast<double2 *>(smem + L.psi);
     double2 *lam = reinterpret_cast<double2 *>(smem + L.lam);
     double2 *mats = reinterpret_cast<double2 *>(smem + L.mats);
@@ -194,6 +207,9 @@ __global__ __launch_bounds__(256) void k_small_run(SmallKernelArgs ka)
     SmallOp *fops = reinterpret_cast<SmallOp *>(smem + L.ops);
     SmallOp *rops = reinterpret_cast<SmallOp *>(smem + L.rops);
     uint32_t *gf = reinterpret_cast<uint32_t *>(smem + L.gf);
+    GateDev *gdev = reinterpret_cast<GateDev *>(smem + L.gdev);
+    int32_t *poff = reinterpret_cast<int32_t *>(smem + L.poff);
+    int32_t *pidx = reinterpret_cast<int32_t *>(smem + L.pidx);
     double *tabr = reinterpret_cast<double *>(smem + L.tab);
     double2 *tabc = reinterpret_cast<double2 *>(smem + L.tab);
     int32_t *stoff = reinterpret_cast<int32_t *>(smem + L.toff);
@@ -215,7 +231,10 @@ __global__ __launch_bounds__(256) void k_small_run(SmallKernelArgs ka)
     for (int q = tid; q < G; q += bs) {
         fops[q] = pack_op(a.ops[q]);
         rops[q] = pack_op(ka.rops[q]);
+        gdev[q] = a.gates[q];
     }
+    for (int p = tid; p <= P; p += bs) poff[p] = ka.pmap_off[p];
+    for (int i = tid; i < ka.n_pgates; i += bs) pidx[i] = ka.pmap_idx[i];
     for (int g = tid; g < NG; g += bs) {
         gf[2 * g] = a.groups[g].floc;
         gf[2 * g + 1] = a.groups[g].pivot;
@@ -264,7 +283,7 @@ __global__ __launch_bounds__(256) void k_small_run(SmallKernelArgs ka)
     for (int it = 0; it <= a.iters; ++it) {
         // gate matrices at the current parameters; reference state
         for (int g = tid; g < G; g += bs) {
-            const GateDev gd = a.gates[g];
+            const GateDev gd = gdev[g];
             gate_matrix(gd.kind, gd.pidx >= 0 ? th[gd.pidx] : gd.fixed, mats + 4 * g);
         }
         for (int j = tid; j < D; j += bs) psi[j] = make_double2(j == (int)a.ref ? 1.0 : 0.0, 0.0);
@@ -298,6 +317,7 @@ __global__ __launch_bounds__(256) void k_small_run(SmallKernelArgs ka)
             for (int b = tid; b < D; b += bs) {
                 double2 acc = make_double2(0.0, 0.0);
                 if (ka.mode == 1) {
+#pragma unroll 4
                     for (int g = 0; g < NG; ++g) {
                         const double d = tabr[g * D + b];
                         const double2 x = psi[b ^ gf[2 * g]];
@@ -305,6 +325,7 @@ __global__ __launch_bounds__(256) void k_small_run(SmallKernelArgs ka)
                         acc.y += d * x.y;
                     }
                 } else {
+#pragma unroll 4
                     for (int g = 0; g < NG; ++g) acc = cadd(acc, cmul(tabc[g * D + b], psi[b ^ gf[2 * g]]));
                 }
                 lam[b] = acc;
@@ -384,8 +405,12 @@ __global__ __launch_bounds__(256) void k_small_run(SmallKernelArgs ka)
                 }
             }
             if (param) {
-                acc = wave_sum(acc);
-                if (lane == 0) red[o.pgate * L.nw + wave] = acc;
+                if (L.defer) {
+                    red[o.pgate * bs + tid] = acc;
+                } else {
+                    acc = wave_sum(acc);
+                    if (lane == 0) red[o.pgate * L.nw + wave] = acc;
+                }
             }
             __syncthreads();
         }
@@ -394,10 +419,22 @@ __global__ __launch_bounds__(256) void k_small_run(SmallKernelArgs ka)
         b2t *= a.b2;
         for (int p = tid; p < P; p += bs) {
             double gp = 0.0;
-            for (int e2 = ka.pmap_off[p]; e2 < ka.pmap_off[p + 1]; ++e2) {
-                const int pg = ka.pmap_idx[e2];
+            for (int e2 = poff[p]; e2 < poff[p + 1]; ++e2) {
+                const int pg = pidx[e2];
                 double s = 0.0;
-                for (int w = 0; w < L.nw; ++w) s += red[pg * L.nw + w];
+                if (L.defer) {
+                    // fixed order: four interleaved partial sums over the threads' partials
+                    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+                    for (int t = 0; t < bs; t += 4) {
+                        s0 += red[pg * bs + t];
+                        s1 += red[pg * bs + t + 1];
+                        s2 += red[pg * bs + t + 2];
+                        s3 += red[pg * bs + t + 3];
+                    }
+                    s = (s0 + s1) + (s2 + s3);
+                } else {
+                    for (int w = 0; w < L.nw; ++w) s += red[pg * L.nw + w];
+                }
                 gp += s;
             }
             if (a.opt == VQE_OPT_ADAM) {
@@ -417,7 +454,429 @@ __global__ __launch_bounds__(256) void k_small_run(SmallKernelArgs ka)
     for (int p = tid; p < P; p += bs) a.theta[(size_t)inst * P + p] = th[p];
 }
 
+// ---------------------------------------------------------------------------
+// The same loop for states of at most 8 qubits with the Hamiltonian as
+// XOR-offset diagonals, built for latency.  An iteration is a chain of
+// dependent steps (gate after gate, then H psi, then the reverse sweep); on
+// this hardware a dependent FP64 operation costs about 32 cycles, an LDS
+// round trip about 70 and a taken branch tens of cycles, so every link of the
+// chain is cut to its data dependence:
+//  * one amplitude and at most one pair per thread (NT = max(64, 2^n));
+//  * each thread's pair indices for every op are tabulated once per launch
+//    and the gate matrices are laid out in op order (the reverse ones already
+//    conjugate-transposed); after each barrier a thread reads its pair, then
+//    the next op's table entry and matrix (into the other of two register
+//    sets), applies the full 2x2 without branching on the gate class and
+//    writes back;
+//  * cos and sin of the half angles are taken in the optimiser step, so
+//    building the matrices needs no transcendental;
+//  * lambda = H psi uses eight interleaved accumulators;
+//  * gradient partials are written per thread; with several waves the last
+//    wave, which holds no pairs, sums each op's partials during the next op;
+//    the energy's sum runs on that wave beside the optimiser step.
+struct FastLayout {
+    size_t psi, lam, matf, matr, cs, fcs, th, mom, vel, gpart, gsum, epart, finf, rinf, ptf, ptr, gdev, poff, pidx,
+        gf, tab, total;
+};
+
+__host__ __device__ inline int fast_threads(int n) { return n <= 6 ? 64 : (1 << n); }
+
+__host__ __device__ inline FastLayout fast_layout(int n, int G, int P, int NPG, int NG, int complex_tab)
+{
+    FastLayout L;
+    const size_t D = (size_t)1 << n, H = D / 2 > 0 ? D / 2 : 1, nt = (size_t)fast_threads(n);
+    const size_t npg = NPG > 0 ? NPG : 1;
+    size_t o = 0;
+    auto take = [&](size_t bytes, size_t align) {
+        o = (o + align - 1) / align * align;
+        size_t r = o;
+        o += bytes;
+        return r;
+    };
+    L.psi = take(16 * (D + 2), 16);  // + two trash slots for threads without a pair
+    L.lam = take(16 * (D + 2), 16);
+    L.matf = take((size_t)64 * (G + 2), 16);  // + two padding ops (branch-free prefetch)
+    L.matr = take((size_t)64 * (G + 2), 16);
+    L.cs = take((size_t)16 * (P > 0 ? P : 1), 16);
+    L.fcs = take((size_t)16 * G, 16);
+    L.th = take((size_t)8 * P, 8);
+    L.mom = take((size_t)8 * P, 8);
+    L.vel = take((size_t)8 * P, 8);
+    L.gpart = take(8 * H * npg, 8);
+    L.gsum = take((size_t)8 * 16 * npg, 8);
+    L.epart = take(8 * nt, 8);
+    L.finf = take((size_t)8 * (G + 2), 8);  // {gen | (pgate + 1) << 8, gate} per op
+    L.rinf = take((size_t)8 * (G + 2), 8);
+    L.ptf = take(2 * (size_t)(G + 2) * H, 4);  // pairs live on threads t < H
+    L.ptr = take(2 * (size_t)(G + 2) * H, 4);
+    L.gdev = take(sizeof(GateDev) * G, 16);
+    L.poff = take((size_t)4 * (P + 1), 4);
+    L.pidx = take((size_t)4 * npg, 4);
+    const size_t ng8 = (size_t)(NG + 7) / 8 * 8;  // groups padded with zero diagonals
+    L.gf = take(4 * ng8, 16);
+    L.tab = take((complex_tab ? 16 : 8) * ng8 * D, 16);
+    L.total = o;
+    return L;
+}
+
+__device__ __forceinline__ uint32_t ufirst(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// u x + v y with balanced dependency chains
+__device__ __forceinline__ double2 mac2(double2 u, double2 x, double2 v, double2 y)
+{
+    const double r0 = fma(u.x, x.x, -u.y * x.y), r1 = fma(v.x, y.x, -v.y * y.y);
+    const double i0 = fma(u.x, x.y, u.y * x.x), i1 = fma(v.x, y.y, v.y * y.x);
+    return make_double2(r0 + r1, i0 + i1);
+}
+
+constexpr uint32_t kNoPair = 0xFFFFu;
+
+// one forward op: read the pair (clamped to index 0 when the thread has none),
+// read the next op's entry and matrix into (pn, un), apply, write back
+__device__ __forceinline__ void fast_fwd_op(double2 *psi, const uint16_t *ptf, const double2 *matf, int qn, int H,
+                                            int D, uint32_t cur, const double2 (&u)[4], uint32_t &pn,
+                                            double2 (&un)[4])
+{
+    // a thread without a pair works on the trash slots D, D + 1 (no branch)
+    const bool act = cur != kNoPair;
+    const uint32_t i0 = act ? (cur & 255u) : (uint32_t)D, i1 = act ? (cur >> 8) : (uint32_t)D + 1u;
+    const double2 x = psi[i0], y = psi[i1];
+    const int t = (int)threadIdx.x;
+    const uint32_t e = ptf[qn * H + (t < H ? t : H - 1)];  // unconditional read, then select
+    pn = t < H ? e : kNoPair;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) un[k] = matf[4 * qn + k];
+    psi[i0] = mac2(u[0], x, u[1], y);
+    psi[i1] = mac2(u[2], x, u[3], y);
+}
+
+// one reverse op: gradient partial Im <lam|G|psi> on the pair, U^dagger on both
+__device__ __forceinline__ double fast_rev_op(double2 *psi, double2 *lam, const uint16_t *ptr, const double2 *matr,
+                                              const int2 *rinf, int qn, int H, int D, uint32_t cur, int gen,
+                                              const double2 (&u)[4], uint32_t &pn, double2 (&un)[4], int &coden)
+{
+    const bool act = cur != kNoPair;
+    const uint32_t i0 = act ? (cur & 255u) : (uint32_t)D, i1 = act ? (cur >> 8) : (uint32_t)D + 1u;
+    const double2 x = psi[i0], y = psi[i1], lx = lam[i0], ly = lam[i1];
+    const int t = (int)threadIdx.x;
+    const uint32_t e = ptr[qn * H + (t < H ? t : H - 1)];  // unconditional read, then select
+    pn = t < H ? e : kNoPair;
+    coden = rinf[qn].x;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) un[k] = matr[4 * qn + k];
+    const double gx = (lx.x * y.y - lx.y * y.x) + (ly.x * x.y - ly.y * x.x);
+    const double gy = (ly.x * x.x + ly.y * x.y) - (lx.x * y.x + lx.y * y.y);
+    const double gz = (lx.x * x.y - lx.y * x.x) - (ly.x * y.y - ly.y * y.x);
+    psi[i0] = mac2(u[0], x, u[1], y);
+    psi[i1] = mac2(u[2], x, u[3], y);
+    lam[i0] = mac2(u[0], lx, u[1], ly);
+    lam[i1] = mac2(u[2], lx, u[3], ly);
+    const double g = gen == GEN_Y ? gy : (gen == GEN_X ? gx : gz);
+    return act ? g : 0.0;
+}
+
+// 16 fixed-stride partial sums of a gradient row of H partials
+__device__ __forceinline__ double row_part(const double *row, int H, int part)
+{
+    double s0 = 0.0, s1 = 0.0;
+    int t = part;
+    for (; t + 16 < H; t += 32) {
+        s0 += row[t];
+        s1 += row[t + 16];
+    }
+    if (t < H) s0 += row[t];
+    return s0 + s1;
+}
+
+template <int NT, bool CT>
+__global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
+{
+    constexpr int NW = NT / 64;
+    constexpr bool OVERLAP = NW > 1;  // the last wave holds no pairs and reduces gradients meanwhile
+    extern __shared__ __align__(16) unsigned char smem[];
+    const SmallRunArgs &a = ka.a;
+    const FastLayout L = fast_layout(a.n, a.n_gates, a.n_params, ka.n_pgates, a.n_groups, CT);
+    double2 *psi = reinterpret_cast<double2 *>(smem + L.psi);
+    double2 *lam = reinterpret_cast<double2 *>(smem + L.lam);
+    double2 *matf = reinterpret_cast<double2 *>(smem + L.matf);
+    double2 *matr = reinterpret_cast<double2 *>(smem + L.matr);
+    double2 *cs = reinterpret_cast<double2 *>(smem + L.cs);
+    double2 *fcs = reinterpret_cast<double2 *>(smem + L.fcs);
+    double *th = reinterpret_cast<double *>(smem + L.th);
+    double *mom = reinterpret_cast<double *>(smem + L.mom);
+    double *vel = reinterpret_cast<double *>(smem + L.vel);
+    double *gpart = reinterpret_cast<double *>(smem + L.gpart);
+    double *gsum = reinterpret_cast<double *>(smem + L.gsum);
+    double *epart = reinterpret_cast<double *>(smem + L.epart);
+    int2 *finf = reinterpret_cast<int2 *>(smem + L.finf);
+    int2 *rinf = reinterpret_cast<int2 *>(smem + L.rinf);
+    uint16_t *ptf = reinterpret_cast<uint16_t *>(smem + L.ptf);
+    uint16_t *ptr = reinterpret_cast<uint16_t *>(smem + L.ptr);
+    GateDev *gdev = reinterpret_cast<GateDev *>(smem + L.gdev);
+    int32_t *poff = reinterpret_cast<int32_t *>(smem + L.poff);
+    int32_t *pidx = reinterpret_cast<int32_t *>(smem + L.pidx);
+    uint32_t *gf = reinterpret_cast<uint32_t *>(smem + L.gf);
+    double *tabr = reinterpret_cast<double *>(smem + L.tab);
+    double2 *tabc = reinterpret_cast<double2 *>(smem + L.tab);
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const bool redw = OVERLAP && wave == NW - 1;  // the reducing wave
+    const int inst = blockIdx.x;
+    const int D = 1 << a.n, H = D > 1 ? D / 2 : 1;
+    const int G = a.n_gates, P = a.n_params, NG = a.n_groups, NG8 = (NG + 7) / 8 * 8, NPG = ka.n_pgates;
+    const int32_t *to = a.toff + (size_t)(a.shared_ham ? 0 : inst) * NG * 3;
+    double *energies = a.energies + (size_t)inst * (a.iters + 1);
+
+    // ---- one-time staging (ops G and G + 1 pad the tables and are never applied)
+    for (int p = tid; p < P; p += NT) {
+        const double t = a.theta[(size_t)inst * P + p];
+        th[p] = t;
+        mom[p] = 0.0;
+        vel[p] = 0.0;
+        double sn, cn;
+        sincos(0.5 * t, &sn, &cn);
+        cs[p] = make_double2(cn, sn);
+    }
+    for (int q = tid; q < G + 2; q += NT) {
+        if (q < G) {
+            const OpDesc f = a.ops[q], r = ka.rops[q];
+            finf[q] = make_int2(f.gen | ((f.pgate + 1) << 8), f.gate);
+            rinf[q] = make_int2(r.gen | ((r.pgate + 1) << 8), r.gate);
+            const GateDev gd = a.gates[q];
+            gdev[q] = gd;
+            double sn, cn;
+            sincos(0.5 * gd.fixed, &sn, &cn);
+            fcs[q] = make_double2(cn, sn);
+        } else {
+            finf[q] = rinf[q] = make_int2(0, 0);
+        }
+    }
+    // pair table: op q, thread t < H -> p0 | p1 << 8 (kNoPair past the op's pair count)
+    for (int w = tid; w < 2 * (G + 2) * H; w += NT) {
+        const int rev = w >= (G + 2) * H;
+        const int q = (w - (rev ? (G + 2) * H : 0)) / H, t = w % H;
+        uint32_t e = kNoPair;
+        if (q < G) {
+            const SmallOp o = pack_op(rev ? ka.rops[q] : a.ops[q]);
+            if (t < (D >> o.nfix)) {
+                const uint32_t p0 = insert_zeros((uint32_t)t, o.fixpack, o.nfix) | o.fixed_bits;
+                e = p0 | ((p0 ^ o.m) << 8);
+            }
+        }
+        (rev ? ptr : ptf)[q * H + t] = (uint16_t)e;
+    }
+    for (int k = tid; k < 8; k += NT) {
+        matf[4 * G + k] = make_double2(0.0, 0.0);
+        matr[4 * G + k] = make_double2(0.0, 0.0);
+    }
+    for (int p = tid; p <= P; p += NT) poff[p] = ka.pmap_off[p];
+    for (int i = tid; i < NPG; i += NT) pidx[i] = ka.pmap_idx[i];
+    for (int g = tid; g < NG8; g += NT) gf[g] = g < NG ? a.groups[g].floc : 0u;
+    __syncthreads();
+    // D_g[b] = sum_t kappa_t (-1)^{z_t . (b ^ f_g)}; zero rows pad the groups
+    for (int i = tid; i < NG8 * D; i += NT) {
+        const int g = i >> a.n;
+        const uint32_t b = (uint32_t)(i & (D - 1));
+        double re = 0.0, im = 0.0;
+        if (g < NG) {
+            const int ug = a.groups[g].ugroup;
+            const int tb = to[ug * 3], tm = to[ug * 3 + 1], te = to[ug * 3 + 2];
+            const uint32_t bb = b ^ gf[g];
+            for (int t = tb; t < tm; ++t) {
+                const TermDev d = a.terms[t];
+                re += (__popc(d.zloc & bb) & 1) ? -d.w : d.w;
+            }
+            for (int t = tm; t < te; ++t) {
+                const TermDev d = a.terms[t];
+                im += (__popc(d.zloc & bb) & 1) ? -d.w : d.w;
+            }
+        }
+        if (CT)
+            tabc[i] = make_double2(re, im);
+        else
+            tabr[i] = re;
+    }
+    __syncthreads();
+
+    const bool mine = tid < D;  // this thread's amplitude b = tid
+    double b1t = 1.0, b2t = 1.0;  // beta1^t, beta2^t for Adam's bias corrections
+    for (int it = 0; it <= a.iters; ++it) {
+        // matrices in op order (forward U, reverse U^dagger) from the stored half-angle cos / sin
+        for (int w = tid; w < 2 * G; w += NT) {
+            const int rev = w >= G, q = rev ? w - G : w;
+            const int g = (rev ? rinf : finf)[q].y;
+            const GateDev gd = gdev[g];
+            const double2 c = gd.pidx >= 0 ? cs[gd.pidx] : fcs[g];
+            double2 m[4];
+            gate_matrix_cs(gd.kind, c.x, c.y, m);
+            double2 *dst = (rev ? matr : matf) + 4 * q;
+            if (rev) {
+                dst[0] = cconj(m[0]);
+                dst[1] = cconj(m[2]);
+                dst[2] = cconj(m[1]);
+                dst[3] = cconj(m[3]);
+            } else {
+                dst[0] = m[0];
+                dst[1] = m[1];
+                dst[2] = m[2];
+                dst[3] = m[3];
+            }
+        }
+        if (mine) psi[tid] = make_double2(tid == (int)a.ref ? 1.0 : 0.0, 0.0);
+        __syncthreads();
+
+        // U(theta) e_ref, two register sets in turn (op q uses set q & 1)
+        {
+            uint32_t p0 = tid < H ? ptf[tid] : kNoPair, p1;
+            double2 u0[4] = {matf[0], matf[1], matf[2], matf[3]}, u1[4];
+            int q = 0;
+            for (; q + 1 < G; q += 2) {
+                fast_fwd_op(psi, ptf, matf, q + 1, H, D, p0, u0, p1, u1);
+                __syncthreads();
+                fast_fwd_op(psi, ptf, matf, q + 2, H, D, p1, u1, p0, u0);
+                __syncthreads();
+            }
+            if (q < G) {
+                fast_fwd_op(psi, ptf, matf, q + 1, H, D, p0, u0, p1, u1);
+                __syncthreads();
+            }
+        }
+
+        // lambda = H psi with the XOR-offset diagonals, eight interleaved
+        // accumulators; this thread's part of E = Re <psi|lambda>
+        double e = 0.0;
+        if (mine) {
+            const uint32_t b = (uint32_t)tid;
+            double2 sacc[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) sacc[k] = make_double2(0.0, 0.0);
+            for (int g = 0; g < NG8; g += 8) {
+                const uint4 fa = *reinterpret_cast<const uint4 *>(gf + g);
+                const uint4 fb = *reinterpret_cast<const uint4 *>(gf + g + 4);
+                const uint32_t fk[8] = {fa.x, fa.y, fa.z, fa.w, fb.x, fb.y, fb.z, fb.w};
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const double2 x = psi[b ^ fk[k]];
+                    if (CT) {
+                        sacc[k] = cadd(sacc[k], cmul(tabc[(g + k) * D + b], x));
+                    } else {
+                        const double d = tabr[(g + k) * D + b];
+                        sacc[k].x = fma(d, x.x, sacc[k].x);
+                        sacc[k].y = fma(d, x.y, sacc[k].y);
+                    }
+                }
+            }
+            const double2 acc = cadd(cadd(cadd(sacc[0], sacc[1]), cadd(sacc[2], sacc[3])),
+                                     cadd(cadd(sacc[4], sacc[5]), cadd(sacc[6], sacc[7])));
+            lam[b] = acc;
+            const double2 x = psi[b];
+            e = x.x * acc.x + x.y * acc.y;
+        }
+        epart[tid] = e;
+        __syncthreads();
+        if (it == a.iters) {
+            const double sE = block_sum_all(e, gsum);
+            if (tid == 0) energies[it] = sE;
+            break;
+        }
+
+        // reverse sweep: g_l = Im <lambda|G_l|psi>, then U_l^dagger on both states;
+        // the reducing wave (no pairs) sums op q's partials while op q + 1 runs
+        if (redw) {
+            int prev = -1;
+            for (int q = 0; q < G; ++q) {
+                const int pg = (int)(ufirst((uint32_t)rinf[q].x) >> 8) - 1;
+                if (prev >= 0 && lane < 16) gsum[prev * 16 + lane] = row_part(gpart + (size_t)prev * H, H, lane);
+                prev = pg;
+                __syncthreads();
+            }
+            if (prev >= 0 && lane < 16) gsum[prev * 16 + lane] = row_part(gpart + (size_t)prev * H, H, lane);
+        } else {
+            uint32_t p0 = tid < H ? ptr[tid] : kNoPair, p1;
+            double2 u0[4] = {matr[0], matr[1], matr[2], matr[3]}, u1[4];
+            int code0 = rinf[0].x, code1;
+            int q = 0;
+            for (; q + 1 < G; q += 2) {
+                {
+                    const uint32_t cd = ufirst((uint32_t)code0);
+                    const int pg = (int)(cd >> 8) - 1;
+                    const double g = fast_rev_op(psi, lam, ptr, matr, rinf, q + 1, H, D, p0, (int)(cd & 15u), u0, p1, u1, code1);
+                    if (pg >= 0 && tid < H) gpart[pg * H + tid] = g;
+                }
+                __syncthreads();
+                {
+                    const uint32_t cd = ufirst((uint32_t)code1);
+                    const int pg = (int)(cd >> 8) - 1;
+                    const double g = fast_rev_op(psi, lam, ptr, matr, rinf, q + 2, H, D, p1, (int)(cd & 15u), u1, p0, u0, code0);
+                    if (pg >= 0 && tid < H) gpart[pg * H + tid] = g;
+                }
+                __syncthreads();
+            }
+            if (q < G) {
+                const uint32_t cd = ufirst((uint32_t)code0);
+                const int pg = (int)(cd >> 8) - 1;
+                const double g = fast_rev_op(psi, lam, ptr, matr, rinf, q + 1, H, D, p0, (int)(cd & 15u), u0, p1, u1, code1);
+                if (pg >= 0 && tid < H) gpart[pg * H + tid] = g;
+                __syncthreads();
+            }
+            if (!OVERLAP)
+                for (int w = tid; w < NPG * 16; w += NT) gsum[w] = row_part(gpart + (size_t)(w >> 4) * H, H, w & 15);
+        }
+        __syncthreads();
+        // the energy's sum (last wave) beside the optimiser step (other threads)
+        if (OVERLAP && redw) {
+            double sE = 0.0;
+            for (int t = lane; t < NT; t += 64) sE += epart[t];
+            sE = wave_sum(sE);
+            if (lane == 0) energies[it] = sE;
+        }
+        b1t *= a.b1;
+        b2t *= a.b2;
+        const double rc1 = 1.0 / (1.0 - b1t), rc2 = 1.0 / (1.0 - b2t);
+        constexpr int nopt = OVERLAP ? NT - 64 : NT;
+        if (!redw) {
+            for (int p = tid; p < P; p += nopt) {
+                double gp = 0.0;
+                for (int e2 = poff[p]; e2 < poff[p + 1]; ++e2) {
+                    const double *gs = gsum + (size_t)pidx[e2] * 16;
+                    double s4[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) s4[k] = (gs[k] + gs[k + 4]) + (gs[k + 8] + gs[k + 12]);
+                    gp += (s4[0] + s4[1]) + (s4[2] + s4[3]);
+                }
+                double t = th[p];
+                if (a.opt == VQE_OPT_ADAM) {
+                    const double mi = a.b1 * mom[p] + (1.0 - a.b1) * gp;
+                    const double vi = a.b2 * vel[p] + (1.0 - a.b2) * gp * gp;
+                    mom[p] = mi;
+                    vel[p] = vi;
+                    t -= a.lr * (mi * rc1) / (sqrt(vi * rc2) + a.eps);
+                } else {
+                    t -= a.lr * gp;
+                }
+                th[p] = t;
+                double sn, cn;
+                sincos(0.5 * t, &sn, &cn);
+                cs[p] = make_double2(cn, sn);
+            }
+        }
+        if (!OVERLAP) {
+            const double sE = wave_sum(epart[tid]);  // one wave: nothing to overlap with
+            if (tid == 0) energies[it] = sE;
+        }
+        __syncthreads();
+    }
+    for (int p = tid; p < P; p += NT) a.theta[(size_t)inst * P + p] = th[p];
+}
+
 constexpr size_t kSmallLdsMax = 160 * 1024 - 1024;
+constexpr int kSmallFast = 1 << 5;  // mode flag: k_small_fast
+
+inline void (*fast_kernel(int n, bool complex_tab))(SmallKernelArgs)
+{
+    if (complex_tab) return n <= 6 ? k_small_fast<64, true> : (n == 7 ? k_small_fast<128, true> : k_small_fast<256, true>);
+    return n <= 6 ? k_small_fast<64, false> : (n == 7 ? k_small_fast<128, false> : k_small_fast<256, false>);
+}
 
 int choose_block(int n)
 {
@@ -433,34 +892,58 @@ int small_run_plan(int n, int n_gates, int n_params, int n_pgates, int n_groups,
                    int has_imag, int *mode_out, size_t *lds_out)
 {
     if (n > 10 || n_gates > 2048 || n_params > 2048) return 0;
-    const int nt = choose_block(n);
-    int mode = has_imag ? 2 : 1;
-    SmallLayout L = small_layout(n, n_gates, n_params, n_pgates, n_groups, max_inst_terms, nt, mode);
-    if (L.total > kSmallLdsMax) {
-        mode = 0;
-        L = small_layout(n, n_gates, n_params, n_pgates, n_groups, max_inst_terms, nt, mode);
-        if (L.total > kSmallLdsMax) return 0;
+    // up to 8 qubits with the Hamiltonian as a table: the latency-built kernel
+    if (n <= 8 && n_gates <= 1024) {
+        const FastLayout W = fast_layout(n, n_gates, n_params, n_pgates, n_groups, has_imag);
+        if (W.total <= kSmallLdsMax) {
+            *mode_out = (has_imag ? 2 : 1) | kSmallFast;
+            *lds_out = W.total;
+            return 1;
+        }
     }
-    *mode_out = mode;
-    *lds_out = L.total;
-    return 1;
+    const int nt = choose_block(n);
+    // preference: Hamiltonian table with deferred gradient sums, table, terms with deferred sums, terms
+    const int tmode = has_imag ? 2 : 1;
+    const int order[4][2] = {{tmode, 1}, {tmode, 0}, {0, 1}, {0, 0}};
+    for (auto &o : order) {
+        const SmallLayout L = small_layout(n, n_gates, n_params, n_pgates, n_groups, max_inst_terms, nt, o[0], o[1]);
+        if (L.total <= kSmallLdsMax) {
+            *mode_out = o[0] | (o[1] << 4);
+            *lds_out = L.total;
+            return 1;
+        }
+    }
+    return 0;
 }
 
 hipError_t launch_small_run(const SmallRunArgs &a, const OpDesc *rops, const int32_t *pmap_off,
                             const int32_t *pmap_idx, int n_pgates, int mode, int max_inst_terms,
                             int64_t batch, hipStream_t s)
 {
-    const int nthreads = choose_block(a.n);
     SmallKernelArgs ka;
     ka.a = a;
     ka.rops = rops;
     ka.pmap_off = pmap_off;
     ka.pmap_idx = pmap_idx;
     ka.n_pgates = n_pgates;
-    ka.mode = mode;
+    ka.mode = mode & 15;
+    ka.defer = (mode >> 4) & 1;
     ka.max_inst_terms = max_inst_terms;
+    if (mode & kSmallFast) {
+        const int nt = fast_threads(a.n);
+        const FastLayout W = fast_layout(a.n, a.n_gates, a.n_params, n_pgates, a.n_groups, ka.mode == 2);
+        void (*kern)(SmallKernelArgs) = fast_kernel(a.n, ka.mode == 2);
+        if (W.total > 65536) {
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)W.total);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(kern, dim3((unsigned)batch), dim3(nt), W.total, s, ka);
+        return hipGetLastError();
+    }
+    const int nthreads = choose_block(a.n);
     const SmallLayout L = small_layout(a.n, a.n_gates, a.n_params, n_pgates, a.n_groups, max_inst_terms,
-                                       nthreads, mode);
+                                       nthreads, ka.mode, ka.defer);
     if (L.total > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_small_run),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total);

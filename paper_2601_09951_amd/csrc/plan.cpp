@@ -154,16 +154,16 @@ int build_circuit_gates(Circ *C, int64_t n_gates, const int32_t *kind, const int
         h.gen = GEN_NONE;
         switch (h.kind) {
         case VQE_GATE_RX: h.m = B(0); h.gen = GEN_X; break;
-        case VQE_GATE_RY: h.m = B(0); h.gen = GEN_Y; break;
+        case VQE_GATE_RY: h.m = B(0); h.gen = GEN_Y; h.cls = CLS_REAL; break;
         case VQE_GATE_RZ: h.m = B(0); h.gen = GEN_Z; h.cls = CLS_DIAG; break;
-        case VQE_GATE_H: h.m = B(0); break;
+        case VQE_GATE_H: h.m = B(0); h.cls = CLS_REAL; break;
         case VQE_GATE_X: h.m = B(0); h.cls = CLS_SWAP; break;
         case VQE_GATE_CNOT: h.m = B(1); h.cmask = h.cval = B(0); h.cls = CLS_SWAP; break;
         case VQE_GATE_CZ: h.m = B(1); h.cmask = h.cval = B(0); h.cls = CLS_DIAG; break;
         case VQE_GATE_SINGLE_EXC:  // first element |01> on (a, b)
-            h.m = B(0) | B(1); h.first = B(1); h.gen = GEN_Y; break;
+            h.m = B(0) | B(1); h.first = B(1); h.gen = GEN_Y; h.cls = CLS_REAL; break;
         case VQE_GATE_DOUBLE_EXC:  // first element |0011> on (a, b, c, d)
-            h.m = B(0) | B(1) | B(2) | B(3); h.first = B(2) | B(3); h.gen = GEN_Y; break;
+            h.m = B(0) | B(1) | B(2) | B(3); h.first = B(2) | B(3); h.gen = GEN_Y; h.cls = CLS_REAL; break;
         }
         if (h.pidx < 0) h.gen = GEN_NONE;
         C->gates.push_back(h);
