@@ -70,15 +70,16 @@ FIXED_WIRES = {"RX": 1, "RY": 1, "RZ": 1, "H": 1, "X": 1, "CNOT": 2, "CZ": 2, "S
                "DoubleExcitation": 4}
 
 
-def eval_flops(spec, n_terms, n_groups, n_diag_terms):
-    """Algorithmic FP64 flops of one energy + adjoint-gradient evaluation.
+def eval_flops(spec, n_groups, complex_table):
+    """Algorithmic FP64 flops of one energy + adjoint-gradient evaluation with
+    H held as XOR-offset diagonals (lambda[b] = sum_f D_f[b] psi[b ^ f]; the
+    diagonals are built once per Hamiltonian and reused by every iteration).
 
     gates: 12 flops per active amplitude pair for rotations, 8 for H, 0 for
-    permutations; H psi: 1 flop per term per pair (signed accumulate) plus 16
-    per pair per flip group (two complex multiply-adds), diagonal group 4 per
-    amplitude plus 1 per term per amplitude; E = Re<psi|lambda>: 4 per
-    amplitude; reverse sweep: the gates twice (psi and lambda) plus 7 flops
-    per active pair of every parametric gate.
+    permutations; H psi: 4 flops per amplitude per flip group (real
+    diagonals; 8 when complex); E = Re<psi|lambda>: 4 per amplitude; reverse
+    sweep: the gates twice (psi and lambda) plus 7 flops per active pair of
+    every parametric gate.
     """
     n = spec.n
     D = 1 << n
@@ -89,11 +90,38 @@ def eval_flops(spec, n_terms, n_groups, n_diag_terms):
         fwd += GATE_FLOPS_PER_PAIR[k] * pairs
         if p >= 0:
             grad += 7 * pairs
-    off_terms = n_terms - n_diag_terms
-    off_groups = n_groups - (1 if n_diag_terms else 0)
-    hpsi = (D // 2) * (off_terms + 16 * off_groups) + D * (n_diag_terms + 4 * (1 if n_diag_terms else 0))
+    hpsi = D * n_groups * (8 if complex_table else 4)
     energy = 4 * D
     return fwd + hpsi + energy + 2 * fwd + grad
+
+
+def _odd_y(x, z):
+    """Terms whose phase i^{|x & z|} is imaginary (odd number of Y factors)."""
+    return np.array([bin(int(a) & int(b)).count("1") % 2 == 1 for a, b in zip(x, z)], dtype=bool)
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter runs
+    (FETCH_SIZE + WRITE_SIZE scaled by a plain copy of known size), or None
+    when none were taken or the kernel source changed since."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f).get(kernel)
+    except (OSError, ValueError):
+        return None
+    if not rec:
+        return None
+    h = hashlib.sha256()
+    for src in rec.get("sources", []):
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec.get("sources_sha256"):
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def main():
@@ -145,10 +173,10 @@ def main():
 
     def one_scan(events=None):
         for i, p in enumerate(problems):
-            if events is not None:
-                events[i][0].record(stream)
             p["fam"].set_integrals(p["ints_dev"])      # S0: H(d_i) for every bond length
             p["theta"].zero_()                          # theta_0 = 0
+            if events is not None:
+                events[i][0].record(stream)
             vqe.run(ctx, p["C"], p["hams"], p["theta"], ITERS, ws=p["ws"], energies=p["energies"])
             if events is not None:
                 events[i][1].record(stream)
@@ -174,16 +202,18 @@ def main():
     # roofline of the dominant kernel: the persistent loop of the 8-qubit scan
     p8 = problems[1]
     x, z, c = p8["hams"][0].terms()
-    n_diag = int(np.sum(x == 0))
     n_groups = len(set(int(v) for v in x))
-    flops_eval = eval_flops(p8["spec"], len(c), n_groups, n_diag)
+    complex_table = bool(np.any(_odd_y(x, z)))
+    flops_eval = eval_flops(p8["spec"], n_groups, complex_table)
     flops_launch = flops_eval * BATCH * ITERS
     achieved = flops_launch / (kernel_ms[8] * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": "k_small_run (8 qubits, 100 instances x 200 steps; the event "
-                                          "interval also holds the H(d) build and theta reset, < 1 %)",
+    roofline = {"bound": "alu", "kernel": "k_small_fast<256> (8 qubits, 100 instances x 200 steps in one "
+                                          "launch; the event interval also holds the weight refresh, < 0.2 %)",
                 "achieved": round(achieved, 4), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP64_PEAK_TFLOPS, 5), "traffic": None,
-                "flops_per_eval": flops_eval, "kernel_ms": round(kernel_ms[8], 4)}
+                "frac": round(achieved / FP64_PEAK_TFLOPS, 5),
+                "traffic": measured_traffic("k_small_fast"),
+                "flops_per_eval": flops_eval, "evals_per_launch": BATCH * ITERS,
+                "kernel_ms": round(kernel_ms[8], 4)}
 
     final_e = {p["n"]: p["energies"][:, -1].cpu().numpy() for p in problems}
     out = {
@@ -424,11 +454,12 @@ def served_measure(ctx, count, rates=(1.0,)):
 
 
 def cpu_baseline(problems, budget_s):
-    """The oracle (plain FP64 C, one thread) on a bounded sample of the same
-    scan: the first bond lengths of each qubit count, 200 Adam steps each on
-    adjoint gradients.  Each qubit count gets about budget_s / 2 seconds of
-    wall time (the oracle's dense Jordan-Wigner build included, but only the
-    optimisation loop is timed); the rate is scaled to the full scan."""
+    """The oracle (plain FP64 C for the loop, one thread) on a bounded sample
+    of the same scan: the first bond lengths of each qubit count, each with
+    its Hamiltonian build (the oracle's dense Jordan-Wigner construction, as
+    the GPU step builds H(d_i) too) and 200 Adam steps on adjoint gradients.
+    Each qubit count gets about budget_s / 2 seconds; the rate is scaled to
+    the full scan."""
     import oracle
     from oracle import fermion
     oracle.set_threads(1)
@@ -438,8 +469,8 @@ def cpu_baseline(problems, budget_s):
         done[n], spent[n] = 0, 0.0
         wall0 = time.perf_counter()
         while done[n] < BATCH and (done[n] == 0 or time.perf_counter() - wall0 < budget_s / 2):
-            ho = fermion.qubit_hamiltonian(p["ints"][done[n]])
             t0 = time.perf_counter()
+            ho = fermion.qubit_hamiltonian(p["ints"][done[n]])
             oracle.vqe_run(p["spec"], ho, np.zeros(p["spec"].n_params), ITERS)
             spent[n] += time.perf_counter() - t0
             done[n] += 1
@@ -447,7 +478,7 @@ def cpu_baseline(problems, budget_s):
     evals = len(spent) * BATCH * ITERS
     return {"value": round(evals / scan_s, 1), "unit": "evals/s", "cores": 1, "kind": "oracle",
             "sample": " and ".join(f"{done[n]} x {n}q bond lengths" for n in sorted(done))
-                      + f", {ITERS} Adam steps each (adjoint gradients), "
+                      + f", each with its Hamiltonian build and {ITERS} Adam steps (adjoint gradients), "
                       f"{sum(spent.values()):.1f} s of timed CPU; rate scaled to the full 2 x {BATCH}-bond scan",
             "per_qubit_evals_per_s": {f"{n}q": round(done[n] * ITERS / spent[n], 1) for n in sorted(spent)}}
 
