@@ -115,10 +115,13 @@ int vqe_ctx_set_tile(vqe_ctx_t ctx, int k_fwd, int k_rev, int c_low);
  * step). */
 int vqe_ctx_set_loop_mode(vqe_ctx_t ctx, int mode);
 
-/* Kernel variant of the state passes: staged = 1 (default) applies the gates
- * of a pass in register stages of four tile bits (tiles of 8 or more bits);
- * staged = 0 applies one gate per LDS round trip.  Both compute the same
- * result; the switch exists for measurement. */
+/* Kernel variant of the state passes: staged = 2 (default) runs forward
+ * passes made of uncontrolled one-qubit gates, X and CNOT as fused stages
+ * (one 2x2 per qubit, the CNOT / X network folded into data movement) and
+ * everything else as staged = 1; staged = 1 applies the gates of a pass in
+ * register stages of four tile bits (tiles of 8 or more bits); staged = 0
+ * applies one gate per LDS round trip.  All compute the same result; the
+ * switch exists for measurement. */
 int vqe_ctx_set_staged(vqe_ctx_t ctx, int staged);
 
 /* Reserve `bytes` of context scratch now (used by vqe_expect and
@@ -305,15 +308,26 @@ int vqe_run(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams, i
  * natural alignment):
  *
  * vqe_circ_plan_export: int32 {n_passes, n_ops, geom_bytes (72), op_bytes
- *   (48), n_stages, n_stage_ops, stage_bytes (48), stage_op_bytes (40)},
+ *   (48), n_stages, n_stage_ops, stage_bytes (48), stage_op_bytes (48)},
  *   then per pass {geom, int32 op_begin, op_count, n_param_ops,
- *   stage_begin, stage_count, 0, 0, 0}, then n_ops op records, n_stages
- *   stage records and n_stage_ops stage-op records.  geom = int32 {n, k, c,
+ *   stage_begin, stage_count, fstage_begin, fstage_count, 0}, then n_ops
+ *   op records, n_stages stage records and n_stage_ops stage-op records,
+ *   then the fused stages: int32 {n_fstages, fstage_bytes (96), n_fconds,
+ *   fcond_bytes (24), n_slots, n_slot_gates, 0, 0}, n_fstages records
+ *   {uint8 rpos[4], cpos[12], uint16 lr[16], lc[12], c0, perm, int32 na,
+ *   cond_begin, cond_count, slot, 0} (apply the fused 2x2 of slot + j to
+ *   register bit j < na, then store register i of sub-cube u at tile index
+ *   (xor of lc[j] over the bits j of u) ^ lr[i] ^ c0 ^ (xmask of every
+ *   active conditional record) when perm = 1), n_fconds records {uint64
+ *   cmo, cvo, uint32 xmask, 0} (active when (tile base & cmo) == cvo),
+ *   int32 slot offsets [n_slots + 1] and the gate of each slot entry
+ *   (matrices multiplied in list order; an empty slot is the identity).
+ *   Forward plans only; reverse plans have no fused stages.  geom = int32 {n, k, c,
  *   n - k}, uint8 tpos[16]
  *   (index bit of tile bit i), uint8 opos[40] (index bit of tile-number bit
  *   i).  op = uint32 m, uint32 fixed_bits, uint64 cmask_out, uint64
  *   cval_out, int32 gate, int32 pgate, int16 cls (0 general, 1 diagonal,
- *   2 swap), int16 gen (0 none, 1 X, 2 Y, 3 Z), int8 nfix, uint8
+ *   2 swap, 3 real general), int16 gen (0 none, 1 X, 2 Y, 3 Z), int8 nfix, uint8
  *   fixpos[7]: the op updates the pairs p0 = (j with zero bits inserted at
  *   fixpos[0..nfix)) | fixed_bits, p1 = p0 ^ m, j < 2^(k - nfix), of the
  *   tiles whose base satisfies (base & cmask_out) == cval_out.  For tiles
@@ -325,9 +339,11 @@ int vqe_run(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams, i
  *   uint64 cmo, cvo (controls outside the tile),
  *   uint32 cmt, cvt (tile controls outside the registers), int32 gate,
  *   pgate, uint8 M, lo, cmr, cvr (register flip mask, lower-element
- *   pattern, register controls), uint8 swap, cls, gen, 0: register index i
- *   pairs with i ^ M (i < 2^nbits) when (i & M) == lo and the controls hold; swap = 1
- *   means the lower index holds the op's second element.
+ *   pattern, register controls), uint8 swap, cls, gen, 0, uint16 amask
+ *   (bit i set when pair i passes the register predicates), 3 x uint16 0:
+ *   register index i pairs with i ^ M (i < 2^nbits) when (i & M) == lo and
+ *   the controls hold; swap = 1 means the lower index holds the op's second
+ *   element.
  *   reverse = 1 exports the adjoint sweep's schedule (gates in reverse).
  *
  * vqe_ham_plan_export (for_gradient = 0: the expectation schedule, 1: the

@@ -147,6 +147,7 @@ int wg_for(Context *ctx, int n, int k)
 
 // workspace layout; want: 0 energy, 1 energy+grad, 2 run (adds optimiser state)
 int build_shift(Context *ctx, Circ *C);
+int fwd_mats_per_inst(Context *ctx, Circ *C, size_t *count);
 
 int layout_for(Context *ctx, Circ *C, int n_hams, Ham *const *H, int64_t B, int want, Layout &L)
 {
@@ -175,8 +176,11 @@ int layout_for(Context *ctx, Circ *C, int n_hams, Ham *const *H, int64_t B, int 
         L.lam = off;
         off = align_up(off + state);
     }
+    size_t nmats = 0;
+    rc = fwd_mats_per_inst(ctx, C, &nmats);
+    if (rc) return rc;
     L.mats = off;
-    off = align_up(off + (size_t)B * std::max(G, 1) * 64);
+    off = align_up(off + (size_t)B * nmats * 64);
     if (want == 0) {
         PauliPlan *pp = get_pauli_plan(ctx, n_hams, H, n_inst, ctx->k_fwd, ctx->c_low, &rc);
         if (!pp) return rc;
@@ -222,6 +226,50 @@ int refresh_weights(Context *ctx, PauliPlan *pp, hipStream_t s)
                      "refresh weights");
 }
 
+// matrices per instance in the matrix buffer: the gates' and the fused stages'
+int fwd_mats_per_inst(Context *ctx, Circ *C, size_t *count)
+{
+    int rc;
+    CircPlan *fp = get_circ_plan(C, false, ctx->k_fwd, ctx->c_low, &rc);
+    if (!fp) return rc;
+    *count = std::max<size_t>(C->gates.size(), 1) + (size_t)fp->n_fslots();
+    return VQE_OK;
+}
+
+// the forward passes of plan fp over B states, gate matrices already in mats
+// ([B][G][4]); fused-stage matrices go after them ([B][n_fslots][4])
+int run_forward_passes(Context *ctx, Circ *C, CircPlan *fp, int64_t B, double2 *psi, double2 *mats, hipStream_t s)
+{
+    int rc = VQE_OK;
+    const int G = (int)C->gates.size();
+    const bool fuse = ctx->fuse && !ctx->no_stages && fp->n_fslots() > 0;
+    double2 *fused = mats + (size_t)B * G * 4;
+    if (fuse)
+        rc = hip_check(ctx, launch_fuse_mats(reinterpret_cast<const int32_t *>(fp->fslot_off.p),
+                                             reinterpret_cast<const int32_t *>(fp->fslot_gate.p), fp->n_fslots(),
+                                             mats, G, B, fused, s),
+                       "fused stage matrices");
+    for (size_t i = 0; !rc && i < fp->passes.size(); ++i) {
+        const PassPlan &pp = fp->passes[i];
+        const TileGeom *gd = reinterpret_cast<const TileGeom *>(fp->geoms.p) + i;
+        if (fuse && pp.fstage_count > 0)
+            rc = hip_check(ctx, launch_forward_fused(pp, gd, reinterpret_cast<const FusedStage *>(fp->fstages.p),
+                                                     reinterpret_cast<const FusedCond *>(fp->fconds.p), fused,
+                                                     fp->n_fslots(), psi, B, ctx->wg_max, s),
+                           "forward pass (fused)");
+        else if (pp.stage_count > 0 && !ctx->no_stages)
+            rc = hip_check(ctx, launch_forward_staged(pp, pp.stage_bits, gd, reinterpret_cast<const StageDesc *>(fp->stages.p),
+                                                      reinterpret_cast<const StageOp *>(fp->sops.p), mats, G, psi,
+                                                      B, ctx->wg_max, s),
+                           "forward pass (staged)");
+        else
+            rc = hip_check(ctx, launch_forward_pass(pp, gd, reinterpret_cast<const OpDesc *>(fp->ops.p), mats, G,
+                                                    psi, B, ctx->wg_max, s),
+                           "forward pass");
+    }
+    return rc;
+}
+
 int forward(Context *ctx, Circ *C, int64_t B, const double *theta, double2 *psi, double2 *mats,
             hipStream_t s)
 {
@@ -234,21 +282,7 @@ int forward(Context *ctx, Circ *C, int64_t B, const double *theta, double2 *psi,
                                          C->n_params, B, mats, s),
                    "gate matrices");
     if (rc) return rc;
-    for (size_t i = 0; i < fp->passes.size(); ++i) {
-        const PassPlan &pp = fp->passes[i];
-        const TileGeom *gd = reinterpret_cast<const TileGeom *>(fp->geoms.p) + i;
-        if (pp.stage_count > 0 && !ctx->no_stages)
-            rc = hip_check(ctx, launch_forward_staged(pp, pp.stage_bits, gd, reinterpret_cast<const StageDesc *>(fp->stages.p),
-                                                      reinterpret_cast<const StageOp *>(fp->sops.p), mats, G, psi,
-                                                      B, ctx->wg_max, s),
-                           "forward pass (staged)");
-        else
-            rc = hip_check(ctx, launch_forward_pass(pp, gd, reinterpret_cast<const OpDesc *>(fp->ops.p), mats, G,
-                                                    psi, B, ctx->wg_max, s),
-                           "forward pass");
-        if (rc) return rc;
-    }
-    return VQE_OK;
+    return run_forward_passes(ctx, C, fp, B, psi, mats, s);
 }
 
 // energy by paired expectation sweeps (no lambda)
@@ -491,8 +525,9 @@ int vqe_ctx_set_loop_mode(vqe_ctx_t ctx, int mode)
 int vqe_ctx_set_staged(vqe_ctx_t ctx, int staged)
 {
     if (!ctx) return VQE_EINVAL;
-    if (staged != 0 && staged != 1) return set_err(ctx, VQE_EINVAL, "staged must be 0 or 1");
-    ctx->no_stages = !staged;
+    if (staged < 0 || staged > 2) return set_err(ctx, VQE_EINVAL, "staged must be 0, 1 or 2");
+    ctx->no_stages = staged == 0;
+    ctx->fuse = staged == 2;
     return VQE_OK;
 }
 
@@ -865,8 +900,11 @@ int vqe_apply_ansatz(vqe_ctx_t ctx, vqe_circ_t circ, int64_t batch, const double
     if (!circ || !psi || batch < 1 || (circ->n_params > 0 && !theta))
         return set_err(ctx, VQE_EINVAL, "bad argument");
     if (batch > kMaxBatch) return set_err(ctx, VQE_EUNSUPPORTED, "batch > 65535");
+    size_t nmats = 0;
+    rc = fwd_mats_per_inst(ctx, circ, &nmats);
+    if (rc) return rc;
     void *mats;
-    rc = scratch_get(ctx, (size_t)batch * std::max<size_t>(circ->gates.size(), 1) * 64, &mats);
+    rc = scratch_get(ctx, (size_t)batch * nmats * 64, &mats);
     if (rc) return rc;
     return forward(ctx, circ, batch, theta, (double2 *)psi, (double2 *)mats, (hipStream_t)stream);
 }
@@ -1009,19 +1047,7 @@ int vqe_grad_shift(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *
                                               circ->n_params, batch, reinterpret_cast<const ShiftRow *>(circ->shift_tab.p),
                                               R0, mats, s),
                        "shifted gate matrices");
-    for (size_t i = 0; !rc && G > 0 && i < fp->passes.size(); ++i) {
-        const PassPlan &p = fp->passes[i];
-        const TileGeom *gd = reinterpret_cast<const TileGeom *>(fp->geoms.p) + i;
-        if (p.stage_count > 0 && !ctx->no_stages)
-            rc = hip_check(ctx, launch_forward_staged(p, p.stage_bits, gd, reinterpret_cast<const StageDesc *>(fp->stages.p),
-                                                      reinterpret_cast<const StageOp *>(fp->sops.p), mats, G, psi, R,
-                                                      ctx->wg_max, s),
-                           "forward pass (staged)");
-        else
-            rc = hip_check(ctx, launch_forward_pass(p, gd, reinterpret_cast<const OpDesc *>(fp->ops.p), mats, G, psi, R,
-                                                    ctx->wg_max, s),
-                           "forward pass");
-    }
+    if (!rc && G > 0) rc = run_forward_passes(ctx, circ, fp, R, psi, mats, s);
     if (rc) return rc;
     const int W = wg_for(ctx, n, ctx->k_fwd);
     const int S = (int)pp->sweeps.size();
@@ -1169,7 +1195,9 @@ int vqe_circ_plan_export(vqe_ctx_t ctx, vqe_circ_t circ, int reverse, void *buf,
     if (!p) return rc;
     const size_t pass_bytes = sizeof(TileGeom) + 32;
     const size_t need = 32 + p->passes.size() * pass_bytes + p->host_ops.size() * sizeof(OpDesc) +
-                        p->host_stages.size() * sizeof(StageDesc) + p->host_sops.size() * sizeof(StageOp);
+                        p->host_stages.size() * sizeof(StageDesc) + p->host_sops.size() * sizeof(StageOp) + 32 +
+                        p->host_fstages.size() * sizeof(FusedStage) + p->host_fconds.size() * sizeof(FusedCond) +
+                        p->host_fslot_off.size() * 4 + p->host_fslot_gate.size() * 4;
     *needed = need;
     if (!buf || buf_bytes < need) return VQE_OK;
     unsigned char *o = (unsigned char *)buf;
@@ -1180,7 +1208,8 @@ int vqe_circ_plan_export(vqe_ctx_t ctx, vqe_circ_t circ, int reverse, void *buf,
     o += 32;
     for (const PassPlan &pp : p->passes) {
         std::memcpy(o, &pp.geom, sizeof(TileGeom));
-        int32_t meta[8] = {pp.op_begin, pp.op_count, pp.n_param_ops, pp.stage_begin, pp.stage_count, 0, 0, 0};
+        int32_t meta[8] = {pp.op_begin,    pp.op_count,      pp.n_param_ops,     pp.stage_begin,
+                           pp.stage_count, pp.fstage_begin, pp.fstage_count, 0};
         std::memcpy(o + sizeof(TileGeom), meta, 32);
         o += pass_bytes;
     }
@@ -1189,6 +1218,18 @@ int vqe_circ_plan_export(vqe_ctx_t ctx, vqe_circ_t circ, int reverse, void *buf,
     std::memcpy(o, p->host_stages.data(), p->host_stages.size() * sizeof(StageDesc));
     o += p->host_stages.size() * sizeof(StageDesc);
     std::memcpy(o, p->host_sops.data(), p->host_sops.size() * sizeof(StageOp));
+    o += p->host_sops.size() * sizeof(StageOp);
+    int32_t fh[8] = {(int32_t)p->host_fstages.size(), (int32_t)sizeof(FusedStage), (int32_t)p->host_fconds.size(),
+                     (int32_t)sizeof(FusedCond), p->n_fslots(), (int32_t)p->host_fslot_gate.size(), 0, 0};
+    std::memcpy(o, fh, 32);
+    o += 32;
+    std::memcpy(o, p->host_fstages.data(), p->host_fstages.size() * sizeof(FusedStage));
+    o += p->host_fstages.size() * sizeof(FusedStage);
+    std::memcpy(o, p->host_fconds.data(), p->host_fconds.size() * sizeof(FusedCond));
+    o += p->host_fconds.size() * sizeof(FusedCond);
+    std::memcpy(o, p->host_fslot_off.data(), p->host_fslot_off.size() * 4);
+    o += p->host_fslot_off.size() * 4;
+    std::memcpy(o, p->host_fslot_gate.data(), p->host_fslot_gate.size() * 4);
     return VQE_OK;
 }
 

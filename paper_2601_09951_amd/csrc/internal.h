@@ -90,8 +90,37 @@ struct StageOp {
     int32_t gate, pgate;
     uint8_t M, lo, cmr, cvr;
     uint8_t swap, cls, gen, pad;
+    uint16_t amask;      // bit i: register pair (i, i ^ M) passes the register predicates
+    uint16_t pad2[3];
 };
-static_assert(sizeof(StageOp) == 40, "StageOp layout");
+static_assert(sizeof(StageOp) == 48, "StageOp layout");
+
+// Fused stages: forward passes of circuits made of one-qubit gates, X and
+// CNOT.  A stage applies one fused 2x2 per active register bit (the product
+// of that qubit's consecutive one-qubit gates) and then moves every amplitude
+// of the tile by the affine map v -> L v ^ c of the CNOT / X network that
+// follows, folded into the LDS store addresses (CNOTs cost no arithmetic).
+// The register bits are rpos[0..na) (active) and rpos[na..4) (padding).
+struct FusedStage {
+    uint8_t rpos[4];
+    uint8_t cpos[12];    // the other tile bits, ascending (sub-cube index bits)
+    uint16_t lr[16];     // L applied to register offset i
+    uint16_t lc[12];     // L applied to sub-cube bit j (tile bit cpos[j])
+    uint16_t c0;         // constant part of the map (X gates, transformed)
+    uint16_t perm;       // 1 when the map is not the identity
+    int32_t na;          // active register bits
+    int32_t cond_begin, cond_count;  // X conditioned on index bits outside the tile
+    int32_t slot;        // fused matrix of register bit j: slot + j
+    int32_t pad;
+};
+static_assert(sizeof(FusedStage) == 96, "FusedStage layout");
+
+struct FusedCond {
+    uint64_t cmo, cvo;   // active when (tile base & cmo) == cvo
+    uint32_t xmask;      // tile-local bits flipped (already transformed by the later CNOTs)
+    uint32_t pad;
+};
+static_assert(sizeof(FusedCond) == 24, "FusedCond layout");
 
 // Per-gate data for the matrix preparation kernel.
 struct GateDev {
@@ -181,6 +210,7 @@ struct PassPlan {
     int n_param_ops = 0;     // parametric ops in this pass (reverse plans)
     int stage_begin = 0, stage_count = 0;  // register stages (k >= kStageMinK)
     int stage_bits = 0;                     // register bits of this pass's stages
+    int fstage_begin = 0, fstage_count = 0; // fused stages (forward plans; 0: not fusable)
 };
 
 struct CircPlan {
@@ -195,6 +225,13 @@ struct CircPlan {
     std::vector<StageDesc> host_stages;
     std::vector<StageOp> host_sops;
     int max_param_ops = 0;
+    // fused stages: descriptors, conditional X, and per fused matrix (slot)
+    // the CSR list of gates multiplied into it, in application order
+    DevMem fstages, fconds, fslot_off, fslot_gate;
+    std::vector<FusedStage> host_fstages;
+    std::vector<FusedCond> host_fconds;
+    std::vector<int32_t> host_fslot_off{0}, host_fslot_gate;
+    int n_fslots() const { return (int)host_fslot_off.size() - 1; }
 };
 
 // Parameter-shift schedule of a circuit: row r of an instance evaluates the
@@ -252,6 +289,7 @@ struct Context {
     int wg_max = 1024;          // workgroups per instance in tile passes
     int force_generic = 0;      // route vqe_run through the per-step launches
     int no_stages = 0;          // use the one-op-per-LDS-round-trip pass kernels only
+    int fuse = 1;               // forward passes: fused stages where the plan has them
     std::string err;
     DevMem scratch;
     std::map<std::string, std::unique_ptr<PauliPlan>> pauli_cache;
@@ -294,6 +332,11 @@ hipError_t launch_gate_mats(const GateDev *gates, int n_gates, const double *the
 hipError_t launch_forward_pass(const PassPlan &pp, const TileGeom *geom_dev, const OpDesc *ops,
                                const double2 *mats, int n_gates, double2 *psi, int64_t batch,
                                int wg_max, hipStream_t s);
+hipError_t launch_fuse_mats(const int32_t *slot_off, const int32_t *slot_gate, int n_slots, const double2 *mats,
+                            int n_gates, int64_t batch, double2 *fused, hipStream_t s);
+hipError_t launch_forward_fused(const PassPlan &pp, const TileGeom *geom_dev, const FusedStage *fstages,
+                                const FusedCond *fconds, const double2 *fused, int n_slots, double2 *psi,
+                                int64_t batch, int wg_max, hipStream_t s);
 hipError_t launch_forward_staged(const PassPlan &pp, int stage_bits, const TileGeom *geom_dev,
                                  const StageDesc *stages, const StageOp *sops, const double2 *mats,
                                  int n_gates, double2 *psi, int64_t batch, int wg_max, hipStream_t s);

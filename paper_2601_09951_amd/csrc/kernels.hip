@@ -554,7 +554,40 @@ __device__ __forceinline__ double stage_rev(double2 (&x)[1 << RB], double2 (&l)[
     return acc;
 }
 
-#define VQE_MASK_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15)
+// A stage op with every field wave-uniform (scalar registers), so that the
+// per-op branches below are scalar branches, not exec-masked ones.
+struct UStageOp {
+    uint64_t cmo, cvo;
+    uint32_t cmt, cvt, M, lo, cmr, cvr, swap, cls, gen, amask;
+    int32_t pgate;
+};
+
+__device__ __forceinline__ uint32_t ufirst32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ UStageOp uniform_sop(const StageOp &o)
+{
+    UStageOp u;
+    u.cmo = ((uint64_t)ufirst32((uint32_t)(o.cmo >> 32)) << 32) | ufirst32((uint32_t)o.cmo);
+    u.cvo = ((uint64_t)ufirst32((uint32_t)(o.cvo >> 32)) << 32) | ufirst32((uint32_t)o.cvo);
+    u.cmt = ufirst32(o.cmt);
+    u.cvt = ufirst32(o.cvt);
+    const uint32_t w0 = ufirst32((uint32_t)o.M | ((uint32_t)o.lo << 8) | ((uint32_t)o.cmr << 16) | ((uint32_t)o.cvr << 24));
+    const uint32_t w1 = ufirst32((uint32_t)o.swap | ((uint32_t)o.cls << 8) | ((uint32_t)o.gen << 16));
+    u.M = w0 & 255u;
+    u.lo = (w0 >> 8) & 255u;
+    u.cmr = (w0 >> 16) & 255u;
+    u.cvr = w0 >> 24;
+    u.swap = w1 & 255u;
+    u.cls = (w1 >> 8) & 255u;
+    u.gen = (w1 >> 16) & 255u;
+    u.pgate = (int32_t)ufirst32((uint32_t)o.pgate);
+    u.amask = ufirst32((uint32_t)o.amask);
+    return u;
+}
+
+// register flip masks of more than one bit (excitations): the generic,
+// predicated path; one-bit masks take the fast paths below
+#define VQE_MASK_CASES(X) X(3) X(5) X(6) X(7) X(9) X(10) X(11) X(12) X(13) X(14) X(15)
 
 template <int RB>
 __device__ __forceinline__ void dispatch_fwd(int M, double2 (&x)[1 << RB], const Mat2 &v, int cls, int lo, int cmr,
@@ -585,6 +618,157 @@ __device__ __forceinline__ double dispatch_rev(int M, double2 (&x)[1 << RB], dou
     default: break;
     }
     return 0.0;
+}
+
+// ---- one-bit register masks: every one-qubit gate and the targets of CNOT
+// and CZ.  The pairs (i, i ^ M) to update come as a host-computed bit mask
+// (register controls folded in); ALL marks the mask with every pair set, so
+// the common uncontrolled gate runs with no per-pair test.
+template <int RB, int M>
+__host__ __device__ constexpr uint32_t full_pairs()
+{
+    uint32_t f = 0;
+    for (int i = 0; i < (1 << RB); ++i)
+        if (!(i & M)) f |= 1u << i;
+    return f;
+}
+
+template <int CLS>
+__device__ __forceinline__ void pair_fwd(double2 &a, double2 &b, const Mat2 &v)
+{
+    const double2 p = a, q = b;
+    if (CLS == CLS_SWAP) {
+        a = q;
+        b = p;
+    } else if (CLS == CLS_DIAG) {
+        a = cmul(v.a, p);
+        b = cmul(v.d, q);
+    } else if (CLS == CLS_REAL) {
+        a = make_double2(fma(v.a.x, p.x, v.b.x * q.x), fma(v.a.x, p.y, v.b.x * q.y));
+        b = make_double2(fma(v.c.x, p.x, v.d.x * q.x), fma(v.c.x, p.y, v.d.x * q.y));
+    } else {
+        a = cadd(cmul(v.a, p), cmul(v.b, q));
+        b = cadd(cmul(v.c, p), cmul(v.d, q));
+    }
+}
+
+template <int RB, int M, int CLS, bool ALL>
+__device__ __forceinline__ void pairs1_fwd(double2 (&x)[1 << RB], const Mat2 &v, uint32_t amask)
+{
+#pragma unroll
+    for (int i = 0; i < (1 << RB); ++i) {
+        if (i & M) continue;
+        if (!ALL && !((amask >> i) & 1u)) continue;
+        pair_fwd<CLS>(x[i], x[i ^ M], v);
+    }
+}
+
+template <int RB, int CLS>
+__device__ __forceinline__ void apply1_fwd(uint32_t M, double2 (&x)[1 << RB], const Mat2 &v, uint32_t amask)
+{
+#define VQE_ONE(m)                                                                  \
+    if (M == m) {                                                                   \
+        if (amask == full_pairs<RB, m>())                                           \
+            pairs1_fwd<RB, m, CLS, true>(x, v, amask);                              \
+        else                                                                        \
+            pairs1_fwd<RB, m, CLS, false>(x, v, amask);                             \
+        return;                                                                     \
+    }
+    VQE_ONE(1)
+    VQE_ONE(2)
+    VQE_ONE(4)
+    if constexpr (RB > 3) {
+        VQE_ONE(8)
+    }
+#undef VQE_ONE
+}
+
+// gradient term Im<la|G|a> + ... of one pair in the op's (first, second)
+// orientation (sgn = -1 when the lower register holds the second element)
+template <int GEN>
+__device__ __forceinline__ double pair_grad(const double2 &a, const double2 &b, const double2 &la, const double2 &lb,
+                                            double sgn)
+{
+    if (GEN == GEN_Y) return sgn * ((lb.x * a.x + lb.y * a.y) - (la.x * b.x + la.y * b.y));
+    if (GEN == GEN_X) return (la.x * b.y - la.y * b.x) + (lb.x * a.y - lb.y * a.x);
+    if (GEN == GEN_Z) return sgn * ((la.x * a.y - la.y * a.x) - (lb.x * b.y - lb.y * b.x));
+    return 0.0;
+}
+
+// gradient term of one pair for a runtime generator (three forms, selected)
+__device__ __forceinline__ double pair_grad_rt(int gen, const double2 &a, const double2 &b, const double2 &la,
+                                               const double2 &lb, double sgn)
+{
+    const double gy = sgn * ((lb.x * a.x + lb.y * a.y) - (la.x * b.x + la.y * b.y));
+    const double gx = (la.x * b.y - la.y * b.x) + (lb.x * a.y - lb.y * a.x);
+    const double gz = sgn * ((la.x * a.y - la.y * a.x) - (lb.x * b.y - lb.y * b.x));
+    return gen == GEN_Y ? gy : (gen == GEN_X ? gx : (gen == GEN_Z ? gz : 0.0));
+}
+
+template <int RB, int M, int CLS>
+__device__ __forceinline__ double pairs1_rev(double2 (&x)[1 << RB], double2 (&l)[1 << RB], const Mat2 &w,
+                                             uint32_t amask, int gen, double sgn)
+{
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < (1 << RB); ++i) {
+        if (i & M) continue;
+        if (!((amask >> i) & 1u)) continue;
+        acc += pair_grad_rt(gen, x[i], x[i ^ M], l[i], l[i ^ M], sgn);
+        pair_fwd<CLS>(x[i], x[i ^ M], w);
+        pair_fwd<CLS>(l[i], l[i ^ M], w);
+    }
+    return acc;
+}
+
+template <int RB, int CLS>
+__device__ __forceinline__ double apply1_rev(uint32_t M, double2 (&x)[1 << RB], double2 (&l)[1 << RB],
+                                             const Mat2 &w, uint32_t amask, int gen, double sgn)
+{
+    if (M == 1) return pairs1_rev<RB, 1, CLS>(x, l, w, amask, gen, sgn);
+    if (M == 2) return pairs1_rev<RB, 2, CLS>(x, l, w, amask, gen, sgn);
+    if (M == 4) return pairs1_rev<RB, 4, CLS>(x, l, w, amask, gen, sgn);
+    if constexpr (RB > 3)
+        if (M == 8) return pairs1_rev<RB, 8, CLS>(x, l, w, amask, gen, sgn);
+    return 0.0;
+}
+
+// one forward op on a thread's sub-cube (o wave-uniform)
+template <int RB>
+__device__ __forceinline__ void apply_fwd(const UStageOp &o, double2 (&x)[1 << RB], const Mat2 &v, uint32_t bl)
+{
+    const bool tpred = o.cmt == 0 || (bl & o.cmt) == o.cvt;  // control on a sub-cube bit
+    if ((o.M & (o.M - 1)) == 0) {
+        if (!tpred) return;
+        switch (o.cls) {
+        case CLS_SWAP: apply1_fwd<RB, CLS_SWAP>(o.M, x, v, o.amask); break;
+        case CLS_DIAG: apply1_fwd<RB, CLS_DIAG>(o.M, x, v, o.amask); break;
+        case CLS_REAL: apply1_fwd<RB, CLS_REAL>(o.M, x, v, o.amask); break;
+        default: apply1_fwd<RB, CLS_GENERAL>(o.M, x, v, o.amask); break;
+        }
+    } else {
+        dispatch_fwd<RB>((int)o.M, x, v, (int)o.cls, (int)o.lo, (int)o.cmr, (int)o.cvr, tpred);
+    }
+}
+
+// one reverse op: returns this thread's gradient partial (0 for fixed gates)
+template <int RB>
+__device__ __forceinline__ double apply_rev(const UStageOp &o, double2 (&x)[1 << RB], double2 (&l)[1 << RB],
+                                            const Mat2 &w, uint32_t bl, bool have)
+{
+    const bool tpred = have && (o.cmt == 0 || (bl & o.cmt) == o.cvt);
+    const double sgn = o.swap ? -1.0 : 1.0;
+    const int gen = o.pgate >= 0 ? (int)o.gen : GEN_NONE;
+    if ((o.M & (o.M - 1)) == 0) {
+        if (!tpred) return 0.0;
+        switch (o.cls) {
+        case CLS_REAL: return apply1_rev<RB, CLS_REAL>(o.M, x, l, w, o.amask, gen, sgn);
+        case CLS_DIAG: return apply1_rev<RB, CLS_DIAG>(o.M, x, l, w, o.amask, gen, sgn);
+        case CLS_SWAP: return apply1_rev<RB, CLS_SWAP>(o.M, x, l, w, o.amask, gen, sgn);
+        default: return apply1_rev<RB, CLS_GENERAL>(o.M, x, l, w, o.amask, gen, sgn);
+        }
+    }
+    return dispatch_rev<RB>((int)o.M, x, l, w, (int)o.cls, gen, (int)o.lo, (int)o.cmr, (int)o.cvr, tpred, sgn);
 }
 
 template <int RB>
@@ -632,7 +816,14 @@ __device__ __forceinline__ void load_stage_ctl(const StageDesc *__restrict__ sta
         sctl[s].n_param_ops = stages[s].n_param_ops;
     }
     const int nops = nstages ? stages[nstages - 1].op_begin + stages[nstages - 1].op_count - ob0 : 0;
-    for (int q = threadIdx.x; q < nops; q += blockDim.x) {
+    for (int q = threadIdx.x; q <= nops; q += blockDim.x) {
+        if (q == nops) {  // padding entry: the op loop reads one op ahead
+            StageOp z = {};
+            z.M = 1;
+            sop_l[q] = z;
+            mat_l[q] = Mat2{};
+            continue;
+        }
         const StageOp o = sops[ob0 + q];
         sop_l[q] = o;
         const Mat2 v = stage_matrix(Mx, o.gate, o.swap);
@@ -642,7 +833,7 @@ __device__ __forceinline__ void load_stage_ctl(const StageDesc *__restrict__ sta
 
 __host__ __device__ inline size_t stage_ctl_bytes(int nstages, int nops)
 {
-    return (size_t)nstages * sizeof(StageCtl) + (size_t)nops * (sizeof(StageOp) + sizeof(Mat2));
+    return (size_t)nstages * sizeof(StageCtl) + (size_t)(nops + 1) * (sizeof(StageOp) + sizeof(Mat2));
 }
 
 template <int RB>
@@ -655,8 +846,8 @@ __global__ __launch_bounds__(kThreads) void k_forward_staged(
     double2 *tile = reinterpret_cast<double2 *>(smem);
     uint64_t *hoff = reinterpret_cast<uint64_t *>(smem + (16u << k));
     Mat2 *mat_l = reinterpret_cast<Mat2 *>(hoff + (1u << (k - c)));
-    StageOp *sop_l = reinterpret_cast<StageOp *>(mat_l + nops);
-    StageCtl *sctl = reinterpret_cast<StageCtl *>(sop_l + nops);
+    StageOp *sop_l = reinterpret_cast<StageOp *>(mat_l + nops + 1);  // + one padding op
+    StageCtl *sctl = reinterpret_cast<StageCtl *>(sop_l + nops + 1);
     const int tid = threadIdx.x;
     const uint64_t dim = 1ull << n;
     double2 *st = psi + (uint64_t)blockIdx.y * dim;
@@ -680,10 +871,15 @@ __global__ __launch_bounds__(kThreads) void k_forward_staged(
                 double2 x[1 << RB];
 #pragma unroll
                 for (int i = 0; i < (1 << RB); ++i) x[i] = tile[swz(bl | roff[i])];
+                StageOp nop = sop_l[sc.op_begin];
+                Mat2 nmat = mat_l[sc.op_begin];
                 for (int q = sc.op_begin; q < sc.op_begin + sc.op_count; ++q) {
-                    const StageOp o = sop_l[q];
+                    const UStageOp o = uniform_sop(nop);
+                    const Mat2 v = nmat;
+                    nop = sop_l[q + 1];  // the next op's record, read while this op runs
+                    nmat = mat_l[q + 1];
                     if ((base & o.cmo) != o.cvo) continue;
-                    dispatch_fwd<RB>(o.M, x, mat_l[q], o.cls, o.lo, o.cmr, o.cvr, (bl & o.cmt) == o.cvt);
+                    apply_fwd<RB>(o, x, v, bl);
                 }
 #pragma unroll
                 for (int i = 0; i < (1 << RB); ++i) tile[swz(bl | roff[i])] = x[i];
@@ -708,8 +904,8 @@ __global__ __launch_bounds__(kThreads) void k_reverse_staged(
     uint64_t *hoff = reinterpret_cast<uint64_t *>(smem + (32u << k));
     double *red = reinterpret_cast<double *>(hoff + (1u << (k - c)));
     Mat2 *mat_l = reinterpret_cast<Mat2 *>(red + 4 * (size_t)(n_param_ops > 0 ? n_param_ops : 1));
-    StageOp *sop_l = reinterpret_cast<StageOp *>(mat_l + nops);
-    StageCtl *sctl = reinterpret_cast<StageCtl *>(sop_l + nops);
+    StageOp *sop_l = reinterpret_cast<StageOp *>(mat_l + nops + 1);  // + one padding op
+    StageCtl *sctl = reinterpret_cast<StageCtl *>(sop_l + nops + 1);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint64_t dim = 1ull << n;
     double2 *sp = psi + (uint64_t)blockIdx.y * dim;
@@ -743,15 +939,17 @@ __global__ __launch_bounds__(kThreads) void k_reverse_staged(
                     l[i] = have ? tl[swz(bl | roff[i])] : make_double2(0.0, 0.0);
                 }
                 int slot = slot0;
+                StageOp nop = sop_l[sc.op_begin];
+                Mat2 nmat = mat_l[sc.op_begin];
                 for (int q = sc.op_begin; q < sc.op_begin + sc.op_count; ++q) {
-                    const StageOp o = sop_l[q];
+                    const UStageOp o = uniform_sop(nop);
+                    const Mat2 w = nmat;
+                    nop = sop_l[q + 1];  // the next op's record, read while this op runs
+                    nmat = mat_l[q + 1];
                     const int my_slot = slot;
                     if (o.pgate >= 0) ++slot;
                     if ((base & o.cmo) != o.cvo) continue;
-                    const double sgn = o.swap ? -1.0 : 1.0;
-                    const int gen = o.pgate >= 0 ? o.gen : GEN_NONE;
-                    double acc = dispatch_rev<RB>(o.M, x, l, mat_l[q], o.cls, gen, o.lo, o.cmr, o.cvr,
-                                              have && ((bl & o.cmt) == o.cvt), sgn);
+                    double acc = apply_rev<RB>(o, x, l, w, bl, have);
                     if (o.pgate >= 0) {
                         acc = wave_sum(acc);
                         if (lane == 0) red[my_slot * 4 + wave] += acc;
@@ -781,6 +979,153 @@ __global__ __launch_bounds__(kThreads) void k_reverse_staged(
             partials[((size_t)blockIdx.y * n_pgates + pg) * W + blockIdx.x] = v;
             ++slot;
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fused stages (forward passes of one-qubit gates, X and CNOT).
+//
+// fused[inst][slot] = product of the slot's gate matrices in application
+// order (identity for an empty slot).
+__global__ void k_fuse_mats(const int32_t *__restrict__ slot_off, const int32_t *__restrict__ slot_gate, int n_slots,
+                            const double2 *__restrict__ mats, int n_gates, int64_t batch, double2 *__restrict__ fused)
+{
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= batch * n_slots) return;
+    const int64_t inst = w / n_slots;
+    const int slot = (int)(w - inst * n_slots);
+    double2 a = make_double2(1.0, 0.0), b = make_double2(0.0, 0.0), c = b, d = a;  // [[a, b], [c, d]]
+    for (int e = slot_off[slot]; e < slot_off[slot + 1]; ++e) {
+        const double2 *U = mats + ((size_t)inst * n_gates + slot_gate[e]) * 4;
+        const double2 u00 = U[0], u01 = U[1], u10 = U[2], u11 = U[3];
+        const double2 na = cadd(cmul(u00, a), cmul(u01, c)), nb = cadd(cmul(u00, b), cmul(u01, d));
+        const double2 nc = cadd(cmul(u10, a), cmul(u11, c)), nd = cadd(cmul(u10, b), cmul(u11, d));
+        a = na;
+        b = nb;
+        c = nc;
+        d = nd;
+    }
+    double2 *o = fused + (size_t)w * 4;
+    o[0] = a;
+    o[1] = b;
+    o[2] = c;
+    o[3] = d;
+}
+
+// general 2x2 on register bit B (compile time) of a 16-amplitude sub-cube
+template <int B>
+__device__ __forceinline__ void fused_bit(double2 (&x)[16], const Mat2 &v)
+{
+    constexpr int M = 1 << B;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        if (i & M) continue;
+        const double2 p = x[i], q = x[i | M];
+        x[i] = cadd(cmul(v.a, p), cmul(v.b, q));
+        x[i | M] = cadd(cmul(v.c, p), cmul(v.d, q));
+    }
+}
+
+// one fused stage for this thread's sub-cube u (na active register bits;
+// PERM: the CNOT / X network moves the amplitudes on the way back to LDS)
+template <int NA, bool PERM>
+__device__ __forceinline__ void fused_stage(double2 *tile, const FusedStage &fs, const Mat2 *fm, int nsub,
+                                            uint32_t ctile)
+{
+    const int u = threadIdx.x;
+    const bool have = u < nsub;
+    uint32_t bl = 0, lbl = 0;
+#pragma unroll
+    for (int j = 0; j < 12; ++j)
+        if ((u >> j) & 1) {
+            bl |= 1u << fs.cpos[j];
+            lbl ^= fs.lc[j];
+        }
+    uint32_t roff[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+        roff[i] = ((i & 1) ? 1u << fs.rpos[0] : 0u) | ((i & 2) ? 1u << fs.rpos[1] : 0u) |
+                  ((i & 4) ? 1u << fs.rpos[2] : 0u) | ((i & 8) ? 1u << fs.rpos[3] : 0u);
+    double2 x[16];
+    if (have) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) x[i] = tile[swz(bl | roff[i])];
+        if (NA > 0) fused_bit<0>(x, fm[0]);
+        if (NA > 1) fused_bit<1>(x, fm[1]);
+        if (NA > 2) fused_bit<2>(x, fm[2]);
+        if (NA > 3) fused_bit<3>(x, fm[3]);
+    }
+    if (PERM) {
+        __syncthreads();  // every sub-cube is read before any amplitude moves
+        if (have) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) tile[swz(lbl ^ fs.lr[i] ^ ctile)] = x[i];
+        }
+    } else if (have) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) tile[swz(bl | roff[i])] = x[i];
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_forward_fused(const TileGeom *__restrict__ gp, int n, int k, int c,
+                                                            int nout, const FusedStage *__restrict__ fstages,
+                                                            int nstages, const FusedCond *__restrict__ fconds,
+                                                            const double2 *__restrict__ fused, int n_slots,
+                                                            double2 *__restrict__ psi, int64_t tiles)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    double2 *tile = reinterpret_cast<double2 *>(smem);
+    uint64_t *hoff = reinterpret_cast<uint64_t *>(smem + (16u << k));
+    Mat2 *fm = reinterpret_cast<Mat2 *>(hoff + (1u << (k - c)));  // 4 per stage
+    FusedStage *fs_l = reinterpret_cast<FusedStage *>(fm + 4 * nstages);
+    const int tid = threadIdx.x;
+    const uint64_t dim = 1ull << n;
+    double2 *st = psi + (uint64_t)blockIdx.y * dim;
+    const int T = 1 << k;
+    const int nsub = 1 << (k - 4);
+    fill_hoff(gp, k, c, hoff);
+    const int slot0 = nstages ? fstages[0].slot : 0;
+    const double2 *F = fused + ((size_t)blockIdx.y * n_slots + slot0) * 4;
+    for (int i = tid; i < 4 * nstages; i += kThreads) {
+        Mat2 v;
+        v.a = F[4 * i];
+        v.b = F[4 * i + 1];
+        v.c = F[4 * i + 2];
+        v.d = F[4 * i + 3];
+        fm[i] = v;
+    }
+    for (int i = tid; i < nstages; i += kThreads) fs_l[i] = fstages[i];
+    __syncthreads();
+    for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+        const uint64_t base = tile_base(gp, nout, t);
+        tile_in<16, true>(tile, st, base, hoff, T, c);
+        __syncthreads();
+        for (int s = 0; s < nstages; ++s) {
+            const FusedStage &fs = fs_l[s];
+            const int na = (int)__builtin_amdgcn_readfirstlane((uint32_t)fs.na);
+            const int perm = (int)__builtin_amdgcn_readfirstlane((uint32_t)fs.perm);
+            uint32_t ctile = fs.c0;
+            for (int q = 0; q < fs.cond_count; ++q) {
+                const FusedCond fc = fconds[fs.cond_begin + q];
+                if ((base & fc.cmo) == fc.cvo) ctile ^= fc.xmask;
+            }
+            const Mat2 *m4 = fm + 4 * s;
+            switch (na * 2 + perm) {
+            case 0: fused_stage<0, false>(tile, fs, m4, nsub, ctile); break;
+            case 1: fused_stage<0, true>(tile, fs, m4, nsub, ctile); break;
+            case 2: fused_stage<1, false>(tile, fs, m4, nsub, ctile); break;
+            case 3: fused_stage<1, true>(tile, fs, m4, nsub, ctile); break;
+            case 4: fused_stage<2, false>(tile, fs, m4, nsub, ctile); break;
+            case 5: fused_stage<2, true>(tile, fs, m4, nsub, ctile); break;
+            case 6: fused_stage<3, false>(tile, fs, m4, nsub, ctile); break;
+            case 7: fused_stage<3, true>(tile, fs, m4, nsub, ctile); break;
+            case 8: fused_stage<4, false>(tile, fs, m4, nsub, ctile); break;
+            default: fused_stage<4, true>(tile, fs, m4, nsub, ctile); break;
+            }
+            __syncthreads();
+        }
+        tile_out<16, true>(tile, st, base, hoff, T, c);
+        __syncthreads();
     }
 }
 
@@ -1118,6 +1463,33 @@ hipError_t launch_reverse_pass(const PassPlan &pp, const TileGeom *geom_dev, con
     hipLaunchKernelGGL(k_reverse_pass, dim3(wg_per_inst, (unsigned)batch), dim3(kThreads), lds, s, geom_dev,
                        g.n, g.k, g.c, g.nout, ops + pp.op_begin, pp.op_count, pp.n_param_ops, mats, n_gates,
                        psi, lam, tiles, partials, n_pgates);
+    return hipGetLastError();
+}
+
+hipError_t launch_fuse_mats(const int32_t *slot_off, const int32_t *slot_gate, int n_slots, const double2 *mats,
+                            int n_gates, int64_t batch, double2 *fused, hipStream_t s)
+{
+    const int64_t total = batch * n_slots;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fuse_mats, dim3(grid_for(total, 128)), dim3(128), 0, s, slot_off, slot_gate, n_slots, mats,
+                       n_gates, batch, fused);
+    return hipGetLastError();
+}
+
+hipError_t launch_forward_fused(const PassPlan &pp, const TileGeom *geom_dev, const FusedStage *fstages,
+                                const FusedCond *fconds, const double2 *fused, int n_slots, double2 *psi,
+                                int64_t batch, int wg_max, hipStream_t s)
+{
+    const TileGeom &g = pp.geom;
+    if (g.k < 8 || g.k > 12) return hipErrorInvalidValue;
+    const int64_t tiles = 1ll << g.nout;
+    const int W = (int)std::min<int64_t>(tiles, wg_max);
+    const size_t lds = fwd_lds(g) + (size_t)pp.fstage_count * (4 * sizeof(Mat2) + sizeof(FusedStage));
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    hipError_t e = ensure_lds(k_forward_fused, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_forward_fused, dim3(W, (unsigned)batch), dim3(kThreads), lds, s, geom_dev, g.n, g.k, g.c,
+                       g.nout, fstages + pp.fstage_begin, pp.fstage_count, fconds, fused, n_slots, psi, tiles);
     return hipGetLastError();
 }
 

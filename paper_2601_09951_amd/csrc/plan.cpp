@@ -180,7 +180,160 @@ static void free_plan(Context *ctx, CircPlan *p)
         dev_free(ctx, p->geoms);
         dev_free(ctx, p->stages);
         dev_free(ctx, p->sops);
+        dev_free(ctx, p->fstages);
+        dev_free(ctx, p->fconds);
+        dev_free(ctx, p->fslot_off);
+        dev_free(ctx, p->fslot_gate);
     }
+}
+
+// Fused stages of a forward pass (see FusedStage).  Accepts passes of
+// uncontrolled one-qubit gates (RX, RY, RZ, H), X and CNOT (target in the
+// tile, control anywhere); returns false otherwise.  The ops are walked in
+// order: one-qubit gates gather per qubit until a gate meets a qubit that a
+// pending CNOT / X already touched; then the gathered qubits are emitted in
+// stages of four (one-qubit gates on different qubits commute) and the
+// network goes to the last of them as its store map.
+static bool build_fused(const Circ *C, const std::vector<int> &take, const std::vector<int> &tile, int keff,
+                        CircPlan *plan, PassPlan &pp)
+{
+    if (keff < kStageMinK || keff > 12) return false;
+    const uint64_t tmask = mask_of(tile);
+    struct Perm {
+        int kind;          // 0: CNOT inside the tile, 1: X, 2: X under a control outside the tile
+        int t, c;          // tile-local target, control
+        uint64_t cmo, cvo;
+    };
+    for (int g : take) {
+        const GateHost &h = C->gates[g];
+        const bool one = h.kind == VQE_GATE_RX || h.kind == VQE_GATE_RY || h.kind == VQE_GATE_RZ ||
+                         h.kind == VQE_GATE_H || h.kind == VQE_GATE_X;
+        if (one && h.cmask == 0) continue;
+        if (h.kind == VQE_GATE_CNOT && popc(h.m) == 1 && popc(h.cmask) == 1 && h.cval == h.cmask) continue;
+        return false;
+    }
+    std::vector<std::vector<int>> oneq(keff);  // gates per tile bit, in order
+    std::vector<int> order;                    // bits with gates, in order of appearance
+    std::vector<Perm> perm;
+    uint32_t touched = 0;
+    const int st0 = (int)plan->host_fstages.size();
+
+    auto flush = [&]() {
+        if (order.empty() && perm.empty()) return;
+        // the network as v -> L v ^ c0, plus conditional constants
+        uint32_t col[16];
+        for (int b = 0; b < 16; ++b) col[b] = b < keff ? 1u << b : 0u;
+        uint32_t c0 = 0;
+        std::vector<FusedCond> conds;
+        auto cnot = [](uint32_t v, int c, int t) { return ((v >> c) & 1u) ? v ^ (1u << t) : v; };
+        for (const Perm &q : perm) {
+            if (q.kind == 0) {
+                for (int b = 0; b < keff; ++b) col[b] = cnot(col[b], q.c, q.t);
+                c0 = cnot(c0, q.c, q.t);
+                for (FusedCond &f : conds) f.xmask = cnot(f.xmask, q.c, q.t);
+            } else if (q.kind == 1) {
+                c0 ^= 1u << q.t;
+            } else {
+                FusedCond f;
+                std::memset(&f, 0, sizeof(f));
+                f.cmo = q.cmo;
+                f.cvo = q.cvo;
+                f.xmask = 1u << q.t;
+                conds.push_back(f);
+            }
+        }
+        bool ident = c0 == 0 && conds.empty();
+        for (int b = 0; b < keff; ++b) ident = ident && col[b] == (1u << b);
+        // stages of up to four gathered qubits; the network rides on the last
+        const size_t ngroups = std::max<size_t>(1, (order.size() + 3) / 4);
+        for (size_t gi = 0; gi < ngroups; ++gi) {
+            FusedStage fs;
+            std::memset(&fs, 0, sizeof(fs));
+            std::vector<int> act(order.begin() + std::min(order.size(), 4 * gi),
+                                 order.begin() + std::min(order.size(), 4 * gi + 4));
+            uint32_t R = 0;
+            for (int b : act) R |= 1u << b;
+            std::vector<int> rb = act;
+            for (int b = 0; b < keff && (int)rb.size() < 4; ++b)
+                if (!((R >> b) & 1)) {
+                    R |= 1u << b;
+                    rb.push_back(b);
+                }
+            std::vector<int> cb;
+            for (int b = 0; b < keff; ++b)
+                if (!((R >> b) & 1)) cb.push_back(b);
+            for (int i = 0; i < 4; ++i) fs.rpos[i] = (uint8_t)rb[i];
+            for (size_t j = 0; j < cb.size(); ++j) fs.cpos[j] = (uint8_t)cb[j];
+            fs.na = (int)act.size();
+            fs.slot = plan->n_fslots();
+            for (int i = 0; i < 4; ++i) {  // fused matrices: identity (empty list) past na
+                if (i < fs.na)
+                    for (int g : oneq[rb[i]]) plan->host_fslot_gate.push_back(g);
+                plan->host_fslot_off.push_back((int32_t)plan->host_fslot_gate.size());
+            }
+            const bool last = gi + 1 == ngroups;
+            if (last && !ident) {
+                fs.perm = 1;
+                fs.c0 = (uint16_t)c0;
+                for (int i = 0; i < 16; ++i) {
+                    uint32_t v = 0;
+                    for (int j = 0; j < 4; ++j)
+                        if ((i >> j) & 1) v ^= col[rb[j]];
+                    fs.lr[i] = (uint16_t)v;
+                }
+                for (size_t j = 0; j < cb.size(); ++j) fs.lc[j] = (uint16_t)col[cb[j]];
+                fs.cond_begin = (int)plan->host_fconds.size();
+                fs.cond_count = (int)conds.size();
+                for (const FusedCond &f : conds) plan->host_fconds.push_back(f);
+            } else {
+                for (int i = 0; i < 16; ++i) {
+                    uint32_t v = 0;
+                    for (int j = 0; j < 4; ++j)
+                        if ((i >> j) & 1) v |= 1u << rb[j];
+                    fs.lr[i] = (uint16_t)v;
+                }
+                for (size_t j = 0; j < cb.size(); ++j) fs.lc[j] = (uint16_t)(1u << cb[j]);
+                fs.cond_begin = (int)plan->host_fconds.size();
+            }
+            plan->host_fstages.push_back(fs);
+        }
+        for (int b : order) oneq[b].clear();
+        order.clear();
+        perm.clear();
+        touched = 0;
+    };
+
+    for (int g : take) {
+        const GateHost &h = C->gates[g];
+        const int t = __builtin_ctz(compress(h.m, tile));
+        if (h.kind == VQE_GATE_CNOT || h.kind == VQE_GATE_X) {
+            Perm q;
+            q.t = t;
+            q.c = -1;
+            q.cmo = q.cvo = 0;
+            if (h.kind == VQE_GATE_X) {
+                q.kind = 1;
+            } else if (h.cmask & tmask) {
+                q.kind = 0;
+                q.c = __builtin_ctz(compress(h.cmask & tmask, tile));
+                touched |= 1u << q.c;
+            } else {
+                q.kind = 2;
+                q.cmo = h.cmask;
+                q.cvo = h.cval;
+            }
+            touched |= 1u << t;
+            perm.push_back(q);
+            continue;
+        }
+        if ((touched >> t) & 1) flush();
+        if (oneq[t].empty()) order.push_back(t);
+        oneq[t].push_back(g);
+    }
+    flush();
+    pp.fstage_begin = st0;
+    pp.fstage_count = (int)plan->host_fstages.size() - st0;
+    return pp.fstage_count > 0;
 }
 
 // Split a pass's ops (tile-local, in order) into register stages of
@@ -271,6 +424,11 @@ static bool build_stages(const Circ *C, const std::vector<int> &take, const std:
             so.pgate = C->pgate_of_gate[take[q]];
             so.cls = (uint8_t)h.cls;
             so.gen = (uint8_t)h.gen;
+            {
+                const uint32_t hbm = 1u << (31 - __builtin_clz((uint32_t)so.M));
+                for (uint32_t i = 0; i < (1u << sd.nbits); ++i)
+                    if (!(i & hbm) && (i & so.M) == so.lo && (i & so.cmr) == so.cvr) so.amask |= (uint16_t)(1u << i);
+            }
             if (so.pgate >= 0) ++nparam;
             plan->host_sops.push_back(so);
             done[q] = 1;
@@ -369,6 +527,18 @@ CircPlan *get_circ_plan(Circ *C, bool reverse, int k, int c, int *rc)
             done[g] = 1;
             --remaining;
         }
+        if (!reverse) {
+            const size_t f0 = plan->host_fstages.size(), c0 = plan->host_fconds.size();
+            const size_t s0 = plan->host_fslot_off.size(), g0 = plan->host_fslot_gate.size();
+            if (!build_fused(C, take, tile, keff, plan.get(), pp)) {
+                plan->host_fstages.resize(f0);
+                plan->host_fconds.resize(c0);
+                plan->host_fslot_off.resize(s0);
+                plan->host_fslot_gate.resize(g0);
+                pp.fstage_begin = (int)f0;
+                pp.fstage_count = 0;
+            }
+        }
         if (keff >= kStageMinK) {
             const size_t st0 = plan->host_stages.size(), so0 = plan->host_sops.size();
             if (!build_stages(C, take, tile, keff, plan->stage_bits, plan.get(), pp)) {
@@ -391,6 +561,17 @@ CircPlan *get_circ_plan(Circ *C, bool reverse, int k, int c, int *rc)
             r = upload(C->ctx, plan->stages, plan->host_stages.data(), plan->host_stages.size() * sizeof(StageDesc));
         if (!r && !plan->host_sops.empty())
             r = upload(C->ctx, plan->sops, plan->host_sops.data(), plan->host_sops.size() * sizeof(StageOp));
+        if (!r && !plan->host_fstages.empty())
+            r = upload(C->ctx, plan->fstages, plan->host_fstages.data(),
+                       plan->host_fstages.size() * sizeof(FusedStage));
+        if (!r && !plan->host_fconds.empty())
+            r = upload(C->ctx, plan->fconds, plan->host_fconds.data(), plan->host_fconds.size() * sizeof(FusedCond));
+        if (!r && plan->n_fslots() > 0)
+            r = upload(C->ctx, plan->fslot_off, plan->host_fslot_off.data(),
+                       plan->host_fslot_off.size() * sizeof(int32_t));
+        if (!r && !plan->host_fslot_gate.empty())
+            r = upload(C->ctx, plan->fslot_gate, plan->host_fslot_gate.data(),
+                       plan->host_fslot_gate.size() * sizeof(int32_t));
         if (r) {
             free_plan(C->ctx, plan.get());
             *rc = r;

@@ -66,9 +66,12 @@ class Context:
         """0: persistent single-launch loop when the state fits on chip; 1: per-step launches."""
         self.check(lib().vqe_ctx_set_loop_mode(self._h, int(mode)))
 
-    def set_staged(self, staged: bool):
-        """Register-staged state passes (default) or one LDS round trip per gate."""
-        self.check(lib().vqe_ctx_set_staged(self._h, int(bool(staged))))
+    def set_staged(self, staged):
+        """Pass kernels: 2 or True (default): fused stages where a forward pass
+        allows them, register stages elsewhere; 1: register stages only;
+        0 or False: one LDS round trip per gate."""
+        mode = 2 if staged is True else (0 if staged is False else int(staged))
+        self.check(lib().vqe_ctx_set_staged(self._h, mode))
 
     def reserve(self, nbytes: int):
         self.check(lib().vqe_ctx_reserve(self._h, int(nbytes)))
@@ -420,12 +423,17 @@ class VQEEnergy(torch.autograd.Function):
 _GEOM = np.dtype([("n", "<i4"), ("k", "<i4"), ("c", "<i4"), ("nout", "<i4"), ("tpos", "u1", 16),
                   ("opos", "u1", 40)])
 _PASS = np.dtype([("geom", _GEOM), ("op_begin", "<i4"), ("op_count", "<i4"), ("n_param_ops", "<i4"),
-                  ("stage_begin", "<i4"), ("stage_count", "<i4"), ("pad", "<i4", 3)])
+                  ("stage_begin", "<i4"), ("stage_count", "<i4"), ("fstage_begin", "<i4"), ("fstage_count", "<i4"),
+                  ("pad", "<i4")])
 _STAGE = np.dtype([("rpos", "u1", 4), ("cpos", "u1", 12), ("op_begin", "<i4"), ("op_count", "<i4"),
                    ("n_param_ops", "<i4"), ("nbits", "<i4"), ("cpack", "<u8"), ("rpack", "<u4"), ("pad2", "<u4")])
 _SOP = np.dtype([("cmo", "<u8"), ("cvo", "<u8"), ("cmt", "<u4"), ("cvt", "<u4"), ("gate", "<i4"),
                  ("pgate", "<i4"), ("M", "u1"), ("lo", "u1"), ("cmr", "u1"), ("cvr", "u1"), ("swap", "u1"),
-                 ("cls", "u1"), ("gen", "u1"), ("pad", "u1")])
+                 ("cls", "u1"), ("gen", "u1"), ("pad", "u1"), ("amask", "<u2"), ("pad2", "<u2", 3)])
+_FSTAGE = np.dtype([("rpos", "u1", 4), ("cpos", "u1", 12), ("lr", "<u2", 16), ("lc", "<u2", 12), ("c0", "<u2"),
+                    ("perm", "<u2"), ("na", "<i4"), ("cond_begin", "<i4"), ("cond_count", "<i4"), ("slot", "<i4"),
+                    ("pad", "<i4")])
+_FCOND = np.dtype([("cmo", "<u8"), ("cvo", "<u8"), ("xmask", "<u4"), ("pad", "<u4")])
 _OP = np.dtype([("m", "<u4"), ("fixed_bits", "<u4"), ("cmask_out", "<u8"), ("cval_out", "<u8"),
                 ("gate", "<i4"), ("pgate", "<i4"), ("cls", "<i2"), ("gen", "<i2"), ("nfix", "i1"),
                 ("fixpos", "u1", 7), ("pad", "<u4")])
@@ -436,7 +444,8 @@ _TERM = np.dtype([("z", "<u8"), ("zloc", "<u4"), ("pad", "<u4"), ("w", "<f8")])
 
 def circuit_plan(ctx: Context, circ: Circuit, reverse: bool = False, stages: bool = False):
     """(passes, ops) structured arrays of the compiled pass schedule
-    (plus (stages, stage_ops) when stages=True)."""
+    (plus (stages, stage_ops) when stages=True; with stages="fused":
+    (passes, ops, fused_stages, fused_conds, slot_offsets, slot_gates))."""
     need = ctypes.c_size_t()
     ctx.check(lib().vqe_circ_plan_export(ctx.handle, circ.handle, int(reverse), None, 0, ctypes.byref(need)))
     buf = np.zeros(need.value, dtype=np.uint8)
@@ -454,6 +463,20 @@ def circuit_plan(ctx: Context, circ: Circuit, reverse: bool = False, stages: boo
     st = buf[off:off + nst * _STAGE.itemsize].view(_STAGE)
     off += nst * _STAGE.itemsize
     sops = buf[off:off + nsop * _SOP.itemsize].view(_SOP)
+    off += nsop * _SOP.itemsize
+    if stages == "fused":
+        fh = buf[off:off + 32].view("<i4")
+        nfs, nfc, nsl, nsg = int(fh[0]), int(fh[2]), int(fh[4]), int(fh[5])
+        assert fh[1] == _FSTAGE.itemsize and fh[3] == _FCOND.itemsize
+        off += 32
+        fst = buf[off:off + nfs * _FSTAGE.itemsize].view(_FSTAGE)
+        off += nfs * _FSTAGE.itemsize
+        fco = buf[off:off + nfc * _FCOND.itemsize].view(_FCOND)
+        off += nfc * _FCOND.itemsize
+        soff = buf[off:off + (nsl + 1) * 4].view("<i4")
+        off += (nsl + 1) * 4
+        sgate = buf[off:off + nsg * 4].view("<i4")
+        return passes, ops, fst, fco, soff, sgate
     if stages:
         return passes, ops, st, sops
     return passes, ops

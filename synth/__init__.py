@@ -390,6 +390,28 @@ def random_circuit(n: int, n_gates: int, seed: int) -> Circuit:
     return _circuit(n, gates, max(p, 1), ref)
 
 
+def random_rotation_cnot_circuit(n: int, n_gates: int, seed: int) -> Circuit:
+    """A random mix of RX, RY, RZ, H, X and CNOT (the gate set of hardware-
+    efficient ansaetze), with some shared parameters."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    kinds = ["RX", "RY", "RZ", "H", "X", "CNOT", "CNOT"]
+    gates = []
+    p = 0
+    for _ in range(n_gates):
+        kind = kinds[int(rng.integers(0, len(kinds)))]
+        ws = tuple(int(w) for w in rng.choice(n, size=GATE_ARITY[kind], replace=False))
+        if kind in PARAMETRIC:
+            if p > 0 and rng.random() < 0.2:
+                gates.append((kind, ws, int(rng.integers(0, p)), 0.0))
+            else:
+                gates.append((kind, ws, p, 0.0))
+                p += 1
+        else:
+            gates.append((kind, ws, -1, 0.0))
+    ref = int(rng.integers(0, 1 << n))
+    return _circuit(n, gates, max(p, 1), ref)
+
+
 def uniform_thetas(n_params: int, batch: int = 1, seed: int = MASTER_SEED) -> np.ndarray:
     """Parameters U(-pi, pi), shape [batch, n_params]."""
     rng = np.random.Generator(np.random.PCG64(seed))

@@ -244,10 +244,16 @@ def _stage_index(st, k):
 
 
 def _stage_pairs(op, nb):
+    """The register pairs the kernel applies: the host-computed mask, checked
+    against the op's pattern and register controls."""
     M, lo, cmr, cvr = int(op["M"]), int(op["lo"]), int(op["cmr"]), int(op["cvr"])
     assert 1 <= M < (1 << nb) and cmr < (1 << nb)
     hb = 1 << (M.bit_length() - 1)
-    return [(i, i ^ M) for i in range(1 << nb) if not (i & hb) and (i & M) == lo and (i & cmr) == cvr]
+    want = [i for i in range(1 << nb) if not (i & hb) and (i & M) == lo and (i & cmr) == cvr]
+    amask = int(op["amask"])
+    have = [i for i in range(1 << nb) if (amask >> i) & 1]
+    assert have == want, (have, want)
+    return [(i, i ^ M) for i in have]
 
 
 def _stage_matrix(U, swap):
@@ -331,3 +337,62 @@ def reverse_staged(passes, stages, sops, psi, lam, mats, n_pgates):
                         arr[:, sidx[:, col]] = cur
         psi[idx], lam[idx] = TP, TL
     return psi, lam, gpart
+
+
+def forward_fused(passes, ops, fstages, fconds, soff, sgate, psi, mats):
+    """Forward passes with fused stages where the plan has them (one fused
+    2x2 per active register bit, then the stage's affine store map), the
+    op-by-op path elsewhere."""
+    psi = psi.copy()
+    for pi in range(len(passes)):
+        ps = passes[pi:pi + 1]
+        nfs = int(ps[0]["fstage_count"])
+        if nfs == 0:
+            psi = forward(ps, ops, psi, mats)
+            continue
+        g = ps[0]["geom"]
+        k = int(g["k"])
+        idx, base = _tile_index(g)
+        T = psi[idx].copy()
+        for fs in fstages[int(ps[0]["fstage_begin"]):int(ps[0]["fstage_begin"]) + nfs]:
+            na = int(fs["na"])
+            rpos = [int(v) for v in fs["rpos"]]
+            cpos = [int(v) for v in fs["cpos"][:k - 4]]
+            assert len(set(rpos + cpos)) == k and max(rpos + cpos) < k
+            roff = np.array([sum(((i >> b) & 1) << rpos[b] for b in range(4)) for i in range(16)])
+            u = np.arange(1 << (k - 4))
+            bl = np.zeros_like(u)
+            for j, p in enumerate(cpos):
+                bl |= ((u >> j) & 1) << p
+            sidx = bl[:, None] | roff[None, :]
+            X = T[:, sidx]  # [tiles, sub-cubes, 16]
+            for j in range(na):
+                F = np.eye(2, dtype=complex)
+                slot = int(fs["slot"]) + j
+                for e in range(int(soff[slot]), int(soff[slot + 1])):
+                    F = mats[int(sgate[e])] @ F
+                M = 1 << j
+                lo = [i for i in range(16) if not (i & M)]
+                a, b = X[:, :, lo].copy(), X[:, :, [i | M for i in lo]].copy()
+                X[:, :, lo] = F[0, 0] * a + F[0, 1] * b
+                X[:, :, [i | M for i in lo]] = F[1, 0] * a + F[1, 1] * b
+            if int(fs["perm"]):
+                lc = [int(v) for v in fs["lc"][:k - 4]]
+                lbl = np.zeros_like(u)
+                for j in range(k - 4):
+                    lbl ^= ((u >> j) & 1) * lc[j]
+                lr = np.array([int(v) for v in fs["lr"]])
+                for t in range(T.shape[0]):
+                    ct = int(fs["c0"])
+                    for fc in fconds[int(fs["cond_begin"]):int(fs["cond_begin"]) + int(fs["cond_count"])]:
+                        if (int(base[t]) & int(fc["cmo"])) == int(fc["cvo"]):
+                            ct ^= int(fc["xmask"])
+                    dst = lbl[:, None] ^ lr[None, :] ^ ct
+                    assert np.unique(dst).size == dst.size == (1 << k), "store map must permute the tile"
+                    new = np.empty(1 << k, dtype=complex)
+                    new[dst.reshape(-1)] = X[t].reshape(-1)
+                    T[t] = new
+            else:
+                T[:, sidx] = X
+        psi[idx] = T
+    return psi

@@ -132,7 +132,28 @@ def test_energy_grad_random_circuits(vqe, ctx, geom, n, seed):
         np.testing.assert_allclose(g[b], go, atol=G_TOL)
 
 
-@pytest.mark.parametrize("staged", [1, 0])
+@pytest.mark.parametrize("n,k,c,seed", [(10, 8, 2, 1), (12, 9, 4, 2), (13, 12, 4, 3), (14, 10, 4, 4),
+                                         (16, 12, 4, 5), (12, 12, 4, 6)])
+def test_fused_forward_passes(vqe, ctx, n, k, c, seed):
+    """Forward passes of rotation / X / H / CNOT circuits as fused stages
+    (CNOT networks folded into data movement), batch of 2, against the oracle."""
+    _say("fused", n, k, c, seed)
+    ctx.set_tile(k, min(k, 12), c)
+    spec = synth.random_rotation_cnot_circuit(n, 120, seed=seed)
+    th = synth.uniform_thetas(spec.n_params, 2, seed=seed)
+    C = vqe.Circuit.from_spec(ctx, spec)
+    passes = vqe.circuit_plan(ctx, C, stages="fused")[0]
+    assert int(passes["fstage_count"].sum()) > 0
+    psi = torch.empty(2, 1 << n, dtype=torch.complex128, device="cuda:0")
+    vqe.prepare_reference(ctx, n, 2, spec.ref_index, psi)
+    vqe.apply_ansatz(ctx, C, dev(th), psi)
+    torch.cuda.synchronize()
+    got = psi.cpu().numpy()
+    for b in range(2):
+        np.testing.assert_allclose(got[b], oracle.state(spec, th[b]), atol=S_TOL)
+
+
+@pytest.mark.parametrize("staged", [2, 1, 0])
 @pytest.mark.parametrize("n,k,c", [(14, 8, 3), (16, 12, 4), (17, 11, 4), (15, 13, 5)])
 def test_hea_energy_grad_multi_tile(vqe, ctx, n, k, c, staged):
     _say("hea", n, k, c, "staged", staged)
@@ -145,7 +166,7 @@ def test_hea_energy_grad_multi_tile(vqe, ctx, n, k, c, staged):
     H = vqe.Hamiltonian.from_sum(ctx, ham)
     e, g = vqe.energy_grad(ctx, C, H, dev(th))
     torch.cuda.synchronize()
-    ctx.set_staged(1)
+    ctx.set_staged(True)
     eo, go = oracle.energy_grad(spec, ham, th[0], "adjoint")
     assert abs(e.item() - eo) < E_TOL
     np.testing.assert_allclose(g.cpu().numpy()[0], go, atol=G_TOL)

@@ -192,3 +192,24 @@ def test_register_stage_schedules(ctx, kind, n, k, c):
     np.testing.assert_allclose(back, ref, atol=1e-12)
     _, g_or = oracle.energy_grad(spec, ham, th, "adjoint")
     np.testing.assert_allclose(_grad_from_parts(spec, gpart), g_or, atol=1e-11)
+
+
+@pytest.mark.parametrize("kind,n,k,c", [("hea", 12, 8, 3), ("hea", 13, 12, 4), ("hea", 14, 11, 4),
+                                         ("rot", 10, 8, 2), ("rot", 12, 9, 4), ("rot", 13, 12, 4),
+                                         ("rot", 14, 10, 4)])
+def test_fused_stage_schedules(ctx, kind, n, k, c):
+    """Fused forward stages (one 2x2 per qubit, CNOT / X folded into the
+    store map) executed on the CPU reproduce the oracle's state."""
+    ctx.set_tile(k, min(k, 12), c)
+    spec = synth.hea_circuit(n, 2) if kind == "hea" else synth.random_rotation_cnot_circuit(n, 90, seed=n + k)
+    th = synth.uniform_thetas(spec.n_params, 1, seed=n)[0]
+    C = vqe.Circuit.from_spec(ctx, spec)
+    mats = emu.gate_matrices(spec, th)
+    passes, ops, fst, fco, soff, sg = vqe.circuit_plan(ctx, C, stages="fused")
+    assert int(passes["fstage_count"].sum()) == len(fst) > 0
+    if kind == "hea":
+        assert (passes["fstage_count"] > 0).all()
+    ref = np.zeros(1 << n, dtype=complex)
+    ref[spec.ref_index] = 1
+    psi = emu.forward_fused(passes, ops, fst, fco, soff, sg, ref, mats)
+    np.testing.assert_allclose(psi, oracle.state(spec, th), atol=1e-12)
