@@ -181,6 +181,15 @@ __device__ __forceinline__ void tile_out2(const double2 *ta, const double2 *tb, 
     }
 }
 
+// Workgroup barrier that orders LDS only: outstanding global loads (a tile
+// prefetch) stay in flight across it, which __syncthreads would drain.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
@@ -1047,6 +1056,8 @@ __device__ __forceinline__ void fused_stage(double2 *tile, const FusedStage &fs,
         roff[i] = ((i & 1) ? 1u << fs.rpos[0] : 0u) | ((i & 2) ? 1u << fs.rpos[1] : 0u) |
                   ((i & 4) ? 1u << fs.rpos[2] : 0u) | ((i & 8) ? 1u << fs.rpos[3] : 0u);
     double2 x[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) x[i] = make_double2(0.0, 0.0);
     if (have) {
 #pragma unroll
         for (int i = 0; i < 16; ++i) x[i] = tile[swz(bl | roff[i])];
@@ -1056,7 +1067,7 @@ __device__ __forceinline__ void fused_stage(double2 *tile, const FusedStage &fs,
         if (NA > 3) fused_bit<3>(x, fm[3]);
     }
     if (PERM) {
-        __syncthreads();  // every sub-cube is read before any amplitude moves
+        lds_barrier();  // every sub-cube is read before any amplitude moves
         if (have) {
 #pragma unroll
             for (int i = 0; i < 16; ++i) tile[swz(lbl ^ fs.lr[i] ^ ctile)] = x[i];
@@ -1086,20 +1097,14 @@ __global__ __launch_bounds__(kThreads) void k_forward_fused(const TileGeom *__re
     fill_hoff(gp, k, c, hoff);
     const int slot0 = nstages ? fstages[0].slot : 0;
     const double2 *F = fused + ((size_t)blockIdx.y * n_slots + slot0) * 4;
-    for (int i = tid; i < 4 * nstages; i += kThreads) {
-        Mat2 v;
-        v.a = F[4 * i];
-        v.b = F[4 * i + 1];
-        v.c = F[4 * i + 2];
-        v.d = F[4 * i + 3];
-        fm[i] = v;
-    }
+    double2 *fmd = reinterpret_cast<double2 *>(fm);
+    for (int i = tid; i < 16 * nstages; i += kThreads) fmd[i] = F[i];  // 4 double2 per matrix
     for (int i = tid; i < nstages; i += kThreads) fs_l[i] = fstages[i];
     __syncthreads();
     for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
         const uint64_t base = tile_base(gp, nout, t);
         tile_in<16, true>(tile, st, base, hoff, T, c);
-        __syncthreads();
+        lds_barrier();
         for (int s = 0; s < nstages; ++s) {
             const FusedStage &fs = fs_l[s];
             const int na = (int)__builtin_amdgcn_readfirstlane((uint32_t)fs.na);
@@ -1122,10 +1127,10 @@ __global__ __launch_bounds__(kThreads) void k_forward_fused(const TileGeom *__re
             case 8: fused_stage<4, false>(tile, fs, m4, nsub, ctile); break;
             default: fused_stage<4, true>(tile, fs, m4, nsub, ctile); break;
             }
-            __syncthreads();
+            lds_barrier();
         }
         tile_out<16, true>(tile, st, base, hoff, T, c);
-        __syncthreads();
+        lds_barrier();
     }
 }
 
