@@ -320,9 +320,11 @@ int vqe_run(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams, i
  *   (xor of lc[j] over the bits j of u) ^ lr[i] ^ c0 ^ (xmask of every
  *   active conditional record) when perm = 1), n_fconds records {uint64
  *   cmo, cvo, uint32 xmask, 0} (active when (tile base & cmo) == cvo),
- *   int32 slot offsets [n_slots + 1] and the gate of each slot entry
- *   (matrices multiplied in list order; an empty slot is the identity).
- *   Forward plans only; reverse plans have no fused stages.  geom = int32 {n, k, c,
+ *   int32 slot offsets [n_slots + 1], the gate of each slot entry and its
+ *   int32 info ((parametric gate index + 1) << 4 | generator).  Forward
+ *   stages multiply a slot's matrices in list order (an empty slot is the
+ *   identity); adjoint stages (nb = 3) undo them one by one, and there the
+ *   store map is the inverse network of the next gates in reversed order.  geom = int32 {n, k, c,
  *   n - k}, uint8 tpos[16]
  *   (index bit of tile bit i), uint8 opos[40] (index bit of tile-number bit
  *   i).  op = uint32 m, uint32 fixed_bits, uint64 cmask_out, uint64

@@ -1197,7 +1197,7 @@ int vqe_circ_plan_export(vqe_ctx_t ctx, vqe_circ_t circ, int reverse, void *buf,
     const size_t need = 32 + p->passes.size() * pass_bytes + p->host_ops.size() * sizeof(OpDesc) +
                         p->host_stages.size() * sizeof(StageDesc) + p->host_sops.size() * sizeof(StageOp) + 32 +
                         p->host_fstages.size() * sizeof(FusedStage) + p->host_fconds.size() * sizeof(FusedCond) +
-                        p->host_fslot_off.size() * 4 + p->host_fslot_gate.size() * 4;
+                        p->host_fslot_off.size() * 4 + p->host_fslot_gate.size() * 8;
     *needed = need;
     if (!buf || buf_bytes < need) return VQE_OK;
     unsigned char *o = (unsigned char *)buf;
@@ -1230,6 +1230,8 @@ int vqe_circ_plan_export(vqe_ctx_t ctx, vqe_circ_t circ, int reverse, void *buf,
     std::memcpy(o, p->host_fslot_off.data(), p->host_fslot_off.size() * 4);
     o += p->host_fslot_off.size() * 4;
     std::memcpy(o, p->host_fslot_gate.data(), p->host_fslot_gate.size() * 4);
+    o += p->host_fslot_gate.size() * 4;
+    std::memcpy(o, p->host_fslot_info.data(), p->host_fslot_info.size() * 4);
     return VQE_OK;
 }
 

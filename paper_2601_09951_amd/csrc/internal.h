@@ -100,7 +100,11 @@ static_assert(sizeof(StageOp) == 48, "StageOp layout");
 // of that qubit's consecutive one-qubit gates) and then moves every amplitude
 // of the tile by the affine map v -> L v ^ c of the CNOT / X network that
 // follows, folded into the LDS store addresses (CNOTs cost no arithmetic).
-// The register bits are rpos[0..na) (active) and rpos[na..4) (padding).
+// The register bits are rpos[0..na) (active) and rpos[na..nb) (padding).
+// Adjoint plans use the same stages with three register bits: each active
+// bit's gates are undone one by one (gradient term, then U^dagger on psi
+// and lambda), after the network that precedes them in the reversed order
+// has been applied by the previous stage's store map.
 struct FusedStage {
     uint8_t rpos[4];
     uint8_t cpos[12];    // the other tile bits, ascending (sub-cube index bits)
@@ -110,8 +114,8 @@ struct FusedStage {
     uint16_t perm;       // 1 when the map is not the identity
     int32_t na;          // active register bits
     int32_t cond_begin, cond_count;  // X conditioned on index bits outside the tile
-    int32_t slot;        // fused matrix of register bit j: slot + j
-    int32_t pad;
+    int32_t slot;        // gate list of register bit j: slot + j
+    int32_t nb;          // register bits: 4 (forward stages) or 3 (adjoint stages)
 };
 static_assert(sizeof(FusedStage) == 96, "FusedStage layout");
 
@@ -227,10 +231,11 @@ struct CircPlan {
     int max_param_ops = 0;
     // fused stages: descriptors, conditional X, and per fused matrix (slot)
     // the CSR list of gates multiplied into it, in application order
-    DevMem fstages, fconds, fslot_off, fslot_gate;
+    DevMem fstages, fconds, fslot_off, fslot_gate, fslot_info;
     std::vector<FusedStage> host_fstages;
     std::vector<FusedCond> host_fconds;
     std::vector<int32_t> host_fslot_off{0}, host_fslot_gate;
+    std::vector<int32_t> host_fslot_info;  // per slot entry: (pgate + 1) << 4 | generator
     int n_fslots() const { return (int)host_fslot_off.size() - 1; }
 };
 

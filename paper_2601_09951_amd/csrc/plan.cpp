@@ -184,6 +184,7 @@ static void free_plan(Context *ctx, CircPlan *p)
         dev_free(ctx, p->fconds);
         dev_free(ctx, p->fslot_off);
         dev_free(ctx, p->fslot_gate);
+        dev_free(ctx, p->fslot_info);
     }
 }
 
@@ -195,7 +196,7 @@ static void free_plan(Context *ctx, CircPlan *p)
 // stages of four (one-qubit gates on different qubits commute) and the
 // network goes to the last of them as its store map.
 static bool build_fused(const Circ *C, const std::vector<int> &take, const std::vector<int> &tile, int keff,
-                        CircPlan *plan, PassPlan &pp)
+                        int RB, CircPlan *plan, PassPlan &pp)
 {
     if (keff < kStageMinK || keff > 12) return false;
     const uint64_t tmask = mask_of(tile);
@@ -245,16 +246,16 @@ static bool build_fused(const Circ *C, const std::vector<int> &take, const std::
         bool ident = c0 == 0 && conds.empty();
         for (int b = 0; b < keff; ++b) ident = ident && col[b] == (1u << b);
         // stages of up to four gathered qubits; the network rides on the last
-        const size_t ngroups = std::max<size_t>(1, (order.size() + 3) / 4);
+        const size_t ngroups = std::max<size_t>(1, (order.size() + RB - 1) / RB);
         for (size_t gi = 0; gi < ngroups; ++gi) {
             FusedStage fs;
             std::memset(&fs, 0, sizeof(fs));
-            std::vector<int> act(order.begin() + std::min(order.size(), 4 * gi),
-                                 order.begin() + std::min(order.size(), 4 * gi + 4));
+            std::vector<int> act(order.begin() + std::min(order.size(), RB * gi),
+                                 order.begin() + std::min(order.size(), RB * gi + RB));
             uint32_t R = 0;
             for (int b : act) R |= 1u << b;
             std::vector<int> rb = act;
-            for (int b = 0; b < keff && (int)rb.size() < 4; ++b)
+            for (int b = 0; b < keff && (int)rb.size() < RB; ++b)
                 if (!((R >> b) & 1)) {
                     R |= 1u << b;
                     rb.push_back(b);
@@ -262,22 +263,27 @@ static bool build_fused(const Circ *C, const std::vector<int> &take, const std::
             std::vector<int> cb;
             for (int b = 0; b < keff; ++b)
                 if (!((R >> b) & 1)) cb.push_back(b);
-            for (int i = 0; i < 4; ++i) fs.rpos[i] = (uint8_t)rb[i];
+            for (int i = 0; i < RB; ++i) fs.rpos[i] = (uint8_t)rb[i];
+            fs.nb = RB;
             for (size_t j = 0; j < cb.size(); ++j) fs.cpos[j] = (uint8_t)cb[j];
             fs.na = (int)act.size();
             fs.slot = plan->n_fslots();
-            for (int i = 0; i < 4; ++i) {  // fused matrices: identity (empty list) past na
+            for (int i = 0; i < RB; ++i) {  // per register bit: its gates in order (empty past na)
                 if (i < fs.na)
-                    for (int g : oneq[rb[i]]) plan->host_fslot_gate.push_back(g);
+                    for (int g : oneq[rb[i]]) {
+                        plan->host_fslot_gate.push_back(g);
+                        const GateHost &h = C->gates[g];
+                        plan->host_fslot_info.push_back(((C->pgate_of_gate[g] + 1) << 4) | h.gen);
+                    }
                 plan->host_fslot_off.push_back((int32_t)plan->host_fslot_gate.size());
             }
             const bool last = gi + 1 == ngroups;
             if (last && !ident) {
                 fs.perm = 1;
                 fs.c0 = (uint16_t)c0;
-                for (int i = 0; i < 16; ++i) {
+                for (int i = 0; i < (1 << RB); ++i) {
                     uint32_t v = 0;
-                    for (int j = 0; j < 4; ++j)
+                    for (int j = 0; j < RB; ++j)
                         if ((i >> j) & 1) v ^= col[rb[j]];
                     fs.lr[i] = (uint16_t)v;
                 }
@@ -286,9 +292,9 @@ static bool build_fused(const Circ *C, const std::vector<int> &take, const std::
                 fs.cond_count = (int)conds.size();
                 for (const FusedCond &f : conds) plan->host_fconds.push_back(f);
             } else {
-                for (int i = 0; i < 16; ++i) {
+                for (int i = 0; i < (1 << RB); ++i) {
                     uint32_t v = 0;
-                    for (int j = 0; j < 4; ++j)
+                    for (int j = 0; j < RB; ++j)
                         if ((i >> j) & 1) v |= 1u << rb[j];
                     fs.lr[i] = (uint16_t)v;
                 }
@@ -527,14 +533,15 @@ CircPlan *get_circ_plan(Circ *C, bool reverse, int k, int c, int *rc)
             done[g] = 1;
             --remaining;
         }
-        if (!reverse) {
+        {
             const size_t f0 = plan->host_fstages.size(), c0 = plan->host_fconds.size();
             const size_t s0 = plan->host_fslot_off.size(), g0 = plan->host_fslot_gate.size();
-            if (!build_fused(C, take, tile, keff, plan.get(), pp)) {
+            if (!build_fused(C, take, tile, keff, reverse ? 3 : 4, plan.get(), pp)) {
                 plan->host_fstages.resize(f0);
                 plan->host_fconds.resize(c0);
                 plan->host_fslot_off.resize(s0);
                 plan->host_fslot_gate.resize(g0);
+                plan->host_fslot_info.resize(g0);
                 pp.fstage_begin = (int)f0;
                 pp.fstage_count = 0;
             }
@@ -572,6 +579,9 @@ CircPlan *get_circ_plan(Circ *C, bool reverse, int k, int c, int *rc)
         if (!r && !plan->host_fslot_gate.empty())
             r = upload(C->ctx, plan->fslot_gate, plan->host_fslot_gate.data(),
                        plan->host_fslot_gate.size() * sizeof(int32_t));
+        if (!r && !plan->host_fslot_info.empty())
+            r = upload(C->ctx, plan->fslot_info, plan->host_fslot_info.data(),
+                       plan->host_fslot_info.size() * sizeof(int32_t));
         if (r) {
             free_plan(C->ctx, plan.get());
             *rc = r;

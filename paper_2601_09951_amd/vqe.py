@@ -432,7 +432,7 @@ _SOP = np.dtype([("cmo", "<u8"), ("cvo", "<u8"), ("cmt", "<u4"), ("cvt", "<u4"),
                  ("cls", "u1"), ("gen", "u1"), ("pad", "u1"), ("amask", "<u2"), ("pad2", "<u2", 3)])
 _FSTAGE = np.dtype([("rpos", "u1", 4), ("cpos", "u1", 12), ("lr", "<u2", 16), ("lc", "<u2", 12), ("c0", "<u2"),
                     ("perm", "<u2"), ("na", "<i4"), ("cond_begin", "<i4"), ("cond_count", "<i4"), ("slot", "<i4"),
-                    ("pad", "<i4")])
+                    ("nb", "<i4")])
 _FCOND = np.dtype([("cmo", "<u8"), ("cvo", "<u8"), ("xmask", "<u4"), ("pad", "<u4")])
 _OP = np.dtype([("m", "<u4"), ("fixed_bits", "<u4"), ("cmask_out", "<u8"), ("cval_out", "<u8"),
                 ("gate", "<i4"), ("pgate", "<i4"), ("cls", "<i2"), ("gen", "<i2"), ("nfix", "i1"),
@@ -445,7 +445,7 @@ _TERM = np.dtype([("z", "<u8"), ("zloc", "<u4"), ("pad", "<u4"), ("w", "<f8")])
 def circuit_plan(ctx: Context, circ: Circuit, reverse: bool = False, stages: bool = False):
     """(passes, ops) structured arrays of the compiled pass schedule
     (plus (stages, stage_ops) when stages=True; with stages="fused":
-    (passes, ops, fused_stages, fused_conds, slot_offsets, slot_gates))."""
+    (passes, ops, fused_stages, fused_conds, slot_offsets, slot_gates, slot_info))."""
     need = ctypes.c_size_t()
     ctx.check(lib().vqe_circ_plan_export(ctx.handle, circ.handle, int(reverse), None, 0, ctypes.byref(need)))
     buf = np.zeros(need.value, dtype=np.uint8)
@@ -476,7 +476,9 @@ def circuit_plan(ctx: Context, circ: Circuit, reverse: bool = False, stages: boo
         soff = buf[off:off + (nsl + 1) * 4].view("<i4")
         off += (nsl + 1) * 4
         sgate = buf[off:off + nsg * 4].view("<i4")
-        return passes, ops, fst, fco, soff, sgate
+        off += nsg * 4
+        sinfo = buf[off:off + nsg * 4].view("<i4")
+        return passes, ops, fst, fco, soff, sgate, sinfo
     if stages:
         return passes, ops, st, sops
     return passes, ops

@@ -396,3 +396,75 @@ def forward_fused(passes, ops, fstages, fconds, soff, sgate, psi, mats):
                 T[:, sidx] = X
         psi[idx] = T
     return psi
+
+
+def reverse_fused(passes, ops, fstages, fconds, soff, sgate, sinfo, psi, lam, mats, n_pgates):
+    """Adjoint passes with fused stages where the plan has them: per active
+    register bit, its gates undone one by one (gradient term Im<lam|G|psi>,
+    then U^dagger on both states), then the stage's store map; the op-by-op
+    path elsewhere."""
+    psi, lam = psi.copy(), lam.copy()
+    gpart = np.zeros(n_pgates)
+    pauli = {GEN_X: np.array([[0, 1], [1, 0]], dtype=complex), GEN_Y: np.array([[0, -1j], [1j, 0]]),
+             GEN_Z: np.array([[1, 0], [0, -1]], dtype=complex)}
+    for pi in range(len(passes)):
+        ps = passes[pi:pi + 1]
+        nfs = int(ps[0]["fstage_count"])
+        if nfs == 0:
+            psi, lam, gp = reverse(ps, ops, psi, lam, mats, n_pgates)
+            gpart += gp
+            continue
+        g = ps[0]["geom"]
+        k = int(g["k"])
+        idx, base = _tile_index(g)
+        TP, TL = psi[idx].copy(), lam[idx].copy()
+        for fs in fstages[int(ps[0]["fstage_begin"]):int(ps[0]["fstage_begin"]) + nfs]:
+            nb, na = int(fs["nb"]), int(fs["na"])
+            assert nb == 3
+            rpos = [int(v) for v in fs["rpos"][:nb]]
+            cpos = [int(v) for v in fs["cpos"][:k - nb]]
+            assert len(set(rpos + cpos)) == k and max(rpos + cpos) < k
+            roff = np.array([sum(((i >> b) & 1) << rpos[b] for b in range(nb)) for i in range(1 << nb)])
+            u = np.arange(1 << (k - nb))
+            bl = np.zeros_like(u)
+            for j, p in enumerate(cpos):
+                bl |= ((u >> j) & 1) << p
+            sidx = bl[:, None] | roff[None, :]
+            X, L = TP[:, sidx], TL[:, sidx]
+            for j in range(na):
+                M = 1 << j
+                lo = [i for i in range(1 << nb) if not (i & M)]
+                hi = [i | M for i in lo]
+                slot = int(fs["slot"]) + j
+                for e in range(int(soff[slot]), int(soff[slot + 1])):
+                    W = mats[int(sgate[e])].conj().T
+                    info = int(sinfo[e])
+                    pg, gen = (info >> 4) - 1, info & 15
+                    a, b, la, lb = X[:, :, lo].copy(), X[:, :, hi].copy(), L[:, :, lo].copy(), L[:, :, hi].copy()
+                    if pg >= 0:
+                        P = pauli[gen]
+                        ga = P[0, 0] * a + P[0, 1] * b
+                        gb = P[1, 0] * a + P[1, 1] * b
+                        gpart[pg] += (la.conj() * ga + lb.conj() * gb).imag.sum()
+                    X[:, :, lo], X[:, :, hi] = W[0, 0] * a + W[0, 1] * b, W[1, 0] * a + W[1, 1] * b
+                    L[:, :, lo], L[:, :, hi] = W[0, 0] * la + W[0, 1] * lb, W[1, 0] * la + W[1, 1] * lb
+            if int(fs["perm"]):
+                lc = [int(v) for v in fs["lc"][:k - nb]]
+                lbl = np.zeros_like(u)
+                for j in range(k - nb):
+                    lbl ^= ((u >> j) & 1) * lc[j]
+                lr = np.array([int(v) for v in fs["lr"][:1 << nb]])
+                for t in range(TP.shape[0]):
+                    ct = int(fs["c0"])
+                    for fc in fconds[int(fs["cond_begin"]):int(fs["cond_begin"]) + int(fs["cond_count"])]:
+                        if (int(base[t]) & int(fc["cmo"])) == int(fc["cvo"]):
+                            ct ^= int(fc["xmask"])
+                    dst = (lbl[:, None] ^ lr[None, :] ^ ct).reshape(-1)
+                    assert np.unique(dst).size == dst.size == (1 << k), "store map must permute the tile"
+                    nP, nL = np.empty(1 << k, dtype=complex), np.empty(1 << k, dtype=complex)
+                    nP[dst], nL[dst] = X[t].reshape(-1), L[t].reshape(-1)
+                    TP[t], TL[t] = nP, nL
+            else:
+                TP[:, sidx], TL[:, sidx] = X, L
+        psi[idx], lam[idx] = TP, TL
+    return psi, lam, gpart

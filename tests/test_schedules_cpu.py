@@ -205,7 +205,7 @@ def test_fused_stage_schedules(ctx, kind, n, k, c):
     th = synth.uniform_thetas(spec.n_params, 1, seed=n)[0]
     C = vqe.Circuit.from_spec(ctx, spec)
     mats = emu.gate_matrices(spec, th)
-    passes, ops, fst, fco, soff, sg = vqe.circuit_plan(ctx, C, stages="fused")
+    passes, ops, fst, fco, soff, sg, si = vqe.circuit_plan(ctx, C, stages="fused")
     assert int(passes["fstage_count"].sum()) == len(fst) > 0
     if kind == "hea":
         assert (passes["fstage_count"] > 0).all()
@@ -213,3 +213,27 @@ def test_fused_stage_schedules(ctx, kind, n, k, c):
     ref[spec.ref_index] = 1
     psi = emu.forward_fused(passes, ops, fst, fco, soff, sg, ref, mats)
     np.testing.assert_allclose(psi, oracle.state(spec, th), atol=1e-12)
+
+
+@pytest.mark.parametrize("kind,n,k,c", [("hea", 12, 8, 3), ("hea", 13, 11, 4), ("rot", 10, 8, 2),
+                                         ("rot", 12, 9, 4), ("rot", 13, 11, 4)])
+def test_fused_adjoint_schedules(ctx, kind, n, k, c):
+    """Fused adjoint stages on the CPU: the reverse sweep returns to the
+    reference state and its gradient equals the oracle's."""
+    ctx.set_tile(k, k, c)
+    spec = synth.hea_circuit(n, 2) if kind == "hea" else synth.random_rotation_cnot_circuit(n, 90, seed=n + k)
+    ham = synth.random_pauli_sum(n, 30, seed=n)
+    th = synth.uniform_thetas(spec.n_params, 1, seed=n)[0]
+    C = vqe.Circuit.from_spec(ctx, spec)
+    mats = emu.gate_matrices(spec, th)
+    rp, rops, fst, fco, soff, sg, si = vqe.circuit_plan(ctx, C, reverse=True, stages="fused")
+    assert len(fst) > 0 and (fst["nb"] == 3).all()
+    psi = oracle.state(spec, th)
+    n_pg = int((spec.param_idx >= 0).sum())
+    back, _, gpart = emu.reverse_fused(rp, rops, fst, fco, soff, sg, si, psi, oracle.apply_hamiltonian(psi, ham),
+                                       mats, n_pg)
+    ref = np.zeros(1 << n, dtype=complex)
+    ref[spec.ref_index] = 1
+    np.testing.assert_allclose(back, ref, atol=1e-12)
+    _, g_or = oracle.energy_grad(spec, ham, th, "adjoint")
+    np.testing.assert_allclose(_grad_from_parts(spec, gpart), g_or, atol=1e-11)
