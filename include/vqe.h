@@ -321,7 +321,8 @@ int vqe_run(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams, i
  *   active conditional record) when perm = 1), n_fconds records {uint64
  *   cmo, cvo, uint32 xmask, 0} (active when (tile base & cmo) == cvo),
  *   int32 slot offsets [n_slots + 1], the gate of each slot entry and its
- *   int32 info ((parametric gate index + 1) << 4 | generator).  Forward
+ *   int32 info ((parametric gate index + 1) << 4 | class << 2 | generator,
+ *   class and generator as in the op record).  Forward
  *   stages multiply a slot's matrices in list order (an empty slot is the
  *   identity); adjoint stages (nb = 3) undo them one by one, and there the
  *   store map is the inverse network of the next gates in reversed order.  geom = int32 {n, k, c,

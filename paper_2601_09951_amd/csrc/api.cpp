@@ -95,6 +95,7 @@ inline size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
     size_t psi = 0, lam = 0, mats = 0, pe = 0, pg = 0, grad = 0, m = 0, v = 0, etmp = 0;
+    size_t wadj = 0, coef = 0;  // adjoint fused stages: per-slot products, per-entry coefficients
     size_t total = 0;
     int W_fwd_sweep = 1, W_hpsi = 1, W_rev = 1;
     int n_sweeps_e = 1;
@@ -195,6 +196,12 @@ int layout_for(Context *ctx, Circ *C, int n_hams, Ham *const *H, int64_t B, int 
         off = align_up(off + (size_t)B * L.W_hpsi * 8);
         L.pg = off;
         off = align_up(off + (size_t)B * std::max(C->n_pgates, 1) * L.W_rev * 8);
+        CircPlan *rp = get_circ_plan(C, true, ctx->k_rev, ctx->c_low, &rc);
+        if (!rp) return rc;
+        L.wadj = off;
+        off = align_up(off + (size_t)B * rp->n_fslots() * 64);
+        L.coef = off;
+        off = align_up(off + (size_t)B * rp->host_fslot_gate.size() * 32);
     }
     if (want == 2) {
         L.grad = off;
@@ -340,10 +347,31 @@ int energy_grad_into(Context *ctx, Circ *C, int n_hams, Ham *const *H, int64_t B
     rc = hip_check(ctx, launch_reduce_slots(pe, 1, L.W_hpsi, B, energy, e_stride, 1.0, s), "energy reduce");
     if (rc) return rc;
     const int G = (int)C->gates.size();
+    const bool fuse_rev = ctx->fuse && !ctx->no_stages && rp->n_fslots() > 0;
+    const int n_entries = (int)rp->host_fslot_gate.size();
+    double2 *wadj = reinterpret_cast<double2 *>(ws + L.wadj);
+    double *coef = reinterpret_cast<double *>(ws + L.coef);
+    if (fuse_rev) {
+        rc = hip_check(ctx, launch_adjoint_coefs(reinterpret_cast<const int32_t *>(rp->fslot_off.p),
+                                                 reinterpret_cast<const int32_t *>(rp->fslot_gate.p),
+                                                 reinterpret_cast<const int32_t *>(rp->fslot_info.p), rp->n_fslots(),
+                                                 n_entries, mats, G, B, wadj, coef, s),
+                       "adjoint stage coefficients");
+        if (rc) return rc;
+    }
     for (size_t i = 0; i < rp->passes.size(); ++i) {
         const PassPlan &p = rp->passes[i];
         const TileGeom *gd = reinterpret_cast<const TileGeom *>(rp->geoms.p) + i;
-        if (p.stage_count > 0 && !ctx->no_stages)
+        if (fuse_rev && p.fstage_count > 0)
+            rc = hip_check(ctx, launch_reverse_fused(p, gd, reinterpret_cast<const FusedStage *>(rp->fstages.p),
+                                                     reinterpret_cast<const FusedCond *>(rp->fconds.p),
+                                                     reinterpret_cast<const int32_t *>(rp->fslot_off.p),
+                                                     reinterpret_cast<const int32_t *>(rp->fslot_info.p),
+                                                     rp->host_fstages[p.fstage_begin].slot, rp->n_fslots(),
+                                                     n_entries, p.fq_count, wadj, coef, psi, lam, B, L.W_rev, pg,
+                                                     C->n_pgates, s),
+                           "reverse pass (fused)");
+        else if (p.stage_count > 0 && !ctx->no_stages)
             rc = hip_check(ctx, launch_reverse_staged(p, p.stage_bits, gd, reinterpret_cast<const StageDesc *>(rp->stages.p),
                                                       reinterpret_cast<const StageOp *>(rp->sops.p), mats, G, psi,
                                                       lam, B, L.W_rev, pg, C->n_pgates, s),

@@ -214,7 +214,8 @@ struct PassPlan {
     int n_param_ops = 0;     // parametric ops in this pass (reverse plans)
     int stage_begin = 0, stage_count = 0;  // register stages (k >= kStageMinK)
     int stage_bits = 0;                     // register bits of this pass's stages
-    int fstage_begin = 0, fstage_count = 0; // fused stages (forward plans; 0: not fusable)
+    int fstage_begin = 0, fstage_count = 0; // fused stages (0: not fusable)
+    int fq_count = 0;                       // adjoint fused stages: slots holding parametric gates
 };
 
 struct CircPlan {
@@ -235,7 +236,7 @@ struct CircPlan {
     std::vector<FusedStage> host_fstages;
     std::vector<FusedCond> host_fconds;
     std::vector<int32_t> host_fslot_off{0}, host_fslot_gate;
-    std::vector<int32_t> host_fslot_info;  // per slot entry: (pgate + 1) << 4 | generator
+    std::vector<int32_t> host_fslot_info;  // per slot entry: (pgate + 1) << 4 | class << 2 | generator
     int n_fslots() const { return (int)host_fslot_off.size() - 1; }
 };
 
@@ -294,7 +295,7 @@ struct Context {
     int wg_max = 1024;          // workgroups per instance in tile passes
     int force_generic = 0;      // route vqe_run through the per-step launches
     int no_stages = 0;          // use the one-op-per-LDS-round-trip pass kernels only
-    int fuse = 1;               // forward passes: fused stages where the plan has them
+    int fuse = 1;               // forward and adjoint passes: fused stages where the plan has them
     std::string err;
     DevMem scratch;
     std::map<std::string, std::unique_ptr<PauliPlan>> pauli_cache;
@@ -339,6 +340,15 @@ hipError_t launch_forward_pass(const PassPlan &pp, const TileGeom *geom_dev, con
                                int wg_max, hipStream_t s);
 hipError_t launch_fuse_mats(const int32_t *slot_off, const int32_t *slot_gate, int n_slots, const double2 *mats,
                             int n_gates, int64_t batch, double2 *fused, hipStream_t s);
+hipError_t launch_adjoint_coefs(const int32_t *slot_off, const int32_t *slot_gate, const int32_t *slot_info,
+                                int n_slots, int n_entries, const double2 *mats, int n_gates, int64_t batch,
+                                double2 *wadj, double *coef, hipStream_t s);
+size_t reverse_fused_lds(int k, int c, int nstages, int n_qslots);
+hipError_t launch_reverse_fused(const PassPlan &pp, const TileGeom *geom_dev, const FusedStage *fstages,
+                                const FusedCond *fconds, const int32_t *slot_off, const int32_t *slot_info,
+                                int slot0, int n_slots, int n_entries, int n_qslots, const double2 *wadj,
+                                const double *coef, double2 *psi, double2 *lam, int64_t batch, int wg_per_inst,
+                                double *partials, int n_pgates, hipStream_t s);
 hipError_t launch_forward_fused(const PassPlan &pp, const TileGeom *geom_dev, const FusedStage *fstages,
                                 const FusedCond *fconds, const double2 *fused, int n_slots, double2 *psi,
                                 int64_t batch, int wg_max, hipStream_t s);

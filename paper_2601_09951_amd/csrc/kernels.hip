@@ -197,6 +197,33 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// Sum over the 64 lanes, identical in every lane, in a fixed order: DPP
+// lane permutations (no LDS traffic) form quad, half-row and row sums, and
+// the four row sums are added through readlane in row order.  Every lane
+// must be active.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double read_lane(double v, int lane)
+{
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                            __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
+
+__device__ __forceinline__ double wave_total(double v)
+{
+    v += dpp_move<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_move<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_move<0x141>(v);  // row_half_mirror
+    v += dpp_move<0x140>(v);  // row_mirror
+    return ((read_lane(v, 0) + read_lane(v, 16)) + read_lane(v, 32)) + read_lane(v, 48);
+}
+
 // sum of v over the workgroup (kThreads threads), fixed order; result in
 // thread 0.  red must hold kThreads/64 doubles.
 __device__ __forceinline__ double block_sum(double v, double *red)
@@ -1135,6 +1162,267 @@ __global__ __launch_bounds__(kThreads) void k_forward_fused(const TileGeom *__re
 }
 
 // ---------------------------------------------------------------------------
+// Fused adjoint stages (reverse passes of one-qubit gates, X and CNOT; three
+// register bits per sub-cube, both states).
+//
+// The gates of one register bit j (one slot, listed in the order they are
+// undone, W_i = U_i^dagger) act on psi and lam as one product W = W_m ... W_1,
+// and every gradient term of the slot follows from the states before it:
+// with V_i = W_{i-1} ... W_1 and the generator G_i of a parametric entry,
+//   Im <lam_i| G_i |psi_i> = Im <lam| K_i |psi>,   K_i = V_i^dagger G_i V_i,
+// K_i Hermitian and traceless, so per pair (a, b) of psi and (la, lb) of lam
+//   Im <.|K_i|.> = k00 Q0 + Re k01 Q1 + Im k01 Q2,
+//   Q0 = Im(conj(la) a) - Im(conj(lb) b),  Q1 = Im(conj(la) b + conj(lb) a),
+//   Q2 = Re(conj(la) b - conj(lb) a).
+// Gates on the other bits of the stage commute with G_i and cancel in the
+// inner product, so their order does not matter.  The kernels sum Q over
+// the state (per slot, three numbers), and the per-instance coefficients
+// turn the sums into the slot's gradient partials; the state update is one
+// general 2x2 per bit.
+//
+// k_adjoint_coefs: per (instance, slot) the product W and per entry the
+// coefficients (k00, Re k01, Im k01, 0) (zeros for fixed gates).
+__global__ void k_adjoint_coefs(const int32_t *__restrict__ slot_off, const int32_t *__restrict__ slot_gate,
+                                const int32_t *__restrict__ slot_info, int n_slots, int n_entries,
+                                const double2 *__restrict__ mats, int n_gates, int64_t batch,
+                                double2 *__restrict__ wout, double *__restrict__ coef)
+{
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= batch * n_slots) return;
+    const int64_t inst = w / n_slots;
+    const int slot = (int)(w - inst * n_slots);
+    double2 v00 = make_double2(1.0, 0.0), v01 = make_double2(0.0, 0.0), v10 = v01, v11 = v00;  // V
+    for (int e = slot_off[slot]; e < slot_off[slot + 1]; ++e) {
+        const int info = slot_info[e];
+        double *ce = coef + ((size_t)inst * n_entries + e) * 4;
+        double k00 = 0.0, k01r = 0.0, k01i = 0.0;
+        if (info >= 16) {
+            // G V for the Pauli generator, then the first row of V^dagger (G V)
+            double2 g00, g01, g10, g11;
+            const int gen = info & 3;
+            if (gen == GEN_X) {
+                g00 = v10; g01 = v11; g10 = v00; g11 = v01;
+            } else if (gen == GEN_Y) {  // [[0, -i], [i, 0]]
+                g00 = make_double2(v10.y, -v10.x); g01 = make_double2(v11.y, -v11.x);
+                g10 = make_double2(-v00.y, v00.x); g11 = make_double2(-v01.y, v01.x);
+            } else {  // GEN_Z
+                g00 = v00; g01 = v01; g10 = make_double2(-v10.x, -v10.y); g11 = make_double2(-v11.x, -v11.y);
+            }
+            const double2 K00 = cadd(cmul(cconj(v00), g00), cmul(cconj(v10), g10));
+            const double2 K01 = cadd(cmul(cconj(v00), g01), cmul(cconj(v10), g11));
+            k00 = K00.x;
+            k01r = K01.x;
+            k01i = K01.y;
+        }
+        ce[0] = k00;
+        ce[1] = k01r;
+        ce[2] = k01i;
+        ce[3] = 0.0;
+        // V <- U^dagger V
+        const double2 *U = mats + ((size_t)inst * n_gates + slot_gate[e]) * 4;
+        const double2 w00 = cconj(U[0]), w01 = cconj(U[2]), w10 = cconj(U[1]), w11 = cconj(U[3]);
+        const double2 n00 = cadd(cmul(w00, v00), cmul(w01, v10)), n01 = cadd(cmul(w00, v01), cmul(w01, v11));
+        const double2 n10 = cadd(cmul(w10, v00), cmul(w11, v10)), n11 = cadd(cmul(w10, v01), cmul(w11, v11));
+        v00 = n00;
+        v01 = n01;
+        v10 = n10;
+        v11 = n11;
+    }
+    double2 *o = wout + (size_t)w * 4;
+    o[0] = v00;
+    o[1] = v01;
+    o[2] = v10;
+    o[3] = v11;
+}
+
+// the three pair sums Q over this thread's sub-cube for register bit B
+template <int B>
+__device__ __forceinline__ void rbit_q(const double2 (&x)[8], const double2 (&l)[8], double &q0, double &q1,
+                                       double &q2)
+{
+    constexpr int M = 1 << B;
+    q0 = q1 = q2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        if (i & M) continue;
+        const double2 a = x[i], b = x[i | M], la = l[i], lb = l[i | M];
+        q0 += (la.x * a.y - la.y * a.x) - (lb.x * b.y - lb.y * b.x);
+        q1 += (la.x * b.y - la.y * b.x) + (lb.x * a.y - lb.y * a.x);
+        q2 += (la.x * b.x + la.y * b.y) - (lb.x * a.x + lb.y * a.y);
+    }
+}
+
+template <int B>
+__device__ __forceinline__ void rbit_step(double2 (&x)[8], double2 (&l)[8], const Mat2 &w, int qs, double *red)
+{
+    constexpr int M = 1 << B;
+    if (qs >= 0) {  // the slot holds parametric gates (uniform)
+        double q0, q1, q2;
+        rbit_q<B>(x, l, q0, q1, q2);
+        q0 = wave_total(q0);
+        q1 = wave_total(q1);
+        q2 = wave_total(q2);
+        if ((threadIdx.x & 63) == 0) {
+            double *r = red + (size_t)qs * 12 + (threadIdx.x >> 6);
+            r[0] += q0;
+            r[4] += q1;
+            r[8] += q2;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        if (i & M) continue;
+        pair_fwd<CLS_GENERAL>(x[i], x[i | M], w);
+        pair_fwd<CLS_GENERAL>(l[i], l[i | M], w);
+    }
+}
+
+template <int NA, bool PERM>
+__device__ __forceinline__ void rev_fused_stage(double2 *tp, double2 *tl, const FusedStage &fs, const Mat2 *wm,
+                                                const int32_t *qidx, int nsub, uint32_t ctile, double *red)
+{
+    const int u = threadIdx.x;
+    const bool have = u < nsub;
+    uint32_t bl = 0, lbl = 0;
+#pragma unroll
+    for (int j = 0; j < 12; ++j)
+        if ((u >> j) & 1) {
+            bl |= 1u << fs.cpos[j];
+            lbl ^= fs.lc[j];
+        }
+    uint32_t roff[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+        roff[i] = ((i & 1) ? 1u << fs.rpos[0] : 0u) | ((i & 2) ? 1u << fs.rpos[1] : 0u) |
+                  ((i & 4) ? 1u << fs.rpos[2] : 0u);
+    double2 x[8], l[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        x[i] = make_double2(0.0, 0.0);
+        l[i] = make_double2(0.0, 0.0);
+    }
+    if (have) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            x[i] = tp[swz(bl | roff[i])];
+            l[i] = tl[swz(bl | roff[i])];
+        }
+    }
+    // every thread takes part in the sums (a thread with no sub-cube adds zeros)
+    if (NA > 0) rbit_step<0>(x, l, wm[0], (int)__builtin_amdgcn_readfirstlane((uint32_t)qidx[0]), red);
+    if (NA > 1) rbit_step<1>(x, l, wm[1], (int)__builtin_amdgcn_readfirstlane((uint32_t)qidx[1]), red);
+    if (NA > 2) rbit_step<2>(x, l, wm[2], (int)__builtin_amdgcn_readfirstlane((uint32_t)qidx[2]), red);
+    if (PERM) {
+        lds_barrier();  // every sub-cube is read before any amplitude moves
+        if (have) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const uint32_t d = swz(lbl ^ fs.lr[i] ^ ctile);
+                tp[d] = x[i];
+                tl[d] = l[i];
+            }
+        }
+    } else if (have) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            tp[swz(bl | roff[i])] = x[i];
+            tl[swz(bl | roff[i])] = l[i];
+        }
+    }
+}
+
+// One partial per (instance, parametric gate, workgroup), as the staged
+// adjoint writes them.  The pass owns slots [slot0, slot0 + 3 * nstages) and
+// their entries [e0, e0 + ne); wadj / coef hold the per-instance products
+// and coefficients of every slot / entry of the plan (n_slots / n_entries).
+__global__ __launch_bounds__(kThreads) void k_reverse_fused(
+    const TileGeom *__restrict__ gp, int n, int k, int c, int nout, const FusedStage *__restrict__ fstages,
+    int nstages, const FusedCond *__restrict__ fconds, const int32_t *__restrict__ slot_off,
+    const int32_t *__restrict__ slot_info, int slot0, int n_slots, int n_entries, const double2 *__restrict__ wadj,
+    const double *__restrict__ coef, double2 *__restrict__ psi, double2 *__restrict__ lam, int64_t tiles,
+    double *__restrict__ partials, int n_pgates)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    double2 *tp = reinterpret_cast<double2 *>(smem);
+    double2 *tl = tp + (1u << k);
+    uint64_t *hoff = reinterpret_cast<uint64_t *>(smem + (32u << k));
+    const int ns = 3 * nstages;
+    Mat2 *wm = reinterpret_cast<Mat2 *>(hoff + (1u << (k - c)));
+    FusedStage *fs_l = reinterpret_cast<FusedStage *>(wm + ns);
+    int32_t *qidx = reinterpret_cast<int32_t *>(fs_l + nstages);
+    double *red = reinterpret_cast<double *>(qidx + ((ns + 1) & ~1));
+    const int tid = threadIdx.x;
+    const uint64_t dim = 1ull << n;
+    double2 *sp = psi + (uint64_t)blockIdx.y * dim;
+    double2 *sl = lam + (uint64_t)blockIdx.y * dim;
+    const int T = 1 << k;
+    const int nsub = 1 << (k - 3);  // at most kThreads (k <= 11)
+    fill_hoff(gp, k, c, hoff);
+    const double2 *Wg = wadj + ((size_t)blockIdx.y * n_slots + slot0) * 4;
+    double2 *wmd = reinterpret_cast<double2 *>(wm);
+    for (int i = tid; i < 4 * ns; i += kThreads) wmd[i] = Wg[i];
+    for (int i = tid; i < nstages; i += kThreads) fs_l[i] = fstages[i];
+    int nq = 0;  // slots with parametric gates, numbered in order (every thread counts)
+    for (int i = 0; i < ns; ++i) {
+        bool par = false;
+        for (int e = slot_off[slot0 + i]; e < slot_off[slot0 + i + 1]; ++e) par = par || slot_info[e] >= 16;
+        if (tid == 0) qidx[i] = par ? nq : -1;
+        nq += par;
+    }
+    for (int i = tid; i < 12 * nq; i += kThreads) red[i] = 0.0;
+    __syncthreads();
+    for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+        const uint64_t base = tile_base(gp, nout, t);
+        tile_in2<8, true>(tp, tl, sp, sl, base, hoff, T, c);
+        __syncthreads();
+        for (int s = 0; s < nstages; ++s) {
+            const FusedStage &fs = fs_l[s];
+            const int na = (int)__builtin_amdgcn_readfirstlane((uint32_t)fs.na);
+            const int perm = (int)__builtin_amdgcn_readfirstlane((uint32_t)fs.perm);
+            uint32_t ctile = fs.c0;
+            for (int q = 0; q < fs.cond_count; ++q) {
+                const FusedCond fc = fconds[fs.cond_begin + q];
+                if ((base & fc.cmo) == fc.cvo) ctile ^= fc.xmask;
+            }
+            const Mat2 *w3 = wm + 3 * s;
+            const int32_t *q3 = qidx + 3 * s;
+            switch (na * 2 + perm) {
+            case 0: rev_fused_stage<0, false>(tp, tl, fs, w3, q3, nsub, ctile, red); break;
+            case 1: rev_fused_stage<0, true>(tp, tl, fs, w3, q3, nsub, ctile, red); break;
+            case 2: rev_fused_stage<1, false>(tp, tl, fs, w3, q3, nsub, ctile, red); break;
+            case 3: rev_fused_stage<1, true>(tp, tl, fs, w3, q3, nsub, ctile, red); break;
+            case 4: rev_fused_stage<2, false>(tp, tl, fs, w3, q3, nsub, ctile, red); break;
+            case 5: rev_fused_stage<2, true>(tp, tl, fs, w3, q3, nsub, ctile, red); break;
+            case 6: rev_fused_stage<3, false>(tp, tl, fs, w3, q3, nsub, ctile, red); break;
+            default: rev_fused_stage<3, true>(tp, tl, fs, w3, q3, nsub, ctile, red); break;
+            }
+            lds_barrier();
+        }
+        tile_out2<8, true>(tp, tl, sp, sl, base, hoff, T, c);
+        __syncthreads();
+    }
+    // partial of entry e = coef(e) . (the slot's three sums over the four waves)
+    if (tid == 0) {
+        const int W = gridDim.x;
+        const double *cf = coef + (size_t)blockIdx.y * n_entries * 4;
+        for (int i = 0; i < ns; ++i) {
+            const int qs = qidx[i];
+            if (qs < 0) continue;
+            const double *r = red + (size_t)qs * 12;
+            const double Q0 = ((r[0] + r[1]) + r[2]) + r[3];
+            const double Q1 = ((r[4] + r[5]) + r[6]) + r[7];
+            const double Q2 = ((r[8] + r[9]) + r[10]) + r[11];
+            for (int e = slot_off[slot0 + i]; e < slot_off[slot0 + i + 1]; ++e) {
+                const int info = slot_info[e];
+                if (info < 16) continue;
+                const double v = cf[e * 4 + 0] * Q0 + cf[e * 4 + 1] * Q1 + cf[e * 4 + 2] * Q2;
+                partials[((size_t)blockIdx.y * n_pgates + ((info >> 4) - 1)) * W + blockIdx.x] = v;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Pauli sweep over the groups of one sweep.
 //
 // Expectation (lam == nullptr), paired over (b, b ^ f) with b's pivot bit 0,
@@ -1495,6 +1783,43 @@ hipError_t launch_forward_fused(const PassPlan &pp, const TileGeom *geom_dev, co
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_forward_fused, dim3(W, (unsigned)batch), dim3(kThreads), lds, s, geom_dev, g.n, g.k, g.c,
                        g.nout, fstages + pp.fstage_begin, pp.fstage_count, fconds, fused, n_slots, psi, tiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_coefs(const int32_t *slot_off, const int32_t *slot_gate, const int32_t *slot_info,
+                                int n_slots, int n_entries, const double2 *mats, int n_gates, int64_t batch,
+                                double2 *wadj, double *coef, hipStream_t s)
+{
+    const int64_t total = batch * n_slots;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_adjoint_coefs, dim3(grid_for(total, 128)), dim3(128), 0, s, slot_off, slot_gate, slot_info,
+                       n_slots, n_entries, mats, n_gates, batch, wadj, coef);
+    return hipGetLastError();
+}
+
+size_t reverse_fused_lds(int k, int c, int nstages, int n_qslots)
+{
+    const size_t ns = 3 * (size_t)nstages;
+    return (32u << k) + (8u << (k - c)) + ns * sizeof(Mat2) + (size_t)nstages * sizeof(FusedStage) +
+           4 * ((ns + 1) & ~(size_t)1) + 96 * (size_t)n_qslots;
+}
+
+hipError_t launch_reverse_fused(const PassPlan &pp, const TileGeom *geom_dev, const FusedStage *fstages,
+                                const FusedCond *fconds, const int32_t *slot_off, const int32_t *slot_info,
+                                int slot0, int n_slots, int n_entries, int n_qslots, const double2 *wadj,
+                                const double *coef, double2 *psi, double2 *lam, int64_t batch, int wg_per_inst,
+                                double *partials, int n_pgates, hipStream_t s)
+{
+    const TileGeom &g = pp.geom;
+    if (g.k < 8 || g.k > 11 || slot0 < 0 || slot0 + 3 * pp.fstage_count > n_slots) return hipErrorInvalidValue;
+    const int64_t tiles = 1ll << g.nout;
+    const size_t lds = reverse_fused_lds(g.k, g.c, pp.fstage_count, n_qslots);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    hipError_t e = ensure_lds(k_reverse_fused, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reverse_fused, dim3(wg_per_inst, (unsigned)batch), dim3(kThreads), lds, s, geom_dev, g.n,
+                       g.k, g.c, g.nout, fstages + pp.fstage_begin, pp.fstage_count, fconds, slot_off, slot_info,
+                       slot0, n_slots, n_entries, wadj, coef, psi, lam, tiles, partials, n_pgates);
     return hipGetLastError();
 }
 

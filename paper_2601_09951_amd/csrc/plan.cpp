@@ -198,7 +198,8 @@ static void free_plan(Context *ctx, CircPlan *p)
 static bool build_fused(const Circ *C, const std::vector<int> &take, const std::vector<int> &tile, int keff,
                         int RB, CircPlan *plan, PassPlan &pp)
 {
-    if (keff < kStageMinK || keff > 12) return false;
+    // one sub-cube of 2^RB amplitudes per thread of a 256-thread workgroup
+    if (keff < kStageMinK || keff > RB + 8) return false;
     const uint64_t tmask = mask_of(tile);
     struct Perm {
         int kind;          // 0: CNOT inside the tile, 1: X, 2: X under a control outside the tile
@@ -273,7 +274,7 @@ static bool build_fused(const Circ *C, const std::vector<int> &take, const std::
                     for (int g : oneq[rb[i]]) {
                         plan->host_fslot_gate.push_back(g);
                         const GateHost &h = C->gates[g];
-                        plan->host_fslot_info.push_back(((C->pgate_of_gate[g] + 1) << 4) | h.gen);
+                        plan->host_fslot_info.push_back(((C->pgate_of_gate[g] + 1) << 4) | (h.cls << 2) | h.gen);
                     }
                 plan->host_fslot_off.push_back((int32_t)plan->host_fslot_gate.size());
             }
@@ -536,7 +537,23 @@ CircPlan *get_circ_plan(Circ *C, bool reverse, int k, int c, int *rc)
         {
             const size_t f0 = plan->host_fstages.size(), c0 = plan->host_fconds.size();
             const size_t s0 = plan->host_fslot_off.size(), g0 = plan->host_fslot_gate.size();
-            if (!build_fused(C, take, tile, keff, reverse ? 3 : 4, plan.get(), pp)) {
+            bool ok = build_fused(C, take, tile, keff, reverse ? 3 : 4, plan.get(), pp);
+            if (ok && reverse) {
+                // the adjoint kernel keeps both tiles, every slot's product and
+                // three sums per slot with parametric gates in LDS
+                int np = 0, nq = 0;
+                for (int sl = (int)s0 - 1; sl < plan->n_fslots(); ++sl) {
+                    int here = 0;
+                    for (int e = plan->host_fslot_off[sl]; e < plan->host_fslot_off[sl + 1]; ++e)
+                        here += plan->host_fslot_info[e] >= 16;
+                    np += here;
+                    nq += here > 0;
+                }
+                const int nst = (int)(plan->host_fstages.size() - f0);
+                pp.fq_count = nq;
+                ok = np == nparam && reverse_fused_lds(keff, ceff, nst, nq) <= 160 * 1024;
+            }
+            if (!ok) {
                 plan->host_fstages.resize(f0);
                 plan->host_fconds.resize(c0);
                 plan->host_fslot_off.resize(s0);
@@ -544,6 +561,7 @@ CircPlan *get_circ_plan(Circ *C, bool reverse, int k, int c, int *rc)
                 plan->host_fslot_info.resize(g0);
                 pp.fstage_begin = (int)f0;
                 pp.fstage_count = 0;
+                pp.fq_count = 0;
             }
         }
         if (keff >= kStageMinK) {

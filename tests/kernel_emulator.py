@@ -398,11 +398,18 @@ def forward_fused(passes, ops, fstages, fconds, soff, sgate, psi, mats):
     return psi
 
 
-def reverse_fused(passes, ops, fstages, fconds, soff, sgate, sinfo, psi, lam, mats, n_pgates):
-    """Adjoint passes with fused stages where the plan has them: per active
-    register bit, its gates undone one by one (gradient term Im<lam|G|psi>,
-    then U^dagger on both states), then the stage's store map; the op-by-op
-    path elsewhere."""
+def reverse_fused(passes, ops, fstages, fconds, soff, sgate, sinfo, psi, lam, mats, n_pgates, method="gates"):
+    """Adjoint passes with fused stages where the plan has them, then the
+    stage's store map; the op-by-op path elsewhere.  Per active register bit:
+
+    * method "gates": the bit's gates undone one by one (gradient term
+      Im<lam|G|psi>, then U^dagger on both states);
+    * method "coef": as the device kernel does it: the pair sums
+      Q0 = Im(conj(la) a) - Im(conj(lb) b), Q1 = Im(conj(la) b + conj(lb) a),
+      Q2 = Re(conj(la) b - conj(lb) a) of the states before the bit's gates,
+      each gradient as k00 Q0 + Re k01 Q1 + Im k01 Q2 with K = V^dagger G V
+      (V the product of the U^dagger undone before it), then the product of
+      all U^dagger at once."""
     psi, lam = psi.copy(), lam.copy()
     gpart = np.zeros(n_pgates)
     pauli = {GEN_X: np.array([[0, 1], [1, 0]], dtype=complex), GEN_Y: np.array([[0, -1j], [1j, 0]]),
@@ -436,10 +443,27 @@ def reverse_fused(passes, ops, fstages, fconds, soff, sgate, sinfo, psi, lam, ma
                 lo = [i for i in range(1 << nb) if not (i & M)]
                 hi = [i | M for i in lo]
                 slot = int(fs["slot"]) + j
+                if method == "coef":
+                    a, b, la, lb = X[:, :, lo], X[:, :, hi], L[:, :, lo], L[:, :, hi]
+                    q0 = (np.conj(la) * a).imag.sum() - (np.conj(lb) * b).imag.sum()
+                    q1 = (np.conj(la) * b + np.conj(lb) * a).imag.sum()
+                    q2 = (np.conj(la) * b - np.conj(lb) * a).real.sum()
+                    V = np.eye(2, dtype=complex)
+                    for e in range(int(soff[slot]), int(soff[slot + 1])):
+                        info = int(sinfo[e])
+                        pg, gen = (info >> 4) - 1, info & 3
+                        if pg >= 0:
+                            K = V.conj().T @ pauli[gen] @ V
+                            gpart[pg] += K[0, 0].real * q0 + K[0, 1].real * q1 + K[0, 1].imag * q2
+                        V = mats[int(sgate[e])].conj().T @ V
+                    a, b, la, lb = a.copy(), b.copy(), la.copy(), lb.copy()
+                    X[:, :, lo], X[:, :, hi] = V[0, 0] * a + V[0, 1] * b, V[1, 0] * a + V[1, 1] * b
+                    L[:, :, lo], L[:, :, hi] = V[0, 0] * la + V[0, 1] * lb, V[1, 0] * la + V[1, 1] * lb
+                    continue
                 for e in range(int(soff[slot]), int(soff[slot + 1])):
                     W = mats[int(sgate[e])].conj().T
                     info = int(sinfo[e])
-                    pg, gen = (info >> 4) - 1, info & 15
+                    pg, gen = (info >> 4) - 1, info & 3
                     a, b, la, lb = X[:, :, lo].copy(), X[:, :, hi].copy(), L[:, :, lo].copy(), L[:, :, hi].copy()
                     if pg >= 0:
                         P = pauli[gen]

@@ -153,6 +153,31 @@ def test_fused_forward_passes(vqe, ctx, n, k, c, seed):
         np.testing.assert_allclose(got[b], oracle.state(spec, th[b]), atol=S_TOL)
 
 
+@pytest.mark.parametrize("n,kr,c,seed", [(10, 8, 2, 11), (12, 9, 4, 12), (14, 11, 4, 13), (16, 11, 4, 14),
+                                          (13, 10, 3, 15)])
+def test_fused_adjoint_passes(vqe, ctx, n, kr, c, seed):
+    """Energy and adjoint gradient of rotation / X / H / CNOT circuits with
+    the adjoint passes as fused stages (per-qubit pair sums and gradient
+    coefficients, CNOT networks as data movement), batch of 2, against the
+    oracle."""
+    _say("fused adjoint", n, kr, c, seed)
+    ctx.set_tile(12, kr, c)
+    spec = synth.random_rotation_cnot_circuit(n, 120, seed=seed)
+    ham = synth.random_pauli_sum(n, 60, seed=seed)
+    th = synth.uniform_thetas(spec.n_params, 2, seed=seed)
+    C = vqe.Circuit.from_spec(ctx, spec)
+    H = vqe.Hamiltonian.from_sum(ctx, ham)
+    passes = vqe.circuit_plan(ctx, C, reverse=True, stages="fused")[0]
+    assert int(passes["fstage_count"].sum()) > 0
+    e, g = vqe.energy_grad(ctx, C, H, dev(th))
+    torch.cuda.synchronize()
+    e, g = e.cpu().numpy(), g.cpu().numpy()
+    for b in range(2):
+        eo, go = oracle.energy_grad(spec, ham, th[b], "adjoint")
+        assert abs(e[b] - eo) < E_TOL
+        np.testing.assert_allclose(g[b], go, atol=G_TOL)
+
+
 @pytest.mark.parametrize("staged", [2, 1, 0])
 @pytest.mark.parametrize("n,k,c", [(14, 8, 3), (16, 12, 4), (17, 11, 4), (15, 13, 5)])
 def test_hea_energy_grad_multi_tile(vqe, ctx, n, k, c, staged):

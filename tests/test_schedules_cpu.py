@@ -230,10 +230,25 @@ def test_fused_adjoint_schedules(ctx, kind, n, k, c):
     assert len(fst) > 0 and (fst["nb"] == 3).all()
     psi = oracle.state(spec, th)
     n_pg = int((spec.param_idx >= 0).sum())
-    back, _, gpart = emu.reverse_fused(rp, rops, fst, fco, soff, sg, si, psi, oracle.apply_hamiltonian(psi, ham),
-                                       mats, n_pg)
     ref = np.zeros(1 << n, dtype=complex)
     ref[spec.ref_index] = 1
-    np.testing.assert_allclose(back, ref, atol=1e-12)
     _, g_or = oracle.energy_grad(spec, ham, th, "adjoint")
-    np.testing.assert_allclose(_grad_from_parts(spec, gpart), g_or, atol=1e-11)
+    for method in ("gates", "coef"):
+        back, _, gpart = emu.reverse_fused(rp, rops, fst, fco, soff, sg, si, psi,
+                                           oracle.apply_hamiltonian(psi, ham), mats, n_pg, method=method)
+        np.testing.assert_allclose(back, ref, atol=1e-12)
+        np.testing.assert_allclose(_grad_from_parts(spec, gpart), g_or, atol=1e-11)
+
+
+def test_fused_adjoint_tile_limit(ctx):
+    """Adjoint fused stages hold one 8-amplitude sub-cube per thread of a
+    256-thread workgroup, so 12-bit reverse tiles take the staged path while
+    the forward plan (16-amplitude sub-cubes) still fuses."""
+    ctx.set_tile(12, 12, 4)
+    spec = synth.hea_circuit(14, 2)
+    C = vqe.Circuit.from_spec(ctx, spec)
+    fwd = vqe.circuit_plan(ctx, C, stages="fused")[0]
+    rev = vqe.circuit_plan(ctx, C, reverse=True, stages="fused")[0]
+    assert int(fwd["fstage_count"].sum()) > 0
+    assert int(rev["fstage_count"].sum()) == 0
+    assert (rev["stage_count"] > 0).any()
