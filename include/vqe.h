@@ -115,13 +115,17 @@ int vqe_ctx_set_tile(vqe_ctx_t ctx, int k_fwd, int k_rev, int c_low);
  * step). */
 int vqe_ctx_set_loop_mode(vqe_ctx_t ctx, int mode);
 
-/* Kernel variant of the state passes: staged = 2 (default) runs forward
- * passes made of uncontrolled one-qubit gates, X and CNOT as fused stages
- * (one 2x2 per qubit, the CNOT / X network folded into data movement) and
- * everything else as staged = 1; staged = 1 applies the gates of a pass in
- * register stages of four tile bits (tiles of 8 or more bits); staged = 0
- * applies one gate per LDS round trip.  All compute the same result; the
- * switch exists for measurement. */
+/* Kernel variant of the state passes: staged = 2 (default) runs forward and
+ * adjoint passes made of uncontrolled one-qubit gates, X and CNOT as fused
+ * stages (one 2x2 per qubit, the CNOT / X network folded into data
+ * movement; in adjoint passes the gradient terms of a qubit's gates come
+ * from three pair sums of the states before them) and everything else as
+ * staged = 1; staged = 1 applies the gates of a pass in register stages of
+ * four (forward) or three (adjoint) tile bits (tiles of 8 or more bits);
+ * staged = 0 applies one gate per LDS round trip and also accumulates
+ * H psi by pair updates in LDS, where staged >= 1 gathers every amplitude
+ * of H psi in registers (tiles of 8 to 11 bits).  All compute the same
+ * result up to rounding; the switch exists for measurement. */
 int vqe_ctx_set_staged(vqe_ctx_t ctx, int staged);
 
 /* Reserve `bytes` of context scratch now (used by vqe_expect and

@@ -314,6 +314,19 @@ int expect_into(Context *ctx, int n_hams, Ham *const *H, int64_t B, const double
     return hip_check(ctx, launch_reduce_slots(partials, S, W, B, energy, e_stride, 1.0, s), "energy reduce");
 }
 
+// one H psi sweep into lam (first: lam = sweep, else lam += sweep; last: the
+// energy partials); the gather kernel where the tile allows it
+hipError_t hpsi_sweep(Context *ctx, PauliPlan *pp, int i, const double2 *psi, double2 *lam, int64_t B,
+                      int ham_div, int W, double *partials, hipStream_t s)
+{
+    const int S = (int)pp->sweeps.size();
+    const int k = pp->sweeps[i].geom.k;
+    if (!ctx->no_stages && k >= 8 && k <= 11)
+        return launch_hpsi_gather(pp->sweeps[i], *pp, i, psi, lam, B, ham_div, W, partials, i == 0, i == S - 1, s);
+    return launch_pauli_sweep(pp->sweeps[i], *pp, i, psi, lam, B, ham_div, W, partials, 1, true, i == 0,
+                              i == S - 1, s);
+}
+
 int energy_grad_into(Context *ctx, Circ *C, int n_hams, Ham *const *H, int64_t B, uint64_t ref,
                      const double *theta, double *energy, int64_t e_stride, double *grad,
                      unsigned char *ws, const Layout &L, hipStream_t s)
@@ -339,8 +352,7 @@ int energy_grad_into(Context *ctx, Circ *C, int n_hams, Ham *const *H, int64_t B
     if (rc) return rc;
     const int S = (int)pp->sweeps.size();
     for (int i = 0; i < S; ++i) {
-        rc = hip_check(ctx, launch_pauli_sweep(pp->sweeps[i], *pp, i, psi, lam, B, n_hams == 1 ? 0 : 1, L.W_hpsi,
-                                               pe, 1, true, i == 0, i == S - 1, s),
+        rc = hip_check(ctx, hpsi_sweep(ctx, pp, i, psi, lam, B, n_hams == 1 ? 0 : 1, L.W_hpsi, pe, s),
                        "H psi sweep");
         if (rc) return rc;
     }
@@ -980,9 +992,8 @@ int vqe_apply_hamiltonian(vqe_ctx_t ctx, int n_hams, const vqe_ham_t *hams, int6
     if (rc) return rc;
     const int S = (int)pp->sweeps.size();
     for (int i = 0; i < S; ++i) {
-        rc = hip_check(ctx, launch_pauli_sweep(pp->sweeps[i], *pp, i, (const double2 *)psi, (double2 *)out,
-                                               batch, n_hams == 1 ? 0 : 1, W, (double *)part, 1, true, i == 0,
-                                               i == S - 1, (hipStream_t)stream),
+        rc = hip_check(ctx, hpsi_sweep(ctx, pp, i, (const double2 *)psi, (double2 *)out, batch,
+                                       n_hams == 1 ? 0 : 1, W, (double *)part, (hipStream_t)stream),
                        "H psi sweep");
         if (rc) return rc;
     }

@@ -369,6 +369,9 @@ hipError_t launch_pauli_sweep(const SweepPlan &sp, const PauliPlan &pp, int swee
                               int ham_div, int wg_per_inst, double *partials,
                               int n_slots, bool write_lambda, bool first, bool last,
                               hipStream_t s);
+hipError_t launch_hpsi_gather(const SweepPlan &sp, const PauliPlan &pp, int sweep_idx, const double2 *psi,
+                              double2 *lam, int64_t batch, int ham_div, int wg_per_inst, double *partials,
+                              bool first, bool last, hipStream_t s);
 hipError_t launch_reduce_slots(const double *partials, int n_slots, int wg_per_inst,
                                int64_t batch, double *out, int64_t out_stride, double scale,
                                hipStream_t s);

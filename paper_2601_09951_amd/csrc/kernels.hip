@@ -55,6 +55,22 @@ __device__ __forceinline__ uint64_t tile_base(const TileGeom *__restrict__ gp, i
     return base;
 }
 
+// tile bases from an LDS table of the tile-number bits' index masks (obit[i]
+// = 1 << opos[i], filled by fill_obit): LDS reads do not wait on outstanding
+// global loads, as the byte loads of the geometry would
+__device__ __forceinline__ void fill_obit(const TileGeom *__restrict__ gp, int nout, uint64_t *obit)
+{
+    for (int i = threadIdx.x; i < nout; i += blockDim.x) obit[i] = 1ull << gp->opos[i];
+}
+
+__device__ __forceinline__ uint64_t tile_base_l(const uint64_t *obit, int nout, int64_t t)
+{
+    uint64_t base = 0;
+    for (int i = 0; i < nout; ++i)
+        if ((t >> i) & 1) base |= obit[i];
+    return base;
+}
+
 // offsets of the gathered (non-contiguous) part of a tile
 __device__ __forceinline__ void fill_hoff(const TileGeom *__restrict__ gp, int k, int c, uint64_t *hoff)
 {
@@ -1603,6 +1619,158 @@ __global__ __launch_bounds__(kThreads) void k_pauli_sweep(
     }
 }
 
+// H psi of one sweep by gathering.  Every thread owns NO amplitudes
+// o = tid + r * kThreads of the tile and accumulates (H psi)[o] in registers
+// over the sweep's groups.  For a flip group f with pivot bit v, let
+// p = o when bit v of o is 0 and p = o ^ f otherwise (the pair's element with
+// the pivot bit clear, where the pair form above evaluates A and B); then
+//   (H psi)[o] += (A(p) + i s B(p)) psi[o ^ f],   s = +1 if bit v of o is 1, else -1,
+// and the diagonal group adds A(o) psi[o].  psi is only read from LDS, so the
+// groups need no barrier between them, and lambda never passes through LDS:
+// each thread reads its running lambda from HBM at the start of the tile (in
+// flight while the groups run) and writes the sum back.  The last sweep also
+// accumulates Re <psi|lambda> (the energy) over its amplitudes.
+template <int NO>
+__global__ __launch_bounds__(kThreads) void k_hpsi_gather(
+    const TileGeom *__restrict__ gp, int n, int k, int c, int nout, const GroupDev *__restrict__ groups,
+    int ngroups, const int32_t *__restrict__ toff, int n_ugroups, const TermDev *__restrict__ terms, int ham_div,
+    const double2 *__restrict__ psi, double2 *__restrict__ lam, int64_t tiles, int first, int last,
+    double *__restrict__ partials, int n_slots, int tcap)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    double2 *tp = reinterpret_cast<double2 *>(smem);
+    uint64_t *hoff = reinterpret_cast<uint64_t *>(smem + (16u << k));
+    double *red = reinterpret_cast<double *>(hoff + (1u << (k - c)));
+    uint64_t *zf = reinterpret_cast<uint64_t *>(red + 4);
+    double *w0 = reinterpret_cast<double *>(zf + tcap);
+    double *wl = w0 + tcap;
+    uint32_t *zl = reinterpret_cast<uint32_t *>(wl + tcap);
+    __shared__ uint64_t obit[64];
+    const int tid = threadIdx.x;
+    const uint64_t dim = 1ull << n;
+    const int inst = blockIdx.y;
+    const double2 *sp = psi + (uint64_t)inst * dim;
+    double2 *sl = lam + (uint64_t)inst * dim;
+    const int32_t *to = toff + (size_t)(ham_div == 0 ? 0 : inst / ham_div) * n_ugroups * 3;
+    const uint32_t lowm = (1u << c) - 1u;
+    const int tstart = to[groups[0].ugroup * 3];
+    const int nt = to[groups[ngroups - 1].ugroup * 3 + 2] - tstart;
+    const bool staged = nt <= tcap;
+    fill_hoff(gp, k, c, hoff);
+    fill_obit(gp, nout, obit);
+    if (staged)
+        for (int i = tid; i < nt; i += kThreads) {
+            const TermDev d = terms[tstart + i];
+            zf[i] = d.zfull;
+            zl[i] = d.zloc;
+            w0[i] = d.w;
+        }
+    __syncthreads();
+    double eacc = 0.0;
+    for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+        const uint64_t base = tile_base_l(obit, nout, t);
+        {
+            double2 own[NO];
+#pragma unroll
+            for (int r = 0; r < NO; ++r) {
+                const uint32_t o = (uint32_t)(tid + r * kThreads);
+                own[r] = sp[base + hoff[o >> c] + (o & lowm)];
+            }
+#pragma unroll
+            for (int r = 0; r < NO; ++r) tp[tid + r * kThreads] = own[r];
+        }
+        if (staged)  // fold the sign of the bits outside the tile into the weights
+            for (int i = tid; i < nt; i += kThreads)
+                wl[i] = signed_by_parity(w0[i], (uint32_t)(__popcll(zf[i] & base) & 1));
+        lds_barrier();
+        double2 acc[NO];
+#pragma unroll
+        for (int r = 0; r < NO; ++r) acc[r] = make_double2(0.0, 0.0);
+        for (int q = 0; q < ngroups; ++q) {
+            const GroupDev gd = groups[q];
+            const int tb = to[gd.ugroup * 3 + 0], tm = to[gd.ugroup * 3 + 1], te = to[gd.ugroup * 3 + 2];
+            if (te == tb) continue;
+            const uint32_t f = gd.floc, pv = gd.pivot;
+            uint32_t pr[NO];
+            double A[NO], B[NO];
+#pragma unroll
+            for (int r = 0; r < NO; ++r) {
+                const uint32_t o = (uint32_t)(tid + r * kThreads);
+                pr[r] = ((o >> pv) & 1u) ? o ^ f : o;
+                A[r] = 0.0;
+                B[r] = 0.0;
+            }
+            if (staged) {
+                for (int i = tb - tstart; i < tm - tstart; ++i) {
+                    const uint32_t z = zl[i];
+                    const double w = wl[i];
+#pragma unroll
+                    for (int r = 0; r < NO; ++r) A[r] += signed_by_parity(w, z & pr[r]);
+                }
+                for (int i = tm - tstart; i < te - tstart; ++i) {
+                    const uint32_t z = zl[i];
+                    const double w = wl[i];
+#pragma unroll
+                    for (int r = 0; r < NO; ++r) B[r] += signed_by_parity(w, z & pr[r]);
+                }
+            } else {
+                for (int i = tb; i < te; ++i) {
+                    const TermDev d = terms[i];
+                    const double w = signed_by_parity(d.w, (uint32_t)(__popcll(d.zfull & base) & 1));
+#pragma unroll
+                    for (int r = 0; r < NO; ++r) {
+                        const double v = signed_by_parity(w, d.zloc & pr[r]);
+                        if (i < tm)
+                            A[r] += v;
+                        else
+                            B[r] += v;
+                    }
+                }
+            }
+            if (f == 0) {
+#pragma unroll
+                for (int r = 0; r < NO; ++r) {
+                    const double2 x = tp[tid + r * kThreads];
+                    acc[r].x = fma(A[r], x.x, acc[r].x);
+                    acc[r].y = fma(A[r], x.y, acc[r].y);
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < NO; ++r) {
+                    const uint32_t o = (uint32_t)(tid + r * kThreads);
+                    const double2 x = tp[o ^ f];
+                    const double b = ((o >> pv) & 1u) ? B[r] : -B[r];
+                    acc[r].x += A[r] * x.x - b * x.y;
+                    acc[r].y += A[r] * x.y + b * x.x;
+                }
+            }
+        }
+        // lambda += the tile's H psi, all reads of the running sum in flight together
+        uint64_t gi[NO];
+        double2 run[NO];
+#pragma unroll
+        for (int r = 0; r < NO; ++r) {
+            const uint32_t o = (uint32_t)(tid + r * kThreads);
+            gi[r] = base + hoff[o >> c] + (o & lowm);
+            run[r] = first ? make_double2(0.0, 0.0) : sl[gi[r]];
+        }
+#pragma unroll
+        for (int r = 0; r < NO; ++r) {
+            const double2 v = cadd(acc[r], run[r]);
+            sl[gi[r]] = v;
+            if (last) {
+                const double2 a = tp[tid + r * kThreads];
+                eacc += a.x * v.x + a.y * v.y;
+            }
+        }
+        lds_barrier();  // every read of this tile is done before the next tile's writes
+    }
+    if (last) {
+        const double e = block_sum(eacc, red);
+        if (tid == 0) partials[(size_t)inst * n_slots * gridDim.x + blockIdx.x] = e;
+    }
+}
+
 // out[inst * stride] = scale * sum_{slot, wg} partials[inst][slot][wg], fixed order
 __global__ __launch_bounds__(kThreads) void k_reduce_slots(const double *__restrict__ partials,
                                                            int n, double *__restrict__ out,
@@ -1891,6 +2059,41 @@ hipError_t launch_pauli_sweep(const SweepPlan &sp, const PauliPlan &pp, int swee
                        reinterpret_cast<const TermDev *>(pp.terms.p), ham_div, psi,
                        write_lambda ? lam : nullptr, tiles, (int)first, (int)last, partials,
                        n_slots, write_lambda ? 0 : sweep_idx, tcap);
+    return hipGetLastError();
+}
+
+hipError_t launch_hpsi_gather(const SweepPlan &sp, const PauliPlan &pp, int sweep_idx, const double2 *psi,
+                              double2 *lam, int64_t batch, int ham_div, int wg_per_inst, double *partials,
+                              bool first, bool last, hipStream_t s)
+{
+    const TileGeom &g = sp.geom;
+    if (g.k < 8 || g.k > 11) return hipErrorInvalidValue;
+    const int64_t tiles = 1ll << g.nout;
+    // the psi tile, hoff, the reduction slots and alignment slack; then
+    // kTermBytes per staged term, within a quarter, half or all of the LDS
+    const size_t base = (16u << g.k) + (8u << (g.k - g.c)) + 64 + 16 + 512;
+    size_t budget = kLdsLimit / 4;
+    if (base + 64 * kTermBytes > budget) budget = kLdsLimit / 2;
+    if (base + 64 * kTermBytes > budget) budget = kLdsLimit;
+    const int tcap = (int)std::min<size_t>(2048, (budget - std::min(budget, base)) / kTermBytes);
+    const size_t lds = base - 512 + (size_t)tcap * kTermBytes;  // obit is static LDS
+    if (lds + 512 > kLdsLimit) return hipErrorInvalidValue;
+    void (*kern)(const TileGeom *, int, int, int, int, const GroupDev *, int, const int32_t *, int, const TermDev *,
+                 int, const double2 *, double2 *, int64_t, int, int, double *, int, int);
+    switch (g.k) {
+    case 8: kern = k_hpsi_gather<1>; break;
+    case 9: kern = k_hpsi_gather<2>; break;
+    case 10: kern = k_hpsi_gather<4>; break;
+    default: kern = k_hpsi_gather<8>; break;
+    }
+    hipError_t e = ensure_lds(kern, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(wg_per_inst, (unsigned)batch), dim3(kThreads), lds, s,
+                       reinterpret_cast<const TileGeom *>(pp.geoms.p) + sweep_idx, g.n, g.k, g.c, g.nout,
+                       reinterpret_cast<const GroupDev *>(pp.groups.p) + sp.grp_begin, sp.grp_count,
+                       reinterpret_cast<const int32_t *>(pp.toff.p), pp.n_ugroups,
+                       reinterpret_cast<const TermDev *>(pp.terms.p), ham_div, psi, lam, tiles, (int)first,
+                       (int)last, partials, 1, tcap);
     return hipGetLastError();
 }
 
