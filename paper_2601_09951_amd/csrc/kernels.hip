@@ -1131,7 +1131,6 @@ __global__ __launch_bounds__(kThreads) void k_forward_fused(const TileGeom *__re
     double2 *tile = reinterpret_cast<double2 *>(smem);
     uint64_t *hoff = reinterpret_cast<uint64_t *>(smem + (16u << k));
     Mat2 *fm = reinterpret_cast<Mat2 *>(hoff + (1u << (k - c)));  // 4 per stage
-    FusedStage *fs_l = reinterpret_cast<FusedStage *>(fm + 4 * nstages);
     const int tid = threadIdx.x;
     const uint64_t dim = 1ull << n;
     double2 *st = psi + (uint64_t)blockIdx.y * dim;
@@ -1142,14 +1141,13 @@ __global__ __launch_bounds__(kThreads) void k_forward_fused(const TileGeom *__re
     const double2 *F = fused + ((size_t)blockIdx.y * n_slots + slot0) * 4;
     double2 *fmd = reinterpret_cast<double2 *>(fm);
     for (int i = tid; i < 16 * nstages; i += kThreads) fmd[i] = F[i];  // 4 double2 per matrix
-    for (int i = tid; i < nstages; i += kThreads) fs_l[i] = fstages[i];
     __syncthreads();
     for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
         const uint64_t base = tile_base(gp, nout, t);
         tile_in<16, true>(tile, st, base, hoff, T, c);
         lds_barrier();
         for (int s = 0; s < nstages; ++s) {
-            const FusedStage &fs = fs_l[s];
+            const FusedStage fs = fstages[s];  // uniform: scalar loads
             const int na = (int)__builtin_amdgcn_readfirstlane((uint32_t)fs.na);
             const int perm = (int)__builtin_amdgcn_readfirstlane((uint32_t)fs.perm);
             uint32_t ctile = fs.c0;
@@ -1364,8 +1362,7 @@ __global__ __launch_bounds__(kThreads) void k_reverse_fused(
     uint64_t *hoff = reinterpret_cast<uint64_t *>(smem + (32u << k));
     const int ns = 3 * nstages;
     Mat2 *wm = reinterpret_cast<Mat2 *>(hoff + (1u << (k - c)));
-    FusedStage *fs_l = reinterpret_cast<FusedStage *>(wm + ns);
-    int32_t *qidx = reinterpret_cast<int32_t *>(fs_l + nstages);
+    int32_t *qidx = reinterpret_cast<int32_t *>(wm + ns);
     double *red = reinterpret_cast<double *>(qidx + ((ns + 1) & ~1));
     const int tid = threadIdx.x;
     const uint64_t dim = 1ull << n;
@@ -1377,7 +1374,6 @@ __global__ __launch_bounds__(kThreads) void k_reverse_fused(
     const double2 *Wg = wadj + ((size_t)blockIdx.y * n_slots + slot0) * 4;
     double2 *wmd = reinterpret_cast<double2 *>(wm);
     for (int i = tid; i < 4 * ns; i += kThreads) wmd[i] = Wg[i];
-    for (int i = tid; i < nstages; i += kThreads) fs_l[i] = fstages[i];
     int nq = 0;  // slots with parametric gates, numbered in order (every thread counts)
     for (int i = 0; i < ns; ++i) {
         bool par = false;
@@ -1392,7 +1388,7 @@ __global__ __launch_bounds__(kThreads) void k_reverse_fused(
         tile_in2<8, true>(tp, tl, sp, sl, base, hoff, T, c);
         __syncthreads();
         for (int s = 0; s < nstages; ++s) {
-            const FusedStage &fs = fs_l[s];
+            const FusedStage fs = fstages[s];  // uniform: scalar loads
             const int na = (int)__builtin_amdgcn_readfirstlane((uint32_t)fs.na);
             const int perm = (int)__builtin_amdgcn_readfirstlane((uint32_t)fs.perm);
             uint32_t ctile = fs.c0;
@@ -1580,8 +1576,9 @@ __global__ __launch_bounds__(kThreads) void k_pauli_sweep(
                     }
                 }
             }
-            __syncthreads();
+            if (HPSI) __syncthreads();  // the next group updates other threads' lam entries
         }
+        if (!HPSI) __syncthreads();  // expectation: psi is read-only until the next tile
         if (HPSI) {
             // lam += the tile's H psi, all reads of a batch in flight together
             constexpr int NB = 8;
@@ -1945,7 +1942,7 @@ hipError_t launch_forward_fused(const PassPlan &pp, const TileGeom *geom_dev, co
     if (g.k < 8 || g.k > 12) return hipErrorInvalidValue;
     const int64_t tiles = 1ll << g.nout;
     const int W = (int)std::min<int64_t>(tiles, wg_max);
-    const size_t lds = fwd_lds(g) + (size_t)pp.fstage_count * (4 * sizeof(Mat2) + sizeof(FusedStage));
+    const size_t lds = fwd_lds(g) + (size_t)pp.fstage_count * 4 * sizeof(Mat2);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     hipError_t e = ensure_lds(k_forward_fused, lds);
     if (e != hipSuccess) return e;
@@ -1968,8 +1965,7 @@ hipError_t launch_adjoint_coefs(const int32_t *slot_off, const int32_t *slot_gat
 size_t reverse_fused_lds(int k, int c, int nstages, int n_qslots)
 {
     const size_t ns = 3 * (size_t)nstages;
-    return (32u << k) + (8u << (k - c)) + ns * sizeof(Mat2) + (size_t)nstages * sizeof(FusedStage) +
-           4 * ((ns + 1) & ~(size_t)1) + 96 * (size_t)n_qslots;
+    return (32u << k) + (8u << (k - c)) + ns * sizeof(Mat2) + 4 * ((ns + 1) & ~(size_t)1) + 96 * (size_t)n_qslots;
 }
 
 hipError_t launch_reverse_fused(const PassPlan &pp, const TileGeom *geom_dev, const FusedStage *fstages,
