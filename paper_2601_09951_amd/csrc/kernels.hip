@@ -240,6 +240,28 @@ __device__ __forceinline__ double wave_total(double v)
     return ((read_lane(v, 0) + read_lane(v, 16)) + read_lane(v, 32)) + read_lane(v, 48);
 }
 
+// The same sum, complete in lane 63 only (fixed order): the row sums are
+// carried across rows by row_bcast:15 (rows 1, 3) and row_bcast:31 (rows 2,
+// 3), so no readlane round trip through scalar registers is needed.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_move_rows(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_total_last(double v)
+{
+    v += dpp_move<0xB1>(v);
+    v += dpp_move<0x4E>(v);
+    v += dpp_move<0x141>(v);
+    v += dpp_move<0x140>(v);
+    v += dpp_move_rows<0x142, 0xA>(v);  // row_bcast:15
+    v += dpp_move_rows<0x143, 0xC>(v);  // row_bcast:31
+    return v;
+}
+
 // sum of v over the workgroup (kThreads threads), fixed order; result in
 // thread 0.  red must hold kThreads/64 doubles.
 __device__ __forceinline__ double block_sum(double v, double *red)
@@ -1273,14 +1295,14 @@ __device__ __forceinline__ void rbit_step(double2 (&x)[8], double2 (&l)[8], cons
     if (qs >= 0) {  // the slot holds parametric gates (uniform)
         double q0, q1, q2;
         rbit_q<B>(x, l, q0, q1, q2);
-        q0 = wave_total(q0);
-        q1 = wave_total(q1);
-        q2 = wave_total(q2);
-        if ((threadIdx.x & 63) == 0) {
+        q0 = wave_total_last(q0);
+        q1 = wave_total_last(q1);
+        q2 = wave_total_last(q2);
+        if ((threadIdx.x & 63) == 63) {  // LDS adds without a return value: no wait
             double *r = red + (size_t)qs * 12 + (threadIdx.x >> 6);
-            r[0] += q0;
-            r[4] += q1;
-            r[8] += q2;
+            atomicAdd(r, q0);
+            atomicAdd(r + 4, q1);
+            atomicAdd(r + 8, q2);
         }
     }
 #pragma unroll
