@@ -1094,6 +1094,37 @@ __global__ void k_fuse_mats(const int32_t *__restrict__ slot_off, const int32_t 
     o[3] = d;
 }
 
+// The tile index of sub-cube u's first amplitude: u with zero bits inserted
+// at the stage's register positions (the other tile bits, ascending, carry
+// the bits of u).  The positions are wave-uniform, so their sort runs on the
+// scalar unit; four or three insertions replace a loop over every tile bit.
+__device__ __forceinline__ void cswap_u(uint32_t &a, uint32_t &b)
+{
+    const uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
+    a = lo;
+    b = hi;
+}
+
+template <int RB>
+__device__ __forceinline__ uint32_t subcube_base_of(uint32_t u, const FusedStage &fs)
+{
+    uint32_t p[4] = {fs.rpos[0], fs.rpos[1], fs.rpos[2], RB > 3 ? fs.rpos[3] : 0u};
+    if (RB > 3) {
+        cswap_u(p[0], p[1]);
+        cswap_u(p[2], p[3]);
+        cswap_u(p[0], p[2]);
+        cswap_u(p[1], p[3]);
+        cswap_u(p[1], p[2]);
+    } else {
+        cswap_u(p[0], p[1]);
+        cswap_u(p[1], p[2]);
+        cswap_u(p[0], p[1]);
+    }
+#pragma unroll
+    for (int i = 0; i < RB; ++i) u = ((u >> p[i]) << (p[i] + 1)) | (u & ((1u << p[i]) - 1u));
+    return u;
+}
+
 // general 2x2 on register bit B (compile time) of a 16-amplitude sub-cube
 template <int B>
 __device__ __forceinline__ void fused_bit(double2 (&x)[16], const Mat2 &v)
@@ -1114,15 +1145,15 @@ template <int NA, bool PERM>
 __device__ __forceinline__ void fused_stage(double2 *tile, const FusedStage &fs, const Mat2 *fm, int nsub,
                                             uint32_t ctile)
 {
-    const int u = threadIdx.x;
-    const bool have = u < nsub;
-    uint32_t bl = 0, lbl = 0;
+    const bool have = (int)threadIdx.x < nsub;
+    const int u = have ? (int)threadIdx.x : 0;
+    const uint32_t bl = subcube_base_of<4>((uint32_t)u, fs);
+    uint32_t lbl = 0;
+    if (PERM) {
 #pragma unroll
-    for (int j = 0; j < 12; ++j)
-        if ((u >> j) & 1) {
-            bl |= 1u << fs.cpos[j];
-            lbl ^= fs.lc[j];
-        }
+        for (int j = 0; j < 12; ++j)
+            if ((u >> j) & 1) lbl ^= fs.lc[j];
+    }
     uint32_t roff[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i)
@@ -1331,15 +1362,15 @@ template <int NA, bool PERM>
 __device__ __forceinline__ void rev_fused_stage(double2 *tp, double2 *tl, const FusedStage &fs, const Mat2 *wm,
                                                 const int32_t *qidx, int nsub, uint32_t ctile, double *red)
 {
-    const int u = threadIdx.x;
-    const bool have = u < nsub;
-    uint32_t bl = 0, lbl = 0;
+    const bool have = (int)threadIdx.x < nsub;
+    const int u = have ? (int)threadIdx.x : 0;
+    const uint32_t bl = subcube_base_of<3>((uint32_t)u, fs);
+    uint32_t lbl = 0;
+    if (PERM) {
 #pragma unroll
-    for (int j = 0; j < 12; ++j)
-        if ((u >> j) & 1) {
-            bl |= 1u << fs.cpos[j];
-            lbl ^= fs.lc[j];
-        }
+        for (int j = 0; j < 12; ++j)
+            if ((u >> j) & 1) lbl ^= fs.lc[j];
+    }
     uint32_t roff[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i)
