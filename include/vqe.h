@@ -101,7 +101,8 @@ int vqe_ctx_set_mem_budget(vqe_ctx_t ctx, size_t bytes);
  * amplitudes a workgroup holds in LDS in forward / reverse (adjoint) passes
  * (forward 6..13, reverse 6..12), c_low = number of lowest index bits every
  * tile contains (contiguous runs of 2^c_low amplitudes); c_low >= 2 and
- * k - c_low >= 4 for both k, so a four-wire gate always fits a tile.  Pass 0
+ * k - c_low >= 4 for both k, so a four-wire gate always fits a tile.
+ * Defaults: k_fwd 12, k_rev 11, c_low 3 (runs of one 128-byte line).  Pass 0
  * to keep a value.  Changes apply to plans built afterwards.  A Pauli string
  * whose X/Y bits outside the lowest c_low bits number more than
  * k_fwd - c_low (or k_rev - c_low for gradients) is not supported

@@ -291,7 +291,7 @@ struct Context {
     int device = 0;
     size_t budget = 0;
     size_t used = 0;
-    int k_fwd = 12, k_rev = 11, c_low = 4;
+    int k_fwd = 12, k_rev = 11, c_low = 3;  // c_low 3: runs of 8 amplitudes = one 128-byte line
     int wg_max = 1024;          // workgroups per instance in tile passes
     int force_generic = 0;      // route vqe_run through the per-step launches
     int no_stages = 0;          // use the one-op-per-LDS-round-trip pass kernels only
