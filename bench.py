@@ -36,6 +36,11 @@ ITERS = 200
 BATCH = 100
 
 
+def _progress(msg):
+    """One progress line on stderr (stdout carries only the JSON result)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -181,9 +186,11 @@ def main():
             if events is not None:
                 events[i][1].record(stream)
 
+    _progress(f"setup {setup_s:.1f} s; warmup")
     for _ in range(args.warmup):
         one_scan()
     torch.cuda.synchronize()
+    _progress("timed steps")
 
     K = args.steps
     ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in problems]
@@ -243,21 +250,29 @@ def main():
     }
 
     # -------------------------------------------------- large-state HEA
+    _progress(f"scan: {value:.0f} evals/s")
     if not args.no_hea:
         out["hea"] = hea_measure(ctx, vqe, synth, torch, args.hea_n)
+        _progress("hea done")
 
     # -------------------------------------------------- C1: plain vs batched
     if not args.no_c1:
         out["c1"] = c1_measure(ctx, vqe, synth, torch)
+        _progress("c1 done")
     if args.scaling:
-        out["scaling"] = [scaling_measure(ctx, vqe, synth, torch, int(v)) for v in args.scaling.split(",")]
+        out["scaling"] = []
+        for v in args.scaling.split(","):
+            out["scaling"].append(scaling_measure(ctx, vqe, synth, torch, int(v)))
+            _progress(f"scaling n={v} done")
     if args.large:
         out["large"] = large_measure(ctx, vqe, synth, torch)
+        _progress("large done")
 
     # -------------------------------------------------- served stream
     if not args.no_served:
         out["served"] = served_measure(ctx, args.served_requests,
                                        tuple(float(x) for x in args.served_rates.split(",")))
+        _progress("served done")
 
     # -------------------------------------------------- CPU baseline
     if not args.no_cpu_baseline:

@@ -2111,8 +2111,8 @@ hipError_t launch_pauli_sweep(const SweepPlan &sp, const PauliPlan &pp, int swee
                  const TermDev *, int, const double2 *, double2 *, int64_t, int, int, double *, int, int, int);
     if (write_lambda)
         kern = big ? k_pauli_sweep<true, 4> : k_pauli_sweep<true, 1>;
-    else
-        kern = big ? k_pauli_sweep<false, 4> : k_pauli_sweep<false, 1>;
+    else  // expectation: eight pairs per thread per term read on 12-bit tiles
+        kern = g.k >= 12 ? k_pauli_sweep<false, 8> : (big ? k_pauli_sweep<false, 4> : k_pauli_sweep<false, 1>);
     hipError_t e = ensure_lds(kern, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(wg_per_inst, (unsigned)batch), dim3(kThreads), lds, s,
