@@ -52,6 +52,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-c1", action="store_true")
+    ap.add_argument("--no-qaoa", action="store_true")
     ap.add_argument("--scaling", type=str, default="",
                     help="comma-separated qubit counts for the hardware-efficient scaling leg (L = n, 500 strings)")
     ap.add_argument("--large", action="store_true",
@@ -259,6 +260,9 @@ def main():
     if not args.no_c1:
         out["c1"] = c1_measure(ctx, vqe, synth, torch)
         _progress("c1 done")
+    if not args.no_qaoa:
+        out["qaoa"] = qaoa_measure(ctx, vqe, synth, torch, 24, 4)
+        _progress("qaoa done")
     if args.scaling:
         out["scaling"] = []
         for v in args.scaling.split(","):
@@ -343,6 +347,36 @@ def hea_measure(ctx, vqe, synth, torch, n):
             "expect_sweeps": int(len(pl["sweeps"])), "ms_expect": round(ms_exp, 3),
             "expect_sweep_GBps": round(sweep_gbps, 1),
             "expect_sweep_frac_of_hbm": round(sweep_gbps / HBM_PEAK_GBPS, 4)}
+
+
+def qaoa_measure(ctx, vqe, synth, torch, n, layers):
+    """QAOA MaxCut (the diagonal-only Hamiltonian path): energy + adjoint
+    gradient on a ring of n vertices with n / 2 random chords, `layers`
+    layers (2 shared parameters each)."""
+    dev = torch.device("cuda:0")
+    edges = synth.ring_graph(n, n // 2, seed=synth.MASTER_SEED + n)
+    spec = synth.qaoa_circuit(n, edges, layers)
+    ham = synth.maxcut_hamiltonian(n, edges)
+    C = vqe.Circuit.from_spec(ctx, spec)
+    H = vqe.Hamiltonian.from_sum(ctx, ham)
+    th = torch.tensor(synth.uniform_thetas(spec.n_params, 1, seed=synth.MASTER_SEED + n), device=dev)
+    ws = vqe.workspace(ctx, C, H, 1, 1)
+    e = torch.empty(1, dtype=torch.float64, device=dev)
+    g = torch.empty(1, spec.n_params, dtype=torch.float64, device=dev)
+    vqe.energy_grad(ctx, C, H, th, ws=ws, out_e=e, out_g=g)
+    torch.cuda.synchronize()
+    reps = 3
+    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s0.record()
+    for _ in range(reps):
+        vqe.energy_grad(ctx, C, H, th, ws=ws, out_e=e, out_g=g)
+    s1.record()
+    torch.cuda.synchronize()
+    passes = vqe.circuit_plan(ctx, C)[0]
+    rpasses = vqe.circuit_plan(ctx, C, reverse=True)[0]
+    return {"n": n, "layers": layers, "edges": len(edges), "gates": spec.n_gates, "params": spec.n_params,
+            "terms": len(edges), "flip_groups": int(H.n_groups), "forward_passes": int(len(passes)),
+            "adjoint_passes": int(len(rpasses)), "ms_per_energy_grad": round(s0.elapsed_time(s1) / reps, 3)}
 
 
 def c1_measure(ctx, vqe, synth, torch):

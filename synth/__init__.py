@@ -412,6 +412,48 @@ def random_rotation_cnot_circuit(n: int, n_gates: int, seed: int) -> Circuit:
     return _circuit(n, gates, max(p, 1), ref)
 
 
+def random_graph(n: int, edge_prob: float, seed: int = MASTER_SEED) -> List[Tuple[int, int]]:
+    """Erdos-Renyi graph G(n, p) as a list of edges (a, b), a < b, in order."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return [(a, b) for a in range(n) for b in range(a + 1, n) if rng.random() < edge_prob]
+
+
+def ring_graph(n: int, chords: int = 0, seed: int = MASTER_SEED) -> List[Tuple[int, int]]:
+    """A ring on n vertices plus `chords` distinct random chords."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    edges = {(min(q, (q + 1) % n), max(q, (q + 1) % n)) for q in range(n)}
+    while len(edges) < n + chords:
+        a, b = (int(v) for v in rng.choice(n, size=2, replace=False))
+        edges.add((min(a, b), max(a, b)))
+    return sorted(edges)
+
+
+def qaoa_circuit(n: int, edges: Sequence[Tuple[int, int]], layers: int) -> Circuit:
+    """QAOA ansatz for MaxCut from |0...0>: H on every wire, then per layer l
+    the cost unitary prod_edges exp(-i theta_{2l} Z_a Z_b / 2) as
+    CNOT(a, b) RZ(theta_{2l}) on b CNOT(a, b) (one parameter shared by all
+    edges), and the mixer RX(theta_{2l+1}) on every wire (shared)."""
+    gates = [("H", (q,), -1, 0.0) for q in range(n)]
+    for l in range(layers):
+        for a, b in edges:
+            gates += [("CNOT", (a, b), -1, 0.0), ("RZ", (b,), 2 * l, 0.0), ("CNOT", (a, b), -1, 0.0)]
+        for q in range(n):
+            gates.append(("RX", (q,), 2 * l + 1, 0.0))
+    return _circuit(n, gates, 2 * layers, 0)
+
+
+def maxcut_hamiltonian(n: int, edges: Sequence[Tuple[int, int]], weights=None) -> PauliSum:
+    """sum over edges of w_ab Z_a Z_b (diagonal: one flip group); its minimum
+    is -(total weight) + 2 x (weight of the maximum cut)."""
+    w = np.ones(len(edges)) if weights is None else np.asarray(weights, dtype=np.float64)
+    xs, zs = [], []
+    for a, b in edges:
+        x, z = pauli_masks(n, [(a, "Z"), (b, "Z")])
+        xs.append(x)
+        zs.append(z)
+    return PauliSum(n, np.array(xs, dtype=np.uint64), np.array(zs, dtype=np.uint64), w.copy())
+
+
 def uniform_thetas(n_params: int, batch: int = 1, seed: int = MASTER_SEED) -> np.ndarray:
     """Parameters U(-pi, pi), shape [batch, n_params]."""
     rng = np.random.Generator(np.random.PCG64(seed))

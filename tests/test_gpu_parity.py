@@ -41,7 +41,7 @@ def ctx(vqe):
 
 @pytest.fixture(autouse=True)
 def _default_tile(ctx):
-    ctx.set_tile(12, 11, 4)
+    ctx.set_tile(12, 11, 3)  # the library's default tiles
     yield
 
 

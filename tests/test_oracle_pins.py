@@ -18,6 +18,7 @@ import scipy.linalg
 import oracle
 import synth
 from oracle import fermion
+from .qaoa_closed_form import qaoa1_zz_closed_form
 
 I2 = np.eye(2, dtype=complex)
 X = np.array([[0, 1], [1, 0]], dtype=complex)
@@ -492,3 +493,32 @@ def test_thread_count_does_not_change_results():
         oracle.set_threads(1)
     assert abs(e1 - e4) < 1e-12
     np.testing.assert_allclose(g1, g4, atol=1e-12)
+
+
+@pytest.mark.parametrize("n,prob,seed", [(6, 0.6, 1), (8, 0.4, 2), (9, 0.5, 3)])
+def test_qaoa_one_layer_matches_closed_form(n, prob, seed):
+    """The QAOA MaxCut ansatz (H, CNOT-RZ-CNOT per edge with one shared angle,
+    RX mixer with one shared angle) at one layer: every edge's <Z_u Z_v> and
+    the MaxCut energy equal the published closed form; the energy's gradient
+    equals central differences of the closed form (shared parameters summed)."""
+    edges = synth.random_graph(n, prob, seed=seed)
+    assert len(edges) >= 3
+    circ = synth.qaoa_circuit(n, edges, 1)
+    rng = np.random.default_rng(seed)
+    for _ in range(3):
+        t = rng.uniform(-math.pi, math.pi, size=2)
+        for (u, v) in edges:
+            ham = synth.maxcut_hamiltonian(n, [(u, v)])
+            got = oracle.energy(circ, ham, t)
+            assert abs(got - qaoa1_zz_closed_form(edges, n, u, v, t[0], t[1])) < 1e-12
+        ham = synth.maxcut_hamiltonian(n, edges)
+
+        def closed(tc, tm):
+            return sum(qaoa1_zz_closed_form(edges, n, a, b, tc, tm) for a, b in edges)
+
+        e, g = oracle.energy_grad(circ, ham, t)
+        assert abs(e - closed(*t)) < 1e-12
+        h = 1e-5
+        fd = [(closed(t[0] + h, t[1]) - closed(t[0] - h, t[1])) / (2 * h),
+              (closed(t[0], t[1] + h) - closed(t[0], t[1] - h)) / (2 * h)]
+        np.testing.assert_allclose(g, fd, atol=1e-8)

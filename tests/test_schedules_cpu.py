@@ -194,14 +194,22 @@ def test_register_stage_schedules(ctx, kind, n, k, c):
     np.testing.assert_allclose(_grad_from_parts(spec, gpart), g_or, atol=1e-11)
 
 
+def _fused_spec(kind, n, k):
+    if kind == "hea":
+        return synth.hea_circuit(n, 2)
+    if kind == "qaoa":
+        return synth.qaoa_circuit(n, synth.ring_graph(n, n // 2, seed=n), 2)
+    return synth.random_rotation_cnot_circuit(n, 90, seed=n + k)
+
+
 @pytest.mark.parametrize("kind,n,k,c", [("hea", 12, 8, 3), ("hea", 13, 12, 4), ("hea", 14, 11, 4),
                                          ("rot", 10, 8, 2), ("rot", 12, 9, 4), ("rot", 13, 12, 4),
-                                         ("rot", 14, 10, 4)])
+                                         ("rot", 14, 10, 4), ("qaoa", 12, 9, 3), ("qaoa", 14, 12, 3)])
 def test_fused_stage_schedules(ctx, kind, n, k, c):
     """Fused forward stages (one 2x2 per qubit, CNOT / X folded into the
     store map) executed on the CPU reproduce the oracle's state."""
     ctx.set_tile(k, min(k, 12), c)
-    spec = synth.hea_circuit(n, 2) if kind == "hea" else synth.random_rotation_cnot_circuit(n, 90, seed=n + k)
+    spec = _fused_spec(kind, n, k)
     th = synth.uniform_thetas(spec.n_params, 1, seed=n)[0]
     C = vqe.Circuit.from_spec(ctx, spec)
     mats = emu.gate_matrices(spec, th)
@@ -216,12 +224,13 @@ def test_fused_stage_schedules(ctx, kind, n, k, c):
 
 
 @pytest.mark.parametrize("kind,n,k,c", [("hea", 12, 8, 3), ("hea", 13, 11, 4), ("rot", 10, 8, 2),
-                                         ("rot", 12, 9, 4), ("rot", 13, 11, 4)])
+                                         ("rot", 12, 9, 4), ("rot", 13, 11, 4), ("qaoa", 12, 9, 3),
+                                         ("qaoa", 13, 11, 3)])
 def test_fused_adjoint_schedules(ctx, kind, n, k, c):
     """Fused adjoint stages on the CPU: the reverse sweep returns to the
     reference state and its gradient equals the oracle's."""
     ctx.set_tile(k, k, c)
-    spec = synth.hea_circuit(n, 2) if kind == "hea" else synth.random_rotation_cnot_circuit(n, 90, seed=n + k)
+    spec = _fused_spec(kind, n, k)
     ham = synth.random_pauli_sum(n, 30, seed=n)
     th = synth.uniform_thetas(spec.n_params, 1, seed=n)[0]
     C = vqe.Circuit.from_spec(ctx, spec)
