@@ -42,11 +42,39 @@ __device__ __forceinline__ uint32_t insert_zeros(uint32_t j, uint64_t pack, int 
     return j;
 }
 
+// Sums over the 64 lanes, the same in every lane, in a fixed order: by
+// butterfly shuffles, or (wave_sum_dpp, shorter latency on a single wave) by
+// DPP lane permutations forming quad, half-row and row sums (no LDS traffic)
+// and the four row sums added through readlane in row order.  Every lane of
+// the wave must be active.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double read_lane(double v, int lane)
+{
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                            __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
+
 __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     return v;
+}
+
+__device__ __forceinline__ double wave_sum_dpp(double v)
+{
+    v += dpp_move<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_move<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_move<0x141>(v);  // row_half_mirror
+    v += dpp_move<0x140>(v);  // row_mirror
+    return ((read_lane(v, 0) + read_lane(v, 16)) + read_lane(v, 32)) + read_lane(v, 48);
 }
 
 // workgroup sum in fixed order; valid in every thread after the call
@@ -861,7 +889,7 @@ __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
             }
         }
         if (!OVERLAP) {
-            const double sE = wave_sum(epart[tid]);  // one wave: nothing to overlap with
+            const double sE = wave_sum_dpp(epart[tid]);  // one wave: nothing to overlap with
             if (tid == 0) energies[it] = sE;
         }
         __syncthreads();
