@@ -1521,6 +1521,115 @@ __device__ __forceinline__ double signed_by_parity(double w, uint32_t zb)
     return __hiloint2double(__double2hiint(w) ^ (int)flip, __double2loint(w));
 }
 
+// Expectation of a flip group with a single term (most groups of a random
+// Pauli sum): MODE 0 diagonal (sum of |psi_b|^2 sigma(b)), 1 a real phase
+// (Re conj(psi[b ^ f]) psi[b]), 2 an imaginary one (-Im of the same), each
+// with the term's sign sigma(b) = (-1)^{z . b}; the caller scales by the
+// weight (and by 2 for the pair form).  No per-pair weight sums to clear.
+template <int RP, int MODE>
+__device__ __forceinline__ double single_term_sum(const double2 *tp, int npos, uint32_t pv, uint32_t f, uint32_t z)
+{
+    double s0 = 0.0, s1 = 0.0;
+    for (int j0 = 0; j0 < npos; j0 += RP * kThreads) {
+#pragma unroll
+        for (int r = 0; r < RP; ++r) {
+            const int j = j0 + r * kThreads + (int)threadIdx.x;
+            const bool ok = j < npos;
+            const uint32_t jj = ok ? (uint32_t)j : 0u;
+            const uint32_t b = MODE == 0 ? jj : (((jj >> pv) << (pv + 1)) | (jj & ((1u << pv) - 1u)));
+            const double2 x0 = tp[b];
+            double v;
+            if (MODE == 0) {
+                v = fma(x0.x, x0.x, x0.y * x0.y);
+            } else {
+                const double2 x1 = tp[b ^ f];
+                v = MODE == 1 ? fma(x1.x, x0.x, x1.y * x0.y) : fma(x1.y, x0.x, -x1.x * x0.y);
+            }
+            v = ok ? v : 0.0;
+            if (r & 1)
+                s1 += signed_by_parity(v, z & b);
+            else
+                s0 += signed_by_parity(v, z & b);
+        }
+    }
+    return s0 + s1;
+}
+
+// Expectation of a flip group with many terms on a 12-bit tile, through a
+// Walsh-Hadamard transform of each thread's own positions.  The thread's
+// pair elements are b_r = b_0 ^ e(r), r < R (e(r) = the bits of r placed at
+// tile bits 8.. with the pivot bit skipped, b_0 from the thread id), so a
+// term's sign splits as sigma(b_r) = (-1)^{z . b_0} (-1)^{zr . r} with zr the
+// bits of z at those places.  With v_r the pair products,
+//   sum_r sigma(b_r) v_r = (-1)^{z . b_0} V[zr],  V = WHT(v),
+// so after one transform (R log R additions per part) every term costs a
+// lookup, a sign and an FMA instead of R sign evaluations.
+template <int R, bool DIAG>
+__device__ __forceinline__ double walsh_group(const double2 *tp, uint32_t pv, uint32_t f, const uint32_t *zl,
+                                              const double *wl, int ib, int im, int ie)
+{
+    constexpr int LR = R == 16 ? 4 : (R == 8 ? 3 : (R == 4 ? 2 : (R == 2 ? 1 : 0)));
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lowp = (1u << pv) - 1u;
+    auto ins = [&](uint32_t j) { return DIAG ? j : (((j >> pv) << (pv + 1)) | (j & lowp)); };
+    double vr[R], vi[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t b = ins(tid + 256u * (uint32_t)r);
+        const double2 x0 = tp[b];
+        if (DIAG) {
+            vr[r] = fma(x0.x, x0.x, x0.y * x0.y);
+            vi[r] = 0.0;
+        } else {
+            const double2 x1 = tp[b ^ f];
+            vr[r] = fma(x1.x, x0.x, x1.y * x0.y);
+            vi[r] = fma(x1.y, x0.x, -x1.x * x0.y);
+        }
+    }
+#pragma unroll
+    for (int st = 0; st < LR; ++st)
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (r & (1 << st)) continue;
+            const double a = vr[r], b = vr[r | (1 << st)];
+            vr[r] = a + b;
+            vr[r | (1 << st)] = a - b;
+            if (!DIAG) {
+                const double c = vi[r], d = vi[r | (1 << st)];
+                vi[r] = c + d;
+                vi[r | (1 << st)] = c - d;
+            }
+        }
+    const uint32_t b0 = ins(tid);
+    double sum = 0.0;
+    for (int i = ib; i < ie; ++i) {
+        const uint32_t z = __builtin_amdgcn_readfirstlane(zl[i]);
+        uint32_t zr = 0;  // bit q of zr = bit of z where bit q of r lands
+#pragma unroll
+        for (int q = 0; q < LR; ++q) {
+            const uint32_t pos = DIAG ? 8u + q : (8u + q >= pv ? 9u + q : 8u + q);
+            zr |= ((z >> pos) & 1u) << q;
+        }
+        // uniform index: a scalar branch picks the register (no per-lane selects)
+        const bool re = i < im;
+        double v;
+        switch (zr) {
+#define VQE_PICK(m)                                  \
+    case m:                                          \
+        if constexpr (m < R) v = re ? vr[m] : vi[m]; \
+        break;
+            VQE_PICK(0) VQE_PICK(1) VQE_PICK(2) VQE_PICK(3) VQE_PICK(4) VQE_PICK(5) VQE_PICK(6) VQE_PICK(7)
+            VQE_PICK(8) VQE_PICK(9) VQE_PICK(10) VQE_PICK(11) VQE_PICK(12) VQE_PICK(13) VQE_PICK(14)
+#undef VQE_PICK
+        default:
+            if constexpr (R > 15) v = re ? vr[15] : vi[15];
+            break;
+        }
+        sum = fma(wl[i], signed_by_parity(v, z & b0), sum);
+    }
+    return DIAG ? sum : 2.0 * sum;
+}
+
 // RP pairs per thread at a time share each term read
 template <bool HPSI, int RP>
 __global__ __launch_bounds__(kThreads) void k_pauli_sweep(
@@ -1578,6 +1687,25 @@ __global__ __launch_bounds__(kThreads) void k_pauli_sweep(
             const bool diag = gd.floc == 0;
             const int npos = diag ? T : (T >> 1);
             const uint32_t pv = gd.pivot;
+            if (!HPSI && staged && k == 12 && te - tb >= 4) {  // many terms: one transform per thread
+                acc += diag ? walsh_group<16, true>(tp, pv, gd.floc, zl, wl, tb - tstart, tm - tstart, te - tstart)
+                            : walsh_group<8, false>(tp, pv, gd.floc, zl, wl, tb - tstart, tm - tstart, te - tstart);
+                continue;
+            }
+            if (!HPSI && staged && te - tb == 1) {  // a single term: no weight sums per pair
+                const int i = tb - tstart;
+                const uint32_t z = __builtin_amdgcn_readfirstlane(zl[i]);
+                const double w = wl[i];
+                double sum;
+                if (diag)
+                    sum = single_term_sum<RP, 0>(tp, npos, pv, gd.floc, z);
+                else if (tm > tb)
+                    sum = 2.0 * single_term_sum<RP, 1>(tp, npos, pv, gd.floc, z);
+                else
+                    sum = 2.0 * single_term_sum<RP, 2>(tp, npos, pv, gd.floc, z);
+                acc = fma(w, sum, acc);
+                continue;
+            }
             for (int j0 = 0; j0 < npos; j0 += RP * kThreads) {
                 uint32_t b[RP];
                 double A[RP], B[RP];
