@@ -71,7 +71,7 @@ def test_prepare_reference(vqe, ctx, n, B):
     assert np.array_equal(host, want)
 
 
-GEOMS = [(12, 11, 4), (6, 6, 2), (8, 7, 3)]
+GEOMS = [(12, 11, 3), (12, 11, 4), (6, 6, 2), (8, 7, 3)]
 
 
 @pytest.mark.parametrize("geom", GEOMS)
@@ -92,7 +92,7 @@ def test_apply_ansatz_random_circuits(vqe, ctx, geom, n, seed):
 
 
 @pytest.mark.parametrize("geom", GEOMS)
-@pytest.mark.parametrize("n,T,seed", [(1, 3, 0), (3, 10, 1), (7, 40, 2), (10, 80, 3), (14, 200, 4)])
+@pytest.mark.parametrize("n,T,seed", [(1, 3, 0), (3, 10, 1), (7, 40, 2), (10, 80, 3), (14, 200, 4), (13, 600, 5)])
 def test_expect_and_h_psi(vqe, ctx, geom, n, T, seed):
     _say("expect", geom, n, T, seed)
     ctx.set_tile(*geom)
