@@ -317,20 +317,25 @@ int vqe_run(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams, i
  *   then per pass {geom, int32 op_begin, op_count, n_param_ops,
  *   stage_begin, stage_count, fstage_begin, fstage_count, 0}, then n_ops
  *   op records, n_stages stage records and n_stage_ops stage-op records,
- *   then the fused stages: int32 {n_fstages, fstage_bytes (96), n_fconds,
- *   fcond_bytes (24), n_slots, n_slot_gates, 0, 0}, n_fstages records
- *   {uint8 rpos[4], cpos[12], uint16 lr[16], lc[12], c0, perm, int32 na,
- *   cond_begin, cond_count, slot, 0} (apply the fused 2x2 of slot + j to
- *   register bit j < na, then store register i of sub-cube u at tile index
- *   (xor of lc[j] over the bits j of u) ^ lr[i] ^ c0 ^ (xmask of every
- *   active conditional record) when perm = 1), n_fconds records {uint64
- *   cmo, cvo, uint32 xmask, 0} (active when (tile base & cmo) == cvo),
- *   int32 slot offsets [n_slots + 1], the gate of each slot entry and its
+ *   then the fused stages: int32 {n_fstages, fstage_bytes (104), n_fconds,
+ *   fcond_bytes (24), n_slots, n_slot_gates, n_phases, phase_bytes (16)},
+ *   n_fstages records {uint8 rpos[4], cpos[12], uint16 lr[16], lc[12], c0,
+ *   perm, int32 na, cond_begin, cond_count, slot, nb, phase_begin,
+ *   phase_count} (apply the fused 2x2 of slot + j to register bit j < na,
+ *   then the stage's parity phases, then store register i of sub-cube u at
+ *   tile index (xor of lc[j] over the bits j of u) ^ lr[i] ^ c0 ^ (xmask of
+ *   every active conditional record) when perm = 1), n_fconds records
+ *   {uint64 cmo, cvo, uint32 xmask, 0} (active when (tile base & cmo) ==
+ *   cvo), int32 slot offsets [n_slots + 1], the gate of each slot entry and its
  *   int32 info ((parametric gate index + 1) << 4 | class << 2 | generator,
  *   class and generator as in the op record).  Forward
  *   stages multiply a slot's matrices in list order (an empty slot is the
  *   identity); adjoint stages (nb = 3) undo them one by one, and there the
- *   store map is the inverse network of the next gates in reversed order.  geom = int32 {n, k, c,
+ *   store map is the inverse network of the next gates in reversed order.
+ *   Then n_phases records {uint32 mask, cbit, int32 gate, info}: an RZ met
+ *   after the network had touched its qubit, applied in the stage's index
+ *   frame v as the gate's diagonal entry u00 or u11 chosen by
+ *   parity(mask & v) ^ cbit.  geom = int32 {n, k, c,
  *   n - k}, uint8 tpos[16]
  *   (index bit of tile bit i), uint8 opos[40] (index bit of tile-number bit
  *   i).  op = uint32 m, uint32 fixed_bits, uint64 cmask_out, uint64

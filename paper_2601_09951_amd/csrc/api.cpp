@@ -262,7 +262,8 @@ int run_forward_passes(Context *ctx, Circ *C, CircPlan *fp, int64_t B, double2 *
         if (fuse && pp.fstage_count > 0)
             rc = hip_check(ctx, launch_forward_fused(pp, gd, reinterpret_cast<const FusedStage *>(fp->fstages.p),
                                                      reinterpret_cast<const FusedCond *>(fp->fconds.p), fused,
-                                                     fp->n_fslots(), psi, B, ctx->wg_max, s),
+                                                     fp->n_fslots(), reinterpret_cast<const FusedPhase *>(fp->fphases.p),
+                                                     mats, G, psi, B, ctx->wg_max, s),
                            "forward pass (fused)");
         else if (pp.stage_count > 0 && !ctx->no_stages)
             rc = hip_check(ctx, launch_forward_staged(pp, pp.stage_bits, gd, reinterpret_cast<const StageDesc *>(fp->stages.p),
@@ -380,8 +381,9 @@ int energy_grad_into(Context *ctx, Circ *C, int n_hams, Ham *const *H, int64_t B
                                                      reinterpret_cast<const int32_t *>(rp->fslot_off.p),
                                                      reinterpret_cast<const int32_t *>(rp->fslot_info.p),
                                                      rp->host_fstages[p.fstage_begin].slot, rp->n_fslots(),
-                                                     n_entries, p.fq_count, wadj, coef, psi, lam, B, L.W_rev, pg,
-                                                     C->n_pgates, s),
+                                                     n_entries, p.fq_count, wadj, coef,
+                                                     reinterpret_cast<const FusedPhase *>(rp->fphases.p), mats, G,
+                                                     psi, lam, B, L.W_rev, pg, C->n_pgates, s),
                            "reverse pass (fused)");
         else if (p.stage_count > 0 && !ctx->no_stages)
             rc = hip_check(ctx, launch_reverse_staged(p, p.stage_bits, gd, reinterpret_cast<const StageDesc *>(rp->stages.p),
@@ -1236,7 +1238,8 @@ int vqe_circ_plan_export(vqe_ctx_t ctx, vqe_circ_t circ, int reverse, void *buf,
     const size_t need = 32 + p->passes.size() * pass_bytes + p->host_ops.size() * sizeof(OpDesc) +
                         p->host_stages.size() * sizeof(StageDesc) + p->host_sops.size() * sizeof(StageOp) + 32 +
                         p->host_fstages.size() * sizeof(FusedStage) + p->host_fconds.size() * sizeof(FusedCond) +
-                        p->host_fslot_off.size() * 4 + p->host_fslot_gate.size() * 8;
+                        p->host_fslot_off.size() * 4 + p->host_fslot_gate.size() * 8 +
+                        p->host_fphases.size() * sizeof(FusedPhase);
     *needed = need;
     if (!buf || buf_bytes < need) return VQE_OK;
     unsigned char *o = (unsigned char *)buf;
@@ -1259,7 +1262,8 @@ int vqe_circ_plan_export(vqe_ctx_t ctx, vqe_circ_t circ, int reverse, void *buf,
     std::memcpy(o, p->host_sops.data(), p->host_sops.size() * sizeof(StageOp));
     o += p->host_sops.size() * sizeof(StageOp);
     int32_t fh[8] = {(int32_t)p->host_fstages.size(), (int32_t)sizeof(FusedStage), (int32_t)p->host_fconds.size(),
-                     (int32_t)sizeof(FusedCond), p->n_fslots(), (int32_t)p->host_fslot_gate.size(), 0, 0};
+                     (int32_t)sizeof(FusedCond), p->n_fslots(), (int32_t)p->host_fslot_gate.size(),
+                     (int32_t)p->host_fphases.size(), (int32_t)sizeof(FusedPhase)};
     std::memcpy(o, fh, 32);
     o += 32;
     std::memcpy(o, p->host_fstages.data(), p->host_fstages.size() * sizeof(FusedStage));
@@ -1271,6 +1275,8 @@ int vqe_circ_plan_export(vqe_ctx_t ctx, vqe_circ_t circ, int reverse, void *buf,
     std::memcpy(o, p->host_fslot_gate.data(), p->host_fslot_gate.size() * 4);
     o += p->host_fslot_gate.size() * 4;
     std::memcpy(o, p->host_fslot_info.data(), p->host_fslot_info.size() * 4);
+    o += p->host_fslot_info.size() * 4;
+    std::memcpy(o, p->host_fphases.data(), p->host_fphases.size() * sizeof(FusedPhase));
     return VQE_OK;
 }
 

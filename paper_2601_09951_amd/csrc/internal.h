@@ -116,8 +116,23 @@ struct FusedStage {
     int32_t cond_begin, cond_count;  // X conditioned on index bits outside the tile
     int32_t slot;        // gate list of register bit j: slot + j
     int32_t nb;          // register bits: 4 (forward stages) or 3 (adjoint stages)
+    int32_t phase_begin, phase_count;  // parity phases applied after the 2x2s, before the store
 };
-static_assert(sizeof(FusedStage) == 96, "FusedStage layout");
+static_assert(sizeof(FusedStage) == 104, "FusedStage layout");
+
+// An RZ met after the network had touched its qubit t: with the network so
+// far as w = L v ^ c, RZ on w_t is, in the stage's own index frame v, the
+// phase u00 or u11 of the gate chosen by parity(mask & v) ^ cbit (mask =
+// row t of L, cbit = c_t).  It is diagonal, so it commutes with the group's
+// other phases and with the one-qubit gates on qubits the network has not
+// touched; the last stage of the group applies it after its 2x2s.
+struct FusedPhase {
+    uint32_t mask;       // tile bits whose parity selects the phase
+    uint32_t cbit;
+    int32_t gate;        // circuit gate (its matrix is diagonal)
+    int32_t info;        // (parametric gate index + 1) << 4 | class << 2 | generator
+};
+static_assert(sizeof(FusedPhase) == 16, "FusedPhase layout");
 
 struct FusedCond {
     uint64_t cmo, cvo;   // active when (tile base & cmo) == cvo
@@ -216,6 +231,7 @@ struct PassPlan {
     int stage_bits = 0;                     // register bits of this pass's stages
     int fstage_begin = 0, fstage_count = 0; // fused stages (0: not fusable)
     int fq_count = 0;                       // adjoint fused stages: slots holding parametric gates
+    int fphase_begin = 0, fphase_count = 0; // parity phases of the fused stages
 };
 
 struct CircPlan {
@@ -232,9 +248,10 @@ struct CircPlan {
     int max_param_ops = 0;
     // fused stages: descriptors, conditional X, and per fused matrix (slot)
     // the CSR list of gates multiplied into it, in application order
-    DevMem fstages, fconds, fslot_off, fslot_gate, fslot_info;
+    DevMem fstages, fconds, fslot_off, fslot_gate, fslot_info, fphases;
     std::vector<FusedStage> host_fstages;
     std::vector<FusedCond> host_fconds;
+    std::vector<FusedPhase> host_fphases;
     std::vector<int32_t> host_fslot_off{0}, host_fslot_gate;
     std::vector<int32_t> host_fslot_info;  // per slot entry: (pgate + 1) << 4 | class << 2 | generator
     int n_fslots() const { return (int)host_fslot_off.size() - 1; }
@@ -343,14 +360,17 @@ hipError_t launch_fuse_mats(const int32_t *slot_off, const int32_t *slot_gate, i
 hipError_t launch_adjoint_coefs(const int32_t *slot_off, const int32_t *slot_gate, const int32_t *slot_info,
                                 int n_slots, int n_entries, const double2 *mats, int n_gates, int64_t batch,
                                 double2 *wadj, double *coef, hipStream_t s);
-size_t reverse_fused_lds(int k, int c, int nstages, int n_qslots);
+size_t reverse_fused_lds(int k, int c, int nstages, int n_qslots, int n_phases);
+size_t forward_fused_lds(int k, int c, int nstages, int n_phases);
 hipError_t launch_reverse_fused(const PassPlan &pp, const TileGeom *geom_dev, const FusedStage *fstages,
                                 const FusedCond *fconds, const int32_t *slot_off, const int32_t *slot_info,
                                 int slot0, int n_slots, int n_entries, int n_qslots, const double2 *wadj,
-                                const double *coef, double2 *psi, double2 *lam, int64_t batch, int wg_per_inst,
-                                double *partials, int n_pgates, hipStream_t s);
+                                const double *coef, const FusedPhase *fphases, const double2 *mats, int n_gates,
+                                double2 *psi, double2 *lam, int64_t batch, int wg_per_inst, double *partials,
+                                int n_pgates, hipStream_t s);
 hipError_t launch_forward_fused(const PassPlan &pp, const TileGeom *geom_dev, const FusedStage *fstages,
-                                const FusedCond *fconds, const double2 *fused, int n_slots, double2 *psi,
+                                const FusedCond *fconds, const double2 *fused, int n_slots,
+                                const FusedPhase *fphases, const double2 *mats, int n_gates, double2 *psi,
                                 int64_t batch, int wg_max, hipStream_t s);
 hipError_t launch_forward_staged(const PassPlan &pp, int stage_bits, const TileGeom *geom_dev,
                                  const StageDesc *stages, const StageOp *sops, const double2 *mats,

@@ -1139,11 +1139,37 @@ __device__ __forceinline__ void fused_bit(double2 (&x)[16], const Mat2 &v)
     }
 }
 
+// A parity phase of a stage as staged in LDS: the two diagonal entries of
+// its gate for this instance (forward U, adjoint U^dagger) and, in adjoint
+// passes, the gradient slot of a parametric one (-1 otherwise).
+struct PhaseL {
+    uint32_t mask, cbit;
+    int32_t pslot, pg;
+    double2 d0, d1;
+};
+
+// the stage's parity phases on a sub-cube of N amplitudes at tile indices
+// bl | roff[i]: the parity splits into the thread's part (bl) and a
+// wave-uniform part (roff[i])
+template <int N>
+__device__ __forceinline__ void apply_phases(double2 (&x)[N], const PhaseL *phl, int count, uint32_t bl,
+                                             const uint32_t (&roff)[N])
+{
+    for (int p = 0; p < count; ++p) {
+        const PhaseL &ph = phl[p];
+        const uint32_t mask = __builtin_amdgcn_readfirstlane(ph.mask);
+        const uint32_t sb = ((uint32_t)__popc(mask & bl) ^ __builtin_amdgcn_readfirstlane(ph.cbit)) & 1u;
+        const double2 e0 = sb ? ph.d1 : ph.d0, e1 = sb ? ph.d0 : ph.d1;
+#pragma unroll
+        for (int i = 0; i < N; ++i) x[i] = cmul((__popc(mask & roff[i]) & 1) ? e1 : e0, x[i]);
+    }
+}
+
 // one fused stage for this thread's sub-cube u (na active register bits;
 // PERM: the CNOT / X network moves the amplitudes on the way back to LDS)
 template <int NA, bool PERM>
 __device__ __forceinline__ void fused_stage(double2 *tile, const FusedStage &fs, const Mat2 *fm, int nsub,
-                                            uint32_t ctile)
+                                            uint32_t ctile, const PhaseL *phl, int nph)
 {
     const bool have = (int)threadIdx.x < nsub;
     const int u = have ? (int)threadIdx.x : 0;
@@ -1169,6 +1195,7 @@ __device__ __forceinline__ void fused_stage(double2 *tile, const FusedStage &fs,
         if (NA > 1) fused_bit<1>(x, fm[1]);
         if (NA > 2) fused_bit<2>(x, fm[2]);
         if (NA > 3) fused_bit<3>(x, fm[3]);
+        apply_phases<16>(x, phl, nph, bl, roff);
     }
     if (PERM) {
         lds_barrier();  // every sub-cube is read before any amplitude moves
@@ -1186,7 +1213,9 @@ __global__ __launch_bounds__(kThreads) void k_forward_fused(const TileGeom *__re
                                                             int nout, const FusedStage *__restrict__ fstages,
                                                             int nstages, const FusedCond *__restrict__ fconds,
                                                             const double2 *__restrict__ fused, int n_slots,
-                                                            double2 *__restrict__ psi, int64_t tiles)
+                                                            const FusedPhase *__restrict__ fphases, int ph0,
+                                                            int nph, const double2 *__restrict__ mats,
+                                                            int n_gates, double2 *__restrict__ psi, int64_t tiles)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     double2 *tile = reinterpret_cast<double2 *>(smem);
@@ -1202,6 +1231,19 @@ __global__ __launch_bounds__(kThreads) void k_forward_fused(const TileGeom *__re
     const double2 *F = fused + ((size_t)blockIdx.y * n_slots + slot0) * 4;
     double2 *fmd = reinterpret_cast<double2 *>(fm);
     for (int i = tid; i < 16 * nstages; i += kThreads) fmd[i] = F[i];  // 4 double2 per matrix
+    PhaseL *phl = reinterpret_cast<PhaseL *>(fm + 4 * nstages);
+    const double2 *Mx = mats + (size_t)blockIdx.y * n_gates * 4;
+    for (int i = tid; i < nph; i += kThreads) {
+        const FusedPhase f = fphases[ph0 + i];
+        PhaseL q;
+        q.mask = f.mask;
+        q.cbit = f.cbit;
+        q.pslot = -1;
+        q.pg = -1;
+        q.d0 = Mx[f.gate * 4 + 0];
+        q.d1 = Mx[f.gate * 4 + 3];
+        phl[i] = q;
+    }
     __syncthreads();
     for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
         const uint64_t base = tile_base(gp, nout, t);
@@ -1217,17 +1259,19 @@ __global__ __launch_bounds__(kThreads) void k_forward_fused(const TileGeom *__re
                 if ((base & fc.cmo) == fc.cvo) ctile ^= fc.xmask;
             }
             const Mat2 *m4 = fm + 4 * s;
+            const PhaseL *sp = phl + (fs.phase_begin - ph0);
+            const int np = fs.phase_count;
             switch (na * 2 + perm) {
-            case 0: fused_stage<0, false>(tile, fs, m4, nsub, ctile); break;
-            case 1: fused_stage<0, true>(tile, fs, m4, nsub, ctile); break;
-            case 2: fused_stage<1, false>(tile, fs, m4, nsub, ctile); break;
-            case 3: fused_stage<1, true>(tile, fs, m4, nsub, ctile); break;
-            case 4: fused_stage<2, false>(tile, fs, m4, nsub, ctile); break;
-            case 5: fused_stage<2, true>(tile, fs, m4, nsub, ctile); break;
-            case 6: fused_stage<3, false>(tile, fs, m4, nsub, ctile); break;
-            case 7: fused_stage<3, true>(tile, fs, m4, nsub, ctile); break;
-            case 8: fused_stage<4, false>(tile, fs, m4, nsub, ctile); break;
-            default: fused_stage<4, true>(tile, fs, m4, nsub, ctile); break;
+            case 0: fused_stage<0, false>(tile, fs, m4, nsub, ctile, sp, np); break;
+            case 1: fused_stage<0, true>(tile, fs, m4, nsub, ctile, sp, np); break;
+            case 2: fused_stage<1, false>(tile, fs, m4, nsub, ctile, sp, np); break;
+            case 3: fused_stage<1, true>(tile, fs, m4, nsub, ctile, sp, np); break;
+            case 4: fused_stage<2, false>(tile, fs, m4, nsub, ctile, sp, np); break;
+            case 5: fused_stage<2, true>(tile, fs, m4, nsub, ctile, sp, np); break;
+            case 6: fused_stage<3, false>(tile, fs, m4, nsub, ctile, sp, np); break;
+            case 7: fused_stage<3, true>(tile, fs, m4, nsub, ctile, sp, np); break;
+            case 8: fused_stage<4, false>(tile, fs, m4, nsub, ctile, sp, np); break;
+            default: fused_stage<4, true>(tile, fs, m4, nsub, ctile, sp, np); break;
             }
             lds_barrier();
         }
@@ -1360,7 +1404,8 @@ __device__ __forceinline__ void rbit_step(double2 (&x)[8], double2 (&l)[8], cons
 
 template <int NA, bool PERM>
 __device__ __forceinline__ void rev_fused_stage(double2 *tp, double2 *tl, const FusedStage &fs, const Mat2 *wm,
-                                                const int32_t *qidx, int nsub, uint32_t ctile, double *red)
+                                                const int32_t *qidx, int nsub, uint32_t ctile, double *red,
+                                                const PhaseL *phl, int nph, double *phred)
 {
     const bool have = (int)threadIdx.x < nsub;
     const int u = have ? (int)threadIdx.x : 0;
@@ -1393,6 +1438,34 @@ __device__ __forceinline__ void rev_fused_stage(double2 *tp, double2 *tl, const 
     if (NA > 0) rbit_step<0>(x, l, wm[0], (int)__builtin_amdgcn_readfirstlane((uint32_t)qidx[0]), red);
     if (NA > 1) rbit_step<1>(x, l, wm[1], (int)__builtin_amdgcn_readfirstlane((uint32_t)qidx[1]), red);
     if (NA > 2) rbit_step<2>(x, l, wm[2], (int)__builtin_amdgcn_readfirstlane((uint32_t)qidx[2]), red);
+    if (nph > 0) {
+        // parity phases: every gradient term is (-1)^{parity} Im(conj(lam) psi)
+        // summed over the sub-cube (diagonal phases leave Im(conj(lam) psi)
+        // unchanged, so one set of products serves all), then U^dagger on both
+        double e[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) e[i] = fma(l[i].x, x[i].y, -l[i].y * x[i].x);
+        for (int p = 0; p < nph; ++p) {
+            const PhaseL &ph = phl[p];
+            const uint32_t mask = __builtin_amdgcn_readfirstlane(ph.mask);
+            const uint32_t sb = ((uint32_t)__popc(mask & bl) ^ __builtin_amdgcn_readfirstlane(ph.cbit)) & 1u;
+            const int ps = (int)__builtin_amdgcn_readfirstlane((uint32_t)ph.pslot);
+            if (ps >= 0) {
+                double g = 0.0;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) g += ((__popc(mask & roff[i]) & 1) ^ sb) ? -e[i] : e[i];
+                g = wave_total_last(g);
+                if ((threadIdx.x & 63) == 63) atomicAdd(phred + ps * 4 + (threadIdx.x >> 6), g);
+            }
+            const double2 e0 = sb ? ph.d1 : ph.d0, e1 = sb ? ph.d0 : ph.d1;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const double2 d = (__popc(mask & roff[i]) & 1) ? e1 : e0;
+                x[i] = cmul(d, x[i]);
+                l[i] = cmul(d, l[i]);
+            }
+        }
+    }
     if (PERM) {
         lds_barrier();  // every sub-cube is read before any amplitude moves
         if (have) {
@@ -1420,8 +1493,9 @@ __global__ __launch_bounds__(kThreads) void k_reverse_fused(
     const TileGeom *__restrict__ gp, int n, int k, int c, int nout, const FusedStage *__restrict__ fstages,
     int nstages, const FusedCond *__restrict__ fconds, const int32_t *__restrict__ slot_off,
     const int32_t *__restrict__ slot_info, int slot0, int n_slots, int n_entries, const double2 *__restrict__ wadj,
-    const double *__restrict__ coef, double2 *__restrict__ psi, double2 *__restrict__ lam, int64_t tiles,
-    double *__restrict__ partials, int n_pgates)
+    const double *__restrict__ coef, const FusedPhase *__restrict__ fphases, int ph0, int nph,
+    const double2 *__restrict__ mats, int n_gates, double2 *__restrict__ psi, double2 *__restrict__ lam,
+    int64_t tiles, double *__restrict__ partials, int n_pgates)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     double2 *tp = reinterpret_cast<double2 *>(smem);
@@ -1429,7 +1503,9 @@ __global__ __launch_bounds__(kThreads) void k_reverse_fused(
     uint64_t *hoff = reinterpret_cast<uint64_t *>(smem + (32u << k));
     const int ns = 3 * nstages;
     Mat2 *wm = reinterpret_cast<Mat2 *>(hoff + (1u << (k - c)));
-    int32_t *qidx = reinterpret_cast<int32_t *>(wm + ns);
+    PhaseL *phl = reinterpret_cast<PhaseL *>(wm + ns);
+    double *phred = reinterpret_cast<double *>(phl + nph);  // 4 per phase
+    int32_t *qidx = reinterpret_cast<int32_t *>(phred + 4 * (size_t)nph);
     double *red = reinterpret_cast<double *>(qidx + ((ns + 1) & ~1));
     const int tid = threadIdx.x;
     const uint64_t dim = 1ull << n;
@@ -1449,6 +1525,26 @@ __global__ __launch_bounds__(kThreads) void k_reverse_fused(
         nq += par;
     }
     for (int i = tid; i < 12 * nq; i += kThreads) red[i] = 0.0;
+    {
+        const double2 *Mx = mats + (size_t)blockIdx.y * n_gates * 4;
+        int pslot = 0;  // parametric phases numbered in order (every thread counts)
+        for (int i = 0; i < nph; ++i) {
+            const FusedPhase f = fphases[ph0 + i];
+            const bool par = f.info >= 16;
+            if (tid == 0) {
+                PhaseL q;
+                q.mask = f.mask;
+                q.cbit = f.cbit;
+                q.pslot = par ? pslot : -1;
+                q.pg = (f.info >> 4) - 1;
+                q.d0 = cconj(Mx[f.gate * 4 + 0]);
+                q.d1 = cconj(Mx[f.gate * 4 + 3]);
+                phl[i] = q;
+            }
+            pslot += par;
+        }
+        for (int i = tid; i < 4 * nph; i += kThreads) phred[i] = 0.0;
+    }
     __syncthreads();
     for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
         const uint64_t base = tile_base(gp, nout, t);
@@ -1465,15 +1561,17 @@ __global__ __launch_bounds__(kThreads) void k_reverse_fused(
             }
             const Mat2 *w3 = wm + 3 * s;
             const int32_t *q3 = qidx + 3 * s;
+            const PhaseL *sp = phl + (fs.phase_begin - ph0);
+            const int np = fs.phase_count;
             switch (na * 2 + perm) {
-            case 0: rev_fused_stage<0, false>(tp, tl, fs, w3, q3, nsub, ctile, red); break;
-            case 1: rev_fused_stage<0, true>(tp, tl, fs, w3, q3, nsub, ctile, red); break;
-            case 2: rev_fused_stage<1, false>(tp, tl, fs, w3, q3, nsub, ctile, red); break;
-            case 3: rev_fused_stage<1, true>(tp, tl, fs, w3, q3, nsub, ctile, red); break;
-            case 4: rev_fused_stage<2, false>(tp, tl, fs, w3, q3, nsub, ctile, red); break;
-            case 5: rev_fused_stage<2, true>(tp, tl, fs, w3, q3, nsub, ctile, red); break;
-            case 6: rev_fused_stage<3, false>(tp, tl, fs, w3, q3, nsub, ctile, red); break;
-            default: rev_fused_stage<3, true>(tp, tl, fs, w3, q3, nsub, ctile, red); break;
+            case 0: rev_fused_stage<0, false>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred); break;
+            case 1: rev_fused_stage<0, true>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred); break;
+            case 2: rev_fused_stage<1, false>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred); break;
+            case 3: rev_fused_stage<1, true>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred); break;
+            case 4: rev_fused_stage<2, false>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred); break;
+            case 5: rev_fused_stage<2, true>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred); break;
+            case 6: rev_fused_stage<3, false>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred); break;
+            default: rev_fused_stage<3, true>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred); break;
             }
             lds_barrier();
         }
@@ -1497,6 +1595,12 @@ __global__ __launch_bounds__(kThreads) void k_reverse_fused(
                 const double v = cf[e * 4 + 0] * Q0 + cf[e * 4 + 1] * Q1 + cf[e * 4 + 2] * Q2;
                 partials[((size_t)blockIdx.y * n_pgates + ((info >> 4) - 1)) * W + blockIdx.x] = v;
             }
+        }
+        for (int i = 0; i < nph; ++i) {
+            const PhaseL &q = phl[i];
+            if (q.pslot < 0) continue;
+            const double *r = phred + (size_t)q.pslot * 4;
+            partials[((size_t)blockIdx.y * n_pgates + q.pg) * W + blockIdx.x] = ((r[0] + r[1]) + r[2]) + r[3];
         }
     }
 }
@@ -2130,19 +2234,21 @@ hipError_t launch_fuse_mats(const int32_t *slot_off, const int32_t *slot_gate, i
 }
 
 hipError_t launch_forward_fused(const PassPlan &pp, const TileGeom *geom_dev, const FusedStage *fstages,
-                                const FusedCond *fconds, const double2 *fused, int n_slots, double2 *psi,
+                                const FusedCond *fconds, const double2 *fused, int n_slots,
+                                const FusedPhase *fphases, const double2 *mats, int n_gates, double2 *psi,
                                 int64_t batch, int wg_max, hipStream_t s)
 {
     const TileGeom &g = pp.geom;
     if (g.k < 8 || g.k > 12) return hipErrorInvalidValue;
     const int64_t tiles = 1ll << g.nout;
     const int W = (int)std::min<int64_t>(tiles, wg_max);
-    const size_t lds = fwd_lds(g) + (size_t)pp.fstage_count * 4 * sizeof(Mat2);
+    const size_t lds = forward_fused_lds(g.k, g.c, pp.fstage_count, pp.fphase_count);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     hipError_t e = ensure_lds(k_forward_fused, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_forward_fused, dim3(W, (unsigned)batch), dim3(kThreads), lds, s, geom_dev, g.n, g.k, g.c,
-                       g.nout, fstages + pp.fstage_begin, pp.fstage_count, fconds, fused, n_slots, psi, tiles);
+                       g.nout, fstages + pp.fstage_begin, pp.fstage_count, fconds, fused, n_slots, fphases,
+                       pp.fphase_begin, pp.fphase_count, mats, n_gates, psi, tiles);
     return hipGetLastError();
 }
 
@@ -2157,28 +2263,36 @@ hipError_t launch_adjoint_coefs(const int32_t *slot_off, const int32_t *slot_gat
     return hipGetLastError();
 }
 
-size_t reverse_fused_lds(int k, int c, int nstages, int n_qslots)
+size_t reverse_fused_lds(int k, int c, int nstages, int n_qslots, int n_phases)
 {
     const size_t ns = 3 * (size_t)nstages;
-    return (32u << k) + (8u << (k - c)) + ns * sizeof(Mat2) + 4 * ((ns + 1) & ~(size_t)1) + 96 * (size_t)n_qslots;
+    return (32u << k) + (8u << (k - c)) + ns * sizeof(Mat2) + (size_t)n_phases * (sizeof(PhaseL) + 32) +
+           4 * ((ns + 1) & ~(size_t)1) + 96 * (size_t)n_qslots;
+}
+
+size_t forward_fused_lds(int k, int c, int nstages, int n_phases)
+{
+    return (16u << k) + (8u << (k - c)) + (size_t)nstages * 4 * sizeof(Mat2) + (size_t)n_phases * sizeof(PhaseL);
 }
 
 hipError_t launch_reverse_fused(const PassPlan &pp, const TileGeom *geom_dev, const FusedStage *fstages,
                                 const FusedCond *fconds, const int32_t *slot_off, const int32_t *slot_info,
                                 int slot0, int n_slots, int n_entries, int n_qslots, const double2 *wadj,
-                                const double *coef, double2 *psi, double2 *lam, int64_t batch, int wg_per_inst,
-                                double *partials, int n_pgates, hipStream_t s)
+                                const double *coef, const FusedPhase *fphases, const double2 *mats, int n_gates,
+                                double2 *psi, double2 *lam, int64_t batch, int wg_per_inst, double *partials,
+                                int n_pgates, hipStream_t s)
 {
     const TileGeom &g = pp.geom;
     if (g.k < 8 || g.k > 11 || slot0 < 0 || slot0 + 3 * pp.fstage_count > n_slots) return hipErrorInvalidValue;
     const int64_t tiles = 1ll << g.nout;
-    const size_t lds = reverse_fused_lds(g.k, g.c, pp.fstage_count, n_qslots);
+    const size_t lds = reverse_fused_lds(g.k, g.c, pp.fstage_count, n_qslots, pp.fphase_count);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     hipError_t e = ensure_lds(k_reverse_fused, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_reverse_fused, dim3(wg_per_inst, (unsigned)batch), dim3(kThreads), lds, s, geom_dev, g.n,
                        g.k, g.c, g.nout, fstages + pp.fstage_begin, pp.fstage_count, fconds, slot_off, slot_info,
-                       slot0, n_slots, n_entries, wadj, coef, psi, lam, tiles, partials, n_pgates);
+                       slot0, n_slots, n_entries, wadj, coef, fphases, pp.fphase_begin, pp.fphase_count, mats,
+                       n_gates, psi, lam, tiles, partials, n_pgates);
     return hipGetLastError();
 }
 

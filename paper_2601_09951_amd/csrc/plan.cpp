@@ -185,6 +185,7 @@ static void free_plan(Context *ctx, CircPlan *p)
         dev_free(ctx, p->fslot_off);
         dev_free(ctx, p->fslot_gate);
         dev_free(ctx, p->fslot_info);
+        dev_free(ctx, p->fphases);
     }
 }
 
@@ -217,6 +218,7 @@ static bool build_fused(const Circ *C, const std::vector<int> &take, const std::
     std::vector<std::vector<int>> oneq(keff);  // gates per tile bit, in order
     std::vector<int> order;                    // bits with gates, in order of appearance
     std::vector<Perm> perm;
+    std::vector<FusedPhase> phases;            // RZ met after the network touched its qubit
     uint32_t touched = 0;
     const int st0 = (int)plan->host_fstages.size();
 
@@ -304,10 +306,45 @@ static bool build_fused(const Circ *C, const std::vector<int> &take, const std::
             }
             plan->host_fstages.push_back(fs);
         }
+        // the group's phases ride on its last stage
+        FusedStage &last = plan->host_fstages.back();
+        last.phase_begin = (int)plan->host_fphases.size();
+        last.phase_count = (int)phases.size();
+        for (const FusedPhase &f : phases) plan->host_fphases.push_back(f);
         for (int b : order) oneq[b].clear();
         order.clear();
         perm.clear();
+        phases.clear();
         touched = 0;
+    };
+
+    // an RZ on touched bit t as a parity phase (only while the network has no
+    // X conditioned on bits outside the tile); false: flush instead
+    auto as_phase = [&](int g, int t) {
+        if (C->gates[g].kind != VQE_GATE_RZ) return false;
+        uint32_t col[16];
+        for (int b = 0; b < 16; ++b) col[b] = b < keff ? 1u << b : 0u;
+        uint32_t c0 = 0;
+        auto cnot = [](uint32_t v, int c, int tt) { return ((v >> c) & 1u) ? v ^ (1u << tt) : v; };
+        for (const Perm &q : perm) {
+            if (q.kind == 2) return false;
+            if (q.kind == 0) {
+                for (int b = 0; b < keff; ++b) col[b] = cnot(col[b], q.c, q.t);
+                c0 = cnot(c0, q.c, q.t);
+            } else {
+                c0 ^= 1u << q.t;
+            }
+        }
+        FusedPhase f;
+        std::memset(&f, 0, sizeof(f));
+        for (int b = 0; b < keff; ++b)
+            if ((col[b] >> t) & 1u) f.mask |= 1u << b;
+        f.cbit = (c0 >> t) & 1u;
+        f.gate = g;
+        const GateHost &h = C->gates[g];
+        f.info = ((C->pgate_of_gate[g] + 1) << 4) | (h.cls << 2) | h.gen;
+        phases.push_back(f);
+        return true;
     };
 
     for (int g : take) {
@@ -333,7 +370,10 @@ static bool build_fused(const Circ *C, const std::vector<int> &take, const std::
             perm.push_back(q);
             continue;
         }
-        if ((touched >> t) & 1) flush();
+        if ((touched >> t) & 1) {
+            if (as_phase(g, t)) continue;
+            flush();
+        }
         if (oneq[t].empty()) order.push_back(t);
         oneq[t].push_back(g);
     }
@@ -537,6 +577,7 @@ CircPlan *get_circ_plan(Circ *C, bool reverse, int k, int c, int *rc)
         {
             const size_t f0 = plan->host_fstages.size(), c0 = plan->host_fconds.size();
             const size_t s0 = plan->host_fslot_off.size(), g0 = plan->host_fslot_gate.size();
+            const size_t ph0 = plan->host_fphases.size();
             bool ok = build_fused(C, take, tile, keff, reverse ? 3 : 4, plan.get(), pp);
             if (ok && reverse) {
                 // the adjoint kernel keeps both tiles, every slot's product and
@@ -549,16 +590,28 @@ CircPlan *get_circ_plan(Circ *C, bool reverse, int k, int c, int *rc)
                     np += here;
                     nq += here > 0;
                 }
+                int nph = 0, npp = 0;
+                for (size_t e = ph0; e < plan->host_fphases.size(); ++e) {
+                    ++nph;
+                    npp += plan->host_fphases[e].info >= 16;
+                }
+                np += npp;
                 const int nst = (int)(plan->host_fstages.size() - f0);
                 pp.fq_count = nq;
-                ok = np == nparam && reverse_fused_lds(keff, ceff, nst, nq) <= 160 * 1024;
+                ok = np == nparam && reverse_fused_lds(keff, ceff, nst, nq, nph) <= 160 * 1024;
+            } else if (ok) {
+                const size_t nph = plan->host_fphases.size() - ph0;
+                ok = forward_fused_lds(keff, ceff, (int)(plan->host_fstages.size() - f0), (int)nph) <= 160 * 1024;
             }
+            pp.fphase_begin = (int)ph0;
+            pp.fphase_count = ok ? (int)(plan->host_fphases.size() - ph0) : 0;
             if (!ok) {
                 plan->host_fstages.resize(f0);
                 plan->host_fconds.resize(c0);
                 plan->host_fslot_off.resize(s0);
                 plan->host_fslot_gate.resize(g0);
                 plan->host_fslot_info.resize(g0);
+                plan->host_fphases.resize(ph0);
                 pp.fstage_begin = (int)f0;
                 pp.fstage_count = 0;
                 pp.fq_count = 0;
@@ -600,6 +653,9 @@ CircPlan *get_circ_plan(Circ *C, bool reverse, int k, int c, int *rc)
         if (!r && !plan->host_fslot_info.empty())
             r = upload(C->ctx, plan->fslot_info, plan->host_fslot_info.data(),
                        plan->host_fslot_info.size() * sizeof(int32_t));
+        if (!r && !plan->host_fphases.empty())
+            r = upload(C->ctx, plan->fphases, plan->host_fphases.data(),
+                       plan->host_fphases.size() * sizeof(FusedPhase));
         if (r) {
             free_plan(C->ctx, plan.get());
             *rc = r;

@@ -432,8 +432,9 @@ _SOP = np.dtype([("cmo", "<u8"), ("cvo", "<u8"), ("cmt", "<u4"), ("cvt", "<u4"),
                  ("cls", "u1"), ("gen", "u1"), ("pad", "u1"), ("amask", "<u2"), ("pad2", "<u2", 3)])
 _FSTAGE = np.dtype([("rpos", "u1", 4), ("cpos", "u1", 12), ("lr", "<u2", 16), ("lc", "<u2", 12), ("c0", "<u2"),
                     ("perm", "<u2"), ("na", "<i4"), ("cond_begin", "<i4"), ("cond_count", "<i4"), ("slot", "<i4"),
-                    ("nb", "<i4")])
+                    ("nb", "<i4"), ("phase_begin", "<i4"), ("phase_count", "<i4")])
 _FCOND = np.dtype([("cmo", "<u8"), ("cvo", "<u8"), ("xmask", "<u4"), ("pad", "<u4")])
+_FPHASE = np.dtype([("mask", "<u4"), ("cbit", "<u4"), ("gate", "<i4"), ("info", "<i4")])
 _OP = np.dtype([("m", "<u4"), ("fixed_bits", "<u4"), ("cmask_out", "<u8"), ("cval_out", "<u8"),
                 ("gate", "<i4"), ("pgate", "<i4"), ("cls", "<i2"), ("gen", "<i2"), ("nfix", "i1"),
                 ("fixpos", "u1", 7), ("pad", "<u4")])
@@ -445,7 +446,7 @@ _TERM = np.dtype([("z", "<u8"), ("zloc", "<u4"), ("pad", "<u4"), ("w", "<f8")])
 def circuit_plan(ctx: Context, circ: Circuit, reverse: bool = False, stages: bool = False):
     """(passes, ops) structured arrays of the compiled pass schedule
     (plus (stages, stage_ops) when stages=True; with stages="fused":
-    (passes, ops, fused_stages, fused_conds, slot_offsets, slot_gates, slot_info))."""
+    (passes, ops, fused_stages, fused_conds, slot_offsets, slot_gates, slot_info, phases))."""
     need = ctypes.c_size_t()
     ctx.check(lib().vqe_circ_plan_export(ctx.handle, circ.handle, int(reverse), None, 0, ctypes.byref(need)))
     buf = np.zeros(need.value, dtype=np.uint8)
@@ -466,8 +467,8 @@ def circuit_plan(ctx: Context, circ: Circuit, reverse: bool = False, stages: boo
     off += nsop * _SOP.itemsize
     if stages == "fused":
         fh = buf[off:off + 32].view("<i4")
-        nfs, nfc, nsl, nsg = int(fh[0]), int(fh[2]), int(fh[4]), int(fh[5])
-        assert fh[1] == _FSTAGE.itemsize and fh[3] == _FCOND.itemsize
+        nfs, nfc, nsl, nsg, nph = int(fh[0]), int(fh[2]), int(fh[4]), int(fh[5]), int(fh[6])
+        assert fh[1] == _FSTAGE.itemsize and fh[3] == _FCOND.itemsize and fh[7] == _FPHASE.itemsize
         off += 32
         fst = buf[off:off + nfs * _FSTAGE.itemsize].view(_FSTAGE)
         off += nfs * _FSTAGE.itemsize
@@ -478,7 +479,9 @@ def circuit_plan(ctx: Context, circ: Circuit, reverse: bool = False, stages: boo
         sgate = buf[off:off + nsg * 4].view("<i4")
         off += nsg * 4
         sinfo = buf[off:off + nsg * 4].view("<i4")
-        return passes, ops, fst, fco, soff, sgate, sinfo
+        off += nsg * 4
+        fph = buf[off:off + nph * _FPHASE.itemsize].view(_FPHASE)
+        return passes, ops, fst, fco, soff, sgate, sinfo, fph
     if stages:
         return passes, ops, st, sops
     return passes, ops

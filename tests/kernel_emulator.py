@@ -339,10 +339,20 @@ def reverse_staged(passes, stages, sops, psi, lam, mats, n_pgates):
     return psi, lam, gpart
 
 
-def forward_fused(passes, ops, fstages, fconds, soff, sgate, psi, mats):
+def _parity(v):
+    v = np.asarray(v, dtype=np.int64)
+    out = np.zeros_like(v)
+    while np.any(v):
+        out ^= v & 1
+        v = v >> 1
+    return out
+
+
+def forward_fused(passes, ops, fstages, fconds, soff, sgate, psi, mats, phases=()):
     """Forward passes with fused stages where the plan has them (one fused
-    2x2 per active register bit, then the stage's affine store map), the
-    op-by-op path elsewhere."""
+    2x2 per active register bit, then the stage's parity phases: the gate's
+    diagonal entry chosen by parity(mask & v) ^ cbit of the tile index v,
+    then the stage's affine store map), the op-by-op path elsewhere."""
     psi = psi.copy()
     for pi in range(len(passes)):
         ps = passes[pi:pi + 1]
@@ -376,6 +386,11 @@ def forward_fused(passes, ops, fstages, fconds, soff, sgate, psi, mats):
                 a, b = X[:, :, lo].copy(), X[:, :, [i | M for i in lo]].copy()
                 X[:, :, lo] = F[0, 0] * a + F[0, 1] * b
                 X[:, :, [i | M for i in lo]] = F[1, 0] * a + F[1, 1] * b
+            for ph in phases[int(fs["phase_begin"]):int(fs["phase_begin"]) + int(fs["phase_count"])]:
+                U = mats[int(ph["gate"])]
+                assert abs(U[0, 1]) == 0 and abs(U[1, 0]) == 0, "a parity phase must come from a diagonal gate"
+                sel = _parity(sidx & int(ph["mask"])) ^ int(ph["cbit"])
+                X = X * np.where(sel == 1, U[1, 1], U[0, 0])[None, :, :]
             if int(fs["perm"]):
                 lc = [int(v) for v in fs["lc"][:k - 4]]
                 lbl = np.zeros_like(u)
@@ -398,7 +413,8 @@ def forward_fused(passes, ops, fstages, fconds, soff, sgate, psi, mats):
     return psi
 
 
-def reverse_fused(passes, ops, fstages, fconds, soff, sgate, sinfo, psi, lam, mats, n_pgates, method="gates"):
+def reverse_fused(passes, ops, fstages, fconds, soff, sgate, sinfo, psi, lam, mats, n_pgates, method="gates",
+                  phases=()):
     """Adjoint passes with fused stages where the plan has them, then the
     stage's store map; the op-by-op path elsewhere.  Per active register bit:
 
@@ -409,7 +425,11 @@ def reverse_fused(passes, ops, fstages, fconds, soff, sgate, sinfo, psi, lam, ma
       Q2 = Re(conj(la) b - conj(lb) a) of the states before the bit's gates,
       each gradient as k00 Q0 + Re k01 Q1 + Im k01 Q2 with K = V^dagger G V
       (V the product of the U^dagger undone before it), then the product of
-      all U^dagger at once."""
+      all U^dagger at once;
+
+    then the stage's parity phases, each a gradient term
+    sum_v (-1)^{parity(mask & v) ^ cbit} Im(conj(lam_v) psi_v) (for an RZ) and
+    U^dagger's diagonal entry on both states."""
     psi, lam = psi.copy(), lam.copy()
     gpart = np.zeros(n_pgates)
     pauli = {GEN_X: np.array([[0, 1], [1, 0]], dtype=complex), GEN_Y: np.array([[0, -1j], [1j, 0]]),
@@ -472,6 +492,16 @@ def reverse_fused(passes, ops, fstages, fconds, soff, sgate, sinfo, psi, lam, ma
                         gpart[pg] += (la.conj() * ga + lb.conj() * gb).imag.sum()
                     X[:, :, lo], X[:, :, hi] = W[0, 0] * a + W[0, 1] * b, W[1, 0] * a + W[1, 1] * b
                     L[:, :, lo], L[:, :, hi] = W[0, 0] * la + W[0, 1] * lb, W[1, 0] * la + W[1, 1] * lb
+            for ph in phases[int(fs["phase_begin"]):int(fs["phase_begin"]) + int(fs["phase_count"])]:
+                W = mats[int(ph["gate"])].conj().T
+                info = int(ph["info"])
+                sel = _parity(sidx & int(ph["mask"])) ^ int(ph["cbit"])
+                if (info >> 4) - 1 >= 0:
+                    assert info & 3 == GEN_Z
+                    sgn = np.where(sel == 1, -1.0, 1.0)[None, :, :]
+                    gpart[(info >> 4) - 1] += (sgn * (np.conj(L) * X).imag).sum()
+                d = np.where(sel == 1, W[1, 1], W[0, 0])[None, :, :]
+                X, L = X * d, L * d
             if int(fs["perm"]):
                 lc = [int(v) for v in fs["lc"][:k - nb]]
                 lbl = np.zeros_like(u)

@@ -213,13 +213,15 @@ def test_fused_stage_schedules(ctx, kind, n, k, c):
     th = synth.uniform_thetas(spec.n_params, 1, seed=n)[0]
     C = vqe.Circuit.from_spec(ctx, spec)
     mats = emu.gate_matrices(spec, th)
-    passes, ops, fst, fco, soff, sg, si = vqe.circuit_plan(ctx, C, stages="fused")
+    passes, ops, fst, fco, soff, sg, si, fph = vqe.circuit_plan(ctx, C, stages="fused")
     assert int(passes["fstage_count"].sum()) == len(fst) > 0
     if kind == "hea":
         assert (passes["fstage_count"] > 0).all()
     ref = np.zeros(1 << n, dtype=complex)
     ref[spec.ref_index] = 1
-    psi = emu.forward_fused(passes, ops, fst, fco, soff, sg, ref, mats)
+    if kind == "qaoa":  # the RZ between a CNOT pair becomes a parity phase
+        assert len(fph) > 0
+    psi = emu.forward_fused(passes, ops, fst, fco, soff, sg, ref, mats, fph)
     np.testing.assert_allclose(psi, oracle.state(spec, th), atol=1e-12)
 
 
@@ -235,7 +237,9 @@ def test_fused_adjoint_schedules(ctx, kind, n, k, c):
     th = synth.uniform_thetas(spec.n_params, 1, seed=n)[0]
     C = vqe.Circuit.from_spec(ctx, spec)
     mats = emu.gate_matrices(spec, th)
-    rp, rops, fst, fco, soff, sg, si = vqe.circuit_plan(ctx, C, reverse=True, stages="fused")
+    rp, rops, fst, fco, soff, sg, si, fph = vqe.circuit_plan(ctx, C, reverse=True, stages="fused")
+    if kind == "qaoa":
+        assert len(fph) > 0 and (fph["info"] >= 16).any()
     assert len(fst) > 0 and (fst["nb"] == 3).all()
     psi = oracle.state(spec, th)
     n_pg = int((spec.param_idx >= 0).sum())
@@ -244,7 +248,8 @@ def test_fused_adjoint_schedules(ctx, kind, n, k, c):
     _, g_or = oracle.energy_grad(spec, ham, th, "adjoint")
     for method in ("gates", "coef"):
         back, _, gpart = emu.reverse_fused(rp, rops, fst, fco, soff, sg, si, psi,
-                                           oracle.apply_hamiltonian(psi, ham), mats, n_pg, method=method)
+                                           oracle.apply_hamiltonian(psi, ham), mats, n_pg, method=method,
+                                           phases=fph)
         np.testing.assert_allclose(back, ref, atol=1e-12)
         np.testing.assert_allclose(_grad_from_parts(spec, gpart), g_or, atol=1e-11)
 
