@@ -1167,7 +1167,7 @@ __device__ __forceinline__ void apply_phases(double2 (&x)[N], const PhaseL *phl,
 
 // one fused stage for this thread's sub-cube u (na active register bits;
 // PERM: the CNOT / X network moves the amplitudes on the way back to LDS)
-template <int NA, bool PERM>
+template <int NA, bool PERM, bool PH>
 __device__ __forceinline__ void fused_stage(double2 *tile, const FusedStage &fs, const Mat2 *fm, int nsub,
                                             uint32_t ctile, const PhaseL *phl, int nph)
 {
@@ -1195,7 +1195,7 @@ __device__ __forceinline__ void fused_stage(double2 *tile, const FusedStage &fs,
         if (NA > 1) fused_bit<1>(x, fm[1]);
         if (NA > 2) fused_bit<2>(x, fm[2]);
         if (NA > 3) fused_bit<3>(x, fm[3]);
-        apply_phases<16>(x, phl, nph, bl, roff);
+        if (PH) apply_phases<16>(x, phl, nph, bl, roff);
     }
     if (PERM) {
         lds_barrier();  // every sub-cube is read before any amplitude moves
@@ -1209,6 +1209,7 @@ __device__ __forceinline__ void fused_stage(double2 *tile, const FusedStage &fs,
     }
 }
 
+template <bool PH>
 __global__ __launch_bounds__(kThreads) void k_forward_fused(const TileGeom *__restrict__ gp, int n, int k, int c,
                                                             int nout, const FusedStage *__restrict__ fstages,
                                                             int nstages, const FusedCond *__restrict__ fconds,
@@ -1233,7 +1234,7 @@ __global__ __launch_bounds__(kThreads) void k_forward_fused(const TileGeom *__re
     for (int i = tid; i < 16 * nstages; i += kThreads) fmd[i] = F[i];  // 4 double2 per matrix
     PhaseL *phl = reinterpret_cast<PhaseL *>(fm + 4 * nstages);
     const double2 *Mx = mats + (size_t)blockIdx.y * n_gates * 4;
-    for (int i = tid; i < nph; i += kThreads) {
+    for (int i = tid; PH && i < nph; i += kThreads) {
         const FusedPhase f = fphases[ph0 + i];
         PhaseL q;
         q.mask = f.mask;
@@ -1262,16 +1263,16 @@ __global__ __launch_bounds__(kThreads) void k_forward_fused(const TileGeom *__re
             const PhaseL *sp = phl + (fs.phase_begin - ph0);
             const int np = fs.phase_count;
             switch (na * 2 + perm) {
-            case 0: fused_stage<0, false>(tile, fs, m4, nsub, ctile, sp, np); break;
-            case 1: fused_stage<0, true>(tile, fs, m4, nsub, ctile, sp, np); break;
-            case 2: fused_stage<1, false>(tile, fs, m4, nsub, ctile, sp, np); break;
-            case 3: fused_stage<1, true>(tile, fs, m4, nsub, ctile, sp, np); break;
-            case 4: fused_stage<2, false>(tile, fs, m4, nsub, ctile, sp, np); break;
-            case 5: fused_stage<2, true>(tile, fs, m4, nsub, ctile, sp, np); break;
-            case 6: fused_stage<3, false>(tile, fs, m4, nsub, ctile, sp, np); break;
-            case 7: fused_stage<3, true>(tile, fs, m4, nsub, ctile, sp, np); break;
-            case 8: fused_stage<4, false>(tile, fs, m4, nsub, ctile, sp, np); break;
-            default: fused_stage<4, true>(tile, fs, m4, nsub, ctile, sp, np); break;
+            case 0: fused_stage<0, false, PH>(tile, fs, m4, nsub, ctile, sp, np); break;
+            case 1: fused_stage<0, true, PH>(tile, fs, m4, nsub, ctile, sp, np); break;
+            case 2: fused_stage<1, false, PH>(tile, fs, m4, nsub, ctile, sp, np); break;
+            case 3: fused_stage<1, true, PH>(tile, fs, m4, nsub, ctile, sp, np); break;
+            case 4: fused_stage<2, false, PH>(tile, fs, m4, nsub, ctile, sp, np); break;
+            case 5: fused_stage<2, true, PH>(tile, fs, m4, nsub, ctile, sp, np); break;
+            case 6: fused_stage<3, false, PH>(tile, fs, m4, nsub, ctile, sp, np); break;
+            case 7: fused_stage<3, true, PH>(tile, fs, m4, nsub, ctile, sp, np); break;
+            case 8: fused_stage<4, false, PH>(tile, fs, m4, nsub, ctile, sp, np); break;
+            default: fused_stage<4, true, PH>(tile, fs, m4, nsub, ctile, sp, np); break;
             }
             lds_barrier();
         }
@@ -1402,7 +1403,7 @@ __device__ __forceinline__ void rbit_step(double2 (&x)[8], double2 (&l)[8], cons
     }
 }
 
-template <int NA, bool PERM>
+template <int NA, bool PERM, bool PH>
 __device__ __forceinline__ void rev_fused_stage(double2 *tp, double2 *tl, const FusedStage &fs, const Mat2 *wm,
                                                 const int32_t *qidx, int nsub, uint32_t ctile, double *red,
                                                 const PhaseL *phl, int nph, double *phred)
@@ -1438,7 +1439,7 @@ __device__ __forceinline__ void rev_fused_stage(double2 *tp, double2 *tl, const 
     if (NA > 0) rbit_step<0>(x, l, wm[0], (int)__builtin_amdgcn_readfirstlane((uint32_t)qidx[0]), red);
     if (NA > 1) rbit_step<1>(x, l, wm[1], (int)__builtin_amdgcn_readfirstlane((uint32_t)qidx[1]), red);
     if (NA > 2) rbit_step<2>(x, l, wm[2], (int)__builtin_amdgcn_readfirstlane((uint32_t)qidx[2]), red);
-    if (nph > 0) {
+    if (PH) {
         // parity phases: every gradient term is (-1)^{parity} Im(conj(lam) psi)
         // summed over the sub-cube (diagonal phases leave Im(conj(lam) psi)
         // unchanged, so one set of products serves all), then U^dagger on both
@@ -1489,6 +1490,7 @@ __device__ __forceinline__ void rev_fused_stage(double2 *tp, double2 *tl, const 
 // adjoint writes them.  The pass owns slots [slot0, slot0 + 3 * nstages) and
 // their entries [e0, e0 + ne); wadj / coef hold the per-instance products
 // and coefficients of every slot / entry of the plan (n_slots / n_entries).
+template <bool PH>
 __global__ __launch_bounds__(kThreads) void k_reverse_fused(
     const TileGeom *__restrict__ gp, int n, int k, int c, int nout, const FusedStage *__restrict__ fstages,
     int nstages, const FusedCond *__restrict__ fconds, const int32_t *__restrict__ slot_off,
@@ -1528,7 +1530,7 @@ __global__ __launch_bounds__(kThreads) void k_reverse_fused(
     {
         const double2 *Mx = mats + (size_t)blockIdx.y * n_gates * 4;
         int pslot = 0;  // parametric phases numbered in order (every thread counts)
-        for (int i = 0; i < nph; ++i) {
+        for (int i = 0; PH && i < nph; ++i) {
             const FusedPhase f = fphases[ph0 + i];
             const bool par = f.info >= 16;
             if (tid == 0) {
@@ -1564,14 +1566,14 @@ __global__ __launch_bounds__(kThreads) void k_reverse_fused(
             const PhaseL *sp = phl + (fs.phase_begin - ph0);
             const int np = fs.phase_count;
             switch (na * 2 + perm) {
-            case 0: rev_fused_stage<0, false>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred); break;
-            case 1: rev_fused_stage<0, true>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred); break;
-            case 2: rev_fused_stage<1, false>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred); break;
-            case 3: rev_fused_stage<1, true>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred); break;
-            case 4: rev_fused_stage<2, false>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred); break;
-            case 5: rev_fused_stage<2, true>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred); break;
-            case 6: rev_fused_stage<3, false>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred); break;
-            default: rev_fused_stage<3, true>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred); break;
+            case 0: rev_fused_stage<0, false, PH>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred); break;
+            case 1: rev_fused_stage<0, true, PH>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred); break;
+            case 2: rev_fused_stage<1, false, PH>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred); break;
+            case 3: rev_fused_stage<1, true, PH>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred); break;
+            case 4: rev_fused_stage<2, false, PH>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred); break;
+            case 5: rev_fused_stage<2, true, PH>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred); break;
+            case 6: rev_fused_stage<3, false, PH>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred); break;
+            default: rev_fused_stage<3, true, PH>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred); break;
             }
             lds_barrier();
         }
@@ -1596,7 +1598,7 @@ __global__ __launch_bounds__(kThreads) void k_reverse_fused(
                 partials[((size_t)blockIdx.y * n_pgates + ((info >> 4) - 1)) * W + blockIdx.x] = v;
             }
         }
-        for (int i = 0; i < nph; ++i) {
+        for (int i = 0; PH && i < nph; ++i) {
             const PhaseL &q = phl[i];
             if (q.pslot < 0) continue;
             const double *r = phred + (size_t)q.pslot * 4;
@@ -2244,9 +2246,10 @@ hipError_t launch_forward_fused(const PassPlan &pp, const TileGeom *geom_dev, co
     const int W = (int)std::min<int64_t>(tiles, wg_max);
     const size_t lds = forward_fused_lds(g.k, g.c, pp.fstage_count, pp.fphase_count);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
-    hipError_t e = ensure_lds(k_forward_fused, lds);
+    auto kern = pp.fphase_count > 0 ? k_forward_fused<true> : k_forward_fused<false>;
+    hipError_t e = ensure_lds(kern, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_forward_fused, dim3(W, (unsigned)batch), dim3(kThreads), lds, s, geom_dev, g.n, g.k, g.c,
+    hipLaunchKernelGGL(kern, dim3(W, (unsigned)batch), dim3(kThreads), lds, s, geom_dev, g.n, g.k, g.c,
                        g.nout, fstages + pp.fstage_begin, pp.fstage_count, fconds, fused, n_slots, fphases,
                        pp.fphase_begin, pp.fphase_count, mats, n_gates, psi, tiles);
     return hipGetLastError();
@@ -2287,9 +2290,10 @@ hipError_t launch_reverse_fused(const PassPlan &pp, const TileGeom *geom_dev, co
     const int64_t tiles = 1ll << g.nout;
     const size_t lds = reverse_fused_lds(g.k, g.c, pp.fstage_count, n_qslots, pp.fphase_count);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
-    hipError_t e = ensure_lds(k_reverse_fused, lds);
+    auto kern = pp.fphase_count > 0 ? k_reverse_fused<true> : k_reverse_fused<false>;
+    hipError_t e = ensure_lds(kern, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reverse_fused, dim3(wg_per_inst, (unsigned)batch), dim3(kThreads), lds, s, geom_dev, g.n,
+    hipLaunchKernelGGL(kern, dim3(wg_per_inst, (unsigned)batch), dim3(kThreads), lds, s, geom_dev, g.n,
                        g.k, g.c, g.nout, fstages + pp.fstage_begin, pp.fstage_count, fconds, slot_off, slot_info,
                        slot0, n_slots, n_entries, wadj, coef, fphases, pp.fphase_begin, pp.fphase_count, mats,
                        n_gates, psi, lam, tiles, partials, n_pgates);

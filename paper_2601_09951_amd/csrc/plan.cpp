@@ -320,6 +320,19 @@ static bool build_fused(const Circ *C, const std::vector<int> &take, const std::
 
     // an RZ on touched bit t as a parity phase (only while the network has no
     // X conditioned on bits outside the tile); false: flush instead
+    // A phase pays off only when it saves a flush: when the next gate of the
+    // pass on tile bit t is a network gate (or there is none).  When a
+    // non-diagonal one-qubit gate comes next, the group flushes there anyway
+    // and the RZ is cheaper as part of that qubit's next 2x2.
+    auto next_is_network = [&](size_t pos, int t) {
+        for (size_t q = pos + 1; q < take.size(); ++q) {
+            const GateHost &h = C->gates[take[q]];
+            const uint32_t bits = compress(h.m | (h.cmask & tmask), tile);
+            if (!((bits >> t) & 1u)) continue;
+            return h.kind == VQE_GATE_CNOT || h.kind == VQE_GATE_X;
+        }
+        return true;
+    };
     auto as_phase = [&](int g, int t) {
         if (C->gates[g].kind != VQE_GATE_RZ) return false;
         uint32_t col[16];
@@ -347,7 +360,8 @@ static bool build_fused(const Circ *C, const std::vector<int> &take, const std::
         return true;
     };
 
-    for (int g : take) {
+    for (size_t pos = 0; pos < take.size(); ++pos) {
+        const int g = take[pos];
         const GateHost &h = C->gates[g];
         const int t = __builtin_ctz(compress(h.m, tile));
         if (h.kind == VQE_GATE_CNOT || h.kind == VQE_GATE_X) {
@@ -371,7 +385,7 @@ static bool build_fused(const Circ *C, const std::vector<int> &take, const std::
             continue;
         }
         if ((touched >> t) & 1) {
-            if (as_phase(g, t)) continue;
+            if (next_is_network(pos, t) && as_phase(g, t)) continue;
             flush();
         }
         if (oneq[t].empty()) order.push_back(t);
