@@ -96,6 +96,7 @@ inline size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 struct Layout {
     size_t psi = 0, lam = 0, mats = 0, pe = 0, pg = 0, grad = 0, m = 0, v = 0, etmp = 0;
     size_t wadj = 0, coef = 0;  // adjoint fused stages: per-slot products, per-entry coefficients
+    size_t hist = 0;            // persistent loop on small states: pair values after each gate
     size_t total = 0;
     int W_fwd_sweep = 1, W_hpsi = 1, W_rev = 1;
     int n_sweeps_e = 1;
@@ -217,6 +218,10 @@ int layout_for(Context *ctx, Circ *C, int n_hams, Ham *const *H, int64_t B, int 
         L.W_fwd_sweep = wg_for(ctx, n, ctx->k_fwd);
         L.etmp = off;
         off = align_up(off + (size_t)B * L.n_sweeps_e * L.W_fwd_sweep * 8);
+        if (n <= 8) {
+            L.hist = off;
+            off = align_up(off + (size_t)B * small_fast_hist_bytes(n, G));
+        }
     }
     L.total = off;
     return VQE_OK;
@@ -1120,6 +1125,23 @@ int vqe_adam_step(vqe_ctx_t ctx, int64_t batch, int32_t n_params, double *theta,
                      "adam");
 }
 
+namespace {
+// single-pass plans of one circuit: forward op g and reverse op G - 1 - g are
+// the same gate with the same pair layout (the persistent loop's history of
+// pair values is written by the one and read by the other)
+bool same_pairs(const CircPlan *fp, const CircPlan *rp, int G)
+{
+    if ((int)fp->host_ops.size() != G || (int)rp->host_ops.size() != G) return false;
+    for (int g = 0; g < G; ++g) {
+        const OpDesc &f = fp->host_ops[g], &r = rp->host_ops[G - 1 - g];
+        if (f.gate != g || r.gate != g || f.m != r.m || f.fixed_bits != r.fixed_bits || f.nfix != r.nfix ||
+            std::memcmp(f.fixpos, r.fixpos, sizeof(f.fixpos)) != 0)
+            return false;
+    }
+    return true;
+}
+}  // namespace
+
 int vqe_run(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams, int64_t batch,
             uint64_t ref_index, double *theta, int32_t iters, int32_t optimizer, double lr, double b1,
             double b2, double eps, double *energies, void *workspace, size_t ws_bytes, void *stream)
@@ -1165,7 +1187,7 @@ int vqe_run(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams, i
         size_t lds = 0;
         if (fp->passes.size() == 1 && rp->passes.size() == 1 && pp->sweeps.size() == 1 &&
             fp->passes[0].op_count == G && rp->passes[0].op_count == G &&
-            pp->sweeps[0].grp_count == NU &&
+            pp->sweeps[0].grp_count == NU && same_pairs(fp, rp, G) &&
             small_run_plan(n, G, P, circ->n_pgates, NU, max_inst_terms, has_imag, &mode, &lds)) {
             SmallRunArgs a;
             a.n = n;
@@ -1188,13 +1210,15 @@ int vqe_run(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams, i
             a.shared_ham = n_hams == 1;
             a.theta = theta;
             a.energies = energies;
-            a.work = nullptr;
+            a.hist = reinterpret_cast<double2 *>(ws + L.hist);
             rc = refresh_weights(ctx, pp, s);
             if (rc) return rc;
+            int max_pairs = 1;
+            for (const OpDesc &o : fp->host_ops) max_pairs = std::max(max_pairs, 1 << (n - o.nfix));
             return hip_check(ctx, launch_small_run(a, reinterpret_cast<const OpDesc *>(rp->ops.p),
                                                    reinterpret_cast<const int32_t *>(circ->pmap_off.p),
                                                    reinterpret_cast<const int32_t *>(circ->pmap_idx.p),
-                                                   circ->n_pgates, mode, max_inst_terms, batch, s),
+                                                   circ->n_pgates, mode, max_inst_terms, max_pairs, batch, s),
                              "persistent VQE loop");
         }
     }

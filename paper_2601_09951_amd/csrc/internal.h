@@ -428,13 +428,14 @@ struct SmallRunArgs {
     int shared_ham;
     double *theta;                 // [B][P]
     double *energies;              // [B][iters+1]
-    double *work;                  // [B][2P] Adam moments
+    double2 *hist;                 // [B][n_gates + 1][slots][64][2] pair values after each gate (fast loop)
 };
 hipError_t launch_small_run(const SmallRunArgs &a, const OpDesc *rops, const int32_t *pmap_off,
-                            const int32_t *pmap_idx, int n_pgates, int mode, int max_inst_terms,
+                            const int32_t *pmap_idx, int n_pgates, int mode, int max_inst_terms, int max_pairs,
                             int64_t batch, hipStream_t s);
 int small_run_plan(int n, int n_gates, int n_params, int n_pgates, int n_groups, int max_inst_terms,
                    int has_imag, int *mode_out, size_t *lds_out);
+size_t small_fast_hist_bytes(int n, int n_gates);  // per instance
 }  // namespace vqe
 
 struct vqe_ctx : vqe::Context {};

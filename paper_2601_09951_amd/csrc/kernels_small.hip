@@ -483,29 +483,45 @@ __global__ __launch_bounds__(256) void k_small_run(SmallKernelArgs ka)
 }
 
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
 // The same loop for states of at most 8 qubits with the Hamiltonian as
 // XOR-offset diagonals, built for latency.  An iteration is a chain of
-// dependent steps (gate after gate, then H psi, then the reverse sweep); on
-// this hardware a dependent FP64 operation costs about 32 cycles, an LDS
-// round trip about 70 and a taken branch tens of cycles, so every link of the
-// chain is cut to its data dependence:
-//  * one amplitude and at most one pair per thread (NT = max(64, 2^n));
-//  * each thread's pair indices for every op are tabulated once per launch
-//    and the gate matrices are laid out in op order (the reverse ones already
-//    conjugate-transposed); after each barrier a thread reads its pair, then
-//    the next op's table entry and matrix (into the other of two register
-//    sets), applies the full 2x2 without branching on the gate class and
-//    writes back;
-//  * cos and sin of the half angles are taken in the optimiser step, so
-//    building the matrices needs no transcendental;
-//  * lambda = H psi uses eight interleaved accumulators;
-//  * gradient partials are written per thread; with several waves the last
-//    wave, which holds no pairs, sums each op's partials during the next op;
-//    the energy's sum runs on that wave beside the optimiser step.
+// dependent steps (gate after gate, then H psi, then the reverse sweep, then
+// the optimiser step); on this hardware a dependent FP64 operation costs tens
+// of cycles, an LDS round trip about 70 and a workgroup barrier with the wave
+// skew it waits for well over 100, so every link of the chain is cut to its
+// data dependence:
+//  * the gate chains (forward and reverse) and the optimiser step run on one
+//    wave, which needs no workgroup barrier between dependent steps: a
+//    wave's LDS operations execute in issue order, so a wave-level fence
+//    (a compiler code-motion barrier) is all that orders one gate's writes
+//    before the next gate's reads; only H psi, whose work is spread over all
+//    amplitudes, uses every wave, with one barrier on each side;
+//  * a lane holds one pair of a gate, two when a gate has more pairs than
+//    lanes (one-qubit gates at 8 qubits; a template parameter); the pair
+//    indices of every op are tabulated once per launch and the gate
+//    matrices are laid out in op order (the reverse ones already
+//    conjugate-transposed);
+//  * the forward sweep records each lane's pair values after every gate in
+//    a history buffer in global memory; the reverse sweep reads psi back
+//    from it (four ops ahead) instead of undoing the gates on psi, so only
+//    lambda is carried back;
+//  * the optimiser step writes the next iteration's matrices of each
+//    parameter's gates directly (U = A cos(a/2) + B sin(a/2) with A, B
+//    tabulated per parametric gate); constant gates keep theirs;
+//  * lambda = H psi uses eight interleaved accumulators, one amplitude per
+//    thread;
+//  * a gate's gradient partials go to an LDS row per parametric gate, one
+//    per lane, summed in fixed order after the sweep; with several waves
+//    the last one sums the energy during the reverse sweep.
 struct FastLayout {
-    size_t psi, lam, matf, matr, cs, fcs, th, mom, vel, gpart, gsum, epart, finf, rinf, ptf, ptr, gdev, poff, pidx,
-        gf, tab, total;
+    size_t psi, lam, matf, matr, cs, fcs, th, mom, vel, gpart, gsum, epart, finf, rinf, ptf, ptr, pq, mab, gdev, poff,
+        pidx, gf, tab, total;
 };
+
+// padding ops after the last op of the gate chains: no pairs, zero
+// matrices, gate index G (a spare history row)
+constexpr int kFastPad = 4;
 
 __host__ __device__ inline int fast_threads(int n) { return n <= 6 ? 64 : (1 << n); }
 
@@ -521,22 +537,24 @@ __host__ __device__ inline FastLayout fast_layout(int n, int G, int P, int NPG, 
         o += bytes;
         return r;
     };
-    L.psi = take(16 * (D + 2), 16);  // + two trash slots for threads without a pair
-    L.lam = take(16 * (D + 2), 16);
-    L.matf = take((size_t)64 * (G + 2), 16);  // + two padding ops (branch-free prefetch)
-    L.matr = take((size_t)64 * (G + 2), 16);
+    L.psi = take(16 * (D + 128), 16);  // + two trash slots per lane for lanes without a pair
+    L.lam = take(16 * (D + 128), 16);
+    L.matf = take((size_t)64 * (G + kFastPad), 16);  // + padding ops (branch-free prefetch)
+    L.matr = take((size_t)64 * (G + kFastPad), 16);
     L.cs = take((size_t)16 * (P > 0 ? P : 1), 16);
     L.fcs = take((size_t)16 * G, 16);
     L.th = take((size_t)8 * P, 8);
     L.mom = take((size_t)8 * P, 8);
     L.vel = take((size_t)8 * P, 8);
-    L.gpart = take(8 * H * npg, 8);
-    L.gsum = take((size_t)8 * 16 * npg, 8);
+    L.gpart = take((size_t)8 * 64 * (npg + 1), 16);  // per parametric gate (+ a spare row), one partial per lane
+    L.gsum = take((size_t)8 * (npg > 4 ? npg : 4), 8);  // one sum per parametric gate (4: block sum scratch)
     L.epart = take(8 * nt, 8);
-    L.finf = take((size_t)8 * (G + 2), 8);  // {gen | (pgate + 1) << 8, gate} per op
-    L.rinf = take((size_t)8 * (G + 2), 8);
-    L.ptf = take(2 * (size_t)(G + 2) * H, 4);  // pairs live on threads t < H
-    L.ptr = take(2 * (size_t)(G + 2) * H, 4);
+    L.finf = take((size_t)8 * (G + kFastPad), 8);  // {gen | (pgate + 1) << 8, gate} per op
+    L.rinf = take((size_t)8 * (G + kFastPad), 8);
+    L.ptf = take(2 * (size_t)(G + kFastPad) * H, 4);  // pairs live on threads t < H
+    L.ptr = take(2 * (size_t)(G + kFastPad) * H, 4);
+    L.pq = take((size_t)8 * npg, 8);            // per parametric gate: forward and reverse op
+    L.mab = take((size_t)256 * npg, 16);        // per parametric gate: U = A cos + B sin, forward and reverse
     L.gdev = take(sizeof(GateDev) * G, 16);
     L.poff = take((size_t)4 * (P + 1), 4);
     L.pidx = take((size_t)4 * npg, 4);
@@ -559,68 +577,248 @@ __device__ __forceinline__ double2 mac2(double2 u, double2 x, double2 v, double2
 
 constexpr uint32_t kNoPair = 0xFFFFu;
 
-// one forward op: read the pair (clamped to index 0 when the thread has none),
-// read the next op's entry and matrix into (pn, un), apply, write back
-__device__ __forceinline__ void fast_fwd_op(double2 *psi, const uint16_t *ptf, const double2 *matf, int qn, int H,
-                                            int D, uint32_t cur, const double2 (&u)[4], uint32_t &pn,
-                                            double2 (&un)[4])
+// Orders the calling wave's LDS writes before its later LDS reads by other
+// lanes: LDS operations of one wave execute in issue order, so no wait is
+// needed, only that the compiler moves no memory operation across.
+__device__ __forceinline__ void wave_lds_sync()
 {
-    // a thread without a pair works on the trash slots D, D + 1 (no branch)
-    const bool act = cur != kNoPair;
-    const uint32_t i0 = act ? (cur & 255u) : (uint32_t)D, i1 = act ? (cur >> 8) : (uint32_t)D + 1u;
-    const double2 x = psi[i0], y = psi[i1];
-    const int t = (int)threadIdx.x;
-    const uint32_t e = ptf[qn * H + (t < H ? t : H - 1)];  // unconditional read, then select
-    pn = t < H ? e : kNoPair;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) un[k] = matf[4 * qn + k];
-    psi[i0] = mac2(u[0], x, u[1], y);
-    psi[i1] = mac2(u[2], x, u[3], y);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// one reverse op: gradient partial Im <lam|G|psi> on the pair, U^dagger on both
-__device__ __forceinline__ double fast_rev_op(double2 *psi, double2 *lam, const uint16_t *ptr, const double2 *matr,
-                                              const int2 *rinf, int qn, int H, int D, uint32_t cur, int gen,
-                                              const double2 (&u)[4], uint32_t &pn, double2 (&un)[4], int &coden)
+// op q's pair entries of this lane (pairs lane + 64 s, kNoPair past the op's
+// pair count) and its matrix; ops G and G + 1 are padding (no pairs, zero
+// matrices), so the prefetch of op q + 1 needs no branch
+template <int SP>
+__device__ __forceinline__ void fast_tables(const uint16_t *pt, const double2 *mat, int q, int H, int lane,
+                                            uint32_t (&pe)[SP], double2 (&u)[4])
 {
-    const bool act = cur != kNoPair;
-    const uint32_t i0 = act ? (cur & 255u) : (uint32_t)D, i1 = act ? (cur >> 8) : (uint32_t)D + 1u;
-    const double2 x = psi[i0], y = psi[i1], lx = lam[i0], ly = lam[i1];
-    const int t = (int)threadIdx.x;
-    const uint32_t e = ptr[qn * H + (t < H ? t : H - 1)];  // unconditional read, then select
-    pn = t < H ? e : kNoPair;
-    coden = rinf[qn].x;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) un[k] = matr[4 * qn + k];
-    const double gx = (lx.x * y.y - lx.y * y.x) + (ly.x * x.y - ly.y * x.x);
-    const double gy = (ly.x * x.x + ly.y * x.y) - (lx.x * y.x + lx.y * y.y);
-    const double gz = (lx.x * x.y - lx.y * x.x) - (ly.x * y.y - ly.y * y.x);
-    psi[i0] = mac2(u[0], x, u[1], y);
-    psi[i1] = mac2(u[2], x, u[3], y);
-    lam[i0] = mac2(u[0], lx, u[1], ly);
-    lam[i1] = mac2(u[2], lx, u[3], ly);
-    const double g = gen == GEN_Y ? gy : (gen == GEN_X ? gx : gz);
-    return act ? g : 0.0;
-}
-
-// 16 fixed-stride partial sums of a gradient row of H partials
-__device__ __forceinline__ double row_part(const double *row, int H, int part)
-{
-    double s0 = 0.0, s1 = 0.0;
-    int t = part;
-    for (; t + 16 < H; t += 32) {
-        s0 += row[t];
-        s1 += row[t + 16];
+    for (int s = 0; s < SP; ++s) {
+        const int t = lane + 64 * s;
+        const uint32_t e = pt[q * H + (t < H ? t : H - 1)];  // unconditional read, then select
+        pe[s] = t < H ? e : kNoPair;
     }
-    if (t < H) s0 += row[t];
-    return s0 + s1;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) u[k] = mat[4 * q + k];
 }
 
-template <int NT, bool CT>
+// pair indices of a table entry; a lane without a pair works on its own two
+// trash slots past the state (no branch, no two lanes on one address)
+__device__ __forceinline__ void pair_of(uint32_t e, int D, int lane, uint32_t &i0, uint32_t &i1)
+{
+    const bool act = e != kNoPair;
+    i0 = act ? (e & 255u) : (uint32_t)(D + 2 * lane);
+    i1 = act ? (e >> 8) : (uint32_t)(D + 2 * lane + 1);
+}
+
+// bit 4 of an op's info word: the op has more pairs than lanes, so the
+// second pair slot is in use (a wave-uniform test)
+constexpr int kTwoSlots = 16;
+
+// pair slots per lane: a gate on 2^n amplitudes has at most 2^n / 2 pairs
+__host__ __device__ constexpr int fast_slots(int n) { return n >= 8 ? 2 : 1; }
+
+// One gate op as the gate wave sees it: the lane's pair table entries, the
+// op's matrix and info word, the state values read on the lane's pairs and
+// (reverse sweep) psi on those pairs after the gate, from the forward
+// history.  The chains below alternate two of these buffers over the ops
+// (op q in buffer q & 1): while op q computes, the pairs of op q + 1 are
+// already read and the tables of op q + 2 are on their way, so each op costs
+// one LDS read latency plus its arithmetic, and no value is moved between
+// registers (a move would have to wait for its load).
+template <int SP>
+struct FastOp {
+    uint32_t pe[SP];
+    double2 u[4];
+    int2 info;
+    double2 x[SP], y[SP];  // the state on the pairs before the op
+};
+
+// psi on the lane's pairs after a gate (forward history, reverse sweep)
+template <int SP>
+struct FastHist {
+    double2 hx[SP], hy[SP];
+};
+
+template <int SP>
+__device__ __forceinline__ void fast_op_load(FastOp<SP> &o, const uint16_t *pt, const double2 *mat, const int2 *inf,
+                                             int q, int H, int lane)
+{
+    fast_tables<SP>(pt, mat, q, H, lane, o.pe, o.u);
+    o.info = inf[q];
+}
+
+// read the op's pairs of a state (psi forward, lambda reverse)
+template <int SP>
+__device__ __forceinline__ void fast_op_read(FastOp<SP> &o, const double2 *st, int D, int lane)
+{
+    const bool two = SP > 1 && (ufirst((uint32_t)o.info.x) & kTwoSlots);
+#pragma unroll
+    for (int s = 0; s < SP; ++s)
+        if (s == 0 || two) {
+            uint32_t i0, i1;
+            pair_of(o.pe[s], D, lane, i0, i1);
+            o.x[s] = st[i0];
+            o.y[s] = st[i1];
+        }
+}
+
+// forward op: update the lane's pairs of psi and record them after the gate
+// in hist[gate][slot][lane] (global memory, off the chain)
+template <int SP>
+__device__ __forceinline__ void fast_fwd_step(const FastOp<SP> &o, double2 *psi, double2 *__restrict__ hist, int D,
+                                              int lane)
+{
+    const bool two = SP > 1 && (ufirst((uint32_t)o.info.x) & kTwoSlots);
+    double2 *hq = hist + (size_t)ufirst((uint32_t)o.info.y) * (SP * 128) + 2 * lane;
+#pragma unroll
+    for (int s = 0; s < SP; ++s)
+        if (s == 0 || two) {
+            uint32_t i0, i1;
+            pair_of(o.pe[s], D, lane, i0, i1);
+            const double2 nx = mac2(o.u[0], o.x[s], o.u[1], o.y[s]), ny = mac2(o.u[2], o.x[s], o.u[3], o.y[s]);
+            psi[i0] = nx;
+            psi[i1] = ny;
+            hq[128 * s] = nx;
+            hq[128 * s + 1] = ny;
+        }
+    wave_lds_sync();
+}
+
+// reverse op: the gradient partial Im <lam|G|psi> of the lane's pairs (psi
+// from the history) into gpart[pgate][lane], then U^dagger on lambda; psi
+// itself is not carried back
+template <int SP>
+__device__ __forceinline__ void fast_rev_step(const FastOp<SP> &o, const FastHist<SP> &h, double2 *lam, double *gpart,
+                                              int npg, int D, int lane)
+{
+    const uint32_t cd = ufirst((uint32_t)o.info.x);
+    const bool two = SP > 1 && (cd & kTwoSlots);
+    const int pg = (int)(cd >> 8) - 1, gen = (int)(cd & 15u);
+    double g = 0.0;
+#pragma unroll
+    for (int s = 0; s < SP; ++s)
+        if (s == 0 || two) {
+            uint32_t i0, i1;
+            pair_of(o.pe[s], D, lane, i0, i1);
+            const double2 a = o.x[s], b = o.y[s];
+            lam[i0] = mac2(o.u[0], a, o.u[1], b);
+            lam[i1] = mac2(o.u[2], a, o.u[3], b);
+            const double2 x = h.hx[s], y = h.hy[s];
+            const double gy = (b.x * x.x + b.y * x.y) - (a.x * y.x + a.y * y.y);
+            const double gx = (a.x * y.y - a.y * y.x) + (b.x * x.y - b.y * x.x);
+            const double gz = (a.x * x.y - a.y * x.x) - (b.x * y.y - b.y * y.x);
+            const double gs = gen == GEN_Y ? gy : (gen == GEN_X ? gx : gz);
+            g += o.pe[s] != kNoPair ? gs : 0.0;
+        }
+    gpart[(pg >= 0 ? pg : npg) * 64 + lane] = g;  // row npg: ops without a parameter
+    wave_lds_sync();
+}
+
+// the forward chain U(theta) e_ref on one wave, two ops per trip (an odd G
+// ends on a harmless padding op)
+template <int SP>
+__device__ __forceinline__ void fast_forward(double2 *psi, const uint16_t *ptf, const double2 *matf,
+                                             const int2 *finf, double2 *__restrict__ hist, int G, int H, int D,
+                                             int lane)
+{
+    FastOp<SP> A, B;
+    fast_op_load<SP>(A, ptf, matf, finf, 0, H, lane);
+    fast_op_load<SP>(B, ptf, matf, finf, 1, H, lane);
+    fast_op_read<SP>(A, psi, D, lane);
+    for (int q = 0; q < G; q += 2) {
+        fast_fwd_step<SP>(A, psi, hist, D, lane);
+        fast_op_read<SP>(B, psi, D, lane);
+        fast_op_load<SP>(A, ptf, matf, finf, q + 2, H, lane);
+        fast_fwd_step<SP>(B, psi, hist, D, lane);
+        fast_op_read<SP>(A, psi, D, lane);
+        fast_op_load<SP>(B, ptf, matf, finf, q + 3, H, lane);
+    }
+}
+
+template <int SP>
+__device__ __forceinline__ void fast_hist_load(FastHist<SP> &h, const double2 *__restrict__ hist, const int2 *inf,
+                                               int q, int lane)
+{
+    const double2 *hq = hist + (size_t)ufirst((uint32_t)inf[q].y) * (SP * 128) + 2 * lane;
+#pragma unroll
+    for (int s = 0; s < SP; ++s) {
+        h.hx[s] = hq[128 * s];
+        h.hy[s] = hq[128 * s + 1];
+    }
+}
+
+template <int SP>
+__device__ __forceinline__ void fast_rev_op(FastOp<SP> &cur, const FastHist<SP> &h, FastOp<SP> &nxt, double2 *lam,
+                                            double *gpart, const uint16_t *ptr, const double2 *matr,
+                                            const int2 *rinf, int npg, int qload, int H, int D, int lane)
+{
+    fast_rev_step<SP>(cur, h, lam, gpart, npg, D, lane);
+    fast_op_read<SP>(nxt, lam, D, lane);
+    fast_op_load<SP>(cur, ptr, matr, rinf, qload, H, lane);
+}
+
+// the reverse chain on one wave, four ops per trip; the history of op q is
+// loaded four ops ahead (global memory latency), the tables two ops ahead
+template <int SP>
+__device__ __forceinline__ void fast_reverse(double2 *lam, const uint16_t *ptr, const double2 *matr, const int2 *rinf,
+                                             const double2 *__restrict__ hist, double *gpart, int npg, int G, int H,
+                                             int D, int lane)
+{
+    FastOp<SP> A, B;
+    FastHist<SP> H0, H1, H2, H3;
+    const int last = G + kFastPad - 1;
+    fast_op_load<SP>(A, ptr, matr, rinf, 0, H, lane);
+    fast_op_load<SP>(B, ptr, matr, rinf, 1, H, lane);
+    fast_hist_load<SP>(H0, hist, rinf, 0, lane);
+    fast_hist_load<SP>(H1, hist, rinf, 1, lane);
+    fast_hist_load<SP>(H2, hist, rinf, 2, lane);
+    fast_hist_load<SP>(H3, hist, rinf, 3, lane);
+    fast_op_read<SP>(A, lam, D, lane);
+    for (int q = 0; q < G; q += 4) {
+        fast_rev_op<SP>(A, H0, B, lam, gpart, ptr, matr, rinf, npg, q + 2, H, D, lane);
+        fast_hist_load<SP>(H0, hist, rinf, min(q + 4, last), lane);
+        fast_rev_op<SP>(B, H1, A, lam, gpart, ptr, matr, rinf, npg, q + 3, H, D, lane);
+        fast_hist_load<SP>(H1, hist, rinf, min(q + 5, last), lane);
+        fast_rev_op<SP>(A, H2, B, lam, gpart, ptr, matr, rinf, npg, min(q + 4, last), H, D, lane);
+        fast_hist_load<SP>(H2, hist, rinf, min(q + 6, last), lane);
+        fast_rev_op<SP>(B, H3, A, lam, gpart, ptr, matr, rinf, npg, min(q + 5, last), H, D, lane);
+        fast_hist_load<SP>(H3, hist, rinf, min(q + 7, last), lane);
+    }
+}
+
+// per parametric gate the sum of its 64 lane partials, on one wave in fixed
+// order: four lanes per gate add 16 partials each, then a quad sum
+__device__ __forceinline__ void gate_sums(const double *gpart, double *gsum, int NPG, int lane)
+{
+    for (int r0 = 0; r0 < NPG; r0 += 16) {
+        const int row = r0 + (lane >> 2), part = lane & 3;
+        double s0 = 0.0, s1 = 0.0;
+        if (row < NPG) {
+            const double2 *v = reinterpret_cast<const double2 *>(gpart + row * 64 + part * 16);
+#pragma unroll
+            for (int j = 0; j < 8; j += 2) {
+                const double2 a = v[j], b = v[j + 1];
+                s0 += a.x + a.y;
+                s1 += b.x + b.y;
+            }
+        }
+        double t = s0 + s1;
+        t += dpp_move<0xB1>(t);  // quad_perm [1, 0, 3, 2]
+        t += dpp_move<0x4E>(t);  // quad_perm [2, 3, 0, 1]
+        if (part == 0 && row < NPG) gsum[row] = t;
+    }
+}
+
+// SP: pair slots per lane of the gate wave, 2 only when some op has more
+// pairs than lanes (one-qubit gates at 8 qubits)
+template <int NT, int SP, bool CT>
 __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
 {
     constexpr int NW = NT / 64;
-    constexpr bool OVERLAP = NW > 1;  // the last wave holds no pairs and reduces gradients meanwhile
+    static_assert(SP == 1 || (SP == 2 && NT == 256), "pair slots per lane");
     extern __shared__ __align__(16) unsigned char smem[];
     const SmallRunArgs &a = ka.a;
     const FastLayout L = fast_layout(a.n, a.n_gates, a.n_params, ka.n_pgates, a.n_groups, CT);
@@ -648,12 +846,12 @@ __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
     double2 *tabc = reinterpret_cast<double2 *>(smem + L.tab);
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const bool redw = OVERLAP && wave == NW - 1;  // the reducing wave
     const int inst = blockIdx.x;
     const int D = 1 << a.n, H = D > 1 ? D / 2 : 1;
     const int G = a.n_gates, P = a.n_params, NG = a.n_groups, NG8 = (NG + 7) / 8 * 8, NPG = ka.n_pgates;
     const int32_t *to = a.toff + (size_t)(a.shared_ham ? 0 : inst) * NG * 3;
     double *energies = a.energies + (size_t)inst * (a.iters + 1);
+    double2 *hist = a.hist + (size_t)inst * (G + 1) * (SP * 128);
 
     // ---- one-time staging (ops G and G + 1 pad the tables and are never applied)
     for (int p = tid; p < P; p += NT) {
@@ -665,24 +863,26 @@ __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
         sincos(0.5 * t, &sn, &cn);
         cs[p] = make_double2(cn, sn);
     }
-    for (int q = tid; q < G + 2; q += NT) {
+    for (int q = tid; q < G + kFastPad; q += NT) {
         if (q < G) {
             const OpDesc f = a.ops[q], r = ka.rops[q];
-            finf[q] = make_int2(f.gen | ((f.pgate + 1) << 8), f.gate);
-            rinf[q] = make_int2(r.gen | ((r.pgate + 1) << 8), r.gate);
+            const int f2 = (D >> pack_op(f).nfix) > 64 ? kTwoSlots : 0;
+            const int r2 = (D >> pack_op(r).nfix) > 64 ? kTwoSlots : 0;
+            finf[q] = make_int2(f.gen | f2 | ((f.pgate + 1) << 8), f.gate);
+            rinf[q] = make_int2(r.gen | r2 | ((r.pgate + 1) << 8), r.gate);
             const GateDev gd = a.gates[q];
             gdev[q] = gd;
             double sn, cn;
             sincos(0.5 * gd.fixed, &sn, &cn);
             fcs[q] = make_double2(cn, sn);
         } else {
-            finf[q] = rinf[q] = make_int2(0, 0);
+            finf[q] = rinf[q] = make_int2(0, G);
         }
     }
-    // pair table: op q, thread t < H -> p0 | p1 << 8 (kNoPair past the op's pair count)
-    for (int w = tid; w < 2 * (G + 2) * H; w += NT) {
-        const int rev = w >= (G + 2) * H;
-        const int q = (w - (rev ? (G + 2) * H : 0)) / H, t = w % H;
+    // pair table: op q, pair t < H -> p0 | p1 << 8 (kNoPair past the op's pair count)
+    for (int w = tid; w < 2 * (G + kFastPad) * H; w += NT) {
+        const int rev = w >= (G + kFastPad) * H;
+        const int q = (w - (rev ? (G + kFastPad) * H : 0)) / H, t = w % H;
         uint32_t e = kNoPair;
         if (q < G) {
             const SmallOp o = pack_op(rev ? ka.rops[q] : a.ops[q]);
@@ -693,7 +893,7 @@ __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
         }
         (rev ? ptr : ptf)[q * H + t] = (uint16_t)e;
     }
-    for (int k = tid; k < 8; k += NT) {
+    for (int k = tid; k < 4 * kFastPad; k += NT) {
         matf[4 * G + k] = make_double2(0.0, 0.0);
         matr[4 * G + k] = make_double2(0.0, 0.0);
     }
@@ -726,49 +926,55 @@ __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
     }
     __syncthreads();
 
-    const bool mine = tid < D;  // this thread's amplitude b = tid
-    double b1t = 1.0, b2t = 1.0;  // beta1^t, beta2^t for Adam's bias corrections
-    for (int it = 0; it <= a.iters; ++it) {
-        // matrices in op order (forward U, reverse U^dagger) from the stored half-angle cos / sin
-        for (int w = tid; w < 2 * G; w += NT) {
-            const int rev = w >= G, q = rev ? w - G : w;
-            const int g = (rev ? rinf : finf)[q].y;
-            const GateDev gd = gdev[g];
-            const double2 c = gd.pidx >= 0 ? cs[gd.pidx] : fcs[g];
-            double2 m[4];
-            gate_matrix_cs(gd.kind, c.x, c.y, m);
-            double2 *dst = (rev ? matr : matf) + 4 * q;
-            if (rev) {
-                dst[0] = cconj(m[0]);
-                dst[1] = cconj(m[2]);
-                dst[2] = cconj(m[1]);
-                dst[3] = cconj(m[3]);
-            } else {
-                dst[0] = m[0];
-                dst[1] = m[1];
-                dst[2] = m[2];
-                dst[3] = m[3];
+    // the first iteration's matrices in op order (forward U, reverse
+    // U^dagger); afterwards the optimiser step rewrites the parametric ones.
+    // A rotation's 2x2 is A cos(a/2) + B sin(a/2) with constant A, B, kept
+    // per parametric gate for both directions (mab: A fwd, B fwd, A rev, B rev).
+    for (int w = tid; w < 2 * G; w += NT) {
+        const int rev = w >= G, q = rev ? w - G : w;
+        const int2 inf = (rev ? rinf : finf)[q];
+        const GateDev gd = gdev[inf.y];
+        const double2 c = gd.pidx >= 0 ? cs[gd.pidx] : fcs[inf.y];
+        double2 m[4], ma[4], mb[4];
+        gate_matrix_cs(gd.kind, c.x, c.y, m);
+        gate_matrix_cs(gd.kind, 1.0, 0.0, ma);
+        gate_matrix_cs(gd.kind, 0.0, 1.0, mb);
+        double2 *dst = (rev ? matr : matf) + 4 * q;
+        const int order[4] = {0, rev ? 2 : 1, rev ? 1 : 2, 3};  // U^dagger: transpose and conjugate
+        const int pg = (inf.x >> 8) - 1;
+        const bool rot = gd.kind == VQE_GATE_RX || gd.kind == VQE_GATE_RY || gd.kind == VQE_GATE_RZ ||
+                         gd.kind == VQE_GATE_SINGLE_EXC || gd.kind == VQE_GATE_DOUBLE_EXC;
+        double2 *ab = reinterpret_cast<double2 *>(smem + L.mab) + (pg >= 0 ? pg : 0) * 16 + (rev ? 8 : 0);
+        int2 *pq = reinterpret_cast<int2 *>(smem + L.pq);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double2 v = m[order[k]], va = ma[order[k]], vb = mb[order[k]];
+            dst[k] = rev ? cconj(v) : v;
+            if (pg >= 0) {
+                ab[k] = rev ? cconj(va) : va;
+                ab[4 + k] = rev ? cconj(vb) : vb;
             }
         }
-        if (mine) psi[tid] = make_double2(tid == (int)a.ref ? 1.0 : 0.0, 0.0);
-        __syncthreads();
+        if (pg >= 0) {  // a constant gate kind with a parameter keeps its matrix (q = -1: never rewritten)
+            if (rev)
+                pq[pg].y = rot ? q : -1;
+            else
+                pq[pg].x = rot ? q : -1;
+        }
+    }
+    __syncthreads();
 
-        // U(theta) e_ref, two register sets in turn (op q uses set q & 1)
-        {
-            uint32_t p0 = tid < H ? ptf[tid] : kNoPair, p1;
-            double2 u0[4] = {matf[0], matf[1], matf[2], matf[3]}, u1[4];
-            int q = 0;
-            for (; q + 1 < G; q += 2) {
-                fast_fwd_op(psi, ptf, matf, q + 1, H, D, p0, u0, p1, u1);
-                __syncthreads();
-                fast_fwd_op(psi, ptf, matf, q + 2, H, D, p1, u1, p0, u0);
-                __syncthreads();
-            }
-            if (q < G) {
-                fast_fwd_op(psi, ptf, matf, q + 1, H, D, p0, u0, p1, u1);
-                __syncthreads();
-            }
+    const bool mine = tid < D;  // this thread's amplitude b = tid in H psi
+    double b1t = 1.0, b2t = 1.0;  // beta1^t, beta2^t for Adam's bias corrections
+    const int2 *pq = reinterpret_cast<const int2 *>(smem + L.pq);
+    const double2 *mab = reinterpret_cast<const double2 *>(smem + L.mab);
+    for (int it = 0; it <= a.iters; ++it) {
+        if (wave == 0) {
+            for (int b = lane; b < D; b += 64) psi[b] = make_double2(b == (int)a.ref ? 1.0 : 0.0, 0.0);
+            wave_lds_sync();
+            fast_forward<SP>(psi, ptf, matf, finf, hist, G, H, D, lane);  // U(theta) e_ref
         }
+        __syncthreads();
 
         // lambda = H psi with the XOR-offset diagonals, eight interleaved
         // accumulators; this thread's part of E = Re <psi|lambda>
@@ -808,70 +1014,19 @@ __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
             break;
         }
 
-        // reverse sweep: g_l = Im <lambda|G_l|psi>, then U_l^dagger on both states;
-        // the reducing wave (no pairs) sums op q's partials while op q + 1 runs
-        if (redw) {
-            int prev = -1;
-            for (int q = 0; q < G; ++q) {
-                const int pg = (int)(ufirst((uint32_t)rinf[q].x) >> 8) - 1;
-                if (prev >= 0 && lane < 16) gsum[prev * 16 + lane] = row_part(gpart + (size_t)prev * H, H, lane);
-                prev = pg;
-                __syncthreads();
-            }
-            if (prev >= 0 && lane < 16) gsum[prev * 16 + lane] = row_part(gpart + (size_t)prev * H, H, lane);
-        } else {
-            uint32_t p0 = tid < H ? ptr[tid] : kNoPair, p1;
-            double2 u0[4] = {matr[0], matr[1], matr[2], matr[3]}, u1[4];
-            int code0 = rinf[0].x, code1;
-            int q = 0;
-            for (; q + 1 < G; q += 2) {
-                {
-                    const uint32_t cd = ufirst((uint32_t)code0);
-                    const int pg = (int)(cd >> 8) - 1;
-                    const double g = fast_rev_op(psi, lam, ptr, matr, rinf, q + 1, H, D, p0, (int)(cd & 15u), u0, p1, u1, code1);
-                    if (pg >= 0 && tid < H) gpart[pg * H + tid] = g;
-                }
-                __syncthreads();
-                {
-                    const uint32_t cd = ufirst((uint32_t)code1);
-                    const int pg = (int)(cd >> 8) - 1;
-                    const double g = fast_rev_op(psi, lam, ptr, matr, rinf, q + 2, H, D, p1, (int)(cd & 15u), u1, p0, u0, code0);
-                    if (pg >= 0 && tid < H) gpart[pg * H + tid] = g;
-                }
-                __syncthreads();
-            }
-            if (q < G) {
-                const uint32_t cd = ufirst((uint32_t)code0);
-                const int pg = (int)(cd >> 8) - 1;
-                const double g = fast_rev_op(psi, lam, ptr, matr, rinf, q + 1, H, D, p0, (int)(cd & 15u), u0, p1, u1, code1);
-                if (pg >= 0 && tid < H) gpart[pg * H + tid] = g;
-                __syncthreads();
-            }
-            if (!OVERLAP)
-                for (int w = tid; w < NPG * 16; w += NT) gsum[w] = row_part(gpart + (size_t)(w >> 4) * H, H, w & 15);
-        }
-        __syncthreads();
-        // the energy's sum (last wave) beside the optimiser step (other threads)
-        if (OVERLAP && redw) {
-            double sE = 0.0;
-            for (int t = lane; t < NT; t += 64) sE += epart[t];
-            sE = wave_sum(sE);
-            if (lane == 0) energies[it] = sE;
-        }
         b1t *= a.b1;
         b2t *= a.b2;
-        const double rc1 = 1.0 / (1.0 - b1t), rc2 = 1.0 / (1.0 - b2t);
-        constexpr int nopt = OVERLAP ? NT - 64 : NT;
-        if (!redw) {
-            for (int p = tid; p < P; p += nopt) {
+        if (wave == 0) {
+            // reverse sweep: g_l = Im <lambda|G_l|psi>, then U_l^dagger on both states
+            fast_reverse<SP>(lam, ptr, matr, rinf, hist, gpart, NPG, G, H, D, lane);
+            gate_sums(gpart, gsum, NPG, lane);
+            wave_lds_sync();
+            // optimiser step, then the next iteration's matrices of the
+            // parameter's gates
+            const double rc1 = 1.0 / (1.0 - b1t), rc2 = 1.0 / (1.0 - b2t);
+            for (int p = lane; p < P; p += 64) {
                 double gp = 0.0;
-                for (int e2 = poff[p]; e2 < poff[p + 1]; ++e2) {
-                    const double *gs = gsum + (size_t)pidx[e2] * 16;
-                    double s4[4];
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) s4[k] = (gs[k] + gs[k + 4]) + (gs[k + 8] + gs[k + 12]);
-                    gp += (s4[0] + s4[1]) + (s4[2] + s4[3]);
-                }
+                for (int e2 = poff[p]; e2 < poff[p + 1]; ++e2) gp += gsum[pidx[e2]];
                 double t = th[p];
                 if (a.opt == VQE_OPT_ADAM) {
                     const double mi = a.b1 * mom[p] + (1.0 - a.b1) * gp;
@@ -885,25 +1040,48 @@ __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
                 th[p] = t;
                 double sn, cn;
                 sincos(0.5 * t, &sn, &cn);
-                cs[p] = make_double2(cn, sn);
+                for (int e2 = poff[p]; e2 < poff[p + 1]; ++e2) {
+                    const int j = pidx[e2];
+                    const int2 qq = pq[j];
+                    const double2 *ab = mab + j * 16;
+                    if (qq.x >= 0)
+#pragma unroll
+                        for (int k = 0; k < 4; ++k)
+                            matf[4 * qq.x + k] = make_double2(fma(ab[k].x, cn, ab[4 + k].x * sn),
+                                                              fma(ab[k].y, cn, ab[4 + k].y * sn));
+                    if (qq.y >= 0)
+#pragma unroll
+                        for (int k = 0; k < 4; ++k)
+                            matr[4 * qq.y + k] = make_double2(fma(ab[8 + k].x, cn, ab[12 + k].x * sn),
+                                                              fma(ab[8 + k].y, cn, ab[12 + k].y * sn));
+                }
             }
+            if (NW == 1) {
+                const double sE = wave_sum_dpp(e);  // one wave: epart[tid] is this lane's e
+                if (lane == 0) energies[it] = sE;
+            }
+            wave_lds_sync();
+        } else if (wave == NW - 1) {
+            // the energy's sum beside the reverse sweep
+            double sE = 0.0;
+            for (int t = lane; t < NT; t += 64) sE += epart[t];
+            sE = wave_sum(sE);
+            if (lane == 0) energies[it] = sE;
         }
-        if (!OVERLAP) {
-            const double sE = wave_sum_dpp(epart[tid]);  // one wave: nothing to overlap with
-            if (tid == 0) energies[it] = sE;
-        }
-        __syncthreads();
     }
+    __syncthreads();
     for (int p = tid; p < P; p += NT) a.theta[(size_t)inst * P + p] = th[p];
 }
 
 constexpr size_t kSmallLdsMax = 160 * 1024 - 1024;
 constexpr int kSmallFast = 1 << 5;  // mode flag: k_small_fast
 
-inline void (*fast_kernel(int n, bool complex_tab))(SmallKernelArgs)
+inline void (*fast_kernel(int n, bool complex_tab, bool two_slots))(SmallKernelArgs)
 {
-    if (complex_tab) return n <= 6 ? k_small_fast<64, true> : (n == 7 ? k_small_fast<128, true> : k_small_fast<256, true>);
-    return n <= 6 ? k_small_fast<64, false> : (n == 7 ? k_small_fast<128, false> : k_small_fast<256, false>);
+    if (n <= 6) return complex_tab ? k_small_fast<64, 1, true> : k_small_fast<64, 1, false>;
+    if (n == 7) return complex_tab ? k_small_fast<128, 1, true> : k_small_fast<128, 1, false>;
+    if (two_slots) return complex_tab ? k_small_fast<256, 2, true> : k_small_fast<256, 2, false>;
+    return complex_tab ? k_small_fast<256, 1, true> : k_small_fast<256, 1, false>;
 }
 
 int choose_block(int n)
@@ -914,6 +1092,11 @@ int choose_block(int n)
 }
 
 }  // namespace
+
+size_t small_fast_hist_bytes(int n, int n_gates)
+{
+    return (size_t)(n_gates + 1) * fast_slots(n) * 128 * sizeof(double2);
+}
 
 // 1 if the persistent loop can run this problem; *mode_out gets the Hamiltonian form
 int small_run_plan(int n, int n_gates, int n_params, int n_pgates, int n_groups, int max_inst_terms,
@@ -945,7 +1128,7 @@ int small_run_plan(int n, int n_gates, int n_params, int n_pgates, int n_groups,
 }
 
 hipError_t launch_small_run(const SmallRunArgs &a, const OpDesc *rops, const int32_t *pmap_off,
-                            const int32_t *pmap_idx, int n_pgates, int mode, int max_inst_terms,
+                            const int32_t *pmap_idx, int n_pgates, int mode, int max_inst_terms, int max_pairs,
                             int64_t batch, hipStream_t s)
 {
     SmallKernelArgs ka;
@@ -960,7 +1143,7 @@ hipError_t launch_small_run(const SmallRunArgs &a, const OpDesc *rops, const int
     if (mode & kSmallFast) {
         const int nt = fast_threads(a.n);
         const FastLayout W = fast_layout(a.n, a.n_gates, a.n_params, n_pgates, a.n_groups, ka.mode == 2);
-        void (*kern)(SmallKernelArgs) = fast_kernel(a.n, ka.mode == 2);
+        void (*kern)(SmallKernelArgs) = fast_kernel(a.n, ka.mode == 2, max_pairs > 64);
         if (W.total > 65536) {
             hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)W.total);

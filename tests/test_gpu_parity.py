@@ -312,10 +312,12 @@ def test_errors_do_not_launch(vqe, ctx):
         vqe.energy(ctx, C, [H4, H4], dev(np.zeros((3, 1))))  # n_hams neither 1 nor B
 
 
-@pytest.mark.parametrize("n,T,L,iters", [(6, 40, 2, 25), (10, 300, 1, 6), (3, 20, 2, 30)])
+@pytest.mark.parametrize("n,T,L,iters", [(6, 40, 2, 25), (10, 300, 1, 6), (3, 20, 2, 30), (7, 60, 2, 15),
+                                           (8, 80, 2, 12)])
 def test_persistent_loop_hamiltonian_forms(vqe, ctx, n, T, L, iters):
-    # random strings carry imaginary phases (odd Y count): complex table at n = 3, 6;
-    # at n = 10 the diagonal table does not fit LDS and the term form runs
+    # random strings carry imaginary phases (odd Y count): complex table at n = 3, 6, 7, 8;
+    # at n = 10 the diagonal table does not fit LDS and the term form runs; at
+    # n = 8 a one-qubit gate has 128 pairs, two per lane of the gate wave
     _say("persistent forms", n, T, L, iters)
     spec = synth.hea_circuit(n, L)
     ham = synth.random_pauli_sum(n, min(T, 4 ** n - 1), seed=n)
