@@ -717,8 +717,7 @@ __device__ __forceinline__ void fast_rev_step(const FastOp<SP> &o, const FastHis
     wave_lds_sync();
 }
 
-// the forward chain U(theta) e_ref on one wave, two ops per trip (an odd G
-// ends on a harmless padding op)
+// the forward chain U(theta) e_ref on one wave, two ops per trip
 template <int SP>
 __device__ __forceinline__ void fast_forward(double2 *psi, const uint16_t *ptf, const double2 *matf,
                                              const int2 *finf, double2 *__restrict__ hist, int G, int H, int D,
@@ -730,6 +729,7 @@ __device__ __forceinline__ void fast_forward(double2 *psi, const uint16_t *ptf, 
     fast_op_read<SP>(A, psi, D, lane);
     for (int q = 0; q < G; q += 2) {
         fast_fwd_step<SP>(A, psi, hist, D, lane);
+        if (q + 1 >= G) break;
         fast_op_read<SP>(B, psi, D, lane);
         fast_op_load<SP>(A, ptf, matf, finf, q + 2, H, lane);
         fast_fwd_step<SP>(B, psi, hist, D, lane);
@@ -760,8 +760,9 @@ __device__ __forceinline__ void fast_rev_op(FastOp<SP> &cur, const FastHist<SP> 
     fast_op_load<SP>(cur, ptr, matr, rinf, qload, H, lane);
 }
 
-// the reverse chain on one wave, four ops per trip; the history of op q is
-// loaded four ops ahead (global memory latency), the tables two ops ahead
+// the reverse chain on one wave, four ops per trip (leaving after op G - 1);
+// the history of op q is loaded four ops ahead (global memory latency), the
+// tables two ops ahead
 template <int SP>
 __device__ __forceinline__ void fast_reverse(double2 *lam, const uint16_t *ptr, const double2 *matr, const int2 *rinf,
                                              const double2 *__restrict__ hist, double *gpart, int npg, int G, int H,
@@ -779,10 +780,13 @@ __device__ __forceinline__ void fast_reverse(double2 *lam, const uint16_t *ptr, 
     fast_op_read<SP>(A, lam, D, lane);
     for (int q = 0; q < G; q += 4) {
         fast_rev_op<SP>(A, H0, B, lam, gpart, ptr, matr, rinf, npg, q + 2, H, D, lane);
+        if (q + 1 >= G) break;
         fast_hist_load<SP>(H0, hist, rinf, min(q + 4, last), lane);
         fast_rev_op<SP>(B, H1, A, lam, gpart, ptr, matr, rinf, npg, q + 3, H, D, lane);
+        if (q + 2 >= G) break;
         fast_hist_load<SP>(H1, hist, rinf, min(q + 5, last), lane);
         fast_rev_op<SP>(A, H2, B, lam, gpart, ptr, matr, rinf, npg, min(q + 4, last), H, D, lane);
+        if (q + 3 >= G) break;
         fast_hist_load<SP>(H2, hist, rinf, min(q + 6, last), lane);
         fast_rev_op<SP>(B, H3, A, lam, gpart, ptr, matr, rinf, npg, min(q + 5, last), H, D, lane);
         fast_hist_load<SP>(H3, hist, rinf, min(q + 7, last), lane);
