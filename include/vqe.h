@@ -223,8 +223,10 @@ int vqe_circ_destroy(vqe_circ_t circ);
 /* Bytes of device workspace that vqe_energy (want_grad = 0),
  * vqe_energy_grad (want_grad = 1), vqe_run (want_grad = 2) or
  * vqe_grad_shift (want_grad = 3) needs for `batch` instances: the state, the
- * adjoint state lambda = H psi, and small per-launch tables.  A state is
- * batch * 2^n * 16 bytes. */
+ * adjoint state lambda = H psi, and small per-launch tables; for vqe_run on
+ * states of at most 8 qubits also the persistent loop's history of the
+ * state on every gate's pairs, (gates + 1) * 4 KB per instance at 8 qubits
+ * (2 KB below).  A state is batch * 2^n * 16 bytes. */
 int vqe_workspace_bytes(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams,
                         int64_t batch, int want_grad, size_t *bytes);
 
@@ -299,8 +301,10 @@ int vqe_adam_step(vqe_ctx_t ctx, int64_t batch, int32_t n_params, double *theta,
  * with step lr), each on the adjoint gradient at the current theta.
  * energies: device float64 [batch][iters + 1]: the energy before each step,
  * then the energy at the final theta.  Small states run the whole loop in
- * one persistent launch; larger ones loop over vqe_energy_grad-style
- * launches on the stream.  workspace: at least
+ * one persistent launch (one workgroup per instance; the workspace keeps
+ * the state on each gate's pairs after the forward sweep for the reverse
+ * sweep, so calls that overlap on one workspace race); larger ones loop over
+ * vqe_energy_grad-style launches on the stream.  workspace: at least
  * vqe_workspace_bytes(..., want_grad = 2). */
 int vqe_run(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams, int64_t batch,
             uint64_t ref_index, double *theta, int32_t iters, int32_t optimizer, double lr,
