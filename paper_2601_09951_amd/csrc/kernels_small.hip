@@ -760,36 +760,32 @@ __device__ __forceinline__ void fast_rev_op(FastOp<SP> &cur, const FastHist<SP> 
     fast_op_load<SP>(cur, ptr, matr, rinf, qload, H, lane);
 }
 
-// the reverse chain on one wave, four ops per trip (leaving after op G - 1);
-// the history of op q is loaded four ops ahead (global memory latency), the
-// tables two ops ahead
+// the reverse chain on one wave (leaving after op G - 1); the history of op
+// q is loaded kHistAhead ops ahead (a global-memory round trip spans
+// several ops), the tables two ops ahead
+constexpr int kHistAhead = 8;
+
 template <int SP>
 __device__ __forceinline__ void fast_reverse(double2 *lam, const uint16_t *ptr, const double2 *matr, const int2 *rinf,
                                              const double2 *__restrict__ hist, double *gpart, int npg, int G, int H,
                                              int D, int lane)
 {
-    FastOp<SP> A, B;
-    FastHist<SP> H0, H1, H2, H3;
+    FastOp<SP> ops[2];
+    FastHist<SP> hs[kHistAhead];
     const int last = G + kFastPad - 1;
-    fast_op_load<SP>(A, ptr, matr, rinf, 0, H, lane);
-    fast_op_load<SP>(B, ptr, matr, rinf, 1, H, lane);
-    fast_hist_load<SP>(H0, hist, rinf, 0, lane);
-    fast_hist_load<SP>(H1, hist, rinf, 1, lane);
-    fast_hist_load<SP>(H2, hist, rinf, 2, lane);
-    fast_hist_load<SP>(H3, hist, rinf, 3, lane);
-    fast_op_read<SP>(A, lam, D, lane);
-    for (int q = 0; q < G; q += 4) {
-        fast_rev_op<SP>(A, H0, B, lam, gpart, ptr, matr, rinf, npg, q + 2, H, D, lane);
-        if (q + 1 >= G) break;
-        fast_hist_load<SP>(H0, hist, rinf, min(q + 4, last), lane);
-        fast_rev_op<SP>(B, H1, A, lam, gpart, ptr, matr, rinf, npg, q + 3, H, D, lane);
-        if (q + 2 >= G) break;
-        fast_hist_load<SP>(H1, hist, rinf, min(q + 5, last), lane);
-        fast_rev_op<SP>(A, H2, B, lam, gpart, ptr, matr, rinf, npg, min(q + 4, last), H, D, lane);
-        if (q + 3 >= G) break;
-        fast_hist_load<SP>(H2, hist, rinf, min(q + 6, last), lane);
-        fast_rev_op<SP>(B, H3, A, lam, gpart, ptr, matr, rinf, npg, min(q + 5, last), H, D, lane);
-        fast_hist_load<SP>(H3, hist, rinf, min(q + 7, last), lane);
+    fast_op_load<SP>(ops[0], ptr, matr, rinf, 0, H, lane);
+    fast_op_load<SP>(ops[1], ptr, matr, rinf, 1, H, lane);
+#pragma unroll
+    for (int j = 0; j < kHistAhead; ++j) fast_hist_load<SP>(hs[j], hist, rinf, min(j, last), lane);
+    fast_op_read<SP>(ops[0], lam, D, lane);
+    for (int q = 0; q < G; q += kHistAhead) {
+#pragma unroll
+        for (int j = 0; j < kHistAhead; ++j) {
+            fast_rev_op<SP>(ops[j & 1], hs[j], ops[(j + 1) & 1], lam, gpart, ptr, matr, rinf, npg,
+                            min(q + j + 2, last), H, D, lane);
+            if (q + j + 1 >= G) break;
+            fast_hist_load<SP>(hs[j], hist, rinf, min(q + j + kHistAhead, last), lane);
+        }
     }
 }
 
@@ -1029,8 +1025,16 @@ __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
             // parameter's gates
             const double rc1 = 1.0 / (1.0 - b1t), rc2 = 1.0 / (1.0 - b2t);
             for (int p = lane; p < P; p += 64) {
+                const int e0 = poff[p], e1 = poff[p + 1];
+                // the parameter's first gate: its op slots and matrix coefficients,
+                // read before the update so they land during its arithmetic
+                const int j0 = e0 < e1 ? pidx[e0] : 0;  // row 0 exists (at least one is laid out)
+                const int2 q0 = pq[j0];
+                double2 ab[16];
+#pragma unroll
+                for (int k = 0; k < 16; ++k) ab[k] = mab[j0 * 16 + k];
                 double gp = 0.0;
-                for (int e2 = poff[p]; e2 < poff[p + 1]; ++e2) gp += gsum[pidx[e2]];
+                for (int e2 = e0; e2 < e1; ++e2) gp += gsum[pidx[e2]];
                 double t = th[p];
                 if (a.opt == VQE_OPT_ADAM) {
                     const double mi = a.b1 * mom[p] + (1.0 - a.b1) * gp;
@@ -1044,20 +1048,32 @@ __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
                 th[p] = t;
                 double sn, cn;
                 sincos(0.5 * t, &sn, &cn);
-                for (int e2 = poff[p]; e2 < poff[p + 1]; ++e2) {
+                if (e0 < e1) {
+                    if (q0.x >= 0)
+#pragma unroll
+                        for (int k = 0; k < 4; ++k)
+                            matf[4 * q0.x + k] = make_double2(fma(ab[k].x, cn, ab[4 + k].x * sn),
+                                                              fma(ab[k].y, cn, ab[4 + k].y * sn));
+                    if (q0.y >= 0)
+#pragma unroll
+                        for (int k = 0; k < 4; ++k)
+                            matr[4 * q0.y + k] = make_double2(fma(ab[8 + k].x, cn, ab[12 + k].x * sn),
+                                                              fma(ab[8 + k].y, cn, ab[12 + k].y * sn));
+                }
+                for (int e2 = e0 + 1; e2 < e1; ++e2) {  // further gates sharing the parameter
                     const int j = pidx[e2];
                     const int2 qq = pq[j];
-                    const double2 *ab = mab + j * 16;
+                    const double2 *abj = mab + j * 16;
                     if (qq.x >= 0)
 #pragma unroll
                         for (int k = 0; k < 4; ++k)
-                            matf[4 * qq.x + k] = make_double2(fma(ab[k].x, cn, ab[4 + k].x * sn),
-                                                              fma(ab[k].y, cn, ab[4 + k].y * sn));
+                            matf[4 * qq.x + k] = make_double2(fma(abj[k].x, cn, abj[4 + k].x * sn),
+                                                              fma(abj[k].y, cn, abj[4 + k].y * sn));
                     if (qq.y >= 0)
 #pragma unroll
                         for (int k = 0; k < 4; ++k)
-                            matr[4 * qq.y + k] = make_double2(fma(ab[8 + k].x, cn, ab[12 + k].x * sn),
-                                                              fma(ab[8 + k].y, cn, ab[12 + k].y * sn));
+                            matr[4 * qq.y + k] = make_double2(fma(abj[8 + k].x, cn, abj[12 + k].x * sn),
+                                                              fma(abj[8 + k].y, cn, abj[12 + k].y * sn));
                 }
             }
             if (NW == 1) {
