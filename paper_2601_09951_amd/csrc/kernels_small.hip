@@ -525,6 +525,9 @@ constexpr int kFastPad = 4;
 
 __host__ __device__ inline int fast_threads(int n) { return n <= 6 ? 64 : (1 << n); }
 
+// entries per op in the pair tables: the pair count 2^n / 2, at least 64
+__host__ __device__ inline int fast_row(int n) { return n >= 8 ? (1 << (n - 1)) : 64; }
+
 __host__ __device__ inline FastLayout fast_layout(int n, int G, int P, int NPG, int NG, int complex_tab)
 {
     FastLayout L;
@@ -551,8 +554,8 @@ __host__ __device__ inline FastLayout fast_layout(int n, int G, int P, int NPG, 
     L.epart = take(8 * nt, 8);
     L.finf = take((size_t)8 * (G + kFastPad), 8);  // {gen | (pgate + 1) << 8, gate} per op
     L.rinf = take((size_t)8 * (G + kFastPad), 8);
-    L.ptf = take(2 * (size_t)(G + kFastPad) * H, 4);  // pairs live on threads t < H
-    L.ptr = take(2 * (size_t)(G + kFastPad) * H, 4);
+    L.ptf = take(2 * (size_t)(G + kFastPad) * fast_row(n), 4);  // pair t of op q at [q][t]
+    L.ptr = take(2 * (size_t)(G + kFastPad) * fast_row(n), 4);
     L.pq = take((size_t)8 * npg, 8);            // per parametric gate: forward and reverse op
     L.mab = take((size_t)256 * npg, 16);        // per parametric gate: U = A cos + B sin, forward and reverse
     L.gdev = take(sizeof(GateDev) * G, 16);
@@ -589,17 +592,16 @@ __device__ __forceinline__ void wave_lds_sync()
 
 // op q's pair entries of this lane (pairs lane + 64 s, kNoPair past the op's
 // pair count) and its matrix; ops G and G + 1 are padding (no pairs, zero
-// matrices), so the prefetch of op q + 1 needs no branch
+// op q's pair entries of this lane (pairs lane + 64 s; the rows are padded
+// to at least 64 entries with kNoPair, so no lane needs a bound) and its
+// matrix; ops G.. are padding (no pairs, zero matrices), so the prefetch of
+// later ops needs no branch
 template <int SP>
-__device__ __forceinline__ void fast_tables(const uint16_t *pt, const double2 *mat, int q, int H, int lane,
+__device__ __forceinline__ void fast_tables(const uint16_t *pt, const double2 *mat, int q, int HP, int lane,
                                             uint32_t (&pe)[SP], double2 (&u)[4])
 {
 #pragma unroll
-    for (int s = 0; s < SP; ++s) {
-        const int t = lane + 64 * s;
-        const uint32_t e = pt[q * H + (t < H ? t : H - 1)];  // unconditional read, then select
-        pe[s] = t < H ? e : kNoPair;
-    }
+    for (int s = 0; s < SP; ++s) pe[s] = pt[q * HP + lane + 64 * s];
 #pragma unroll
     for (int k = 0; k < 4; ++k) u[k] = mat[4 * q + k];
 }
@@ -644,9 +646,9 @@ struct FastHist {
 
 template <int SP>
 __device__ __forceinline__ void fast_op_load(FastOp<SP> &o, const uint16_t *pt, const double2 *mat, const int2 *inf,
-                                             int q, int H, int lane)
+                                             int q, int HP, int lane)
 {
-    fast_tables<SP>(pt, mat, q, H, lane, o.pe, o.u);
+    fast_tables<SP>(pt, mat, q, HP, lane, o.pe, o.u);
     o.info = inf[q];
 }
 
@@ -720,29 +722,33 @@ __device__ __forceinline__ void fast_rev_step(const FastOp<SP> &o, const FastHis
 // the forward chain U(theta) e_ref on one wave, two ops per trip
 template <int SP>
 __device__ __forceinline__ void fast_forward(double2 *psi, const uint16_t *ptf, const double2 *matf,
-                                             const int2 *finf, double2 *__restrict__ hist, int G, int H, int D,
+                                             const int2 *finf, double2 *__restrict__ hist, int G, int HP, int D,
                                              int lane)
 {
     FastOp<SP> A, B;
-    fast_op_load<SP>(A, ptf, matf, finf, 0, H, lane);
-    fast_op_load<SP>(B, ptf, matf, finf, 1, H, lane);
+    fast_op_load<SP>(A, ptf, matf, finf, 0, HP, lane);
+    fast_op_load<SP>(B, ptf, matf, finf, 1, HP, lane);
     fast_op_read<SP>(A, psi, D, lane);
     for (int q = 0; q < G; q += 2) {
         fast_fwd_step<SP>(A, psi, hist, D, lane);
         if (q + 1 >= G) break;
         fast_op_read<SP>(B, psi, D, lane);
-        fast_op_load<SP>(A, ptf, matf, finf, q + 2, H, lane);
+        fast_op_load<SP>(A, ptf, matf, finf, q + 2, HP, lane);
         fast_fwd_step<SP>(B, psi, hist, D, lane);
         fast_op_read<SP>(A, psi, D, lane);
-        fast_op_load<SP>(B, ptf, matf, finf, q + 3, H, lane);
+        fast_op_load<SP>(B, ptf, matf, finf, q + 3, HP, lane);
     }
 }
 
+// the history of reverse op q: gate G - 1 - q (the host checks that the
+// reverse plan lists the gates in exactly that order), padding ops read the
+// spare row G; no table read, so the load's address is ready at once
 template <int SP>
-__device__ __forceinline__ void fast_hist_load(FastHist<SP> &h, const double2 *__restrict__ hist, const int2 *inf,
-                                               int q, int lane)
+__device__ __forceinline__ void fast_hist_load(FastHist<SP> &h, const double2 *__restrict__ hist, int G, int q,
+                                               int lane)
 {
-    const double2 *hq = hist + (size_t)ufirst((uint32_t)inf[q].y) * (SP * 128) + 2 * lane;
+    const int gate = q < G ? G - 1 - q : G;
+    const double2 *hq = hist + (size_t)gate * (SP * 128) + 2 * lane;
 #pragma unroll
     for (int s = 0; s < SP; ++s) {
         h.hx[s] = hq[128 * s];
@@ -753,11 +759,11 @@ __device__ __forceinline__ void fast_hist_load(FastHist<SP> &h, const double2 *_
 template <int SP>
 __device__ __forceinline__ void fast_rev_op(FastOp<SP> &cur, const FastHist<SP> &h, FastOp<SP> &nxt, double2 *lam,
                                             double *gpart, const uint16_t *ptr, const double2 *matr,
-                                            const int2 *rinf, int npg, int qload, int H, int D, int lane)
+                                            const int2 *rinf, int npg, int qload, int HP, int D, int lane)
 {
     fast_rev_step<SP>(cur, h, lam, gpart, npg, D, lane);
     fast_op_read<SP>(nxt, lam, D, lane);
-    fast_op_load<SP>(cur, ptr, matr, rinf, qload, H, lane);
+    fast_op_load<SP>(cur, ptr, matr, rinf, qload, HP, lane);
 }
 
 // the reverse chain on one wave (leaving after op G - 1); the history of op
@@ -767,24 +773,24 @@ constexpr int kHistAhead = 8;
 
 template <int SP>
 __device__ __forceinline__ void fast_reverse(double2 *lam, const uint16_t *ptr, const double2 *matr, const int2 *rinf,
-                                             const double2 *__restrict__ hist, double *gpart, int npg, int G, int H,
+                                             const double2 *__restrict__ hist, double *gpart, int npg, int G, int HP,
                                              int D, int lane)
 {
     FastOp<SP> ops[2];
     FastHist<SP> hs[kHistAhead];
     const int last = G + kFastPad - 1;
-    fast_op_load<SP>(ops[0], ptr, matr, rinf, 0, H, lane);
-    fast_op_load<SP>(ops[1], ptr, matr, rinf, 1, H, lane);
+    fast_op_load<SP>(ops[0], ptr, matr, rinf, 0, HP, lane);
+    fast_op_load<SP>(ops[1], ptr, matr, rinf, 1, HP, lane);
 #pragma unroll
-    for (int j = 0; j < kHistAhead; ++j) fast_hist_load<SP>(hs[j], hist, rinf, min(j, last), lane);
+    for (int j = 0; j < kHistAhead; ++j) fast_hist_load<SP>(hs[j], hist, G, j, lane);
     fast_op_read<SP>(ops[0], lam, D, lane);
     for (int q = 0; q < G; q += kHistAhead) {
 #pragma unroll
         for (int j = 0; j < kHistAhead; ++j) {
             fast_rev_op<SP>(ops[j & 1], hs[j], ops[(j + 1) & 1], lam, gpart, ptr, matr, rinf, npg,
-                            min(q + j + 2, last), H, D, lane);
+                            min(q + j + 2, last), HP, D, lane);
             if (q + j + 1 >= G) break;
-            fast_hist_load<SP>(hs[j], hist, rinf, min(q + j + kHistAhead, last), lane);
+            fast_hist_load<SP>(hs[j], hist, G, q + j + kHistAhead, lane);
         }
     }
 }
@@ -847,7 +853,7 @@ __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int inst = blockIdx.x;
-    const int D = 1 << a.n, H = D > 1 ? D / 2 : 1;
+    const int D = 1 << a.n, HP = fast_row(a.n);
     const int G = a.n_gates, P = a.n_params, NG = a.n_groups, NG8 = (NG + 7) / 8 * 8, NPG = ka.n_pgates;
     const int32_t *to = a.toff + (size_t)(a.shared_ham ? 0 : inst) * NG * 3;
     double *energies = a.energies + (size_t)inst * (a.iters + 1);
@@ -879,10 +885,10 @@ __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
             finf[q] = rinf[q] = make_int2(0, G);
         }
     }
-    // pair table: op q, pair t < H -> p0 | p1 << 8 (kNoPair past the op's pair count)
-    for (int w = tid; w < 2 * (G + kFastPad) * H; w += NT) {
-        const int rev = w >= (G + kFastPad) * H;
-        const int q = (w - (rev ? (G + kFastPad) * H : 0)) / H, t = w % H;
+    // pair table: op q, pair t -> p0 | p1 << 8 (kNoPair past the op's pair count)
+    for (int w = tid; w < 2 * (G + kFastPad) * HP; w += NT) {
+        const int rev = w >= (G + kFastPad) * HP;
+        const int q = (w - (rev ? (G + kFastPad) * HP : 0)) / HP, t = w % HP;
         uint32_t e = kNoPair;
         if (q < G) {
             const SmallOp o = pack_op(rev ? ka.rops[q] : a.ops[q]);
@@ -891,7 +897,7 @@ __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
                 e = p0 | ((p0 ^ o.m) << 8);
             }
         }
-        (rev ? ptr : ptf)[q * H + t] = (uint16_t)e;
+        (rev ? ptr : ptf)[q * HP + t] = (uint16_t)e;
     }
     for (int k = tid; k < 4 * kFastPad; k += NT) {
         matf[4 * G + k] = make_double2(0.0, 0.0);
@@ -972,7 +978,7 @@ __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
         if (wave == 0) {
             for (int b = lane; b < D; b += 64) psi[b] = make_double2(b == (int)a.ref ? 1.0 : 0.0, 0.0);
             wave_lds_sync();
-            fast_forward<SP>(psi, ptf, matf, finf, hist, G, H, D, lane);  // U(theta) e_ref
+            fast_forward<SP>(psi, ptf, matf, finf, hist, G, HP, D, lane);  // U(theta) e_ref
         }
         __syncthreads();
 
@@ -1018,7 +1024,7 @@ __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
         b2t *= a.b2;
         if (wave == 0) {
             // reverse sweep: g_l = Im <lambda|G_l|psi>, then U_l^dagger on both states
-            fast_reverse<SP>(lam, ptr, matr, rinf, hist, gpart, NPG, G, H, D, lane);
+            fast_reverse<SP>(lam, ptr, matr, rinf, hist, gpart, NPG, G, HP, D, lane);
             gate_sums(gpart, gsum, NPG, lane);
             wave_lds_sync();
             // optimiser step, then the next iteration's matrices of the
