@@ -508,7 +508,8 @@ __global__ __launch_bounds__(256) void k_small_run(SmallKernelArgs ka)
 //    lambda is carried back;
 //  * the optimiser step writes the next iteration's matrices of each
 //    parameter's gates directly (U = A cos(a/2) + B sin(a/2) with A, B
-//    tabulated per parametric gate); constant gates keep theirs;
+//    tabulated per parametric gate; cos and sin by rotating the stored pair
+//    through the half step); constant gates keep theirs;
 //  * lambda = H psi uses eight interleaved accumulators, one amplitude per
 //    thread;
 //  * a gate's gradient partials go to an LDS row per parametric gate, one
@@ -1041,7 +1042,9 @@ __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
                 for (int k = 0; k < 16; ++k) ab[k] = mab[j0 * 16 + k];
                 double gp = 0.0;
                 for (int e2 = e0; e2 < e1; ++e2) gp += gsum[pidx[e2]];
-                double t = th[p];
+                const double t0 = th[p];
+                const double2 c0 = cs[p];
+                double t = t0;
                 if (a.opt == VQE_OPT_ADAM) {
                     const double mi = a.b1 * mom[p] + (1.0 - a.b1) * gp;
                     const double vi = a.b2 * vel[p] + (1.0 - a.b2) * gp * gp;
@@ -1052,8 +1055,22 @@ __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
                     t -= a.lr * gp;
                 }
                 th[p] = t;
+                // cos and sin of the new half angle: the old pair rotated by
+                // the half step d (|d| < 1/16: Taylor series to d^9, error
+                // below 1e-19), else from scratch
+                const double d = 0.5 * (t - t0);
                 double sn, cn;
-                sincos(0.5 * t, &sn, &cn);
+                if (fabs(d) < 0.0625) {
+                    const double d2 = d * d;
+                    const double cd = fma(d2, fma(d2, fma(d2, fma(d2, 1.0 / 40320, -1.0 / 720), 1.0 / 24), -0.5), 1.0);
+                    const double sd =
+                        d * fma(d2, fma(d2, fma(d2, fma(d2, 1.0 / 362880, -1.0 / 5040), 1.0 / 120), -1.0 / 6), 1.0);
+                    cn = fma(c0.x, cd, -c0.y * sd);
+                    sn = fma(c0.y, cd, c0.x * sd);
+                } else {
+                    sincos(0.5 * t, &sn, &cn);
+                }
+                cs[p] = make_double2(cn, sn);
                 if (e0 < e1) {
                     if (q0.x >= 0)
 #pragma unroll
