@@ -591,8 +591,6 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// op q's pair entries of this lane (pairs lane + 64 s, kNoPair past the op's
-// pair count) and its matrix; ops G and G + 1 are padding (no pairs, zero
 // op q's pair entries of this lane (pairs lane + 64 s; the rows are padded
 // to at least 64 entries with kNoPair, so no lane needs a bound) and its
 // matrix; ops G.. are padding (no pairs, zero matrices), so the prefetch of
@@ -624,9 +622,9 @@ constexpr int kTwoSlots = 16;
 __host__ __device__ constexpr int fast_slots(int n) { return n >= 8 ? 2 : 1; }
 
 // One gate op as the gate wave sees it: the lane's pair table entries, the
-// op's matrix and info word, the state values read on the lane's pairs and
-// (reverse sweep) psi on those pairs after the gate, from the forward
-// history.  The chains below alternate two of these buffers over the ops
+// op's matrix and info word and the state values read on the lane's pairs
+// (psi after the gate, which the reverse sweep needs, comes separately from
+// the forward history).  The chains below alternate two of these buffers over the ops
 // (op q in buffer q & 1): while op q computes, the pairs of op q + 1 are
 // already read and the tables of op q + 2 are on their way, so each op costs
 // one LDS read latency plus its arithmetic, and no value is moved between
