@@ -226,9 +226,9 @@ def main():
     flops_eval = eval_flops(p8["spec"], n_groups, complex_table)
     flops_launch = flops_eval * BATCH * ITERS
     achieved = flops_launch / (kernel_ms[8] * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": "k_small_fast, 8 qubits (256 threads per instance, 100 instances x 200 "
-                                          "steps in one launch; the event interval also holds the weight refresh, "
-                                          "< 0.2 %)",
+    roofline = {"bound": "alu", "kernel": "k_small_fast, 8 qubits (one workgroup of 320 threads per instance: a gate "
+                                          "wave and four H psi waves; 100 instances x 200 steps in one launch; the "
+                                          "event interval also holds the weight refresh, < 0.2 %)",
                 "achieved": round(achieved, 4), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP64_PEAK_TFLOPS, 5),
                 "traffic": measured_traffic("k_small_fast"),

@@ -511,7 +511,10 @@ __global__ __launch_bounds__(256) void k_small_run(SmallKernelArgs ka)
 //    tabulated per parametric gate; cos and sin by rotating the stored pair
 //    through the half step); constant gates keep theirs;
 //  * lambda = H psi uses eight interleaved accumulators, one amplitude per
-//    thread;
+//    thread; at 8 qubits with a real Hamiltonian of at most 64 flip groups
+//    (and gates of at most 64 pairs) four extra waves do it, each thread
+//    holding its amplitude's row of the table in registers for the whole
+//    launch, so only psi is read from LDS;
 //  * a gate's gradient partials go to an LDS row per parametric gate, one
 //    per lane, summed in fixed order after the sweep; with several waves
 //    the last one sums the energy during the reverse sweep.
@@ -529,10 +532,11 @@ __host__ __device__ inline int fast_threads(int n) { return n <= 6 ? 64 : (1 << 
 // entries per op in the pair tables: the pair count 2^n / 2, at least 64
 __host__ __device__ inline int fast_row(int n) { return n >= 8 ? (1 << (n - 1)) : 64; }
 
-__host__ __device__ inline FastLayout fast_layout(int n, int G, int P, int NPG, int NG, int complex_tab)
+__host__ __device__ inline FastLayout fast_layout(int n, int G, int P, int NPG, int NG, int complex_tab,
+                                                  bool regtab = false)
 {
     FastLayout L;
-    const size_t D = (size_t)1 << n, H = D / 2 > 0 ? D / 2 : 1, nt = (size_t)fast_threads(n);
+    const size_t D = (size_t)1 << n, H = D / 2 > 0 ? D / 2 : 1, nt = (size_t)fast_threads(n) + (regtab ? 64 : 0);
     const size_t npg = NPG > 0 ? NPG : 1;
     size_t o = 0;
     auto take = [&](size_t bytes, size_t align) {
@@ -551,7 +555,7 @@ __host__ __device__ inline FastLayout fast_layout(int n, int G, int P, int NPG, 
     L.mom = take((size_t)8 * P, 8);
     L.vel = take((size_t)8 * P, 8);
     L.gpart = take((size_t)8 * 64 * (npg + 1), 16);  // per parametric gate (+ a spare row), one partial per lane
-    L.gsum = take((size_t)8 * (npg > 4 ? npg : 4), 8);  // one sum per parametric gate (4: block sum scratch)
+    L.gsum = take((size_t)8 * (npg > 8 ? npg : 8), 8);  // one sum per parametric gate (8: block sum scratch)
     L.epart = take(8 * nt, 8);
     L.finf = take((size_t)8 * (G + kFastPad), 8);  // {gen | (pgate + 1) << 8, gate} per op
     L.rinf = take((size_t)8 * (G + kFastPad), 8);
@@ -564,9 +568,20 @@ __host__ __device__ inline FastLayout fast_layout(int n, int G, int P, int NPG, 
     L.pidx = take((size_t)4 * npg, 4);
     const size_t ng8 = (size_t)(NG + 7) / 8 * 8;  // groups padded with zero diagonals
     L.gf = take(4 * ng8, 16);
-    L.tab = take((complex_tab ? 16 : 8) * ng8 * D, 16);
+    L.tab = take(regtab ? 0 : (complex_tab ? 16 : 8) * ng8 * D, 16);  // in registers with regtab
     L.total = o;
     return L;
+}
+
+// Register-held Hamiltonian rows: at 8 qubits with a real table of at most
+// kRegGroups flip groups and at most 64 pairs per gate, one wave runs the
+// gate chains and four more waves run H psi, each thread keeping its amplitude's diagonal entries for all
+// groups in registers for the whole launch, so H psi reads only psi from LDS.
+constexpr int kRegGroups = 64;
+
+__host__ __device__ inline bool fast_regtab(int n, int NG, int complex_tab)
+{
+    return n == 8 && !complex_tab && NG <= kRegGroups;
 }
 
 __device__ __forceinline__ uint32_t ufirst(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -819,14 +834,17 @@ __device__ __forceinline__ void gate_sums(const double *gpart, double *gsum, int
 
 // SP: pair slots per lane of the gate wave, 2 only when some op has more
 // pairs than lanes (one-qubit gates at 8 qubits)
-template <int NT, int SP, bool CT>
+// RT: the register-held Hamiltonian rows (NT = 320: the gate wave, then
+// four waves for H psi with one amplitude per thread)
+template <int NT, int SP, bool CT, bool RT>
 __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
 {
     constexpr int NW = NT / 64;
-    static_assert(SP == 1 || (SP == 2 && NT == 256), "pair slots per lane");
+    static_assert(SP == 1 || (SP == 2 && NT >= 256), "pair slots per lane");
+    static_assert(!RT || (NT == 320 && !CT), "register rows: 8 qubits, real table");
     extern __shared__ __align__(16) unsigned char smem[];
     const SmallRunArgs &a = ka.a;
-    const FastLayout L = fast_layout(a.n, a.n_gates, a.n_params, ka.n_pgates, a.n_groups, CT);
+    const FastLayout L = fast_layout(a.n, a.n_gates, a.n_params, ka.n_pgates, a.n_groups, CT, RT);
     double2 *psi = reinterpret_cast<double2 *>(smem + L.psi);
     double2 *lam = reinterpret_cast<double2 *>(smem + L.lam);
     double2 *matf = reinterpret_cast<double2 *>(smem + L.matf);
@@ -907,7 +925,7 @@ __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
     for (int g = tid; g < NG8; g += NT) gf[g] = g < NG ? a.groups[g].floc : 0u;
     __syncthreads();
     // D_g[b] = sum_t kappa_t (-1)^{z_t . (b ^ f_g)}; zero rows pad the groups
-    for (int i = tid; i < NG8 * D; i += NT) {
+    for (int i = tid; i < (RT ? 0 : NG8 * D); i += NT) {
         const int g = i >> a.n;
         const uint32_t b = (uint32_t)(i & (D - 1));
         double re = 0.0, im = 0.0;
@@ -969,7 +987,69 @@ __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
     }
     __syncthreads();
 
-    const bool mine = tid < D;  // this thread's amplitude b = tid in H psi
+    if (RT && wave >= 1) {
+        // H psi waves: amplitude b's diagonal entries of every group in
+        // registers (groups past NG are zero), then per iteration the same
+        // barriers as the gate wave's loop
+        const uint32_t b = (uint32_t)(tid - 64);
+        double tv[kRegGroups];
+#pragma unroll
+        for (int g = 0; g < kRegGroups; ++g) {
+            double re = 0.0;
+            if (g < NG) {
+                const int ug = a.groups[g].ugroup;
+                const int tb = to[ug * 3], tm = to[ug * 3 + 1];
+                const uint32_t bb = b ^ gf[g];
+                for (int t = tb; t < tm; ++t) {
+                    const TermDev d = a.terms[t];
+                    re += (__popc(d.zloc & bb) & 1) ? -d.w : d.w;
+                }
+            }
+            tv[g] = re;
+        }
+        for (int it = 0; it <= a.iters; ++it) {
+            __syncthreads();  // psi is final
+            double2 sacc[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) sacc[k] = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int g = 0; g < kRegGroups; g += 8) {
+                if (g < NG) {  // wave-uniform: whole blocks of eight, zero rows pad the last
+                    const uint4 fa = *reinterpret_cast<const uint4 *>(gf + g);
+                    const uint4 fb = *reinterpret_cast<const uint4 *>(gf + g + 4);
+                    const uint32_t fk[8] = {fa.x, fa.y, fa.z, fa.w, fb.x, fb.y, fb.z, fb.w};
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        const double2 x = psi[b ^ fk[k]];
+                        sacc[k].x = fma(tv[g + k], x.x, sacc[k].x);
+                        sacc[k].y = fma(tv[g + k], x.y, sacc[k].y);
+                    }
+                }
+            }
+            const double2 acc = cadd(cadd(cadd(sacc[0], sacc[1]), cadd(sacc[2], sacc[3])),
+                                     cadd(cadd(sacc[4], sacc[5]), cadd(sacc[6], sacc[7])));
+            lam[b] = acc;
+            const double2 x = psi[b];
+            const double e = x.x * acc.x + x.y * acc.y;
+            epart[b] = e;
+            __syncthreads();  // lambda is final
+            if (it == a.iters) {
+                const double sE = block_sum_all(e, gsum);
+                (void)sE;
+                break;
+            }
+            if (wave == NW - 1) {  // the energy's sum beside the reverse sweep
+                double sE = 0.0;
+                for (int t = lane; t < D; t += 64) sE += epart[t];
+                sE = wave_sum(sE);
+                if (lane == 0) energies[it] = sE;
+            }
+        }
+        __syncthreads();
+        return;
+    }
+
+    const bool mine = !RT && tid < D;  // this thread's amplitude b = tid in H psi
     double b1t = 1.0, b2t = 1.0;  // beta1^t, beta2^t for Adam's bias corrections
     const int2 *pq = reinterpret_cast<const int2 *>(smem + L.pq);
     const double2 *mab = reinterpret_cast<const double2 *>(smem + L.mab);
@@ -1011,7 +1091,7 @@ __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
             const double2 x = psi[b];
             e = x.x * acc.x + x.y * acc.y;
         }
-        epart[tid] = e;
+        if (!RT) epart[tid] = e;
         __syncthreads();
         if (it == a.iters) {
             const double sE = block_sum_all(e, gsum);
@@ -1105,7 +1185,7 @@ __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
         } else if (wave == NW - 1) {
             // the energy's sum beside the reverse sweep
             double sE = 0.0;
-            for (int t = lane; t < NT; t += 64) sE += epart[t];
+            for (int t = lane; t < D; t += 64) sE += epart[t];
             sE = wave_sum(sE);
             if (lane == 0) energies[it] = sE;
         }
@@ -1117,12 +1197,13 @@ __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
 constexpr size_t kSmallLdsMax = 160 * 1024 - 1024;
 constexpr int kSmallFast = 1 << 5;  // mode flag: k_small_fast
 
-inline void (*fast_kernel(int n, bool complex_tab, bool two_slots))(SmallKernelArgs)
+inline void (*fast_kernel(int n, bool complex_tab, bool two_slots, bool regtab))(SmallKernelArgs)
 {
-    if (n <= 6) return complex_tab ? k_small_fast<64, 1, true> : k_small_fast<64, 1, false>;
-    if (n == 7) return complex_tab ? k_small_fast<128, 1, true> : k_small_fast<128, 1, false>;
-    if (two_slots) return complex_tab ? k_small_fast<256, 2, true> : k_small_fast<256, 2, false>;
-    return complex_tab ? k_small_fast<256, 1, true> : k_small_fast<256, 1, false>;
+    if (n <= 6) return complex_tab ? k_small_fast<64, 1, true, false> : k_small_fast<64, 1, false, false>;
+    if (n == 7) return complex_tab ? k_small_fast<128, 1, true, false> : k_small_fast<128, 1, false, false>;
+    if (regtab) return k_small_fast<320, 1, false, true>;  // one pair slot only (two would spill)
+    if (two_slots) return complex_tab ? k_small_fast<256, 2, true, false> : k_small_fast<256, 2, false, false>;
+    return complex_tab ? k_small_fast<256, 1, true, false> : k_small_fast<256, 1, false, false>;
 }
 
 int choose_block(int n)
@@ -1146,7 +1227,7 @@ int small_run_plan(int n, int n_gates, int n_params, int n_pgates, int n_groups,
     if (n > 10 || n_gates > 2048 || n_params > 2048) return 0;
     // up to 8 qubits with the Hamiltonian as a table: the latency-built kernel
     if (n <= 8 && n_gates <= 1024) {
-        const FastLayout W = fast_layout(n, n_gates, n_params, n_pgates, n_groups, has_imag);
+        const FastLayout W = fast_layout(n, n_gates, n_params, n_pgates, n_groups, has_imag);  // (register rows need less)
         if (W.total <= kSmallLdsMax) {
             *mode_out = (has_imag ? 2 : 1) | kSmallFast;
             *lds_out = W.total;
@@ -1182,9 +1263,10 @@ hipError_t launch_small_run(const SmallRunArgs &a, const OpDesc *rops, const int
     ka.defer = (mode >> 4) & 1;
     ka.max_inst_terms = max_inst_terms;
     if (mode & kSmallFast) {
-        const int nt = fast_threads(a.n);
-        const FastLayout W = fast_layout(a.n, a.n_gates, a.n_params, n_pgates, a.n_groups, ka.mode == 2);
-        void (*kern)(SmallKernelArgs) = fast_kernel(a.n, ka.mode == 2, max_pairs > 64);
+        const bool rt = fast_regtab(a.n, a.n_groups, ka.mode == 2) && max_pairs <= 64;
+        const int nt = fast_threads(a.n) + (rt ? 64 : 0);
+        const FastLayout W = fast_layout(a.n, a.n_gates, a.n_params, n_pgates, a.n_groups, ka.mode == 2, rt);
+        void (*kern)(SmallKernelArgs) = fast_kernel(a.n, ka.mode == 2, max_pairs > 64, rt);
         if (W.total > 65536) {
             hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)W.total);

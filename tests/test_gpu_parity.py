@@ -416,3 +416,49 @@ def test_parameter_shift_gradient_on_device(vqe, ctx, case):
         assert abs(e[b] - eo) < E_TOL
         np.testing.assert_allclose(g[b], go, atol=G_TOL)
         np.testing.assert_allclose(g[b], ga[b], atol=G_TOL)
+
+
+def _real_pauli_sum(n, n_groups, seed):
+    """X/Z strings only (no Y factor, so every coefficient stays real), with
+    exactly n_groups distinct flip masks (the identity group included)."""
+    rng = np.random.default_rng(seed)
+    flips = [0]
+    while len(flips) < n_groups:
+        f = int(rng.integers(1, 1 << n))
+        if f not in flips:
+            flips.append(f)
+    xs, zs = [], []
+    for f in flips:
+        seen = set()
+        for _ in range(int(rng.integers(1, 4))):
+            z = int(rng.integers(0, 1 << n)) & ~f
+            if (f == 0 and z == 0) or z in seen:
+                continue
+            seen.add(z)
+            xs.append(f)
+            zs.append(z)
+    c = rng.normal(size=len(xs)) / np.sqrt(len(xs))
+    return synth.PauliSum(n, np.array(xs, dtype=np.uint64), np.array(zs, dtype=np.uint64), c)
+
+
+@pytest.mark.parametrize("n_groups", [60, 90])
+def test_persistent_loop_register_rows(vqe, ctx, n_groups):
+    # 8 qubits, a real Hamiltonian and gates of at most 64 pairs: with at most
+    # 64 flip groups the loop keeps each amplitude's Hamiltonian row in
+    # registers (60: the last block of eight partly padding); with 90 groups
+    # the table does not fit and the general persistent loop runs
+    _say("register rows", n_groups)
+    spec = synth.ucc_circuit(8, 2)
+    ham = _real_pauli_sum(8, n_groups, seed=n_groups)
+    assert len(set(int(v) for v in ham.xmask)) == n_groups
+    C = vqe.Circuit.from_spec(ctx, spec)
+    H = vqe.Hamiltonian.from_sum(ctx, ham)
+    th0 = synth.uniform_thetas(spec.n_params, 3, seed=n_groups)
+    th = dev(th0)
+    iters = 20
+    traj = vqe.run(ctx, C, H, th, iters).cpu().numpy()
+    tho_gpu = th.cpu().numpy()
+    for b in range(3):
+        want, tho = oracle.vqe_run(spec, ham, th0[b], iters)
+        np.testing.assert_allclose(traj[b], want, atol=E_TOL)
+        np.testing.assert_allclose(tho_gpu[b], tho, atol=1e-7)
