@@ -12,10 +12,13 @@ two scans are independent and run on two HIP streams side by side.
 
 Prints one JSON line.  Extra objects: `roofline` for the dominant kernel
 (the persistent loop of the 8-qubit scan), `cpu_baseline` (the oracle on a
-bounded sample of the same workload, rank 0 only), `setup` (host-side
-Hamiltonian build and upload per scan, outside the timed region) and
-`hea` (a large-state energy + gradient evaluation of the hardware-efficient
-ansatz with per-pass HBM bandwidth, measured separately).
+bounded sample of the same workload, one core and all cores, rank 0 only),
+`setup` (host-side Hamiltonian build and upload per scan, outside the timed
+region), `hea` (the hardware-efficient scaling sweep n = 12..26 with per-pass
+HBM bandwidth at 26 qubits, where one state is 1 GiB, four times the last-level
+cache), `large` (30 qubits energy + gradient, 32 qubits energy), `c1`, `qaoa`
+and `served` (the mixed request stream at five arrival rates), each measured
+outside the timed region.
 """
 from __future__ import annotations
 
@@ -49,21 +52,23 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-hea", action="store_true")
-    ap.add_argument("--hea-n", type=int, default=24)
+    ap.add_argument("--hea-n", type=int, default=26, help="qubits of the per-pass bandwidth leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-c1", action="store_true")
     ap.add_argument("--no-qaoa", action="store_true")
-    ap.add_argument("--scaling", type=str, default="",
+    ap.add_argument("--scaling", type=str, default="12,16,20,24,26",
                     help="comma-separated qubit counts for the hardware-efficient scaling leg (L = n, 500 strings)")
-    ap.add_argument("--large", action="store_true",
-                    help="30-qubit energy + gradient and 32-qubit energy (L = 4, 2000 strings)")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip 30-qubit energy + gradient and 32-qubit energy (L = 4, 2000 strings)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (calibrates the HBM byte "
                          "counters FETCH_SIZE / WRITE_SIZE of a profiler run) and exit")
-    ap.add_argument("--served-requests", type=int, default=400)
-    ap.add_argument("--served-rates", type=str, default="1.0",
+    ap.add_argument("--served-requests", type=int, default=5000)
+    ap.add_argument("--served-rates", type=str, default="0.25,0.5,1.0,1.5,2.0",
                     help="comma-separated multiples of the measured plain-path capacity")
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="processes of the all-cores oracle leg (0: the host's cores, at most 16)")
     return ap.parse_args()
 
 
@@ -100,6 +105,14 @@ def eval_flops(spec, n_groups, complex_table):
     hpsi = D * n_groups * (8 if complex_table else 4)
     energy = 4 * D
     return fwd + hpsi + energy + 2 * fwd + grad
+
+
+def scope_table_flops(spec, n_terms):
+    """The scope table's per-evaluation flop estimate for a small state:
+    gates x 2^n amplitudes x 6 flops x 3 (forward, and the reverse sweep on psi
+    and lambda) + 2 x terms x 2^n x 8 (the energy and H psi, term by term)."""
+    D = 1 << spec.n
+    return spec.n_gates * D * 6 * 3 + 2 * n_terms * D * 8
 
 
 def _odd_y(x, z):
@@ -139,6 +152,10 @@ def main():
         sys.exit(2)
 
     import torch
+
+    # the all-cores oracle leg runs in worker processes forked now, before
+    # anything touches the GPU (they only ever run the CPU oracle)
+    pool, workers = (None, 0) if args.no_cpu_baseline else _cpu_pool(args.cpu_workers)
 
     if args.copy_calibration:
         nbytes = args.copy_calibration << 20
@@ -226,14 +243,20 @@ def main():
     flops_eval = eval_flops(p8["spec"], n_groups, complex_table)
     flops_launch = flops_eval * BATCH * ITERS
     achieved = flops_launch / (kernel_ms[8] * 1e-3) / 1e12
+    flops_scope = scope_table_flops(p8["spec"], len(c))
+    achieved_scope = flops_scope * BATCH * ITERS / (kernel_ms[8] * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": "k_small_fast, 8 qubits (one workgroup of 320 threads per instance: a gate "
                                           "wave and four H psi waves; 100 instances x 200 steps in one launch; the "
                                           "event interval also holds the weight refresh, < 0.2 %)",
                 "achieved": round(achieved, 4), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP64_PEAK_TFLOPS, 5),
                 "traffic": measured_traffic("k_small_fast"),
-                "flops_per_eval": flops_eval, "evals_per_launch": BATCH * ITERS,
-                "kernel_ms": round(kernel_ms[8], 4)}
+                "flops_per_eval": flops_eval, "flops_count": "grouped: H held as XOR-offset diagonals, active "
+                                                             "pairs only (eval_flops)",
+                "evals_per_launch": BATCH * ITERS, "kernel_ms": round(kernel_ms[8], 4),
+                "scope_table_count": {"flops_per_eval": flops_scope, "achieved": round(achieved_scope, 4),
+                                      "frac": round(achieved_scope / FP64_PEAK_TFLOPS, 5),
+                                      "formula": "gates x 2^n x 6 x 3 + 2 x terms x 2^n x 8"}}
 
     final_e = {p["n"]: p["energies"][:, -1].cpu().numpy() for p in problems}
     out = {
@@ -267,6 +290,11 @@ def main():
     if not args.no_hea:
         out["hea"] = hea_measure(ctx, vqe, synth, torch, args.hea_n)
         _progress("hea done")
+        if args.scaling:
+            out["hea"]["scaling"] = []
+            for v in args.scaling.split(","):
+                out["hea"]["scaling"].append(scaling_measure(ctx, vqe, synth, torch, int(v)))
+                _progress(f"scaling n={v} done")
 
     # -------------------------------------------------- C1: plain vs batched
     if not args.no_c1:
@@ -275,12 +303,7 @@ def main():
     if not args.no_qaoa:
         out["qaoa"] = qaoa_measure(ctx, vqe, synth, torch, 24, 4)
         _progress("qaoa done")
-    if args.scaling:
-        out["hea_scaling"] = []
-        for v in args.scaling.split(","):
-            out["hea_scaling"].append(scaling_measure(ctx, vqe, synth, torch, int(v)))
-            _progress(f"scaling n={v} done")
-    if args.large:
+    if not args.no_large:
         out["large"] = large_measure(ctx, vqe, synth, torch)
         _progress("large done")
 
@@ -292,14 +315,21 @@ def main():
 
     # -------------------------------------------------- CPU baseline
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(problems, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(problems, args.cpu_seconds, pool, workers)
+        pool.close()
+        pool.join()
 
     print(json.dumps(out), flush=True)
 
 
 def hea_measure(ctx, vqe, synth, torch, n):
-    """One energy + gradient of the hardware-efficient ansatz (L = n layers,
-    500 random Pauli strings) and the HBM bandwidth of its forward passes."""
+    """Energy + adjoint gradient of the hardware-efficient ansatz (L = n
+    layers, 500 random Pauli strings) at n qubits, then the same calls again
+    with the library's kernel timing on (HIP events around every launch, on
+    its own stream): per kernel class the average duration, the algorithmic
+    HBM bytes per launch and their ratio against the 8 TB/s peak.  At 26
+    qubits one state is 1 GiB, four times the 256 MB last-level cache, so the
+    bytes come from HBM."""
     dev = torch.device("cuda:0")
     spec = synth.hea_circuit(n, n)
     ham = synth.random_pauli_sum(n, 500, seed=synth.MASTER_SEED + n)
@@ -310,8 +340,9 @@ def hea_measure(ctx, vqe, synth, torch, n):
     e = torch.empty(1, dtype=torch.float64, device=dev)
     g = torch.empty(1, spec.n_params, dtype=torch.float64, device=dev)
     vqe.energy_grad(ctx, C, H, th, ws=ws, out_e=e, out_g=g)
+    vqe.energy(ctx, C, H, th, ws=ws, out=e)
     torch.cuda.synchronize()
-    reps = 3
+    reps = 2
     s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     s0.record()
     for _ in range(reps):
@@ -319,46 +350,40 @@ def hea_measure(ctx, vqe, synth, torch, n):
     s1.record()
     torch.cuda.synchronize()
     ms_eval = s0.elapsed_time(s1) / reps
-    # forward passes alone
+    s0.record()
+    for _ in range(reps):
+        vqe.energy(ctx, C, H, th, ws=ws, out=e)
+    s1.record()
+    torch.cuda.synchronize()
+    ms_energy = s0.elapsed_time(s1) / reps
+    ctx.profile(reset=True)
+    ctx.set_profiling(True)
+    for _ in range(reps):
+        vqe.energy_grad(ctx, C, H, th, ws=ws, out_e=e, out_g=g)
+        vqe.energy(ctx, C, H, th, ws=ws, out=e)
+    prof = ctx.profile(reset=True)
+    ctx.set_profiling(False)
+    kernels = {}
+    for name, r in sorted(prof.items()):
+        if r["bytes"] <= 0:
+            continue
+        gbps = r["bytes"] / (r["ms"] * 1e-3) / 1e9
+        kernels[name] = {"launches_per_eval": r["launches"] // reps, "avg_us": round(r["ms"] / r["launches"] * 1e3, 2),
+                         "bytes_per_launch": int(r["bytes"] / r["launches"]), "GBps": round(gbps, 1),
+                         "frac_of_hbm": round(gbps / HBM_PEAK_GBPS, 4)}
     passes, _ = vqe.circuit_plan(ctx, C)
-    psi = torch.empty(1, 1 << n, dtype=torch.complex128, device=dev)
-    vqe.prepare_reference(ctx, n, 1, 0, psi)
-    vqe.apply_ansatz(ctx, C, th, psi)
-    torch.cuda.synchronize()
-    s0.record()
-    for _ in range(reps):
-        vqe.apply_ansatz(ctx, C, th, psi)
-    s1.record()
-    torch.cuda.synchronize()
-    ms_fwd = s0.elapsed_time(s1) / reps
-    pass_ms = ms_fwd / len(passes)
-    gbps = 32.0 * (1 << n) / (pass_ms * 1e-3) / 1e9
-    # the same passes with one LDS round trip per gate (A/B of the register stages)
-    ctx.set_staged(False)
-    vqe.apply_ansatz(ctx, C, th, psi)
-    s0.record()
-    vqe.apply_ansatz(ctx, C, th, psi)
-    s1.record()
-    torch.cuda.synchronize()
-    ctx.set_staged(True)
-    ms_fwd_unstaged = s0.elapsed_time(s1)
-    # expectation sweeps alone
     pl = vqe.hamiltonian_plan(ctx, H, 1, False)
-    s0.record()
-    for _ in range(reps):
-        vqe.expect(ctx, H, psi)
-    s1.record()
-    torch.cuda.synchronize()
-    ms_exp = s0.elapsed_time(s1) / reps
-    sweep_gbps = 16.0 * (1 << n) * len(pl["sweeps"]) / (ms_exp * 1e-3) / 1e9
+    del ws
+    torch.cuda.empty_cache()
     return {"n": n, "layers": n, "gates": spec.n_gates, "params": spec.n_params, "terms": 500,
-            "flip_groups": int(H.n_groups), "ms_per_energy_grad": round(ms_eval, 3),
-            "forward_passes": int(len(passes)), "ms_forward": round(ms_fwd, 3),
-            "forward_pass_GBps": round(gbps, 1), "forward_pass_frac_of_hbm": round(gbps / HBM_PEAK_GBPS, 4),
-            "ms_forward_one_gate_per_lds_trip": round(ms_fwd_unstaged, 3),
-            "expect_sweeps": int(len(pl["sweeps"])), "ms_expect": round(ms_exp, 3),
-            "expect_sweep_GBps": round(sweep_gbps, 1),
-            "expect_sweep_frac_of_hbm": round(sweep_gbps / HBM_PEAK_GBPS, 4)}
+            "flip_groups": int(H.n_groups), "state_GiB": round((16 << n) / 2 ** 30, 3),
+            "ms_per_energy_grad": round(ms_eval, 3), "ms_per_energy": round(ms_energy, 3),
+            "forward_passes": int(len(passes)), "expect_sweeps": int(len(pl["sweeps"])),
+            "kernels": kernels,
+            "timing": "HIP events around each launch on its stream (library kernel timing), "
+                      f"{reps} energy + gradient and {reps} energy evaluations; bytes = algorithmic "
+                      "(forward pass 32 B, adjoint pass 64 B, expectation sweep 16 B, H psi sweep "
+                      "32 / 48 B per amplitude)"}
 
 
 def qaoa_measure(ctx, vqe, synth, torch, n, layers):
@@ -514,34 +539,94 @@ def served_measure(ctx, count, rates=(1.0,)):
     return out
 
 
-def cpu_baseline(problems, budget_s):
-    """The oracle (plain FP64 C for the loop, one thread) on a bounded sample
-    of the same scan: the first bond lengths of each qubit count, each with
-    its Hamiltonian build (the oracle's dense Jordan-Wigner construction, as
-    the GPU step builds H(d_i) too) and 200 Adam steps on adjoint gradients.
-    Each qubit count gets about budget_s / 2 seconds; the rate is scaled to
-    the full scan."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.lower().startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _cpu_pool(requested):
+    """Worker processes for the all-cores oracle leg, forked before the GPU is
+    initialised (each runs the oracle on one thread)."""
+    import multiprocessing as mp
+    import oracle
+    oracle.lib()  # built once here, not by every worker
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    workers = requested or max(1, min(16, avail))
+    return mp.get_context("fork").Pool(workers), workers
+
+
+def _oracle_bond(task):
+    """One bond length on the oracle: Hamiltonian build and the Adam loop."""
+    spec, ints, iters = task
     import oracle
     from oracle import fermion
+    from threadpoolctl import threadpool_limits
     oracle.set_threads(1)
-    done, spent = {}, {}
+    threadpool_limits(1)  # one core per bond: numpy's BLAS in the Hamiltonian build too
+    t0 = time.perf_counter()
+    ho = fermion.qubit_hamiltonian(ints)
+    e, _ = oracle.vqe_run(spec, ho, np.zeros(spec.n_params), iters)
+    return time.perf_counter() - t0, float(e[-1])
+
+
+def cpu_baseline(problems, budget_s, pool, workers):
+    """The oracle (plain FP64 C for the loop) on a bounded sample of the same
+    scan: the first bond lengths of each qubit count, each with its
+    Hamiltonian build (the oracle's dense Jordan-Wigner construction, as the
+    GPU step builds H(d_i) too) and 200 Adam steps on adjoint gradients.
+
+    (i) one core: bond lengths one after another, about budget_s / 2 seconds
+    per qubit count; (ii) all cores: bond lengths in parallel, one oracle
+    process per core (the bond lengths are independent, so this is the
+    paper's MPI-over-bond-lengths pattern), at least one bond per worker.
+    Rates are scaled to the full scan; both runs compute the same final
+    energies bit for bit (checked)."""
+    import oracle
+    oracle.set_threads(1)
+    done, spent, final = {}, {}, {}
     for p in problems:
         n = p["n"]
-        done[n], spent[n] = 0, 0.0
+        done[n], spent[n], final[n] = 0, 0.0, []
         wall0 = time.perf_counter()
         while done[n] < BATCH and (done[n] == 0 or time.perf_counter() - wall0 < budget_s / 2):
-            t0 = time.perf_counter()
-            ho = fermion.qubit_hamiltonian(p["ints"][done[n]])
-            oracle.vqe_run(p["spec"], ho, np.zeros(p["spec"].n_params), ITERS)
-            spent[n] += time.perf_counter() - t0
+            dt, ef = _oracle_bond((p["spec"], p["ints"][done[n]], ITERS))
+            spent[n] += dt
+            final[n].append(ef)
             done[n] += 1
     scan_s = sum(spent[n] / done[n] * BATCH for n in spent)
     evals = len(spent) * BATCH * ITERS
-    return {"value": round(evals / scan_s, 1), "unit": "evals/s", "cores": 1, "kind": "oracle",
-            "sample": " and ".join(f"{done[n]} x {n}q bond lengths" for n in sorted(done))
-                      + f", each with its Hamiltonian build and {ITERS} Adam steps (adjoint gradients), "
-                      f"{sum(spent.values()):.1f} s of timed CPU; rate scaled to the full 2 x {BATCH}-bond scan",
-            "per_qubit_evals_per_s": {f"{n}q": round(done[n] * ITERS / spent[n], 1) for n in sorted(spent)}}
+    one = {"value": round(evals / scan_s, 1), "cores": 1,
+           "per_qubit_evals_per_s": {f"{n}q": round(done[n] * ITERS / spent[n], 1) for n in sorted(spent)},
+           "sample": " and ".join(f"{done[n]} x {n}q" for n in sorted(done)) + " bond lengths"}
+    par, agree = {}, 0.0
+    for p in problems:
+        n = p["n"]
+        cnt = min(BATCH, max(workers, done[n]))
+        t0 = time.perf_counter()
+        res = pool.map(_oracle_bond, [(p["spec"], p["ints"][i], ITERS) for i in range(cnt)], chunksize=1)
+        par[n] = (cnt, time.perf_counter() - t0)
+        for i, ef in enumerate(final[n]):
+            agree = max(agree, abs(res[i][1] - ef))
+    assert agree <= 1e-12, f"all-cores oracle run disagrees with the one-core run by {agree}"
+    scan_par = sum(par[n][1] / par[n][0] * BATCH for n in par)
+    return {"value": round(evals / scan_par, 1), "unit": "evals/s", "cores": workers, "kind": "oracle",
+            "sample": " and ".join(f"{par[n][0]} x {n}q" for n in sorted(par))
+                      + f" bond lengths on {workers} worker processes (one oracle thread each), each bond with "
+                      f"its Hamiltonian build and {ITERS} Adam steps (adjoint gradients); wall time scaled to "
+                      f"the full 2 x {BATCH}-bond scan",
+            "per_qubit_evals_per_s": {f"{n}q": round(par[n][0] * ITERS / par[n][1], 1) for n in sorted(par)},
+            "host": {"nproc": os.cpu_count(), "cpu_model": _cpu_model(), "threads_used": workers},
+            "one_core": one, "max_final_energy_diff_vs_one_core": agree}
 
 
 if __name__ == "__main__":

@@ -133,6 +133,32 @@ int vqe_ctx_set_staged(vqe_ctx_t ctx, int staged);
  * vqe_apply_ansatz for per-launch tables), so later calls do not allocate. */
 int vqe_ctx_reserve(vqe_ctx_t ctx, size_t bytes);
 
+/* ---- kernel timing (measurement) ----------------------------------------
+ * With profiling on, the library brackets each launch of the state passes,
+ * the Pauli sweeps and the persistent loop with a pair of HIP events on the
+ * launch's own stream and accumulates, per kernel (and role), the launch
+ * count, the summed event durations and the algorithmic HBM bytes of those
+ * launches (every amplitude read and written once per forward pass: 32 B;
+ * adjoint pass with psi and lambda: 64 B; expectation sweep: 16 B; H psi
+ * sweep: 32 B for the first, 48 B for later sweeps; times 2^n per state and
+ * the batch).  The events add a few microseconds per launch; launches on a
+ * stream that is being captured are not timed. */
+typedef struct {
+    char name[48];      /* kernel and role, NUL-terminated */
+    int64_t launches;
+    double total_ms;    /* summed event-measured durations */
+    double bytes;       /* algorithmic HBM bytes of those launches (0: not counted) */
+} vqe_kernel_stat;
+
+/* on = 1 starts timing launches made afterwards, 0 stops. */
+int vqe_ctx_set_profiling(vqe_ctx_t ctx, int on);
+
+/* Wait for every timed launch, then copy up to `capacity` per-kernel totals
+ * into out (sorted by name) and the number of kernels into *count (which may
+ * exceed capacity).  reset = 1 clears the totals afterwards.  out may be NULL
+ * when capacity is 0. */
+int vqe_ctx_profile(vqe_ctx_t ctx, vqe_kernel_stat *out, int capacity, int *count, int reset);
+
 /* Text of the last error on this context (never NULL). */
 const char *vqe_last_error(vqe_ctx_t ctx);
 

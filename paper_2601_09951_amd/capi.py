@@ -34,7 +34,14 @@ EXPORTED = [
     "vqe_apply_hamiltonian", "vqe_energy_grad", "vqe_grad_shift", "vqe_adam_step", "vqe_run",
     "vqe_circ_plan_export", "vqe_ham_plan_export",
     "vqe_hfam_create", "vqe_hfam_info", "vqe_hfam_member", "vqe_hfam_set_integrals", "vqe_hfam_destroy",
+    "vqe_ctx_set_profiling", "vqe_ctx_profile",
 ]
+
+
+class KernelStat(ctypes.Structure):
+    """vqe_kernel_stat."""
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
 
 
 class VQEError(RuntimeError):
@@ -87,6 +94,8 @@ def _declare(L):
         "vqe_hfam_member": [P, i64, PP],
         "vqe_hfam_set_integrals": [P, P, i64, i64, P, P],
         "vqe_hfam_destroy": [P],
+        "vqe_ctx_set_profiling": [P, i32],
+        "vqe_ctx_profile": [P, P, i32, P, i32],
     }
     for name, args in sig.items():
         f = getattr(L, name)

@@ -30,11 +30,60 @@ int hip_check(Context *ctx, hipError_t e, const char *what)
     return set_err(ctx, VQE_EHIP, os.str());
 }
 
+namespace {
+constexpr int kPoolMinCls = 8;             // 256-byte blocks
+constexpr int kPoolMaxCls = 24;            // 16 MiB blocks; larger tables use hipMalloc directly
+constexpr size_t kPoolChunk = 2u << 20;    // small classes are carved from 2 MiB chunks
+
+int pool_class(size_t bytes)
+{
+    int c = kPoolMinCls;
+    while (((size_t)1 << c) < bytes) ++c;
+    return c;
+}
+
+bool events_done(const std::vector<StreamUse> &uses)
+{
+    for (const StreamUse &u : uses) {
+        hipError_t e = hipEventQuery(u.event);
+        if (e == hipErrorNotReady) return false;
+        if (e != hipSuccess) (void)hipGetLastError();  // a failed event cannot hold the tables back
+    }
+    return true;
+}
+}  // namespace
+
 int dev_alloc(Context *ctx, DevMem &m, size_t bytes)
 {
     m.p = nullptr;
     m.bytes = 0;
+    m.pool_cls = -1;
     if (bytes == 0) return VQE_OK;
+    const int cls = pool_class(bytes);
+    if (cls <= kPoolMaxCls) {
+        if (ctx->pool_free.size() <= (size_t)cls) ctx->pool_free.resize(cls + 1);
+        if (ctx->pool_free[cls].empty()) poll_retired(ctx, false);
+        if (ctx->pool_free[cls].empty()) {
+            const size_t block = (size_t)1 << cls, chunk = std::max(block, kPoolChunk);
+            if (ctx->budget && ctx->used + chunk > ctx->budget)
+                return set_err(ctx, VQE_ENOMEM, "context memory budget exhausted");
+            void *p = nullptr;
+            hipError_t e = hipMalloc(&p, chunk);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                return set_err(ctx, VQE_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+            }
+            ctx->used += chunk;
+            ctx->pool_chunks.push_back(p);
+            for (size_t off = chunk; off >= block; off -= block)
+                ctx->pool_free[cls].push_back(static_cast<unsigned char *>(p) + off - block);
+        }
+        m.p = ctx->pool_free[cls].back();
+        ctx->pool_free[cls].pop_back();
+        m.bytes = bytes;
+        m.pool_cls = cls;
+        return VQE_OK;
+    }
     if (ctx->budget && ctx->used + bytes > ctx->budget)
         return set_err(ctx, VQE_ENOMEM, "context memory budget exhausted");
     void *p = nullptr;
@@ -49,27 +98,172 @@ int dev_alloc(Context *ctx, DevMem &m, size_t bytes)
     return VQE_OK;
 }
 
+// Immediate release: the caller guarantees that no queued kernel reads m.
 void dev_free(Context *ctx, DevMem &m)
 {
     if (m.p) {
-        (void)hipFree(m.p);
-        if (ctx) ctx->used -= std::min(ctx->used, m.bytes);
+        if (m.pool_cls >= 0 && ctx) {
+            ctx->pool_free[m.pool_cls].push_back(m.p);
+        } else {
+            (void)hipFree(m.p);
+            if (ctx) ctx->used -= std::min(ctx->used, m.bytes);
+        }
     }
     m.p = nullptr;
     m.bytes = 0;
+    m.pool_cls = -1;
 }
 
+int note_use(Context *ctx, std::vector<StreamUse> &uses, hipStream_t s)
+{
+    if (ctx->device < 0) return VQE_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        cs = hipStreamCaptureStatusNone;
+    }
+    if (cs != hipStreamCaptureStatusNone) return VQE_OK;  // a captured graph keeps its own reference
+    for (StreamUse &u : uses)
+        if (u.stream == s) return hip_check(ctx, hipEventRecord(u.event, s), "hipEventRecord");
+    StreamUse u{s, nullptr};
+    int rc = hip_check(ctx, hipEventCreateWithFlags(&u.event, hipEventDisableTiming), "hipEventCreate");
+    if (rc) return rc;
+    uses.push_back(u);
+    return hip_check(ctx, hipEventRecord(u.event, s), "hipEventRecord");
+}
+
+void retire(Context *ctx, std::vector<DevMem> mem, std::vector<StreamUse> uses)
+{
+    if (ctx->device < 0 || uses.empty() || events_done(uses)) {
+        for (DevMem &m : mem) dev_free(ctx, m);
+        for (StreamUse &u : uses) (void)hipEventDestroy(u.event);
+        return;
+    }
+    ctx->retired.push_back(Context::Retired{std::move(mem), std::move(uses)});
+}
+
+void retire_pauli_plan(Context *ctx, PauliPlan *p)
+{
+    retire(ctx, {p->groups, p->geoms, p->wsrc, p->toff, p->terms}, std::move(p->uses));
+    p->groups = p->geoms = p->wsrc = p->toff = p->terms = DevMem{};
+    p->uses.clear();
+}
+
+// recycle retired tables whose readers have finished (wait: block until all have)
+void poll_retired(Context *ctx, bool wait)
+{
+    std::vector<Context::Retired> keep;
+    for (Context::Retired &r : ctx->retired) {
+        if (wait)
+            for (StreamUse &u : r.uses) (void)hipEventSynchronize(u.event);
+        if (wait || events_done(r.uses)) {
+            for (DevMem &m : r.mem) dev_free(ctx, m);
+            for (StreamUse &u : r.uses) (void)hipEventDestroy(u.event);
+        } else {
+            keep.push_back(std::move(r));
+        }
+    }
+    ctx->retired.swap(keep);
+}
+
+namespace {
+bool capturing(hipStream_t s)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return cs != hipStreamCaptureStatusNone;
+}
+
+hipEvent_t prof_event(Context *ctx)
+{
+    hipEvent_t e = nullptr;
+    if (!ctx->prof_events.empty()) {
+        e = ctx->prof_events.back();
+        ctx->prof_events.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        e = nullptr;
+    }
+    return e;
+}
+
+// fold completed event pairs into the per-kernel totals (waits for them)
+void prof_collect(Context *ctx)
+{
+    for (Context::ProfRec &r : ctx->prof_pending) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            Context::ProfAcc &a = ctx->prof_acc[r.name];
+            a.launches += 1;
+            a.ms += ms;
+            a.bytes += r.bytes;
+        } else {
+            (void)hipGetLastError();
+        }
+        ctx->prof_events.push_back(r.a);
+        ctx->prof_events.push_back(r.b);
+    }
+    ctx->prof_pending.clear();
+}
+}  // namespace
+
+ProfScope::ProfScope(Context *c, const char *nm, hipStream_t st, double b) : ctx(c), name(nm), s(st), bytes(b)
+{
+    if (!c->profile || c->device < 0 || capturing(st)) return;
+    e0 = prof_event(c);
+    if (e0 && hipEventRecord(e0, st) != hipSuccess) {
+        (void)hipGetLastError();
+        c->prof_events.push_back(e0);
+        e0 = nullptr;
+    }
+}
+
+ProfScope::~ProfScope()
+{
+    if (!e0) return;
+    hipEvent_t e1 = prof_event(ctx);
+    if (!e1 || hipEventRecord(e1, s) != hipSuccess) {
+        (void)hipGetLastError();
+        ctx->prof_events.push_back(e0);
+        if (e1) ctx->prof_events.push_back(e1);
+        return;
+    }
+    ctx->prof_pending.push_back(Context::ProfRec{name, bytes, e0, e1});
+}
+
+// Host data to a new device table: staged through pinned memory and copied on
+// the context's own stream, so the host waits for this copy only.
 int upload(Context *ctx, DevMem &m, const void *src, size_t bytes)
 {
     if (ctx->device < 0) {  // host-only planning context: plans keep host copies only
-        m.p = nullptr;
-        m.bytes = 0;
+        m = DevMem{};
         return VQE_OK;
     }
     int r = dev_alloc(ctx, m, bytes);
     if (r) return r;
     if (!bytes) return VQE_OK;
-    return hip_check(ctx, hipMemcpy(m.p, src, bytes, hipMemcpyHostToDevice), "hipMemcpy (upload)");
+    if (!ctx->upload_stream) {
+        r = hip_check(ctx, hipStreamCreateWithFlags(&ctx->upload_stream, hipStreamNonBlocking), "hipStreamCreate");
+        if (r) return r;
+    }
+    if (ctx->staging_bytes < bytes) {
+        // the old buffer may be the source of a copy still in flight: kept until the context goes
+        if (ctx->staging) ctx->old_staging.push_back(ctx->staging);
+        const size_t want = std::max<size_t>(bytes, std::max<size_t>(2 * ctx->staging_bytes, 1u << 20));
+        ctx->staging = nullptr;
+        ctx->staging_bytes = 0;
+        r = hip_check(ctx, hipHostMalloc(&ctx->staging, want, hipHostMallocDefault), "hipHostMalloc (staging)");
+        if (r) return r;
+        ctx->staging_bytes = want;
+    }
+    std::memcpy(ctx->staging, src, bytes);
+    r = hip_check(ctx, hipMemcpyAsync(m.p, ctx->staging, bytes, hipMemcpyHostToDevice, ctx->upload_stream),
+                  "hipMemcpyAsync (upload)");
+    if (r) return r;
+    return hip_check(ctx, hipStreamSynchronize(ctx->upload_stream), "upload");
 }
 
 int scratch_get(Context *ctx, size_t bytes, void **p)
@@ -261,16 +455,20 @@ int run_forward_passes(Context *ctx, Circ *C, CircPlan *fp, int64_t B, double2 *
                                              reinterpret_cast<const int32_t *>(fp->fslot_gate.p), fp->n_fslots(),
                                              mats, G, B, fused, s),
                        "fused stage matrices");
+    const double pass_bytes = 32.0 * (double)(1ull << C->n) * (double)B;  // read + write of every amplitude
     for (size_t i = 0; !rc && i < fp->passes.size(); ++i) {
         const PassPlan &pp = fp->passes[i];
         const TileGeom *gd = reinterpret_cast<const TileGeom *>(fp->geoms.p) + i;
-        if (fuse && pp.fstage_count > 0)
+        const bool fused_pass = fuse && pp.fstage_count > 0, staged_pass = pp.stage_count > 0 && !ctx->no_stages;
+        ProfScope prof(ctx, fused_pass ? "k_forward_fused" : staged_pass ? "k_forward_staged" : "k_forward_pass", s,
+                       pass_bytes);
+        if (fused_pass)
             rc = hip_check(ctx, launch_forward_fused(pp, gd, reinterpret_cast<const FusedStage *>(fp->fstages.p),
                                                      reinterpret_cast<const FusedCond *>(fp->fconds.p), fused,
                                                      fp->n_fslots(), reinterpret_cast<const FusedPhase *>(fp->fphases.p),
                                                      mats, G, psi, B, ctx->wg_max, s),
                            "forward pass (fused)");
-        else if (pp.stage_count > 0 && !ctx->no_stages)
+        else if (staged_pass)
             rc = hip_check(ctx, launch_forward_staged(pp, pp.stage_bits, gd, reinterpret_cast<const StageDesc *>(fp->stages.p),
                                                       reinterpret_cast<const StageOp *>(fp->sops.p), mats, G, psi,
                                                       B, ctx->wg_max, s),
@@ -312,12 +510,15 @@ int expect_into(Context *ctx, int n_hams, Ham *const *H, int64_t B, const double
     const int W = wg_for(ctx, n, ctx->k_fwd);
     const int S = (int)pp->sweeps.size();
     for (int i = 0; i < S; ++i) {
+        ProfScope prof(ctx, "k_pauli_sweep (expectation)", s, 16.0 * (double)(1ull << n) * (double)B);
         rc = hip_check(ctx, launch_pauli_sweep(pp->sweeps[i], *pp, i, psi, nullptr, B, n_hams == 1 ? 0 : 1, W,
                                                partials, S, false, i == 0, i == S - 1, s),
                        "expectation sweep");
         if (rc) return rc;
     }
-    return hip_check(ctx, launch_reduce_slots(partials, S, W, B, energy, e_stride, 1.0, s), "energy reduce");
+    rc = hip_check(ctx, launch_reduce_slots(partials, S, W, B, energy, e_stride, 1.0, s), "energy reduce");
+    if (rc) return rc;
+    return note_use(ctx, pp->uses, s);
 }
 
 // one H psi sweep into lam (first: lam = sweep, else lam += sweep; last: the
@@ -327,7 +528,11 @@ hipError_t hpsi_sweep(Context *ctx, PauliPlan *pp, int i, const double2 *psi, do
 {
     const int S = (int)pp->sweeps.size();
     const int k = pp->sweeps[i].geom.k;
-    if (!ctx->no_stages && k >= 8 && k <= 11)
+    const bool gather = !ctx->no_stages && k >= 8 && k <= 11;
+    // psi read, lambda written (and read back after the first sweep)
+    ProfScope prof(ctx, gather ? "k_hpsi_gather" : "k_pauli_sweep (H psi)", s,
+                   (i == 0 ? 32.0 : 48.0) * (double)(1ull << pp->n) * (double)B);
+    if (gather)
         return launch_hpsi_gather(pp->sweeps[i], *pp, i, psi, lam, B, ham_div, W, partials, i == 0, i == S - 1, s);
     return launch_pauli_sweep(pp->sweeps[i], *pp, i, psi, lam, B, ham_div, W, partials, 1, true, i == 0,
                               i == S - 1, s);
@@ -363,6 +568,7 @@ int energy_grad_into(Context *ctx, Circ *C, int n_hams, Ham *const *H, int64_t B
         if (rc) return rc;
     }
     rc = hip_check(ctx, launch_reduce_slots(pe, 1, L.W_hpsi, B, energy, e_stride, 1.0, s), "energy reduce");
+    if (!rc) rc = note_use(ctx, pp->uses, s);
     if (rc) return rc;
     const int G = (int)C->gates.size();
     const bool fuse_rev = ctx->fuse && !ctx->no_stages && rp->n_fslots() > 0;
@@ -380,7 +586,10 @@ int energy_grad_into(Context *ctx, Circ *C, int n_hams, Ham *const *H, int64_t B
     for (size_t i = 0; i < rp->passes.size(); ++i) {
         const PassPlan &p = rp->passes[i];
         const TileGeom *gd = reinterpret_cast<const TileGeom *>(rp->geoms.p) + i;
-        if (fuse_rev && p.fstage_count > 0)
+        const bool fused_pass = fuse_rev && p.fstage_count > 0, staged_pass = p.stage_count > 0 && !ctx->no_stages;
+        ProfScope prof(ctx, fused_pass ? "k_reverse_fused" : staged_pass ? "k_reverse_staged" : "k_reverse_pass", s,
+                       64.0 * (double)(1ull << n) * (double)B);  // psi and lambda, read + write
+        if (fused_pass)
             rc = hip_check(ctx, launch_reverse_fused(p, gd, reinterpret_cast<const FusedStage *>(rp->fstages.p),
                                                      reinterpret_cast<const FusedCond *>(rp->fconds.p),
                                                      reinterpret_cast<const int32_t *>(rp->fslot_off.p),
@@ -390,7 +599,7 @@ int energy_grad_into(Context *ctx, Circ *C, int n_hams, Ham *const *H, int64_t B
                                                      reinterpret_cast<const FusedPhase *>(rp->fphases.p), mats, G,
                                                      psi, lam, B, L.W_rev, pg, C->n_pgates, s),
                            "reverse pass (fused)");
-        else if (p.stage_count > 0 && !ctx->no_stages)
+        else if (staged_pass)
             rc = hip_check(ctx, launch_reverse_staged(p, p.stage_bits, gd, reinterpret_cast<const StageDesc *>(rp->stages.p),
                                                       reinterpret_cast<const StageOp *>(rp->sops.p), mats, G, psi,
                                                       lam, B, L.W_rev, pg, C->n_pgates, s),
@@ -514,16 +723,21 @@ int vqe_ctx_create(int device, vqe_ctx_t *out)
 int vqe_ctx_destroy(vqe_ctx_t ctx)
 {
     if (!ctx) return VQE_EINVAL;
-    if (ctx->device >= 0) (void)hipSetDevice(ctx->device);
-    for (auto &kv : ctx->pauli_cache) {
-        dev_free(ctx, kv.second->groups);
-            dev_free(ctx, kv.second->geoms);
-            dev_free(ctx, kv.second->wsrc);
-        dev_free(ctx, kv.second->toff);
-        dev_free(ctx, kv.second->terms);
+    if (ctx->device >= 0) {
+        (void)hipSetDevice(ctx->device);
+        (void)hipDeviceSynchronize();
     }
+    for (auto &kv : ctx->pauli_cache) retire_pauli_plan(ctx, kv.second.get());
     ctx->pauli_cache.clear();
+    poll_retired(ctx, true);
+    prof_collect(ctx);
+    for (hipEvent_t e : ctx->prof_events) (void)hipEventDestroy(e);
     dev_free(ctx, ctx->scratch);
+    for (void *p : ctx->pool_chunks) (void)hipFree(p);
+    ctx->pool_chunks.clear();
+    if (ctx->staging) (void)hipHostFree(ctx->staging);
+    for (void *p : ctx->old_staging) (void)hipHostFree(p);
+    if (ctx->upload_stream) (void)hipStreamDestroy(ctx->upload_stream);
     delete ctx;
     return VQE_OK;
 }
@@ -541,20 +755,6 @@ int vqe_ctx_set_tile(vqe_ctx_t ctx, int k_fwd, int k_rev, int c_low)
     int kf = k_fwd ? k_fwd : ctx->k_fwd, kr = k_rev ? k_rev : ctx->k_rev, c = c_low ? c_low : ctx->c_low;
     if (kf < 6 || kf > kMaxTileBits || kr < 6 || kr > 12 || c < 2 || std::min(kf, kr) - c < 4)
         return set_err(ctx, VQE_EINVAL, "tile geometry out of range (need 6 <= k, 2 <= c, k - c >= 4)");
-    if (kf != ctx->k_fwd || kr != ctx->k_rev || c != ctx->c_low) {
-        if (ctx->device >= 0) {
-            (void)hipSetDevice(ctx->device);
-            (void)hipDeviceSynchronize();
-        }
-        for (auto &kv : ctx->pauli_cache) {
-            dev_free(ctx, kv.second->groups);
-            dev_free(ctx, kv.second->geoms);
-            dev_free(ctx, kv.second->wsrc);
-            dev_free(ctx, kv.second->toff);
-            dev_free(ctx, kv.second->terms);
-        }
-        ctx->pauli_cache.clear();
-    }
     ctx->k_fwd = kf;
     ctx->k_rev = kr;
     ctx->c_low = c;
@@ -575,6 +775,36 @@ int vqe_ctx_set_staged(vqe_ctx_t ctx, int staged)
     if (staged < 0 || staged > 2) return set_err(ctx, VQE_EINVAL, "staged must be 0, 1 or 2");
     ctx->no_stages = staged == 0;
     ctx->fuse = staged == 2;
+    return VQE_OK;
+}
+
+int vqe_ctx_set_profiling(vqe_ctx_t ctx, int on)
+{
+    if (!ctx) return VQE_EINVAL;
+    ctx->profile = on ? 1 : 0;
+    return VQE_OK;
+}
+
+int vqe_ctx_profile(vqe_ctx_t ctx, vqe_kernel_stat *out, int capacity, int *count, int reset)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!count || capacity < 0 || (capacity > 0 && !out)) return set_err(ctx, VQE_EINVAL, "bad argument");
+    prof_collect(ctx);
+    int i = 0;
+    for (const auto &kv : ctx->prof_acc) {
+        if (i < capacity) {
+            vqe_kernel_stat &o = out[i];
+            std::memset(o.name, 0, sizeof(o.name));
+            std::strncpy(o.name, kv.first.c_str(), sizeof(o.name) - 1);
+            o.launches = kv.second.launches;
+            o.total_ms = kv.second.ms;
+            o.bytes = kv.second.bytes;
+        }
+        ++i;
+    }
+    *count = i;
+    if (reset) ctx->prof_acc.clear();
     return VQE_OK;
 }
 
@@ -792,11 +1022,12 @@ int vqe_ham_destroy(vqe_ham_t ham)
     if (!ham) return VQE_EINVAL;
     Context *ctx = ham->ctx;
     if (ctx) {
-        // drop cached plans that reference this Hamiltonian
+        // drop cached plans that reference this Hamiltonian; their tables are
+        // recycled once the kernels queued on them have run (no device sync)
         std::ostringstream tag;
         tag << ':' << ham->id;
         const std::string t = tag.str();
-        bool synced = false;
+        if (ctx->device >= 0) (void)hipSetDevice(ctx->device);
         for (auto it = ctx->pauli_cache.begin(); it != ctx->pauli_cache.end();) {
             const std::string &k = it->first;
             bool hit = false;
@@ -808,16 +1039,7 @@ int vqe_ham_destroy(vqe_ham_t ham)
                 }
             }
             if (hit) {
-                if (!synced && ctx->device >= 0) {
-                    (void)hipSetDevice(ctx->device);
-                    (void)hipDeviceSynchronize();
-                    synced = true;
-                }
-                dev_free(ctx, it->second->groups);
-                dev_free(ctx, it->second->geoms);
-                dev_free(ctx, it->second->wsrc);
-                dev_free(ctx, it->second->toff);
-                dev_free(ctx, it->second->terms);
+                retire_pauli_plan(ctx, it->second.get());
                 it = ctx->pauli_cache.erase(it);
             } else {
                 ++it;
@@ -1004,7 +1226,7 @@ int vqe_apply_hamiltonian(vqe_ctx_t ctx, int n_hams, const vqe_ham_t *hams, int6
                        "H psi sweep");
         if (rc) return rc;
     }
-    return VQE_OK;
+    return note_use(ctx, pp->uses, (hipStream_t)stream);
 }
 
 int vqe_energy(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams, int64_t batch,
@@ -1104,6 +1326,7 @@ int vqe_grad_shift(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *
         if (rc) return rc;
     }
     rc = hip_check(ctx, launch_reduce_slots(part, S, W, R, erows, 1, 1.0, s), "energy reduce");
+    if (!rc) rc = note_use(ctx, pp->uses, s);
     if (rc) return rc;
     return hip_check(ctx, launch_shift_combine(erows, R0, reinterpret_cast<const int32_t *>(circ->shift_off.p),
                                                reinterpret_cast<const int32_t *>(circ->shift_row.p),
@@ -1215,11 +1438,14 @@ int vqe_run(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams, i
             if (rc) return rc;
             int max_pairs = 1;
             for (const OpDesc &o : fp->host_ops) max_pairs = std::max(max_pairs, 1 << (n - o.nfix));
-            return hip_check(ctx, launch_small_run(a, reinterpret_cast<const OpDesc *>(rp->ops.p),
-                                                   reinterpret_cast<const int32_t *>(circ->pmap_off.p),
-                                                   reinterpret_cast<const int32_t *>(circ->pmap_idx.p),
-                                                   circ->n_pgates, mode, max_inst_terms, max_pairs, batch, s),
-                             "persistent VQE loop");
+            ProfScope prof(ctx, "k_small_fast / k_small_run (persistent loop)", s, 0.0);
+            rc = hip_check(ctx, launch_small_run(a, reinterpret_cast<const OpDesc *>(rp->ops.p),
+                                                 reinterpret_cast<const int32_t *>(circ->pmap_off.p),
+                                                 reinterpret_cast<const int32_t *>(circ->pmap_idx.p),
+                                                 circ->n_pgates, mode, max_inst_terms, max_pairs, batch, s),
+                           "persistent VQE loop");
+            if (rc) return rc;
+            return note_use(ctx, pp->uses, s);
         }
     }
 

@@ -172,6 +172,15 @@ struct GroupDev {
 struct DevMem {
     void *p = nullptr;
     size_t bytes = 0;
+    int pool_cls = -1;   // >= 0: a block of the context's table pool (size class 2^pool_cls)
+};
+
+// Streams a plan's device tables were last read on, each with an event
+// recorded after the reads (see note_use): the tables may be recycled once
+// every event has completed, with no device-wide synchronisation.
+struct StreamUse {
+    hipStream_t stream;
+    hipEvent_t event;
 };
 
 struct Context;
@@ -302,6 +311,7 @@ struct PauliPlan {
     int max_terms_group = 0;
     const HamFamily *fam = nullptr;  // weights refreshed from the family's device coefficients
     DevMem wsrc;                     // WeightSrc[terms] when fam is set
+    std::vector<StreamUse> uses;     // where the tables were read (recycling is stream-ordered)
 };
 
 struct Context {
@@ -318,6 +328,52 @@ struct Context {
     std::map<std::string, std::unique_ptr<PauliPlan>> pauli_cache;
     uint64_t next_id = 1;
     int cu_count = 256;
+    // Table pool: device blocks of power-of-two size classes carved from
+    // chunks that live until the context is destroyed, so freeing a table
+    // never calls hipFree (which waits for the whole device).
+    std::vector<std::vector<void *>> pool_free;
+    std::vector<void *> pool_chunks;
+    // tables dropped while kernels may still read them: recycled once every
+    // event recorded after those reads has completed
+    struct Retired {
+        std::vector<DevMem> mem;
+        std::vector<StreamUse> uses;
+    };
+    std::vector<Retired> retired;
+    // uploads: pinned staging copied on a context stream of its own, so a
+    // table upload waits only for its own copy, never for queued kernels
+    hipStream_t upload_stream = nullptr;
+    void *staging = nullptr;
+    size_t staging_bytes = 0;
+    std::vector<void *> old_staging;
+    // kernel timing (vqe_ctx_set_profiling): an event pair around every
+    // timed launch, on the launch's own stream, folded into totals when read
+    int profile = 0;
+    struct ProfRec {
+        const char *name;
+        double bytes;
+        hipEvent_t a, b;
+    };
+    std::vector<ProfRec> prof_pending;
+    std::vector<hipEvent_t> prof_events;
+    struct ProfAcc {
+        int64_t launches = 0;
+        double ms = 0.0, bytes = 0.0;
+    };
+    std::map<std::string, ProfAcc> prof_acc;
+};
+
+// Times the launches enqueued during its lifetime on stream s under `name`
+// (no-op unless profiling is on, or while s is being captured); `bytes` is
+// the algorithmic HBM traffic of those launches.
+struct ProfScope {
+    Context *ctx;
+    const char *name;
+    hipStream_t s;
+    double bytes;
+    hipEvent_t e0 = nullptr;
+    ProfScope(Context *c, const char *nm, hipStream_t st, double b);
+    ~ProfScope();
 };
 
 // ---------------------------------------------------------------------------
@@ -329,6 +385,12 @@ void dev_free(Context *ctx, DevMem &m);
 int upload(Context *ctx, DevMem &m, const void *src, size_t bytes);
 int hip_check(Context *ctx, hipError_t e, const char *what);
 int scratch_get(Context *ctx, size_t bytes, void **p);
+// record on `s` that plan tables were read there (no-op while `s` is captured)
+int note_use(Context *ctx, std::vector<StreamUse> &uses, hipStream_t s);
+// drop device tables that queued kernels may still read (stream-ordered)
+void retire(Context *ctx, std::vector<DevMem> mem, std::vector<StreamUse> uses);
+void retire_pauli_plan(Context *ctx, PauliPlan *p);
+void poll_retired(Context *ctx, bool wait);
 
 // jw.cpp
 int jordan_wigner(int n_orb, const double *h1, const double *h2, double e_core,

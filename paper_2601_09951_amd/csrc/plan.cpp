@@ -701,15 +701,8 @@ PauliPlan *get_pauli_plan(Context *ctx, int n_hams, Ham *const *hams, int n_inst
         return it->second.get();
     }
     // bound the cache: plans are small, but a serving loop creates many
-    if (ctx->pauli_cache.size() >= 256) {
-        if (ctx->device >= 0) (void)hipDeviceSynchronize();
-        for (auto &kv : ctx->pauli_cache) {
-            dev_free(ctx, kv.second->geoms);
-            dev_free(ctx, kv.second->wsrc);
-            dev_free(ctx, kv.second->groups);
-            dev_free(ctx, kv.second->toff);
-            dev_free(ctx, kv.second->terms);
-        }
+    if (ctx->pauli_cache.size() >= 256) {  // stream-ordered: no device synchronisation
+        for (auto &kv : ctx->pauli_cache) retire_pauli_plan(ctx, kv.second.get());
         ctx->pauli_cache.clear();
     }
 

@@ -50,19 +50,36 @@ class Result:
 
 
 class LibvqeExecutor:
-    """Executes batches with libvqe on one device (one HIP stream per class)."""
+    """Executes batches with libvqe on one device.
 
-    def __init__(self, ctx: vqe.Context, device: int = 0):
+    Batches run on a small fixed set of HIP streams (default priority): the
+    runtime maps streams onto a few hardware queues, and work of two streams
+    on one queue runs in order, so the longest batches (20 qubits and more)
+    get a stream of their own and the short classes spread over the others;
+    a short request then never waits behind a long batch.  Results are copied
+    to pinned host memory on the batch's own stream, and the completion event
+    follows that copy, so nothing runs on the null stream and collecting a
+    finished batch does not wait for the device.
+    """
+
+    def __init__(self, ctx: vqe.Context, device: int = 0, n_streams: int = 4):
         self.ctx = ctx
         self.dev = torch.device(f"cuda:{device}")
         self._circuits: Dict[str, vqe.Circuit] = {}
-        self._streams: Dict[tuple, torch.cuda.Stream] = {}
+        self._streams = [torch.cuda.Stream(device=self.dev) for _ in range(max(2, n_streams))]
 
     def _circuit(self, spec) -> vqe.Circuit:
         key = spec.shape_key()
         if key not in self._circuits:
             self._circuits[key] = vqe.Circuit.from_spec(self.ctx, spec)
         return self._circuits[key]
+
+    def stream_index(self, key) -> int:
+        n = key[0]
+        if n >= 20:
+            return 0
+        rest = len(self._streams) - 1
+        return 1 + min(rest - 1, (n - 1) // 4)
 
     def hamiltonian(self, req):
         if req.integrals is not None:
@@ -71,7 +88,7 @@ class LibvqeExecutor:
         return vqe.Hamiltonian.from_sum(self.ctx, req.pauli)
 
     def release(self, ham):
-        ham.close()
+        ham.close()  # stream-ordered in the library: no device synchronisation
 
     def request_bytes(self, key, req) -> int:
         """Upper estimate of one request's share of a batch workspace."""
@@ -86,35 +103,38 @@ class LibvqeExecutor:
     def launch(self, key, reqs, hams, nbytes):
         C = self._circuit(reqs[0].circuit)
         B = len(reqs)
-        if key not in self._streams:
-            self._streams[key] = torch.cuda.Stream(device=self.dev)  # default priority
-        s = self._streams[key]
+        s = self._streams[self.stream_index(key)]
         theta_h = torch.from_numpy(np.stack([r.theta for r in reqs]).astype(np.float64)).pin_memory()
         with torch.cuda.stream(s):
             theta = theta_h.to(self.dev, non_blocking=True)
             ws = torch.empty(nbytes, dtype=torch.uint8, device=self.dev)
             e = torch.empty(B, dtype=torch.float64, device=self.dev)
+            e_h = torch.empty(B, dtype=torch.float64, pin_memory=True)
             if key[2]:
                 g = torch.empty(B, C.n_params, dtype=torch.float64, device=self.dev)
                 vqe.energy_grad(self.ctx, C, hams, theta, ws=ws, out_e=e, out_g=g)
+                g_h = torch.empty(B, C.n_params, dtype=torch.float64, pin_memory=True)
+                g_h.copy_(g, non_blocking=True)
             else:
-                g = None
+                g = g_h = None
                 vqe.energy(self.ctx, C, hams, theta, ws=ws, out=e)
+            e_h.copy_(e, non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(s)
-        return {"theta": theta, "theta_h": theta_h, "ws": ws, "e": e, "g": g, "event": ev}
+        return {"theta": theta, "theta_h": theta_h, "ws": ws, "e": e, "g": g, "e_h": e_h, "g_h": g_h,
+                "event": ev}
 
     def done(self, handle) -> bool:
         return handle["event"].query()
 
     def collect(self, handle):
         handle["event"].synchronize()
-        e = handle["e"].cpu().numpy()
-        g = handle["g"].cpu().numpy() if handle["g"] is not None else None
+        e = handle["e_h"].numpy().copy()
+        g = handle["g_h"].numpy().copy() if handle["g_h"] is not None else None
         return e, g
 
     def drain(self):
-        for s in self._streams.values():
+        for s in self._streams:
             s.synchronize()
 
     def close(self):

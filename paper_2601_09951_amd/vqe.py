@@ -73,6 +73,20 @@ class Context:
         mode = 2 if staged is True else (0 if staged is False else int(staged))
         self.check(lib().vqe_ctx_set_staged(self._h, mode))
 
+    def set_profiling(self, on: bool = True):
+        """Time the pass, sweep and loop launches with HIP events on their streams."""
+        self.check(lib().vqe_ctx_set_profiling(self._h, 1 if on else 0))
+
+    def profile(self, reset: bool = True) -> dict:
+        """Per-kernel totals of the timed launches: {name: {launches, ms, bytes}}
+        (waits for the timed launches to finish)."""
+        cnt = ctypes.c_int()
+        self.check(lib().vqe_ctx_profile(self._h, None, 0, ctypes.byref(cnt), 0))
+        buf = (capi.KernelStat * max(1, cnt.value))()
+        self.check(lib().vqe_ctx_profile(self._h, buf, cnt.value, ctypes.byref(cnt), 1 if reset else 0))
+        return {buf[i].name.decode(): {"launches": int(buf[i].launches), "ms": float(buf[i].total_ms),
+                                       "bytes": float(buf[i].bytes)} for i in range(cnt.value)}
+
     def reserve(self, nbytes: int):
         self.check(lib().vqe_ctx_reserve(self._h, int(nbytes)))
 

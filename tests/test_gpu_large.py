@@ -5,10 +5,19 @@ what holds at any size:
 * a product state (RY then RZ on every wire, no entangler) against the Bloch
   closed form of single-qubit Pauli expectations: <Z> = cos a,
   <X> = sin a cos b, <Y> = sin a sin b (independent of the library);
-* the norm <psi|I|psi> = 1 after an entangling ansatz;
-* the energy from vqe_energy equals the one fused into vqe_energy_grad;
-* the adjoint gradient equals a parameter-shift gradient evaluated with the
-  library's own energy on sampled parameters (RY/RZ: [E(+pi/2) - E(-pi/2)]/2).
+* an entangled state: RY, RZ on every wire followed by the CNOT ladder
+  q -> q+1.  The ladder maps the computational basis by prefix XOR (wire q
+  ends up holding the parity of wires 0..q), so after it Z on wire q equals
+  Z_0 ... Z_q before it and Z_q Z_{q+1} equals Z_{q+1} before it: on the
+  product state <Z_q> = prod_{i<=q} cos a_i and <Z_q Z_{q+1}> = cos a_{q+1},
+  with the gradient following by differentiating the products (the RZ angles
+  drop out).  This reaches index bits above 31 through the fused CNOT store
+  maps, the sweeps and (at 30 qubits) the adjoint passes;
+* at the hardware-efficient configuration of 4 layers and 2000 random
+  strings: the norm <psi|I|psi> = 1, the energy from vqe_energy equals the
+  one fused into vqe_energy_grad, and the adjoint gradient equals a
+  parameter-shift gradient evaluated with the library's own energy on
+  sampled parameters (RY/RZ: [E(+pi/2) - E(-pi/2)]/2).
 """
 import math
 
@@ -49,6 +58,38 @@ def _product_case(n, seed):
     return spec, ham, theta, want
 
 
+def _ladder_case(n, seed):
+    """One hardware-efficient layer (RY, RZ on every wire, CNOT ladder) with
+    H = sum_q c_q Z_q + sum_q d_q Z_q Z_{q+1}; returns the closed-form energy
+    and gradient.  RY angles are drawn from U(-0.5, 0.5) so that the products
+    of cosines stay of order 0.01 or more on every wire."""
+    rng = np.random.default_rng(seed)
+    spec = synth.hea_circuit(n, 1)
+    theta = np.empty(spec.n_params)
+    a = rng.uniform(-0.5, 0.5, size=n)
+    theta[:n] = a                                   # RY on wire q: parameter q
+    theta[n:2 * n] = rng.uniform(-math.pi, math.pi, size=n)  # RZ: parameter n + q
+    c = rng.normal(size=n)
+    d = rng.normal(size=n - 1)
+    xs, zs, cs = [], [], []
+    for q in range(n):
+        x, z = synth.pauli_masks(n, [(q, "Z")])
+        xs.append(x), zs.append(z), cs.append(float(c[q]))
+    for q in range(n - 1):
+        x, z = synth.pauli_masks(n, [(q, "Z"), (q + 1, "Z")])
+        xs.append(x), zs.append(z), cs.append(float(d[q]))
+    ham = synth.PauliSum(n, np.array(xs, dtype=np.uint64), np.array(zs, dtype=np.uint64), np.array(cs))
+    prefix = np.cumprod(np.cos(a))  # <Z_q> after the ladder
+    energy = float(np.dot(c, prefix) + np.dot(d, np.cos(a[1:])))
+    grad = np.zeros(spec.n_params)
+    t = np.tan(a)
+    for i in range(n):
+        grad[i] = -t[i] * float(np.sum(c[i:] * prefix[i:]))  # d/da_i of prod_{j<=q} cos a_j, q >= i
+        if i >= 1:
+            grad[i] += -d[i - 1] * math.sin(a[i])
+    return spec, ham, theta, energy, grad
+
+
 @pytest.mark.parametrize("n", [30, 32])
 def test_product_state_closed_form(vqe, n):
     print("[case] product state", n, flush=True)
@@ -65,12 +106,39 @@ def test_product_state_closed_form(vqe, n):
     ctx.close()
 
 
+@pytest.mark.parametrize("n", [30, 32])
+def test_cnot_ladder_closed_form(vqe, n):
+    """Energy (32 qubits: one 64 GiB state) and, at 30 qubits, energy and
+    adjoint gradient of the entangled ladder state against its closed form."""
+    print("[case] CNOT ladder closed form", n, flush=True)
+    spec, ham, theta, want_e, want_g = _ladder_case(n, seed=100 + n)
+    ctx = vqe.Context(0)
+    C = vqe.Circuit.from_spec(ctx, spec)
+    H = vqe.Hamiltonian.from_sum(ctx, ham)
+    th = torch.tensor(theta[None, :], dtype=torch.float64, device="cuda:0")
+    e = vqe.energy(ctx, C, H, th)
+    torch.cuda.synchronize()
+    assert abs(e.item() - want_e) < 1e-10
+    torch.cuda.empty_cache()
+    if n <= 30:
+        e2, g = vqe.energy_grad(ctx, C, H, th)
+        torch.cuda.synchronize()
+        assert abs(e2.item() - want_e) < 1e-10
+        np.testing.assert_allclose(g.cpu().numpy()[0], want_g, atol=1e-9)
+        del e2, g
+        torch.cuda.empty_cache()
+    del C, H
+    ctx.close()
+
+
 def test_thirty_qubit_energy_grad_invariants(vqe):
+    """The 30-qubit configuration at its own shape: 4 layers (356 gates, 240
+    parameters) and 2000 random strings of weight <= 4."""
     n = 30
-    print("[case] 30-qubit invariants", flush=True)
-    spec = synth.hea_circuit(n, 1)
-    ham = synth.random_pauli_sum(n, 120, seed=30)
-    theta = synth.uniform_thetas(spec.n_params, 1, seed=30)
+    print("[case] 30-qubit invariants (4 layers, 2000 strings)", flush=True)
+    spec = synth.hea_circuit(n, 4)
+    ham = synth.random_pauli_sum(n, 2000, seed=synth.MASTER_SEED + n)
+    theta = synth.uniform_thetas(spec.n_params, 1, seed=synth.MASTER_SEED + n)
     ctx = vqe.Context(0)
     C = vqe.Circuit.from_spec(ctx, spec)
     H = vqe.Hamiltonian.from_sum(ctx, ham)
@@ -86,13 +154,14 @@ def test_thirty_qubit_energy_grad_invariants(vqe):
     assert abs(e.item() - e0.item()) < 1e-10
     g = g.cpu().numpy()[0]
     torch.cuda.empty_cache()
-    for p in (0, 7, n + 3, 2 * n - 1):
+    # RY of layer 0, RZ of layer 1, RY of the last wire of layer 2, RZ of layer 3
+    for p in (0, 2 * n + n + 7, 4 * n + n - 1, 6 * n + n + 13):
         tp, tm = theta.copy(), theta.copy()
         tp[0, p] += math.pi / 2
         tm[0, p] -= math.pi / 2
         ep = vqe.energy(ctx, C, H, torch.tensor(tp, device="cuda:0")).item()
         em = vqe.energy(ctx, C, H, torch.tensor(tm, device="cuda:0")).item()
-        assert abs(0.5 * (ep - em) - g[p]) < 1e-9
+        assert abs(0.5 * (ep - em) - g[p]) < 1e-9, p
     del C, H, I
     torch.cuda.empty_cache()
     ctx.close()

@@ -83,3 +83,49 @@ def test_plain_path_matches(mods, ctx):
     served = serve.Server(serve.LibvqeExecutor(ctx)).run(reqs)
     for a, b in zip(plain, served):
         assert abs(a.energy - b.energy) < 1e-10
+
+
+def test_short_requests_finish_while_a_long_batch_runs(mods, ctx):
+    """Continuous batching on the device: while a batch of 24-qubit energy +
+    gradient requests is in flight, single 4-qubit requests launched after it
+    complete (their own completion events fire) before it does, and their
+    results equal the same requests evaluated alone."""
+    serve, vqe = mods
+    print("[case] short requests beside a long batch", flush=True)
+    ex = serve.LibvqeExecutor(ctx)
+    big = [r for r in synth.served_requests(600, 1000.0, seed=21) if r.n == 24 and r.want_grad][:8]
+    small = synth.served_requests(24, 1000.0, seed=22, mix=((4, 1.0),))
+    assert len(big) == 8
+
+    def run_one(r):
+        k = serve.Server._class(r)
+        hs = [ex.hamiltonian(r)]
+        return k, hs, ex.launch(k, [r], hs, ex.batch_bytes(k, [r], hs))
+
+    k, hs, h = run_one(small[0])  # warm the small class (plans, code objects)
+    ex.collect(h)
+    ex.release(hs[0])
+    kb = serve.Server._class(big[0])
+    hb = [ex.hamiltonian(r) for r in big]
+    hbig = ex.launch(kb, big, hb, ex.batch_bytes(kb, big, hb))
+    before, got = 0, []
+    for r in small[1:]:
+        k, hs, h = run_one(r)
+        h["event"].synchronize()  # waits for this request's own stream only
+        if not ex.done(hbig):
+            before += 1
+        got.append((r, ex.collect(h)))
+        ex.release(hs[0])
+    big_done_last = not ex.done(hbig) or before == len(small) - 1
+    ex.collect(hbig)
+    for hm in hb:
+        ex.release(hm)
+    ex.close()
+    for r, (e, g) in got:
+        if r.want_grad:
+            e1, g1 = _alone(vqe, ctx, r)
+            assert abs(e[0] - e1) < 1e-10
+            np.testing.assert_allclose(g[0], g1, atol=1e-9)
+    print(f"[case] {before} of {len(small) - 1} short requests finished before the long batch "
+          f"(long batch still running at the end: {big_done_last})", flush=True)
+    assert before >= 1, "every short request waited for the long batch"

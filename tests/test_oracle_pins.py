@@ -450,6 +450,27 @@ def test_adam_constant_gradient_closed_form():
         np.testing.assert_allclose(theta - before, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=1e-18)
 
 
+def test_adam_varying_gradient_hand_computed():
+    # Three steps with a gradient that changes sign and size, beta1 != beta2,
+    # eps = 0, so that the moment recurrences (and which beta belongs to which
+    # moment) decide the result.  Values worked by hand from Kingma and Ba's
+    # Algorithm 1 with beta1 = 1/2, beta2 = 3/4, lr = 1/10, g = 1, -2, 3:
+    #   t=1: m = 1/2,   v = 1/4,      m^ = 1,    v^ = 1        -> step -1/10
+    #   t=2: m = -3/4,  v = 19/16,    m^ = -1,   v^ = 19/7     -> step +(1/10) sqrt(7/19)
+    #   t=3: m = 9/8,   v = 201/64,   m^ = 9/7,  v^ = 201/37   -> step -(1/10)(9/7) sqrt(37/201)
+    # With the betas swapped, step 2 would be +(1/10)(5/7)/sqrt(3) instead.
+    want_steps = [-0.1, 0.1 * math.sqrt(7 / 19), -0.1 * (9 / 7) * math.sqrt(37 / 201)]
+    want_m = [0.5, -0.75, 1.125]
+    want_v = [0.25, 19 / 16, 201 / 64]
+    theta, m, v = np.zeros(1), np.zeros(1), np.zeros(1)
+    for t, g in enumerate([1.0, -2.0, 3.0], start=1):
+        before = theta.copy()
+        oracle.adam_step(theta, m, v, np.array([g]), t, lr=0.1, b1=0.5, b2=0.75, eps=0.0)
+        assert abs((theta - before)[0] - want_steps[t - 1]) < 1e-15
+        assert abs(m[0] - want_m[t - 1]) < 1e-15 and abs(v[0] - want_v[t - 1]) < 1e-15
+    assert abs(theta[0] - sum(want_steps)) < 1e-15
+
+
 def test_vqe_gd_loop_follows_closed_form_derivative():
     # Gradient descent driven by the closed-form derivative of the C1 curve.
     ham = fermion.qubit_hamiltonian(synth.random_integrals(2, seed=synth.MASTER_SEED))
