@@ -159,6 +159,18 @@ int vqe_ctx_set_profiling(vqe_ctx_t ctx, int on);
  * when capacity is 0. */
 int vqe_ctx_profile(vqe_ctx_t ctx, vqe_kernel_stat *out, int capacity, int *count, int reset);
 
+/* ---- streams for concurrent callers ------------------------------------
+ * A HIP stream (default priority, every compute unit) on a hardware queue of
+ * its own.  The runtime maps ordinary streams onto a small pool of hardware
+ * queues, and the work of streams that share a queue runs in submission
+ * order; a serving loop that lets short requests pass a long batch therefore
+ * runs each request class on such a stream.  *stream receives a hipStream_t
+ * owned by the caller until vqe_stream_destroy (which does not wait for the
+ * stream's work).  Errors: EINVAL (NULL out), EUNSUPPORTED (host-only
+ * context), EHIP. */
+int vqe_stream_create(vqe_ctx_t ctx, void **stream);
+int vqe_stream_destroy(vqe_ctx_t ctx, void *stream);
+
 /* Text of the last error on this context (never NULL). */
 const char *vqe_last_error(vqe_ctx_t ctx);
 

@@ -34,7 +34,7 @@ EXPORTED = [
     "vqe_apply_hamiltonian", "vqe_energy_grad", "vqe_grad_shift", "vqe_adam_step", "vqe_run",
     "vqe_circ_plan_export", "vqe_ham_plan_export",
     "vqe_hfam_create", "vqe_hfam_info", "vqe_hfam_member", "vqe_hfam_set_integrals", "vqe_hfam_destroy",
-    "vqe_ctx_set_profiling", "vqe_ctx_profile",
+    "vqe_ctx_set_profiling", "vqe_ctx_profile", "vqe_stream_create", "vqe_stream_destroy",
 ]
 
 
@@ -96,6 +96,8 @@ def _declare(L):
         "vqe_hfam_destroy": [P],
         "vqe_ctx_set_profiling": [P, i32],
         "vqe_ctx_profile": [P, P, i32, P, i32],
+        "vqe_stream_create": [P, PP],
+        "vqe_stream_destroy": [P, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)

@@ -144,6 +144,7 @@ void retire(Context *ctx, std::vector<DevMem> mem, std::vector<StreamUse> uses)
 
 void retire_pauli_plan(Context *ctx, PauliPlan *p)
 {
+    ready_free(p->ready);  // destroying a pending event is deferred by the runtime
     retire(ctx, {p->groups, p->geoms, p->wsrc, p->toff, p->terms}, std::move(p->uses));
     p->groups = p->geoms = p->wsrc = p->toff = p->terms = DevMem{};
     p->uses.clear();
@@ -234,8 +235,67 @@ ProfScope::~ProfScope()
     ctx->prof_pending.push_back(Context::ProfRec{name, bytes, e0, e1});
 }
 
-// Host data to a new device table: staged through pinned memory and copied on
-// the context's own stream, so the host waits for this copy only.
+namespace {
+constexpr size_t kStageChunk = 4u << 20;  // pinned staging chunk
+
+// `bytes` of pinned staging: appended to a chunk with room, else a chunk whose
+// copies have all completed is reused, else a new chunk is allocated
+int stage_take(Context *ctx, size_t bytes, void **p, size_t *chunk)
+{
+    const size_t need = (bytes + 255) & ~(size_t)255;
+    for (size_t i = 0; i < ctx->stage_chunks.size(); ++i) {
+        Context::StageChunk &c = ctx->stage_chunks[i];
+        if (c.off + need <= c.bytes) {
+            *p = static_cast<unsigned char *>(c.p) + c.off;
+            c.off += need;
+            *chunk = i;
+            return VQE_OK;
+        }
+    }
+    for (size_t i = 0; i < ctx->stage_chunks.size(); ++i) {
+        Context::StageChunk &c = ctx->stage_chunks[i];
+        if (c.bytes >= need && events_done(c.uses)) {
+            for (StreamUse &u : c.uses) (void)hipEventDestroy(u.event);
+            c.uses.clear();
+            *p = c.p;
+            c.off = need;
+            *chunk = i;
+            return VQE_OK;
+        }
+    }
+    Context::StageChunk c;
+    c.bytes = std::max(need, kStageChunk);
+    int r = hip_check(ctx, hipHostMalloc(&c.p, c.bytes, hipHostMallocDefault), "hipHostMalloc (staging)");
+    if (r) return r;
+    c.off = need;
+    *p = c.p;
+    *chunk = ctx->stage_chunks.size();
+    ctx->stage_chunks.push_back(std::move(c));
+    return VQE_OK;
+}
+}  // namespace
+
+int dedicated_stream(Context *ctx, hipStream_t *out)
+{
+    // A stream with a compute-unit mask gets a hardware queue of its own
+    // instead of sharing one of the process's pooled queues with other
+    // streams (work of streams sharing a queue runs in order).  The mask
+    // enables every compute unit; the priority is the default.
+    std::vector<uint32_t> mask((ctx->cu_count + 31) / 32, 0xffffffffu);
+    if (ctx->cu_count % 32) mask.back() = (1u << (ctx->cu_count % 32)) - 1;
+    hipError_t e = hipExtStreamCreateWithCUMask(out, (uint32_t)mask.size(), mask.data());
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return hip_check(ctx, hipStreamCreateWithFlags(out, hipStreamNonBlocking), "hipStreamCreate");
+    }
+    return VQE_OK;
+}
+
+// Host data to a new device table, staged through pinned memory.  Inside a
+// call that enqueues work the copy goes on that call's stream (later work of
+// the call is ordered after it; other streams wait through the plan's Ready
+// event); otherwise on the context's upload stream, followed by upload_ev.
+// The host never waits for a copy.
 int upload(Context *ctx, DevMem &m, const void *src, size_t bytes)
 {
     if (ctx->device < 0) {  // host-only planning context: plans keep host copies only
@@ -245,35 +305,99 @@ int upload(Context *ctx, DevMem &m, const void *src, size_t bytes)
     int r = dev_alloc(ctx, m, bytes);
     if (r) return r;
     if (!bytes) return VQE_OK;
-    if (!ctx->upload_stream) {
-        r = hip_check(ctx, hipStreamCreateWithFlags(&ctx->upload_stream, hipStreamNonBlocking), "hipStreamCreate");
-        if (r) return r;
+    hipStream_t s;
+    if (ctx->in_call) {
+        s = ctx->cur_stream;
+        if (capturing(s)) {
+            dev_free(ctx, m);
+            return set_err(ctx, VQE_EINVAL,
+                           "device tables would be uploaded inside a stream capture: make the same call once "
+                           "before capturing");
+        }
+    } else {
+        if (!ctx->upload_stream) {
+            r = dedicated_stream(ctx, &ctx->upload_stream);
+            if (!r) r = hip_check(ctx, hipEventCreateWithFlags(&ctx->upload_ev, hipEventDisableTiming),
+                                  "hipEventCreate");
+            if (r) return r;
+        }
+        s = ctx->upload_stream;
     }
-    if (ctx->staging_bytes < bytes) {
-        // the old buffer may be the source of a copy still in flight: kept until the context goes
-        if (ctx->staging) ctx->old_staging.push_back(ctx->staging);
-        const size_t want = std::max<size_t>(bytes, std::max<size_t>(2 * ctx->staging_bytes, 1u << 20));
-        ctx->staging = nullptr;
-        ctx->staging_bytes = 0;
-        r = hip_check(ctx, hipHostMalloc(&ctx->staging, want, hipHostMallocDefault), "hipHostMalloc (staging)");
-        if (r) return r;
-        ctx->staging_bytes = want;
-    }
-    std::memcpy(ctx->staging, src, bytes);
-    r = hip_check(ctx, hipMemcpyAsync(m.p, ctx->staging, bytes, hipMemcpyHostToDevice, ctx->upload_stream),
-                  "hipMemcpyAsync (upload)");
+    void *stage = nullptr;
+    size_t ci = 0;
+    r = stage_take(ctx, bytes, &stage, &ci);
     if (r) return r;
-    return hip_check(ctx, hipStreamSynchronize(ctx->upload_stream), "upload");
+    std::memcpy(stage, src, bytes);
+    r = hip_check(ctx, hipMemcpyAsync(m.p, stage, bytes, hipMemcpyHostToDevice, s), "hipMemcpyAsync (upload)");
+    if (!r) r = note_use(ctx, ctx->stage_chunks[ci].uses, s);
+    if (!r && !ctx->in_call) r = hip_check(ctx, hipEventRecord(ctx->upload_ev, s), "hipEventRecord");
+    return r;
+}
+
+StreamCall::StreamCall(Context *c, hipStream_t s) : ctx(c), prev_in(c->in_call), prev(c->cur_stream)
+{
+    c->in_call = true;
+    c->cur_stream = s;
+    if (c->device < 0 || !c->upload_ev) return;
+    hipError_t q = hipEventQuery(c->upload_ev);
+    if (q == hipSuccess) return;
+    if (q != hipErrorNotReady) {
+        rc = hip_check(c, q, "upload event");
+        return;
+    }
+    if (capturing(s)) {
+        rc = set_err(c, VQE_EINVAL, "uploads still in flight when a captured call began");
+        return;
+    }
+    rc = hip_check(c, hipStreamWaitEvent(s, c->upload_ev, 0), "hipStreamWaitEvent (uploads)");
+}
+
+StreamCall::~StreamCall()
+{
+    ctx->in_call = prev_in;
+    ctx->cur_stream = prev;
+}
+
+void ready_mark(Context *ctx, Ready &r)
+{
+    if (ctx->device < 0 || !ctx->in_call) return;  // outside a call: covered by upload_ev
+    if (!r.ev && hipEventCreateWithFlags(&r.ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        r.ev = nullptr;
+        return;
+    }
+    if (hipEventRecord(r.ev, ctx->cur_stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    r.s = ctx->cur_stream;
+}
+
+int ready_wait(Context *ctx, Ready &r)
+{
+    if (!r.ev || !ctx->in_call || r.s == ctx->cur_stream) return VQE_OK;
+    hipError_t q = hipEventQuery(r.ev);
+    if (q == hipSuccess) return VQE_OK;
+    if (q != hipErrorNotReady) return hip_check(ctx, q, "table upload event");
+    if (capturing(ctx->cur_stream))
+        return set_err(ctx, VQE_EINVAL, "tables still uploading on another stream when a captured call began");
+    return hip_check(ctx, hipStreamWaitEvent(ctx->cur_stream, r.ev, 0), "hipStreamWaitEvent (tables)");
+}
+
+void ready_free(Ready &r)
+{
+    if (r.ev) (void)hipEventDestroy(r.ev);
+    r = Ready{};
 }
 
 int scratch_get(Context *ctx, size_t bytes, void **p)
 {
     if (ctx->scratch.bytes < bytes) {
+        // the old buffer may still be read by queued work: recycled once that has run
         if (ctx->scratch.p) {
-            // the old buffer may still be read by queued work
-            int r = hip_check(ctx, hipDeviceSynchronize(), "hipDeviceSynchronize");
-            if (r) return r;
-            dev_free(ctx, ctx->scratch);
+            retire(ctx, {ctx->scratch}, std::move(ctx->scratch_uses));
+            ctx->scratch = DevMem{};
+            ctx->scratch_uses.clear();
         }
         size_t want = std::max<size_t>(bytes, 1 << 20);
         int r = dev_alloc(ctx, ctx->scratch, want);
@@ -620,7 +744,7 @@ int energy_grad_into(Context *ctx, Circ *C, int n_hams, Ham *const *H, int64_t B
 
 int build_shift(Context *ctx, Circ *C)
 {
-    if (C->shift_rows > 0) return VQE_OK;
+    if (C->shift_rows > 0) return ready_wait(ctx, C->shift_ready);
     const double dp = (std::sqrt(2.0) + 1.0) / (4.0 * std::sqrt(2.0));
     const double dm = (std::sqrt(2.0) - 1.0) / (4.0 * std::sqrt(2.0));
     const double h = 0.5 * M_PI;
@@ -665,6 +789,7 @@ int build_shift(Context *ctx, Circ *C)
         return rc;
     }
     C->shift_rows = (int)rows.size();
+    ready_mark(ctx, C->shift_ready);
     return VQE_OK;
 }
 
@@ -735,11 +860,35 @@ int vqe_ctx_destroy(vqe_ctx_t ctx)
     dev_free(ctx, ctx->scratch);
     for (void *p : ctx->pool_chunks) (void)hipFree(p);
     ctx->pool_chunks.clear();
-    if (ctx->staging) (void)hipHostFree(ctx->staging);
-    for (void *p : ctx->old_staging) (void)hipHostFree(p);
+    for (Context::StageChunk &c : ctx->stage_chunks) {
+        for (StreamUse &u : c.uses) (void)hipEventDestroy(u.event);
+        (void)hipHostFree(c.p);
+    }
+    for (StreamUse &u : ctx->scratch_uses) (void)hipEventDestroy(u.event);
+    if (ctx->upload_ev) (void)hipEventDestroy(ctx->upload_ev);
     if (ctx->upload_stream) (void)hipStreamDestroy(ctx->upload_stream);
     delete ctx;
     return VQE_OK;
+}
+
+int vqe_stream_create(vqe_ctx_t ctx, void **stream)
+{
+    int rc = check_dev(ctx);
+    if (rc) return rc;
+    if (!stream) return set_err(ctx, VQE_EINVAL, "stream is NULL");
+    hipStream_t s = nullptr;
+    rc = dedicated_stream(ctx, &s);
+    if (rc) return rc;
+    *stream = s;
+    return VQE_OK;
+}
+
+int vqe_stream_destroy(vqe_ctx_t ctx, void *stream)
+{
+    int rc = check_dev(ctx);
+    if (rc) return rc;
+    if (!stream) return set_err(ctx, VQE_EINVAL, "stream is NULL");
+    return hip_check(ctx, hipStreamDestroy((hipStream_t)stream), "hipStreamDestroy");
 }
 
 int vqe_ctx_set_mem_budget(vqe_ctx_t ctx, size_t bytes)
@@ -942,9 +1091,13 @@ int vqe_hfam_create(vqe_ctx_t ctx, int n_orb, int64_t capacity, vqe_hfam_t *out)
     if (!rc) rc = upload(ctx, f->d_col, f->col.data(), f->col.size() * 4);
     if (!rc) rc = upload(ctx, f->d_val, f->val.data(), f->val.size() * 8);
     if (!rc && ctx->device >= 0) {
+        // zeroed on the upload stream (the uploads above created it): calls
+        // wait for upload_ev, recorded after the fill
         rc = dev_alloc(ctx, f->d_coef, (size_t)capacity * T * 8);
-        if (!rc) rc = hip_check(ctx, launch_fill((double *)f->d_coef.p, capacity * (int64_t)T, 0.0, nullptr), "zero");
-        if (!rc) rc = hip_check(ctx, hipDeviceSynchronize(), "zero coefficients");
+        if (!rc)
+            rc = hip_check(ctx, launch_fill((double *)f->d_coef.p, capacity * (int64_t)T, 0.0, ctx->upload_stream),
+                           "zero");
+        if (!rc) rc = hip_check(ctx, hipEventRecord(ctx->upload_ev, ctx->upload_stream), "hipEventRecord");
     }
     if (rc) {
         dev_free(ctx, f->d_row);
@@ -989,6 +1142,8 @@ int vqe_hfam_set_integrals(vqe_ctx_t ctx, vqe_hfam_t fam, int64_t first, int64_t
 {
     int rc = check_dev(ctx);
     if (rc) return rc;
+    StreamCall call(ctx, (hipStream_t)stream);
+    if (call.rc) return call.rc;
     if (!fam || fam->ctx != ctx || !integrals || first < 0 || count < 1 || first + count > fam->capacity)
         return set_err(ctx, VQE_EINVAL, "bad family range or pointer");
     const int64_t T = (int64_t)fam->x.size();
@@ -1112,13 +1267,8 @@ int vqe_circ_destroy(vqe_circ_t C)
         (void)hipSetDevice(ctx->device);
         (void)hipDeviceSynchronize();
     }
-    for (auto *cache : {&C->fwd, &C->rev})
-        for (auto &kv : *cache) {
-            dev_free(ctx, kv.second->ops);
-            dev_free(ctx, kv.second->geoms);
-            dev_free(ctx, kv.second->stages);
-            dev_free(ctx, kv.second->sops);
-        }
+    free_circ_plans(ctx, C);
+    ready_free(C->shift_ready);
     dev_free(ctx, C->gates_dev);
     dev_free(ctx, C->pmap_off);
     dev_free(ctx, C->pmap_idx);
@@ -1153,6 +1303,8 @@ int vqe_prepare_reference(vqe_ctx_t ctx, int n_qubits, int64_t batch, uint64_t r
 {
     int rc = check_dev(ctx);
     if (rc) return rc;
+    StreamCall call(ctx, (hipStream_t)stream);
+    if (call.rc) return call.rc;
     if (n_qubits < 1 || n_qubits > VQE_MAX_QUBITS) return set_err(ctx, VQE_EUNSUPPORTED, "n_qubits");
     if (!psi || batch < 1) return set_err(ctx, VQE_EINVAL, "psi NULL or batch < 1");
     if (batch > kMaxBatch) return set_err(ctx, VQE_EUNSUPPORTED, "batch > 65535");
@@ -1166,6 +1318,8 @@ int vqe_apply_ansatz(vqe_ctx_t ctx, vqe_circ_t circ, int64_t batch, const double
 {
     int rc = check_dev(ctx);
     if (rc) return rc;
+    StreamCall call(ctx, (hipStream_t)stream);
+    if (call.rc) return call.rc;
     if (!circ || !psi || batch < 1 || (circ->n_params > 0 && !theta))
         return set_err(ctx, VQE_EINVAL, "bad argument");
     if (batch > kMaxBatch) return set_err(ctx, VQE_EUNSUPPORTED, "batch > 65535");
@@ -1175,7 +1329,9 @@ int vqe_apply_ansatz(vqe_ctx_t ctx, vqe_circ_t circ, int64_t batch, const double
     void *mats;
     rc = scratch_get(ctx, (size_t)batch * nmats * 64, &mats);
     if (rc) return rc;
-    return forward(ctx, circ, batch, theta, (double2 *)psi, (double2 *)mats, (hipStream_t)stream);
+    rc = forward(ctx, circ, batch, theta, (double2 *)psi, (double2 *)mats, (hipStream_t)stream);
+    if (rc) return rc;
+    return note_use(ctx, ctx->scratch_uses, (hipStream_t)stream);
 }
 
 int vqe_expect(vqe_ctx_t ctx, int n_hams, const vqe_ham_t *hams, int64_t batch, const void *psi,
@@ -1183,6 +1339,8 @@ int vqe_expect(vqe_ctx_t ctx, int n_hams, const vqe_ham_t *hams, int64_t batch, 
 {
     int rc = check_dev(ctx);
     if (rc) return rc;
+    StreamCall call(ctx, (hipStream_t)stream);
+    if (call.rc) return call.rc;
     if (!psi || !energy || batch < 1) return set_err(ctx, VQE_EINVAL, "bad argument");
     if (!hams || n_hams < 1 || !hams[0]) return set_err(ctx, VQE_EINVAL, "no Hamiltonian");
     std::vector<Ham *> H;
@@ -1195,8 +1353,10 @@ int vqe_expect(vqe_ctx_t ctx, int n_hams, const vqe_ham_t *hams, int64_t batch, 
     void *part;
     rc = scratch_get(ctx, (size_t)batch * pp->sweeps.size() * wg_for(ctx, n, ctx->k_fwd) * 8, &part);
     if (rc) return rc;
-    return expect_into(ctx, n_hams, H.data(), batch, (const double2 *)psi, energy, 1, (double *)part,
-                       (hipStream_t)stream);
+    rc = expect_into(ctx, n_hams, H.data(), batch, (const double2 *)psi, energy, 1, (double *)part,
+                     (hipStream_t)stream);
+    if (rc) return rc;
+    return note_use(ctx, ctx->scratch_uses, (hipStream_t)stream);
 }
 
 int vqe_apply_hamiltonian(vqe_ctx_t ctx, int n_hams, const vqe_ham_t *hams, int64_t batch,
@@ -1204,6 +1364,8 @@ int vqe_apply_hamiltonian(vqe_ctx_t ctx, int n_hams, const vqe_ham_t *hams, int6
 {
     int rc = check_dev(ctx);
     if (rc) return rc;
+    StreamCall call(ctx, (hipStream_t)stream);
+    if (call.rc) return call.rc;
     if (!psi || !out || batch < 1 || psi == out) return set_err(ctx, VQE_EINVAL, "bad argument");
     if (!hams || n_hams < 1 || !hams[0]) return set_err(ctx, VQE_EINVAL, "no Hamiltonian");
     std::vector<Ham *> H;
@@ -1226,6 +1388,8 @@ int vqe_apply_hamiltonian(vqe_ctx_t ctx, int n_hams, const vqe_ham_t *hams, int6
                        "H psi sweep");
         if (rc) return rc;
     }
+    rc = note_use(ctx, ctx->scratch_uses, (hipStream_t)stream);
+    if (rc) return rc;
     return note_use(ctx, pp->uses, (hipStream_t)stream);
 }
 
@@ -1235,6 +1399,8 @@ int vqe_energy(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams
 {
     int rc = check_dev(ctx);
     if (rc) return rc;
+    StreamCall call(ctx, (hipStream_t)stream);
+    if (call.rc) return call.rc;
     if (!circ || !energy || !workspace || batch < 1 || (circ->n_params > 0 && !theta))
         return set_err(ctx, VQE_EINVAL, "bad argument");
     if (ref_index >> circ->n) return set_err(ctx, VQE_EINVAL, "ref_index >= 2^n");
@@ -1261,6 +1427,8 @@ int vqe_energy_grad(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t 
 {
     int rc = check_dev(ctx);
     if (rc) return rc;
+    StreamCall call(ctx, (hipStream_t)stream);
+    if (call.rc) return call.rc;
     if (!circ || !energy || !grad || !workspace || batch < 1 || (circ->n_params > 0 && !theta))
         return set_err(ctx, VQE_EINVAL, "bad argument");
     if (ref_index >> circ->n) return set_err(ctx, VQE_EINVAL, "ref_index >= 2^n");
@@ -1281,6 +1449,8 @@ int vqe_grad_shift(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *
 {
     int rc = check_dev(ctx);
     if (rc) return rc;
+    StreamCall call(ctx, (hipStream_t)stream);
+    if (call.rc) return call.rc;
     if (!circ || !energy || !grad || !workspace || batch < 1 || (circ->n_params > 0 && !theta))
         return set_err(ctx, VQE_EINVAL, "bad argument");
     if (ref_index >> circ->n) return set_err(ctx, VQE_EINVAL, "ref_index >= 2^n");
@@ -1341,6 +1511,8 @@ int vqe_adam_step(vqe_ctx_t ctx, int64_t batch, int32_t n_params, double *theta,
 {
     int rc = check_dev(ctx);
     if (rc) return rc;
+    StreamCall call(ctx, (hipStream_t)stream);
+    if (call.rc) return call.rc;
     if (batch < 1 || n_params < 0 || t < 1 || !theta || !m || !v || !grad)
         return set_err(ctx, VQE_EINVAL, "bad argument");
     return hip_check(ctx, launch_adam(batch * n_params, theta, m, v, grad, t, lr, b1, b2, eps,
@@ -1371,6 +1543,8 @@ int vqe_run(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams, i
 {
     int rc = check_dev(ctx);
     if (rc) return rc;
+    StreamCall call(ctx, (hipStream_t)stream);
+    if (call.rc) return call.rc;
     if (!circ || !energies || !workspace || batch < 1 || iters < 0 || (circ->n_params > 0 && !theta))
         return set_err(ctx, VQE_EINVAL, "bad argument");
     if (optimizer != VQE_OPT_ADAM && optimizer != VQE_OPT_GD) return set_err(ctx, VQE_EINVAL, "optimizer");

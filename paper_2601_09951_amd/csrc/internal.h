@@ -183,6 +183,16 @@ struct StreamUse {
     hipEvent_t event;
 };
 
+// Device tables uploaded during a call that enqueues work on a stream are
+// copied on that stream (no host wait); `ev` is recorded there after the
+// copies, and a call on another stream waits for it on the device before
+// reading the tables.  Tables uploaded by calls without a stream go through
+// the context's upload stream and are covered by Context::upload_ev.
+struct Ready {
+    hipEvent_t ev = nullptr;
+    hipStream_t s = nullptr;
+};
+
 struct Context;
 
 struct HamFamily;
@@ -264,6 +274,7 @@ struct CircPlan {
     std::vector<int32_t> host_fslot_off{0}, host_fslot_gate;
     std::vector<int32_t> host_fslot_info;  // per slot entry: (pgate + 1) << 4 | class << 2 | generator
     int n_fslots() const { return (int)host_fslot_off.size() - 1; }
+    Ready ready;             // where the device tables were uploaded
 };
 
 // Parameter-shift schedule of a circuit: row r of an instance evaluates the
@@ -289,6 +300,7 @@ struct Circ {
     int shift_rows = 0;              // rows per instance of the parameter-shift schedule
     DevMem shift_tab;                // ShiftRow[shift_rows]
     DevMem shift_off, shift_row, shift_coef;  // CSR param -> (row, coefficient)
+    Ready shift_ready;
 };
 
 // Union Pauli plan for a list of Hamiltonians on one tile geometry.
@@ -312,6 +324,7 @@ struct PauliPlan {
     const HamFamily *fam = nullptr;  // weights refreshed from the family's device coefficients
     DevMem wsrc;                     // WeightSrc[terms] when fam is set
     std::vector<StreamUse> uses;     // where the tables were read (recycling is stream-ordered)
+    Ready ready;                     // where the tables were uploaded
 };
 
 struct Context {
@@ -325,6 +338,7 @@ struct Context {
     int fuse = 1;               // forward and adjoint passes: fused stages where the plan has them
     std::string err;
     DevMem scratch;
+    std::vector<StreamUse> scratch_uses;  // streams that read the scratch buffer (growth is stream-ordered)
     std::map<std::string, std::unique_ptr<PauliPlan>> pauli_cache;
     uint64_t next_id = 1;
     int cu_count = 256;
@@ -340,12 +354,24 @@ struct Context {
         std::vector<StreamUse> uses;
     };
     std::vector<Retired> retired;
-    // uploads: pinned staging copied on a context stream of its own, so a
-    // table upload waits only for its own copy, never for queued kernels
+    // The call in progress (set by StreamCall): uploads made inside a call
+    // that enqueues work are copied on its stream, so a request never waits
+    // on the host for another stream's work.
+    bool in_call = false;
+    hipStream_t cur_stream = nullptr;
+    // Uploads made outside such a call (creating circuits and families) are
+    // copied on the context's upload stream (a hardware queue of its own);
+    // upload_ev follows the latest, and every call waits for it on the device
+    // while it is pending.
     hipStream_t upload_stream = nullptr;
-    void *staging = nullptr;
-    size_t staging_bytes = 0;
-    std::vector<void *> old_staging;
+    hipEvent_t upload_ev = nullptr;
+    // pinned staging for uploads: chunks reused once the copies from them completed
+    struct StageChunk {
+        void *p = nullptr;
+        size_t bytes = 0, off = 0;
+        std::vector<StreamUse> uses;
+    };
+    std::vector<StageChunk> stage_chunks;
     // kernel timing (vqe_ctx_set_profiling): an event pair around every
     // timed launch, on the launch's own stream, folded into totals when read
     int profile = 0;
@@ -385,6 +411,22 @@ void dev_free(Context *ctx, DevMem &m);
 int upload(Context *ctx, DevMem &m, const void *src, size_t bytes);
 int hip_check(Context *ctx, hipError_t e, const char *what);
 int scratch_get(Context *ctx, size_t bytes, void **p);
+// Held by every entry point that enqueues work on `s` (see Context::in_call);
+// rc is the status of waiting for pending uploads.
+struct StreamCall {
+    Context *ctx;
+    bool prev_in;
+    hipStream_t prev;
+    int rc = 0;
+    StreamCall(Context *c, hipStream_t s);
+    ~StreamCall();
+};
+// after a set of tables was uploaded / before reading them on ctx->cur_stream
+void ready_mark(Context *ctx, Ready &r);
+int ready_wait(Context *ctx, Ready &r);
+void ready_free(Ready &r);
+// a stream on a hardware queue of its own (all compute units, default priority)
+int dedicated_stream(Context *ctx, hipStream_t *out);
 // record on `s` that plan tables were read there (no-op while `s` is captured)
 int note_use(Context *ctx, std::vector<StreamUse> &uses, hipStream_t s);
 // drop device tables that queued kernels may still read (stream-ordered)
@@ -406,6 +448,7 @@ int jordan_wigner_linear(int n_orb, std::vector<uint64_t> &xo, std::vector<uint6
 int build_circuit_gates(Circ *C, int64_t n_gates, const int32_t *kind, const int32_t *wires,
                         const int32_t *pidx, const double *fixed, std::string &err);
 CircPlan *get_circ_plan(Circ *C, bool reverse, int k, int c, int *rc);
+void free_circ_plans(Context *ctx, Circ *C);  // immediate: the caller has synchronised
 PauliPlan *get_pauli_plan(Context *ctx, int n_hams, Ham *const *hams, int n_inst, int k, int c,
                           int *rc);
 TileGeom make_geom(int n, int k, int c, const std::vector<int> &tile_bits);

@@ -186,6 +186,15 @@ static void free_plan(Context *ctx, CircPlan *p)
         dev_free(ctx, p->fslot_gate);
         dev_free(ctx, p->fslot_info);
         dev_free(ctx, p->fphases);
+        ready_free(p->ready);
+    }
+}
+
+void free_circ_plans(Context *ctx, Circ *C)
+{
+    for (auto *cache : {&C->fwd, &C->rev}) {
+        for (auto &kv : *cache) free_plan(ctx, kv.second.get());
+        cache->clear();
     }
 }
 
@@ -511,8 +520,8 @@ CircPlan *get_circ_plan(Circ *C, bool reverse, int k, int c, int *rc)
     auto key = std::make_pair(keff, ceff);
     auto it = cache.find(key);
     if (it != cache.end()) {
-        *rc = VQE_OK;
-        return it->second.get();
+        *rc = ready_wait(C->ctx, it->second->ready);
+        return *rc ? nullptr : it->second.get();
     }
     std::unique_ptr<CircPlan> plan(new CircPlan);
     plan->k = keff;
@@ -677,6 +686,7 @@ CircPlan *get_circ_plan(Circ *C, bool reverse, int k, int c, int *rc)
         }
     }
     plan->host_ops = std::move(ops);
+    ready_mark(C->ctx, plan->ready);
     CircPlan *out = plan.get();
     cache[key] = std::move(plan);
     *rc = VQE_OK;
@@ -697,8 +707,8 @@ PauliPlan *get_pauli_plan(Context *ctx, int n_hams, Ham *const *hams, int n_inst
     for (int i = 0; i < n_hams; ++i) key << ':' << hams[i]->id;
     auto it = ctx->pauli_cache.find(key.str());
     if (it != ctx->pauli_cache.end()) {
-        *rc = VQE_OK;
-        return it->second.get();
+        *rc = ready_wait(ctx, it->second->ready);
+        return *rc ? nullptr : it->second.get();
     }
     // bound the cache: plans are small, but a serving loop creates many
     if (ctx->pauli_cache.size() >= 256) {  // stream-ordered: no device synchronisation
@@ -862,6 +872,7 @@ PauliPlan *get_pauli_plan(Context *ctx, int n_hams, Ham *const *hams, int n_inst
     plan->host_groups = std::move(gdev);
     plan->host_toff = std::move(toff);
     plan->host_terms = std::move(terms);
+    ready_mark(ctx, plan->ready);
     PauliPlan *out = plan.get();
     ctx->pauli_cache[key.str()] = std::move(plan);
     *rc = VQE_OK;

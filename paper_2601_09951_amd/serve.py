@@ -52,11 +52,12 @@ class Result:
 class LibvqeExecutor:
     """Executes batches with libvqe on one device.
 
-    Batches run on a small fixed set of HIP streams (default priority): the
-    runtime maps streams onto a few hardware queues, and work of two streams
-    on one queue runs in order, so the longest batches (20 qubits and more)
-    get a stream of their own and the short classes spread over the others;
-    a short request then never waits behind a long batch.  Results are copied
+    Batches run on a small fixed set of HIP streams (default priority), each
+    on a hardware queue of its own (vqe_stream_create): the runtime otherwise
+    maps streams onto a small pool of hardware queues, and the work of two
+    streams on one queue runs in order.  The longest batches (20 qubits and
+    more) get one stream and the short classes spread over the others, so a
+    short request never waits behind a long batch.  Results are copied
     to pinned host memory on the batch's own stream, and the completion event
     follows that copy, so nothing runs on the null stream and collecting a
     finished batch does not wait for the device.
@@ -66,7 +67,7 @@ class LibvqeExecutor:
         self.ctx = ctx
         self.dev = torch.device(f"cuda:{device}")
         self._circuits: Dict[str, vqe.Circuit] = {}
-        self._streams = [torch.cuda.Stream(device=self.dev) for _ in range(max(2, n_streams))]
+        self._streams = [ctx.dedicated_stream(i) for i in range(max(2, n_streams))]
 
     def _circuit(self, spec) -> vqe.Circuit:
         key = spec.shape_key()
@@ -138,6 +139,7 @@ class LibvqeExecutor:
             s.synchronize()
 
     def close(self):
+        self.drain()
         for c in self._circuits.values():
             c.close()
         self._circuits.clear()

@@ -38,6 +38,9 @@ def _hp(a: np.ndarray):
     return a.ctypes.data_as(_P)
 
 
+_DEDICATED = {}  # (device, index) -> torch.cuda.ExternalStream on a hardware queue of its own
+
+
 class Context:
     """A libvqe context bound to one device (device=-1: host-only planning)."""
 
@@ -89,6 +92,20 @@ class Context:
 
     def reserve(self, nbytes: int):
         self.check(lib().vqe_ctx_reserve(self._h, int(nbytes)))
+
+    def dedicated_stream(self, index: int):
+        """Stream `index` of this device's dedicated streams: a HIP stream on a
+        hardware queue of its own (vqe_stream_create), as a
+        torch.cuda.ExternalStream.  Like torch's own stream pool these live
+        until the process ends (torch's pinned-memory allocator records
+        events on the streams a buffer was copied on when it frees the
+        buffer, so a stream must outlive every tensor used on it)."""
+        key = (self.device, int(index))
+        if key not in _DEDICATED:
+            h = _P()
+            self.check(lib().vqe_stream_create(self._h, ctypes.byref(h)))
+            _DEDICATED[key] = torch.cuda.ExternalStream(h.value, device=torch.device(f"cuda:{self.device}"))
+        return _DEDICATED[key]
 
     def close(self):
         if self._h:
