@@ -280,6 +280,22 @@ int vqe_prepare_reference(vqe_ctx_t ctx, int n_qubits, int64_t batch, uint64_t r
 int vqe_apply_ansatz(vqe_ctx_t ctx, vqe_circ_t circ, int64_t batch, const double *theta,
                      void *psi, void *stream);
 
+/* vqe_apply_ansatz for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and result, but the per-call gate and fused-stage
+ * matrices (batch * (gates + fused slots) * 64 bytes) go to a static device
+ * array of VQE_NOALLOC_SCRATCH_BYTES per GPU instead of context scratch, and
+ * the call makes no device or host allocation.  The circuit's forward plan
+ * for the context's current tiles must exist: vqe_circ_create builds it, and
+ * any evaluation of the circuit after vqe_ctx_set_tile rebuilds it.  Every
+ * call on one GPU uses that GPU's single array, so calls that overlap on one
+ * GPU (other streams, other contexts, other threads) race; serialise them.
+ * Errors: as vqe_apply_ansatz; EINVAL when the matrices exceed the array
+ * (the message gives the largest batch) or the plan is missing. */
+#define VQE_NOALLOC_SCRATCH_BYTES (8u << 20)
+int vqe_apply_ansatz_noalloc(vqe_ctx_t ctx, vqe_circ_t circ, int64_t batch, const double *theta,
+                             void *psi, void *stream);
+
 /* energy[b] = <psi[b]|H_b|psi[b]> (real part; Eq. 2).  hams has n_hams = 1
  * (shared) or n_hams = batch entries, all on the state's qubit count.  Terms
  * are evaluated grouped by flip mask, one tile sweep serving every group

@@ -17,6 +17,7 @@ VQE_EINVAL = -1
 VQE_ENOMEM = -2
 VQE_EUNSUPPORTED = -3
 VQE_EHIP = -4
+NOALLOC_SCRATCH_BYTES = 8 << 20  # VQE_NOALLOC_SCRATCH_BYTES
 
 GATE_CODES = {
     "RX": 0, "RY": 1, "RZ": 2, "H": 3, "X": 4,
@@ -35,6 +36,7 @@ EXPORTED = [
     "vqe_circ_plan_export", "vqe_ham_plan_export",
     "vqe_hfam_create", "vqe_hfam_info", "vqe_hfam_member", "vqe_hfam_set_integrals", "vqe_hfam_destroy",
     "vqe_ctx_set_profiling", "vqe_ctx_profile", "vqe_stream_create", "vqe_stream_destroy",
+    "vqe_apply_ansatz_noalloc",
 ]
 
 
@@ -98,6 +100,7 @@ def _declare(L):
         "vqe_ctx_profile": [P, P, i32, P, i32],
         "vqe_stream_create": [P, PP],
         "vqe_stream_destroy": [P, P],
+        "vqe_apply_ansatz_noalloc": [P, P, i64, P, P, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)

@@ -14,7 +14,33 @@
 
 #include "internal.h"
 
+// The matrices of vqe_apply_ansatz_noalloc: one array per GPU, held until the
+// process ends.  Host code never passes this name to a kernel (in host code
+// it is a stand-in, not a device address): it uses the address that
+// hipGetSymbolAddress returns on each device (Context::noalloc_scratch).
+static __device__ __align__(256) unsigned char scratch[VQE_NOALLOC_SCRATCH_BYTES];
+
 namespace vqe {
+
+namespace {
+std::mutex g_noalloc_mu;
+std::vector<void *> g_noalloc_ptr;  // per device ordinal: the device address of `scratch`
+}  // namespace
+
+// Once per device, with that device current (vqe_ctx_create).
+int noalloc_scratch_init(Context *ctx)
+{
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (g_noalloc_ptr.size() <= (size_t)ctx->device) g_noalloc_ptr.resize(ctx->device + 1, nullptr);
+    if (!g_noalloc_ptr[ctx->device]) {
+        void *p = nullptr;
+        int rc = hip_check(ctx, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress (scratch)");
+        if (rc) return rc;
+        g_noalloc_ptr[ctx->device] = p;
+    }
+    ctx->noalloc_scratch = g_noalloc_ptr[ctx->device];
+    return VQE_OK;
+}
 
 int set_err(Context *ctx, int code, const std::string &msg)
 {
@@ -841,6 +867,10 @@ int vqe_ctx_create(int device, vqe_ctx_t *out)
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
         c->cu_count = cus;
+    if (noalloc_scratch_init(c)) {
+        delete c;
+        return VQE_EHIP;
+    }
     *out = c;
     return VQE_OK;
 }
@@ -1255,6 +1285,16 @@ int vqe_circ_create(vqe_ctx_t ctx, int n_qubits, int64_t n_gates, const int32_t 
         return rc;
     }
     C->id = ctx->next_id++;
+    // the forward plan for the current tiles now, so vqe_apply_ansatz_noalloc
+    // finds it without allocating
+    if (!C->gates.empty() && !get_circ_plan(C, false, ctx->k_fwd, ctx->c_low, &rc)) {
+        free_circ_plans(ctx, C);
+        dev_free(ctx, C->gates_dev);
+        dev_free(ctx, C->pmap_off);
+        dev_free(ctx, C->pmap_idx);
+        delete C;
+        return rc;
+    }
     *out = C;
     return VQE_OK;
 }
@@ -1332,6 +1372,35 @@ int vqe_apply_ansatz(vqe_ctx_t ctx, vqe_circ_t circ, int64_t batch, const double
     rc = forward(ctx, circ, batch, theta, (double2 *)psi, (double2 *)mats, (hipStream_t)stream);
     if (rc) return rc;
     return note_use(ctx, ctx->scratch_uses, (hipStream_t)stream);
+}
+
+int vqe_apply_ansatz_noalloc(vqe_ctx_t ctx, vqe_circ_t circ, int64_t batch, const double *theta, void *psi,
+                             void *stream)
+{
+    int rc = check_dev(ctx);
+    if (rc) return rc;
+    StreamCall call(ctx, (hipStream_t)stream);
+    if (call.rc) return call.rc;
+    if (!circ || !psi || batch < 1 || (circ->n_params > 0 && !theta))
+        return set_err(ctx, VQE_EINVAL, "bad argument");
+    if (batch > kMaxBatch) return set_err(ctx, VQE_EUNSUPPORTED, "batch > 65535");
+    if (!ctx->noalloc_scratch) return set_err(ctx, VQE_EHIP, "static scratch address not initialised");
+    if (circ->gates.empty()) return VQE_OK;
+    CircPlan *fp = find_circ_plan(circ, false, ctx->k_fwd, ctx->c_low, &rc);
+    if (rc) return rc;
+    if (!fp)
+        return set_err(ctx, VQE_EINVAL,
+                       "the circuit has no forward plan for the current tiles: evaluate it once (that call may "
+                       "allocate) before calling vqe_apply_ansatz_noalloc");
+    const size_t per_inst = ((size_t)circ->gates.size() + (size_t)fp->n_fslots()) * 64;
+    if ((size_t)batch * per_inst > VQE_NOALLOC_SCRATCH_BYTES) {
+        std::ostringstream os;
+        os << "batch " << batch << " needs " << (size_t)batch * per_inst << " bytes of matrices, more than the "
+           << VQE_NOALLOC_SCRATCH_BYTES << "-byte static scratch: at most " << VQE_NOALLOC_SCRATCH_BYTES / per_inst
+           << " instances of this circuit per call";
+        return set_err(ctx, VQE_EINVAL, os.str());
+    }
+    return forward(ctx, circ, batch, theta, (double2 *)psi, (double2 *)ctx->noalloc_scratch, (hipStream_t)stream);
 }
 
 int vqe_expect(vqe_ctx_t ctx, int n_hams, const vqe_ham_t *hams, int64_t batch, const void *psi,

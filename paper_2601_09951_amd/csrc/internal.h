@@ -342,6 +342,7 @@ struct Context {
     std::map<std::string, std::unique_ptr<PauliPlan>> pauli_cache;
     uint64_t next_id = 1;
     int cu_count = 256;
+    void *noalloc_scratch = nullptr;  // this device's static array of vqe_apply_ansatz_noalloc
     // Table pool: device blocks of power-of-two size classes carved from
     // chunks that live until the context is destroyed, so freeing a table
     // never calls hipFree (which waits for the whole device).
@@ -449,6 +450,7 @@ int build_circuit_gates(Circ *C, int64_t n_gates, const int32_t *kind, const int
                         const int32_t *pidx, const double *fixed, std::string &err);
 CircPlan *get_circ_plan(Circ *C, bool reverse, int k, int c, int *rc);
 void free_circ_plans(Context *ctx, Circ *C);  // immediate: the caller has synchronised
+CircPlan *find_circ_plan(Circ *C, bool reverse, int k, int c, int *rc);  // cached plan or nullptr; never builds
 PauliPlan *get_pauli_plan(Context *ctx, int n_hams, Ham *const *hams, int n_inst, int k, int c,
                           int *rc);
 TileGeom make_geom(int n, int k, int c, const std::vector<int> &tile_bits);

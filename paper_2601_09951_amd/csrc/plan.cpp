@@ -511,6 +511,18 @@ static bool build_stages(const Circ *C, const std::vector<int> &take, const std:
     return true;
 }
 
+CircPlan *find_circ_plan(Circ *C, bool reverse, int k, int c, int *rc)
+{
+    const int n = C->n;
+    const auto key = std::make_pair(n <= k ? n : k, n <= k ? n : std::min(c, k));
+    auto &cache = reverse ? C->rev : C->fwd;
+    auto it = cache.find(key);
+    *rc = VQE_OK;
+    if (it == cache.end()) return nullptr;
+    *rc = ready_wait(C->ctx, it->second->ready);
+    return *rc ? nullptr : it->second.get();
+}
+
 CircPlan *get_circ_plan(Circ *C, bool reverse, int k, int c, int *rc)
 {
     const int n = C->n;

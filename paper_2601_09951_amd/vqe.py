@@ -332,6 +332,16 @@ def expect(ctx: Context, hams, psi: torch.Tensor, out: torch.Tensor = None) -> t
     return out
 
 
+def apply_ansatz_noalloc(ctx: Context, circ: Circuit, theta: torch.Tensor, psi: torch.Tensor):
+    """vqe_apply_ansatz_noalloc: apply_ansatz with the matrices in the library's
+    static per-GPU array (no allocation; overlapping calls on one GPU race)."""
+    B = psi.shape[0]
+    _check_tensor(psi, torch.complex128, (B, 1 << circ.n_qubits), "psi")
+    _check_tensor(theta, torch.float64, (B, circ.n_params), "theta")
+    ctx.check(lib().vqe_apply_ansatz_noalloc(ctx.handle, circ.handle, B, _ptr(theta), _ptr(psi),
+                                             _stream(psi.device)))
+
+
 def apply_hamiltonian(ctx: Context, hams, psi: torch.Tensor, out: torch.Tensor = None) -> torch.Tensor:
     arr, nh = _hams_array(hams)
     _check_tensor(psi, torch.complex128, None, "psi")
