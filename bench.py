@@ -461,16 +461,23 @@ def c1_measure(ctx, vqe, synth, torch):
             "gd_final_energy": round(float(traj[0, -1]), 12)}
 
 
-def _hea_eval(ctx, vqe, synth, torch, n, layers, terms, batch, want_grad, reps=3):
+def _hea_eval(ctx, vqe, synth, torch, n, layers, terms, batch, want_grad, reps=3, graphs=True, tune=False, warm=2):
+    """ms per energy (+ gradient) evaluation of the hardware-efficient ansatz:
+    two untimed calls (plans; with graphs on, the capture), then `reps` timed
+    calls between events.  tune: vqe_autotune first (its choice is used and
+    returned)."""
     dev = torch.device("cuda:0")
     spec = synth.hea_circuit(n, layers)
     ham = synth.random_pauli_sum(n, terms, seed=synth.MASTER_SEED + n)
     C = vqe.Circuit.from_spec(ctx, spec)
     H = vqe.Hamiltonian.from_sum(ctx, ham)
     th = torch.tensor(synth.uniform_thetas(spec.n_params, batch, seed=synth.MASTER_SEED + n), device=dev)
+    ctx.set_graphs(graphs)
+    tuned = vqe.autotune(ctx, C, H, th, want_grad=want_grad) if tune else None
     ws = vqe.workspace(ctx, C, H, batch, 1 if want_grad else 0)
     call = (lambda: vqe.energy_grad(ctx, C, H, th, ws=ws)) if want_grad else (lambda: vqe.energy(ctx, C, H, th, ws=ws))
-    call()
+    for _ in range(warm):
+        call()
     torch.cuda.synchronize()
     s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     s0.record()
@@ -479,21 +486,34 @@ def _hea_eval(ctx, vqe, synth, torch, n, layers, terms, batch, want_grad, reps=3
     s1.record()
     torch.cuda.synchronize()
     ms = s0.elapsed_time(s1) / reps
+    ctx.clear_tuning()
+    ctx.set_graphs(True)
     del ws
     torch.cuda.empty_cache()
-    return ms, spec, H
+    return ms, spec, H, tuned
 
 
 def scaling_measure(ctx, vqe, synth, torch, n):
     """Energy + adjoint gradient of the hardware-efficient ansatz, L = n layers,
-    500 random strings; batches of 8 and 32 where the states are small."""
-    ms, spec, H = _hea_eval(ctx, vqe, synth, torch, n, n, 500, 1, True, reps=2 if n >= 24 else 3)
-    out = {"n": n, "gates": spec.n_gates, "params": spec.n_params, "flip_groups": int(H.n_groups),
-           "ms_per_energy_grad": round(ms, 3)}
-    if n <= 20:
-        for B in (8, 32):
-            msb, _, _ = _hea_eval(ctx, vqe, synth, torch, n, n, 500, B, True)
-            out[f"batch{B}_evals_per_s"] = round(B / (msb * 1e-3), 2)
+    500 random strings: one instance per call, and batches of 8 and 32 where
+    the states are small; each eager (one launch per kernel), replayed from a
+    captured graph, and with the autotuner's tiles / batch tile (plus graphs)."""
+    reps = 2 if n >= 24 else 5
+    out = {"n": n}
+    for B in ((1, 8, 32) if n <= 20 else (1,)):
+        row = {}
+        ms_e, spec, H, _ = _hea_eval(ctx, vqe, synth, torch, n, n, 500, B, True, reps=reps, graphs=False)
+        ms_g, _, _, _ = _hea_eval(ctx, vqe, synth, torch, n, n, 500, B, True, reps=reps, graphs=True)
+        row["eager_evals_per_s"] = round(B / (ms_e * 1e-3), 2)
+        row["graph_evals_per_s"] = round(B / (ms_g * 1e-3), 2)
+        if n <= 24:
+            ms_t, _, _, tuned = _hea_eval(ctx, vqe, synth, torch, n, n, 500, B, True, reps=reps, graphs=True,
+                                          tune=True)
+            row["tuned_evals_per_s"] = round(B / (ms_t * 1e-3), 2)
+            row["tuned"] = {k: tuned[k] for k in ("k_fwd", "k_rev", "c_low", "wg_max", "batch_tile", "candidates")}
+        out[f"batch{B}"] = row
+    out.update({"gates": spec.n_gates, "params": spec.n_params, "flip_groups": int(H.n_groups),
+                "ms_per_energy_grad": round(1e3 / out["batch1"]["graph_evals_per_s"], 3)})
     return out
 
 
@@ -501,8 +521,8 @@ def large_measure(ctx, vqe, synth, torch):
     """30 qubits energy + gradient (two resident 16 GiB states) and 32 qubits
     energy only (one 64 GiB state); hardware-efficient ansatz with 4 layers,
     2000 random strings."""
-    ms30, spec30, H30 = _hea_eval(ctx, vqe, synth, torch, 30, 4, 2000, 1, True, reps=1)
-    ms32, spec32, H32 = _hea_eval(ctx, vqe, synth, torch, 32, 4, 2000, 1, False, reps=1)
+    ms30, spec30, H30, _ = _hea_eval(ctx, vqe, synth, torch, 30, 4, 2000, 1, True, reps=1, graphs=False, warm=1)
+    ms32, spec32, H32, _ = _hea_eval(ctx, vqe, synth, torch, 32, 4, 2000, 1, False, reps=1, graphs=False, warm=1)
     return {"n30_energy_grad_s": round(ms30 * 1e-3, 3), "n30_flip_groups": int(H30.n_groups),
             "n32_energy_s": round(ms32 * 1e-3, 3), "n32_flip_groups": int(H32.n_groups),
             "n32_state_GiB": 64}

@@ -103,10 +103,10 @@ int vqe_ctx_set_mem_budget(vqe_ctx_t ctx, size_t bytes);
  * tile contains (contiguous runs of 2^c_low amplitudes); c_low >= 2 and
  * k - c_low >= 4 for both k, so a four-wire gate always fits a tile.
  * Defaults: k_fwd 12, k_rev 11, c_low 3 (runs of one 128-byte line).  Pass 0
- * to keep a value.  Changes apply to plans built afterwards.  A Pauli string
- * whose X/Y bits outside the lowest c_low bits number more than
- * k_fwd - c_low (or k_rev - c_low for gradients) is not supported
- * (VQE_EUNSUPPORTED from the calls that evaluate it). */
+ * to keep a value.  Changes apply to plans built afterwards.  A flip group
+ * whose X/Y bits outside the lowest c_low bits number more than k - c_low
+ * fits no tile; it is evaluated by a whole-state pair sweep of its own (one
+ * more read of the state per such group). */
 int vqe_ctx_set_tile(vqe_ctx_t ctx, int k_fwd, int k_rev, int c_low);
 
 /* How vqe_run executes: mode 0 (default) runs the whole loop in one
@@ -128,6 +128,64 @@ int vqe_ctx_set_loop_mode(vqe_ctx_t ctx, int mode);
  * of H psi in registers (tiles of 8 to 11 bits).  All compute the same
  * result up to rounding; the switch exists for measurement. */
 int vqe_ctx_set_staged(vqe_ctx_t ctx, int staged);
+
+/* Launch graphs (on = 1, the default): a launch sequence of vqe_energy,
+ * vqe_energy_grad or one optimiser step of vqe_run's per-step loop that is
+ * seen a second time with identical arguments (pointers included) is
+ * captured into a hipGraph, which is launched instead of the individual
+ * kernels from then on; the optimiser step reads its step index from the
+ * workspace, so every step of a loop is the same graph.  The second call
+ * waits once for its stream and for pending table uploads before capturing.
+ * A graph is dropped when a Pauli plan it reads is retired (a Hamiltonian
+ * destroyed, the plan cache flushed) or its circuit is destroyed.  Kernel
+ * timing (vqe_ctx_set_profiling) keeps calls eager.  on = 0 drops every
+ * graph. */
+int vqe_ctx_set_graphs(vqe_ctx_t ctx, int on);
+
+/* Graphs captured and launched so far, and graphs cached now (any pointer
+ * may be NULL). */
+int vqe_ctx_graph_stats(vqe_ctx_t ctx, int64_t *captures, int64_t *launches, int64_t *cached);
+
+/* ---- autotuning ----------------------------------------------------------
+ * vqe_autotune times vqe_energy (want_grad = 0) or vqe_energy_grad
+ * (want_grad = 1) on the caller's arguments for candidate execution choices
+ * and keeps the fastest for (circuit, batch, want_grad); later calls of
+ * vqe_energy / vqe_energy_grad / vqe_workspace_bytes with that circuit and
+ * batch (and vqe_run's per-step loop, with the energy + gradient choice) use
+ * it instead of the context defaults.  Candidates, one coordinate at a time
+ * from the defaults (coordinate descent, a change kept when it is 2 % faster):
+ * forward tile bits k_fwd 8..min(n, 13), adjoint tile bits k_rev 8..min(n,
+ * 12), contiguous low bits c_low 2..4, the batch tile (instances per launch
+ * sequence: batch / 2, batch / 4, ..., 1; a batch then runs as consecutive
+ * chunks, so that a chunk's states can stay in the last-level cache), and
+ * the cap on workgroups per instance (256, 1024, 4096).  Each candidate runs
+ * twice untimed (plans, uploads, graph capture) and then at least 3 times
+ * (until 20 ms) between HIP events on `stream`, with outputs and a workspace
+ * that the tuner allocates for each candidate's size (set-up work: size the
+ * caller's workspace with vqe_workspace_bytes after tuning); a candidate that
+ * cannot evaluate the Hamiltonian with its tiles is skipped.  States of at
+ * most 8 qubits are one tile at every width: only the defaults are timed.
+ * The host waits for the stream.  Errors: EINVAL, ENOMEM (the defaults could
+ * not be evaluated), EHIP. */
+typedef struct {
+    int k_fwd, k_rev, c_low, wg_max;
+    int64_t batch_tile;  /* instances per launch sequence */
+    double ms_default;   /* ms per call with the context defaults */
+    double ms_tuned;     /* ms per call with the chosen configuration */
+    int candidates;      /* configurations timed */
+} vqe_tune_result;
+
+int vqe_autotune(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams, int64_t batch,
+                 uint64_t ref_index, int want_grad, const double *theta, void *stream, vqe_tune_result *out);
+
+/* Use `cfg` (its k_fwd, k_rev, c_low, wg_max and batch_tile; the timing
+ * fields are ignored) for (circuit, batch, want_grad) as if vqe_autotune had
+ * chosen it: a configuration found earlier can be reused without timing.
+ * Errors: EINVAL (ranges as vqe_ctx_set_tile, wg_max >= 1, batch_tile >= 1). */
+int vqe_tune_set(vqe_ctx_t ctx, vqe_circ_t circ, int64_t batch, int want_grad, const vqe_tune_result *cfg);
+
+/* Forget every tuned choice of the context (calls use the defaults again). */
+int vqe_ctx_clear_tuning(vqe_ctx_t ctx);
 
 /* Reserve `bytes` of context scratch now (used by vqe_expect and
  * vqe_apply_ansatz for per-launch tables), so later calls do not allocate. */
@@ -423,7 +481,10 @@ int vqe_run(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams, i
  *   {geom, int32 group_begin, group_count, 0, 0}, groups {uint32 floc,
  *   uint32 pivot, int32 union_group, 0}, int32 toff[n_inst][n_union][3]
  *   (begin of real-phase terms, begin of imaginary-phase terms, end), terms
- *   {uint64 z, uint32 zloc, 0, double w}. */
+ *   {uint64 z, uint32 zloc, 0, double w}, then int32 {n_wide, wide_bytes
+ *   (16)} and n_wide records {uint64 f, int32 pivot, int32 union_group}: the
+ *   flip groups too wide for a tile, each evaluated over the whole state on
+ *   the pairs (b, b ^ f) with bit pivot of b clear (their terms' zloc is 0). */
 int vqe_circ_plan_export(vqe_ctx_t ctx, vqe_circ_t circ, int reverse, void *buf, size_t buf_bytes,
                          size_t *needed);
 int vqe_ham_plan_export(vqe_ctx_t ctx, int n_hams, const vqe_ham_t *hams, int64_t batch,

@@ -36,7 +36,8 @@ EXPORTED = [
     "vqe_circ_plan_export", "vqe_ham_plan_export",
     "vqe_hfam_create", "vqe_hfam_info", "vqe_hfam_member", "vqe_hfam_set_integrals", "vqe_hfam_destroy",
     "vqe_ctx_set_profiling", "vqe_ctx_profile", "vqe_stream_create", "vqe_stream_destroy",
-    "vqe_apply_ansatz_noalloc",
+    "vqe_apply_ansatz_noalloc", "vqe_ctx_set_graphs", "vqe_ctx_graph_stats", "vqe_ctx_clear_tuning",
+    "vqe_autotune", "vqe_tune_set",
 ]
 
 
@@ -44,6 +45,13 @@ class KernelStat(ctypes.Structure):
     """vqe_kernel_stat."""
     _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
                 ("bytes", ctypes.c_double)]
+
+
+class TuneResult(ctypes.Structure):
+    """vqe_tune_result."""
+    _fields_ = [("k_fwd", ctypes.c_int), ("k_rev", ctypes.c_int), ("c_low", ctypes.c_int), ("wg_max", ctypes.c_int),
+                ("batch_tile", ctypes.c_int64), ("ms_default", ctypes.c_double), ("ms_tuned", ctypes.c_double),
+                ("candidates", ctypes.c_int)]
 
 
 class VQEError(RuntimeError):
@@ -101,6 +109,11 @@ def _declare(L):
         "vqe_stream_create": [P, PP],
         "vqe_stream_destroy": [P, P],
         "vqe_apply_ansatz_noalloc": [P, P, i64, P, P, P],
+        "vqe_ctx_set_graphs": [P, i32],
+        "vqe_ctx_graph_stats": [P, P, P, P],
+        "vqe_ctx_clear_tuning": [P],
+        "vqe_autotune": [P, P, i32, P, i64, u64, i32, P, P, P],
+        "vqe_tune_set": [P, P, i64, i32, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)

@@ -8,6 +8,7 @@
 //   run:         Algorithm 1's loop: energy_grad + Adam/GD per step.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <sstream>
@@ -170,6 +171,7 @@ void retire(Context *ctx, std::vector<DevMem> mem, std::vector<StreamUse> uses)
 
 void retire_pauli_plan(Context *ctx, PauliPlan *p)
 {
+    ++ctx->plan_epoch;  // graphs that read this plan are dropped before their next launch
     ready_free(p->ready);  // destroying a pending event is deferred by the runtime
     retire(ctx, {p->groups, p->geoms, p->wsrc, p->toff, p->terms}, std::move(p->uses));
     p->groups = p->geoms = p->wsrc = p->toff = p->terms = DevMem{};
@@ -185,12 +187,62 @@ void poll_retired(Context *ctx, bool wait)
             for (StreamUse &u : r.uses) (void)hipEventSynchronize(u.event);
         if (wait || events_done(r.uses)) {
             for (DevMem &m : r.mem) dev_free(ctx, m);
+            for (hipGraphExec_t x : r.execs) (void)hipGraphExecDestroy(x);
             for (StreamUse &u : r.uses) (void)hipEventDestroy(u.event);
         } else {
             keep.push_back(std::move(r));
         }
     }
     ctx->retired.swap(keep);
+}
+
+void drop_graphs(Context *ctx, uint64_t circ_id)
+{
+    for (auto it = ctx->graph_cache.begin(); it != ctx->graph_cache.end();) {
+        if (circ_id == 0 || it->second.circ_id == circ_id) {
+            Context::GraphEntry &e = it->second;
+            if (e.exec) {
+                Context::Retired r;
+                r.uses = std::move(e.uses);
+                r.execs.push_back(e.exec);
+                e.exec = nullptr;
+                if (r.uses.empty()) {
+                    (void)hipGraphExecDestroy(r.execs[0]);
+                } else {
+                    ctx->retired.push_back(std::move(r));
+                }
+            }
+            it = ctx->graph_cache.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
+
+TileScope::TileScope(Context *c, const Circ *C, int64_t batch, int mode)
+    : ctx(c), kf(c->k_fwd), kr(c->k_rev), cl(c->c_low), wm(c->wg_max)
+{
+    const Context::Tuned *t = c->tune_override;
+    if (!t && mode >= 0 && !c->tuned.empty()) {
+        std::ostringstream k;
+        k << C->id << ':' << batch << ':' << mode;
+        auto it = c->tuned.find(k.str());
+        if (it != c->tuned.end()) t = &it->second;
+    }
+    if (!t) return;
+    c->k_fwd = t->k_fwd;
+    c->k_rev = t->k_rev;
+    c->c_low = t->c_low;
+    c->wg_max = t->wg_max;
+    bt = t->batch_tile;
+}
+
+TileScope::~TileScope()
+{
+    ctx->k_fwd = kf;
+    ctx->k_rev = kr;
+    ctx->c_low = cl;
+    ctx->wg_max = wm;
 }
 
 namespace {
@@ -441,9 +493,12 @@ struct Layout {
     size_t psi = 0, lam = 0, mats = 0, pe = 0, pg = 0, grad = 0, m = 0, v = 0, etmp = 0;
     size_t wadj = 0, coef = 0;  // adjoint fused stages: per-slot products, per-entry coefficients
     size_t hist = 0;            // persistent loop on small states: pair values after each gate
+    size_t estep = 0, step = 0; // per-step loop: the step's energies [B], the step index (int64)
+    int64_t Bs = 0;             // instances per launch sequence (the batch tile)
     size_t total = 0;
     int W_fwd_sweep = 1, W_hpsi = 1, W_rev = 1;
-    int n_sweeps_e = 1;
+    int n_sweeps_e = 1;         // expectation partial slots (tile sweeps + wide groups)
+    int n_slots_h = 1;          // H psi partial slots (1 + wide groups)
 };
 
 int check_ctx(Context *ctx)
@@ -495,7 +550,39 @@ int wg_for(Context *ctx, int n, int k)
 int build_shift(Context *ctx, Circ *C);
 int fwd_mats_per_inst(Context *ctx, Circ *C, size_t *count);
 
-int layout_for(Context *ctx, Circ *C, int n_hams, Ham *const *H, int64_t B, int want, Layout &L)
+// Most partial-sum slots over the batch's launch chunks (one plan per chunk
+// when every instance has its own Hamiltonian): expectation slots (tile
+// sweeps + wide groups) of the k_fwd plans into *S, H psi slots (1 + wide
+// groups) of the k_rev plans into *Sh (when Sh is not NULL).
+int slots_max(Context *ctx, int n_hams, Ham *const *H, int64_t B, int64_t Bs, int *S, int *Sh)
+{
+    int rc = VQE_OK;
+    *S = 1;
+    if (Sh) *Sh = 1;
+    auto visit = [&](int nh, Ham *const *Hc) -> int {
+        PauliPlan *pp = get_pauli_plan(ctx, nh, Hc, nh, ctx->k_fwd, ctx->c_low, &rc);
+        if (!pp) return rc;
+        *S = std::max(*S, (int)(pp->sweeps.size() + pp->wide.size()));
+        if (Sh) {
+            PauliPlan *ph = get_pauli_plan(ctx, nh, Hc, nh, ctx->k_rev, ctx->c_low, &rc);
+            if (!ph) return rc;
+            *Sh = std::max(*Sh, 1 + (int)ph->wide.size());
+        }
+        return VQE_OK;
+    };
+    if (n_hams == 1 || n_hams != B || Bs >= B)  // one plan (parameter-shift rows share the instances' tables)
+        return visit(n_hams, H);
+    for (int64_t c0 = 0; c0 < B; c0 += Bs) {
+        rc = visit((int)std::min(Bs, B - c0), H + c0);
+        if (rc) return rc;
+    }
+    return VQE_OK;
+}
+
+// Workspace layout; want: 0 energy, 1 energy + grad, 2 run (adds optimiser
+// state), 3 parameter shift.  States and per-launch tables are sized for
+// Bs instances (the batch tile, 0 = B): a batch runs as chunks of Bs.
+int layout_for(Context *ctx, Circ *C, int n_hams, Ham *const *H, int64_t B, int want, Layout &L, int64_t Bs = 0)
 {
     int rc;
     if (want == 3) {  // parameter shift: B * rows states, matrices, expectation partials, row energies
@@ -510,11 +597,12 @@ int layout_for(Context *ctx, Circ *C, int n_hams, Ham *const *H, int64_t B, int 
         L.total = align_up(L.total + (size_t)R * 8);
         return VQE_OK;
     }
+    Bs = (Bs <= 0 || Bs > B) ? B : Bs;
+    L.Bs = Bs;
     const int n = C->n;
     const uint64_t dim = 1ull << n;
-    const size_t state = (size_t)B * dim * 16;
+    const size_t state = (size_t)Bs * dim * 16;
     const int G = (int)C->gates.size();
-    const int n_inst = n_hams;  // 1 (shared) or one table per instance
     size_t off = 0;
     L.psi = off;
     off = align_up(off + state);
@@ -526,42 +614,48 @@ int layout_for(Context *ctx, Circ *C, int n_hams, Ham *const *H, int64_t B, int 
     rc = fwd_mats_per_inst(ctx, C, &nmats);
     if (rc) return rc;
     L.mats = off;
-    off = align_up(off + (size_t)B * nmats * 64);
-    if (want == 0) {
-        PauliPlan *pp = get_pauli_plan(ctx, n_hams, H, n_inst, ctx->k_fwd, ctx->c_low, &rc);
-        if (!pp) return rc;
-        L.n_sweeps_e = (int)pp->sweeps.size();
+    off = align_up(off + (size_t)Bs * nmats * 64);
+    if (want == 0 || want == 2) {
+        rc = slots_max(ctx, n_hams, H, B, Bs, &L.n_sweeps_e, want == 2 ? &L.n_slots_h : nullptr);
+        if (rc) return rc;
         L.W_fwd_sweep = wg_for(ctx, n, ctx->k_fwd);
+    } else {
+        int se = 1;
+        rc = slots_max(ctx, n_hams, H, B, Bs, &se, &L.n_slots_h);
+        if (rc) return rc;
+    }
+    if (want == 0) {
         L.pe = off;
-        off = align_up(off + (size_t)B * L.n_sweeps_e * L.W_fwd_sweep * 8);
+        off = align_up(off + (size_t)Bs * L.n_sweeps_e * L.W_fwd_sweep * 8);
     } else {
         L.W_hpsi = wg_for(ctx, n, ctx->k_rev);
         L.W_rev = wg_for(ctx, n, ctx->k_rev);
         L.pe = off;
-        off = align_up(off + (size_t)B * L.W_hpsi * 8);
+        off = align_up(off + (size_t)Bs * L.n_slots_h * L.W_hpsi * 8);
         L.pg = off;
-        off = align_up(off + (size_t)B * std::max(C->n_pgates, 1) * L.W_rev * 8);
+        off = align_up(off + (size_t)Bs * std::max(C->n_pgates, 1) * L.W_rev * 8);
         CircPlan *rp = get_circ_plan(C, true, ctx->k_rev, ctx->c_low, &rc);
         if (!rp) return rc;
         L.wadj = off;
-        off = align_up(off + (size_t)B * rp->n_fslots() * 64);
+        off = align_up(off + (size_t)Bs * rp->n_fslots() * 64);
         L.coef = off;
-        off = align_up(off + (size_t)B * rp->host_fslot_gate.size() * 32);
+        off = align_up(off + (size_t)Bs * rp->host_fslot_gate.size() * 32);
     }
     if (want == 2) {
+        const size_t bp = (size_t)B * std::max(C->n_params, 1) * 8;
         L.grad = off;
-        off = align_up(off + (size_t)B * std::max(C->n_params, 1) * 8);
+        off = align_up(off + bp);
         L.m = off;
-        off = align_up(off + (size_t)B * std::max(C->n_params, 1) * 8);
+        off = align_up(off + bp);
         L.v = off;
-        off = align_up(off + (size_t)B * std::max(C->n_params, 1) * 8);
+        off = align_up(off + bp);
+        L.estep = off;
+        off = align_up(off + (size_t)B * 8);
+        L.step = off;
+        off = align_up(off + 8);
         // expectation partials for the final energy evaluation
-        PauliPlan *pp = get_pauli_plan(ctx, n_hams, H, n_inst, ctx->k_fwd, ctx->c_low, &rc);
-        if (!pp) return rc;
-        L.n_sweeps_e = (int)pp->sweeps.size();
-        L.W_fwd_sweep = wg_for(ctx, n, ctx->k_fwd);
         L.etmp = off;
-        off = align_up(off + (size_t)B * L.n_sweeps_e * L.W_fwd_sweep * 8);
+        off = align_up(off + (size_t)Bs * L.n_sweeps_e * L.W_fwd_sweep * 8);
         if (n <= 8) {
             L.hist = off;
             off = align_up(off + (size_t)B * small_fast_hist_bytes(n, G));
@@ -646,6 +740,31 @@ int forward(Context *ctx, Circ *C, int64_t B, const double *theta, double2 *psi,
     return run_forward_passes(ctx, C, fp, B, psi, mats, s);
 }
 
+// the expectation sweeps of plan pp (tile sweeps, then the wide groups) into
+// partials [B][slots][W]; returns the slot count in *slots
+int expect_sweeps(Context *ctx, PauliPlan *pp, const double2 *psi, int64_t B, int ham_div, int W, double *partials,
+                  int *slots, hipStream_t s)
+{
+    const int S = (int)pp->sweeps.size(), NS = S + (int)pp->wide.size();
+    const double bytes = 16.0 * (double)(1ull << pp->n) * (double)B;
+    for (int i = 0; i < S; ++i) {
+        ProfScope prof(ctx, "k_pauli_sweep (expectation)", s, bytes);
+        int rc = hip_check(ctx, launch_pauli_sweep(pp->sweeps[i], *pp, i, psi, nullptr, B, ham_div, W, partials, NS,
+                                                   false, i == 0, i == S - 1, s),
+                           "expectation sweep");
+        if (rc) return rc;
+    }
+    for (size_t j = 0; j < pp->wide.size(); ++j) {
+        ProfScope prof(ctx, "k_pauli_wide (expectation)", s, bytes);
+        int rc = hip_check(ctx, launch_pauli_wide(pp->wide[j], *pp, psi, nullptr, B, ham_div, W, partials, NS,
+                                                  S + (int)j, s),
+                           "wide group sweep");
+        if (rc) return rc;
+    }
+    *slots = NS;
+    return VQE_OK;
+}
+
 // energy by paired expectation sweeps (no lambda)
 int expect_into(Context *ctx, int n_hams, Ham *const *H, int64_t B, const double2 *psi,
                 double *energy, int64_t e_stride, double *partials, hipStream_t s)
@@ -658,18 +777,20 @@ int expect_into(Context *ctx, int n_hams, Ham *const *H, int64_t B, const double
     rc = refresh_weights(ctx, pp, s);
     if (rc) return rc;
     const int W = wg_for(ctx, n, ctx->k_fwd);
-    const int S = (int)pp->sweeps.size();
-    for (int i = 0; i < S; ++i) {
-        ProfScope prof(ctx, "k_pauli_sweep (expectation)", s, 16.0 * (double)(1ull << n) * (double)B);
-        rc = hip_check(ctx, launch_pauli_sweep(pp->sweeps[i], *pp, i, psi, nullptr, B, n_hams == 1 ? 0 : 1, W,
-                                               partials, S, false, i == 0, i == S - 1, s),
-                       "expectation sweep");
-        if (rc) return rc;
-    }
-    rc = hip_check(ctx, launch_reduce_slots(partials, S, W, B, energy, e_stride, 1.0, s), "energy reduce");
+    int NS = 0;
+    rc = expect_sweeps(ctx, pp, psi, B, n_hams == 1 ? 0 : 1, W, partials, &NS, s);
+    if (rc) return rc;
+    rc = hip_check(ctx, launch_reduce_slots(partials, NS, W, B, energy, e_stride, 1.0, s), "energy reduce");
     if (rc) return rc;
     return note_use(ctx, pp->uses, s);
 }
+
+// lam = H psi over every sweep of pp, with the energy partials in partials
+// [B][1 + wide][W]: the tile sweeps (the first writes lam, the last adds the
+// energy of everything before it into slot 0), then the wide groups (added
+// into lam, each with its energy term in a slot of its own)
+int hpsi_all(Context *ctx, PauliPlan *pp, const double2 *psi, double2 *lam, int64_t B, int ham_div, int W,
+             double *partials, int *slots, hipStream_t s);
 
 // one H psi sweep into lam (first: lam = sweep, else lam += sweep; last: the
 // energy partials); the gather kernel where the tile allows it
@@ -686,6 +807,31 @@ hipError_t hpsi_sweep(Context *ctx, PauliPlan *pp, int i, const double2 *psi, do
         return launch_hpsi_gather(pp->sweeps[i], *pp, i, psi, lam, B, ham_div, W, partials, i == 0, i == S - 1, s);
     return launch_pauli_sweep(pp->sweeps[i], *pp, i, psi, lam, B, ham_div, W, partials, 1, true, i == 0,
                               i == S - 1, s);
+}
+
+int hpsi_all(Context *ctx, PauliPlan *pp, const double2 *psi, double2 *lam, int64_t B, int ham_div, int W,
+             double *partials, int *slots, hipStream_t s)
+{
+    const int S = (int)pp->sweeps.size(), NW = (int)pp->wide.size();
+    int rc = VQE_OK;
+    if (S == 0) {  // only wide groups: lambda and the tile sweeps' energy slot start at zero
+        const uint64_t dim = 1ull << pp->n;
+        rc = hip_check(ctx, launch_fill(reinterpret_cast<double *>(lam), (int64_t)(2 * dim * B), 0.0, s), "zero lambda");
+        if (!rc) rc = hip_check(ctx, launch_fill(partials, B * (1 + NW) * (int64_t)W, 0.0, s), "zero partials");
+        if (rc) return rc;
+    }
+    for (int i = 0; i < S; ++i) {
+        rc = hip_check(ctx, hpsi_sweep(ctx, pp, i, psi, lam, B, ham_div, W, partials, s), "H psi sweep");
+        if (rc) return rc;
+    }
+    for (int j = 0; j < NW; ++j) {
+        ProfScope prof(ctx, "k_pauli_wide (H psi)", s, 48.0 * (double)(1ull << pp->n) * (double)B);
+        rc = hip_check(ctx, launch_pauli_wide(pp->wide[j], *pp, psi, lam, B, ham_div, W, partials, 1 + NW, 1 + j, s),
+                       "wide group H psi");
+        if (rc) return rc;
+    }
+    *slots = 1 + NW;
+    return VQE_OK;
 }
 
 int energy_grad_into(Context *ctx, Circ *C, int n_hams, Ham *const *H, int64_t B, uint64_t ref,
@@ -711,13 +857,10 @@ int energy_grad_into(Context *ctx, Circ *C, int n_hams, Ham *const *H, int64_t B
     if (rc) return rc;
     rc = forward(ctx, C, B, theta, psi, mats, s);
     if (rc) return rc;
-    const int S = (int)pp->sweeps.size();
-    for (int i = 0; i < S; ++i) {
-        rc = hip_check(ctx, hpsi_sweep(ctx, pp, i, psi, lam, B, n_hams == 1 ? 0 : 1, L.W_hpsi, pe, s),
-                       "H psi sweep");
-        if (rc) return rc;
-    }
-    rc = hip_check(ctx, launch_reduce_slots(pe, 1, L.W_hpsi, B, energy, e_stride, 1.0, s), "energy reduce");
+    int NH = 1;
+    rc = hpsi_all(ctx, pp, psi, lam, B, n_hams == 1 ? 0 : 1, L.W_hpsi, pe, &NH, s);
+    if (rc) return rc;
+    rc = hip_check(ctx, launch_reduce_slots(pe, NH, L.W_hpsi, B, energy, e_stride, 1.0, s), "energy reduce");
     if (!rc) rc = note_use(ctx, pp->uses, s);
     if (rc) return rc;
     const int G = (int)C->gates.size();
@@ -766,6 +909,159 @@ int energy_grad_into(Context *ctx, Circ *C, int n_hams, Ham *const *H, int64_t B
                                              reinterpret_cast<const int32_t *>(C->pmap_idx.p),
                                              C->n_params, B, grad, s),
                      "gradient reduce");
+}
+
+// energy + gradient of a batch in launch chunks of L.Bs instances
+int energy_grad_chunks(Context *ctx, Circ *C, int n_hams, Ham *const *H, int64_t B, uint64_t ref,
+                       const double *theta, double *energy, int64_t e_stride, double *grad, unsigned char *ws,
+                       const Layout &L, hipStream_t s)
+{
+    const int P = C->n_params;
+    for (int64_t c0 = 0; c0 < B; c0 += L.Bs) {
+        const int64_t nb = std::min(L.Bs, B - c0);
+        Ham *const *Hc = n_hams == 1 ? H : H + c0;
+        int rc = energy_grad_into(ctx, C, n_hams == 1 ? 1 : (int)nb, Hc, nb, ref, theta ? theta + c0 * P : nullptr,
+                                  energy + c0 * e_stride, e_stride, grad + c0 * P, ws, L, s);
+        if (rc) return rc;
+    }
+    return VQE_OK;
+}
+
+// energy of a batch in launch chunks of L.Bs instances (partials: L.pe or L.etmp)
+int energy_chunks(Context *ctx, Circ *C, int n_hams, Ham *const *H, int64_t B, uint64_t ref, const double *theta,
+                  double *energy, int64_t e_stride, unsigned char *ws, const Layout &L, size_t partials,
+                  hipStream_t s)
+{
+    const int P = C->n_params;
+    double2 *psi = (double2 *)(ws + L.psi);
+    for (int64_t c0 = 0; c0 < B; c0 += L.Bs) {
+        const int64_t nb = std::min(L.Bs, B - c0);
+        Ham *const *Hc = n_hams == 1 ? H : H + c0;
+        int rc = hip_check(ctx, launch_prepare(psi, C->n, nb, ref, s), "prepare");
+        if (!rc) rc = forward(ctx, C, nb, theta ? theta + c0 * P : nullptr, psi, (double2 *)(ws + L.mats), s);
+        if (!rc)
+            rc = expect_into(ctx, n_hams == 1 ? 1 : (int)nb, Hc, nb, psi, energy + c0 * e_stride, e_stride,
+                             (double *)(ws + partials), s);
+        if (rc) return rc;
+    }
+    return VQE_OK;
+}
+
+std::string tune_key(const Circ *C, int64_t batch, int mode)
+{
+    std::ostringstream k;
+    k << C->id << ':' << batch << ':' << mode;
+    return k.str();
+}
+
+// The tuned-tile mode of a vqe_run batch: the persistent loop (states that
+// fit one workgroup) keeps the default tiles; the per-step loop uses the
+// energy + gradient tuning.
+int run_mode(const Context *ctx, const Circ *C)
+{
+    return (C->n <= std::min(ctx->k_fwd, ctx->k_rev) && !C->gates.empty() && !ctx->force_generic) ? -1 : 1;
+}
+
+// Key of a launch sequence: every argument and setting the captured launches
+// depend on (pointers included: a graph replays them unchanged).
+std::string graph_key(Context *ctx, const char *what, const Circ *C, int n_hams, Ham *const *H, int64_t B,
+                      const Layout &L, uint64_t ref, const void *a, const void *b, const void *c, const void *ws,
+                      const std::string &extra)
+{
+    std::ostringstream k;
+    k << what << ':' << C->id << ':' << B << ':' << L.Bs << ':' << ref << ':' << a << ':' << b << ':' << c << ':'
+      << ws << ':' << ctx->k_fwd << ':' << ctx->k_rev << ':' << ctx->c_low << ':' << ctx->wg_max << ':'
+      << ctx->no_stages << ':' << ctx->fuse << ':' << extra << ':' << n_hams;
+    for (int i = 0; i < n_hams; ++i) k << ':' << H[i]->id;
+    return k.str();
+}
+
+void drop_entry(Context *ctx, Context::GraphEntry &e)
+{
+    if (!e.exec) return;
+    if (e.uses.empty() || events_done(e.uses)) {
+        (void)hipGraphExecDestroy(e.exec);
+        for (StreamUse &u : e.uses) (void)hipEventDestroy(u.event);
+    } else {
+        Context::Retired r;
+        r.uses = std::move(e.uses);
+        r.execs.push_back(e.exec);
+        ctx->retired.push_back(std::move(r));
+    }
+    e.exec = nullptr;
+    e.uses.clear();
+}
+
+// Run the launch sequence `body` (enqueues on the stream it is given) for
+// `key`: eagerly the first time; captured into a graph and launched the
+// second time; launched from the graph after that.  Profiling, a stream that
+// is itself being captured, or vqe_ctx_set_graphs(ctx, 0) keep it eager.
+template <class F>
+int run_graphed(Context *ctx, const std::string &key, uint64_t circ_id, hipStream_t s, F body)
+{
+    if (!ctx->graphs || ctx->profile || capturing(s)) return body(s);
+    auto it = ctx->graph_cache.find(key);
+    if (it != ctx->graph_cache.end() && it->second.epoch != ctx->plan_epoch) {  // a plan it read was retired
+        drop_entry(ctx, it->second);
+        ctx->graph_cache.erase(it);
+        it = ctx->graph_cache.end();
+    }
+    if (it == ctx->graph_cache.end()) {
+        if (ctx->graph_cache.size() >= 64) drop_graphs(ctx, 0);
+        Context::GraphEntry e;
+        e.epoch = ctx->plan_epoch;
+        e.circ_id = circ_id;
+        ctx->graph_cache.emplace(key, std::move(e));
+        return body(s);
+    }
+    Context::GraphEntry &e = it->second;
+    if (e.failed) return body(s);
+    if (!e.exec) {
+        // Capture on a stream of the context's own.  The first call built
+        // every table; wait once for it and for pending uploads, so no launch
+        // in the sequence needs an event recorded outside the capture.
+        int rc = hip_check(ctx, hipStreamSynchronize(s), "hipStreamSynchronize (before capture)");
+        if (!rc && ctx->upload_ev) rc = hip_check(ctx, hipEventSynchronize(ctx->upload_ev), "upload event");
+        if (!rc && !ctx->capture_stream)
+            rc = hip_check(ctx, hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking),
+                           "hipStreamCreate (capture)");
+        if (rc) return rc;
+        std::vector<PauliPlan *> plans;
+        ctx->capture_plans = &plans;
+        hipGraph_t g = nullptr;
+        rc = hip_check(ctx, hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeRelaxed),
+                       "hipStreamBeginCapture");
+        if (!rc) {
+            {
+                StreamCall sc(ctx, ctx->capture_stream);
+                rc = sc.rc ? sc.rc : body(ctx->capture_stream);
+            }
+            hipError_t ee = hipStreamEndCapture(ctx->capture_stream, &g);
+            if (!rc) rc = hip_check(ctx, ee, "hipStreamEndCapture");
+            else (void)hipGetLastError();
+        }
+        ctx->capture_plans = nullptr;
+        if (!rc) rc = hip_check(ctx, hipGraphInstantiate(&e.exec, g, nullptr, nullptr, 0), "hipGraphInstantiate");
+        if (g) (void)hipGraphDestroy(g);
+        if (rc) {
+            e.exec = nullptr;
+            e.failed = true;  // this sequence stays eager
+            ctx->err.clear();
+            return body(s);
+        }
+        std::sort(plans.begin(), plans.end());
+        plans.erase(std::unique(plans.begin(), plans.end()), plans.end());
+        e.plans = std::move(plans);
+        ++ctx->graph_captures;
+    }
+    int rc = hip_check(ctx, hipGraphLaunch(e.exec, s), "hipGraphLaunch");
+    if (rc) return rc;
+    ++ctx->graph_launches;
+    for (PauliPlan *p : e.plans) {
+        rc = note_use(ctx, p->uses, s);
+        if (rc) return rc;
+    }
+    return note_use(ctx, e.uses, s);
 }
 
 int build_shift(Context *ctx, Circ *C)
@@ -882,9 +1178,11 @@ int vqe_ctx_destroy(vqe_ctx_t ctx)
         (void)hipSetDevice(ctx->device);
         (void)hipDeviceSynchronize();
     }
+    drop_graphs(ctx, 0);
     for (auto &kv : ctx->pauli_cache) retire_pauli_plan(ctx, kv.second.get());
     ctx->pauli_cache.clear();
     poll_retired(ctx, true);
+    if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
     prof_collect(ctx);
     for (hipEvent_t e : ctx->prof_events) (void)hipEventDestroy(e);
     dev_free(ctx, ctx->scratch);
@@ -919,6 +1217,34 @@ int vqe_stream_destroy(vqe_ctx_t ctx, void *stream)
     if (rc) return rc;
     if (!stream) return set_err(ctx, VQE_EINVAL, "stream is NULL");
     return hip_check(ctx, hipStreamDestroy((hipStream_t)stream), "hipStreamDestroy");
+}
+
+int vqe_ctx_set_graphs(vqe_ctx_t ctx, int on)
+{
+    if (!ctx) return VQE_EINVAL;
+    ctx->graphs = on ? 1 : 0;
+    if (!on) drop_graphs(ctx, 0);
+    return VQE_OK;
+}
+
+int vqe_ctx_graph_stats(vqe_ctx_t ctx, int64_t *captures, int64_t *launches, int64_t *cached)
+{
+    if (!ctx) return VQE_EINVAL;
+    if (captures) *captures = ctx->graph_captures;
+    if (launches) *launches = ctx->graph_launches;
+    if (cached) {
+        int64_t c = 0;
+        for (auto &kv : ctx->graph_cache) c += kv.second.exec != nullptr;
+        *cached = c;
+    }
+    return VQE_OK;
+}
+
+int vqe_ctx_clear_tuning(vqe_ctx_t ctx)
+{
+    if (!ctx) return VQE_EINVAL;
+    ctx->tuned.clear();
+    return VQE_OK;
 }
 
 int vqe_ctx_set_mem_budget(vqe_ctx_t ctx, size_t bytes)
@@ -1307,6 +1633,8 @@ int vqe_circ_destroy(vqe_circ_t C)
         (void)hipSetDevice(ctx->device);
         (void)hipDeviceSynchronize();
     }
+    drop_graphs(ctx, C->id);
+    poll_retired(ctx, true);
     free_circ_plans(ctx, C);
     ready_free(C->shift_ready);
     dev_free(ctx, C->gates_dev);
@@ -1330,8 +1658,10 @@ int vqe_workspace_bytes(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ha
     std::vector<Ham *> H;
     rc = check_hams(ctx, n_hams, hams, batch, circ->n, H);
     if (rc) return rc;
+    const int mode = want_grad == 3 ? -1 : want_grad == 2 ? run_mode(ctx, circ) : want_grad;
+    TileScope tiles(ctx, circ, batch, mode);
     Layout L;
-    rc = layout_for(ctx, circ, n_hams, H.data(), batch, want_grad, L);
+    rc = layout_for(ctx, circ, n_hams, H.data(), batch, want_grad, L, tiles.bt);
     if (rc) return rc;
     *bytes = L.total;
     return VQE_OK;
@@ -1420,7 +1750,8 @@ int vqe_expect(vqe_ctx_t ctx, int n_hams, const vqe_ham_t *hams, int64_t batch, 
     PauliPlan *pp = get_pauli_plan(ctx, n_hams, H.data(), n_inst, ctx->k_fwd, ctx->c_low, &rc);
     if (!pp) return rc;
     void *part;
-    rc = scratch_get(ctx, (size_t)batch * pp->sweeps.size() * wg_for(ctx, n, ctx->k_fwd) * 8, &part);
+    rc = scratch_get(ctx, (size_t)batch * (pp->sweeps.size() + pp->wide.size()) * wg_for(ctx, n, ctx->k_fwd) * 8,
+                     &part);
     if (rc) return rc;
     rc = expect_into(ctx, n_hams, H.data(), batch, (const double2 *)psi, energy, 1, (double *)part,
                      (hipStream_t)stream);
@@ -1448,15 +1779,12 @@ int vqe_apply_hamiltonian(vqe_ctx_t ctx, int n_hams, const vqe_ham_t *hams, int6
     if (rc) return rc;
     const int W = wg_for(ctx, n, ctx->k_rev);
     void *part;
-    rc = scratch_get(ctx, (size_t)batch * W * 8, &part);
+    rc = scratch_get(ctx, (size_t)batch * (1 + pp->wide.size()) * W * 8, &part);
     if (rc) return rc;
-    const int S = (int)pp->sweeps.size();
-    for (int i = 0; i < S; ++i) {
-        rc = hip_check(ctx, hpsi_sweep(ctx, pp, i, (const double2 *)psi, (double2 *)out, batch,
-                                       n_hams == 1 ? 0 : 1, W, (double *)part, (hipStream_t)stream),
-                       "H psi sweep");
-        if (rc) return rc;
-    }
+    int NH = 1;
+    rc = hpsi_all(ctx, pp, (const double2 *)psi, (double2 *)out, batch, n_hams == 1 ? 0 : 1, W, (double *)part, &NH,
+                  (hipStream_t)stream);
+    if (rc) return rc;
     rc = note_use(ctx, ctx->scratch_uses, (hipStream_t)stream);
     if (rc) return rc;
     return note_use(ctx, pp->uses, (hipStream_t)stream);
@@ -1476,18 +1804,17 @@ int vqe_energy(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams
     std::vector<Ham *> H;
     rc = check_hams(ctx, n_hams, hams, batch, circ->n, H);
     if (rc) return rc;
+    TileScope tiles(ctx, circ, batch, 0);
     Layout L;
-    rc = layout_for(ctx, circ, n_hams, H.data(), batch, 0, L);
+    rc = layout_for(ctx, circ, n_hams, H.data(), batch, 0, L, tiles.bt);
     if (rc) return rc;
     if (ws_bytes < L.total) return set_err(ctx, VQE_EINVAL, "workspace too small");
     unsigned char *ws = (unsigned char *)workspace;
-    hipStream_t s = (hipStream_t)stream;
-    double2 *psi = (double2 *)(ws + L.psi);
-    rc = hip_check(ctx, launch_prepare(psi, circ->n, batch, ref_index, s), "prepare");
-    if (rc) return rc;
-    rc = forward(ctx, circ, batch, theta, psi, (double2 *)(ws + L.mats), s);
-    if (rc) return rc;
-    return expect_into(ctx, n_hams, H.data(), batch, psi, energy, 1, (double *)(ws + L.pe), s);
+    const std::string key = graph_key(ctx, "e", circ, n_hams, H.data(), batch, L, ref_index, theta, energy,
+                                      nullptr, ws, "");
+    return run_graphed(ctx, key, circ->id, (hipStream_t)stream, [&](hipStream_t s) {
+        return energy_chunks(ctx, circ, n_hams, H.data(), batch, ref_index, theta, energy, 1, ws, L, L.pe, s);
+    });
 }
 
 int vqe_energy_grad(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams, int64_t batch,
@@ -1504,12 +1831,17 @@ int vqe_energy_grad(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t 
     std::vector<Ham *> H;
     rc = check_hams(ctx, n_hams, hams, batch, circ->n, H);
     if (rc) return rc;
+    TileScope tiles(ctx, circ, batch, 1);
     Layout L;
-    rc = layout_for(ctx, circ, n_hams, H.data(), batch, 1, L);
+    rc = layout_for(ctx, circ, n_hams, H.data(), batch, 1, L, tiles.bt);
     if (rc) return rc;
     if (ws_bytes < L.total) return set_err(ctx, VQE_EINVAL, "workspace too small");
-    return energy_grad_into(ctx, circ, n_hams, H.data(), batch, ref_index, theta, energy, 1, grad,
-                            (unsigned char *)workspace, L, (hipStream_t)stream);
+    unsigned char *ws = (unsigned char *)workspace;
+    const std::string key = graph_key(ctx, "g", circ, n_hams, H.data(), batch, L, ref_index, theta, energy, grad,
+                                      ws, "");
+    return run_graphed(ctx, key, circ->id, (hipStream_t)stream, [&](hipStream_t s) {
+        return energy_grad_chunks(ctx, circ, n_hams, H.data(), batch, ref_index, theta, energy, 1, grad, ws, L, s);
+    });
 }
 
 int vqe_grad_shift(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams, int64_t batch,
@@ -1557,14 +1889,10 @@ int vqe_grad_shift(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *
     if (!rc && G > 0) rc = run_forward_passes(ctx, circ, fp, R, psi, mats, s);
     if (rc) return rc;
     const int W = wg_for(ctx, n, ctx->k_fwd);
-    const int S = (int)pp->sweeps.size();
-    for (int i = 0; i < S; ++i) {
-        rc = hip_check(ctx, launch_pauli_sweep(pp->sweeps[i], *pp, i, psi, nullptr, R, n_hams == 1 ? 0 : R0, W, part,
-                                               S, false, i == 0, i == S - 1, s),
-                       "expectation sweep");
-        if (rc) return rc;
-    }
-    rc = hip_check(ctx, launch_reduce_slots(part, S, W, R, erows, 1, 1.0, s), "energy reduce");
+    int NS = 0;
+    rc = expect_sweeps(ctx, pp, psi, R, n_hams == 1 ? 0 : R0, W, part, &NS, s);
+    if (rc) return rc;
+    rc = hip_check(ctx, launch_reduce_slots(part, NS, W, R, erows, 1, 1.0, s), "energy reduce");
     if (!rc) rc = note_use(ctx, pp->uses, s);
     if (rc) return rc;
     return hip_check(ctx, launch_shift_combine(erows, R0, reinterpret_cast<const int32_t *>(circ->shift_off.p),
@@ -1621,8 +1949,9 @@ int vqe_run(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams, i
     std::vector<Ham *> H;
     rc = check_hams(ctx, n_hams, hams, batch, circ->n, H);
     if (rc) return rc;
+    TileScope tiles(ctx, circ, batch, run_mode(ctx, circ));
     Layout L;
-    rc = layout_for(ctx, circ, n_hams, H.data(), batch, 2, L);
+    rc = layout_for(ctx, circ, n_hams, H.data(), batch, 2, L, tiles.bt);
     if (rc) return rc;
     if (ws_bytes < L.total) return set_err(ctx, VQE_EINVAL, "workspace too small");
     unsigned char *ws = (unsigned char *)workspace;
@@ -1692,7 +2021,12 @@ int vqe_run(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams, i
         }
     }
 
+    // per-step loop: every step is the same launch sequence (the step index
+    // and the energy column live in device memory), captured once into a
+    // graph and replayed
     double *g = (double *)(ws + L.grad), *m = (double *)(ws + L.m), *v = (double *)(ws + L.v);
+    double *estep = (double *)(ws + L.estep);
+    int64_t *step = (int64_t *)(ws + L.step);
     const int64_t e_stride = (int64_t)iters + 1;
     const int64_t np = batch * (int64_t)P;
     if (np > 0) {
@@ -1700,23 +2034,183 @@ int vqe_run(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams, i
         if (!rc) rc = hip_check(ctx, launch_fill(v, np, 0.0, s), "zero moments");
         if (rc) return rc;
     }
+    rc = hip_check(ctx, launch_step_set(step, 0, s), "step index");
+    if (rc) return rc;
+    char extra[160];
+    std::snprintf(extra, sizeof extra, "%d:%a:%a:%a:%a:%lld", optimizer, lr, b1, b2, eps, (long long)e_stride);
+    const std::string key = graph_key(ctx, "r", circ, n_hams, H.data(), batch, L, ref_index, theta, energies,
+                                      nullptr, ws, extra);
     for (int it = 0; it < iters; ++it) {
-        rc = energy_grad_into(ctx, circ, n_hams, H.data(), batch, ref_index, theta, energies + it, e_stride, g,
-                              ws, L, s);
-        if (rc) return rc;
-        if (optimizer == VQE_OPT_ADAM)
-            rc = hip_check(ctx, launch_adam(np, theta, m, v, g, it + 1, lr, b1, b2, eps, s), "adam");
-        else
-            rc = hip_check(ctx, launch_gd(np, theta, g, lr, s), "gd");
+        rc = run_graphed(ctx, key, circ->id, s, [&](hipStream_t st) {
+            int r = energy_grad_chunks(ctx, circ, n_hams, H.data(), batch, ref_index, theta, estep, 1, g, ws, L, st);
+            if (!r)
+                r = hip_check(ctx, launch_opt_step(optimizer, batch, P, theta, m, v, g, estep, energies, e_stride,
+                                                   step, lr, b1, b2, eps, st),
+                              "optimiser step");
+            if (!r) r = hip_check(ctx, launch_step_advance(step, st), "step index");
+            return r;
+        });
         if (rc) return rc;
     }
     // energy at the final parameters
-    double2 *psi = (double2 *)(ws + L.psi);
-    rc = hip_check(ctx, launch_prepare(psi, circ->n, batch, ref_index, s), "prepare");
+    return energy_chunks(ctx, circ, n_hams, H.data(), batch, ref_index, theta, energies + iters, e_stride, ws, L,
+                         L.etmp, s);
+}
+
+int vqe_autotune(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams, int64_t batch,
+                 uint64_t ref_index, int want_grad, const double *theta, void *stream, vqe_tune_result *out)
+{
+    int rc = check_dev(ctx);
     if (rc) return rc;
-    rc = forward(ctx, circ, batch, theta, psi, (double2 *)(ws + L.mats), s);
+    if (!circ || !out || batch < 1 || (want_grad != 0 && want_grad != 1) || (circ->n_params > 0 && !theta))
+        return set_err(ctx, VQE_EINVAL, "bad argument");
+    if (batch > kMaxBatch) return set_err(ctx, VQE_EUNSUPPORTED, "batch > 65535");
+    if (ctx->tune_override) return set_err(ctx, VQE_EINVAL, "autotune re-entered");
+    hipStream_t s = (hipStream_t)stream;
+    const int n = circ->n;
+    const std::string key = tune_key(circ, batch, want_grad);
+    ctx->tuned.erase(key);  // time the defaults, not an earlier choice
+
+    // the tuner's own outputs and workspace (grown per candidate; tuning is set-up work)
+    DevMem outs, wsm;
+    const size_t out_bytes = align_up((size_t)batch * 8) + (size_t)batch * std::max(circ->n_params, 1) * 8;
+    rc = dev_alloc(ctx, outs, out_bytes);
     if (rc) return rc;
-    return expect_into(ctx, n_hams, H.data(), batch, psi, energies + iters, e_stride, (double *)(ws + L.etmp), s);
+    double *energy = (double *)outs.p;
+    double *grad = (double *)((unsigned char *)outs.p + align_up((size_t)batch * 8));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    rc = hip_check(ctx, hipEventCreate(&e0), "hipEventCreate");
+    if (!rc) rc = hip_check(ctx, hipEventCreate(&e1), "hipEventCreate");
+    if (rc) {
+        dev_free(ctx, outs);
+        return rc;
+    }
+    int timed = 0;
+    // ms per call of one candidate; false when it does not run (memory, an
+    // unsupported Pauli string for its tiles, ...)
+    auto time_cfg = [&](const Context::Tuned &t, double *ms) -> bool {
+        ctx->tune_override = &t;
+        size_t need = 0;
+        int r = vqe_workspace_bytes(ctx, circ, n_hams, hams, batch, want_grad, &need);
+        if (!r && wsm.bytes < need) {
+            if (wsm.p) {  // earlier candidates' launches may still read it
+                std::vector<StreamUse> u;
+                r = note_use(ctx, u, s);
+                retire(ctx, {wsm}, std::move(u));
+                wsm = DevMem{};
+            }
+            if (!r) r = dev_alloc(ctx, wsm, need);
+        }
+        auto call = [&]() {
+            return want_grad ? vqe_energy_grad(ctx, circ, n_hams, hams, batch, ref_index, theta, energy, grad,
+                                               wsm.p, wsm.bytes, stream)
+                             : vqe_energy(ctx, circ, n_hams, hams, batch, ref_index, theta, energy, wsm.p,
+                                          wsm.bytes, stream);
+        };
+        // two untimed calls: plans and uploads, then the graph capture
+        for (int w = 0; !r && w < 2; ++w) r = call();
+        if (!r) r = hip_check(ctx, hipStreamSynchronize(s), "hipStreamSynchronize");
+        int reps = 0;
+        float total = 0.0f;
+        while (!r && (reps < 3 || (total < 20.0f && reps < 50))) {
+            const int chunk = reps < 3 ? 3 : reps;
+            r = hip_check(ctx, hipEventRecord(e0, s), "hipEventRecord");
+            for (int i = 0; !r && i < chunk; ++i) r = call();
+            if (!r) r = hip_check(ctx, hipEventRecord(e1, s), "hipEventRecord");
+            if (!r) r = hip_check(ctx, hipEventSynchronize(e1), "hipEventSynchronize");
+            float t_ms = 0.0f;
+            if (!r) r = hip_check(ctx, hipEventElapsedTime(&t_ms, e0, e1), "hipEventElapsedTime");
+            total += t_ms;
+            reps += chunk;
+        }
+        ctx->tune_override = nullptr;
+        if (r) {
+            ctx->err.clear();
+            (void)hipGetLastError();
+            return false;
+        }
+        ++timed;
+        *ms = total / reps;
+        return true;
+    };
+
+    Context::Tuned best;
+    best.k_fwd = ctx->k_fwd;
+    best.k_rev = ctx->k_rev;
+    best.c_low = ctx->c_low;
+    best.wg_max = ctx->wg_max;
+    best.batch_tile = 0;
+    double best_ms = 0.0;
+    auto release = [&]() {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        std::vector<StreamUse> u;
+        (void)note_use(ctx, u, s);
+        retire(ctx, {outs, wsm}, std::move(u));
+    };
+    if (!time_cfg(best, &best_ms)) {
+        release();
+        return set_err(ctx, VQE_ENOMEM, "the default configuration could not be evaluated (memory?)");
+    }
+    const double ms_default = best_ms;
+    auto valid = [&](const Context::Tuned &t) {
+        return t.k_fwd >= 6 && t.k_fwd <= kMaxTileBits && t.k_rev >= 6 && t.k_rev <= 12 && t.c_low >= 2 &&
+               std::min(t.k_fwd, t.k_rev) - t.c_low >= 4;
+    };
+    auto try_values = [&](auto set, const std::vector<int64_t> &vals) {
+        for (int64_t v : vals) {
+            Context::Tuned t = best;
+            set(t, v);
+            if (!valid(t) || std::memcmp(&t, &best, sizeof t) == 0) continue;
+            double ms;
+            if (time_cfg(t, &ms) && ms < best_ms * 0.98) {  // 2 %: below the run-to-run noise
+                best = t;
+                best_ms = ms;
+            }
+        }
+    };
+    if (n > 8) {  // smaller states are one tile at every width
+        std::vector<int64_t> kf, kr, cl = {2, 3, 4}, wg = {256, 1024, 4096}, bt;
+        for (int k = 8; k <= std::min(n, (int)kMaxTileBits); ++k) kf.push_back(k);
+        for (int k = 8; k <= std::min(n, 12); ++k) kr.push_back(k);
+        for (int64_t b = batch / 2; b >= 1; b /= 2) bt.push_back(b);
+        try_values([](Context::Tuned &t, int64_t v) { t.k_fwd = (int)v; }, kf);
+        if (want_grad) try_values([](Context::Tuned &t, int64_t v) { t.k_rev = (int)v; }, kr);
+        try_values([](Context::Tuned &t, int64_t v) { t.c_low = (int)v; }, cl);
+        if (batch > 1) try_values([](Context::Tuned &t, int64_t v) { t.batch_tile = v; }, bt);
+        try_values([](Context::Tuned &t, int64_t v) { t.wg_max = (int)v; }, wg);
+    }
+    release();
+    ctx->tuned[key] = best;
+    out->k_fwd = best.k_fwd;
+    out->k_rev = best.k_rev;
+    out->c_low = best.c_low;
+    out->wg_max = best.wg_max;
+    out->batch_tile = best.batch_tile ? best.batch_tile : batch;
+    out->ms_default = ms_default;
+    out->ms_tuned = best_ms;
+    out->candidates = timed;
+    return VQE_OK;
+}
+
+int vqe_tune_set(vqe_ctx_t ctx, vqe_circ_t circ, int64_t batch, int want_grad, const vqe_tune_result *cfg)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!circ || !cfg || batch < 1 || (want_grad != 0 && want_grad != 1))
+        return set_err(ctx, VQE_EINVAL, "bad argument");
+    Context::Tuned t;
+    t.k_fwd = cfg->k_fwd;
+    t.k_rev = cfg->k_rev;
+    t.c_low = cfg->c_low;
+    t.wg_max = cfg->wg_max;
+    t.batch_tile = cfg->batch_tile >= batch ? 0 : cfg->batch_tile;
+    if (t.k_fwd < 6 || t.k_fwd > kMaxTileBits || t.k_rev < 6 || t.k_rev > 12 || t.c_low < 2 ||
+        std::min(t.k_fwd, t.k_rev) - t.c_low < 4 || t.wg_max < 1 || cfg->batch_tile < 1)
+        return set_err(ctx, VQE_EINVAL, "configuration out of range (6 <= k, k_rev <= 12, k - c_low >= 4, "
+                                        "wg_max >= 1, batch_tile >= 1)");
+    ctx->tuned[tune_key(circ, batch, want_grad)] = t;
+    return VQE_OK;
 }
 
 int vqe_circ_plan_export(vqe_ctx_t ctx, vqe_circ_t circ, int reverse, void *buf, size_t buf_bytes,
@@ -1788,7 +2282,8 @@ int vqe_ham_plan_export(vqe_ctx_t ctx, int n_hams, const vqe_ham_t *hams, int64_
     if (!p) return rc;
     const size_t sweep_bytes = sizeof(TileGeom) + 16;
     const size_t need = 32 + p->sweeps.size() * sweep_bytes + p->host_groups.size() * sizeof(GroupDev) +
-                        p->host_toff.size() * 4 + p->host_terms.size() * sizeof(TermDev);
+                        p->host_toff.size() * 4 + p->host_terms.size() * sizeof(TermDev) + 8 +
+                        p->wide.size() * sizeof(WideGroup);
     *needed = need;
     if (!buf || buf_bytes < need) return VQE_OK;
     unsigned char *o = (unsigned char *)buf;
@@ -1808,6 +2303,11 @@ int vqe_ham_plan_export(vqe_ctx_t ctx, int n_hams, const vqe_ham_t *hams, int64_
     std::memcpy(o, p->host_toff.data(), p->host_toff.size() * 4);
     o += p->host_toff.size() * 4;
     std::memcpy(o, p->host_terms.data(), p->host_terms.size() * sizeof(TermDev));
+    o += p->host_terms.size() * sizeof(TermDev);
+    const int32_t wh[2] = {(int32_t)p->wide.size(), (int32_t)sizeof(WideGroup)};
+    std::memcpy(o, wh, 8);
+    o += 8;
+    if (!p->wide.empty()) std::memcpy(o, p->wide.data(), p->wide.size() * sizeof(WideGroup));
     return VQE_OK;
 }
 

@@ -303,6 +303,16 @@ struct Circ {
     Ready shift_ready;
 };
 
+// A flip group too wide for any tile (more flip bits outside the low c bits
+// than a tile has free bits): evaluated by a whole-state pair sweep over
+// b with bit `pivot` clear and its partner b ^ f.
+struct WideGroup {
+    uint64_t f;
+    int32_t pivot;       // lowest set bit of f
+    int32_t ugroup;      // union group index (after every tile sweep's groups)
+};
+static_assert(sizeof(WideGroup) == 16, "WideGroup layout");
+
 // Union Pauli plan for a list of Hamiltonians on one tile geometry.
 struct SweepPlan {
     TileGeom geom;
@@ -313,6 +323,7 @@ struct PauliPlan {
     int n = 0, n_inst = 0, k = 0, c = 0;
     int n_ugroups = 0;
     std::vector<SweepPlan> sweeps;
+    std::vector<WideGroup> wide;     // whole-state pair sweeps, after the tile sweeps
     DevMem groups;   // GroupDev[total groups over sweeps]
     DevMem geoms;    // TileGeom[sweeps]
     DevMem toff;     // int32 [n_inst][n_ugroups][3] (begin_re, begin_im, end)
@@ -353,6 +364,7 @@ struct Context {
     struct Retired {
         std::vector<DevMem> mem;
         std::vector<StreamUse> uses;
+        std::vector<hipGraphExec_t> execs;
     };
     std::vector<Retired> retired;
     // The call in progress (set by StreamCall): uploads made inside a call
@@ -388,6 +400,44 @@ struct Context {
         double ms = 0.0, bytes = 0.0;
     };
     std::map<std::string, ProfAcc> prof_acc;
+
+    // Launch graphs (vqe_ctx_set_graphs): a launch sequence seen a second
+    // time with identical arguments is captured into a hipGraph and replayed
+    // from then on.  Arguments that change between launches of one sequence
+    // (the optimiser step) live in device memory.  An entry is dropped when a
+    // Pauli plan it reads is retired (plan_epoch) or its circuit destroyed.
+    int graphs = 1;
+    uint64_t plan_epoch = 0;
+    hipStream_t capture_stream = nullptr;
+    std::vector<PauliPlan *> *capture_plans = nullptr;  // Pauli plans read by the sequence being captured
+    struct GraphEntry {
+        hipGraphExec_t exec = nullptr;
+        bool failed = false;             // capture failed once: stays eager
+        uint64_t epoch = 0;
+        uint64_t circ_id = 0;
+        std::vector<PauliPlan *> plans;
+        std::vector<StreamUse> uses;     // streams the graph was launched on
+    };
+    std::map<std::string, GraphEntry> graph_cache;
+    int64_t graph_launches = 0, graph_captures = 0;
+
+    // Autotuned execution choices (vqe_autotune) per (circuit, batch, mode).
+    struct Tuned {
+        int k_fwd = 12, k_rev = 11, c_low = 3, wg_max = 1024;
+        int64_t batch_tile = 0;          // instances per launch sequence (0: the whole batch)
+    };
+    std::map<std::string, Tuned> tuned;
+    const Tuned *tune_override = nullptr;  // set while the tuner times a candidate
+};
+
+// Applies the tuned tiles of (circ, batch, mode) to the context for one call
+// (calls on a context are single-threaded) and restores the defaults after.
+struct TileScope {
+    Context *ctx;
+    int kf, kr, cl, wm;
+    int64_t bt = 0;  // batch tile of the call (0: whole batch)
+    TileScope(Context *c, const Circ *C, int64_t batch, int mode);
+    ~TileScope();
 };
 
 // Times the launches enqueued during its lifetime on stream s under `name`
@@ -433,6 +483,8 @@ int note_use(Context *ctx, std::vector<StreamUse> &uses, hipStream_t s);
 // drop device tables that queued kernels may still read (stream-ordered)
 void retire(Context *ctx, std::vector<DevMem> mem, std::vector<StreamUse> uses);
 void retire_pauli_plan(Context *ctx, PauliPlan *p);
+// drop the graphs of a circuit (circ_id != 0) or every graph (circ_id == 0)
+void drop_graphs(Context *ctx, uint64_t circ_id);
 void poll_retired(Context *ctx, bool wait);
 
 // jw.cpp
@@ -496,6 +548,12 @@ hipError_t launch_pauli_sweep(const SweepPlan &sp, const PauliPlan &pp, int swee
                               int ham_div, int wg_per_inst, double *partials,
                               int n_slots, bool write_lambda, bool first, bool last,
                               hipStream_t s);
+// a wide group's whole-state pair sweep: lam NULL = expectation into slot
+// `slot` of partials [batch][n_slots][wg]; else H psi added into lam and its
+// energy term into that slot
+hipError_t launch_pauli_wide(const WideGroup &w, const PauliPlan &pp, const double2 *psi, double2 *lam,
+                             int64_t batch, int ham_div, int wg_per_inst, double *partials, int n_slots, int slot,
+                             hipStream_t s);
 hipError_t launch_hpsi_gather(const SweepPlan &sp, const PauliPlan &pp, int sweep_idx, const double2 *psi,
                               double2 *lam, int64_t batch, int ham_div, int wg_per_inst, double *partials,
                               bool first, bool last, hipStream_t s);
@@ -508,6 +566,13 @@ hipError_t launch_grad_reduce(const double *partials, int n_pgates, int wg_per_i
 hipError_t launch_adam(int64_t count, double *theta, double *m, double *v, const double *g,
                        int t, double lr, double b1, double b2, double eps, hipStream_t s);
 hipError_t launch_gd(int64_t count, double *theta, const double *g, double lr, hipStream_t s);
+// one optimiser step of a replayable loop: the step index lives in *step
+// (read, not advanced); energies[b * stride + *step] = e[b] for b < batch
+hipError_t launch_opt_step(int opt, int64_t batch, int32_t n_params, double *theta, double *m, double *v,
+                           const double *g, const double *e, double *energies, int64_t e_stride,
+                           const int64_t *step, double lr, double b1, double b2, double eps, hipStream_t s);
+hipError_t launch_step_set(int64_t *step, int64_t value, hipStream_t s);   // *step = value
+hipError_t launch_step_advance(int64_t *step, hipStream_t s);             // *step += 1
 hipError_t launch_fill(double *p, int64_t count, double value, hipStream_t s);
 hipError_t launch_shift_mats(const GateDev *gates, int n_gates, const double *theta, int n_params,
                              int64_t batch, const ShiftRow *rows, int rows_per_inst, double2 *mats,

@@ -1917,6 +1917,57 @@ __global__ __launch_bounds__(kThreads) void k_pauli_sweep(
     }
 }
 
+// A wide flip group f over the whole state: every pair (b, b ^ f) with bit
+// `pivot` of b clear, b anywhere in the index space (no tile holds the
+// pair).  A(b) and B(b) are the group's real- and imaginary-phase weights
+// signed by (-1)^{|z & b|} over the full z masks; the expectation term is
+// 2 (Re w A - Im w B) with w = conj(psi[b ^ f]) psi[b] (the same pair form
+// as the tile sweeps), and H psi adds (A + iB) psi[b] to lambda[b ^ f] and
+// (A - iB) psi[b ^ f] to lambda[b] (each element belongs to one pair, so no
+// two threads update it) and accumulates the same energy term.
+template <bool HPSI>
+__global__ __launch_bounds__(kThreads) void k_pauli_wide(int n, uint64_t f, int pivot, int ug,
+                                                        const int32_t *__restrict__ toff, int n_ugroups,
+                                                        const TermDev *__restrict__ terms, int ham_div,
+                                                        const double2 *__restrict__ psi, double2 *__restrict__ lam,
+                                                        double *__restrict__ partials, int n_slots, int slot)
+{
+    __shared__ double red[4];
+    const int inst = blockIdx.y;
+    const uint64_t dim = 1ull << n, half = dim >> 1;
+    const double2 *sp = psi + (uint64_t)inst * dim;
+    double2 *sl = HPSI ? lam + (uint64_t)inst * dim : nullptr;
+    const int32_t *to = toff + (size_t)(ham_div == 0 ? 0 : inst / ham_div) * n_ugroups * 3;
+    const int tb = to[ug * 3 + 0], tm = to[ug * 3 + 1], te = to[ug * 3 + 2];
+    const uint64_t lowm = (1ull << pivot) - 1ull;
+    double acc = 0.0;
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < half;
+         j += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t b = ((j >> pivot) << (pivot + 1)) | (j & lowm);
+        const uint64_t bf = b ^ f;
+        const double2 x0 = sp[b], x1 = sp[bf];
+        double A = 0.0, B = 0.0;
+        for (int i = tb; i < tm; ++i) {
+            const TermDev d = terms[i];
+            A += signed_by_parity(d.w, (uint32_t)(__popcll(d.zfull & b) & 1));
+        }
+        for (int i = tm; i < te; ++i) {
+            const TermDev d = terms[i];
+            B += signed_by_parity(d.w, (uint32_t)(__popcll(d.zfull & b) & 1));
+        }
+        const double wr = x1.x * x0.x + x1.y * x0.y;
+        const double wi = x1.x * x0.y - x1.y * x0.x;
+        acc += 2.0 * (wr * A - wi * B);
+        if (HPSI) {
+            const double2 l1 = sl[bf], l0 = sl[b];
+            sl[bf] = cadd(l1, make_double2(A * x0.x - B * x0.y, A * x0.y + B * x0.x));
+            sl[b] = cadd(l0, make_double2(A * x1.x + B * x1.y, A * x1.y - B * x1.x));
+        }
+    }
+    const double sum = block_sum(acc, red);
+    if (threadIdx.x == 0) partials[((size_t)inst * n_slots + slot) * gridDim.x + blockIdx.x] = sum;
+}
+
 // H psi of one sweep by gathering.  Every thread owns NO amplitudes
 // o = tid + r * kThreads of the tile and accumulates (H psi)[o] in registers
 // over the sweep's groups.  For a flip group f with pivot bit v, let
@@ -2122,6 +2173,41 @@ __global__ void k_gd(int64_t count, double *__restrict__ theta, const double *__
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
          i += (int64_t)gridDim.x * blockDim.x)
         theta[i] -= lr * g[i];
+}
+
+// One optimiser step of a loop whose launches are replayed unchanged (a
+// captured graph): the step index t - 1 comes from device memory, so the
+// bias corrections 1 - b^t are formed here; the first `batch` threads also
+// file the step's energies into column *step of energies[batch][stride].
+__global__ void k_opt_step(int opt, int64_t batch, int64_t count, double *__restrict__ theta, double *__restrict__ m,
+                           double *__restrict__ v, const double *__restrict__ g, const double *__restrict__ e,
+                           double *__restrict__ energies, int64_t e_stride, const int64_t *__restrict__ step,
+                           double lr, double b1, double b2, double eps)
+{
+    const int64_t it = *step;
+    const double t = (double)(it + 1);
+    const double c1 = 1.0 - pow(b1, t), c2 = 1.0 - pow(b2, t);
+    const int64_t total = count > batch ? count : batch;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (i < batch) energies[i * e_stride + it] = e[i];
+        if (i >= count) continue;
+        const double gi = g[i];
+        if (opt == 0) {
+            const double mi = b1 * m[i] + (1.0 - b1) * gi;
+            const double vi = b2 * v[i] + (1.0 - b2) * gi * gi;
+            m[i] = mi;
+            v[i] = vi;
+            theta[i] -= lr * (mi / c1) / (sqrt(vi / c2) + eps);
+        } else {
+            theta[i] -= lr * gi;
+        }
+    }
+}
+
+__global__ void k_step_set(int64_t *step, int64_t value, int64_t add)
+{
+    if (threadIdx.x == 0) *step = add ? *step + 1 : value;
 }
 
 __global__ void k_fill(double *__restrict__ p, int64_t count, double value)
@@ -2367,7 +2453,22 @@ hipError_t launch_pauli_sweep(const SweepPlan &sp, const PauliPlan &pp, int swee
                        reinterpret_cast<const int32_t *>(pp.toff.p), pp.n_ugroups,
                        reinterpret_cast<const TermDev *>(pp.terms.p), ham_div, psi,
                        write_lambda ? lam : nullptr, tiles, (int)first, (int)last, partials,
-                       n_slots, write_lambda ? 0 : sweep_idx, tcap);
+                       write_lambda ? 1 + (int)pp.wide.size() : n_slots, write_lambda ? 0 : sweep_idx, tcap);
+    return hipGetLastError();
+}
+
+hipError_t launch_pauli_wide(const WideGroup &w, const PauliPlan &pp, const double2 *psi, double2 *lam,
+                             int64_t batch, int ham_div, int wg_per_inst, double *partials, int n_slots, int slot,
+                             hipStream_t s)
+{
+    if (lam)
+        hipLaunchKernelGGL(k_pauli_wide<true>, dim3(wg_per_inst, (unsigned)batch), dim3(kThreads), 0, s, pp.n, w.f,
+                           w.pivot, w.ugroup, reinterpret_cast<const int32_t *>(pp.toff.p), pp.n_ugroups,
+                           reinterpret_cast<const TermDev *>(pp.terms.p), ham_div, psi, lam, partials, n_slots, slot);
+    else
+        hipLaunchKernelGGL(k_pauli_wide<false>, dim3(wg_per_inst, (unsigned)batch), dim3(kThreads), 0, s, pp.n, w.f,
+                           w.pivot, w.ugroup, reinterpret_cast<const int32_t *>(pp.toff.p), pp.n_ugroups,
+                           reinterpret_cast<const TermDev *>(pp.terms.p), ham_div, psi, lam, partials, n_slots, slot);
     return hipGetLastError();
 }
 
@@ -2402,7 +2503,7 @@ hipError_t launch_hpsi_gather(const SweepPlan &sp, const PauliPlan &pp, int swee
                        reinterpret_cast<const GroupDev *>(pp.groups.p) + sp.grp_begin, sp.grp_count,
                        reinterpret_cast<const int32_t *>(pp.toff.p), pp.n_ugroups,
                        reinterpret_cast<const TermDev *>(pp.terms.p), ham_div, psi, lam, tiles, (int)first,
-                       (int)last, partials, 1, tcap);
+                       (int)last, partials, 1 + (int)pp.wide.size(), tcap);
     return hipGetLastError();
 }
 
@@ -2438,6 +2539,29 @@ hipError_t launch_gd(int64_t count, double *theta, const double *g, double lr, h
 {
     if (count == 0) return hipSuccess;
     hipLaunchKernelGGL(k_gd, dim3(grid_for(count, 256)), dim3(256), 0, s, count, theta, g, lr);
+    return hipGetLastError();
+}
+
+hipError_t launch_opt_step(int opt, int64_t batch, int32_t n_params, double *theta, double *m, double *v,
+                           const double *g, const double *e, double *energies, int64_t e_stride,
+                           const int64_t *step, double lr, double b1, double b2, double eps, hipStream_t s)
+{
+    const int64_t count = batch * n_params;
+    const int64_t total = std::max(count, batch);
+    hipLaunchKernelGGL(k_opt_step, dim3(grid_for(total, 256)), dim3(256), 0, s, opt, batch, count, theta, m, v, g,
+                       e, energies, e_stride, step, lr, b1, b2, eps);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_set(int64_t *step, int64_t value, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_step_set, dim3(1), dim3(64), 0, s, step, value, (int64_t)0);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_advance(int64_t *step, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_step_set, dim3(1), dim3(64), 0, s, step, (int64_t)0, (int64_t)1);
     return hipGetLastError();
 }
 

@@ -720,7 +720,9 @@ PauliPlan *get_pauli_plan(Context *ctx, int n_hams, Ham *const *hams, int n_inst
     auto it = ctx->pauli_cache.find(key.str());
     if (it != ctx->pauli_cache.end()) {
         *rc = ready_wait(ctx, it->second->ready);
-        return *rc ? nullptr : it->second.get();
+        if (*rc) return nullptr;
+        if (ctx->capture_plans) ctx->capture_plans->push_back(it->second.get());
+        return it->second.get();
     }
     // bound the cache: plans are small, but a serving loop creates many
     if (ctx->pauli_cache.size() >= 256) {  // stream-ordered: no device synchronisation
@@ -743,18 +745,28 @@ PauliPlan *get_pauli_plan(Context *ctx, int n_hams, Ham *const *hams, int n_inst
     for (size_t g = 0; g < flips.size(); ++g) ug[flips[g]] = (int)g;
     plan->n_ugroups = (int)flips.size();
 
-    // greedy sweep cover
+    // greedy sweep cover.  A group with more flip bits outside the low c bits
+    // than a tile has free bits cannot pair inside any tile: it is a wide
+    // group, evaluated by a whole-state pair sweep of its own (after the tile
+    // sweeps), and the cover skips it (sweep_of = -2).
     const uint64_t low = ((1ull << ceff) - 1);
     std::vector<int> sweep_of(flips.size(), -1);
     std::vector<std::vector<int>> sweep_tiles;
     std::vector<std::vector<int>> sweep_groups;
+    std::vector<int> wide_groups;
     size_t assigned = 0;
+    for (size_t g = 0; g < flips.size(); ++g)
+        if (popc(flips[g] & ~low) > keff - ceff) {
+            sweep_of[g] = -2;
+            wide_groups.push_back((int)g);
+            ++assigned;
+        }
     while (assigned < flips.size()) {
         uint64_t S = low;
         for (;;) {
             int best = -1, best_new = 1 << 30;
             for (size_t g = 0; g < flips.size(); ++g) {
-                if (sweep_of[g] >= 0) continue;
+                if (sweep_of[g] != -1) continue;
                 uint64_t f = flips[g];
                 int nw = popc(f & ~S);
                 if (nw == 0) continue;
@@ -772,21 +784,21 @@ PauliPlan *get_pauli_plan(Context *ctx, int n_hams, Ham *const *hams, int n_inst
         sweep_tiles.push_back(tile);
         sweep_groups.emplace_back();
         for (size_t g = 0; g < flips.size(); ++g) {
-            if (sweep_of[g] >= 0) continue;
+            if (sweep_of[g] != -1) continue;
             if ((flips[g] & ~tmask) == 0) {
                 sweep_of[g] = s;
                 sweep_groups[s].push_back((int)g);
                 ++assigned;
             }
         }
-        if (sweep_groups[s].empty()) {  // a group wider than a tile: impossible for k >= 4
+        if (sweep_groups[s].empty()) {  // cannot happen: every group left fits the low bits plus k - c more
             *rc = VQE_EUNSUPPORTED;
             return nullptr;
         }
     }
 
     // renumber the union groups in sweep order, so that every sweep's terms
-    // form one contiguous range per instance
+    // form one contiguous range per instance; the wide groups come last
     {
         std::vector<uint64_t> nf;
         std::vector<int> nsweep;
@@ -796,6 +808,15 @@ PauliPlan *get_pauli_plan(Context *ctx, int n_hams, Ham *const *hams, int n_inst
                 nsweep.push_back((int)s);
                 g = (int)nf.size() - 1;
             }
+        for (int g : wide_groups) {
+            WideGroup w;
+            w.f = flips[g];
+            w.pivot = __builtin_ctzll(flips[g]);
+            w.ugroup = (int32_t)nf.size();
+            plan->wide.push_back(w);
+            nf.push_back(flips[g]);
+            nsweep.push_back(-2);
+        }
         flips.swap(nf);
         sweep_of.assign(nsweep.begin(), nsweep.end());
     }
@@ -834,7 +855,8 @@ PauliPlan *get_pauli_plan(Context *ctx, int n_hams, Ham *const *hams, int n_inst
         for (size_t t = 0; t < H->x.size(); ++t) by_f[H->x[t]].push_back(t);
         for (size_t g = 0; g < flips.size(); ++g) {
             int32_t *o = &toff[((size_t)i * flips.size() + g) * 3];
-            const std::vector<int> &tile = sweep_tiles[sweep_of[g]];
+            static const std::vector<int> no_tile;  // wide groups: signs from the full z mask only
+            const std::vector<int> &tile = sweep_of[g] >= 0 ? sweep_tiles[sweep_of[g]] : no_tile;
             o[0] = (int32_t)terms.size();
             auto itf = by_f.find(flips[g]);
             int cnt = 0;
@@ -886,6 +908,7 @@ PauliPlan *get_pauli_plan(Context *ctx, int n_hams, Ham *const *hams, int n_inst
     plan->host_terms = std::move(terms);
     ready_mark(ctx, plan->ready);
     PauliPlan *out = plan.get();
+    if (ctx->capture_plans) ctx->capture_plans->push_back(out);
     ctx->pauli_cache[key.str()] = std::move(plan);
     *rc = VQE_OK;
     return out;

@@ -93,6 +93,18 @@ class Context:
     def reserve(self, nbytes: int):
         self.check(lib().vqe_ctx_reserve(self._h, int(nbytes)))
 
+    def set_graphs(self, on: bool = True):
+        """Capture repeated launch sequences into hipGraphs and replay them (default on)."""
+        self.check(lib().vqe_ctx_set_graphs(self._h, 1 if on else 0))
+
+    def graph_stats(self) -> dict:
+        c, l, k = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        self.check(lib().vqe_ctx_graph_stats(self._h, ctypes.byref(c), ctypes.byref(l), ctypes.byref(k)))
+        return {"captures": c.value, "launches": l.value, "cached": k.value}
+
+    def clear_tuning(self):
+        self.check(lib().vqe_ctx_clear_tuning(self._h))
+
     def dedicated_stream(self, index: int):
         """Stream `index` of this device's dedicated streams: a HIP stream on a
         hardware queue of its own (vqe_stream_create), as a
@@ -385,6 +397,31 @@ def energy_grad(ctx: Context, circ: Circuit, hams, theta: torch.Tensor, ref_inde
     return out_e, out_g
 
 
+def autotune(ctx: Context, circ: Circuit, hams, theta: torch.Tensor, want_grad: bool = True,
+             ref_index: int = None) -> dict:
+    """vqe_autotune: time candidate tiles, batch tile and workgroup cap for this
+    (circuit, batch) on energy (+ gradient) calls and keep the fastest.  Size
+    workspaces after tuning (the choice changes vqe_workspace_bytes)."""
+    B = theta.shape[0]
+    _check_tensor(theta, torch.float64, (B, circ.n_params), "theta")
+    arr, nh = _hams_array(hams)
+    ref = circ.ref_index if ref_index is None else ref_index
+    r = capi.TuneResult()
+    ctx.check(lib().vqe_autotune(ctx.handle, circ.handle, nh, arr, B, ref, 1 if want_grad else 0, _ptr(theta),
+                                 _stream(theta.device), ctypes.byref(r)))
+    return {"k_fwd": r.k_fwd, "k_rev": r.k_rev, "c_low": r.c_low, "wg_max": r.wg_max,
+            "batch_tile": int(r.batch_tile), "ms_default": r.ms_default, "ms_tuned": r.ms_tuned,
+            "candidates": r.candidates}
+
+
+def tune_set(ctx: Context, circ: Circuit, batch: int, want_grad: bool, k_fwd: int = 12, k_rev: int = 11,
+             c_low: int = 3, wg_max: int = 1024, batch_tile: int = None):
+    """vqe_tune_set: pin an execution configuration for (circuit, batch, mode)."""
+    r = capi.TuneResult(k_fwd=k_fwd, k_rev=k_rev, c_low=c_low, wg_max=wg_max,
+                        batch_tile=int(batch if batch_tile is None else batch_tile))
+    ctx.check(lib().vqe_tune_set(ctx.handle, circ.handle, int(batch), 1 if want_grad else 0, ctypes.byref(r)))
+
+
 def grad_shift(ctx: Context, circ: Circuit, hams, theta: torch.Tensor, ref_index: int = None,
                ws: torch.Tensor = None):
     """(E, dE/dtheta) by the parameter-shift rules (Algorithm 1), all shifted rows in one batch."""
@@ -482,6 +519,7 @@ _OP = np.dtype([("m", "<u4"), ("fixed_bits", "<u4"), ("cmask_out", "<u8"), ("cva
 _SWEEP = np.dtype([("geom", _GEOM), ("grp_begin", "<i4"), ("grp_count", "<i4"), ("pad", "<i4", 2)])
 _GROUP = np.dtype([("floc", "<u4"), ("pivot", "<u4"), ("ugroup", "<i4"), ("pad", "<i4")])
 _TERM = np.dtype([("z", "<u8"), ("zloc", "<u4"), ("pad", "<u4"), ("w", "<f8")])
+_WIDE = np.dtype([("f", "<u8"), ("pivot", "<i4"), ("ugroup", "<i4")])
 
 
 def circuit_plan(ctx: Context, circ: Circuit, reverse: bool = False, stages: bool = False):
@@ -548,4 +586,10 @@ def hamiltonian_plan(ctx: Context, hams, batch: int = 1, for_gradient: bool = Fa
     toff = buf[off:off + ni * nu * 3 * 4].view("<i4").reshape(ni, nu, 3)
     off += ni * nu * 3 * 4
     terms = buf[off:off + nt * _TERM.itemsize].view(_TERM)
-    return {"sweeps": sweeps, "groups": groups, "toff": toff, "terms": terms, "n_union": nu, "n_inst": ni}
+    off += nt * _TERM.itemsize
+    nw, wsz = (int(v) for v in buf[off:off + 8].view("<i4"))
+    assert wsz == _WIDE.itemsize
+    off += 8
+    wide = buf[off:off + nw * _WIDE.itemsize].view(_WIDE)
+    return {"sweeps": sweeps, "groups": groups, "toff": toff, "terms": terms, "wide": wide, "n_union": nu,
+            "n_inst": ni}

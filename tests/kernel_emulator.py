@@ -217,6 +217,32 @@ def sweeps(plan, psi, inst=0, hpsi=False):
                     E += float(np.sum(2.0 * (w.real * A - w.imag * Bv)))
         if hpsi:
             lam[idx] += TL
+    # wide groups: whole-state pairs (b, b ^ f), bit `pivot` of b clear
+    dim = psi.size
+    for wg in plan.get("wide", ()):
+        tb, tm, te = (int(v) for v in toff[int(wg["ugroup"])])
+        if te == tb:
+            continue
+        f, pv = np.uint64(int(wg["f"])), np.uint64(int(wg["pivot"]))
+        jj = np.arange(dim // 2, dtype=np.uint64)
+        b = ((jj >> pv) << (pv + np.uint64(1))) | (jj & ((np.uint64(1) << pv) - np.uint64(1)))
+        A = np.zeros(b.size)
+        Bv = np.zeros(b.size)
+        for t in range(tb, te):
+            d = terms[t]
+            val = np.where(_parity(np.uint64(int(d["z"])) & b) == 1, -d["w"], d["w"])
+            if t < tm:
+                A += val
+            else:
+                Bv += val
+        bi, bf = b.astype(np.int64), (b ^ f).astype(np.int64)
+        x0, x1 = psi[bi], psi[bf]
+        if hpsi:
+            lam[bf] += (A + 1j * Bv) * x0
+            lam[bi] += (A - 1j * Bv) * x1
+        else:
+            w = x1.conj() * x0
+            E += float(np.sum(2.0 * (w.real * A - w.imag * Bv)))
     if hpsi:
         return lam, float(np.vdot(psi, lam).real)
     return E

@@ -462,3 +462,65 @@ def test_persistent_loop_register_rows(vqe, ctx, n_groups):
         want, tho = oracle.vqe_run(spec, ham, th0[b], iters)
         np.testing.assert_allclose(traj[b], want, atol=E_TOL)
         np.testing.assert_allclose(tho_gpu[b], tho, atol=1e-7)
+
+
+@pytest.mark.parametrize("n,tiles,seed", [(14, (12, 11, 3), 81), (15, (9, 9, 3), 82), (16, (12, 11, 3), 83)])
+def test_any_weight_pauli_strings(vqe, ctx, n, tiles, seed):
+    """Strings of weight up to n (flip groups too wide for any tile run as
+    whole-state pair sweeps): energy, adjoint and parameter-shift gradients,
+    H psi and per-instance Hamiltonians against the oracle."""
+    _say("wide groups", n, tiles, seed)
+    ctx.set_tile(*tiles)
+    k, c = tiles[1], tiles[2]
+    spec = synth.hea_circuit(n, 1)
+    hams = [synth.random_pauli_sum(n, 30, seed=seed + b, max_weight=n) for b in range(2)]
+    low = (1 << c) - 1
+    assert any(bin(int(x) & ~low).count("1") > k - c for x in hams[0].xmask)
+    th = synth.uniform_thetas(spec.n_params, 2, seed=seed)
+    C = vqe.Circuit.from_spec(ctx, spec)
+    H = [vqe.Hamiltonian.from_sum(ctx, h) for h in hams]
+    e, g = vqe.energy_grad(ctx, C, H, dev(th))
+    e0 = vqe.energy(ctx, C, H, dev(th))
+    es, gs = vqe.grad_shift(ctx, C, H[0], dev(th[:1]))
+    psi = dev(np.stack([oracle.state(spec, th[b]) for b in range(2)]), torch.complex128)
+    lam = vqe.apply_hamiltonian(ctx, H, psi)
+    torch.cuda.synchronize()
+    for b in range(2):
+        eo, go = oracle.energy_grad(spec, hams[b], th[b], "adjoint")
+        assert abs(e[b].item() - eo) < E_TOL
+        assert abs(e0[b].item() - eo) < E_TOL
+        np.testing.assert_allclose(g[b].cpu().numpy(), go, atol=G_TOL)
+        np.testing.assert_allclose(lam[b].cpu().numpy(), oracle.apply_hamiltonian(psi[b].cpu().numpy(), hams[b]),
+                                   atol=S_TOL)
+        if b == 0:
+            assert abs(es[0].item() - eo) < E_TOL
+            np.testing.assert_allclose(gs[0].cpu().numpy(), go, atol=G_TOL)
+
+
+def test_only_wide_groups(vqe, ctx):
+    """A Hamiltonian whose every flip group is too wide for a tile (no tile
+    sweep at all): lambda and the energy slot start from zero."""
+    n = 14
+    _say("only wide groups", n)
+    ctx.set_tile(12, 11, 3)
+    low = 7
+    rng = np.random.Generator(np.random.PCG64(5))
+    xs, zs = [], []
+    while len(xs) < 6:
+        x = int(rng.integers(0, 1 << n))
+        if bin(x & ~low).count("1") > 11 - 3 and x not in xs:
+            xs.append(x)
+            zs.append(int(rng.integers(0, 1 << n)))
+    ham = synth.PauliSum(n, np.array(xs, dtype=np.uint64), np.array(zs, dtype=np.uint64), rng.normal(size=6))
+    spec = synth.hea_circuit(n, 1)
+    th = synth.uniform_thetas(spec.n_params, 1, seed=6)
+    C = vqe.Circuit.from_spec(ctx, spec)
+    H = vqe.Hamiltonian.from_sum(ctx, ham)
+    assert len(vqe.hamiltonian_plan(ctx, H, 1, True)["sweeps"]) == 0
+    e, g = vqe.energy_grad(ctx, C, H, dev(th))
+    e0 = vqe.energy(ctx, C, H, dev(th))
+    torch.cuda.synchronize()
+    eo, go = oracle.energy_grad(spec, ham, th[0], "adjoint")
+    assert abs(e.item() - eo) < E_TOL
+    assert abs(e0.item() - eo) < E_TOL
+    np.testing.assert_allclose(g.cpu().numpy()[0], go, atol=G_TOL)

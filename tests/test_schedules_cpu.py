@@ -266,3 +266,31 @@ def test_fused_adjoint_tile_limit(ctx):
     assert int(fwd["fstage_count"].sum()) > 0
     assert int(rev["fstage_count"].sum()) == 0
     assert (rev["stage_count"] > 0).any()
+
+
+@pytest.mark.parametrize("n,k,c,seed", [(12, 8, 3, 71), (13, 9, 2, 72), (10, 6, 2, 73)])
+def test_wide_flip_groups(ctx, n, k, c, seed):
+    """Strings of any weight: groups with more than k - c flip bits outside
+    the low c bits pair over the whole state (wide groups); the schedule's
+    energy and H psi still equal the oracle's."""
+    ctx.set_tile(k, k, c)
+    ham = synth.random_pauli_sum(n, 40, seed=seed, max_weight=n)
+    H = vqe.Hamiltonian.from_sum(ctx, ham)
+    psi = synth.random_state(n, seed=seed)
+    low = (1 << c) - 1
+    n_wide = len({int(x) for x in ham.xmask if bin(int(x) & ~low).count("1") > k - c})
+    assert n_wide > 0
+    for for_grad in (False, True):
+        plan = vqe.hamiltonian_plan(ctx, H, 1, for_grad)
+        assert len(plan["wide"]) == n_wide
+        assert all(bin(int(w["f"]) & ~low).count("1") > k - c for w in plan["wide"])
+        assert abs(emu.sweeps(plan, psi) - oracle.expect(psi, ham).real) < 1e-12
+        lam, e2 = emu.sweeps(plan, psi, hpsi=True)
+        np.testing.assert_allclose(lam, oracle.apply_hamiltonian(psi, ham), atol=1e-12)
+    # only wide groups: no tile sweep at all
+    wide_idx = [i for i, x in enumerate(ham.xmask) if bin(int(x) & ~low).count("1") > k - c]
+    only = synth.PauliSum(n, ham.xmask[wide_idx], ham.zmask[wide_idx], ham.coeff[wide_idx])
+    plan = vqe.hamiltonian_plan(ctx, vqe.Hamiltonian.from_sum(ctx, only), 1, True)
+    assert len(plan["sweeps"]) == 0 and len(plan["wide"]) == n_wide
+    lam, _ = emu.sweeps(plan, psi, hpsi=True)
+    np.testing.assert_allclose(lam, oracle.apply_hamiltonian(psi, only), atol=1e-12)
