@@ -371,6 +371,13 @@ def hea_measure(ctx, vqe, synth, torch, n):
         kernels[name] = {"launches_per_eval": r["launches"] // reps, "avg_us": round(r["ms"] / r["launches"] * 1e3, 2),
                          "bytes_per_launch": int(r["bytes"] / r["launches"]), "GBps": round(gbps, 1),
                          "frac_of_hbm": round(gbps / HBM_PEAK_GBPS, 4)}
+        # HBM bytes per launch from the committed counter runs (26 qubits, the
+        # same kernel source), beside the algorithmic bytes
+        base = {"k_pauli_sweep (expectation)": "k_pauli_sweep"}.get(name, name)
+        tb = measured_traffic(base) if n == 26 and base in ("k_forward_fused", "k_reverse_fused", "k_hpsi_gather",
+                                                             "k_pauli_sweep") else None
+        kernels[name]["traffic_bytes_per_launch"] = tb
+        kernels[name]["traffic_over_algorithmic"] = round(tb / (r["bytes"] / r["launches"]), 4) if tb else None
     passes, _ = vqe.circuit_plan(ctx, C)
     pl = vqe.hamiltonian_plan(ctx, H, 1, False)
     del ws
