@@ -549,11 +549,16 @@ CircPlan *get_circ_plan(Circ *C, bool reverse, int k, int c, int *rc)
     std::vector<OpDesc> ops;
     const uint64_t low = ceff >= 64 ? ~0ull : ((1ull << ceff) - 1);
 
-    while (remaining > 0) {
-        uint64_t S = low;
-        uint64_t blocked = 0;
+    // One pass: walk the gates not yet applied in list order and take every
+    // gate whose flip bits the tile can hold, unless a gate it must follow
+    // (one touching a shared bit) was left out.  With fixed = 0 the walk
+    // claims tile bits for gates first come, first served; otherwise the
+    // tile's bits are `fixed` and only gates inside it are taken.
+    auto walk = [&](uint64_t fixed, uint64_t &S, int &nparam) {
         std::vector<int> take;
-        int nparam = 0;
+        S = fixed ? fixed : low;
+        nparam = 0;
+        uint64_t blocked = 0;
         for (int oi = 0; oi < G; ++oi) {
             int g = order[oi];
             if (done[g]) continue;
@@ -564,7 +569,7 @@ CircPlan *get_circ_plan(Circ *C, bool reverse, int k, int c, int *rc)
                 continue;
             }
             uint64_t need = h.m & ~S;
-            bool room = popc(S) + popc(need) <= keff;
+            bool room = fixed ? need == 0 : popc(S) + popc(need) <= keff;
             bool param_room = (h.pidx < 0 || nparam < kMaxParamOpsPerPass) && (int)take.size() < kMaxOpsPerPass;
             if (room && param_room) {
                 S |= need;
@@ -572,6 +577,31 @@ CircPlan *get_circ_plan(Circ *C, bool reverse, int k, int c, int *rc)
                 if (h.pidx >= 0) ++nparam;
             } else {
                 blocked |= touched;
+            }
+        }
+        return take;
+    };
+    // Tile choice: the first-come walk fills the tile with the first free bits
+    // it meets, which for circuits whose dependencies advance like a wavefront
+    // (a CNOT ladder repeated over layers) leaves the front behind after the
+    // first pass.  Every window of k - c consecutive index bits above the low
+    // bits is scored too, by the gates a walk restricted to it takes; the
+    // window that takes the most gates is used (ties keep the first-come
+    // tile), so a pass never takes fewer gates than before.
+    const int free_bits = keff - ceff;
+    while (remaining > 0) {
+        uint64_t S = low;
+        int nparam = 0;
+        std::vector<int> take = walk(0, S, nparam);
+        for (int b = ceff; free_bits > 0 && b + free_bits <= n; ++b) {
+            const uint64_t win = low | (((1ull << free_bits) - 1) << b);
+            uint64_t Sw;
+            int npw;
+            std::vector<int> tw = walk(win, Sw, npw);
+            if (tw.size() > take.size()) {
+                take.swap(tw);
+                S = Sw;
+                nparam = npw;
             }
         }
         if (take.empty()) {  // cannot happen: a gate touches at most 4 bits
