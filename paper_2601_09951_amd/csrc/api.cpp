@@ -710,7 +710,8 @@ int run_forward_passes(Context *ctx, Circ *C, CircPlan *fp, int64_t B, double2 *
             rc = hip_check(ctx, launch_forward_fused(pp, gd, reinterpret_cast<const FusedStage *>(fp->fstages.p),
                                                      reinterpret_cast<const FusedCond *>(fp->fconds.p), fused,
                                                      fp->n_fslots(), reinterpret_cast<const FusedPhase *>(fp->fphases.p),
-                                                     mats, G, psi, B, ctx->wg_max, s),
+                                                     mats, G, psi, B, ctx->wg_max,
+                                                     reinterpret_cast<const uint32_t *>(fp->fsub.p), fp->fsub_n, s),
                            "forward pass (fused)");
         else if (staged_pass)
             rc = hip_check(ctx, launch_forward_staged(pp, pp.stage_bits, gd, reinterpret_cast<const StageDesc *>(fp->stages.p),
@@ -890,7 +891,8 @@ int energy_grad_into(Context *ctx, Circ *C, int n_hams, Ham *const *H, int64_t B
                                                      rp->host_fstages[p.fstage_begin].slot, rp->n_fslots(),
                                                      n_entries, p.fq_count, wadj, coef,
                                                      reinterpret_cast<const FusedPhase *>(rp->fphases.p), mats, G,
-                                                     psi, lam, B, L.W_rev, pg, C->n_pgates, s),
+                                                     psi, lam, B, L.W_rev, pg, C->n_pgates,
+                                                     reinterpret_cast<const uint32_t *>(rp->fsub.p), rp->fsub_n, s),
                            "reverse pass (fused)");
         else if (staged_pass)
             rc = hip_check(ctx, launch_reverse_staged(p, p.stage_bits, gd, reinterpret_cast<const StageDesc *>(rp->stages.p),

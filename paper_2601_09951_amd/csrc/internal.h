@@ -274,6 +274,10 @@ struct CircPlan {
     std::vector<int32_t> host_fslot_off{0}, host_fslot_gate;
     std::vector<int32_t> host_fslot_info;  // per slot entry: (pgate + 1) << 4 | class << 2 | generator
     int n_fslots() const { return (int)host_fslot_off.size() - 1; }
+    // per fused stage and sub-cube: swizzled sub-cube base | swizzled store-map image << 16
+    DevMem fsub;
+    std::vector<uint32_t> host_fsub;
+    int fsub_n = 0;          // sub-cubes per stage
     Ready ready;             // where the device tables were uploaded
 };
 
@@ -526,11 +530,11 @@ hipError_t launch_reverse_fused(const PassPlan &pp, const TileGeom *geom_dev, co
                                 int slot0, int n_slots, int n_entries, int n_qslots, const double2 *wadj,
                                 const double *coef, const FusedPhase *fphases, const double2 *mats, int n_gates,
                                 double2 *psi, double2 *lam, int64_t batch, int wg_per_inst, double *partials,
-                                int n_pgates, hipStream_t s);
+                                int n_pgates, const uint32_t *fsub, int fsub_n, hipStream_t s);
 hipError_t launch_forward_fused(const PassPlan &pp, const TileGeom *geom_dev, const FusedStage *fstages,
                                 const FusedCond *fconds, const double2 *fused, int n_slots,
                                 const FusedPhase *fphases, const double2 *mats, int n_gates, double2 *psi,
-                                int64_t batch, int wg_max, hipStream_t s);
+                                int64_t batch, int wg_max, const uint32_t *fsub, int fsub_n, hipStream_t s);
 hipError_t launch_forward_staged(const PassPlan &pp, int stage_bits, const TileGeom *geom_dev,
                                  const StageDesc *stages, const StageOp *sops, const double2 *mats,
                                  int n_gates, double2 *psi, int64_t batch, int wg_max, hipStream_t s);

@@ -1166,46 +1166,44 @@ __device__ __forceinline__ void apply_phases(double2 (&x)[N], const PhaseL *phl,
 }
 
 // one fused stage for this thread's sub-cube u (na active register bits;
-// PERM: the CNOT / X network moves the amplitudes on the way back to LDS)
+// PERM: the CNOT / X network moves the amplitudes on the way back to LDS).
+// sub = the plan's entry for (stage, u): swz(bl) | swz(lbl) << 16 (see
+// build_fsub); the swizzle is linear over xor, so every address is one of
+// them xor a wave-uniform term.
 template <int NA, bool PERM, bool PH>
 __device__ __forceinline__ void fused_stage(double2 *tile, const FusedStage &fs, const Mat2 *fm, int nsub,
-                                            uint32_t ctile, const PhaseL *phl, int nph)
+                                            uint32_t ctile, const PhaseL *phl, int nph, uint32_t sub)
 {
     const bool have = (int)threadIdx.x < nsub;
-    const int u = have ? (int)threadIdx.x : 0;
-    const uint32_t bl = subcube_base_of<4>((uint32_t)u, fs);
-    uint32_t lbl = 0;
-    if (PERM) {
+    const uint32_t sbl = sub & 0xFFFFu, slbl = sub >> 16;
+    uint32_t roff[16], sro[16];
 #pragma unroll
-        for (int j = 0; j < 12; ++j)
-            if ((u >> j) & 1) lbl ^= fs.lc[j];
-    }
-    uint32_t roff[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i)
+    for (int i = 0; i < 16; ++i) {
         roff[i] = ((i & 1) ? 1u << fs.rpos[0] : 0u) | ((i & 2) ? 1u << fs.rpos[1] : 0u) |
                   ((i & 4) ? 1u << fs.rpos[2] : 0u) | ((i & 8) ? 1u << fs.rpos[3] : 0u);
+        sro[i] = swz(roff[i]);  // uniform
+    }
     double2 x[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) x[i] = make_double2(0.0, 0.0);
     if (have) {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) x[i] = tile[swz(bl | roff[i])];
+        for (int i = 0; i < 16; ++i) x[i] = tile[sbl ^ sro[i]];
         if (NA > 0) fused_bit<0>(x, fm[0]);
         if (NA > 1) fused_bit<1>(x, fm[1]);
         if (NA > 2) fused_bit<2>(x, fm[2]);
         if (NA > 3) fused_bit<3>(x, fm[3]);
-        if (PH) apply_phases<16>(x, phl, nph, bl, roff);
+        if (PH) apply_phases<16>(x, phl, nph, swz(sbl), roff);  // swz is its own inverse
     }
     if (PERM) {
         lds_barrier();  // every sub-cube is read before any amplitude moves
         if (have) {
 #pragma unroll
-            for (int i = 0; i < 16; ++i) tile[swz(lbl ^ fs.lr[i] ^ ctile)] = x[i];
+            for (int i = 0; i < 16; ++i) tile[slbl ^ swz(fs.lr[i] ^ ctile)] = x[i];
         }
     } else if (have) {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) tile[swz(bl | roff[i])] = x[i];
+        for (int i = 0; i < 16; ++i) tile[sbl ^ sro[i]] = x[i];
     }
 }
 
@@ -1216,7 +1214,8 @@ __global__ __launch_bounds__(kThreads) void k_forward_fused(const TileGeom *__re
                                                             const double2 *__restrict__ fused, int n_slots,
                                                             const FusedPhase *__restrict__ fphases, int ph0,
                                                             int nph, const double2 *__restrict__ mats,
-                                                            int n_gates, double2 *__restrict__ psi, int64_t tiles)
+                                                            int n_gates, double2 *__restrict__ psi, int64_t tiles,
+                                                            const uint32_t *__restrict__ fsub)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     double2 *tile = reinterpret_cast<double2 *>(smem);
@@ -1250,7 +1249,11 @@ __global__ __launch_bounds__(kThreads) void k_forward_fused(const TileGeom *__re
         const uint64_t base = tile_base(gp, nout, t);
         tile_in<16, true>(tile, st, base, hoff, T, c);
         lds_barrier();
+        const uint32_t *fsu = fsub + (tid < nsub ? tid : 0);
+        uint32_t sub_next = fsu[0];
         for (int s = 0; s < nstages; ++s) {
+            const uint32_t sub = sub_next;
+            if (s + 1 < nstages) sub_next = fsu[(size_t)(s + 1) * nsub];  // in flight during this stage
             const FusedStage fs = fstages[s];  // uniform: scalar loads
             const int na = (int)__builtin_amdgcn_readfirstlane((uint32_t)fs.na);
             const int perm = (int)__builtin_amdgcn_readfirstlane((uint32_t)fs.perm);
@@ -1263,16 +1266,16 @@ __global__ __launch_bounds__(kThreads) void k_forward_fused(const TileGeom *__re
             const PhaseL *sp = phl + (fs.phase_begin - ph0);
             const int np = fs.phase_count;
             switch (na * 2 + perm) {
-            case 0: fused_stage<0, false, PH>(tile, fs, m4, nsub, ctile, sp, np); break;
-            case 1: fused_stage<0, true, PH>(tile, fs, m4, nsub, ctile, sp, np); break;
-            case 2: fused_stage<1, false, PH>(tile, fs, m4, nsub, ctile, sp, np); break;
-            case 3: fused_stage<1, true, PH>(tile, fs, m4, nsub, ctile, sp, np); break;
-            case 4: fused_stage<2, false, PH>(tile, fs, m4, nsub, ctile, sp, np); break;
-            case 5: fused_stage<2, true, PH>(tile, fs, m4, nsub, ctile, sp, np); break;
-            case 6: fused_stage<3, false, PH>(tile, fs, m4, nsub, ctile, sp, np); break;
-            case 7: fused_stage<3, true, PH>(tile, fs, m4, nsub, ctile, sp, np); break;
-            case 8: fused_stage<4, false, PH>(tile, fs, m4, nsub, ctile, sp, np); break;
-            default: fused_stage<4, true, PH>(tile, fs, m4, nsub, ctile, sp, np); break;
+            case 0: fused_stage<0, false, PH>(tile, fs, m4, nsub, ctile, sp, np, sub); break;
+            case 1: fused_stage<0, true, PH>(tile, fs, m4, nsub, ctile, sp, np, sub); break;
+            case 2: fused_stage<1, false, PH>(tile, fs, m4, nsub, ctile, sp, np, sub); break;
+            case 3: fused_stage<1, true, PH>(tile, fs, m4, nsub, ctile, sp, np, sub); break;
+            case 4: fused_stage<2, false, PH>(tile, fs, m4, nsub, ctile, sp, np, sub); break;
+            case 5: fused_stage<2, true, PH>(tile, fs, m4, nsub, ctile, sp, np, sub); break;
+            case 6: fused_stage<3, false, PH>(tile, fs, m4, nsub, ctile, sp, np, sub); break;
+            case 7: fused_stage<3, true, PH>(tile, fs, m4, nsub, ctile, sp, np, sub); break;
+            case 8: fused_stage<4, false, PH>(tile, fs, m4, nsub, ctile, sp, np, sub); break;
+            default: fused_stage<4, true, PH>(tile, fs, m4, nsub, ctile, sp, np, sub); break;
             }
             lds_barrier();
         }
@@ -1406,22 +1409,19 @@ __device__ __forceinline__ void rbit_step(double2 (&x)[8], double2 (&l)[8], cons
 template <int NA, bool PERM, bool PH>
 __device__ __forceinline__ void rev_fused_stage(double2 *tp, double2 *tl, const FusedStage &fs, const Mat2 *wm,
                                                 const int32_t *qidx, int nsub, uint32_t ctile, double *red,
-                                                const PhaseL *phl, int nph, double *phred)
+                                                const PhaseL *phl, int nph, double *phred, uint32_t sub)
 {
     const bool have = (int)threadIdx.x < nsub;
-    const int u = have ? (int)threadIdx.x : 0;
-    const uint32_t bl = subcube_base_of<3>((uint32_t)u, fs);
-    uint32_t lbl = 0;
-    if (PERM) {
+    // sub = swz(bl) | swz(lbl) << 16 (build_fsub); addresses are these xor a uniform term
+    const uint32_t sbl = sub & 0xFFFFu, slbl = sub >> 16;
+    const uint32_t bl = PH ? swz(sbl) : 0u;  // swz is its own inverse
+    uint32_t roff[8], sro[8];
 #pragma unroll
-        for (int j = 0; j < 12; ++j)
-            if ((u >> j) & 1) lbl ^= fs.lc[j];
-    }
-    uint32_t roff[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i)
+    for (int i = 0; i < 8; ++i) {
         roff[i] = ((i & 1) ? 1u << fs.rpos[0] : 0u) | ((i & 2) ? 1u << fs.rpos[1] : 0u) |
                   ((i & 4) ? 1u << fs.rpos[2] : 0u);
+        sro[i] = swz(roff[i]);  // uniform
+    }
     double2 x[8], l[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -1431,8 +1431,8 @@ __device__ __forceinline__ void rev_fused_stage(double2 *tp, double2 *tl, const 
     if (have) {
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-            x[i] = tp[swz(bl | roff[i])];
-            l[i] = tl[swz(bl | roff[i])];
+            x[i] = tp[sbl ^ sro[i]];
+            l[i] = tl[sbl ^ sro[i]];
         }
     }
     // every thread takes part in the sums (a thread with no sub-cube adds zeros)
@@ -1472,7 +1472,7 @@ __device__ __forceinline__ void rev_fused_stage(double2 *tp, double2 *tl, const 
         if (have) {
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-                const uint32_t d = swz(lbl ^ fs.lr[i] ^ ctile);
+                const uint32_t d = slbl ^ swz(fs.lr[i] ^ ctile);
                 tp[d] = x[i];
                 tl[d] = l[i];
             }
@@ -1480,8 +1480,8 @@ __device__ __forceinline__ void rev_fused_stage(double2 *tp, double2 *tl, const 
     } else if (have) {
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-            tp[swz(bl | roff[i])] = x[i];
-            tl[swz(bl | roff[i])] = l[i];
+            tp[sbl ^ sro[i]] = x[i];
+            tl[sbl ^ sro[i]] = l[i];
         }
     }
 }
@@ -1497,7 +1497,7 @@ __global__ __launch_bounds__(kThreads) void k_reverse_fused(
     const int32_t *__restrict__ slot_info, int slot0, int n_slots, int n_entries, const double2 *__restrict__ wadj,
     const double *__restrict__ coef, const FusedPhase *__restrict__ fphases, int ph0, int nph,
     const double2 *__restrict__ mats, int n_gates, double2 *__restrict__ psi, double2 *__restrict__ lam,
-    int64_t tiles, double *__restrict__ partials, int n_pgates)
+    int64_t tiles, double *__restrict__ partials, int n_pgates, const uint32_t *__restrict__ fsub)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     double2 *tp = reinterpret_cast<double2 *>(smem);
@@ -1552,7 +1552,11 @@ __global__ __launch_bounds__(kThreads) void k_reverse_fused(
         const uint64_t base = tile_base(gp, nout, t);
         tile_in2<8, true>(tp, tl, sp, sl, base, hoff, T, c);
         __syncthreads();
+        const uint32_t *fsu = fsub + (tid < nsub ? tid : 0);
+        uint32_t sub_next = fsu[0];
         for (int s = 0; s < nstages; ++s) {
+            const uint32_t sub = sub_next;
+            if (s + 1 < nstages) sub_next = fsu[(size_t)(s + 1) * nsub];  // in flight during this stage
             const FusedStage fs = fstages[s];  // uniform: scalar loads
             const int na = (int)__builtin_amdgcn_readfirstlane((uint32_t)fs.na);
             const int perm = (int)__builtin_amdgcn_readfirstlane((uint32_t)fs.perm);
@@ -1566,14 +1570,14 @@ __global__ __launch_bounds__(kThreads) void k_reverse_fused(
             const PhaseL *sp = phl + (fs.phase_begin - ph0);
             const int np = fs.phase_count;
             switch (na * 2 + perm) {
-            case 0: rev_fused_stage<0, false, PH>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred); break;
-            case 1: rev_fused_stage<0, true, PH>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred); break;
-            case 2: rev_fused_stage<1, false, PH>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred); break;
-            case 3: rev_fused_stage<1, true, PH>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred); break;
-            case 4: rev_fused_stage<2, false, PH>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred); break;
-            case 5: rev_fused_stage<2, true, PH>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred); break;
-            case 6: rev_fused_stage<3, false, PH>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred); break;
-            default: rev_fused_stage<3, true, PH>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred); break;
+            case 0: rev_fused_stage<0, false, PH>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred, sub); break;
+            case 1: rev_fused_stage<0, true, PH>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred, sub); break;
+            case 2: rev_fused_stage<1, false, PH>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred, sub); break;
+            case 3: rev_fused_stage<1, true, PH>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred, sub); break;
+            case 4: rev_fused_stage<2, false, PH>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred, sub); break;
+            case 5: rev_fused_stage<2, true, PH>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred, sub); break;
+            case 6: rev_fused_stage<3, false, PH>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred, sub); break;
+            default: rev_fused_stage<3, true, PH>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred, sub); break;
             }
             lds_barrier();
         }
@@ -2324,10 +2328,10 @@ hipError_t launch_fuse_mats(const int32_t *slot_off, const int32_t *slot_gate, i
 hipError_t launch_forward_fused(const PassPlan &pp, const TileGeom *geom_dev, const FusedStage *fstages,
                                 const FusedCond *fconds, const double2 *fused, int n_slots,
                                 const FusedPhase *fphases, const double2 *mats, int n_gates, double2 *psi,
-                                int64_t batch, int wg_max, hipStream_t s)
+                                int64_t batch, int wg_max, const uint32_t *fsub, int fsub_n, hipStream_t s)
 {
     const TileGeom &g = pp.geom;
-    if (g.k < 8 || g.k > 12) return hipErrorInvalidValue;
+    if (g.k < 8 || g.k > 12 || !fsub || fsub_n != (1 << (g.k - 4))) return hipErrorInvalidValue;
     const int64_t tiles = 1ll << g.nout;
     const int W = (int)std::min<int64_t>(tiles, wg_max);
     const size_t lds = forward_fused_lds(g.k, g.c, pp.fstage_count, pp.fphase_count);
@@ -2337,7 +2341,8 @@ hipError_t launch_forward_fused(const PassPlan &pp, const TileGeom *geom_dev, co
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(W, (unsigned)batch), dim3(kThreads), lds, s, geom_dev, g.n, g.k, g.c,
                        g.nout, fstages + pp.fstage_begin, pp.fstage_count, fconds, fused, n_slots, fphases,
-                       pp.fphase_begin, pp.fphase_count, mats, n_gates, psi, tiles);
+                       pp.fphase_begin, pp.fphase_count, mats, n_gates, psi, tiles,
+                       fsub + (size_t)pp.fstage_begin * fsub_n);
     return hipGetLastError();
 }
 
@@ -2369,10 +2374,11 @@ hipError_t launch_reverse_fused(const PassPlan &pp, const TileGeom *geom_dev, co
                                 int slot0, int n_slots, int n_entries, int n_qslots, const double2 *wadj,
                                 const double *coef, const FusedPhase *fphases, const double2 *mats, int n_gates,
                                 double2 *psi, double2 *lam, int64_t batch, int wg_per_inst, double *partials,
-                                int n_pgates, hipStream_t s)
+                                int n_pgates, const uint32_t *fsub, int fsub_n, hipStream_t s)
 {
     const TileGeom &g = pp.geom;
     if (g.k < 8 || g.k > 11 || slot0 < 0 || slot0 + 3 * pp.fstage_count > n_slots) return hipErrorInvalidValue;
+    if (!fsub || fsub_n != (1 << (g.k - 3))) return hipErrorInvalidValue;
     const int64_t tiles = 1ll << g.nout;
     const size_t lds = reverse_fused_lds(g.k, g.c, pp.fstage_count, n_qslots, pp.fphase_count);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
@@ -2382,7 +2388,7 @@ hipError_t launch_reverse_fused(const PassPlan &pp, const TileGeom *geom_dev, co
     hipLaunchKernelGGL(kern, dim3(wg_per_inst, (unsigned)batch), dim3(kThreads), lds, s, geom_dev, g.n,
                        g.k, g.c, g.nout, fstages + pp.fstage_begin, pp.fstage_count, fconds, slot_off, slot_info,
                        slot0, n_slots, n_entries, wadj, coef, fphases, pp.fphase_begin, pp.fphase_count, mats,
-                       n_gates, psi, lam, tiles, partials, n_pgates);
+                       n_gates, psi, lam, tiles, partials, n_pgates, fsub + (size_t)pp.fstage_begin * fsub_n);
     return hipGetLastError();
 }
 

@@ -186,6 +186,7 @@ static void free_plan(Context *ctx, CircPlan *p)
         dev_free(ctx, p->fslot_gate);
         dev_free(ctx, p->fslot_info);
         dev_free(ctx, p->fphases);
+        dev_free(ctx, p->fsub);
         ready_free(p->ready);
     }
 }
@@ -195,6 +196,40 @@ void free_circ_plans(Context *ctx, Circ *C)
     for (auto *cache : {&C->fwd, &C->rev}) {
         for (auto &kv : *cache) free_plan(ctx, kv.second.get());
         cache->clear();
+    }
+}
+
+// Per fused stage and sub-cube u the two LDS indices a thread needs (see
+// FusedStage): the swizzled base of its sub-cube, swz(bl(u)) with bl(u) = u
+// with zeros inserted at the register bits, and for stages whose store map
+// moves amplitudes the swizzled image of u under that map, swz(lbl(u)) with
+// lbl(u) = xor of lc[j] over the set bits j of u; packed as low | high << 16.
+// The LDS swizzle is linear over xor, so every amplitude address is one of
+// these xor a wave-uniform term.
+static uint32_t lds_swz(uint32_t i) { return i ^ ((i >> 4) & 15u); }
+
+static void build_fsub(CircPlan *plan, int keff)
+{
+    plan->fsub_n = 0;
+    plan->host_fsub.clear();
+    if (plan->host_fstages.empty()) return;
+    const int nb = plan->host_fstages[0].nb;
+    const int nsub = 1 << (keff - nb);
+    plan->fsub_n = nsub;
+    plan->host_fsub.resize(plan->host_fstages.size() * (size_t)nsub);
+    for (size_t st = 0; st < plan->host_fstages.size(); ++st) {
+        const FusedStage &fs = plan->host_fstages[st];
+        uint32_t pos[4];
+        for (int i = 0; i < nb; ++i) pos[i] = fs.rpos[i];
+        std::sort(pos, pos + nb);
+        for (int u = 0; u < nsub; ++u) {
+            uint32_t bl = (uint32_t)u;
+            for (int i = 0; i < nb; ++i) bl = ((bl >> pos[i]) << (pos[i] + 1)) | (bl & ((1u << pos[i]) - 1u));
+            uint32_t lbl = 0;
+            for (int j = 0; j < 12; ++j)
+                if ((u >> j) & 1) lbl ^= fs.lc[j];
+            plan->host_fsub[st * nsub + u] = lds_swz(bl) | (lds_swz(lbl) << 16);
+        }
     }
 }
 
@@ -721,6 +756,10 @@ CircPlan *get_circ_plan(Circ *C, bool reverse, int k, int c, int *rc)
         if (!r && !plan->host_fphases.empty())
             r = upload(C->ctx, plan->fphases, plan->host_fphases.data(),
                        plan->host_fphases.size() * sizeof(FusedPhase));
+        if (!r && !plan->host_fstages.empty()) {
+            build_fsub(plan.get(), keff);
+            r = upload(C->ctx, plan->fsub, plan->host_fsub.data(), plan->host_fsub.size() * sizeof(uint32_t));
+        }
         if (r) {
             free_plan(C->ctx, plan.get());
             *rc = r;
