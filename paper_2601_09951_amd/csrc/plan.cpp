@@ -27,6 +27,10 @@ namespace {
 // bounds that keep a pass's control data plus a two-state 2^12 tile inside 160 KiB of LDS
 constexpr int kMaxParamOpsPerPass = 128;
 constexpr int kMaxOpsPerPass = 128;
+// bit exchanges tried per sweep tile: a plan of one Hamiltonian is built once
+// and serves every step of a loop; plans over a batch of request
+// Hamiltonians are built per batch, so they keep the plain cover
+constexpr int kSweepSwapRounds = 16;
 
 inline int popc(uint64_t v) { return __builtin_popcountll(v); }
 inline int bit_of_wire(int n, int w) { return n - 1 - w; }
@@ -847,7 +851,46 @@ PauliPlan *get_pauli_plan(Context *ctx, int n_hams, Ham *const *hams, int n_inst
             if (best < 0) break;
             S |= flips[best];
         }
-        std::vector<int> tile = complete_tile(S, n, keff);
+        // Fill the tile's remaining bits with those that let the most
+        // unassigned groups in, then exchange single bits (outside the low
+        // ones) while that lets more groups in: fewer sweeps of the state.
+        auto covered = [&](uint64_t T) {
+            int cnt = 0;
+            for (size_t g = 0; g < flips.size(); ++g) cnt += sweep_of[g] == -1 && (flips[g] & ~T) == 0;
+            return cnt;
+        };
+        while (popc(S) < keff) {
+            int best_b = -1, best_c = -1;
+            for (int b = 0; b < n; ++b) {
+                if ((S >> b) & 1) continue;
+                const int cv = covered(S | (1ull << b));
+                if (cv > best_c) {
+                    best_c = cv;
+                    best_b = b;
+                }
+            }
+            S |= 1ull << best_b;
+        }
+        for (int it = 0, cur = covered(S); it < (n_hams == 1 ? kSweepSwapRounds : 0); ++it) {
+            int best_c = cur;
+            uint64_t best_S = S;
+            for (int bo = ceff; bo < n; ++bo) {
+                if (!((S >> bo) & 1)) continue;
+                for (int bi = ceff; bi < n; ++bi) {
+                    if ((S >> bi) & 1) continue;
+                    const uint64_t T = S ^ (1ull << bo) ^ (1ull << bi);
+                    const int cv = covered(T);
+                    if (cv > best_c) {
+                        best_c = cv;
+                        best_S = T;
+                    }
+                }
+            }
+            if (best_c == cur) break;
+            S = best_S;
+            cur = best_c;
+        }
+        std::vector<int> tile = bits_of(S);
         uint64_t tmask = mask_of(tile);
         int s = (int)sweep_tiles.size();
         sweep_tiles.push_back(tile);
