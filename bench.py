@@ -494,7 +494,7 @@ def _hea_eval(ctx, vqe, synth, torch, n, layers, terms, batch, want_grad, reps=3
     torch.cuda.synchronize()
     ms = s0.elapsed_time(s1) / reps
     ctx.clear_tuning()
-    ctx.set_graphs(True)
+    ctx.set_graphs(False)  # the library default
     del ws
     torch.cuda.empty_cache()
     return ms, spec, H, tuned

@@ -129,7 +129,7 @@ int vqe_ctx_set_loop_mode(vqe_ctx_t ctx, int mode);
  * result up to rounding; the switch exists for measurement. */
 int vqe_ctx_set_staged(vqe_ctx_t ctx, int staged);
 
-/* Launch graphs (on = 1, the default): a launch sequence of vqe_energy,
+/* Launch graphs (on = 1; off by default): a launch sequence of vqe_energy,
  * vqe_energy_grad or one optimiser step of vqe_run's per-step loop that is
  * seen a second time with identical arguments (pointers included) is
  * captured into a hipGraph, which is launched instead of the individual
@@ -139,7 +139,10 @@ int vqe_ctx_set_staged(vqe_ctx_t ctx, int staged);
  * A graph is dropped when a Pauli plan it reads is retired (a Hamiltonian
  * destroyed, the plan cache flushed) or its circuit is destroyed.  Kernel
  * timing (vqe_ctx_set_profiling) keeps calls eager.  on = 0 drops every
- * graph. */
+ * graph.  Off by default: on the measured workloads (4 to 26 qubits) replays
+ * were no faster than eager launches, and for a call of a few short kernels
+ * a graph launch costs more host time than the launches it replaces; it is
+ * for callers whose host loop cannot keep the GPU busy. */
 int vqe_ctx_set_graphs(vqe_ctx_t ctx, int on);
 
 /* Graphs captured and launched so far, and graphs cached now (any pointer

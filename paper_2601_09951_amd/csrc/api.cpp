@@ -998,10 +998,11 @@ void drop_entry(Context *ctx, Context::GraphEntry &e)
 // `key`: eagerly the first time; captured into a graph and launched the
 // second time; launched from the graph after that.  Profiling, a stream that
 // is itself being captured, or vqe_ctx_set_graphs(ctx, 0) keep it eager.
-template <class F>
-int run_graphed(Context *ctx, const std::string &key, uint64_t circ_id, hipStream_t s, F body)
+template <class K, class F>
+int run_graphed(Context *ctx, K make_key, uint64_t circ_id, hipStream_t s, F body)
 {
     if (!ctx->graphs || ctx->profile || capturing(s)) return body(s);
+    const std::string key = make_key();
     auto it = ctx->graph_cache.find(key);
     if (it != ctx->graph_cache.end() && it->second.epoch != ctx->plan_epoch) {  // a plan it read was retired
         drop_entry(ctx, it->second);
@@ -1812,8 +1813,9 @@ int vqe_energy(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams
     if (rc) return rc;
     if (ws_bytes < L.total) return set_err(ctx, VQE_EINVAL, "workspace too small");
     unsigned char *ws = (unsigned char *)workspace;
-    const std::string key = graph_key(ctx, "e", circ, n_hams, H.data(), batch, L, ref_index, theta, energy,
-                                      nullptr, ws, "");
+    auto key = [&]() {
+        return graph_key(ctx, "e", circ, n_hams, H.data(), batch, L, ref_index, theta, energy, nullptr, ws, "");
+    };
     return run_graphed(ctx, key, circ->id, (hipStream_t)stream, [&](hipStream_t s) {
         return energy_chunks(ctx, circ, n_hams, H.data(), batch, ref_index, theta, energy, 1, ws, L, L.pe, s);
     });
@@ -1839,8 +1841,9 @@ int vqe_energy_grad(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t 
     if (rc) return rc;
     if (ws_bytes < L.total) return set_err(ctx, VQE_EINVAL, "workspace too small");
     unsigned char *ws = (unsigned char *)workspace;
-    const std::string key = graph_key(ctx, "g", circ, n_hams, H.data(), batch, L, ref_index, theta, energy, grad,
-                                      ws, "");
+    auto key = [&]() {
+        return graph_key(ctx, "g", circ, n_hams, H.data(), batch, L, ref_index, theta, energy, grad, ws, "");
+    };
     return run_graphed(ctx, key, circ->id, (hipStream_t)stream, [&](hipStream_t s) {
         return energy_grad_chunks(ctx, circ, n_hams, H.data(), batch, ref_index, theta, energy, 1, grad, ws, L, s);
     });
@@ -2038,10 +2041,17 @@ int vqe_run(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams, i
     }
     rc = hip_check(ctx, launch_step_set(step, 0, s), "step index");
     if (rc) return rc;
-    char extra[160];
-    std::snprintf(extra, sizeof extra, "%d:%a:%a:%a:%a:%lld", optimizer, lr, b1, b2, eps, (long long)e_stride);
-    const std::string key = graph_key(ctx, "r", circ, n_hams, H.data(), batch, L, ref_index, theta, energies,
-                                      nullptr, ws, extra);
+    std::string key_s;  // built once, only when graphs are on
+    auto key = [&]() {
+        if (key_s.empty()) {
+            char extra[160];
+            std::snprintf(extra, sizeof extra, "%d:%a:%a:%a:%a:%lld", optimizer, lr, b1, b2, eps,
+                          (long long)e_stride);
+            key_s = graph_key(ctx, "r", circ, n_hams, H.data(), batch, L, ref_index, theta, energies, nullptr, ws,
+                              extra);
+        }
+        return key_s;
+    };
     for (int it = 0; it < iters; ++it) {
         rc = run_graphed(ctx, key, circ->id, s, [&](hipStream_t st) {
             int r = energy_grad_chunks(ctx, circ, n_hams, H.data(), batch, ref_index, theta, estep, 1, g, ws, L, st);

@@ -410,7 +410,7 @@ struct Context {
     // from then on.  Arguments that change between launches of one sequence
     // (the optimiser step) live in device memory.  An entry is dropped when a
     // Pauli plan it reads is retired (plan_epoch) or its circuit destroyed.
-    int graphs = 1;
+    int graphs = 0;  // off by default: measured replays were no faster than eager launches here
     uint64_t plan_epoch = 0;
     hipStream_t capture_stream = nullptr;
     std::vector<PauliPlan *> *capture_plans = nullptr;  // Pauli plans read by the sequence being captured
