@@ -1985,10 +1985,12 @@ int vqe_run(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams, i
         }
         int mode = 0;
         size_t lds = 0;
+        int max_pairs = 1;
+        for (const OpDesc &o : fp->host_ops) max_pairs = std::max(max_pairs, 1 << (n - o.nfix));
         if (fp->passes.size() == 1 && rp->passes.size() == 1 && pp->sweeps.size() == 1 &&
             fp->passes[0].op_count == G && rp->passes[0].op_count == G &&
             pp->sweeps[0].grp_count == NU && same_pairs(fp, rp, G) &&
-            small_run_plan(n, G, P, circ->n_pgates, NU, max_inst_terms, has_imag, &mode, &lds)) {
+            small_run_plan(n, G, P, circ->n_pgates, NU, max_inst_terms, has_imag, max_pairs, &mode, &lds)) {
             SmallRunArgs a;
             a.n = n;
             a.n_gates = G;
@@ -2013,9 +2015,7 @@ int vqe_run(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams, i
             a.hist = reinterpret_cast<double2 *>(ws + L.hist);
             rc = refresh_weights(ctx, pp, s);
             if (rc) return rc;
-            int max_pairs = 1;
-            for (const OpDesc &o : fp->host_ops) max_pairs = std::max(max_pairs, 1 << (n - o.nfix));
-            ProfScope prof(ctx, "k_small_fast / k_small_run (persistent loop)", s, 0.0);
+            ProfScope prof(ctx, small_run_variant(a, mode, max_pairs), s, 0.0);
             rc = hip_check(ctx, launch_small_run(a, reinterpret_cast<const OpDesc *>(rp->ops.p),
                                                  reinterpret_cast<const int32_t *>(circ->pmap_off.p),
                                                  reinterpret_cast<const int32_t *>(circ->pmap_idx.p),

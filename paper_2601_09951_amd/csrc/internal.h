@@ -610,7 +610,9 @@ hipError_t launch_small_run(const SmallRunArgs &a, const OpDesc *rops, const int
                             const int32_t *pmap_idx, int n_pgates, int mode, int max_inst_terms, int max_pairs,
                             int64_t batch, hipStream_t s);
 int small_run_plan(int n, int n_gates, int n_params, int n_pgates, int n_groups, int max_inst_terms,
-                   int has_imag, int *mode_out, size_t *lds_out);
+                   int has_imag, int max_pairs, int *mode_out, size_t *lds_out);
+// name of the persistent kernel variant that launch_small_run runs (profiling records it)
+const char *small_run_variant(const SmallRunArgs &a, int mode, int max_pairs);
 size_t small_fast_hist_bytes(int n, int n_gates);  // per instance
 }  // namespace vqe
 

@@ -504,7 +504,7 @@ __global__ __launch_bounds__(256) void k_small_run(SmallKernelArgs ka)
 //    conjugate-transposed);
 //  * the forward sweep records each lane's pair values after every gate in
 //    a history buffer in global memory; the reverse sweep reads psi back
-//    from it (four ops ahead) instead of undoing the gates on psi, so only
+//    from it (kHistAhead = 8 ops ahead) instead of undoing the gates on psi, so only
 //    lambda is carried back;
 //  * the optimiser step writes the next iteration's matrices of each
 //    parameter's gates directly (U = A cos(a/2) + B sin(a/2) with A, B
@@ -1222,12 +1222,15 @@ size_t small_fast_hist_bytes(int n, int n_gates)
 
 // 1 if the persistent loop can run this problem; *mode_out gets the Hamiltonian form
 int small_run_plan(int n, int n_gates, int n_params, int n_pgates, int n_groups, int max_inst_terms,
-                   int has_imag, int *mode_out, size_t *lds_out)
+                   int has_imag, int max_pairs, int *mode_out, size_t *lds_out)
 {
     if (n > 10 || n_gates > 2048 || n_params > 2048) return 0;
-    // up to 8 qubits with the Hamiltonian as a table: the latency-built kernel
+    // up to 8 qubits with the Hamiltonian as a table: the latency-built kernel,
+    // sized with the layout of the variant that will run (register rows keep
+    // no table in LDS)
     if (n <= 8 && n_gates <= 1024) {
-        const FastLayout W = fast_layout(n, n_gates, n_params, n_pgates, n_groups, has_imag);  // (register rows need less)
+        const bool rt = fast_regtab(n, n_groups, has_imag) && max_pairs <= 64;
+        const FastLayout W = fast_layout(n, n_gates, n_params, n_pgates, n_groups, has_imag, rt);
         if (W.total <= kSmallLdsMax) {
             *mode_out = (has_imag ? 2 : 1) | kSmallFast;
             *lds_out = W.total;
@@ -1247,6 +1250,14 @@ int small_run_plan(int n, int n_gates, int n_params, int n_pgates, int n_groups,
         }
     }
     return 0;
+}
+
+const char *small_run_variant(const SmallRunArgs &a, int mode, int max_pairs)
+{
+    if (!(mode & kSmallFast)) return "k_small_run (persistent loop)";
+    if (fast_regtab(a.n, a.n_groups, (mode & 15) == 2) && max_pairs <= 64)
+        return "k_small_fast (persistent loop, register rows)";
+    return "k_small_fast (persistent loop, table)";
 }
 
 hipError_t launch_small_run(const SmallRunArgs &a, const OpDesc *rops, const int32_t *pmap_off,

@@ -456,7 +456,15 @@ def test_persistent_loop_register_rows(vqe, ctx, n_groups):
     th0 = synth.uniform_thetas(spec.n_params, 3, seed=n_groups)
     th = dev(th0)
     iters = 20
+    ctx.profile(reset=True)
+    ctx.set_profiling(True)  # records which persistent kernel variant ran
     traj = vqe.run(ctx, C, H, th, iters).cpu().numpy()
+    ran = set(ctx.profile(reset=True))
+    ctx.set_profiling(False)
+    # 90 groups: the 8-qubit table (96 x 256 doubles) exceeds the LDS
+    want_kernel = ("k_small_fast (persistent loop, register rows)" if n_groups <= 64
+                   else "k_small_run (persistent loop)")
+    assert want_kernel in ran, ran
     tho_gpu = th.cpu().numpy()
     for b in range(3):
         want, tho = oracle.vqe_run(spec, ham, th0[b], iters)
