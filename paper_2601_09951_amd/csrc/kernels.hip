@@ -205,6 +205,17 @@ __device__ __forceinline__ void tile_out2(const double2 *ta, const double2 *tb, 
     }
 }
 
+// An amplitude read field by field: a register array filled this way stays
+// in registers even where a stage stores it back unchanged (a whole-struct
+// copy from LDS into the array and back can leave the array in scratch).
+__device__ __forceinline__ double2 lds_get(const double2 *p)
+{
+    double2 r;
+    r.x = p->x;
+    r.y = p->y;
+    return r;
+}
+
 // Workgroup barrier that orders LDS only: outstanding global loads (a tile
 // prefetch) stay in flight across it, which __syncthreads would drain.
 __device__ __forceinline__ void lds_barrier()
@@ -224,12 +235,15 @@ __device__ __forceinline__ double wave_sum(double v)
 // Sum over the 64 lanes, identical in every lane, in a fixed order: DPP
 // lane permutations (no LDS traffic) form quad, half-row and row sums, and
 // the four row sums are added through readlane in row order.  Every lane
-// must be active.
+// must be active.  The moves carry no "old" value: the quad and mirror
+// permutations give every lane a source, and the row broadcasts below leave
+// only rows whose values the final lane never reads (a zero "old" would cost
+// one extra move per DPP instruction).
 template <int CTRL>
 __device__ __forceinline__ double dpp_move(double v)
 {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
     return __hiloint2double(hi, lo);
 }
 
@@ -254,8 +268,8 @@ __device__ __forceinline__ double wave_total(double v)
 template <int CTRL, int ROWS>
 __device__ __forceinline__ double dpp_move_rows(double v)
 {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, ROWS, 0xF, false);
     return __hiloint2double(hi, lo);
 }
 
@@ -1183,12 +1197,12 @@ __device__ __forceinline__ void fused_stage(double2 *tile, const FusedStage &fs,
                   ((i & 4) ? 1u << fs.rpos[2] : 0u) | ((i & 8) ? 1u << fs.rpos[3] : 0u);
         sro[i] = swz(roff[i]);  // uniform
     }
+    // every thread loads (one without a sub-cube reads sub-cube 0's
+    // addresses, which the caller passes it); only owners compute and store
     double2 x[16];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) x[i] = make_double2(0.0, 0.0);
+    for (int i = 0; i < 16; ++i) x[i] = lds_get(tile + (sbl ^ sro[i]));
     if (have) {
-#pragma unroll
-        for (int i = 0; i < 16; ++i) x[i] = tile[sbl ^ sro[i]];
         if (NA > 0) fused_bit<0>(x, fm[0]);
         if (NA > 1) fused_bit<1>(x, fm[1]);
         if (NA > 2) fused_bit<2>(x, fm[2]);
@@ -1382,12 +1396,14 @@ __device__ __forceinline__ void rbit_q(const double2 (&x)[8], const double2 (&l)
 }
 
 template <int B>
-__device__ __forceinline__ void rbit_step(double2 (&x)[8], double2 (&l)[8], const Mat2 &w, int qs, double *red)
+__device__ __forceinline__ void rbit_step(double2 (&x)[8], double2 (&l)[8], const Mat2 &w, int qs, double *red,
+                                          bool have)
 {
     constexpr int M = 1 << B;
     if (qs >= 0) {  // the slot holds parametric gates (uniform)
         double q0, q1, q2;
         rbit_q<B>(x, l, q0, q1, q2);
+        if (!have) q0 = q1 = q2 = 0.0;  // a thread without a sub-cube adds zeros
         q0 = wave_total_last(q0);
         q1 = wave_total_last(q1);
         q2 = wave_total_last(q2);
@@ -1422,23 +1438,18 @@ __device__ __forceinline__ void rev_fused_stage(double2 *tp, double2 *tl, const 
                   ((i & 4) ? 1u << fs.rpos[2] : 0u);
         sro[i] = swz(roff[i]);  // uniform
     }
+    // every thread loads a sub-cube (one without its own reads sub-cube 0's
+    // addresses, which the caller passes it) and takes part in the sums,
+    // adding zeros; only owners store
     double2 x[8], l[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-        x[i] = make_double2(0.0, 0.0);
-        l[i] = make_double2(0.0, 0.0);
+        x[i] = lds_get(tp + (sbl ^ sro[i]));
+        l[i] = lds_get(tl + (sbl ^ sro[i]));
     }
-    if (have) {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            x[i] = tp[sbl ^ sro[i]];
-            l[i] = tl[sbl ^ sro[i]];
-        }
-    }
-    // every thread takes part in the sums (a thread with no sub-cube adds zeros)
-    if (NA > 0) rbit_step<0>(x, l, wm[0], (int)__builtin_amdgcn_readfirstlane((uint32_t)qidx[0]), red);
-    if (NA > 1) rbit_step<1>(x, l, wm[1], (int)__builtin_amdgcn_readfirstlane((uint32_t)qidx[1]), red);
-    if (NA > 2) rbit_step<2>(x, l, wm[2], (int)__builtin_amdgcn_readfirstlane((uint32_t)qidx[2]), red);
+    if (NA > 0) rbit_step<0>(x, l, wm[0], (int)__builtin_amdgcn_readfirstlane((uint32_t)qidx[0]), red, have);
+    if (NA > 1) rbit_step<1>(x, l, wm[1], (int)__builtin_amdgcn_readfirstlane((uint32_t)qidx[1]), red, have);
+    if (NA > 2) rbit_step<2>(x, l, wm[2], (int)__builtin_amdgcn_readfirstlane((uint32_t)qidx[2]), red, have);
     if (PH) {
         // parity phases: every gradient term is (-1)^{parity} Im(conj(lam) psi)
         // summed over the sub-cube (diagonal phases leave Im(conj(lam) psi)
@@ -1455,6 +1466,7 @@ __device__ __forceinline__ void rev_fused_stage(double2 *tp, double2 *tl, const 
                 double g = 0.0;
 #pragma unroll
                 for (int i = 0; i < 8; ++i) g += ((__popc(mask & roff[i]) & 1) ^ sb) ? -e[i] : e[i];
+                if (!have) g = 0.0;
                 g = wave_total_last(g);
                 if ((threadIdx.x & 63) == 63) atomicAdd(phred + ps * 4 + (threadIdx.x >> 6), g);
             }
