@@ -235,10 +235,10 @@ __device__ __forceinline__ double wave_sum(double v)
 // Sum over the 64 lanes, identical in every lane, in a fixed order: DPP
 // lane permutations (no LDS traffic) form quad, half-row and row sums, and
 // the four row sums are added through readlane in row order.  Every lane
-// must be active.  The moves carry no "old" value: the quad and mirror
-// permutations give every lane a source, and the row broadcasts below leave
-// only rows whose values the final lane never reads (a zero "old" would cost
-// one extra move per DPP instruction).
+// must be active.  The moves carry no "old" value: the quad permutations,
+// mirrors and row rotations give every lane a source, and the row broadcasts
+// below leave only rows whose values the final lane never reads (a zero
+// "old" would cost one extra move per DPP instruction).
 template <int CTRL>
 __device__ __forceinline__ double dpp_move(double v)
 {
@@ -282,6 +282,49 @@ __device__ __forceinline__ double wave_total_last(double v)
     v += dpp_move_rows<0x142, 0xA>(v);  // row_bcast:15
     v += dpp_move_rows<0x143, 0xC>(v);  // row_bcast:31
     return v;
+}
+
+// v plus its partner 16 (32) lanes away, the lower lane's value first, by
+// the gfx950 row swaps (both operands the same value: each output holds the
+// partner's value in one half of the rows and the lane's own in the other).
+__device__ __forceinline__ double swap16_sum(double v)
+{
+    const unsigned lo = __double2loint(v), hi = __double2hiint(v);
+    const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
+}
+
+__device__ __forceinline__ double swap32_sum(double v)
+{
+    const unsigned lo = __double2loint(v), hi = __double2hiint(v);
+    const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
+}
+
+// Wave sums of three values a, b, c at once, fixed order: the total of a
+// ends in every lane whose index is 0 mod 4, of b in lanes 1 mod 4, of c in
+// lanes 2 mod 4.  The first two exchange steps (partners lane ^ 1, lane ^ 2)
+// also sort the values by lane class, so the remaining four (row rotations
+// by 4 and 8, then the 16- and 32-lane swaps, all class-preserving) carry
+// one value instead of three.  Every lane must be active.
+__device__ __forceinline__ double wave_total3(double a, double b, double c)
+{
+    const int lane = (int)threadIdx.x & 63;
+    const bool o1 = lane & 1, o2 = lane & 2;
+    // partner lane ^ 1: even lanes keep a and c, odd lanes b and nothing
+    double k1 = o1 ? b : a, k2 = o1 ? 0.0 : c;
+    const double s1 = o1 ? a : b, s2 = o1 ? c : 0.0;
+    k1 += dpp_move<0xB1>(s1);  // quad_perm [1, 0, 3, 2]
+    k2 += dpp_move<0xB1>(s2);
+    // partner lane ^ 2: lanes 0, 1 of a quad keep k1 (a, b), lanes 2, 3 keep k2 (c, 0)
+    double k = o2 ? k2 : k1;
+    const double s = o2 ? k1 : k2;
+    k += dpp_move<0x4E>(s);  // quad_perm [2, 3, 0, 1]
+    k += dpp_move<0x124>(k);  // row_ror:4
+    k += dpp_move<0x128>(k);  // row_ror:8
+    return swap32_sum(swap16_sum(k));
 }
 
 // sum of v over the workgroup (kThreads threads), fixed order; result in
@@ -1404,15 +1447,10 @@ __device__ __forceinline__ void rbit_step(double2 (&x)[8], double2 (&l)[8], cons
         double q0, q1, q2;
         rbit_q<B>(x, l, q0, q1, q2);
         if (!have) q0 = q1 = q2 = 0.0;  // a thread without a sub-cube adds zeros
-        q0 = wave_total_last(q0);
-        q1 = wave_total_last(q1);
-        q2 = wave_total_last(q2);
-        if ((threadIdx.x & 63) == 63) {  // LDS adds without a return value: no wait
-            double *r = red + (size_t)qs * 12 + (threadIdx.x >> 6);
-            atomicAdd(r, q0);
-            atomicAdd(r + 4, q1);
-            atomicAdd(r + 8, q2);
-        }
+        const double t = wave_total3(q0, q1, q2);
+        const int lane = (int)threadIdx.x & 63;
+        if (lane < 3)  // lane j holds Q_j's wave total; LDS adds without a return value: no wait
+            atomicAdd(red + (size_t)qs * 12 + 4 * lane + (threadIdx.x >> 6), t);
     }
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
