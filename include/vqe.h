@@ -161,7 +161,9 @@ int vqe_ctx_graph_stats(vqe_ctx_t ctx, int64_t *captures, int64_t *launches, int
  * 12), contiguous low bits c_low 2..4, the batch tile (instances per launch
  * sequence: batch / 2, batch / 4, ..., 1; a batch then runs as consecutive
  * chunks, so that a chunk's states can stay in the last-level cache), and
- * the cap on workgroups per instance (256, 1024, 4096).  Each candidate runs
+ * the cap on workgroups per instance (256, 1024, 4096; the default cap is
+ * 8192, and a pass uses about one workgroup per four tiles, at least 512,
+ * within the cap).  Each candidate runs
  * twice untimed (plans, uploads, graph capture) and then at least 3 times
  * (until 20 ms) between HIP events on `stream`, with outputs and a workspace
  * that the tuner allocates for each candidate's size (set-up work: size the

@@ -543,7 +543,7 @@ int wg_for(Context *ctx, int n, int k)
 {
     const int keff = std::min(n, k);
     const int64_t tiles = 1ll << (n - keff);
-    return (int)std::min<int64_t>(tiles, ctx->wg_max);
+    return pass_workgroups(tiles, ctx->wg_max);
 }
 
 // workspace layout; want: 0 energy, 1 energy+grad, 2 run (adds optimiser state)
@@ -888,6 +888,8 @@ int energy_grad_into(Context *ctx, Circ *C, int n_hams, Ham *const *H, int64_t B
                                                      reinterpret_cast<const FusedCond *>(rp->fconds.p),
                                                      reinterpret_cast<const int32_t *>(rp->fslot_off.p),
                                                      reinterpret_cast<const int32_t *>(rp->fslot_info.p),
+                                                     reinterpret_cast<const int32_t *>(rp->fslot_q.p),
+                                                     reinterpret_cast<const int32_t *>(rp->fphase_q.p),
                                                      rp->host_fstages[p.fstage_begin].slot, rp->n_fslots(),
                                                      n_entries, p.fq_count, wadj, coef,
                                                      reinterpret_cast<const FusedPhase *>(rp->fphases.p), mats, G,
@@ -2182,7 +2184,7 @@ int vqe_autotune(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *ha
         }
     };
     if (n > 8) {  // smaller states are one tile at every width
-        std::vector<int64_t> kf, kr, cl = {2, 3, 4}, wg = {256, 1024, 4096}, bt;
+        std::vector<int64_t> kf, kr, cl = {2, 3, 4}, wg = {256, 1024, 4096}, bt;  // caps below the default
         for (int k = 8; k <= std::min(n, (int)kMaxTileBits); ++k) kf.push_back(k);
         for (int k = 8; k <= std::min(n, 12); ++k) kr.push_back(k);
         for (int64_t b = batch / 2; b >= 1; b /= 2) bt.push_back(b);

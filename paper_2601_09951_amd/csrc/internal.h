@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <map>
 #include <memory>
@@ -20,6 +21,19 @@ namespace vqe {
 // ---------------------------------------------------------------------------
 
 constexpr int kMaxTileBits = 13;   // 2^13 complex128 = 128 KiB of LDS
+constexpr int kPassWgMin = 512;    // two workgroups on each of the 256 compute units
+
+// Workgroups per instance of a tile pass over `tiles` tiles: about four tiles
+// per workgroup, so that workgroups end and their successors start at
+// staggered times (two of these workgroups share a compute unit, and two
+// that start together keep their LDS, arithmetic and HBM phases in step,
+// which leaves each unit idle in turn), at least kPassWgMin, at most tiles
+// and the cap wg_max.
+inline int pass_workgroups(int64_t tiles, int wg_max)
+{
+    const int64_t w = tiles / 4 > kPassWgMin ? tiles / 4 : kPassWgMin;
+    return (int)std::min<int64_t>(std::min<int64_t>(tiles, w), wg_max);
+}
 constexpr int kMaxOutBits = 40;
 constexpr int kThreads = 256;      // workgroup size of the state passes
 
@@ -274,6 +288,10 @@ struct CircPlan {
     std::vector<int32_t> host_fslot_off{0}, host_fslot_gate;
     std::vector<int32_t> host_fslot_info;  // per slot entry: (pgate + 1) << 4 | class << 2 | generator
     int n_fslots() const { return (int)host_fslot_off.size() - 1; }
+    // per slot and per phase its index among the parametric slots (phases)
+    // of its pass, -1 when it holds no parametric gate
+    DevMem fslot_q, fphase_q;
+    std::vector<int32_t> host_fslot_q, host_fphase_q;
     // per fused stage and sub-cube: swizzled sub-cube base | swizzled store-map image << 16
     DevMem fsub;
     std::vector<uint32_t> host_fsub;
@@ -347,7 +365,7 @@ struct Context {
     size_t budget = 0;
     size_t used = 0;
     int k_fwd = 12, k_rev = 11, c_low = 3;  // c_low 3: runs of 8 amplitudes = one 128-byte line
-    int wg_max = 1024;          // workgroups per instance in tile passes
+    int wg_max = 8192;          // cap on workgroups per instance in tile passes
     int force_generic = 0;      // route vqe_run through the per-step launches
     int no_stages = 0;          // use the one-op-per-LDS-round-trip pass kernels only
     int fuse = 1;               // forward and adjoint passes: fused stages where the plan has them
@@ -427,7 +445,7 @@ struct Context {
 
     // Autotuned execution choices (vqe_autotune) per (circuit, batch, mode).
     struct Tuned {
-        int k_fwd = 12, k_rev = 11, c_low = 3, wg_max = 1024;
+        int k_fwd = 12, k_rev = 11, c_low = 3, wg_max = 8192;
         int64_t batch_tile = 0;          // instances per launch sequence (0: the whole batch)
     };
     std::map<std::string, Tuned> tuned;
@@ -527,7 +545,8 @@ size_t reverse_fused_lds(int k, int c, int nstages, int n_qslots, int n_phases);
 size_t forward_fused_lds(int k, int c, int nstages, int n_phases);
 hipError_t launch_reverse_fused(const PassPlan &pp, const TileGeom *geom_dev, const FusedStage *fstages,
                                 const FusedCond *fconds, const int32_t *slot_off, const int32_t *slot_info,
-                                int slot0, int n_slots, int n_entries, int n_qslots, const double2 *wadj,
+                                const int32_t *slot_q, const int32_t *phase_q, int slot0, int n_slots,
+                                int n_entries, int n_qslots, const double2 *wadj,
                                 const double *coef, const FusedPhase *fphases, const double2 *mats, int n_gates,
                                 double2 *psi, double2 *lam, int64_t batch, int wg_per_inst, double *partials,
                                 int n_pgates, const uint32_t *fsub, int fsub_n, hipStream_t s);

@@ -1544,7 +1544,8 @@ template <bool PH>
 __global__ __launch_bounds__(kThreads) void k_reverse_fused(
     const TileGeom *__restrict__ gp, int n, int k, int c, int nout, const FusedStage *__restrict__ fstages,
     int nstages, const FusedCond *__restrict__ fconds, const int32_t *__restrict__ slot_off,
-    const int32_t *__restrict__ slot_info, int slot0, int n_slots, int n_entries, const double2 *__restrict__ wadj,
+    const int32_t *__restrict__ slot_info, const int32_t *__restrict__ slot_q, const int32_t *__restrict__ phase_q,
+    int nq, int slot0, int n_slots, int n_entries, const double2 *__restrict__ wadj,
     const double *__restrict__ coef, const FusedPhase *__restrict__ fphases, int ph0, int nph,
     const double2 *__restrict__ mats, int n_gates, double2 *__restrict__ psi, double2 *__restrict__ lam,
     int64_t tiles, double *__restrict__ partials, int n_pgates, const uint32_t *__restrict__ fsub)
@@ -1569,31 +1570,21 @@ __global__ __launch_bounds__(kThreads) void k_reverse_fused(
     const double2 *Wg = wadj + ((size_t)blockIdx.y * n_slots + slot0) * 4;
     double2 *wmd = reinterpret_cast<double2 *>(wm);
     for (int i = tid; i < 4 * ns; i += kThreads) wmd[i] = Wg[i];
-    int nq = 0;  // slots with parametric gates, numbered in order (every thread counts)
-    for (int i = 0; i < ns; ++i) {
-        bool par = false;
-        for (int e = slot_off[slot0 + i]; e < slot_off[slot0 + i + 1]; ++e) par = par || slot_info[e] >= 16;
-        if (tid == 0) qidx[i] = par ? nq : -1;
-        nq += par;
-    }
+    // slots (phases) with parametric gates carry their index among this
+    // pass's, numbered by the plan
+    for (int i = tid; i < ns; i += kThreads) qidx[i] = slot_q[slot0 + i];
     for (int i = tid; i < 12 * nq; i += kThreads) red[i] = 0.0;
     {
         const double2 *Mx = mats + (size_t)blockIdx.y * n_gates * 4;
-        int pslot = 0;  // parametric phases numbered in order (every thread counts)
-        for (int i = 0; PH && i < nph; ++i) {
+        for (int i = tid; PH && i < nph; i += kThreads) {
             const FusedPhase f = fphases[ph0 + i];
-            const bool par = f.info >= 16;
-            if (tid == 0) {
-                PhaseL q;
-                q.mask = f.mask;
-                q.cbit = f.cbit;
-                q.pslot = par ? pslot : -1;
-                q.pg = (f.info >> 4) - 1;
-                q.d0 = cconj(Mx[f.gate * 4 + 0]);
-                q.d1 = cconj(Mx[f.gate * 4 + 3]);
-                phl[i] = q;
-            }
-            pslot += par;
+            PhaseL &q = phl[i];  // field by field (a whole-struct copy into LDS goes through scratch)
+            q.mask = f.mask;
+            q.cbit = f.cbit;
+            q.pslot = phase_q[ph0 + i];
+            q.pg = (f.info >> 4) - 1;
+            q.d0 = cconj(Mx[f.gate * 4 + 0]);
+            q.d1 = cconj(Mx[f.gate * 4 + 3]);
         }
         for (int i = tid; i < 4 * nph; i += kThreads) phred[i] = 0.0;
     }
@@ -1634,11 +1625,12 @@ __global__ __launch_bounds__(kThreads) void k_reverse_fused(
         tile_out2<8, true>(tp, tl, sp, sl, base, hoff, T, c);
         __syncthreads();
     }
-    // partial of entry e = coef(e) . (the slot's three sums over the four waves)
-    if (tid == 0) {
+    // partial of entry e = coef(e) . (the slot's three sums over the four
+    // waves); one thread per slot (phase)
+    {
         const int W = gridDim.x;
         const double *cf = coef + (size_t)blockIdx.y * n_entries * 4;
-        for (int i = 0; i < ns; ++i) {
+        for (int i = tid; i < ns; i += kThreads) {
             const int qs = qidx[i];
             if (qs < 0) continue;
             const double *r = red + (size_t)qs * 12;
@@ -1652,7 +1644,7 @@ __global__ __launch_bounds__(kThreads) void k_reverse_fused(
                 partials[((size_t)blockIdx.y * n_pgates + ((info >> 4) - 1)) * W + blockIdx.x] = v;
             }
         }
-        for (int i = 0; PH && i < nph; ++i) {
+        for (int i = tid; PH && i < nph; i += kThreads) {
             const PhaseL &q = phl[i];
             if (q.pslot < 0) continue;
             const double *r = phred + (size_t)q.pslot * 4;
@@ -2030,8 +2022,8 @@ __global__ __launch_bounds__(kThreads) void k_pauli_wide(int n, uint64_t f, int 
 //   (H psi)[o] += (A(p) + i s B(p)) psi[o ^ f],   s = +1 if bit v of o is 1, else -1,
 // and the diagonal group adds A(o) psi[o].  psi is only read from LDS, so the
 // groups need no barrier between them, and lambda never passes through LDS:
-// each thread reads its running lambda from HBM at the start of the tile (in
-// flight while the groups run) and writes the sum back.  The last sweep also
+// each thread reads its running lambda from HBM after the groups, adds and
+// writes the sum back.  The last sweep also
 // accumulates Re <psi|lambda> (the energy) over its amplitudes.
 template <int NO>
 __global__ __launch_bounds__(kThreads) void k_hpsi_gather(
@@ -2148,7 +2140,10 @@ __global__ __launch_bounds__(kThreads) void k_hpsi_gather(
                 }
             }
         }
-        // lambda += the tile's H psi, all reads of the running sum in flight together
+        // lambda += the tile's H psi, all reads of the running sum in flight
+        // together (read here rather than at the start of the tile: held
+        // across the groups they cost registers, and occupancy, that the
+        // overlap does not repay)
         uint64_t gi[NO];
         double2 run[NO];
 #pragma unroll
@@ -2340,7 +2335,7 @@ hipError_t launch_forward_pass(const PassPlan &pp, const TileGeom *geom_dev, con
 {
     const TileGeom &g = pp.geom;
     const int64_t tiles = 1ll << g.nout;
-    const int W = (int)std::min<int64_t>(tiles, wg_max);
+    const int W = pass_workgroups(tiles, wg_max);
     const size_t lds = fwd_lds(g);
     hipError_t e = ensure_lds(k_forward_pass, lds);
     if (e != hipSuccess) return e;
@@ -2383,7 +2378,7 @@ hipError_t launch_forward_fused(const PassPlan &pp, const TileGeom *geom_dev, co
     const TileGeom &g = pp.geom;
     if (g.k < 8 || g.k > 12 || !fsub || fsub_n != (1 << (g.k - 4))) return hipErrorInvalidValue;
     const int64_t tiles = 1ll << g.nout;
-    const int W = (int)std::min<int64_t>(tiles, wg_max);
+    const int W = pass_workgroups(tiles, wg_max);
     const size_t lds = forward_fused_lds(g.k, g.c, pp.fstage_count, pp.fphase_count);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     auto kern = pp.fphase_count > 0 ? k_forward_fused<true> : k_forward_fused<false>;
@@ -2421,7 +2416,8 @@ size_t forward_fused_lds(int k, int c, int nstages, int n_phases)
 
 hipError_t launch_reverse_fused(const PassPlan &pp, const TileGeom *geom_dev, const FusedStage *fstages,
                                 const FusedCond *fconds, const int32_t *slot_off, const int32_t *slot_info,
-                                int slot0, int n_slots, int n_entries, int n_qslots, const double2 *wadj,
+                                const int32_t *slot_q, const int32_t *phase_q, int slot0, int n_slots,
+                                int n_entries, int n_qslots, const double2 *wadj,
                                 const double *coef, const FusedPhase *fphases, const double2 *mats, int n_gates,
                                 double2 *psi, double2 *lam, int64_t batch, int wg_per_inst, double *partials,
                                 int n_pgates, const uint32_t *fsub, int fsub_n, hipStream_t s)
@@ -2429,6 +2425,7 @@ hipError_t launch_reverse_fused(const PassPlan &pp, const TileGeom *geom_dev, co
     const TileGeom &g = pp.geom;
     if (g.k < 8 || g.k > 11 || slot0 < 0 || slot0 + 3 * pp.fstage_count > n_slots) return hipErrorInvalidValue;
     if (!fsub || fsub_n != (1 << (g.k - 3))) return hipErrorInvalidValue;
+    if (!slot_q || (pp.fphase_count > 0 && !phase_q)) return hipErrorInvalidValue;
     const int64_t tiles = 1ll << g.nout;
     const size_t lds = reverse_fused_lds(g.k, g.c, pp.fstage_count, n_qslots, pp.fphase_count);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
@@ -2437,7 +2434,7 @@ hipError_t launch_reverse_fused(const PassPlan &pp, const TileGeom *geom_dev, co
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(wg_per_inst, (unsigned)batch), dim3(kThreads), lds, s, geom_dev, g.n,
                        g.k, g.c, g.nout, fstages + pp.fstage_begin, pp.fstage_count, fconds, slot_off, slot_info,
-                       slot0, n_slots, n_entries, wadj, coef, fphases, pp.fphase_begin, pp.fphase_count, mats,
+                       slot_q, phase_q, n_qslots, slot0, n_slots, n_entries, wadj, coef, fphases, pp.fphase_begin, pp.fphase_count, mats,
                        n_gates, psi, lam, tiles, partials, n_pgates, fsub + (size_t)pp.fstage_begin * fsub_n);
     return hipGetLastError();
 }
@@ -2448,7 +2445,7 @@ hipError_t launch_forward_staged(const PassPlan &pp, int stage_bits, const TileG
 {
     const TileGeom &g = pp.geom;
     const int64_t tiles = 1ll << g.nout;
-    const int W = (int)std::min<int64_t>(tiles, wg_max);
+    const int W = pass_workgroups(tiles, wg_max);
     const size_t lds = fwd_lds(g) + stage_ctl_bytes(pp.stage_count, pp.op_count);
     if (stage_bits != 3 && stage_bits != 4) return hipErrorInvalidValue;
     auto kern = stage_bits == 4 ? k_forward_staged<4> : k_forward_staged<3>;

@@ -177,6 +177,31 @@ int build_circuit_gates(Circ *C, int64_t n_gates, const int32_t *kind, const int
     return VQE_OK;
 }
 
+// Number, within each pass, its slots and its phases that hold parametric
+// gates (0, 1, ... in slot / phase order; -1 for the others): the adjoint
+// kernel files each slot's three pair sums and each phase's sum under these
+// indices.
+static void number_param_slots(CircPlan *plan)
+{
+    plan->host_fslot_q.assign(plan->n_fslots(), -1);
+    plan->host_fphase_q.assign(plan->host_fphases.size(), -1);
+    for (const PassPlan &pp : plan->passes) {
+        if (pp.fstage_count == 0) continue;
+        const FusedStage &f0 = plan->host_fstages[pp.fstage_begin];
+        int nq = 0;
+        for (int i = 0; i < f0.nb * pp.fstage_count; ++i) {
+            const int sl = f0.slot + i;
+            bool par = false;
+            for (int e = plan->host_fslot_off[sl]; e < plan->host_fslot_off[sl + 1]; ++e)
+                par = par || plan->host_fslot_info[e] >= 16;
+            if (par) plan->host_fslot_q[sl] = nq++;
+        }
+        int np = 0;
+        for (int i = 0; i < pp.fphase_count; ++i)
+            if (plan->host_fphases[pp.fphase_begin + i].info >= 16) plan->host_fphase_q[pp.fphase_begin + i] = np++;
+    }
+}
+
 static void free_plan(Context *ctx, CircPlan *p)
 {
     if (p) {
@@ -190,6 +215,8 @@ static void free_plan(Context *ctx, CircPlan *p)
         dev_free(ctx, p->fslot_gate);
         dev_free(ctx, p->fslot_info);
         dev_free(ctx, p->fphases);
+        dev_free(ctx, p->fslot_q);
+        dev_free(ctx, p->fphase_q);
         dev_free(ctx, p->fsub);
         ready_free(p->ready);
     }
@@ -760,6 +787,13 @@ CircPlan *get_circ_plan(Circ *C, bool reverse, int k, int c, int *rc)
         if (!r && !plan->host_fphases.empty())
             r = upload(C->ctx, plan->fphases, plan->host_fphases.data(),
                        plan->host_fphases.size() * sizeof(FusedPhase));
+        if (!r && plan->n_fslots() > 0) {
+            number_param_slots(plan.get());
+            r = upload(C->ctx, plan->fslot_q, plan->host_fslot_q.data(), plan->host_fslot_q.size() * sizeof(int32_t));
+            if (!r && !plan->host_fphase_q.empty())
+                r = upload(C->ctx, plan->fphase_q, plan->host_fphase_q.data(),
+                           plan->host_fphase_q.size() * sizeof(int32_t));
+        }
         if (!r && !plan->host_fstages.empty()) {
             build_fsub(plan.get(), keff);
             r = upload(C->ctx, plan->fsub, plan->host_fsub.data(), plan->host_fsub.size() * sizeof(uint32_t));

@@ -415,7 +415,7 @@ def autotune(ctx: Context, circ: Circuit, hams, theta: torch.Tensor, want_grad: 
 
 
 def tune_set(ctx: Context, circ: Circuit, batch: int, want_grad: bool, k_fwd: int = 12, k_rev: int = 11,
-             c_low: int = 3, wg_max: int = 1024, batch_tile: int = None):
+             c_low: int = 3, wg_max: int = 8192, batch_tile: int = None):
     """vqe_tune_set: pin an execution configuration for (circuit, batch, mode)."""
     r = capi.TuneResult(k_fwd=k_fwd, k_rev=k_rev, c_low=c_low, wg_max=wg_max,
                         batch_tile=int(batch if batch_tile is None else batch_tile))
