@@ -1227,6 +1227,111 @@ __device__ __forceinline__ void apply_phases(double2 (&x)[N], const PhaseL *phl,
 // sub = the plan's entry for (stage, u): swz(bl) | swz(lbl) << 16 (see
 // build_fsub); the swizzle is linear over xor, so every address is one of
 // them xor a wave-uniform term.
+// A pass whose first stage holds no gates and no phases only permutes the
+// tile by its network (the amplitude at tile index v moves to L v ^ c, c
+// depending on the tile through X gates conditioned on bits outside it).
+// That map is applied while the tile is read in, instead of by a round trip
+// through LDS: mcol[b] = L e_b for every tile bit b (threads 0 .. k-1 fill
+// it), and element j = tid + 256 u of the tile goes to swz(L tid ^ L (256 u)
+// ^ c).
+__device__ __forceinline__ bool network_only(const FusedStage &fs)
+{
+    return __builtin_amdgcn_readfirstlane((uint32_t)fs.na) == 0 &&
+           __builtin_amdgcn_readfirstlane((uint32_t)fs.phase_count) == 0;
+}
+
+__device__ __forceinline__ void network_columns(const FusedStage &fs, int k, uint32_t *mcol)
+{
+    const int b = (int)threadIdx.x, nb = fs.nb;
+    if (b < nb)
+        mcol[fs.rpos[b]] = fs.lr[1 << b];
+    else if (b < k)
+        mcol[fs.cpos[b - nb]] = fs.lc[b - nb];
+}
+
+// L tid (bits 0-7 of the tile index) and L e_{8+i} (i < 4) from the columns
+struct NetMap {
+    uint32_t lt, m[4];
+};
+
+__device__ __forceinline__ NetMap network_map(const uint32_t *mcol, int k)
+{
+    NetMap nm;
+    nm.lt = 0;
+    for (int b = 0; b < 8 && b < k; ++b)
+        if ((threadIdx.x >> b) & 1u) nm.lt ^= mcol[b];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) nm.m[i] = 8 + i < k ? mcol[8 + i] : 0u;
+    return nm;
+}
+
+// the constant of a stage's network for the tile at `base`
+__device__ __forceinline__ uint32_t stage_const(const FusedStage &fs, const FusedCond *__restrict__ fconds,
+                                                uint64_t base)
+{
+    uint32_t ctile = fs.c0;
+    for (int q = 0; q < fs.cond_count; ++q) {
+        const FusedCond fc = fconds[fs.cond_begin + q];
+        if ((base & fc.cmo) == fc.cvo) ctile ^= fc.xmask;
+    }
+    return ctile;
+}
+
+// LDS index of tile element tid + 256 u under the network (u compile-time)
+__device__ __forceinline__ uint32_t net_index(const NetMap &nm, uint32_t cn, int u)
+{
+    return swz(nm.lt ^ cn ^ ((u & 1) ? nm.m[0] : 0u) ^ ((u & 2) ? nm.m[1] : 0u) ^ ((u & 4) ? nm.m[2] : 0u) ^
+               ((u & 8) ? nm.m[3] : 0u));
+}
+
+// tile_in (one state / two states) with the network folded in; the tile has
+// at most NB * kThreads amplitudes
+template <int NB>
+__device__ __forceinline__ void tile_in_net(double2 *tile, const double2 *__restrict__ src, uint64_t base,
+                                            const uint64_t *hoff, int T, int c, const NetMap &nm, uint32_t cn)
+{
+    const uint32_t lowm = (1u << c) - 1u;
+    double rx[NB], ry[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+        const int j0 = (int)threadIdx.x + u * kThreads;
+        const int j = j0 < T ? j0 : (int)threadIdx.x;
+        const double2 v = src[base + hoff[j >> c] + (j & lowm)];
+        rx[u] = v.x;
+        ry[u] = v.y;
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u)
+        if ((int)threadIdx.x + u * kThreads < T) tile[net_index(nm, cn, u)] = make_double2(rx[u], ry[u]);
+}
+
+template <int NB>
+__device__ __forceinline__ void tile_in2_net(double2 *ta, double2 *tb, const double2 *__restrict__ a,
+                                             const double2 *__restrict__ b, uint64_t base, const uint64_t *hoff,
+                                             int T, int c, const NetMap &nm, uint32_t cn)
+{
+    const uint32_t lowm = (1u << c) - 1u;
+    double ax[NB], ay[NB], bx[NB], by[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+        const int j0 = (int)threadIdx.x + u * kThreads;
+        const int j = j0 < T ? j0 : (int)threadIdx.x;
+        const uint64_t gi = base + hoff[j >> c] + (j & lowm);
+        const double2 va = a[gi], vb = b[gi];
+        ax[u] = va.x;
+        ay[u] = va.y;
+        bx[u] = vb.x;
+        by[u] = vb.y;
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u)
+        if ((int)threadIdx.x + u * kThreads < T) {
+            const uint32_t d = net_index(nm, cn, u);
+            ta[d] = make_double2(ax[u], ay[u]);
+            tb[d] = make_double2(bx[u], by[u]);
+        }
+}
+
 template <int NA, bool PERM, bool PH>
 __device__ __forceinline__ void fused_stage(double2 *tile, const FusedStage &fs, const Mat2 *fm, int nsub,
                                             uint32_t ctile, const PhaseL *phl, int nph, uint32_t sub)
@@ -1292,23 +1397,30 @@ __global__ __launch_bounds__(kThreads) void k_forward_fused(const TileGeom *__re
     const double2 *Mx = mats + (size_t)blockIdx.y * n_gates * 4;
     for (int i = tid; PH && i < nph; i += kThreads) {
         const FusedPhase f = fphases[ph0 + i];
-        PhaseL q;
+        PhaseL &q = phl[i];  // field by field (a whole-struct copy into LDS goes through scratch)
         q.mask = f.mask;
         q.cbit = f.cbit;
         q.pslot = -1;
         q.pg = -1;
         q.d0 = Mx[f.gate * 4 + 0];
         q.d1 = Mx[f.gate * 4 + 3];
-        phl[i] = q;
     }
+    uint32_t *mcol = reinterpret_cast<uint32_t *>(phl + nph);  // 16
+    const bool fold = nstages > 0 && T <= 16 * kThreads && network_only(fstages[0]);
+    if (fold) network_columns(fstages[0], k, mcol);
     __syncthreads();
+    const NetMap nm = fold ? network_map(mcol, k) : NetMap{};
+    const int s0 = fold ? 1 : 0;
     for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
         const uint64_t base = tile_base(gp, nout, t);
-        tile_in<16, true>(tile, st, base, hoff, T, c);
+        if (fold)
+            tile_in_net<16>(tile, st, base, hoff, T, c, nm, stage_const(fstages[0], fconds, base));
+        else
+            tile_in<16, true>(tile, st, base, hoff, T, c);
         lds_barrier();
         const uint32_t *fsu = fsub + (tid < nsub ? tid : 0);
-        uint32_t sub_next = fsu[0];
-        for (int s = 0; s < nstages; ++s) {
+        uint32_t sub_next = fsu[(size_t)s0 * nsub];
+        for (int s = s0; s < nstages; ++s) {
             const uint32_t sub = sub_next;
             if (s + 1 < nstages) sub_next = fsu[(size_t)(s + 1) * nsub];  // in flight during this stage
             const FusedStage fs = fstages[s];  // uniform: scalar loads
@@ -1588,14 +1700,22 @@ __global__ __launch_bounds__(kThreads) void k_reverse_fused(
         }
         for (int i = tid; i < 4 * nph; i += kThreads) phred[i] = 0.0;
     }
+    uint32_t *mcol = reinterpret_cast<uint32_t *>(red + 12 * (size_t)nq);  // 16
+    const bool fold = nstages > 0 && network_only(fstages[0]);  // k <= 11: T <= 8 * kThreads
+    if (fold) network_columns(fstages[0], k, mcol);
     __syncthreads();
+    const NetMap nm = fold ? network_map(mcol, k) : NetMap{};
+    const int s0 = fold ? 1 : 0;
     for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
         const uint64_t base = tile_base(gp, nout, t);
-        tile_in2<8, true>(tp, tl, sp, sl, base, hoff, T, c);
+        if (fold)
+            tile_in2_net<8>(tp, tl, sp, sl, base, hoff, T, c, nm, stage_const(fstages[0], fconds, base));
+        else
+            tile_in2<8, true>(tp, tl, sp, sl, base, hoff, T, c);
         __syncthreads();
         const uint32_t *fsu = fsub + (tid < nsub ? tid : 0);
-        uint32_t sub_next = fsu[0];
-        for (int s = 0; s < nstages; ++s) {
+        uint32_t sub_next = fsu[(size_t)s0 * nsub];
+        for (int s = s0; s < nstages; ++s) {
             const uint32_t sub = sub_next;
             if (s + 1 < nstages) sub_next = fsu[(size_t)(s + 1) * nsub];  // in flight during this stage
             const FusedStage fs = fstages[s];  // uniform: scalar loads
@@ -2406,12 +2526,13 @@ size_t reverse_fused_lds(int k, int c, int nstages, int n_qslots, int n_phases)
 {
     const size_t ns = 3 * (size_t)nstages;
     return (32u << k) + (8u << (k - c)) + ns * sizeof(Mat2) + (size_t)n_phases * (sizeof(PhaseL) + 32) +
-           4 * ((ns + 1) & ~(size_t)1) + 96 * (size_t)n_qslots;
+           4 * ((ns + 1) & ~(size_t)1) + 96 * (size_t)n_qslots + 64;  // + network columns
 }
 
 size_t forward_fused_lds(int k, int c, int nstages, int n_phases)
 {
-    return (16u << k) + (8u << (k - c)) + (size_t)nstages * 4 * sizeof(Mat2) + (size_t)n_phases * sizeof(PhaseL);
+    return (16u << k) + (8u << (k - c)) + (size_t)nstages * 4 * sizeof(Mat2) + (size_t)n_phases * sizeof(PhaseL) +
+           64;  // + network columns
 }
 
 hipError_t launch_reverse_fused(const PassPlan &pp, const TileGeom *geom_dev, const FusedStage *fstages,
