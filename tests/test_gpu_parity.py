@@ -197,6 +197,39 @@ def test_hea_energy_grad_multi_tile(vqe, ctx, n, k, c, staged):
     np.testing.assert_allclose(g.cpu().numpy()[0], go, atol=G_TOL)
 
 
+@pytest.mark.parametrize("n,kf,kr,c", [(16, 12, 11, 3), (18, 10, 9, 3)])
+def test_network_only_first_stage(vqe, ctx, n, kf, kr, c):
+    """Passes whose first fused stage holds only a CNOT network (no gates, no
+    phases) apply it while the tile is read in; the HEA's window passes have
+    such stages, some with X conditioned on bits outside the tile.  The
+    state, energy and gradient against the oracle."""
+    _say("network-only first stage", n, kf, kr, c)
+    ctx.set_tile(kf, kr, c)
+    spec = synth.hea_circuit(n, 6)
+    ham = synth.random_pauli_sum(n, 80, seed=n + 1)
+    th = synth.uniform_thetas(spec.n_params, 1, seed=n + 1)
+    C = vqe.Circuit.from_spec(ctx, spec)
+    H = vqe.Hamiltonian.from_sum(ctx, ham)
+    folded = 0
+    for rev in (False, True):
+        passes, _, fst = vqe.circuit_plan(ctx, C, reverse=rev, stages="fused")[:3]
+        for p in passes:
+            if int(p["fstage_count"]) > 0:
+                f0 = fst[int(p["fstage_begin"])]
+                folded += int(f0["na"]) == 0 and int(f0["phase_count"]) == 0
+    assert folded > 0  # the case exercises the folded tile read
+    psi = torch.empty(1, 1 << n, dtype=torch.complex128, device="cuda")
+    vqe.prepare_reference(ctx, n, 1, spec.ref_index, psi)
+    vqe.apply_ansatz(ctx, C, dev(th), psi)
+    e, g = vqe.energy_grad(ctx, C, H, dev(th))
+    torch.cuda.synchronize()
+    ctx.set_tile(12, 11, 3)
+    np.testing.assert_allclose(psi.cpu().numpy()[0], oracle.state(spec, th[0]), atol=S_TOL)
+    eo, go = oracle.energy_grad(spec, ham, th[0], "adjoint")
+    assert abs(e.item() - eo) < E_TOL
+    np.testing.assert_allclose(g.cpu().numpy()[0], go, atol=G_TOL)
+
+
 def test_batched_per_instance_hamiltonians(vqe, ctx):
     _say("batched hams")
     n, B = 8, 5
