@@ -119,6 +119,15 @@ static_assert(sizeof(StageOp) == 48, "StageOp layout");
 // bit's gates are undone one by one (gradient term, then U^dagger on psi
 // and lambda), after the network that precedes them in the reversed order
 // has been applied by the previous stage's store map.
+//
+// A stage may also apply the chain of one more qubit, the tile bit
+// cpos[4] (xbit = 1): the threads are ordered so that thread bit 4 is that
+// tile bit, and after the register chains the 16-lane row swap of gfx950
+// exchanges register bit nb-1 with it, so its pairs sit in registers.  The
+// stage then stores through its map (perm = 1), and lr / lc describe the
+// layout after the exchange: register bit nb-1 is the tile bit cpos[4], and
+// thread bit 4 is rpos[nb-1].  Every stage owns nb + 1 slots (the last for
+// the exchanged qubit's chain, empty without one).
 struct FusedStage {
     uint8_t rpos[4];
     uint8_t cpos[12];    // the other tile bits, ascending (sub-cube index bits)
@@ -131,8 +140,10 @@ struct FusedStage {
     int32_t slot;        // gate list of register bit j: slot + j
     int32_t nb;          // register bits: 4 (forward stages) or 3 (adjoint stages)
     int32_t phase_begin, phase_count;  // parity phases applied after the 2x2s, before the store
+    int32_t xbit;        // 1: the chain of tile bit cpos[4] too, through the row swap
 };
-static_assert(sizeof(FusedStage) == 104, "FusedStage layout");
+static_assert(sizeof(FusedStage) == 108, "FusedStage layout");
+constexpr int kXLane = 4;  // the thread bit the row swap exchanges (lanes l and l ^ 16)
 
 // An RZ met after the network had touched its qubit t: with the network so
 // far as w = L v ^ c, RZ on w_t is, in the stage's own index frame v, the

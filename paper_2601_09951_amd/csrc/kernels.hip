@@ -295,6 +295,24 @@ __device__ __forceinline__ double swap16_sum(double v)
     return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
 }
 
+// The 16-lane row swap on a pair of values: lanes l with bit 4 set take b
+// of lane l ^ 16 into a, lanes with it clear hand their a to lane l ^ 16's
+// b.  On the register pair x[i], x[i | M] (register bit M clear / set) this
+// exchanges register bit M with thread bit 4.
+__device__ __forceinline__ void row_swap16(double &a, double &b)
+{
+    const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)__double2loint(a), (unsigned)__double2loint(b), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)__double2hiint(a), (unsigned)__double2hiint(b), false, false);
+    a = __hiloint2double((int)hi[0], (int)lo[0]);
+    b = __hiloint2double((int)hi[1], (int)lo[1]);
+}
+
+__device__ __forceinline__ void row_swap16(double2 &a, double2 &b)
+{
+    row_swap16(a.x, b.x);
+    row_swap16(a.y, b.y);
+}
+
 __device__ __forceinline__ double swap32_sum(double v)
 {
     const unsigned lo = __double2loint(v), hi = __double2hiint(v);
@@ -1237,7 +1255,8 @@ __device__ __forceinline__ void apply_phases(double2 (&x)[N], const PhaseL *phl,
 __device__ __forceinline__ bool network_only(const FusedStage &fs)
 {
     return __builtin_amdgcn_readfirstlane((uint32_t)fs.na) == 0 &&
-           __builtin_amdgcn_readfirstlane((uint32_t)fs.phase_count) == 0;
+           __builtin_amdgcn_readfirstlane((uint32_t)fs.phase_count) == 0 &&
+           __builtin_amdgcn_readfirstlane((uint32_t)fs.xbit) == 0;
 }
 
 __device__ __forceinline__ void network_columns(const FusedStage &fs, int k, uint32_t *mcol)
@@ -1332,10 +1351,14 @@ __device__ __forceinline__ void tile_in2_net(double2 *ta, double2 *tb, const dou
         }
 }
 
-template <int NA, bool PERM, bool PH>
+// XB: the stage's qubit on thread bit 4 (tile bit cpos[4]) is exchanged
+// into register bit 3 after the register chains and takes its chain there
+// (fm[4]); the store then follows the exchanged layout (PERM).
+template <int NA, bool PERM, bool PH, bool XB = false>
 __device__ __forceinline__ void fused_stage(double2 *tile, const FusedStage &fs, const Mat2 *fm, int nsub,
                                             uint32_t ctile, const PhaseL *phl, int nph, uint32_t sub)
 {
+    static_assert(!XB || (NA == 4 && PERM), "the exchange follows four register chains and stores through the map");
     const bool have = (int)threadIdx.x < nsub;
     const uint32_t sbl = sub & 0xFFFFu, slbl = sub >> 16;
     uint32_t roff[16], sro[16];
@@ -1355,8 +1378,20 @@ __device__ __forceinline__ void fused_stage(double2 *tile, const FusedStage &fs,
         if (NA > 1) fused_bit<1>(x, fm[1]);
         if (NA > 2) fused_bit<2>(x, fm[2]);
         if (NA > 3) fused_bit<3>(x, fm[3]);
-        if (PH) apply_phases<16>(x, phl, nph, swz(sbl), roff);  // swz is its own inverse
     }
+    uint32_t bl = swz(sbl);  // swz is its own inverse
+    if (XB) {
+        // every lane takes part (threads with and without sub-cubes pair
+        // among themselves: the sub-cube count is a multiple of 32)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) row_swap16(x[i], x[i + 8]);
+        if (have) fused_bit<3>(x, fm[4]);
+        const uint32_t d = (1u << fs.rpos[3]) ^ (1u << fs.cpos[kXLane]);  // the exchanged tile bits
+        if ((threadIdx.x >> kXLane) & 1u) bl ^= d;
+#pragma unroll
+        for (int i = 8; i < 16; ++i) roff[i] ^= d;
+    }
+    if (PH && have) apply_phases<16>(x, phl, nph, bl, roff);
     if (PERM) {
         lds_barrier();  // every sub-cube is read before any amplitude moves
         if (have) {
@@ -1392,8 +1427,8 @@ __global__ __launch_bounds__(kThreads) void k_forward_fused(const TileGeom *__re
     const int slot0 = nstages ? fstages[0].slot : 0;
     const double2 *F = fused + ((size_t)blockIdx.y * n_slots + slot0) * 4;
     double2 *fmd = reinterpret_cast<double2 *>(fm);
-    for (int i = tid; i < 16 * nstages; i += kThreads) fmd[i] = F[i];  // 4 double2 per matrix
-    PhaseL *phl = reinterpret_cast<PhaseL *>(fm + 4 * nstages);
+    for (int i = tid; i < 20 * nstages; i += kThreads) fmd[i] = F[i];  // 5 slots per stage, 4 double2 each
+    PhaseL *phl = reinterpret_cast<PhaseL *>(fm + 5 * nstages);
     const double2 *Mx = mats + (size_t)blockIdx.y * n_gates * 4;
     for (int i = tid; PH && i < nph; i += kThreads) {
         const FusedPhase f = fphases[ph0 + i];
@@ -1431,9 +1466,14 @@ __global__ __launch_bounds__(kThreads) void k_forward_fused(const TileGeom *__re
                 const FusedCond fc = fconds[fs.cond_begin + q];
                 if ((base & fc.cmo) == fc.cvo) ctile ^= fc.xmask;
             }
-            const Mat2 *m4 = fm + 4 * s;
+            const Mat2 *m4 = fm + 5 * s;
             const PhaseL *sp = phl + (fs.phase_begin - ph0);
             const int np = fs.phase_count;
+            if (__builtin_amdgcn_readfirstlane((uint32_t)fs.xbit)) {
+                fused_stage<4, true, PH, true>(tile, fs, m4, nsub, ctile, sp, np, sub);
+                lds_barrier();
+                continue;
+            }
             switch (na * 2 + perm) {
             case 0: fused_stage<0, false, PH>(tile, fs, m4, nsub, ctile, sp, np, sub); break;
             case 1: fused_stage<0, true, PH>(tile, fs, m4, nsub, ctile, sp, np, sub); break;
@@ -1572,15 +1612,18 @@ __device__ __forceinline__ void rbit_step(double2 (&x)[8], double2 (&l)[8], cons
     }
 }
 
-template <int NA, bool PERM, bool PH>
+// XB as in fused_stage: the qubit on thread bit 4 is exchanged into register
+// bit 2 of both states and undone there (wm[3], sums under qidx[3]).
+template <int NA, bool PERM, bool PH, bool XB = false>
 __device__ __forceinline__ void rev_fused_stage(double2 *tp, double2 *tl, const FusedStage &fs, const Mat2 *wm,
                                                 const int32_t *qidx, int nsub, uint32_t ctile, double *red,
                                                 const PhaseL *phl, int nph, double *phred, uint32_t sub)
 {
+    static_assert(!XB || (NA == 3 && PERM), "the exchange follows three register chains and stores through the map");
     const bool have = (int)threadIdx.x < nsub;
     // sub = swz(bl) | swz(lbl) << 16 (build_fsub); addresses are these xor a uniform term
     const uint32_t sbl = sub & 0xFFFFu, slbl = sub >> 16;
-    const uint32_t bl = PH ? swz(sbl) : 0u;  // swz is its own inverse
+    uint32_t bl = PH ? swz(sbl) : 0u;  // swz is its own inverse
     uint32_t roff[8], sro[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -1600,6 +1643,18 @@ __device__ __forceinline__ void rev_fused_stage(double2 *tp, double2 *tl, const 
     if (NA > 0) rbit_step<0>(x, l, wm[0], (int)__builtin_amdgcn_readfirstlane((uint32_t)qidx[0]), red, have);
     if (NA > 1) rbit_step<1>(x, l, wm[1], (int)__builtin_amdgcn_readfirstlane((uint32_t)qidx[1]), red, have);
     if (NA > 2) rbit_step<2>(x, l, wm[2], (int)__builtin_amdgcn_readfirstlane((uint32_t)qidx[2]), red, have);
+    if (XB) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            row_swap16(x[i], x[i + 4]);
+            row_swap16(l[i], l[i + 4]);
+        }
+        rbit_step<2>(x, l, wm[3], (int)__builtin_amdgcn_readfirstlane((uint32_t)qidx[3]), red, have);
+        const uint32_t d = (1u << fs.rpos[2]) ^ (1u << fs.cpos[kXLane]);  // the exchanged tile bits
+        if (PH && ((threadIdx.x >> kXLane) & 1u)) bl ^= d;
+#pragma unroll
+        for (int i = 4; i < 8; ++i) roff[i] ^= d;
+    }
     if (PH) {
         // parity phases: every gradient term is (-1)^{parity} Im(conj(lam) psi)
         // summed over the sub-cube (diagonal phases leave Im(conj(lam) psi)
@@ -1666,7 +1721,7 @@ __global__ __launch_bounds__(kThreads) void k_reverse_fused(
     double2 *tp = reinterpret_cast<double2 *>(smem);
     double2 *tl = tp + (1u << k);
     uint64_t *hoff = reinterpret_cast<uint64_t *>(smem + (32u << k));
-    const int ns = 3 * nstages;
+    const int ns = 4 * nstages;  // slots: three register bits and the exchanged qubit per stage
     Mat2 *wm = reinterpret_cast<Mat2 *>(hoff + (1u << (k - c)));
     PhaseL *phl = reinterpret_cast<PhaseL *>(wm + ns);
     double *phred = reinterpret_cast<double *>(phl + nph);  // 4 per phase
@@ -1726,10 +1781,15 @@ __global__ __launch_bounds__(kThreads) void k_reverse_fused(
                 const FusedCond fc = fconds[fs.cond_begin + q];
                 if ((base & fc.cmo) == fc.cvo) ctile ^= fc.xmask;
             }
-            const Mat2 *w3 = wm + 3 * s;
-            const int32_t *q3 = qidx + 3 * s;
+            const Mat2 *w3 = wm + 4 * s;
+            const int32_t *q3 = qidx + 4 * s;
             const PhaseL *sp = phl + (fs.phase_begin - ph0);
             const int np = fs.phase_count;
+            if (__builtin_amdgcn_readfirstlane((uint32_t)fs.xbit)) {
+                rev_fused_stage<3, true, PH, true>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred, sub);
+                lds_barrier();
+                continue;
+            }
             switch (na * 2 + perm) {
             case 0: rev_fused_stage<0, false, PH>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred, sub); break;
             case 1: rev_fused_stage<0, true, PH>(tp, tl, fs, w3, q3, nsub, ctile, red, sp, np, phred, sub); break;
@@ -2524,14 +2584,14 @@ hipError_t launch_adjoint_coefs(const int32_t *slot_off, const int32_t *slot_gat
 
 size_t reverse_fused_lds(int k, int c, int nstages, int n_qslots, int n_phases)
 {
-    const size_t ns = 3 * (size_t)nstages;
+    const size_t ns = 4 * (size_t)nstages;
     return (32u << k) + (8u << (k - c)) + ns * sizeof(Mat2) + (size_t)n_phases * (sizeof(PhaseL) + 32) +
            4 * ((ns + 1) & ~(size_t)1) + 96 * (size_t)n_qslots + 64;  // + network columns
 }
 
 size_t forward_fused_lds(int k, int c, int nstages, int n_phases)
 {
-    return (16u << k) + (8u << (k - c)) + (size_t)nstages * 4 * sizeof(Mat2) + (size_t)n_phases * sizeof(PhaseL) +
+    return (16u << k) + (8u << (k - c)) + (size_t)nstages * 5 * sizeof(Mat2) + (size_t)n_phases * sizeof(PhaseL) +
            64;  // + network columns
 }
 
@@ -2544,7 +2604,7 @@ hipError_t launch_reverse_fused(const PassPlan &pp, const TileGeom *geom_dev, co
                                 int n_pgates, const uint32_t *fsub, int fsub_n, hipStream_t s)
 {
     const TileGeom &g = pp.geom;
-    if (g.k < 8 || g.k > 11 || slot0 < 0 || slot0 + 3 * pp.fstage_count > n_slots) return hipErrorInvalidValue;
+    if (g.k < 8 || g.k > 11 || slot0 < 0 || slot0 + 4 * pp.fstage_count > n_slots) return hipErrorInvalidValue;
     if (!fsub || fsub_n != (1 << (g.k - 3))) return hipErrorInvalidValue;
     if (!slot_q || (pp.fphase_count > 0 && !phase_q)) return hipErrorInvalidValue;
     const int64_t tiles = 1ll << g.nout;

@@ -189,7 +189,7 @@ static void number_param_slots(CircPlan *plan)
         if (pp.fstage_count == 0) continue;
         const FusedStage &f0 = plan->host_fstages[pp.fstage_begin];
         int nq = 0;
-        for (int i = 0; i < f0.nb * pp.fstage_count; ++i) {
+        for (int i = 0; i < (f0.nb + 1) * pp.fstage_count; ++i) {
             const int sl = f0.slot + i;
             bool par = false;
             for (int e = plan->host_fslot_off[sl]; e < plan->host_fslot_off[sl + 1]; ++e)
@@ -250,12 +250,10 @@ static void build_fsub(CircPlan *plan, int keff)
     plan->host_fsub.resize(plan->host_fstages.size() * (size_t)nsub);
     for (size_t st = 0; st < plan->host_fstages.size(); ++st) {
         const FusedStage &fs = plan->host_fstages[st];
-        uint32_t pos[4];
-        for (int i = 0; i < nb; ++i) pos[i] = fs.rpos[i];
-        std::sort(pos, pos + nb);
         for (int u = 0; u < nsub; ++u) {
-            uint32_t bl = (uint32_t)u;
-            for (int i = 0; i < nb; ++i) bl = ((bl >> pos[i]) << (pos[i] + 1)) | (bl & ((1u << pos[i]) - 1u));
+            uint32_t bl = 0;  // thread bit j is tile bit cpos[j]
+            for (int j = 0; j < keff - nb; ++j)
+                if ((u >> j) & 1) bl |= 1u << fs.cpos[j];
             uint32_t lbl = 0;
             for (int j = 0; j < 12; ++j)
                 if ((u >> j) & 1) lbl ^= fs.lc[j];
@@ -323,52 +321,67 @@ static bool build_fused(const Circ *C, const std::vector<int> &take, const std::
         }
         bool ident = c0 == 0 && conds.empty();
         for (int b = 0; b < keff; ++b) ident = ident && col[b] == (1u << b);
-        // stages of up to four gathered qubits; the network rides on the last
-        const size_t ngroups = std::max<size_t>(1, (order.size() + RB - 1) / RB);
+        // stages of up to RB gathered qubits in registers and, when the tile
+        // has more than kXLane thread bits, one more exchanged into registers
+        // by the row swap (thread bit kXLane); the network rides on the last
+        const size_t cap = RB + (keff - RB > kXLane ? 1 : 0);
+        const size_t ngroups = std::max<size_t>(1, (order.size() + cap - 1) / cap);
         for (size_t gi = 0; gi < ngroups; ++gi) {
             FusedStage fs;
             std::memset(&fs, 0, sizeof(fs));
-            std::vector<int> act(order.begin() + std::min(order.size(), RB * gi),
-                                 order.begin() + std::min(order.size(), RB * gi + RB));
+            std::vector<int> act(order.begin() + std::min(order.size(), cap * gi),
+                                 order.begin() + std::min(order.size(), cap * gi + cap));
+            const int xq = act.size() > RB ? act[RB] : -1;
+            if (xq >= 0) act.pop_back();
             uint32_t R = 0;
             for (int b : act) R |= 1u << b;
             std::vector<int> rb = act;
             for (int b = 0; b < keff && (int)rb.size() < RB; ++b)
-                if (!((R >> b) & 1)) {
+                if (!((R >> b) & 1) && b != xq) {
                     R |= 1u << b;
                     rb.push_back(b);
                 }
             std::vector<int> cb;
             for (int b = 0; b < keff; ++b)
-                if (!((R >> b) & 1)) cb.push_back(b);
+                if (!((R >> b) & 1) && b != xq) cb.push_back(b);
+            if (xq >= 0) cb.insert(cb.begin() + kXLane, xq);  // thread bit kXLane
             for (int i = 0; i < RB; ++i) fs.rpos[i] = (uint8_t)rb[i];
             fs.nb = RB;
             for (size_t j = 0; j < cb.size(); ++j) fs.cpos[j] = (uint8_t)cb[j];
             fs.na = (int)act.size();
+            fs.xbit = xq >= 0;
             fs.slot = plan->n_fslots();
-            for (int i = 0; i < RB; ++i) {  // per register bit: its gates in order (empty past na)
-                if (i < fs.na)
-                    for (int g : oneq[rb[i]]) {
+            for (int i = 0; i <= RB; ++i) {  // per register bit, then the exchanged qubit: its gates in order
+                const int qb = i < RB ? (i < fs.na ? rb[i] : -1) : xq;
+                if (qb >= 0)
+                    for (int g : oneq[qb]) {
                         plan->host_fslot_gate.push_back(g);
                         const GateHost &h = C->gates[g];
                         plan->host_fslot_info.push_back(((C->pgate_of_gate[g] + 1) << 4) | (h.cls << 2) | h.gen);
                     }
                 plan->host_fslot_off.push_back((int32_t)plan->host_fslot_gate.size());
             }
+            // the tile bit of register bit j and of thread bit j as stored
+            // (after the exchange when the stage has one)
+            auto reg_bit = [&](int j) { return fs.xbit && j == RB - 1 ? xq : rb[j]; };
+            auto thr_bit = [&](int j) { return fs.xbit && j == kXLane ? rb[RB - 1] : cb[j]; };
             const bool last = gi + 1 == ngroups;
-            if (last && !ident) {
+            const bool net = last && !ident;
+            fs.cond_begin = (int)plan->host_fconds.size();
+            if (net || fs.xbit) {
                 fs.perm = 1;
-                fs.c0 = (uint16_t)c0;
                 for (int i = 0; i < (1 << RB); ++i) {
                     uint32_t v = 0;
                     for (int j = 0; j < RB; ++j)
-                        if ((i >> j) & 1) v ^= col[rb[j]];
+                        if ((i >> j) & 1) v ^= net ? col[reg_bit(j)] : 1u << reg_bit(j);
                     fs.lr[i] = (uint16_t)v;
                 }
-                for (size_t j = 0; j < cb.size(); ++j) fs.lc[j] = (uint16_t)col[cb[j]];
-                fs.cond_begin = (int)plan->host_fconds.size();
-                fs.cond_count = (int)conds.size();
-                for (const FusedCond &f : conds) plan->host_fconds.push_back(f);
+                for (size_t j = 0; j < cb.size(); ++j) fs.lc[j] = (uint16_t)(net ? col[thr_bit((int)j)] : 1u << thr_bit((int)j));
+                if (net) {
+                    fs.c0 = (uint16_t)c0;
+                    fs.cond_count = (int)conds.size();
+                    for (const FusedCond &f : conds) plan->host_fconds.push_back(f);
+                }
             } else {
                 for (int i = 0; i < (1 << RB); ++i) {
                     uint32_t v = 0;
@@ -377,7 +390,6 @@ static bool build_fused(const Circ *C, const std::vector<int> &take, const std::
                     fs.lr[i] = (uint16_t)v;
                 }
                 for (size_t j = 0; j < cb.size(); ++j) fs.lc[j] = (uint16_t)(1u << cb[j]);
-                fs.cond_begin = (int)plan->host_fconds.size();
             }
             plan->host_fstages.push_back(fs);
         }

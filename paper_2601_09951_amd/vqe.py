@@ -510,7 +510,7 @@ _SOP = np.dtype([("cmo", "<u8"), ("cvo", "<u8"), ("cmt", "<u4"), ("cvt", "<u4"),
                  ("cls", "u1"), ("gen", "u1"), ("pad", "u1"), ("amask", "<u2"), ("pad2", "<u2", 3)])
 _FSTAGE = np.dtype([("rpos", "u1", 4), ("cpos", "u1", 12), ("lr", "<u2", 16), ("lc", "<u2", 12), ("c0", "<u2"),
                     ("perm", "<u2"), ("na", "<i4"), ("cond_begin", "<i4"), ("cond_count", "<i4"), ("slot", "<i4"),
-                    ("nb", "<i4"), ("phase_begin", "<i4"), ("phase_count", "<i4")])
+                    ("nb", "<i4"), ("phase_begin", "<i4"), ("phase_count", "<i4"), ("xbit", "<i4")])
 _FCOND = np.dtype([("cmo", "<u8"), ("cvo", "<u8"), ("xmask", "<u4"), ("pad", "<u4")])
 _FPHASE = np.dtype([("mask", "<u4"), ("cbit", "<u4"), ("gate", "<i4"), ("info", "<i4")])
 _OP = np.dtype([("m", "<u4"), ("fixed_bits", "<u4"), ("cmask_out", "<u8"), ("cval_out", "<u8"),

@@ -374,6 +374,38 @@ def _parity(v):
     return out
 
 
+X_LANE = 4  # the thread bit the row swap exchanges with the top register bit
+
+
+def _exchange(A, nb):
+    """The row swap of an exchanged-qubit stage on [tiles, threads, registers]
+    data: the element at thread u, register i moves to the thread and
+    register with bit 4 of u and bit nb - 1 of i swapped."""
+    U, R = A.shape[1], A.shape[2]
+    u = np.arange(U)[:, None]
+    i = np.arange(R)[None, :]
+    ub, ib = (u >> X_LANE) & 1, (i >> (nb - 1)) & 1
+    su = (u & ~(1 << X_LANE)) | (ib << X_LANE)
+    si = (i & ~(1 << (nb - 1))) | (ub << (nb - 1))
+    return A[:, su, si]
+
+
+def _chain(mats, soff, sgate, slot):
+    F = np.eye(2, dtype=complex)
+    for e in range(int(soff[slot]), int(soff[slot + 1])):
+        F = mats[int(sgate[e])] @ F
+    return F
+
+
+def _apply_bit(X, F, j, nb):
+    M = 1 << j
+    lo = [i for i in range(1 << nb) if not (i & M)]
+    hi = [i | M for i in lo]
+    a, b = X[:, :, lo].copy(), X[:, :, hi].copy()
+    X[:, :, lo] = F[0, 0] * a + F[0, 1] * b
+    X[:, :, hi] = F[1, 0] * a + F[1, 1] * b
+
+
 def forward_fused(passes, ops, fstages, fconds, soff, sgate, psi, mats, phases=()):
     """Forward passes with fused stages where the plan has them (one fused
     2x2 per active register bit, then the stage's parity phases: the gate's
@@ -403,15 +435,12 @@ def forward_fused(passes, ops, fstages, fconds, soff, sgate, psi, mats, phases=(
             sidx = bl[:, None] | roff[None, :]
             X = T[:, sidx]  # [tiles, sub-cubes, 16]
             for j in range(na):
-                F = np.eye(2, dtype=complex)
-                slot = int(fs["slot"]) + j
-                for e in range(int(soff[slot]), int(soff[slot + 1])):
-                    F = mats[int(sgate[e])] @ F
-                M = 1 << j
-                lo = [i for i in range(16) if not (i & M)]
-                a, b = X[:, :, lo].copy(), X[:, :, [i | M for i in lo]].copy()
-                X[:, :, lo] = F[0, 0] * a + F[0, 1] * b
-                X[:, :, [i | M for i in lo]] = F[1, 0] * a + F[1, 1] * b
+                _apply_bit(X, _chain(mats, soff, sgate, int(fs["slot"]) + j), j, 4)
+            if int(fs["xbit"]):  # the qubit on thread bit 4, exchanged into register bit 3
+                assert na == 4 and int(fs["perm"]) and k - 4 > X_LANE
+                X = _exchange(X, 4)
+                sidx = _exchange(sidx[None], 4)[0]
+                _apply_bit(X, _chain(mats, soff, sgate, int(fs["slot"]) + 4), 3, 4)
             for ph in phases[int(fs["phase_begin"]):int(fs["phase_begin"]) + int(fs["phase_count"])]:
                 U = mats[int(ph["gate"])]
                 assert abs(U[0, 1]) == 0 and abs(U[1, 0]) == 0, "a parity phase must come from a diagonal gate"
@@ -484,11 +513,18 @@ def reverse_fused(passes, ops, fstages, fconds, soff, sgate, sinfo, psi, lam, ma
                 bl |= ((u >> j) & 1) << p
             sidx = bl[:, None] | roff[None, :]
             X, L = TP[:, sidx], TL[:, sidx]
-            for j in range(na):
+            xb = int(fs["xbit"])
+            assert not xb or (na == 3 and int(fs["perm"]) and k - nb > X_LANE)
+            for jj in range(na + xb):
+                j = jj
+                if jj == 3:  # the qubit on thread bit 4, exchanged into register bit 2
+                    X, L = _exchange(X, nb), _exchange(L, nb)
+                    sidx = _exchange(sidx[None], nb)[0]
+                    j = 2
                 M = 1 << j
                 lo = [i for i in range(1 << nb) if not (i & M)]
                 hi = [i | M for i in lo]
-                slot = int(fs["slot"]) + j
+                slot = int(fs["slot"]) + jj
                 if method == "coef":
                     a, b, la, lb = X[:, :, lo], X[:, :, hi], L[:, :, lo], L[:, :, hi]
                     q0 = (np.conj(la) * a).imag.sum() - (np.conj(lb) * b).imag.sum()
