@@ -322,6 +322,33 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def fused_pass_flops(ctx, vqe, C, n):
+    """FP64 flops of one evaluation's fused passes, from the plan (FMA = 2):
+    forward, per stage and chain (register chains and the exchanged qubit) a
+    2x2 on every pair, 16 flops per amplitude, and 6 per amplitude for each
+    parity phase; adjoint, the 2x2 on both states (32 per amplitude) plus,
+    for a chain with parametric gates, its three pair sums (12), and for a
+    phase 12 (both states) plus 4 when it is parametric.  Returns (forward
+    flops, adjoint flops) per evaluation."""
+    out = []
+    for rev in (False, True):
+        passes, _, fst, _, soff, _, sinfo, fph = vqe.circuit_plan(ctx, C, reverse=rev, stages="fused")
+        flops = 0.0
+        for p in passes:
+            for s in range(int(p["fstage_begin"]), int(p["fstage_begin"]) + int(p["fstage_count"])):
+                f = fst[s]
+                nb = int(f["nb"])
+                chains = list(range(int(f["na"]))) + ([nb] if int(f["xbit"]) else [])
+                for j in chains:
+                    sl = int(f["slot"]) + j
+                    par = any(int(sinfo[e]) >= 16 for e in range(int(soff[sl]), int(soff[sl + 1])))
+                    flops += (32 + (12 if par else 0)) if rev else 16
+                for q in range(int(f["phase_begin"]), int(f["phase_begin"]) + int(f["phase_count"])):
+                    flops += (12 + (4 if int(fph[q]["info"]) >= 16 else 0)) if rev else 6
+        out.append(flops * (1 << n))
+    return out[0], out[1]
+
+
 def hea_measure(ctx, vqe, synth, torch, n):
     """Energy + adjoint gradient of the hardware-efficient ansatz (L = n
     layers, 500 random Pauli strings) at n qubits, then the same calls again
@@ -378,6 +405,16 @@ def hea_measure(ctx, vqe, synth, torch, n):
                                                              "k_pauli_sweep") else None
         kernels[name]["traffic_bytes_per_launch"] = tb
         kernels[name]["traffic_over_algorithmic"] = round(tb / (r["bytes"] / r["launches"]), 4) if tb else None
+    # FP64 rate of the fused passes (their other bound: arithmetic per
+    # amplitude with the tile held on chip)
+    ff, fr = fused_pass_flops(ctx, vqe, C, n)
+    for name, fl in (("k_forward_fused", ff), ("k_reverse_fused", fr)):
+        if name in kernels:
+            kk = kernels[name]
+            per_launch = fl / (kk["launches_per_eval"] / (2 if name == "k_forward_fused" else 1))
+            kk["fp64_flops_per_launch"] = int(per_launch)
+            kk["fp64_tflops"] = round(per_launch / (kk["avg_us"] * 1e-6) / 1e12, 2)
+            kk["frac_of_fp64"] = round(kk["fp64_tflops"] / FP64_PEAK_TFLOPS, 4)
     passes, _ = vqe.circuit_plan(ctx, C)
     pl = vqe.hamiltonian_plan(ctx, H, 1, False)
     del ws
