@@ -2266,6 +2266,30 @@ __global__ __launch_bounds__(kThreads) void k_hpsi_gather(
             const int tb = to[gd.ugroup * 3 + 0], tm = to[gd.ugroup * 3 + 1], te = to[gd.ugroup * 3 + 2];
             if (te == tb) continue;
             const uint32_t f = gd.floc, pv = gd.pivot;
+            if (staged && f != 0 && te - tb == 1) {
+                // a single term (most flip groups of a random Pauli sum): its
+                // signed weight times the partner, no weight sums
+                const int i = tb - tstart;
+                const uint32_t z = __builtin_amdgcn_readfirstlane(zl[i]);
+                const double w = wl[i];
+                const bool re = tm > tb;  // real: A = +-w; imaginary: B = +-w
+#pragma unroll
+                for (int r = 0; r < NO; ++r) {
+                    const uint32_t o = (uint32_t)(tid + r * kThreads);
+                    const uint32_t piv = (o >> pv) & 1u;
+                    const double2 x = tp[o ^ f];
+                    const double v = signed_by_parity(w, z & (piv ? o ^ f : o));
+                    if (re) {
+                        acc[r].x = fma(v, x.x, acc[r].x);
+                        acc[r].y = fma(v, x.y, acc[r].y);
+                    } else {
+                        const double b = signed_by_parity(v, piv ^ 1u);  // -B below the pivot
+                        acc[r].x = fma(-b, x.y, acc[r].x);
+                        acc[r].y = fma(b, x.x, acc[r].y);
+                    }
+                }
+                continue;
+            }
             uint32_t pr[NO];
             double A[NO], B[NO];
 #pragma unroll
