@@ -82,16 +82,18 @@ FIXED_WIRES = {"RX": 1, "RY": 1, "RZ": 1, "H": 1, "X": 1, "CNOT": 2, "CZ": 2, "S
                "DoubleExcitation": 4}
 
 
-def eval_flops(spec, n_groups, complex_table):
+def eval_flops(spec, n_groups, complex_table, real_state=False):
     """Algorithmic FP64 flops of one energy + adjoint-gradient evaluation with
     H held as XOR-offset diagonals (lambda[b] = sum_f D_f[b] psi[b ^ f]; the
     diagonals are built once per Hamiltonian and reused by every iteration).
 
-    gates: 12 flops per active amplitude pair for rotations, 8 for H, 0 for
-    permutations; H psi: 4 flops per amplitude per flip group (real
-    diagonals; 8 when complex); E = Re<psi|lambda>: 4 per amplitude; reverse
-    sweep: the gates twice (psi and lambda) plus 7 flops per active pair of
-    every parametric gate.
+    Complex amplitudes: gates 12 flops per active amplitude pair for
+    rotations, 8 for H, 0 for permutations; H psi 4 flops per amplitude per
+    flip group (real diagonals; 8 when complex); E = Re<psi|lambda> 4 per
+    amplitude; the reverse sweep the gates twice (psi and lambda) plus 7 flops
+    per active pair of every parametric gate.  A state that stays real (real
+    gate matrices, a real Hamiltonian) needs half of that for the gates, H psi
+    and E, and 3 flops per pair for a gradient partial.
     """
     n = spec.n
     D = 1 << n
@@ -99,11 +101,11 @@ def eval_flops(spec, n_groups, complex_table):
     grad = 0
     for k, p in zip(spec.kinds, spec.param_idx):
         pairs = D >> FIXED_WIRES[k]
-        fwd += GATE_FLOPS_PER_PAIR[k] * pairs
+        fwd += GATE_FLOPS_PER_PAIR[k] * pairs // (2 if real_state else 1)
         if p >= 0:
-            grad += 7 * pairs
-    hpsi = D * n_groups * (8 if complex_table else 4)
-    energy = 4 * D
+            grad += (3 if real_state else 7) * pairs
+    hpsi = D * n_groups * (8 if complex_table else 4) // (2 if real_state else 1)
+    energy = (2 if real_state else 4) * D
     return fwd + hpsi + energy + 2 * fwd + grad
 
 
@@ -240,7 +242,8 @@ def main():
     x, z, c = p8["hams"][0].terms()
     n_groups = len(set(int(v) for v in x))
     complex_table = bool(np.any(_odd_y(x, z)))
-    flops_eval = eval_flops(p8["spec"], n_groups, complex_table)
+    real_state = not complex_table and set(p8["spec"].kinds) <= synth.REAL_KINDS
+    flops_eval = eval_flops(p8["spec"], n_groups, complex_table, real_state)
     flops_launch = flops_eval * BATCH * ITERS
     achieved = flops_launch / (kernel_ms[8] * 1e-3) / 1e12
     flops_scope = scope_table_flops(p8["spec"], len(c))
@@ -251,8 +254,9 @@ def main():
                 "achieved": round(achieved, 4), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP64_PEAK_TFLOPS, 5),
                 "traffic": measured_traffic("k_small_fast"),
-                "flops_per_eval": flops_eval, "flops_count": "grouped: H held as XOR-offset diagonals, active "
-                                                             "pairs only (eval_flops)",
+                "flops_per_eval": flops_eval,
+                "flops_count": "grouped: H held as XOR-offset diagonals, active pairs only (eval_flops)"
+                               + ("; real amplitudes (real gates, real Hamiltonian)" if real_state else ""),
                 "evals_per_launch": BATCH * ITERS, "kernel_ms": round(kernel_ms[8], 4),
                 "scope_table_count": {"flops_per_eval": flops_scope, "achieved": round(achieved_scope, 4),
                                       "frac": round(achieved_scope / FP64_PEAK_TFLOPS, 5),

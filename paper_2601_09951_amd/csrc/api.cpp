@@ -1989,10 +1989,14 @@ int vqe_run(vqe_ctx_t ctx, vqe_circ_t circ, int n_hams, const vqe_ham_t *hams, i
         size_t lds = 0;
         int max_pairs = 1;
         for (const OpDesc &o : fp->host_ops) max_pairs = std::max(max_pairs, 1 << (n - o.nfix));
+        int real_gates = 1;  // RX and RZ are the only kinds with complex entries
+        for (const GateHost &h : circ->gates)
+            if (h.kind == VQE_GATE_RX || h.kind == VQE_GATE_RZ) real_gates = 0;
         if (fp->passes.size() == 1 && rp->passes.size() == 1 && pp->sweeps.size() == 1 &&
             fp->passes[0].op_count == G && rp->passes[0].op_count == G &&
             pp->sweeps[0].grp_count == NU && same_pairs(fp, rp, G) &&
-            small_run_plan(n, G, P, circ->n_pgates, NU, max_inst_terms, has_imag, max_pairs, &mode, &lds)) {
+            small_run_plan(n, G, P, circ->n_pgates, NU, max_inst_terms, has_imag, real_gates, max_pairs, &mode,
+                           &lds)) {
             SmallRunArgs a;
             a.n = n;
             a.n_gates = G;

@@ -634,13 +634,16 @@ struct SmallRunArgs {
     int shared_ham;
     double *theta;                 // [B][P]
     double *energies;              // [B][iters+1]
-    double2 *hist;                 // [B][n_gates + 1][slots][64][2] pair values after each gate (fast loop)
+    double2 *hist;                 // [B][n_gates + 1][slots][64][2] pair values after each gate (fast loop;
+                                   // a real state packs real values at the same indices)
 };
 hipError_t launch_small_run(const SmallRunArgs &a, const OpDesc *rops, const int32_t *pmap_off,
                             const int32_t *pmap_idx, int n_pgates, int mode, int max_inst_terms, int max_pairs,
                             int64_t batch, hipStream_t s);
+// real_gates: every gate matrix is real for every angle (no RX, RZ), so with a
+// real Hamiltonian the state stays real and the loop runs on real amplitudes
 int small_run_plan(int n, int n_gates, int n_params, int n_pgates, int n_groups, int max_inst_terms,
-                   int has_imag, int max_pairs, int *mode_out, size_t *lds_out);
+                   int has_imag, int real_gates, int max_pairs, int *mode_out, size_t *lds_out);
 // name of the persistent kernel variant that launch_small_run runs (profiling records it)
 const char *small_run_variant(const SmallRunArgs &a, int mode, int max_pairs);
 size_t small_fast_hist_bytes(int n, int n_gates);  // per instance

@@ -17,6 +17,8 @@
 //    XOR-offset diagonal storage, built once per launch);
 //  * term form (when the table does not fit LDS): terms staged in LDS and
 //    summed per pair of each flip group.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace vqe {
@@ -573,15 +575,17 @@ __host__ __device__ inline FastLayout fast_layout(int n, int G, int P, int NPG, 
     return L;
 }
 
-// Register-held Hamiltonian rows: at 8 qubits with a real table of at most
+// Register-held Hamiltonian rows: at 8 qubits with a real state, at most
 // kRegGroups flip groups and at most 64 pairs per gate, one wave runs the
-// gate chains and four more waves run H psi, each thread keeping its amplitude's diagonal entries for all
-// groups in registers for the whole launch, so H psi reads only psi from LDS.
+// gate chains and four more waves run H psi, each thread keeping its
+// amplitude's diagonal entries for all groups in registers for the whole
+// launch, so H psi reads only psi from LDS.  (A complex state at 8 qubits
+// has a one-qubit RX or RZ, 128 pairs, so it never meets the pair limit.)
 constexpr int kRegGroups = 64;
 
-__host__ __device__ inline bool fast_regtab(int n, int NG, int complex_tab)
+__host__ __device__ inline bool fast_regtab(int n, int NG, bool real_state, int max_pairs)
 {
-    return n == 8 && !complex_tab && NG <= kRegGroups;
+    return n == 8 && real_state && NG <= kRegGroups && max_pairs <= 64;
 }
 
 __device__ __forceinline__ uint32_t ufirst(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -593,6 +597,27 @@ __device__ __forceinline__ double2 mac2(double2 u, double2 x, double2 v, double2
     const double i0 = fma(u.x, x.y, u.y * x.x), i1 = fma(v.x, y.y, v.y * y.x);
     return make_double2(r0 + r1, i0 + i1);
 }
+
+// the same with real amplitudes and real matrix entries (a state that stays
+// real: every gate matrix real for every angle, a real Hamiltonian)
+__device__ __forceinline__ double mac2(double u, double x, double v, double y) { return fma(u, x, v * y); }
+
+// amplitude helpers for the complex (double2) and the real (double) state
+__device__ __forceinline__ void amp_fma(double2 &acc, double d, double2 x)
+{
+    acc.x = fma(d, x.x, acc.x);
+    acc.y = fma(d, x.y, acc.y);
+}
+__device__ __forceinline__ void amp_fma(double &acc, double d, double x) { acc = fma(d, x, acc); }
+__device__ __forceinline__ double amp_add(double a, double b) { return a + b; }
+__device__ __forceinline__ double2 amp_add(double2 a, double2 b) { return cadd(a, b); }
+__device__ __forceinline__ double amp_dot(double2 x, double2 y) { return x.x * y.x + x.y * y.y; }  // Re x* y
+__device__ __forceinline__ double amp_dot(double x, double y) { return x * y; }
+__device__ __forceinline__ void amp_set(double2 &a, double v) { a = make_double2(v, 0.0); }
+__device__ __forceinline__ void amp_set(double &a, double v) { a = v; }
+// a gate matrix entry as the chain applies it (the real state takes the real part)
+__device__ __forceinline__ void mat_get(double2 &d, const double2 &m) { d = m; }
+__device__ __forceinline__ void mat_get(double &d, const double2 &m) { d = m.x; }
 
 constexpr uint32_t kNoPair = 0xFFFFu;
 
@@ -610,14 +635,14 @@ __device__ __forceinline__ void wave_lds_sync()
 // to at least 64 entries with kNoPair, so no lane needs a bound) and its
 // matrix; ops G.. are padding (no pairs, zero matrices), so the prefetch of
 // later ops needs no branch
-template <int SP>
+template <int SP, typename T>
 __device__ __forceinline__ void fast_tables(const uint16_t *pt, const double2 *mat, int q, int HP, int lane,
-                                            uint32_t (&pe)[SP], double2 (&u)[4])
+                                            uint32_t (&pe)[SP], T (&u)[4])
 {
 #pragma unroll
     for (int s = 0; s < SP; ++s) pe[s] = pt[q * HP + lane + 64 * s];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) u[k] = mat[4 * q + k];
+    for (int k = 0; k < 4; ++k) mat_get(u[k], mat[4 * q + k]);
 }
 
 // pair indices of a table entry; a lane without a pair works on its own two
@@ -643,32 +668,33 @@ __host__ __device__ constexpr int fast_slots(int n) { return n >= 8 ? 2 : 1; }
 // (op q in buffer q & 1): while op q computes, the pairs of op q + 1 are
 // already read and the tables of op q + 2 are on their way, so each op costs
 // one LDS read latency plus its arithmetic, and no value is moved between
-// registers (a move would have to wait for its load).
-template <int SP>
+// registers (a move would have to wait for its load).  T is the amplitude
+// type: double2, or double for a state that stays real.
+template <int SP, typename T>
 struct FastOp {
     uint32_t pe[SP];
-    double2 u[4];
+    T u[4];
     int2 info;
-    double2 x[SP], y[SP];  // the state on the pairs before the op
+    T x[SP], y[SP];  // the state on the pairs before the op
 };
 
 // psi on the lane's pairs after a gate (forward history, reverse sweep)
-template <int SP>
+template <int SP, typename T>
 struct FastHist {
-    double2 hx[SP], hy[SP];
+    T hx[SP], hy[SP];
 };
 
-template <int SP>
-__device__ __forceinline__ void fast_op_load(FastOp<SP> &o, const uint16_t *pt, const double2 *mat, const int2 *inf,
-                                             int q, int HP, int lane)
+template <int SP, typename T>
+__device__ __forceinline__ void fast_op_load(FastOp<SP, T> &o, const uint16_t *pt, const double2 *mat,
+                                             const int2 *inf, int q, int HP, int lane)
 {
     fast_tables<SP>(pt, mat, q, HP, lane, o.pe, o.u);
     o.info = inf[q];
 }
 
 // read the op's pairs of a state (psi forward, lambda reverse)
-template <int SP>
-__device__ __forceinline__ void fast_op_read(FastOp<SP> &o, const double2 *st, int D, int lane)
+template <int SP, typename T>
+__device__ __forceinline__ void fast_op_read(FastOp<SP, T> &o, const T *st, int D, int lane)
 {
     const bool two = SP > 1 && (ufirst((uint32_t)o.info.x) & kTwoSlots);
 #pragma unroll
@@ -683,18 +709,17 @@ __device__ __forceinline__ void fast_op_read(FastOp<SP> &o, const double2 *st, i
 
 // forward op: update the lane's pairs of psi and record them after the gate
 // in hist[gate][slot][lane] (global memory, off the chain)
-template <int SP>
-__device__ __forceinline__ void fast_fwd_step(const FastOp<SP> &o, double2 *psi, double2 *__restrict__ hist, int D,
-                                              int lane)
+template <int SP, typename T>
+__device__ __forceinline__ void fast_fwd_step(const FastOp<SP, T> &o, T *psi, T *__restrict__ hist, int D, int lane)
 {
     const bool two = SP > 1 && (ufirst((uint32_t)o.info.x) & kTwoSlots);
-    double2 *hq = hist + (size_t)ufirst((uint32_t)o.info.y) * (SP * 128) + 2 * lane;
+    T *hq = hist + (size_t)ufirst((uint32_t)o.info.y) * (SP * 128) + 2 * lane;
 #pragma unroll
     for (int s = 0; s < SP; ++s)
         if (s == 0 || two) {
             uint32_t i0, i1;
             pair_of(o.pe[s], D, lane, i0, i1);
-            const double2 nx = mac2(o.u[0], o.x[s], o.u[1], o.y[s]), ny = mac2(o.u[2], o.x[s], o.u[3], o.y[s]);
+            const T nx = mac2(o.u[0], o.x[s], o.u[1], o.y[s]), ny = mac2(o.u[2], o.x[s], o.u[3], o.y[s]);
             psi[i0] = nx;
             psi[i1] = ny;
             hq[128 * s] = nx;
@@ -703,12 +728,24 @@ __device__ __forceinline__ void fast_fwd_step(const FastOp<SP> &o, double2 *psi,
     wave_lds_sync();
 }
 
+// Im <lam|G|psi> on one pair (a, b of lambda, x, y of psi) for the op's generator
+__device__ __forceinline__ double pair_grad(int gen, double2 a, double2 b, double2 x, double2 y)
+{
+    const double gy = (b.x * x.x + b.y * x.y) - (a.x * y.x + a.y * y.y);
+    const double gx = (a.x * y.y - a.y * y.x) + (b.x * x.y - b.y * x.x);
+    const double gz = (a.x * x.y - a.y * x.x) - (b.x * y.y - b.y * y.x);
+    return gen == GEN_Y ? gy : (gen == GEN_X ? gx : gz);
+}
+// real states: only Y-type generators (RY, the excitations) keep the state
+// real, and Im <lam|G|psi> = b x - a y
+__device__ __forceinline__ double pair_grad(int, double a, double b, double x, double y) { return b * x - a * y; }
+
 // reverse op: the gradient partial Im <lam|G|psi> of the lane's pairs (psi
 // from the history) into gpart[pgate][lane], then U^dagger on lambda; psi
 // itself is not carried back
-template <int SP>
-__device__ __forceinline__ void fast_rev_step(const FastOp<SP> &o, const FastHist<SP> &h, double2 *lam, double *gpart,
-                                              int npg, int D, int lane)
+template <int SP, typename T>
+__device__ __forceinline__ void fast_rev_step(const FastOp<SP, T> &o, const FastHist<SP, T> &h, T *lam,
+                                              double *gpart, int npg, int D, int lane)
 {
     const uint32_t cd = ufirst((uint32_t)o.info.x);
     const bool two = SP > 1 && (cd & kTwoSlots);
@@ -719,14 +756,10 @@ __device__ __forceinline__ void fast_rev_step(const FastOp<SP> &o, const FastHis
         if (s == 0 || two) {
             uint32_t i0, i1;
             pair_of(o.pe[s], D, lane, i0, i1);
-            const double2 a = o.x[s], b = o.y[s];
+            const T a = o.x[s], b = o.y[s];
             lam[i0] = mac2(o.u[0], a, o.u[1], b);
             lam[i1] = mac2(o.u[2], a, o.u[3], b);
-            const double2 x = h.hx[s], y = h.hy[s];
-            const double gy = (b.x * x.x + b.y * x.y) - (a.x * y.x + a.y * y.y);
-            const double gx = (a.x * y.y - a.y * y.x) + (b.x * x.y - b.y * x.x);
-            const double gz = (a.x * x.y - a.y * x.x) - (b.x * y.y - b.y * y.x);
-            const double gs = gen == GEN_Y ? gy : (gen == GEN_X ? gx : gz);
+            const double gs = pair_grad(gen, a, b, h.hx[s], h.hy[s]);
             g += o.pe[s] != kNoPair ? gs : 0.0;
         }
     gpart[(pg >= 0 ? pg : npg) * 64 + lane] = g;  // row npg: ops without a parameter
@@ -734,35 +767,34 @@ __device__ __forceinline__ void fast_rev_step(const FastOp<SP> &o, const FastHis
 }
 
 // the forward chain U(theta) e_ref on one wave, two ops per trip
-template <int SP>
-__device__ __forceinline__ void fast_forward(double2 *psi, const uint16_t *ptf, const double2 *matf,
-                                             const int2 *finf, double2 *__restrict__ hist, int G, int HP, int D,
-                                             int lane)
+template <int SP, typename T>
+__device__ __forceinline__ void fast_forward(T *psi, const uint16_t *ptf, const double2 *matf, const int2 *finf,
+                                             T *__restrict__ hist, int G, int HP, int D, int lane)
 {
-    FastOp<SP> A, B;
-    fast_op_load<SP>(A, ptf, matf, finf, 0, HP, lane);
-    fast_op_load<SP>(B, ptf, matf, finf, 1, HP, lane);
-    fast_op_read<SP>(A, psi, D, lane);
+    FastOp<SP, T> A, B;
+    fast_op_load(A, ptf, matf, finf, 0, HP, lane);
+    fast_op_load(B, ptf, matf, finf, 1, HP, lane);
+    fast_op_read(A, psi, D, lane);
     for (int q = 0; q < G; q += 2) {
-        fast_fwd_step<SP>(A, psi, hist, D, lane);
+        fast_fwd_step(A, psi, hist, D, lane);
         if (q + 1 >= G) break;
-        fast_op_read<SP>(B, psi, D, lane);
-        fast_op_load<SP>(A, ptf, matf, finf, q + 2, HP, lane);
-        fast_fwd_step<SP>(B, psi, hist, D, lane);
-        fast_op_read<SP>(A, psi, D, lane);
-        fast_op_load<SP>(B, ptf, matf, finf, q + 3, HP, lane);
+        fast_op_read(B, psi, D, lane);
+        fast_op_load(A, ptf, matf, finf, q + 2, HP, lane);
+        fast_fwd_step(B, psi, hist, D, lane);
+        fast_op_read(A, psi, D, lane);
+        fast_op_load(B, ptf, matf, finf, q + 3, HP, lane);
     }
 }
 
 // the history of reverse op q: gate G - 1 - q (the host checks that the
 // reverse plan lists the gates in exactly that order), padding ops read the
 // spare row G; no table read, so the load's address is ready at once
-template <int SP>
-__device__ __forceinline__ void fast_hist_load(FastHist<SP> &h, const double2 *__restrict__ hist, int G, int q,
+template <int SP, typename T>
+__device__ __forceinline__ void fast_hist_load(FastHist<SP, T> &h, const T *__restrict__ hist, int G, int q,
                                                int lane)
 {
     const int gate = q < G ? G - 1 - q : G;
-    const double2 *hq = hist + (size_t)gate * (SP * 128) + 2 * lane;
+    const T *hq = hist + (size_t)gate * (SP * 128) + 2 * lane;
 #pragma unroll
     for (int s = 0; s < SP; ++s) {
         h.hx[s] = hq[128 * s];
@@ -770,14 +802,14 @@ __device__ __forceinline__ void fast_hist_load(FastHist<SP> &h, const double2 *_
     }
 }
 
-template <int SP>
-__device__ __forceinline__ void fast_rev_op(FastOp<SP> &cur, const FastHist<SP> &h, FastOp<SP> &nxt, double2 *lam,
+template <int SP, typename T>
+__device__ __forceinline__ void fast_rev_op(FastOp<SP, T> &cur, const FastHist<SP, T> &h, FastOp<SP, T> &nxt, T *lam,
                                             double *gpart, const uint16_t *ptr, const double2 *matr,
                                             const int2 *rinf, int npg, int qload, int HP, int D, int lane)
 {
-    fast_rev_step<SP>(cur, h, lam, gpart, npg, D, lane);
-    fast_op_read<SP>(nxt, lam, D, lane);
-    fast_op_load<SP>(cur, ptr, matr, rinf, qload, HP, lane);
+    fast_rev_step(cur, h, lam, gpart, npg, D, lane);
+    fast_op_read(nxt, lam, D, lane);
+    fast_op_load(cur, ptr, matr, rinf, qload, HP, lane);
 }
 
 // the reverse chain on one wave (leaving after op G - 1); the history of op
@@ -785,26 +817,26 @@ __device__ __forceinline__ void fast_rev_op(FastOp<SP> &cur, const FastHist<SP> 
 // several ops), the tables two ops ahead
 constexpr int kHistAhead = 8;
 
-template <int SP>
-__device__ __forceinline__ void fast_reverse(double2 *lam, const uint16_t *ptr, const double2 *matr, const int2 *rinf,
-                                             const double2 *__restrict__ hist, double *gpart, int npg, int G, int HP,
-                                             int D, int lane)
+template <int SP, typename T>
+__device__ __forceinline__ void fast_reverse(T *lam, const uint16_t *ptr, const double2 *matr, const int2 *rinf,
+                                             const T *__restrict__ hist, double *gpart, int npg, int G, int HP, int D,
+                                             int lane)
 {
-    FastOp<SP> ops[2];
-    FastHist<SP> hs[kHistAhead];
+    FastOp<SP, T> ops[2];
+    FastHist<SP, T> hs[kHistAhead];
     const int last = G + kFastPad - 1;
-    fast_op_load<SP>(ops[0], ptr, matr, rinf, 0, HP, lane);
-    fast_op_load<SP>(ops[1], ptr, matr, rinf, 1, HP, lane);
+    fast_op_load(ops[0], ptr, matr, rinf, 0, HP, lane);
+    fast_op_load(ops[1], ptr, matr, rinf, 1, HP, lane);
 #pragma unroll
-    for (int j = 0; j < kHistAhead; ++j) fast_hist_load<SP>(hs[j], hist, G, j, lane);
-    fast_op_read<SP>(ops[0], lam, D, lane);
+    for (int j = 0; j < kHistAhead; ++j) fast_hist_load(hs[j], hist, G, j, lane);
+    fast_op_read(ops[0], lam, D, lane);
     for (int q = 0; q < G; q += kHistAhead) {
 #pragma unroll
         for (int j = 0; j < kHistAhead; ++j) {
-            fast_rev_op<SP>(ops[j & 1], hs[j], ops[(j + 1) & 1], lam, gpart, ptr, matr, rinf, npg,
-                            min(q + j + 2, last), HP, D, lane);
+            fast_rev_op(ops[j & 1], hs[j], ops[(j + 1) & 1], lam, gpart, ptr, matr, rinf, npg, min(q + j + 2, last),
+                        HP, D, lane);
             if (q + j + 1 >= G) break;
-            fast_hist_load<SP>(hs[j], hist, G, q + j + kHistAhead, lane);
+            fast_hist_load(hs[j], hist, G, q + j + kHistAhead, lane);
         }
     }
 }
@@ -836,17 +868,23 @@ __device__ __forceinline__ void gate_sums(const double *gpart, double *gsum, int
 // pairs than lanes (one-qubit gates at 8 qubits)
 // RT: the register-held Hamiltonian rows (NT = 320: the gate wave, then
 // four waves for H psi with one amplitude per thread)
-template <int NT, int SP, bool CT, bool RT>
+// RS: the state stays real (every gate matrix is real for every angle, the
+// reference is a basis state and the Hamiltonian is a real matrix), so psi,
+// lambda and the history hold real amplitudes: half the LDS bytes per pair
+// and a fifth of the FP64 work per gate on the chain
+template <int NT, int SP, bool CT, bool RT, bool RS>
 __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
 {
+    using T = typename std::conditional<RS, double, double2>::type;
     constexpr int NW = NT / 64;
     static_assert(SP == 1 || (SP == 2 && NT >= 256), "pair slots per lane");
-    static_assert(!RT || (NT == 320 && !CT), "register rows: 8 qubits, real table");
+    static_assert(!RT || (NT == 320 && RS), "register rows: 8 qubits, real state");
+    static_assert(!RS || !CT, "a real state needs a real Hamiltonian");
     extern __shared__ __align__(16) unsigned char smem[];
     const SmallRunArgs &a = ka.a;
     const FastLayout L = fast_layout(a.n, a.n_gates, a.n_params, ka.n_pgates, a.n_groups, CT, RT);
-    double2 *psi = reinterpret_cast<double2 *>(smem + L.psi);
-    double2 *lam = reinterpret_cast<double2 *>(smem + L.lam);
+    T *psi = reinterpret_cast<T *>(smem + L.psi);
+    T *lam = reinterpret_cast<T *>(smem + L.lam);
     double2 *matf = reinterpret_cast<double2 *>(smem + L.matf);
     double2 *matr = reinterpret_cast<double2 *>(smem + L.matr);
     double2 *cs = reinterpret_cast<double2 *>(smem + L.cs);
@@ -874,7 +912,7 @@ __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
     const int G = a.n_gates, P = a.n_params, NG = a.n_groups, NG8 = (NG + 7) / 8 * 8, NPG = ka.n_pgates;
     const int32_t *to = a.toff + (size_t)(a.shared_ham ? 0 : inst) * NG * 3;
     double *energies = a.energies + (size_t)inst * (a.iters + 1);
-    double2 *hist = a.hist + (size_t)inst * (G + 1) * (SP * 128);
+    T *hist = reinterpret_cast<T *>(a.hist) + (size_t)inst * (G + 1) * (SP * 128);
 
     // ---- one-time staging (ops G and G + 1 pad the tables and are never applied)
     for (int p = tid; p < P; p += NT) {
@@ -1009,9 +1047,9 @@ __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
         }
         for (int it = 0; it <= a.iters; ++it) {
             __syncthreads();  // psi is final
-            double2 sacc[8];
+            T sacc[8];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) sacc[k] = make_double2(0.0, 0.0);
+            for (int k = 0; k < 8; ++k) amp_set(sacc[k], 0.0);
 #pragma unroll
             for (int g = 0; g < kRegGroups; g += 8) {
                 if (g < NG) {  // wave-uniform: whole blocks of eight, zero rows pad the last
@@ -1019,18 +1057,13 @@ __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
                     const uint4 fb = *reinterpret_cast<const uint4 *>(gf + g + 4);
                     const uint32_t fk[8] = {fa.x, fa.y, fa.z, fa.w, fb.x, fb.y, fb.z, fb.w};
 #pragma unroll
-                    for (int k = 0; k < 8; ++k) {
-                        const double2 x = psi[b ^ fk[k]];
-                        sacc[k].x = fma(tv[g + k], x.x, sacc[k].x);
-                        sacc[k].y = fma(tv[g + k], x.y, sacc[k].y);
-                    }
+                    for (int k = 0; k < 8; ++k) amp_fma(sacc[k], tv[g + k], psi[b ^ fk[k]]);
                 }
             }
-            const double2 acc = cadd(cadd(cadd(sacc[0], sacc[1]), cadd(sacc[2], sacc[3])),
-                                     cadd(cadd(sacc[4], sacc[5]), cadd(sacc[6], sacc[7])));
+            const T acc = amp_add(amp_add(amp_add(sacc[0], sacc[1]), amp_add(sacc[2], sacc[3])),
+                                  amp_add(amp_add(sacc[4], sacc[5]), amp_add(sacc[6], sacc[7])));
             lam[b] = acc;
-            const double2 x = psi[b];
-            const double e = x.x * acc.x + x.y * acc.y;
+            const double e = amp_dot(psi[b], acc);
             epart[b] = e;
             __syncthreads();  // lambda is final
             if (it == a.iters) {
@@ -1055,7 +1088,7 @@ __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
     const double2 *mab = reinterpret_cast<const double2 *>(smem + L.mab);
     for (int it = 0; it <= a.iters; ++it) {
         if (wave == 0) {
-            for (int b = lane; b < D; b += 64) psi[b] = make_double2(b == (int)a.ref ? 1.0 : 0.0, 0.0);
+            for (int b = lane; b < D; b += 64) amp_set(psi[b], b == (int)a.ref ? 1.0 : 0.0);
             wave_lds_sync();
             fast_forward<SP>(psi, ptf, matf, finf, hist, G, HP, D, lane);  // U(theta) e_ref
         }
@@ -1066,30 +1099,26 @@ __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
         double e = 0.0;
         if (mine) {
             const uint32_t b = (uint32_t)tid;
-            double2 sacc[8];
+            T sacc[8];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) sacc[k] = make_double2(0.0, 0.0);
+            for (int k = 0; k < 8; ++k) amp_set(sacc[k], 0.0);
             for (int g = 0; g < NG8; g += 8) {
                 const uint4 fa = *reinterpret_cast<const uint4 *>(gf + g);
                 const uint4 fb = *reinterpret_cast<const uint4 *>(gf + g + 4);
                 const uint32_t fk[8] = {fa.x, fa.y, fa.z, fa.w, fb.x, fb.y, fb.z, fb.w};
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
-                    const double2 x = psi[b ^ fk[k]];
-                    if (CT) {
+                    const T x = psi[b ^ fk[k]];
+                    if constexpr (CT)
                         sacc[k] = cadd(sacc[k], cmul(tabc[(g + k) * D + b], x));
-                    } else {
-                        const double d = tabr[(g + k) * D + b];
-                        sacc[k].x = fma(d, x.x, sacc[k].x);
-                        sacc[k].y = fma(d, x.y, sacc[k].y);
-                    }
+                    else
+                        amp_fma(sacc[k], tabr[(g + k) * D + b], x);
                 }
             }
-            const double2 acc = cadd(cadd(cadd(sacc[0], sacc[1]), cadd(sacc[2], sacc[3])),
-                                     cadd(cadd(sacc[4], sacc[5]), cadd(sacc[6], sacc[7])));
+            const T acc = amp_add(amp_add(amp_add(sacc[0], sacc[1]), amp_add(sacc[2], sacc[3])),
+                                  amp_add(amp_add(sacc[4], sacc[5]), amp_add(sacc[6], sacc[7])));
             lam[b] = acc;
-            const double2 x = psi[b];
-            e = x.x * acc.x + x.y * acc.y;
+            e = amp_dot(psi[b], acc);
         }
         if (!RT) epart[tid] = e;
         __syncthreads();
@@ -1197,13 +1226,22 @@ __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
 constexpr size_t kSmallLdsMax = 160 * 1024 - 1024;
 constexpr int kSmallFast = 1 << 5;  // mode flag: k_small_fast
 
-inline void (*fast_kernel(int n, bool complex_tab, bool two_slots, bool regtab))(SmallKernelArgs)
+constexpr int kSmallReal = 1 << 6;  // mode flag: the state stays real
+
+inline void (*fast_kernel(int n, bool complex_tab, bool two_slots, bool regtab, bool real))(SmallKernelArgs)
 {
-    if (n <= 6) return complex_tab ? k_small_fast<64, 1, true, false> : k_small_fast<64, 1, false, false>;
-    if (n == 7) return complex_tab ? k_small_fast<128, 1, true, false> : k_small_fast<128, 1, false, false>;
-    if (regtab) return k_small_fast<320, 1, false, true>;  // one pair slot only (two would spill)
-    if (two_slots) return complex_tab ? k_small_fast<256, 2, true, false> : k_small_fast<256, 2, false, false>;
-    return complex_tab ? k_small_fast<256, 1, true, false> : k_small_fast<256, 1, false, false>;
+    if (real) {  // real table only: the planner takes the real state only with a real Hamiltonian
+        if (n <= 6) return k_small_fast<64, 1, false, false, true>;
+        if (n == 7) return k_small_fast<128, 1, false, false, true>;
+        if (regtab) return k_small_fast<320, 1, false, true, true>;  // one pair slot only (two would spill)
+        return two_slots ? k_small_fast<256, 2, false, false, true> : k_small_fast<256, 1, false, false, true>;
+    }
+    if (n <= 6) return complex_tab ? k_small_fast<64, 1, true, false, false> : k_small_fast<64, 1, false, false, false>;
+    if (n == 7)
+        return complex_tab ? k_small_fast<128, 1, true, false, false> : k_small_fast<128, 1, false, false, false>;
+    if (two_slots)
+        return complex_tab ? k_small_fast<256, 2, true, false, false> : k_small_fast<256, 2, false, false, false>;
+    return complex_tab ? k_small_fast<256, 1, true, false, false> : k_small_fast<256, 1, false, false, false>;
 }
 
 int choose_block(int n)
@@ -1222,17 +1260,17 @@ size_t small_fast_hist_bytes(int n, int n_gates)
 
 // 1 if the persistent loop can run this problem; *mode_out gets the Hamiltonian form
 int small_run_plan(int n, int n_gates, int n_params, int n_pgates, int n_groups, int max_inst_terms,
-                   int has_imag, int max_pairs, int *mode_out, size_t *lds_out)
+                   int has_imag, int real_gates, int max_pairs, int *mode_out, size_t *lds_out)
 {
     if (n > 10 || n_gates > 2048 || n_params > 2048) return 0;
     // up to 8 qubits with the Hamiltonian as a table: the latency-built kernel,
     // sized with the layout of the variant that will run (register rows keep
     // no table in LDS)
     if (n <= 8 && n_gates <= 1024) {
-        const bool rt = fast_regtab(n, n_groups, has_imag) && max_pairs <= 64;
+        const bool rt = fast_regtab(n, n_groups, real_gates && !has_imag, max_pairs);
         const FastLayout W = fast_layout(n, n_gates, n_params, n_pgates, n_groups, has_imag, rt);
         if (W.total <= kSmallLdsMax) {
-            *mode_out = (has_imag ? 2 : 1) | kSmallFast;
+            *mode_out = (has_imag ? 2 : 1) | kSmallFast | (real_gates && !has_imag ? kSmallReal : 0);
             *lds_out = W.total;
             return 1;
         }
@@ -1255,9 +1293,9 @@ int small_run_plan(int n, int n_gates, int n_params, int n_pgates, int n_groups,
 const char *small_run_variant(const SmallRunArgs &a, int mode, int max_pairs)
 {
     if (!(mode & kSmallFast)) return "k_small_run (persistent loop)";
-    if (fast_regtab(a.n, a.n_groups, (mode & 15) == 2) && max_pairs <= 64)
-        return "k_small_fast (persistent loop, register rows)";
-    return "k_small_fast (persistent loop, table)";
+    const bool real = mode & kSmallReal;
+    if (fast_regtab(a.n, a.n_groups, real, max_pairs)) return "k_small_fast (real state, register rows)";
+    return real ? "k_small_fast (real state, table)" : "k_small_fast (persistent loop, table)";
 }
 
 hipError_t launch_small_run(const SmallRunArgs &a, const OpDesc *rops, const int32_t *pmap_off,
@@ -1274,10 +1312,10 @@ hipError_t launch_small_run(const SmallRunArgs &a, const OpDesc *rops, const int
     ka.defer = (mode >> 4) & 1;
     ka.max_inst_terms = max_inst_terms;
     if (mode & kSmallFast) {
-        const bool rt = fast_regtab(a.n, a.n_groups, ka.mode == 2) && max_pairs <= 64;
+        const bool rt = fast_regtab(a.n, a.n_groups, mode & kSmallReal, max_pairs);
         const int nt = fast_threads(a.n) + (rt ? 64 : 0);
         const FastLayout W = fast_layout(a.n, a.n_gates, a.n_params, n_pgates, a.n_groups, ka.mode == 2, rt);
-        void (*kern)(SmallKernelArgs) = fast_kernel(a.n, ka.mode == 2, max_pairs > 64, rt);
+        void (*kern)(SmallKernelArgs) = fast_kernel(a.n, ka.mode == 2, max_pairs > 64, rt, mode & kSmallReal);
         if (W.total > 65536) {
             hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)W.total);

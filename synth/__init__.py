@@ -43,6 +43,9 @@ GATE_ARITY = {
     "DoubleExcitation": 4,
 }
 PARAMETRIC = {"RX", "RY", "RZ", "SingleExcitation", "DoubleExcitation"}
+# kinds whose matrices are real for every angle: from a basis state under a
+# real Hamiltonian the state stays real
+REAL_KINDS = {"RY", "H", "X", "CNOT", "CZ", "SingleExcitation", "DoubleExcitation"}
 
 
 # ---------------------------------------------------------------------------
@@ -369,10 +372,11 @@ def hea_circuit(n: int, layers: int) -> Circuit:
     return _circuit(n, gates, 2 * n * layers, 0)
 
 
-def random_circuit(n: int, n_gates: int, seed: int) -> Circuit:
-    """A random mix of every supported gate kind (used by parity tests)."""
+def random_circuit(n: int, n_gates: int, seed: int, kinds=None) -> Circuit:
+    """A random mix of every supported gate kind, or of the given kinds (used
+    by parity tests)."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    kinds = [k for k in GATE_ARITY if GATE_ARITY[k] <= n]
+    kinds = [k for k in GATE_ARITY if GATE_ARITY[k] <= n and (kinds is None or k in kinds)]
     gates = []
     p = 0
     for _ in range(n_gates):

@@ -495,8 +495,44 @@ def test_persistent_loop_register_rows(vqe, ctx, n_groups):
     ran = set(ctx.profile(reset=True))
     ctx.set_profiling(False)
     # 90 groups: the 8-qubit table (96 x 256 doubles) exceeds the LDS
-    want_kernel = ("k_small_fast (persistent loop, register rows)" if n_groups <= 64
+    want_kernel = ("k_small_fast (real state, register rows)" if n_groups <= 64
                    else "k_small_run (persistent loop)")
+    assert want_kernel in ran, ran
+    tho_gpu = th.cpu().numpy()
+    for b in range(3):
+        want, tho = oracle.vqe_run(spec, ham, th0[b], iters)
+        np.testing.assert_allclose(traj[b], want, atol=E_TOL)
+        np.testing.assert_allclose(tho_gpu[b], tho, atol=1e-7)
+
+
+@pytest.mark.parametrize("n,n_gates,n_groups,iters,imag", [
+    (3, 14, 5, 30, False), (6, 30, 24, 20, False), (7, 30, 40, 15, False),
+    (8, 24, 50, 12, False),  # one-qubit gates at 8 qubits: two pair slots per lane
+    (6, 30, 0, 20, True),    # strings with odd Y counts: a complex Hamiltonian keeps the complex state
+])
+def test_persistent_loop_real_state(vqe, ctx, n, n_gates, n_groups, iters, imag):
+    # circuits of RY, H, X, CNOT, CZ and the excitations from a random basis
+    # state under a real Hamiltonian: the loop runs on real amplitudes
+    _say("real state", n, n_gates, n_groups, iters, imag)
+    spec = synth.random_circuit(n, n_gates, seed=90 + n, kinds=synth.REAL_KINDS)
+    assert set(spec.kinds) <= synth.REAL_KINDS
+    assert n < 8 or any(k in ("RY", "H", "X") for k in spec.kinds)
+    if imag:
+        ham = synth.random_pauli_sum(n, 40, seed=90 + n)
+        assert any(bin(int(x) & int(z)).count("1") % 2 for x, z in zip(ham.xmask, ham.zmask))
+    else:
+        ham = _real_pauli_sum(n, n_groups, seed=90 + n)
+    C = vqe.Circuit.from_spec(ctx, spec)
+    H = vqe.Hamiltonian.from_sum(ctx, ham)
+    th0 = synth.uniform_thetas(spec.n_params, 3, seed=90 + n)
+    th = dev(th0)
+    ctx.profile(reset=True)
+    ctx.set_profiling(True)  # records which persistent kernel variant ran
+    traj = vqe.run(ctx, C, H, th, iters).cpu().numpy()
+    ran = set(ctx.profile(reset=True))
+    ctx.set_profiling(False)
+    want_kernel = ("k_small_fast (persistent loop, table)" if imag
+                   else "k_small_fast (real state, table)")
     assert want_kernel in ran, ran
     tho_gpu = th.cpu().numpy()
     for b in range(3):
