@@ -864,6 +864,23 @@ __device__ __forceinline__ void gate_sums(const double *gpart, double *gsum, int
     }
 }
 
+// H psi of one amplitude from register-held rows: sum over the first NR
+// groups of tv[g] psi[ad[g]] (ad: the amplitude's partner in group g, fixed
+// for the launch), eight interleaved accumulators; no branch and no table
+// read between the loads, so they issue back to back
+template <int NR, typename T>
+__device__ __forceinline__ T rows_gather(const T *psi, const double (&tv)[kRegGroups],
+                                         const uint32_t (&ad)[kRegGroups])
+{
+    T sacc[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) amp_set(sacc[k], 0.0);
+#pragma unroll
+    for (int g = 0; g < NR; ++g) amp_fma(sacc[g & 7], tv[g], psi[ad[g]]);
+    return amp_add(amp_add(amp_add(sacc[0], sacc[1]), amp_add(sacc[2], sacc[3])),
+                   amp_add(amp_add(sacc[4], sacc[5]), amp_add(sacc[6], sacc[7])));
+}
+
 // SP: pair slots per lane of the gate wave, 2 only when some op has more
 // pairs than lanes (one-qubit gates at 8 qubits)
 // RT: the register-held Hamiltonian rows (NT = 320: the gate wave, then
@@ -1031,9 +1048,11 @@ __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
         // barriers as the gate wave's loop
         const uint32_t b = (uint32_t)(tid - 64);
         double tv[kRegGroups];
+        uint32_t ad[kRegGroups];  // partners b ^ f_g (b itself for the zero rows)
 #pragma unroll
         for (int g = 0; g < kRegGroups; ++g) {
             double re = 0.0;
+            ad[g] = g < NG ? b ^ gf[g] : b;
             if (g < NG) {
                 const int ug = a.groups[g].ugroup;
                 const int tb = to[ug * 3], tm = to[ug * 3 + 1];
@@ -1047,21 +1066,8 @@ __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
         }
         for (int it = 0; it <= a.iters; ++it) {
             __syncthreads();  // psi is final
-            T sacc[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) amp_set(sacc[k], 0.0);
-#pragma unroll
-            for (int g = 0; g < kRegGroups; g += 8) {
-                if (g < NG) {  // wave-uniform: whole blocks of eight, zero rows pad the last
-                    const uint4 fa = *reinterpret_cast<const uint4 *>(gf + g);
-                    const uint4 fb = *reinterpret_cast<const uint4 *>(gf + g + 4);
-                    const uint32_t fk[8] = {fa.x, fa.y, fa.z, fa.w, fb.x, fb.y, fb.z, fb.w};
-#pragma unroll
-                    for (int k = 0; k < 8; ++k) amp_fma(sacc[k], tv[g + k], psi[b ^ fk[k]]);
-                }
-            }
-            const T acc = amp_add(amp_add(amp_add(sacc[0], sacc[1]), amp_add(sacc[2], sacc[3])),
-                                  amp_add(amp_add(sacc[4], sacc[5]), amp_add(sacc[6], sacc[7])));
+            const T acc = NG > kRegGroups / 2 ? rows_gather<kRegGroups>(psi, tv, ad)
+                                              : rows_gather<kRegGroups / 2>(psi, tv, ad);
             lam[b] = acc;
             const double e = amp_dot(psi[b], acc);
             epart[b] = e;
