@@ -841,27 +841,55 @@ __device__ __forceinline__ void fast_reverse(T *lam, const uint16_t *ptr, const 
     }
 }
 
-// per parametric gate the sum of its 64 lane partials, on one wave in fixed
-// order: four lanes per gate add 16 partials each, then a quad sum
+// the sum of parametric gate row's 64 lane partials in fixed order: each of
+// the four lanes of a quad adds 16 partials (part = lane & 3), then a quad
+// sum leaves the total in all four lanes (rows past NPG give zero)
+__device__ __forceinline__ double row_sum(const double *gpart, int row, int NPG, int part)
+{
+    double s0 = 0.0, s1 = 0.0;
+    if (row < NPG) {
+        const double2 *v = reinterpret_cast<const double2 *>(gpart + row * 64 + part * 16);
+#pragma unroll
+        for (int j = 0; j < 8; j += 2) {
+            const double2 a = v[j], b = v[j + 1];
+            s0 += a.x + a.y;
+            s1 += b.x + b.y;
+        }
+    }
+    double t = s0 + s1;
+    t += dpp_move<0xB1>(t);  // quad_perm [1, 0, 3, 2]
+    t += dpp_move<0x4E>(t);  // quad_perm [2, 3, 0, 1]
+    return t;
+}
+
+// per parametric gate the sum of its 64 lane partials, 16 gates per pass
 __device__ __forceinline__ void gate_sums(const double *gpart, double *gsum, int NPG, int lane)
 {
     for (int r0 = 0; r0 < NPG; r0 += 16) {
         const int row = r0 + (lane >> 2), part = lane & 3;
-        double s0 = 0.0, s1 = 0.0;
-        if (row < NPG) {
-            const double2 *v = reinterpret_cast<const double2 *>(gpart + row * 64 + part * 16);
-#pragma unroll
-            for (int j = 0; j < 8; j += 2) {
-                const double2 a = v[j], b = v[j + 1];
-                s0 += a.x + a.y;
-                s1 += b.x + b.y;
-            }
-        }
-        double t = s0 + s1;
-        t += dpp_move<0xB1>(t);  // quad_perm [1, 0, 3, 2]
-        t += dpp_move<0x4E>(t);  // quad_perm [2, 3, 0, 1]
+        const double t = row_sum(gpart, row, NPG, part);
         if (part == 0 && row < NPG) gsum[row] = t;
     }
+}
+
+// the parameters are the parametric gates: one gate per parameter, gate j
+// holding parameter j, at most 16 (then the lane that sums gate j's partials
+// steps parameter j at once, without a round trip through LDS)
+constexpr int kDirectParams = 16;
+
+// the next iteration's matrix of a rotation, U = A cos(t/2) + B sin(t/2),
+// into dst[0..3] (ab[0..3] = A, ab[4..7] = B); with real coefficients only
+// the real parts are written (the imaginary parts stay zero)
+__device__ __forceinline__ void rot_store(double2 *dst, const double2 *ab, double cn, double sn)
+{
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        dst[k] = make_double2(fma(ab[k].x, cn, ab[4 + k].x * sn), fma(ab[k].y, cn, ab[4 + k].y * sn));
+}
+__device__ __forceinline__ void rot_store(double2 *dst, const double *ab, double cn, double sn)
+{
+#pragma unroll
+    for (int k = 0; k < 4; ++k) reinterpret_cast<double *>(dst + k)[0] = fma(ab[k], cn, ab[4 + k] * sn);
 }
 
 // H psi of one amplitude from register-held rows: sum over the first NR
@@ -1092,6 +1120,55 @@ __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
     double b1t = 1.0, b2t = 1.0;  // beta1^t, beta2^t for Adam's bias corrections
     const int2 *pq = reinterpret_cast<const int2 *>(smem + L.pq);
     const double2 *mab = reinterpret_cast<const double2 *>(smem + L.mab);
+    bool direct = NPG == P && P <= kDirectParams;  // the same in every thread
+    for (int p = 0; p < P && direct; ++p) direct = poff[p] == p && pidx[p] == p;
+
+    // optimiser step of parameter p (gradient gp, gates pidx[e0..e1), the
+    // first one's op slots q0 and coefficients ab), then the next
+    // iteration's matrices of its gates
+    auto param_step = [&](int p, double gp, int e0, int e1, int2 q0, const T (&ab)[16], double rc1, double rc2) {
+        const double t0 = th[p];
+        const double2 c0 = cs[p];
+        double t = t0;
+        if (a.opt == VQE_OPT_ADAM) {
+            const double mi = a.b1 * mom[p] + (1.0 - a.b1) * gp;
+            const double vi = a.b2 * vel[p] + (1.0 - a.b2) * gp * gp;
+            mom[p] = mi;
+            vel[p] = vi;
+            t -= a.lr * (mi * rc1) / (sqrt(vi * rc2) + a.eps);
+        } else {
+            t -= a.lr * gp;
+        }
+        th[p] = t;
+        // cos and sin of the new half angle: the old pair rotated by the half
+        // step d (|d| < 1/16: Taylor series to d^9, error below 1e-19), else
+        // from scratch
+        const double d = 0.5 * (t - t0);
+        double sn, cn;
+        if (fabs(d) < 0.0625) {
+            const double d2 = d * d;
+            const double cd = fma(d2, fma(d2, fma(d2, fma(d2, 1.0 / 40320, -1.0 / 720), 1.0 / 24), -0.5), 1.0);
+            const double sd = d * fma(d2, fma(d2, fma(d2, fma(d2, 1.0 / 362880, -1.0 / 5040), 1.0 / 120), -1.0 / 6), 1.0);
+            cn = fma(c0.x, cd, -c0.y * sd);
+            sn = fma(c0.y, cd, c0.x * sd);
+        } else {
+            sincos(0.5 * t, &sn, &cn);
+        }
+        cs[p] = make_double2(cn, sn);
+        if (e0 < e1) {
+            if (q0.x >= 0) rot_store(matf + 4 * q0.x, ab, cn, sn);
+            if (q0.y >= 0) rot_store(matr + 4 * q0.y, ab + 8, cn, sn);
+        }
+        for (int e2 = e0 + 1; e2 < e1; ++e2) {  // further gates sharing the parameter
+            const int j = pidx[e2];
+            const int2 qq = pq[j];
+            T abj[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) mat_get(abj[k], mab[j * 16 + k]);
+            if (qq.x >= 0) rot_store(matf + 4 * qq.x, abj, cn, sn);
+            if (qq.y >= 0) rot_store(matr + 4 * qq.y, abj + 8, cn, sn);
+        }
+    };
     for (int it = 0; it <= a.iters; ++it) {
         if (wave == 0) {
             for (int b = lane; b < D; b += 64) amp_set(psi[b], b == (int)a.ref ? 1.0 : 0.0);
@@ -1139,77 +1216,32 @@ __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
         if (wave == 0) {
             // reverse sweep: g_l = Im <lambda|G_l|psi>, then U_l^dagger on both states
             fast_reverse<SP>(lam, ptr, matr, rinf, hist, gpart, NPG, G, HP, D, lane);
-            gate_sums(gpart, gsum, NPG, lane);
-            wave_lds_sync();
-            // optimiser step, then the next iteration's matrices of the
-            // parameter's gates
             const double rc1 = 1.0 / (1.0 - b1t), rc2 = 1.0 / (1.0 - b2t);
-            for (int p = lane; p < P; p += 64) {
-                const int e0 = poff[p], e1 = poff[p + 1];
-                // the parameter's first gate: its op slots and matrix coefficients,
-                // read before the update so they land during its arithmetic
-                const int j0 = e0 < e1 ? pidx[e0] : 0;  // row 0 exists (at least one is laid out)
-                const int2 q0 = pq[j0];
-                double2 ab[16];
+            if (direct) {
+                // gate p's quad sums its partials; its first lane steps parameter p
+                const int p = min(lane >> 2, P - 1);
+                const int2 q0 = pq[p];
+                T ab[16];
 #pragma unroll
-                for (int k = 0; k < 16; ++k) ab[k] = mab[j0 * 16 + k];
-                double gp = 0.0;
-                for (int e2 = e0; e2 < e1; ++e2) gp += gsum[pidx[e2]];
-                const double t0 = th[p];
-                const double2 c0 = cs[p];
-                double t = t0;
-                if (a.opt == VQE_OPT_ADAM) {
-                    const double mi = a.b1 * mom[p] + (1.0 - a.b1) * gp;
-                    const double vi = a.b2 * vel[p] + (1.0 - a.b2) * gp * gp;
-                    mom[p] = mi;
-                    vel[p] = vi;
-                    t -= a.lr * (mi * rc1) / (sqrt(vi * rc2) + a.eps);
-                } else {
-                    t -= a.lr * gp;
-                }
-                th[p] = t;
-                // cos and sin of the new half angle: the old pair rotated by
-                // the half step d (|d| < 1/16: Taylor series to d^9, error
-                // below 1e-19), else from scratch
-                const double d = 0.5 * (t - t0);
-                double sn, cn;
-                if (fabs(d) < 0.0625) {
-                    const double d2 = d * d;
-                    const double cd = fma(d2, fma(d2, fma(d2, fma(d2, 1.0 / 40320, -1.0 / 720), 1.0 / 24), -0.5), 1.0);
-                    const double sd =
-                        d * fma(d2, fma(d2, fma(d2, fma(d2, 1.0 / 362880, -1.0 / 5040), 1.0 / 120), -1.0 / 6), 1.0);
-                    cn = fma(c0.x, cd, -c0.y * sd);
-                    sn = fma(c0.y, cd, c0.x * sd);
-                } else {
-                    sincos(0.5 * t, &sn, &cn);
-                }
-                cs[p] = make_double2(cn, sn);
-                if (e0 < e1) {
-                    if (q0.x >= 0)
+                for (int k = 0; k < 16; ++k) mat_get(ab[k], mab[p * 16 + k]);
+                const double gp = row_sum(gpart, lane >> 2, NPG, lane & 3);
+                if ((lane & 3) == 0 && (lane >> 2) < P) param_step(p, gp, p, p + 1, q0, ab, rc1, rc2);
+            } else {
+                gate_sums(gpart, gsum, NPG, lane);
+                wave_lds_sync();
+                for (int p = lane; p < P; p += 64) {
+                    const int e0 = poff[p], e1 = poff[p + 1];
+                    // the parameter's first gate: its op slots and matrix
+                    // coefficients, read before the update so they land during
+                    // its arithmetic
+                    const int j0 = e0 < e1 ? pidx[e0] : 0;  // row 0 exists (at least one is laid out)
+                    const int2 q0 = pq[j0];
+                    T ab[16];
 #pragma unroll
-                        for (int k = 0; k < 4; ++k)
-                            matf[4 * q0.x + k] = make_double2(fma(ab[k].x, cn, ab[4 + k].x * sn),
-                                                              fma(ab[k].y, cn, ab[4 + k].y * sn));
-                    if (q0.y >= 0)
-#pragma unroll
-                        for (int k = 0; k < 4; ++k)
-                            matr[4 * q0.y + k] = make_double2(fma(ab[8 + k].x, cn, ab[12 + k].x * sn),
-                                                              fma(ab[8 + k].y, cn, ab[12 + k].y * sn));
-                }
-                for (int e2 = e0 + 1; e2 < e1; ++e2) {  // further gates sharing the parameter
-                    const int j = pidx[e2];
-                    const int2 qq = pq[j];
-                    const double2 *abj = mab + j * 16;
-                    if (qq.x >= 0)
-#pragma unroll
-                        for (int k = 0; k < 4; ++k)
-                            matf[4 * qq.x + k] = make_double2(fma(abj[k].x, cn, abj[4 + k].x * sn),
-                                                              fma(abj[k].y, cn, abj[4 + k].y * sn));
-                    if (qq.y >= 0)
-#pragma unroll
-                        for (int k = 0; k < 4; ++k)
-                            matr[4 * qq.y + k] = make_double2(fma(abj[8 + k].x, cn, abj[12 + k].x * sn),
-                                                              fma(abj[8 + k].y, cn, abj[12 + k].y * sn));
+                    for (int k = 0; k < 16; ++k) mat_get(ab[k], mab[j0 * 16 + k]);
+                    double gp = 0.0;
+                    for (int e2 = e0; e2 < e1; ++e2) gp += gsum[pidx[e2]];
+                    param_step(p, gp, e0, e1, q0, ab, rc1, rc2);
                 }
             }
             if (NW == 1) {
