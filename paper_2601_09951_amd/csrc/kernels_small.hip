@@ -740,16 +740,16 @@ __device__ __forceinline__ double pair_grad(int gen, double2 a, double2 b, doubl
 // real, and Im <lam|G|psi> = b x - a y
 __device__ __forceinline__ double pair_grad(int, double a, double b, double x, double y) { return b * x - a * y; }
 
-// reverse op: the gradient partial Im <lam|G|psi> of the lane's pairs (psi
-// from the history) into gpart[pgate][lane], then U^dagger on lambda; psi
-// itself is not carried back
+// reverse op: U^dagger on the lane's pairs of lambda; returns the lane's
+// gradient partial Im <lam|G|psi> (psi from the history); psi itself is not
+// carried back
 template <int SP, typename T>
-__device__ __forceinline__ void fast_rev_step(const FastOp<SP, T> &o, const FastHist<SP, T> &h, T *lam,
-                                              double *gpart, int npg, int D, int lane)
+__device__ __forceinline__ double fast_rev_step(const FastOp<SP, T> &o, const FastHist<SP, T> &h, T *lam, int D,
+                                                int lane)
 {
     const uint32_t cd = ufirst((uint32_t)o.info.x);
     const bool two = SP > 1 && (cd & kTwoSlots);
-    const int pg = (int)(cd >> 8) - 1, gen = (int)(cd & 15u);
+    const int gen = (int)(cd & 15u);
     double g = 0.0;
 #pragma unroll
     for (int s = 0; s < SP; ++s)
@@ -762,8 +762,8 @@ __device__ __forceinline__ void fast_rev_step(const FastOp<SP, T> &o, const Fast
             const double gs = pair_grad(gen, a, b, h.hx[s], h.hy[s]);
             g += o.pe[s] != kNoPair ? gs : 0.0;
         }
-    gpart[(pg >= 0 ? pg : npg) * 64 + lane] = g;  // row npg: ops without a parameter
     wave_lds_sync();
+    return g;
 }
 
 // the forward chain U(theta) e_ref on one wave, two ops per trip
@@ -807,8 +807,13 @@ __device__ __forceinline__ void fast_rev_op(FastOp<SP, T> &cur, const FastHist<S
                                             double *gpart, const uint16_t *ptr, const double2 *matr,
                                             const int2 *rinf, int npg, int qload, int HP, int D, int lane)
 {
-    fast_rev_step(cur, h, lam, gpart, npg, D, lane);
+    const double g = fast_rev_step(cur, h, lam, D, lane);
     fast_op_read(nxt, lam, D, lane);
+    // the chain's reads first in the wave's LDS queue (LDS operations of a
+    // wave run in issue order), then the partial and the later tables
+    __builtin_amdgcn_sched_barrier(0);
+    const int pg = (int)(ufirst((uint32_t)cur.info.x) >> 8) - 1;
+    gpart[(pg >= 0 ? pg : npg) * 64 + lane] = g;  // row npg: ops without a parameter
     fast_op_load(cur, ptr, matr, rinf, qload, HP, lane);
 }
 
@@ -1216,6 +1221,7 @@ __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
         if (wave == 0) {
             // reverse sweep: g_l = Im <lambda|G_l|psi>, then U_l^dagger on both states
             fast_reverse<SP>(lam, ptr, matr, rinf, hist, gpart, NPG, G, HP, D, lane);
+            wave_lds_sync();  // the last partials before their sums
             const double rc1 = 1.0 / (1.0 - b1t), rc2 = 1.0 / (1.0 - b2t);
             if (direct) {
                 // gate p's quad sums its partials; its first lane steps parameter p
