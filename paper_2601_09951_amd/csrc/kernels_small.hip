@@ -561,8 +561,8 @@ __host__ __device__ inline FastLayout fast_layout(int n, int G, int P, int NPG, 
     L.epart = take(8 * nt, 8);
     L.finf = take((size_t)8 * (G + kFastPad), 8);  // {gen | (pgate + 1) << 8, gate} per op
     L.rinf = take((size_t)8 * (G + kFastPad), 8);
-    L.ptf = take(2 * (size_t)(G + kFastPad) * fast_row(n), 4);  // pair t of op q at [q][t]
-    L.ptr = take(2 * (size_t)(G + kFastPad) * fast_row(n), 4);
+    L.ptf = take(4 * (size_t)(G + kFastPad) * fast_row(n), 4);  // pair t of op q at [q][t]
+    L.ptr = L.ptf;  // the reverse chain reads the forward rows backwards
     L.pq = take((size_t)8 * npg, 8);            // per parametric gate: forward and reverse op
     L.mab = take((size_t)256 * npg, 16);        // per parametric gate: U = A cos + B sin, forward and reverse
     L.gdev = take(sizeof(GateDev) * G, 16);
@@ -619,8 +619,6 @@ __device__ __forceinline__ void amp_set(double &a, double v) { a = v; }
 __device__ __forceinline__ void mat_get(double2 &d, const double2 &m) { d = m; }
 __device__ __forceinline__ void mat_get(double &d, const double2 &m) { d = m.x; }
 
-constexpr uint32_t kNoPair = 0xFFFFu;
-
 // Orders the calling wave's LDS writes before its later LDS reads by other
 // lanes: LDS operations of one wave execute in issue order, so no wait is
 // needed, only that the compiler moves no memory operation across.
@@ -632,26 +630,32 @@ __device__ __forceinline__ void wave_lds_sync()
 }
 
 // op q's pair entries of this lane (pairs lane + 64 s; the rows are padded
-// to at least 64 entries with kNoPair, so no lane needs a bound) and its
-// matrix; ops G.. are padding (no pairs, zero matrices), so the prefetch of
-// later ops needs no branch
+// to at least 64 entries, so no lane needs a bound) and its matrix; ops G..
+// are padding (no pairs, zero matrices), so the prefetch of later ops needs
+// no branch.  An entry holds the byte offsets of the pair's two amplitudes
+// in the state (first | second << 16); a lane without a pair gets its own
+// two trash slots past the state, which hold zeros, so no lane branches or
+// masks its partial
 template <int SP, typename T>
-__device__ __forceinline__ void fast_tables(const uint16_t *pt, const double2 *mat, int q, int HP, int lane,
+__device__ __forceinline__ void fast_tables(const uint32_t *pt, const double2 *mat, int q, int row, int HP, int lane,
                                             uint32_t (&pe)[SP], T (&u)[4])
 {
 #pragma unroll
-    for (int s = 0; s < SP; ++s) pe[s] = pt[q * HP + lane + 64 * s];
+    for (int s = 0; s < SP; ++s) pe[s] = pt[row * HP + lane + 64 * s];
 #pragma unroll
     for (int k = 0; k < 4; ++k) mat_get(u[k], mat[4 * q + k]);
 }
 
-// pair indices of a table entry; a lane without a pair works on its own two
-// trash slots past the state (no branch, no two lanes on one address)
-__device__ __forceinline__ void pair_of(uint32_t e, int D, int lane, uint32_t &i0, uint32_t &i1)
+// the amplitude at a byte offset of a state
+template <typename T>
+__device__ __forceinline__ T &amp_at(T *st, uint32_t off)
 {
-    const bool act = e != kNoPair;
-    i0 = act ? (e & 255u) : (uint32_t)(D + 2 * lane);
-    i1 = act ? (e >> 8) : (uint32_t)(D + 2 * lane + 1);
+    return *reinterpret_cast<T *>(reinterpret_cast<unsigned char *>(st) + off);
+}
+template <typename T>
+__device__ __forceinline__ const T &amp_at(const T *st, uint32_t off)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const unsigned char *>(st) + off);
 }
 
 // bit 4 of an op's info word: the op has more pairs than lanes, so the
@@ -684,13 +688,17 @@ struct FastHist {
     T hx[SP], hy[SP];
 };
 
+// op q of a chain; its pair table row is q forward, and for the reverse
+// chain (the gates in reverse order on the same pairs) the row of forward op
+// G - 1 - q (rows G.. are the padding ops either way)
 template <int SP, typename T>
-__device__ __forceinline__ void fast_op_load(FastOp<SP, T> &o, const uint16_t *pt, const double2 *mat,
-                                             const int2 *inf, int q, int HP, int lane)
+__device__ __forceinline__ void fast_op_load(FastOp<SP, T> &o, const uint32_t *pt, const double2 *mat,
+                                             const int2 *inf, int q, int row, int HP, int lane)
 {
-    fast_tables<SP>(pt, mat, q, HP, lane, o.pe, o.u);
+    fast_tables<SP>(pt, mat, q, row, HP, lane, o.pe, o.u);
     o.info = inf[q];
 }
+__device__ __forceinline__ int rev_row(int q, int G) { return q < G ? G - 1 - q : q; }
 
 // read the op's pairs of a state (psi forward, lambda reverse)
 template <int SP, typename T>
@@ -700,28 +708,24 @@ __device__ __forceinline__ void fast_op_read(FastOp<SP, T> &o, const T *st, int 
 #pragma unroll
     for (int s = 0; s < SP; ++s)
         if (s == 0 || two) {
-            uint32_t i0, i1;
-            pair_of(o.pe[s], D, lane, i0, i1);
-            o.x[s] = st[i0];
-            o.y[s] = st[i1];
+            o.x[s] = amp_at(st, o.pe[s] & 0xFFFFu);
+            o.y[s] = amp_at(st, o.pe[s] >> 16);
         }
 }
 
-// forward op: update the lane's pairs of psi and record them after the gate
-// in hist[gate][slot][lane] (global memory, off the chain)
+// forward op q (gate q): update the lane's pairs of psi and record them
+// after the gate in hist[q][slot][lane] (global memory, off the chain)
 template <int SP, typename T>
-__device__ __forceinline__ void fast_fwd_step(const FastOp<SP, T> &o, T *psi, T *__restrict__ hist, int D, int lane)
+__device__ __forceinline__ void fast_fwd_step(const FastOp<SP, T> &o, T *psi, T *__restrict__ hist, int q, int lane)
 {
     const bool two = SP > 1 && (ufirst((uint32_t)o.info.x) & kTwoSlots);
-    T *hq = hist + (size_t)ufirst((uint32_t)o.info.y) * (SP * 128) + 2 * lane;
+    T *hq = hist + (size_t)q * (SP * 128) + 2 * lane;
 #pragma unroll
     for (int s = 0; s < SP; ++s)
         if (s == 0 || two) {
-            uint32_t i0, i1;
-            pair_of(o.pe[s], D, lane, i0, i1);
             const T nx = mac2(o.u[0], o.x[s], o.u[1], o.y[s]), ny = mac2(o.u[2], o.x[s], o.u[3], o.y[s]);
-            psi[i0] = nx;
-            psi[i1] = ny;
+            amp_at(psi, o.pe[s] & 0xFFFFu) = nx;
+            amp_at(psi, o.pe[s] >> 16) = ny;
             hq[128 * s] = nx;
             hq[128 * s + 1] = ny;
         }
@@ -754,13 +758,10 @@ __device__ __forceinline__ double fast_rev_step(const FastOp<SP, T> &o, const Fa
 #pragma unroll
     for (int s = 0; s < SP; ++s)
         if (s == 0 || two) {
-            uint32_t i0, i1;
-            pair_of(o.pe[s], D, lane, i0, i1);
             const T a = o.x[s], b = o.y[s];
-            lam[i0] = mac2(o.u[0], a, o.u[1], b);
-            lam[i1] = mac2(o.u[2], a, o.u[3], b);
-            const double gs = pair_grad(gen, a, b, h.hx[s], h.hy[s]);
-            g += o.pe[s] != kNoPair ? gs : 0.0;
+            amp_at(lam, o.pe[s] & 0xFFFFu) = mac2(o.u[0], a, o.u[1], b);
+            amp_at(lam, o.pe[s] >> 16) = mac2(o.u[2], a, o.u[3], b);
+            g += pair_grad(gen, a, b, h.hx[s], h.hy[s]);  // zero on trash slots
         }
     wave_lds_sync();
     return g;
@@ -768,21 +769,21 @@ __device__ __forceinline__ double fast_rev_step(const FastOp<SP, T> &o, const Fa
 
 // the forward chain U(theta) e_ref on one wave, two ops per trip
 template <int SP, typename T>
-__device__ __forceinline__ void fast_forward(T *psi, const uint16_t *ptf, const double2 *matf, const int2 *finf,
+__device__ __forceinline__ void fast_forward(T *psi, const uint32_t *ptf, const double2 *matf, const int2 *finf,
                                              T *__restrict__ hist, int G, int HP, int D, int lane)
 {
     FastOp<SP, T> A, B;
-    fast_op_load(A, ptf, matf, finf, 0, HP, lane);
-    fast_op_load(B, ptf, matf, finf, 1, HP, lane);
+    fast_op_load(A, ptf, matf, finf, 0, 0, HP, lane);
+    fast_op_load(B, ptf, matf, finf, 1, 1, HP, lane);
     fast_op_read(A, psi, D, lane);
     for (int q = 0; q < G; q += 2) {
-        fast_fwd_step(A, psi, hist, D, lane);
+        fast_fwd_step(A, psi, hist, q, lane);
         if (q + 1 >= G) break;
         fast_op_read(B, psi, D, lane);
-        fast_op_load(A, ptf, matf, finf, q + 2, HP, lane);
-        fast_fwd_step(B, psi, hist, D, lane);
+        fast_op_load(A, ptf, matf, finf, q + 2, q + 2, HP, lane);
+        fast_fwd_step(B, psi, hist, q + 1, lane);
         fast_op_read(A, psi, D, lane);
-        fast_op_load(B, ptf, matf, finf, q + 3, HP, lane);
+        fast_op_load(B, ptf, matf, finf, q + 3, q + 3, HP, lane);
     }
 }
 
@@ -804,8 +805,8 @@ __device__ __forceinline__ void fast_hist_load(FastHist<SP, T> &h, const T *__re
 
 template <int SP, typename T>
 __device__ __forceinline__ void fast_rev_op(FastOp<SP, T> &cur, const FastHist<SP, T> &h, FastOp<SP, T> &nxt, T *lam,
-                                            double *gpart, const uint16_t *ptr, const double2 *matr,
-                                            const int2 *rinf, int npg, int qload, int HP, int D, int lane)
+                                            double *gpart, const uint32_t *ptr, const double2 *matr,
+                                            const int2 *rinf, int npg, int qload, int G, int HP, int D, int lane)
 {
     const double g = fast_rev_step(cur, h, lam, D, lane);
     fast_op_read(nxt, lam, D, lane);
@@ -814,7 +815,7 @@ __device__ __forceinline__ void fast_rev_op(FastOp<SP, T> &cur, const FastHist<S
     __builtin_amdgcn_sched_barrier(0);
     const int pg = (int)(ufirst((uint32_t)cur.info.x) >> 8) - 1;
     gpart[(pg >= 0 ? pg : npg) * 64 + lane] = g;  // row npg: ops without a parameter
-    fast_op_load(cur, ptr, matr, rinf, qload, HP, lane);
+    fast_op_load(cur, ptr, matr, rinf, qload, rev_row(qload, G), HP, lane);
 }
 
 // the reverse chain on one wave (leaving after op G - 1); the history of op
@@ -823,15 +824,15 @@ __device__ __forceinline__ void fast_rev_op(FastOp<SP, T> &cur, const FastHist<S
 constexpr int kHistAhead = 8;
 
 template <int SP, typename T>
-__device__ __forceinline__ void fast_reverse(T *lam, const uint16_t *ptr, const double2 *matr, const int2 *rinf,
+__device__ __forceinline__ void fast_reverse(T *lam, const uint32_t *ptr, const double2 *matr, const int2 *rinf,
                                              const T *__restrict__ hist, double *gpart, int npg, int G, int HP, int D,
                                              int lane)
 {
     FastOp<SP, T> ops[2];
     FastHist<SP, T> hs[kHistAhead];
     const int last = G + kFastPad - 1;
-    fast_op_load(ops[0], ptr, matr, rinf, 0, HP, lane);
-    fast_op_load(ops[1], ptr, matr, rinf, 1, HP, lane);
+    fast_op_load(ops[0], ptr, matr, rinf, 0, rev_row(0, G), HP, lane);
+    fast_op_load(ops[1], ptr, matr, rinf, 1, rev_row(1, G), HP, lane);
 #pragma unroll
     for (int j = 0; j < kHistAhead; ++j) fast_hist_load(hs[j], hist, G, j, lane);
     fast_op_read(ops[0], lam, D, lane);
@@ -839,7 +840,7 @@ __device__ __forceinline__ void fast_reverse(T *lam, const uint16_t *ptr, const 
 #pragma unroll
         for (int j = 0; j < kHistAhead; ++j) {
             fast_rev_op(ops[j & 1], hs[j], ops[(j + 1) & 1], lam, gpart, ptr, matr, rinf, npg, min(q + j + 2, last),
-                        HP, D, lane);
+                        G, HP, D, lane);
             if (q + j + 1 >= G) break;
             fast_hist_load(hs[j], hist, G, q + j + kHistAhead, lane);
         }
@@ -947,8 +948,8 @@ __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
     double *epart = reinterpret_cast<double *>(smem + L.epart);
     int2 *finf = reinterpret_cast<int2 *>(smem + L.finf);
     int2 *rinf = reinterpret_cast<int2 *>(smem + L.rinf);
-    uint16_t *ptf = reinterpret_cast<uint16_t *>(smem + L.ptf);
-    uint16_t *ptr = reinterpret_cast<uint16_t *>(smem + L.ptr);
+    uint32_t *ptf = reinterpret_cast<uint32_t *>(smem + L.ptf);
+    uint32_t *ptr = reinterpret_cast<uint32_t *>(smem + L.ptr);
     GateDev *gdev = reinterpret_cast<GateDev *>(smem + L.gdev);
     int32_t *poff = reinterpret_cast<int32_t *>(smem + L.poff);
     int32_t *pidx = reinterpret_cast<int32_t *>(smem + L.pidx);
@@ -990,19 +991,24 @@ __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
             finf[q] = rinf[q] = make_int2(0, G);
         }
     }
-    // pair table: op q, pair t -> p0 | p1 << 8 (kNoPair past the op's pair count)
-    for (int w = tid; w < 2 * (G + kFastPad) * HP; w += NT) {
-        const int rev = w >= (G + kFastPad) * HP;
-        const int q = (w - (rev ? (G + kFastPad) * HP : 0)) / HP, t = w % HP;
-        uint32_t e = kNoPair;
+    // pair table of the forward ops (the reverse ops are the same pairs in
+    // reverse order): op q, pair t -> byte offsets of p0 | p1 << 16; past the
+    // op's pair count the trash slots D + 2 l, D + 2 l + 1 of lane l = t mod 64
+    for (int w = tid; w < (G + kFastPad) * HP; w += NT) {
+        const int q = w / HP, t = w % HP;
+        uint32_t p0 = (uint32_t)(D + 2 * (t & 63)), p1 = p0 + 1u;
         if (q < G) {
-            const SmallOp o = pack_op(rev ? ka.rops[q] : a.ops[q]);
+            const SmallOp o = pack_op(a.ops[q]);
             if (t < (D >> o.nfix)) {
-                const uint32_t p0 = insert_zeros((uint32_t)t, o.fixpack, o.nfix) | o.fixed_bits;
-                e = p0 | ((p0 ^ o.m) << 8);
+                p0 = insert_zeros((uint32_t)t, o.fixpack, o.nfix) | o.fixed_bits;
+                p1 = p0 ^ o.m;
             }
         }
-        (rev ? ptr : ptf)[q * HP + t] = (uint16_t)e;
+        ptf[w] = (p0 * (uint32_t)sizeof(T)) | (p1 * (uint32_t)sizeof(T)) << 16;
+    }
+    for (int i = tid; i < 128; i += NT) {  // the trash slots hold zeros (gates keep them zero)
+        amp_set(psi[D + i], 0.0);
+        amp_set(lam[D + i], 0.0);
     }
     for (int k = tid; k < 4 * kFastPad; k += NT) {
         matf[4 * G + k] = make_double2(0.0, 0.0);
