@@ -761,7 +761,8 @@ __device__ __forceinline__ double fast_rev_step(const FastOp<SP, T> &o, const Fa
             const T a = o.x[s], b = o.y[s];
             amp_at(lam, o.pe[s] & 0xFFFFu) = mac2(o.u[0], a, o.u[1], b);
             amp_at(lam, o.pe[s] >> 16) = mac2(o.u[2], a, o.u[3], b);
-            g += pair_grad(gen, a, b, h.hx[s], h.hy[s]);  // zero on trash slots
+            const double gs = pair_grad(gen, a, b, h.hx[s], h.hy[s]);  // zero on trash slots
+            g = s == 0 ? gs : g + gs;
         }
     wave_lds_sync();
     return g;
@@ -1109,8 +1110,17 @@ __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
         }
         for (int it = 0; it <= a.iters; ++it) {
             __syncthreads();  // psi is final
-            const T acc = NG > kRegGroups / 2 ? rows_gather<kRegGroups>(psi, tv, ad)
-                                              : rows_gather<kRegGroups / 2>(psi, tv, ad);
+            T acc;  // the groups in whole blocks of eight (zero rows pad the last)
+            switch ((NG + 7) >> 3) {
+            case 1: acc = rows_gather<8>(psi, tv, ad); break;
+            case 2: acc = rows_gather<16>(psi, tv, ad); break;
+            case 3: acc = rows_gather<24>(psi, tv, ad); break;
+            case 4: acc = rows_gather<32>(psi, tv, ad); break;
+            case 5: acc = rows_gather<40>(psi, tv, ad); break;
+            case 6: acc = rows_gather<48>(psi, tv, ad); break;
+            case 7: acc = rows_gather<56>(psi, tv, ad); break;
+            default: acc = rows_gather<64>(psi, tv, ad); break;
+            }
             lam[b] = acc;
             const double e = amp_dot(psi[b], acc);
             epart[b] = e;
