@@ -5,7 +5,9 @@ Workload (the batched potential-energy-surface scan): 100 bond lengths d in
 model (2 spatial orbitals, HF |1100> + one DoubleExcitation) and the 8-qubit
 model (4 spatial orbitals, all spin-conserving single and double
 excitations from the HF state), each bond length optimised with Adam
-(lr 0.01, 200 iterations, theta_0 = 0) on adjoint gradients, complex128.
+(lr 0.01, 200 iterations, theta_0 = 0) on adjoint gradients (the
+excitation gates and the Hamiltonians are real, so the library runs these
+states on real f64 amplitudes; circuits with RX or RZ run complex128).
 One step = one full scan of both qubit counts: 2 x 100 x 200 = 40,000
 energy + gradient evaluations, the Hamiltonians resident on the device; the
 two scans are independent and run on two HIP streams side by side.
@@ -277,7 +279,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "batched PES scan: 100 bond lengths x 200 Adam steps, 4-qubit H2-like "
-                               "(15 terms) and 8-qubit all-excitations (UCC) models, complex128; each step "
+                               "(15 terms) and 8-qubit all-excitations (UCC) models in f64 (real excitation gates and real Hamiltonians keep the state real; other circuits run complex128); each step "
                                "builds H(d_i) on the device (Jordan-Wigner map) and runs the full loop",
                    "global_batch": BATCH, "iterations": ITERS, "qubits": [4, 8],
                    "evals_per_step": len(problems) * BATCH * ITERS},
