@@ -678,7 +678,7 @@ template <int SP, typename T>
 struct FastOp {
     uint32_t pe[SP];
     T u[4];
-    int2 info;
+    int info;  // gen | two-slot flag | (pgate + 1) << 8
     T x[SP], y[SP];  // the state on the pairs before the op
 };
 
@@ -696,7 +696,7 @@ __device__ __forceinline__ void fast_op_load(FastOp<SP, T> &o, const uint32_t *p
                                              const int2 *inf, int q, int row, int HP, int lane)
 {
     fast_tables<SP>(pt, mat, q, row, HP, lane, o.pe, o.u);
-    o.info = inf[q];
+    o.info = inf[q].x;  // the word the chains use (a 32-bit load: no second register in flight)
 }
 __device__ __forceinline__ int rev_row(int q, int G) { return q < G ? G - 1 - q : q; }
 
@@ -704,7 +704,7 @@ __device__ __forceinline__ int rev_row(int q, int G) { return q < G ? G - 1 - q 
 template <int SP, typename T>
 __device__ __forceinline__ void fast_op_read(FastOp<SP, T> &o, const T *st, int D, int lane)
 {
-    const bool two = SP > 1 && (ufirst((uint32_t)o.info.x) & kTwoSlots);
+    const bool two = SP > 1 && (ufirst((uint32_t)o.info) & kTwoSlots);
 #pragma unroll
     for (int s = 0; s < SP; ++s)
         if (s == 0 || two) {
@@ -718,7 +718,7 @@ __device__ __forceinline__ void fast_op_read(FastOp<SP, T> &o, const T *st, int 
 template <int SP, typename T>
 __device__ __forceinline__ void fast_fwd_step(const FastOp<SP, T> &o, T *psi, T *__restrict__ hist, int q, int lane)
 {
-    const bool two = SP > 1 && (ufirst((uint32_t)o.info.x) & kTwoSlots);
+    const bool two = SP > 1 && (ufirst((uint32_t)o.info) & kTwoSlots);
     T *hq = hist + (size_t)q * (SP * 128) + 2 * lane;
 #pragma unroll
     for (int s = 0; s < SP; ++s)
@@ -751,7 +751,7 @@ template <int SP, typename T>
 __device__ __forceinline__ double fast_rev_step(const FastOp<SP, T> &o, const FastHist<SP, T> &h, T *lam, int D,
                                                 int lane)
 {
-    const uint32_t cd = ufirst((uint32_t)o.info.x);
+    const uint32_t cd = ufirst((uint32_t)o.info);
     const bool two = SP > 1 && (cd & kTwoSlots);
     const int gen = (int)(cd & 15u);
     double g = 0.0;
@@ -814,7 +814,7 @@ __device__ __forceinline__ void fast_rev_op(FastOp<SP, T> &cur, const FastHist<S
     // the chain's reads first in the wave's LDS queue (LDS operations of a
     // wave run in issue order), then the partial and the later tables
     __builtin_amdgcn_sched_barrier(0);
-    const int pg = (int)(ufirst((uint32_t)cur.info.x) >> 8) - 1;
+    const int pg = (int)(ufirst((uint32_t)cur.info) >> 8) - 1;
     gpart[(pg >= 0 ? pg : npg) * 64 + lane] = g;  // row npg: ops without a parameter
     fast_op_load(cur, ptr, matr, rinf, qload, rev_row(qload, G), HP, lane);
 }
