@@ -837,19 +837,23 @@ __device__ __forceinline__ void fast_reverse(T *lam, const uint32_t *ptr, const 
 #pragma unroll
     for (int j = 0; j < kHistAhead; ++j) fast_hist_load(hs[j], hist, G, j, lane);
     fast_op_read(ops[0], lam, D, lane);
-    // (a guarded op rather than an early exit, so that the eight steps unroll
-    // and each history buffer keeps its registers; every step issues its
-    // history load, past the last op from the spare row, so the loads in
-    // flight are the same on every path)
-    for (int q = 0; q < G; q += kHistAhead) {
+    // whole blocks of eight unguarded steps (each history buffer keeps its
+    // registers, and every step finds the same history loads in flight),
+    // then the last G mod 8 ops, whose history is already loaded
+    int q = 0;
+    for (; q + kHistAhead <= G; q += kHistAhead) {
 #pragma unroll
         for (int j = 0; j < kHistAhead; ++j) {
-            if (q + j < G)
-                fast_rev_op(ops[j & 1], hs[j], ops[(j + 1) & 1], lam, gpart, ptr, matr, rinf, npg,
-                            min(q + j + 2, last), G, HP, D, lane);
+            fast_rev_op(ops[j & 1], hs[j], ops[(j + 1) & 1], lam, gpart, ptr, matr, rinf, npg, min(q + j + 2, last),
+                        G, HP, D, lane);
             fast_hist_load(hs[j], hist, G, q + j + kHistAhead, lane);
         }
     }
+#pragma unroll
+    for (int j = 0; j < kHistAhead; ++j)
+        if (q + j < G)
+            fast_rev_op(ops[j & 1], hs[j], ops[(j + 1) & 1], lam, gpart, ptr, matr, rinf, npg, min(q + j + 2, last), G,
+                        HP, D, lane);
 }
 
 // the sum of parametric gate row's 64 lane partials in fixed order: each of
