@@ -867,8 +867,8 @@ __device__ __forceinline__ double row_sum(const double *gpart, int row, int NPG,
 #pragma unroll
         for (int j = 0; j < 8; j += 2) {
             const double2 a = v[j], b = v[j + 1];
-            s0 += a.x + a.y;
-            s1 += b.x + b.y;
+            s0 = j == 0 ? a.x + a.y : s0 + (a.x + a.y);
+            s1 = j == 0 ? b.x + b.y : s1 + (b.x + b.y);
         }
     }
     double t = s0 + s1;
@@ -1155,13 +1155,28 @@ __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
     // optimiser step of parameter p (gradient gp, gates pidx[e0..e1), the
     // first one's op slots q0 and coefficients ab), then the next
     // iteration's matrices of its gates
-    auto param_step = [&](int p, double gp, int e0, int e1, int2 q0, const T (&ab)[16], double rc1, double rc2) {
-        const double t0 = th[p];
-        const double2 c0 = cs[p];
+    // the parameter's state (angle, half-angle pair, Adam moments), read by
+    // the caller before the gradient so that it lands during the sums
+    struct ParamState {
+        double t0, m0, v0;
+        double2 c0;
+    };
+    auto param_load = [&](int p) {
+        ParamState ps;
+        ps.t0 = th[p];
+        ps.c0 = cs[p];
+        ps.m0 = mom[p];
+        ps.v0 = vel[p];
+        return ps;
+    };
+    auto param_step = [&](int p, double gp, int e0, int e1, int2 q0, const T (&ab)[16], const ParamState &ps,
+                          double rc1, double rc2) {
+        const double t0 = ps.t0;
+        const double2 c0 = ps.c0;
         double t = t0;
         if (a.opt == VQE_OPT_ADAM) {
-            const double mi = a.b1 * mom[p] + (1.0 - a.b1) * gp;
-            const double vi = a.b2 * vel[p] + (1.0 - a.b2) * gp * gp;
+            const double mi = a.b1 * ps.m0 + (1.0 - a.b1) * gp;
+            const double vi = a.b2 * ps.v0 + (1.0 - a.b2) * gp * gp;
             mom[p] = mi;
             vel[p] = vi;
             t -= a.lr * (mi * rc1) / (sqrt(vi * rc2) + a.eps);
@@ -1254,8 +1269,9 @@ __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
                 T ab[16];
 #pragma unroll
                 for (int k = 0; k < 16; ++k) mat_get(ab[k], mab[p * 16 + k]);
+                const ParamState ps = param_load(p);
                 const double gp = row_sum(gpart, lane >> 2, NPG, lane & 3);
-                if ((lane & 3) == 0 && (lane >> 2) < P) param_step(p, gp, p, p + 1, q0, ab, rc1, rc2);
+                if ((lane & 3) == 0 && (lane >> 2) < P) param_step(p, gp, p, p + 1, q0, ab, ps, rc1, rc2);
             } else {
                 gate_sums(gpart, gsum, NPG, lane);
                 wave_lds_sync();
@@ -1269,9 +1285,10 @@ __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
                     T ab[16];
 #pragma unroll
                     for (int k = 0; k < 16; ++k) mat_get(ab[k], mab[j0 * 16 + k]);
+                    const ParamState ps = param_load(p);
                     double gp = 0.0;
                     for (int e2 = e0; e2 < e1; ++e2) gp += gsum[pidx[e2]];
-                    param_step(p, gp, e0, e1, q0, ab, rc1, rc2);
+                    param_step(p, gp, e0, e1, q0, ab, ps, rc1, rc2);
                 }
             }
             if (NW == 1) {
