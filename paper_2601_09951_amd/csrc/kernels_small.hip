@@ -499,24 +499,30 @@ __global__ __launch_bounds__(256) void k_small_run(SmallKernelArgs ka)
 //    (a compiler code-motion barrier) is all that orders one gate's writes
 //    before the next gate's reads; only H psi, whose work is spread over all
 //    amplitudes, uses every wave, with one barrier on each side;
+//  * when every gate matrix is real for every angle and the Hamiltonian is
+//    a real matrix, the state stays real and the loop runs on f64
+//    amplitudes (a template variant): half the LDS bytes, a fifth of the
+//    FP64 work per gate;
 //  * a lane holds one pair of a gate, two when a gate has more pairs than
-//    lanes (one-qubit gates at 8 qubits; a template parameter); the pair
-//    indices of every op are tabulated once per launch and the gate
-//    matrices are laid out in op order (the reverse ones already
-//    conjugate-transposed);
+//    lanes (one-qubit gates at 8 qubits; a template parameter); the byte
+//    offsets of every op's pairs are tabulated once per launch (the reverse
+//    chain reads the forward rows backwards), lanes without a pair use
+//    zeroed trash slots, and the gate matrices are laid out in op order (the
+//    reverse ones already conjugate-transposed);
 //  * the forward sweep records each lane's pair values after every gate in
 //    a history buffer in global memory; the reverse sweep reads psi back
-//    from it (kHistAhead = 8 ops ahead) instead of undoing the gates on psi, so only
-//    lambda is carried back;
+//    from it (kHistAhead ops ahead) instead of undoing the gates on psi, so
+//    only lambda is carried back;
 //  * the optimiser step writes the next iteration's matrices of each
 //    parameter's gates directly (U = A cos(a/2) + B sin(a/2) with A, B
 //    tabulated per parametric gate; cos and sin by rotating the stored pair
-//    through the half step); constant gates keep theirs;
+//    through the half step); constant gates keep theirs; with one gate per
+//    parameter the lanes that sum a gate's partials step its parameter;
 //  * lambda = H psi uses eight interleaved accumulators, one amplitude per
-//    thread; at 8 qubits with a real Hamiltonian of at most 64 flip groups
-//    (and gates of at most 64 pairs) four extra waves do it, each thread
-//    holding its amplitude's row of the table in registers for the whole
-//    launch, so only psi is read from LDS;
+//    thread; at 8 qubits with a real state, at most 64 flip groups and gates
+//    of at most 64 pairs four extra waves do it, each thread holding its
+//    amplitude's row of the table and its partners in registers for the
+//    whole launch, so only psi is read from LDS;
 //  * a gate's gradient partials go to an LDS row per parametric gate, one
 //    per lane, summed in fixed order after the sweep; with several waves
 //    the last one sums the energy during the reverse sweep.
