@@ -541,6 +541,38 @@ def test_persistent_loop_real_state(vqe, ctx, n, n_gates, n_groups, iters, imag)
         np.testing.assert_allclose(tho_gpu[b], tho, atol=1e-7)
 
 
+def test_real_state_loop_equals_complex_loop(vqe, ctx):
+    # the 8-qubit scan problem on real amplitudes against the same problem
+    # forced onto complex amplitudes by a trailing fixed RZ(0) (an identity
+    # of a complex gate kind; the complex loop, or the general one where its
+    # tables do not fit): same trajectories up to rounding order
+    _say("real vs complex loop")
+    B, iters = 8, 60
+    model = synth.smooth_integral_model(4, seed=synth.MASTER_SEED)
+    ints = [model.at(float(d)) for d in synth.bond_grid(B)]
+    spec = synth.ucc_circuit(8, 2)
+    spec_c = synth.Circuit(spec.n, list(spec.kinds) + ["RZ"],
+                           np.vstack([spec.wires, np.array([[3, -1, -1, -1]], dtype=np.int32)]),
+                           np.append(spec.param_idx, np.int32(-1)).astype(np.int32),
+                           np.append(spec.fixed_angle, 0.0), spec.n_params, spec.ref_index)
+    hams = [vqe.Hamiltonian.from_integrals(ctx, i.h1, i.h2, i.e_core) for i in ints]
+    out = {}
+    for name, sp in (("real", spec), ("complex", spec_c)):
+        C = vqe.Circuit.from_spec(ctx, sp)
+        th = dev(np.zeros((B, sp.n_params)))
+        ctx.profile(reset=True)
+        ctx.set_profiling(True)
+        traj = vqe.run(ctx, C, hams, th, iters).cpu().numpy()
+        out[name] = (traj, th.cpu().numpy(), set(ctx.profile(reset=True)))
+        ctx.set_profiling(False)
+    assert "k_small_fast (real state, register rows)" in out["real"][2], out["real"][2]
+    assert not any("real state" in k for k in out["complex"][2]), out["complex"][2]  # complex128 amplitudes
+    np.testing.assert_allclose(out["real"][0], out["complex"][0], atol=1e-11, rtol=0)
+    np.testing.assert_allclose(out["real"][1], out["complex"][1], atol=1e-10, rtol=0)
+    want, tho = oracle.vqe_run(spec, fermion.qubit_hamiltonian(ints[3]), np.zeros(spec.n_params), iters)
+    np.testing.assert_allclose(out["real"][0][3], want, atol=E_TOL)
+
+
 @pytest.mark.parametrize("n,tiles,seed", [(14, (12, 11, 3), 81), (15, (9, 9, 3), 82), (16, (12, 11, 3), 83)])
 def test_any_weight_pauli_strings(vqe, ctx, n, tiles, seed):
     """Strings of weight up to n (flip groups too wide for any tile run as
