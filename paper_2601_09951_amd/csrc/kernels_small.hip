@@ -774,15 +774,21 @@ __device__ __forceinline__ double fast_rev_step(const FastOp<SP, T> &o, const Fa
     return g;
 }
 
-// the forward chain U(theta) e_ref on one wave, two ops per trip
+// the forward chain U(theta) e_ref on one wave, two ops per trip; the first
+// op acts on the reference basis state (ref_off: its byte offset), so its
+// pair values follow from its table entry without an LDS read
 template <int SP, typename T>
 __device__ __forceinline__ void fast_forward(T *psi, const uint32_t *ptf, const double2 *matf, const int2 *finf,
-                                             T *__restrict__ hist, int G, int HP, int D, int lane)
+                                             T *__restrict__ hist, int G, int HP, int D, uint32_t ref_off, int lane)
 {
     FastOp<SP, T> A, B;
     fast_op_load(A, ptf, matf, finf, 0, 0, HP, lane);
     fast_op_load(B, ptf, matf, finf, 1, 1, HP, lane);
-    fast_op_read(A, psi, D, lane);
+#pragma unroll
+    for (int s = 0; s < SP; ++s) {
+        amp_set(A.x[s], (A.pe[s] & 0xFFFFu) == ref_off ? 1.0 : 0.0);
+        amp_set(A.y[s], (A.pe[s] >> 16) == ref_off ? 1.0 : 0.0);
+    }
     for (int q = 0; q < G; q += 2) {
         fast_fwd_step(A, psi, hist, q, lane);
         if (q + 1 >= G) break;
@@ -1223,7 +1229,7 @@ __global__ __launch_bounds__(NT) void k_small_fast(SmallKernelArgs ka)
         if (wave == 0) {
             for (int b = lane; b < D; b += 64) amp_set(psi[b], b == (int)a.ref ? 1.0 : 0.0);
             wave_lds_sync();
-            fast_forward<SP>(psi, ptf, matf, finf, hist, G, HP, D, lane);  // U(theta) e_ref
+            fast_forward<SP>(psi, ptf, matf, finf, hist, G, HP, D, a.ref * (uint32_t)sizeof(T), lane);  // U(theta) e_ref
         }
         __syncthreads();
 
