@@ -823,9 +823,6 @@ __device__ __forceinline__ void fast_rev_op(FastOp<SP, T> &cur, const FastHist<S
 {
     const double g = fast_rev_step(cur, h, lam, D, lane);
     fast_op_read(nxt, lam, D, lane);
-    // the chain's reads first in the wave's LDS queue (LDS operations of a
-    // wave run in issue order), then the partial and the later tables
-    __builtin_amdgcn_sched_barrier(0);
     const int pg = (int)(ufirst((uint32_t)cur.info) >> 8) - 1;
     gpart[(pg >= 0 ? pg : npg) * 64 + lane] = g;  // row npg: ops without a parameter
     fast_op_load(cur, ptr, matr, rinf, qload, rev_row(qload, G), HP, lane);
@@ -866,6 +863,10 @@ __device__ __forceinline__ void fast_reverse(T *lam, const uint32_t *ptr, const 
         if (q + j < G)
             fast_rev_op(ops[j & 1], hs[j], ops[(j + 1) & 1], lam, gpart, ptr, matr, rinf, npg, min(q + j + 2, last), G,
                         HP, D, lane);
+    // the last block prefetched spare rows nobody reads; wait for them here
+    // (s_waitcnt vmcnt(0), gfx9 encoding), so no load is in flight when the
+    // next forward chain starts and its stores need no wait of their own
+    __builtin_amdgcn_s_waitcnt(0x0F70);
 }
 
 // the sum of parametric gate row's 64 lane partials in fixed order: each of
